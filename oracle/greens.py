@@ -1,0 +1,57 @@
+"""Green's function, kernel table and self-term (oracle; test infrastructure).
+
+Section 1 gives the free-space Green's function of -(Laplacian + w^2):
+  d = 2: G(x) = (i/4) H0^(1)(w |x|),   d = 3: G(x) = exp(i w |x|) / (4 pi |x|).
+Section 2.1 discretises the convolution with the trapezoid rule on the grid:
+  k_t = G(h t) h^d for t != 0; k_0 is a local quadrature correction whose
+  value the paper does not print.  Reading used here: k_0 is the exact
+  integral of G over the disk (2D) / ball (3D) whose area / volume equals
+  one grid cell h^d, i.e. radius rho = h/sqrt(pi) (2D), h (3/(4 pi))^(1/3) (3D).
+  Closed forms (from d/dz[z H1(z)] = z H0(z), lim_{z->0} z H1^(1)(z) = -2i/pi,
+  and the antiderivative of r exp(i w r)):
+    2D: k_0 = (i pi rho / (2 w)) H1^(1)(w rho) - 1/w^2
+    3D: k_0 = (exp(i w rho)(1 - i w rho) - 1) / w^2
+"""
+import numpy as np
+import scipy.special as sp
+
+
+def green(r, omega, d):
+    """G at distance r > 0 (Section 1)."""
+    r = np.asarray(r, dtype=np.float64)
+    if d == 2:
+        return 0.25j * sp.hankel1(0, omega * r)
+    if d == 3:
+        return np.exp(1j * omega * r) / (4.0 * np.pi * r)
+    raise ValueError("d must be 2 or 3")
+
+
+def self_radius(h, d):
+    """Radius of the disk/ball with the area/volume of one cell."""
+    if d == 2:
+        return h / np.sqrt(np.pi)
+    return h * (3.0 / (4.0 * np.pi)) ** (1.0 / 3.0)
+
+
+def self_term(h, omega, d):
+    """k_0: integral of G over the equal-measure disk/ball (reading above)."""
+    rho = self_radius(h, d)
+    if d == 2:
+        return 1j * np.pi * rho / (2.0 * omega) * sp.hankel1(1, omega * rho) - 1.0 / omega ** 2
+    return (np.exp(1j * omega * rho) * (1.0 - 1j * omega * rho) - 1.0) / omega ** 2
+
+
+def kernel_table(n, d, omega):
+    """k_t for t in [0, n]^d (absolute offsets per axis), shape (n+1,)*d.
+
+    k depends on |t| only, so the table is symmetric under any permutation
+    of its axes and covers every offset -n <= t_a <= n by reflection."""
+    h = 1.0 / n
+    ax = np.arange(n + 1, dtype=np.float64)
+    T = np.meshgrid(*([ax] * d), indexing="ij")
+    r = h * np.sqrt(sum(t * t for t in T))
+    k = np.empty(r.shape, dtype=np.complex128)
+    nz = r > 0
+    k[nz] = green(r[nz], omega, d) * h ** d
+    k[(0,) * d] = self_term(h, omega, d)
+    return k

@@ -1,0 +1,28 @@
+"""End-to-end oracle pipeline: setup, factor, preconditioned GMRES solve."""
+import numpy as np
+
+from .greens import kernel_table
+from .operator import Operator
+from .stencil import all_stencils
+from .sparse import build_QM, Preconditioner
+from .gmres import gmres
+
+
+class OracleProblem:
+    def __init__(self, n, d, omega, m, b=2):
+        self.n, self.d, self.omega, self.b = n, d, float(omega), b
+        self.m = np.asarray(m, dtype=np.float64)
+        self.ktab = kernel_table(n, d, omega)
+        self.op = Operator(n, d, omega, self.m, self.ktab)
+        self.stencils = all_stencils(self.ktab, d, n, b)
+        self.Q, self.M = build_QM(n, d, omega, self.m, self.stencils)
+        self.P = Preconditioner(self.Q, self.M)
+
+    def rhs(self, uI):
+        return self.op.rhs(uI)
+
+    def solve_g(self, g, tol=1e-8, restart=30, max_iters=1000):
+        return gmres(self.op.apply, self.P, g, tol, restart, max_iters)
+
+    def solve(self, uI, tol=1e-8, restart=30, max_iters=1000):
+        return self.solve_g(self.rhs(uI), tol, restart, max_iters)

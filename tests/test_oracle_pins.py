@@ -1,0 +1,395 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test states what it pins.  None of them re-types the oracle's formula:
+they check closed forms against numerical quadrature, the continuous
+identity G * ((-Laplacian - w^2) phi) = phi, brute force, optimality and
+symmetry properties, an exact error bound, and textbook special cases.
+"""
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.special as sp
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle.greens import kernel_table, self_term, self_radius, green
+from oracle.operator import (dense_K, apply_K_direct, apply_K_fft, Operator, grid_index)
+from oracle.stencil import (all_stencils, class_offsets, far_set, kernel_block,
+                            class_tuple, interior_class, point_class, slot)
+from oracle.sparse import build_QM, Preconditioner
+from oracle.gmres import gmres
+from oracle.solve import OracleProblem
+
+
+# ---------------------------------------------------------------- Green / k_0
+@pytest.mark.parametrize("d,n,omega", [(2, 32, 8 * np.pi), (2, 256, 64 * np.pi),
+                                       (3, 64, 16 * np.pi), (3, 16, 3.0)])
+def test_self_term_matches_radial_quadrature(d, n, omega):
+    """k_0 (cell-integral reading of Section 2.1) vs adaptive quadrature of the
+    radial integral of G over the equal-measure disk/ball."""
+    h = 1.0 / n
+    rho = self_radius(h, d)
+    if d == 2:
+        # integral over the disk = int_0^rho G(r) 2 pi r dr
+        re = si.quad(lambda r: (-0.25 * sp.y0(omega * r)) * 2 * np.pi * r, 0, rho,
+                     epsabs=0, epsrel=1e-13, limit=200)[0]
+        im = si.quad(lambda r: (0.25 * sp.j0(omega * r)) * 2 * np.pi * r, 0, rho,
+                     epsabs=0, epsrel=1e-13, limit=200)[0]
+    else:
+        re = si.quad(lambda r: np.cos(omega * r) / (4 * np.pi * r) * 4 * np.pi * r * r, 0, rho,
+                     epsabs=0, epsrel=1e-13)[0]
+        im = si.quad(lambda r: np.sin(omega * r) / (4 * np.pi * r) * 4 * np.pi * r * r, 0, rho,
+                     epsabs=0, epsrel=1e-13)[0]
+    k0 = self_term(h, omega, d)
+    assert abs(k0 - (re + 1j * im)) <= 1e-12 * abs(k0)
+
+
+def test_self_term_small_frequency_series():
+    """For small w the 3D cell integral follows its Taylor series
+    rho^2/2 + i w rho^3/3 - w^2 rho^4/8 (rho^2/2 is the Laplace cell value)."""
+    h = 1.0 / 20
+    rho = self_radius(h, 3)
+    w = 0.05
+    k0 = self_term(h, w, 3)
+    series = rho ** 2 / 2 + 1j * w * rho ** 3 / 3 - w * w * rho ** 4 / 8
+    assert abs(k0 - series) < 1e-9 * rho ** 2
+
+
+def test_green_large_argument_asymptote():
+    """2D G against the leading Hankel asymptote sqrt(2/(pi z)) e^{i(z - pi/4)}."""
+    z = np.array([200.0, 500.0, 1000.0])
+    g = green(z, 1.0, 2)
+    asym = 0.25j * np.sqrt(2 / (np.pi * z)) * np.exp(1j * (z - np.pi / 4))
+    assert np.max(np.abs(g - asym) / np.abs(asym)) < 1e-3
+
+
+@pytest.mark.parametrize("d,ns,bounds", [(2, (64, 128), (4e-3, 1e-3)), (3, (32, 48), (8e-3, 3.5e-3))])
+def test_convolution_inverts_helmholtz(d, ns, bounds):
+    """Continuous identity G * ((-Lap - w^2) phi) = phi for a smooth bump phi.
+    The discrete K (table, h^d weights, self-term, FFT embedding) must
+    reproduce phi at second order; dropping k_0 fails the bound."""
+    omega, s = 2 * np.pi * 4, 0.07
+    errs = []
+    for n, bound in zip(ns, bounds):
+        X = synth.grid_coords(n, d)
+        r2 = np.sum((X - 0.5) ** 2, axis=1)
+        phi = np.exp(-r2 / (2 * s * s))
+        f = -phi * (r2 / s ** 4 - d / s ** 2) - omega ** 2 * phi
+        y = apply_K_fft(f.astype(np.complex128), n, d, omega)
+        err = np.max(np.abs(y - phi)) / np.max(np.abs(phi))
+        assert err < bound
+        errs.append(err)
+        if n == ns[0]:
+            kt = kernel_table(n, d, omega)
+            kt[(0,) * d] = 0.0
+            y0 = apply_K_direct(f.astype(np.complex128), n, d, omega, kt)
+            assert np.max(np.abs(y0 - phi)) / np.max(np.abs(phi)) > 4 * bound
+    ratio = (ns[1] / ns[0]) ** 2
+    assert errs[0] / errs[1] > 0.7 * ratio
+
+
+# ---------------------------------------------------------------- K matvec
+@pytest.mark.parametrize("d,n", [(2, 8), (2, 13), (3, 5), (3, 6)])
+def test_fft_direct_dense_agree(d, n):
+    """Three independent K v: dense matrix, direct sum, FFT embedding."""
+    omega = 2 * np.pi * n / 8
+    v = synth.random_complex((2, n ** d), seed=n * 10 + d)
+    Kd = dense_K(n, d, omega)
+    y_dense = v @ Kd.T
+    y_direct = apply_K_direct(v, n, d, omega)
+    y_fft = apply_K_fft(v, n, d, omega)
+    ref = np.linalg.norm(y_dense)
+    assert np.linalg.norm(y_direct - y_dense) <= 1e-13 * ref
+    assert np.linalg.norm(y_fft - y_dense) <= 1e-12 * ref
+    # brute force single entries by explicit loops over the grid
+    I = grid_index(n, d)
+    kt = kernel_table(n, d, omega)
+    for i in (0, n ** d // 2, n ** d - 1):
+        acc = 0j
+        for j in range(n ** d):
+            t = tuple(abs(int(I[i, a] - I[j, a])) for a in range(d))
+            acc += kt[t] * v[0, j]
+        assert abs(acc - y_dense[0, i]) <= 1e-12 * np.abs(y_dense[0]).max()
+
+
+def test_dense_K_is_symmetric_toeplitz():
+    n, d, omega = 6, 2, 5.0
+    K = dense_K(n, d, omega)
+    assert np.allclose(K, K.T, rtol=0, atol=0)
+    # translation invariance: K(i, j) depends on i - j only
+    I = grid_index(n, d)
+    a, b = 7, 13
+    sh = 1  # shift both by +1 along axis 1 where possible
+    if I[a, 0] + sh < n and I[b, 0] + sh < n:
+        assert K[a, b] == K[a + sh, b + sh]
+
+
+# ---------------------------------------------------------------- stencils
+@pytest.fixture(scope="module")
+def stencils_2d():
+    n, d = 24, 2
+    omega = 2 * np.pi * n / 8
+    kt = kernel_table(n, d, omega)
+    return n, d, omega, kt, all_stencils(kt, d, n, b=2)
+
+
+@pytest.fixture(scope="module")
+def stencils_3d():
+    n, d = 12, 3
+    omega = 2 * np.pi * n / 8
+    kt = kernel_table(n, d, omega)
+    return n, d, omega, kt, all_stencils(kt, d, n, b=2)
+
+
+@pytest.mark.parametrize("fx", ["stencils_2d", "stencils_3d"])
+def test_stencil_is_minimiser(fx, request):
+    """eq:Fmin/eq:Emin/eq:Cmin: ||alpha X|| equals the smallest singular value
+    and no other unit vector (random or perturbed) does better."""
+    n, d, omega, kt, sts = request.getfixturevalue(fx)
+    rng = np.random.default_rng(7)
+    for st in sts:
+        X = kernel_block(kt, st.offsets, far_set(st.c, d, n, 2))
+        val = np.linalg.norm(st.alpha @ X)
+        assert abs(val - st.sigma_min) <= 1e-10 * st.sigma[0]
+        assert abs(np.linalg.norm(st.alpha) - 1) < 1e-14
+        for _ in range(20):
+            z = rng.standard_normal(st.alpha.size) + 1j * rng.standard_normal(st.alpha.size)
+            z /= np.linalg.norm(z)
+            assert np.linalg.norm(z @ X) >= st.sigma_min * (1 - 1e-12)
+            p = st.alpha + 1e-4 * z
+            p /= np.linalg.norm(p)
+            assert np.linalg.norm(p @ X) >= st.sigma_min * (1 - 1e-12)
+        # the minimiser is the least eigenvector of X X^H (a second routine)
+        w, V = np.linalg.eigh(X @ X.conj().T)
+        assert abs(abs(np.vdot(V[:, 0], np.conj(st.alpha))) - 1) < 1e-8
+        centre = int(np.nonzero(np.all(st.offsets == 0, axis=1))[0][0])
+        assert abs(st.alpha[centre].imag) < 1e-14 and st.alpha[centre].real > 0
+
+
+def _alpha_map(st):
+    return {tuple(o): a for o, a in zip(st.offsets, st.alpha)}
+
+
+@pytest.mark.parametrize("fx", ["stencils_2d", "stencils_3d"])
+def test_stencil_lattice_symmetry(fx, request):
+    """k depends on |t|: reflecting an axis maps class Lo<->Hi with mirrored
+    alpha; swapping two axes maps the class with transposed alpha; the
+    interior stencil is invariant under all signed permutations."""
+    n, d, omega, kt, sts = request.getfixturevalue(fx)
+    bycls = {st.c: st for st in sts}
+    tol = 1e-9
+    for st in sts:
+        ct = list(class_tuple(st.c, d))
+        am = _alpha_map(st)
+        for a in range(d):                      # reflection of axis a
+            ct2 = ct.copy()
+            ct2[a] = {0: 2, 1: 1, 2: 0}[ct[a]]
+            st2 = bycls[sum(v * 3 ** k for k, v in enumerate(ct2))]
+            am2 = _alpha_map(st2)
+            for o, v in am.items():
+                o2 = list(o); o2[a] = -o2[a]
+                assert abs(am2[tuple(o2)] - v) < tol
+            assert abs(st2.sigma_min - st.sigma_min) < tol * st.sigma[0]
+        for a in range(d):                      # swap axes a, a+1
+            b_ = (a + 1) % d
+            ct2 = ct.copy(); ct2[a], ct2[b_] = ct[b_], ct[a]
+            st2 = bycls[sum(v * 3 ** k for k, v in enumerate(ct2))]
+            am2 = _alpha_map(st2)
+            for o, v in am.items():
+                o2 = list(o); o2[a], o2[b_] = o[b_], o[a]
+                assert abs(am2[tuple(o2)] - v) < tol
+
+
+def test_interior_stencil_approximates_helmholtz():
+    """The interior A row acts like a Helmholtz difference stencil: applied to
+    a plane wave of wavenumber w it nearly annihilates it (A K ~ C is built on
+    the fact that G solves Helmholtz away from the origin)."""
+    n, d = 64, 2
+    omega = 2 * np.pi * n / 8
+    kt = kernel_table(n, d, omega)
+    st = all_stencils(kt, d, n, 2)[interior_class(d)]
+    h = 1.0 / n
+    for th in (0.0, 0.4, 1.1):
+        k = omega * np.array([np.cos(th), np.sin(th)])
+        val = sum(a * np.exp(1j * h * k @ o) for o, a in zip(st.offsets, st.alpha))
+        assert abs(val) < 2e-3          # the centre weight is O(0.5)
+
+
+@pytest.mark.parametrize("d,n", [(2, 20), (3, 10)])
+def test_sparsified_operator_error_bound(d, n):
+    """Exact bound behind eq:A / eq:B: for m vanishing on the outer b+1
+    layers, every row of E = Q(I + K w^2 m) - M satisfies
+    ||E(i,:)|| <= w^2 max|m| sigma_min(class of i)."""
+    b = 2
+    omega = 2 * np.pi * n / 8
+    X = synth.grid_coords(n, d)
+    I = grid_index(n, d)
+    m = 0.3 * np.exp(-np.sum((X - 0.5) ** 2, axis=1) / (2 * 0.12 ** 2))
+    inner = np.all((I >= b + 1) & (I <= n - 2 - b), axis=1)
+    m = np.where(inner, m, 0.0)
+    kt = kernel_table(n, d, omega)
+    sts = all_stencils(kt, d, n, b)
+    Q, M = build_QM(n, d, omega, m, sts)
+    K = dense_K(n, d, omega, kt)
+    E = Q.toarray() @ (np.eye(n ** d) + K * (omega ** 2 * m)[None, :]) - M.toarray()
+    cls = point_class(n, d)
+    smin = np.array([sts[c].sigma_min for c in cls])
+    rown = np.linalg.norm(E, axis=1)
+    assert np.all(rown <= omega ** 2 * m.max() * smin * (1 + 1e-9) + 1e-13)
+    # and the bound is not vacuous: interior rows near the medium come close
+    assert rown.max() > 1e-3 * omega ** 2 * m.max() * smin.min()
+
+
+@pytest.mark.parametrize("d,n", [(2, 20), (3, 9)])
+def test_QK_numerically_sparse(d, n):
+    """Spec invariant: outside mu(i) the row (Q K)(i, :) has 2-norm at most
+    sigma_min of the class, i.e. relative size sigma_min/sigma_max, which the
+    oracle states (about 1e-4 .. 3e-3 at 8 points per wavelength)."""
+    omega = 2 * np.pi * n / 8
+    kt = kernel_table(n, d, omega)
+    sts = all_stencils(kt, d, n, 2)
+    Q, _ = build_QM(n, d, omega, np.zeros(n ** d), sts)
+    QK = Q.toarray() @ dense_K(n, d, omega, kt)
+    I = grid_index(n, d)
+    cls = point_class(n, d)
+    ic = interior_class(d)
+    for i in range(n ** d):
+        if cls[i] != ic:
+            continue
+        far = np.max(np.abs(I - I[i]), axis=1) > 1
+        st = sts[cls[i]]
+        assert np.linalg.norm(QK[i, far]) <= st.sigma_min * (1 + 1e-9)
+        assert st.sigma_min / st.sigma[0] < 5e-3
+
+
+# ---------------------------------------------------------------- sparse LU
+def test_splu_matches_dense_solve():
+    n, d = 16, 2
+    omega = 2 * np.pi * n / 8
+    m = synth.medium_single_bump(n, d, 0.2, 0.1)
+    kt = kernel_table(n, d, omega)
+    Q, M = build_QM(n, d, omega, m, all_stencils(kt, d, n, 2))
+    P = Preconditioner(Q, M)
+    z = synth.random_complex(n ** d, seed=3)
+    x1 = P.solve_M(z)
+    x2 = np.linalg.solve(M.toarray(), z)
+    assert np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x2)
+
+
+def test_stencil_rows_have_class_support():
+    """Every row of Q / M has exactly |mu(i)| nonzeros inside mu(i)."""
+    n, d = 7, 3
+    omega = 2 * np.pi * n / 8
+    kt = kernel_table(n, d, omega)
+    sts = all_stencils(kt, d, n, 2)
+    Q, M = build_QM(n, d, omega, np.full(n ** d, 0.1), sts)
+    I = grid_index(n, d)
+    for i in range(n ** d):
+        nb = np.all(np.abs(I - I[i]) <= 1, axis=1)
+        assert Q[i].nnz == nb.sum()
+        cols = Q[i].indices
+        assert np.all(nb[cols])
+
+
+# ---------------------------------------------------------------- GMRES
+@pytest.fixture(scope="module")
+def c1_problem():
+    w = synth.workload("c1")
+    prob = OracleProblem(w["n"], w["d"], w["omega"], w["m"], b=2)
+    return w, prob
+
+
+def test_c1_matches_dense_direct_solve(c1_problem):
+    """Workload 2D n=32: preconditioned GMRES to 1e-8 vs a dense LU solve of
+    (I + K w^2 m) u = g; the error is bounded by cond * tol."""
+    w, prob = c1_problem
+    n, d, omega = w["n"], w["d"], w["omega"]
+    K = dense_K(n, d, omega)
+    A = np.eye(n ** d) + K * (omega ** 2 * w["m"])[None, :]
+    g = K @ (-omega ** 2 * w["m"] * w["uI"][0])
+    u_star = np.linalg.solve(A, g)
+    res = prob.solve(w["uI"][0])
+    assert res.converged and res.relres <= 1e-8
+    kappa = np.linalg.cond(A)
+    err = np.linalg.norm(res.x - u_star) / np.linalg.norm(u_star)
+    assert err <= kappa * 1e-8
+    assert np.linalg.norm(prob.rhs(w["uI"][0]) - g) <= 1e-12 * np.linalg.norm(g)
+
+
+def test_zero_medium_gives_zero_field():
+    n, d = 16, 2
+    prob = OracleProblem(n, d, 2 * np.pi * 2, np.zeros(n ** d))
+    res = prob.solve(synth.plane_waves(n, d, 2 * np.pi * 2, [[1.0, 0.0]])[0])
+    assert res.iters == 0 and np.all(res.x == 0)
+
+
+def test_exact_preconditioner_converges_in_one_step():
+    n, d = 12, 2
+    omega = 2 * np.pi * 1.5
+    m = synth.medium_single_bump(n, d, 0.3, 0.15)
+    A = np.eye(n ** d) + dense_K(n, d, omega) * (omega ** 2 * m)[None, :]
+    Ainv = np.linalg.inv(A)
+    g = synth.random_complex(n ** d, seed=11)
+    res = gmres(lambda v: A @ v, lambda v: Ainv @ v, g, tol=1e-10)
+    assert res.iters == 1 and res.relres < 1e-10
+
+
+def test_born_limit():
+    """m -> eps m: u = g + O(eps) (the scattered field is the Born term)."""
+    w = synth.workload("c1")
+    errs = []
+    for eps in (1e-3, 1e-4):
+        prob = OracleProblem(w["n"], w["d"], w["omega"], eps * w["m"])
+        g = prob.rhs(w["uI"][0])
+        res = prob.solve_g(g)
+        errs.append(np.linalg.norm(res.x - g) / np.linalg.norm(g))
+    assert errs[0] < 0.1 and 5 < errs[0] / errs[1] < 20
+
+
+def test_solution_agrees_with_scipy_gmres(c1_problem):
+    w, prob = c1_problem
+    g = prob.rhs(w["uI"][0])
+    N = g.size
+    Aop = spla.LinearOperator((N, N), matvec=prob.op.apply, dtype=np.complex128)
+    Pop = spla.LinearOperator((N, N), matvec=prob.P, dtype=np.complex128)
+    x_sp, info = spla.gmres(Aop, g, M=Pop, rtol=1e-11, restart=30, maxiter=50)
+    assert info == 0
+    res = prob.solve_g(g, tol=1e-11)
+    assert np.linalg.norm(res.x - x_sp) <= 1e-8 * np.linalg.norm(x_sp)
+
+
+def test_preconditioner_cuts_iterations_frequency_independent():
+    """Section 3.3 claims, on a paper-shaped medium (negative Gaussian bump with
+    c down to 2/3, downward plane wave, fixed points per wavelength): the
+    preconditioner cuts the iteration count several-fold versus plain GMRES,
+    and the preconditioned count stays essentially flat as w doubles."""
+    counts = []
+    for n in (48, 96):
+        d, omega = 2, 2 * np.pi * n / 8
+        m = synth.medium_single_bump(n, d, -1.25, 0.12)
+        prob = OracleProblem(n, d, omega, m)
+        g = prob.rhs(synth.plane_waves(n, d, omega, [[0.0, -1.0]])[0])
+        pre = prob.solve_g(g)
+        counts.append(pre.iters)
+        if n == 96:
+            plain = gmres(prob.op.apply, lambda v: v, g, tol=1e-8, max_iters=400)
+            assert plain.iters >= 4 * pre.iters
+    assert max(counts) <= 8 and abs(counts[1] - counts[0]) <= 1
+
+
+def test_golden_c1_regression():
+    """Stored oracle outputs for the 2D n=32 workload (written by
+    tests/golden/make_golden.py, which calls only the oracle)."""
+    import json, os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c1_oracle.json")
+    ref = json.load(open(path))
+    w = synth.workload("c1")
+    prob = OracleProblem(w["n"], w["d"], w["omega"], w["m"], b=2)
+    res = prob.solve(w["uI"][0])
+    assert res.iters == ref["iters"]
+    sig = [st.sigma_min for st in prob.stencils]
+    assert np.allclose(sig, ref["sigma_min"], rtol=1e-10, atol=0)
+    kt = prob.ktab
+    assert abs(kt[0, 0] - complex(*ref["k0"])) < 1e-15
+    u = res.x
+    assert abs(np.linalg.norm(u) - ref["u_norm"]) < 1e-8 * ref["u_norm"]
