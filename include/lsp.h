@@ -1,0 +1,198 @@
+/*
+ * lsp.h -- C ABI of the MI355X (gfx950) solver for the discretised
+ * Lippmann-Schwinger equation with the sparsifying preconditioner
+ * (L. Ying, "Sparsifying Preconditioner for the Lippmann-Schwinger
+ * Equation", 2014).
+ *
+ * Problem (Section 1, eq:ls; Section 2.1, eq:lsd / eq:lso): on the uniform
+ * grid of the unit square / cube with n points per axis, h = 1/n, grid
+ * points x_i = (i + 1/2) h, find the scattered field u with
+ *
+ *     (I + K w^2 m) u = g,   K(i, j) = k_{i-j},   g = K(-w^2 m u_I),
+ *
+ * where k_t = h^d G(h t) (t != 0) samples the free-space Green's function
+ * G of -(Laplacian + w^2) and k_0 is the integral of G over the disk/ball
+ * of one cell's area/volume.  The solver is GMRES right-preconditioned by
+ * P = M^{-1} Q (eq:PC): Q = [A; B] holds the 3^d-point stencils that make
+ * Q K numerically local (eq:Fmin, eq:Emin, eq:Cmin and their 3D sets),
+ * M = [A + C w^2 m; B] (eq:ABop) is factored by nested dissection and the
+ * multifrontal method (Section 2.2, Section 3.2).
+ *
+ * Conventions for every entry point:
+ *  - Grid vectors have N = n^d entries, linear index l = i1 + n i2 + n^2 i3
+ *    (i1 fastest).  A block of nrhs vectors is contiguous, [nrhs][N].
+ *  - Complex values are interleaved (re, im) pairs: complex128 = two
+ *    doubles, complex64 = two floats.  The medium m is real double.
+ *  - Pointers named *_dev are device (HBM) pointers of the GPU current
+ *    when the problem was set up; *_host are host pointers.  The caller
+ *    owns every buffer it passes; the library never frees them.
+ *  - Device work is ordered on the HIP stream given to lsp_setup.  Calls
+ *    that return host data synchronise that stream; the rest only enqueue.
+ *  - No C++ exception crosses this boundary: every function returns an
+ *    lsp_status, and lsp_last_error() gives a message for the calling
+ *    thread's last failure.
+ *  - A problem is used by one host thread at a time.  Distinct problems on
+ *    distinct streams may run concurrently.
+ */
+#ifndef LSP_H
+#define LSP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LSP_OK = 0,
+  LSP_ERR_ARG = 1,       /* invalid argument: d not in {2,3}, n < 4, w <= 0,
+                            null pointer, workspace too small, nrhs too large */
+  LSP_ERR_OOM = 2,       /* a host allocation failed */
+  LSP_ERR_HIP = 3,       /* a HIP runtime call failed */
+  LSP_ERR_STATE = 4,     /* call out of order (e.g. solve before factor) */
+  LSP_ERR_SINGULAR = 5,  /* a zero or tiny pivot in a frontal factorisation */
+  LSP_ERR_NOCONV = 6     /* GMRES hit max_iters; u holds the last iterate */
+} lsp_status;
+
+typedef enum {
+  LSP_FP64 = 0,   /* every step in complex128 */
+  LSP_MIXED = 1   /* preconditioner (Q apply, fronts, triangular solves) and the
+                     operator inside the Arnoldi step in complex64; Arnoldi
+                     orthogonalisation, true residual, iterate update in
+                     complex128 */
+} lsp_precision;
+
+typedef enum {
+  LSP_RHS_INCIDENT = 0,  /* rhs holds u_I; the library forms g = K(-w^2 m u_I) */
+  LSP_RHS_G = 1          /* rhs holds g itself */
+} lsp_rhs_kind;
+
+typedef struct {
+  double tol;        /* relative residual ||g - A u|| / ||g|| to reach (1e-8) */
+  int restart;       /* GMRES restart length (30), 1..64 */
+  int max_iters;     /* total Arnoldi steps allowed per right-hand side (1000) */
+  int precision;     /* lsp_precision (LSP_FP64) */
+  int buffer_b;      /* b of Section 3.1: boundary far sets exclude offsets
+                        within b of the boundary plane (2); 1 <= b < n/2 */
+  int leaf;          /* nested-dissection leaf side in grid points (0 = auto) */
+  int panel;         /* frontal LU panel width, 0 = auto, else 8..64 */
+} lsp_options;
+
+typedef struct {
+  int iters;            /* total Arnoldi steps for this right-hand side */
+  int converged;        /* 1 if the true relative residual met tol */
+  double relres_true;   /* ||g - A u|| / ||g||, recomputed in complex128 */
+  double relres_est;    /* GMRES estimate at the last step */
+} lsp_rhs_info;
+
+typedef struct {
+  int n, d, N, L;             /* grid size, N = n^d, FFT length L = 2n */
+  int nfronts, nlevels;       /* nested-dissection tree nodes and levels */
+  int max_front, max_pivots;  /* largest front order and fully-summed block */
+  double factor_entries;      /* stored L and U entries over all fronts */
+  double front_entries;       /* sum of squared front orders (storage) */
+  double factor_flops;        /* real flops of the numeric factorisation */
+} lsp_plan_stats;
+
+typedef struct lsp_plan lsp_plan;        /* opaque, host-side */
+typedef struct lsp_problem lsp_problem;  /* opaque, owns no device memory */
+
+/* Defaults: tol 1e-8, restart 30, max_iters 1000, FP64, b = 2, auto leaf and
+ * panel.  Returns LSP_ERR_ARG on a null pointer. */
+lsp_status lsp_options_default(lsp_options* opts);
+
+/* Host-side symbolic analysis (Section 2.2: nested dissection of the 3^d
+ * stencil graph): recursive 1-wide separator planes, elimination tree,
+ * front index lists and extend-add maps.  Integer work only; no device
+ * memory is touched.  max_nrhs bounds the right-hand sides of one solve.
+ * The plan is immutable once created and may be shared by problems. */
+lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts,
+                           lsp_plan** plan);
+void lsp_plan_destroy(lsp_plan* plan);
+lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* stats);
+
+/* Device bytes the caller must provide: *problem_bytes for lsp_setup (kernel
+ * table, spectrum, stencils, matrix M, frontal factors, plan index arrays),
+ * *solve_bytes for lsp_solve with nrhs right-hand sides (Krylov basis,
+ * FFT work arrays, solve buffers).  precision selects the factor type. */
+lsp_status lsp_plan_bytes(const lsp_plan* plan, int precision, int nrhs,
+                          size_t* problem_bytes, size_t* solve_bytes);
+
+/* Set-up steps before the factorisation, all on the GPU:
+ *   kernel table k_t (Section 2.1) with k_0 the cell integral of G,
+ *   spectrum of its (2n)^d circulant embedding,
+ *   the 3^d stencil null vectors alpha_c (eq:Fmin, eq:Emin, eq:Cmin) and
+ *   C_c = alpha_c K(mu_c, mu_c) (Section 2.2),
+ *   the stencil matrix M (eq:ABop) in N x 3^d form.
+ * m_dev: [N] real double medium, read during this call only.
+ * ws_dev / ws_bytes: device workspace of at least problem_bytes; it must
+ * outlive the problem.  stream: a hipStream_t (NULL = default stream).
+ * precision comes from the plan's options.  Errors: LSP_ERR_ARG (w <= 0 or
+ * not finite, null pointers, small workspace), LSP_ERR_HIP. */
+lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev,
+                     void* ws_dev, size_t ws_bytes, void* stream,
+                     lsp_problem** problem);
+void lsp_problem_destroy(lsp_problem* problem);
+
+/* Numeric multifrontal LU of M (Section 2.2, nested dissection and the
+ * multifrontal method), level by level from the leaves, with partial
+ * pivoting inside each front's fully-summed block.  Synchronises the
+ * stream to read the pivot-health flag.  Errors: LSP_ERR_SINGULAR (a pivot
+ * of modulus <= 64 eps times the block's largest entry), LSP_ERR_HIP. */
+lsp_status lsp_factor(lsp_problem* problem);
+
+/* Restarted right-preconditioned GMRES (Section 3.3), one independent
+ * Krylov process per right-hand side run in lockstep, each identical to
+ * its solo run.  rhs_dev: [nrhs][N] complex128 (u_I or g per rhs_kind);
+ * u_dev: [nrhs][N] complex128 output; ws_dev: >= solve_bytes for nrhs;
+ * info_host: [nrhs] (may be NULL).  Synchronises the stream.
+ * Errors: LSP_ERR_STATE (not factored), LSP_ERR_ARG, LSP_ERR_NOCONV. */
+lsp_status lsp_solve(lsp_problem* problem, int nrhs, int rhs_kind,
+                     const void* rhs_dev, void* u_dev, void* ws_dev,
+                     size_t ws_bytes, lsp_rhs_info* info_host);
+
+/* ---- single steps of the path (each enqueued on the problem's stream) ---- */
+
+/* y = x + K (w^2 m .* x)   (eq:lso), by zero-padded FFT convolution.
+ * precision LSP_FP64: x, y complex128; LSP_MIXED: the convolution runs in
+ * complex64 (x, y still complex128).  ws_dev as for lsp_solve(nrhs). */
+lsp_status lsp_apply_op(lsp_problem* problem, int nrhs, int precision,
+                        const void* x_dev, void* y_dev, void* ws_dev, size_t ws_bytes);
+
+/* y = K x  (the plain convolution; g = K(-w^2 m u_I) uses it). */
+lsp_status lsp_apply_K(lsp_problem* problem, int nrhs, int precision,
+                       const void* x_dev, void* y_dev, void* ws_dev, size_t ws_bytes);
+
+/* y = Q x with Q = [A; B] (eq:PC); complex128 in and out. */
+lsp_status lsp_apply_Q(lsp_problem* problem, int nrhs, const void* x_dev, void* y_dev);
+
+/* x = M^{-1} z with the multifrontal factors, complex128 in and out (the
+ * factors' precision is the problem's).  ws_dev as for lsp_solve(nrhs). */
+lsp_status lsp_solve_M(lsp_problem* problem, int nrhs, const void* z_dev, void* x_dev,
+                       void* ws_dev, size_t ws_bytes);
+
+/* x = M^{-1} Q v  (the preconditioner of eq:PC). */
+lsp_status lsp_apply_precond(lsp_problem* problem, int nrhs, const void* v_dev, void* x_dev,
+                             void* ws_dev, size_t ws_bytes);
+
+/* Copies out (synchronising the stream):
+ *   kernel table: (n+1)^d complex128 on the device, index t1 + (n+1) t2 (+ ...);
+ *   stencils: alpha [3^d][3^d] complex128 (padded slot q = sum_a (s_a+1) 3^a,
+ *             zero outside the class), sigma [3^d][3^d] double (singular
+ *             values of each class, descending, zero-padded), C like alpha;
+ *             host pointers, any may be NULL;
+ *   matrix: M as [N][3^d] complex128 on the device (slot as above, zero
+ *             where the neighbour is outside the grid). */
+lsp_status lsp_get_kernel_table(lsp_problem* problem, void* k_dev);
+lsp_status lsp_get_stencils(lsp_problem* problem, double* alpha_host, double* sigma_host,
+                            double* C_host);
+lsp_status lsp_get_matrix(lsp_problem* problem, void* mval_dev);
+
+const char* lsp_status_string(lsp_status s);
+/* Copies the calling thread's last error message (NUL-terminated). */
+void lsp_last_error(char* buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSP_H */

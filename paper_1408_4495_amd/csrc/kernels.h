@@ -1,0 +1,82 @@
+// Launch interfaces shared between the kernel translation units and the ABI layer.
+#pragma once
+
+#include "lsp_common.h"
+#include "plan.h"
+
+namespace lsp {
+
+constexpr int kNbMax = 32;  // widest frontal panel
+
+// ---- Green's table
+void launch_ktable(double2* k, int n, int d, double omega, double2 k0, hipStream_t st);
+void launch_embed(double2* E, const double2* k, int n, int d, hipStream_t st);
+void launch_fold_khat(double2* kh64, float2* kh32, const double2* E, int n, int d, hipStream_t st);
+
+// ---- FFT
+struct FftRadices {
+  int r[16];
+  int npass;
+};
+
+template <typename T>
+struct FftPlanDev {
+  int n, d, L, N, ept;
+  long long wstride;         // work array elements per right-hand side (L^d)
+  FftRadices rad;
+  const cplx<T>* tw;         // exp(-2 pi i k / L), k < L
+  const cplx<T>* khat;       // folded spectrum (n+1)^d, scaled by 1/L^d
+};
+
+// y = [x +] K (w2m .* x), fields complex128 [nrhs][N]; w2m == nullptr means
+// no scaling; W is the [nrhs][L^d] work array in precision T.
+template <typename T>
+void kmatvec(const FftPlanDev<T>& fp, int nrhs, const double2* x, double2* y, const double* w2m, bool add_x,
+             cplx<T>* W, hipStream_t st);
+// In-place forward transform of a full L^d array (one right-hand side).
+template <typename T>
+void full_fft_forward(const FftPlanDev<T>& fp, cplx<T>* W, hipStream_t st);
+
+// ---- stencils
+struct ClassGeom {
+  int s;             // stencil size
+  int off[kMaxStencil][3];
+  int flo[3], fsz[3];  // far-set box: start and size per axis
+  long long F;       // far-set box volume
+  int interior;      // 1 for the all-interior class (mu(0) removed)
+};
+
+void compute_stencils(const double2* ktab, int n, int d, const ClassGeom* geo_dev, int nclass, long long maxF,
+                      double2* partial, int nblk, double2* G, double2* U1, double2* alpha_pad, double2* C_pad,
+                      double* sigma_pad, hipStream_t st);
+void launch_assemble(double2* Mval, const double2* alpha_pad, const double2* C_pad, const double* w2m, int n, int d,
+                     long long N, hipStream_t st);
+template <typename Cx>
+void launch_applyQ(Cx* y, const double2* x, const double2* alpha_pad, int n, int d, long long N, int nrhs,
+                   hipStream_t st);
+
+// ---- multifrontal
+template <typename T>
+struct MfDev {
+  cplx<T>* F;               // front matrices
+  const FrontDev* fronts;
+  const int* idx;
+  const int* cpos;
+  const double2* Mval;      // [N][3^d]
+  int* piv;
+  int* perm;
+  double* pivstat;          // per front: smallest pivot ratio
+};
+
+template <typename T>
+void mf_factor(const MfDev<T>& mf, const Plan& plan, int nb, hipStream_t st);
+template <typename T>
+void mf_solve(const MfDev<T>& mf, const Plan& plan, int nb, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
+              hipStream_t st);
+
+// ---- Krylov helpers (complex128 vectors, [nrhs][N] blocks)
+void launch_widen(double2* y, const float2* x, long long count, hipStream_t st);
+void launch_narrow(float2* y, const double2* x, long long count, hipStream_t st);
+void launch_scale_rhs(double2* y, const double2* x, double s, long long count, hipStream_t st);
+
+}  // namespace lsp

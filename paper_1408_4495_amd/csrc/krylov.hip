@@ -1,0 +1,340 @@
+// Device kernels of restarted right-preconditioned GMRES (the iterative
+// solver of Section 3.3), run as one independent Krylov process per
+// right-hand side.  Vectors are complex128 blocks; a basis is stored as
+// [k][nrhs][N] so that vector k of every right-hand side is one contiguous
+// [nrhs][N] block.  Reductions are two-stage with a fixed block count and a
+// fixed summation order, so a right-hand side's arithmetic does not depend
+// on which other right-hand sides share the batch.
+//
+// Arnoldi uses classical Gram-Schmidt applied twice (CGS2): h = V^H w,
+// w -= V h, h2 = V^H w, w -= V h2, H(:,k) = h + h2, H(k+1,k) = ||w||.  The
+// Hessenberg matrix is reduced by Givens rotations as it grows (the
+// rotation that zeroes H(k+1,k) is c = |a|/r, s = (a/|a|) conj(b)/r with
+// a = H(k,k), b = H(k+1,k), r = sqrt(|a|^2+|b|^2)); |gamma(k+1)| is the
+// residual estimate.
+#include "lsp_common.h"
+#include "krylov.h"
+
+namespace lsp {
+
+namespace {
+
+constexpr int KB = 256;  // threads per block of the reduction kernels
+
+__device__ inline double2 wave_sum(double2 v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_down(v.x, off, 64);
+    v.y += __shfl_down(v.y, off, 64);
+  }
+  return v;
+}
+
+// partial[rhs][blk][i] = sum over this block's chunk of conj(V_i) w, i < nvec.
+// V_i of rhs r is at V + (i * nrhs + r) * N.
+__global__ void __launch_bounds__(KB) dots_partial_kernel(const double2* __restrict__ V, const double2* __restrict__ w,
+                                                          double2* __restrict__ partial, int nvec, long long N,
+                                                          int nrhs, const int* __restrict__ active) {
+  const int r = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  if (active && !active[r]) return;
+  const long long e0 = N * blk / nblk, e1 = N * (blk + 1) / nblk;
+  double2 acc[kMaxVec];
+#pragma unroll
+  for (int i = 0; i < kMaxVec; ++i) acc[i] = make_double2(0, 0);
+  const double2* wr = w + (long long)r * N;
+  for (long long e = e0 + threadIdx.x; e < e1; e += KB) {
+    double2 we = wr[e];
+#pragma unroll
+    for (int i = 0; i < kMaxVec; ++i)
+      if (i < nvec) acc[i] = cadd(acc[i], cmulc(V[((long long)i * nrhs + r) * N + e], we));
+  }
+  __shared__ double2 ws[KB / 64][kMaxVec];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll
+  for (int i = 0; i < kMaxVec; ++i) {
+    if (i < nvec) {
+      double2 s = wave_sum(acc[i]);
+      if (lane == 0) ws[wave][i] = s;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nvec; i += KB) {
+    double2 s = ws[0][i];
+    for (int k = 1; k < KB / 64; ++k) s = cadd(s, ws[k][i]);
+    partial[((long long)r * nblk + blk) * kMaxVec + i] = s;
+  }
+}
+
+// h[rhs][i] = sum_blk partial; mode 0: H(i,k) = h, mode 1: H(i,k) += h,
+// mode 2: norm -> H(k+1,k) = sqrt(re h0), inv[r] = 1/that (0 if zero).
+__global__ void dots_final_kernel(const double2* __restrict__ partial, double2* __restrict__ h,
+                                  double2* __restrict__ H, double* __restrict__ scal, int nvec, int nblk, int k,
+                                  int restart, int mode, const int* __restrict__ active) {
+  const int r = blockIdx.x;
+  if (active && !active[r]) return;
+  for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
+    double2 s = make_double2(0, 0);
+    for (int b = 0; b < nblk; ++b) s = cadd(s, partial[((long long)r * nblk + b) * kMaxVec + i]);
+    h[(long long)r * kMaxVec + i] = s;
+    double2* Hr = H + (long long)r * (restart + 1) * restart;
+    if (mode == 0) Hr[i + (restart + 1) * k] = s;
+    else if (mode == 1) Hr[i + (restart + 1) * k] = cadd(Hr[i + (restart + 1) * k], s);
+    else {
+      double nrm = sqrt(fmax(s.x, 0.0));
+      if (k >= 0) Hr[(k + 1) + (restart + 1) * k] = make_double2(nrm, 0.0);
+      scal[r * kScal + S_NORM] = nrm;
+      scal[r * kScal + S_INV] = nrm > 0 ? 1.0 / nrm : 0.0;
+    }
+  }
+}
+
+// w -= sum_i h_i V_i
+__global__ void __launch_bounds__(KB) axpy_kernel(const double2* __restrict__ V, double2* __restrict__ w,
+                                                  const double2* __restrict__ h, int nvec, long long N, int nrhs,
+                                                  const int* __restrict__ active) {
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  double2 hv[kMaxVec];
+#pragma unroll
+  for (int i = 0; i < kMaxVec; ++i) hv[i] = i < nvec ? h[(long long)r * kMaxVec + i] : make_double2(0, 0);
+  double2* wr = w + (long long)r * N;
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < N; e += (long long)gridDim.x * KB) {
+    double2 s = wr[e];
+#pragma unroll
+    for (int i = 0; i < kMaxVec; ++i)
+      if (i < nvec) s = cfms(s, hv[i], V[((long long)i * nrhs + r) * N + e]);
+    wr[e] = s;
+  }
+}
+
+// y = x * scal[r][S_INV]
+__global__ void scale_kernel(double2* __restrict__ y, const double2* __restrict__ x, const double* __restrict__ scal,
+                             long long N, const int* __restrict__ active) {
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  double s = scal[r * kScal + S_INV];
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += (long long)gridDim.x * blockDim.x)
+    y[(long long)r * N + e] = cscale(x[(long long)r * N + e], s);
+}
+
+// Givens update of column k, one thread per right-hand side.
+__global__ void givens_kernel(double2* __restrict__ H, double2* __restrict__ cs, double2* __restrict__ sn,
+                              double2* __restrict__ gam, double* __restrict__ scal, int k, int restart, int nrhs,
+                              const int* __restrict__ active) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs || (active && !active[r])) return;
+  double2* Hc = H + (long long)r * (restart + 1) * restart + (restart + 1) * k;
+  double2* c = cs + (long long)r * restart;
+  double2* s = sn + (long long)r * restart;
+  double2* g = gam + (long long)r * (restart + 1);
+  for (int i = 0; i < k; ++i) {
+    double2 t = cadd(cmul(c[i], Hc[i]), cmul(s[i], Hc[i + 1]));
+    Hc[i + 1] = csub(cmul(c[i], Hc[i + 1]), cmulc(s[i], Hc[i]));  // -conj(s) H_i + conj(c) H_{i+1}, c real
+    Hc[i] = t;
+  }
+  double2 a = Hc[k], b = Hc[k + 1];
+  double aa = sqrt(a.x * a.x + a.y * a.y), bb = sqrt(b.x * b.x + b.y * b.y);
+  double den = sqrt(aa * aa + bb * bb);
+  double2 ck, sk;
+  if (den == 0.0) { ck = make_double2(1, 0); sk = make_double2(0, 0); }
+  else if (aa == 0.0) { ck = make_double2(0, 0); sk = make_double2(1, 0); }
+  else {
+    ck = make_double2(aa / den, 0);
+    double2 ph = make_double2(a.x / aa, a.y / aa);
+    sk = cscale(cmul(ph, cconj(b)), 1.0 / den);
+  }
+  c[k] = ck; s[k] = sk;
+  Hc[k] = cadd(cmul(ck, a), cmul(sk, b));
+  Hc[k + 1] = make_double2(0, 0);
+  double2 gk = g[k];
+  g[k + 1] = cscale(cmulc(sk, gk), -1.0);   // -conj(s) g_k
+  g[k] = cmul(ck, gk);
+  double2 gn = g[k + 1];
+  scal[r * kScal + S_EST] = sqrt(gn.x * gn.x + gn.y * gn.y);
+  scal[r * kScal + S_DEN] = den;
+}
+
+// y = triu(H(0:k,0:k))^{-1} gam(0:k); ksz[r] = number of steps of rhs r.
+__global__ void backsolve_kernel(const double2* __restrict__ H, const double2* __restrict__ gam, double2* __restrict__ y,
+                                 const int* __restrict__ ksz, int restart, int nrhs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const int k = ksz[r];
+  const double2* Hr = H + (long long)r * (restart + 1) * restart;
+  double2* yr = y + (long long)r * kMaxVec;
+  for (int i = 0; i < kMaxVec; ++i) yr[i] = make_double2(0, 0);
+  for (int i = k - 1; i >= 0; --i) {
+    double2 s = gam[(long long)r * (restart + 1) + i];
+    for (int j = i + 1; j < k; ++j) s = cfms(s, Hr[i + (restart + 1) * j], yr[j]);
+    yr[i] = cdiv(s, Hr[i + (restart + 1) * i]);
+  }
+}
+
+// x += sum_{j < ksz[r]} y_j Z_j
+__global__ void update_kernel(double2* __restrict__ x, const double2* __restrict__ Z, const double2* __restrict__ y,
+                              const int* __restrict__ ksz, long long N, int nrhs) {
+  const int r = blockIdx.y;
+  const int k = ksz[r];
+  if (k == 0) return;
+  double2 yv[kMaxVec];
+#pragma unroll
+  for (int i = 0; i < kMaxVec; ++i) yv[i] = i < k ? y[(long long)r * kMaxVec + i] : make_double2(0, 0);
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += (long long)gridDim.x * blockDim.x) {
+    double2 s = x[(long long)r * N + e];
+#pragma unroll
+    for (int i = 0; i < kMaxVec; ++i)
+      if (i < k) s = cfma(s, yv[i], Z[((long long)i * nrhs + r) * N + e]);
+    x[(long long)r * N + e] = s;
+  }
+}
+
+// r = g - t
+__global__ void sub_kernel(double2* __restrict__ r, const double2* __restrict__ g, const double2* __restrict__ t,
+                           long long count) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (long long)gridDim.x * blockDim.x)
+    r[e] = csub(g[e], t[e]);
+}
+
+// start a cycle: gam = [beta, 0...], clear H, V_0 = r / beta
+__global__ void cycle_init_kernel(double2* __restrict__ H, double2* __restrict__ gam, const double* __restrict__ scal,
+                                  int restart, int nrhs) {
+  const int r = blockIdx.x;
+  for (int i = threadIdx.x; i < (restart + 1) * restart; i += blockDim.x)
+    H[(long long)r * (restart + 1) * restart + i] = make_double2(0, 0);
+  for (int i = threadIdx.x; i <= restart; i += blockDim.x)
+    gam[(long long)r * (restart + 1) + i] = make_double2(i == 0 ? scal[r * kScal + S_NORM] : 0.0, 0.0);
+}
+
+__global__ void widen_kernel(double2* __restrict__ y, const float2* __restrict__ x, long long count) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (long long)gridDim.x * blockDim.x)
+    y[e] = to_c128(x[e]);
+}
+__global__ void narrow_kernel(float2* __restrict__ y, const double2* __restrict__ x, long long count) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (long long)gridDim.x * blockDim.x)
+    y[e] = to_c64(x[e]);
+}
+__global__ void scale_rhs_kernel(double2* __restrict__ y, const double2* __restrict__ x, double s, long long count) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (long long)gridDim.x * blockDim.x)
+    y[e] = cscale(x[e], s);
+}
+
+inline unsigned grid1(long long count, int bs = 256, long long cap = 8192) {
+  long long g = (count + bs - 1) / bs;
+  return (unsigned)std::max<long long>(1, std::min(g, cap));
+}
+
+}  // namespace
+
+int dot_blocks(long long N) {
+  long long b = (N + 4095) / 4096;
+  return (int)std::max<long long>(1, std::min<long long>(b, 128));
+}
+
+void k_dots(const double2* V, const double2* w, double2* partial, double2* h, double2* H, double* scal, int nvec,
+            int k, int restart, int mode, long long N, int nrhs, const int* active, hipStream_t st) {
+  int nblk = dot_blocks(N);
+  hipLaunchKernelGGL(dots_partial_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, V, w, partial, nvec, N, nrhs, active);
+  LSP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(dots_final_kernel, dim3(nrhs), dim3(64), 0, st, partial, h, H, scal, nvec, nblk, k, restart, mode,
+                     active);
+  LSP_HIP(hipGetLastError());
+}
+
+void k_norm(const double2* w, double2* partial, double2* h, double2* H, double* scal, int k, int restart, long long N,
+            int nrhs, const int* active, hipStream_t st) {
+  // ||w||^2 = sum conj(w) w: the dot kernel with V = w and nrhs-strided layout
+  int nblk = dot_blocks(N);
+  hipLaunchKernelGGL(dots_partial_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, w, w, partial, 1, N, nrhs, active);
+  LSP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(dots_final_kernel, dim3(nrhs), dim3(64), 0, st, partial, h, H, scal, 1, nblk, k, restart, 2,
+                     active);
+  LSP_HIP(hipGetLastError());
+}
+
+void k_axpy(const double2* V, double2* w, const double2* h, int nvec, long long N, int nrhs, const int* active,
+            hipStream_t st) {
+  hipLaunchKernelGGL(axpy_kernel, dim3(grid1(N, KB, 1024), nrhs), dim3(KB), 0, st, V, w, h, nvec, N, nrhs, active);
+  LSP_HIP(hipGetLastError());
+}
+
+void k_scale(double2* y, const double2* x, const double* scal, long long N, int nrhs, const int* active,
+             hipStream_t st) {
+  hipLaunchKernelGGL(scale_kernel, dim3(grid1(N, 256, 1024), nrhs), dim3(256), 0, st, y, x, scal, N, active);
+  LSP_HIP(hipGetLastError());
+}
+
+void k_givens(double2* H, double2* cs, double2* sn, double2* gam, double* scal, int k, int restart, int nrhs,
+              const int* active, hipStream_t st) {
+  hipLaunchKernelGGL(givens_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, H, cs, sn, gam, scal, k, restart, nrhs,
+                     active);
+  LSP_HIP(hipGetLastError());
+}
+
+void k_backsolve_update(const double2* H, const double2* gam, double2* y, const int* ksz, double2* x, const double2* Z,
+                        int restart, long long N, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(backsolve_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, H, gam, y, ksz, restart, nrhs);
+  LSP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(update_kernel, dim3(grid1(N, 256, 1024), nrhs), dim3(256), 0, st, x, Z, y, ksz, N, nrhs);
+  LSP_HIP(hipGetLastError());
+}
+
+void k_sub(double2* r, const double2* g, const double2* t, long long count, hipStream_t st) {
+  hipLaunchKernelGGL(sub_kernel, dim3(grid1(count)), dim3(256), 0, st, r, g, t, count);
+  LSP_HIP(hipGetLastError());
+}
+
+void k_cycle_init(double2* H, double2* gam, const double* scal, int restart, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(cycle_init_kernel, dim3(nrhs), dim3(256), 0, st, H, gam, scal, restart, nrhs);
+  LSP_HIP(hipGetLastError());
+}
+
+void launch_widen(double2* y, const float2* x, long long count, hipStream_t st) {
+  hipLaunchKernelGGL(widen_kernel, dim3(grid1(count)), dim3(256), 0, st, y, x, count);
+  LSP_HIP(hipGetLastError());
+}
+void launch_narrow(float2* y, const double2* x, long long count, hipStream_t st) {
+  hipLaunchKernelGGL(narrow_kernel, dim3(grid1(count)), dim3(256), 0, st, y, x, count);
+  LSP_HIP(hipGetLastError());
+}
+void launch_scale_rhs(double2* y, const double2* x, double s, long long count, hipStream_t st) {
+  hipLaunchKernelGGL(scale_rhs_kernel, dim3(grid1(count)), dim3(256), 0, st, y, x, s, count);
+  LSP_HIP(hipGetLastError());
+}
+
+}  // namespace lsp
+
+namespace lsp {
+namespace {
+__global__ void fill_zero_kernel(unsigned int* __restrict__ p, long long words) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < words; e += (long long)gridDim.x * blockDim.x)
+    p[e] = 0u;
+}
+__global__ void fill_double_kernel(double* __restrict__ p, double v, long long count) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (long long)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+__global__ void w2m_kernel(double* __restrict__ out, const double* __restrict__ m, double w2, long long N) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += (long long)gridDim.x * blockDim.x)
+    out[e] = w2 * m[e];
+}
+inline unsigned grid_cap(long long count) {
+  long long g = (count + 255) / 256;
+  return (unsigned)std::max<long long>(1, std::min<long long>(g, 8192));
+}
+}  // namespace
+
+void k_fill_zero(void* p, long long bytes, hipStream_t st) {
+  long long words = bytes / 4;
+  if (words <= 0) return;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_cap(words)), dim3(256), 0, st, (unsigned int*)p, words);
+  LSP_HIP(hipGetLastError());
+}
+void k_fill_double(double* p, double v, long long count, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(fill_double_kernel, dim3(grid_cap(count)), dim3(256), 0, st, p, v, count);
+  LSP_HIP(hipGetLastError());
+}
+void k_w2m(double* out, const double* m, double w2, long long N, hipStream_t st) {
+  hipLaunchKernelGGL(w2m_kernel, dim3(grid_cap(N)), dim3(256), 0, st, out, m, w2, N);
+  LSP_HIP(hipGetLastError());
+}
+}  // namespace lsp

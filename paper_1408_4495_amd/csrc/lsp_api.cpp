@@ -1,0 +1,738 @@
+// C ABI of the library: plan / problem objects, workspace carving, and the
+// orchestration of set-up, factorisation and the GMRES solve.  Every O(N)
+// step runs in the HIP kernels of the other translation units; this file only
+// sequences launches on the problem's stream and reads back per-right-hand-
+// side scalars for the GMRES control decisions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "krylov.h"
+#include "lsp_common.h"
+#include "plan.h"
+
+using namespace lsp;
+
+struct lsp_plan {
+  Plan p;
+  std::vector<ClassGeom> geo;
+  int nclass = 0;
+  long long maxF = 0;
+  int gram_blocks = 1;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lsp_status fail(lsp_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+template <typename F>
+lsp_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    return fail(e.status, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(LSP_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(LSP_ERR_HIP, e.what());
+  }
+}
+
+// Bump allocator over a caller-provided device workspace.  With base == null
+// it only measures.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct ProblemPtrs {
+  double2* ktab;
+  double2* khat64;
+  float2* khat32;
+  double2* tw64;
+  float2* tw32;
+  double* w2m;
+  double2* Mval;
+  ClassGeom* geo;
+  double2* alpha_pad;
+  double2* C_pad;
+  double* sigma_pad;
+  double2* G;
+  double2* U1;
+  double2* partial;
+  double2* E;
+  void* F;
+  FrontDev* fronts;
+  int* idx;
+  int* cpos;
+  int* piv;
+  int* perm;
+  double* pivstat;
+};
+
+size_t layout_problem(const lsp_plan* pl, int precision, void* base, ProblemPtrs* out) {
+  const Plan& P = pl->p;
+  Carver cv(base);
+  ProblemPtrs q{};
+  long long n1d = 1, hd = 1, Ld = 1;
+  for (int a = 0; a < P.d; ++a) { n1d *= P.n + 1; hd *= P.n + 1; Ld *= P.L; }
+  const int S = kMaxStencil;
+  q.ktab = cv.take<double2>(n1d);
+  q.khat64 = cv.take<double2>(hd);
+  q.khat32 = cv.take<float2>(hd);
+  q.tw64 = cv.take<double2>(P.L);
+  q.tw32 = cv.take<float2>(P.L);
+  q.w2m = cv.take<double>(P.N);
+  q.Mval = cv.take<double2>((size_t)P.N * (P.d == 2 ? 9 : 27));
+  q.geo = cv.take<ClassGeom>(pl->nclass);
+  q.alpha_pad = cv.take<double2>((size_t)pl->nclass * S);
+  q.C_pad = cv.take<double2>((size_t)pl->nclass * S);
+  q.sigma_pad = cv.take<double>((size_t)pl->nclass * S);
+  q.G = cv.take<double2>((size_t)pl->nclass * S * S);
+  q.U1 = cv.take<double2>((size_t)pl->nclass * S * S);
+  q.partial = cv.take<double2>((size_t)pl->gram_blocks * pl->nclass * S * S);
+  q.E = cv.take<double2>(Ld);
+  size_t esz = precision == LSP_MIXED ? sizeof(float2) : sizeof(double2);
+  q.F = cv.take<char>((size_t)P.front_elems * esz);
+  q.fronts = cv.take<FrontDev>(P.fronts.size());
+  q.idx = cv.take<int>(P.idx.size());
+  q.cpos = cv.take<int>(P.cpos.size());
+  q.piv = cv.take<int>(P.sum_p);
+  q.perm = cv.take<int>(P.sum_p);
+  q.pivstat = cv.take<double>(P.fronts.size());
+  if (out) *out = q;
+  return cv.off + 256;
+}
+
+struct SolvePtrs {
+  void* W;        // FFT work [nrhs][L^d] complex128-sized
+  void* vbuf;     // front vectors [nrhs][sum(p+q)]
+  void* zq;       // Q-apply output [nrhs][N]
+  void* xs;       // M^{-1} output [nrhs][N]
+  double2* V;     // [restart+1][nrhs][N]
+  double2* Z;     // [restart][nrhs][N]
+  double2* w;     // [nrhs][N]
+  double2* g;
+  double2* r;
+  double2* t;
+  double2* H;     // [nrhs][(restart+1) restart]
+  double2* cs;
+  double2* sn;
+  double2* gam;
+  double2* h;     // [nrhs][kMaxVec]
+  double2* y;
+  double2* partial;
+  double* scal;   // [nrhs][kScal]
+  int* active;
+  int* ksz;
+};
+
+size_t layout_solve(const Plan& P, int nrhs, int restart, bool krylov, void* base, SolvePtrs* out) {
+  Carver cv(base);
+  SolvePtrs s{};
+  long long Ld = 1;
+  for (int a = 0; a < P.d; ++a) Ld *= P.L;
+  const size_t N = P.N;
+  s.W = cv.take<double2>((size_t)nrhs * Ld);
+  s.vbuf = cv.take<double2>((size_t)nrhs * P.sum_pq);
+  s.zq = cv.take<double2>((size_t)nrhs * N);
+  s.xs = cv.take<double2>((size_t)nrhs * N);
+  if (krylov) {
+    s.V = cv.take<double2>((size_t)(restart + 1) * nrhs * N);
+    s.Z = cv.take<double2>((size_t)restart * nrhs * N);
+    s.w = cv.take<double2>((size_t)nrhs * N);
+    s.g = cv.take<double2>((size_t)nrhs * N);
+    s.r = cv.take<double2>((size_t)nrhs * N);
+    s.t = cv.take<double2>((size_t)nrhs * N);
+    s.H = cv.take<double2>((size_t)nrhs * (restart + 1) * restart);
+    s.cs = cv.take<double2>((size_t)nrhs * restart);
+    s.sn = cv.take<double2>((size_t)nrhs * restart);
+    s.gam = cv.take<double2>((size_t)nrhs * (restart + 1));
+    s.h = cv.take<double2>((size_t)nrhs * kMaxVec);
+    s.y = cv.take<double2>((size_t)nrhs * kMaxVec);
+    s.partial = cv.take<double2>((size_t)nrhs * dot_blocks((long long)N) * kMaxVec);
+    s.scal = cv.take<double>((size_t)nrhs * kScal);
+    s.active = cv.take<int>(nrhs);
+    s.ksz = cv.take<int>(nrhs);
+  }
+  if (out) *out = s;
+  return cv.off + 256;
+}
+
+}  // namespace
+
+struct lsp_problem {
+  const lsp_plan* plan = nullptr;
+  int precision = LSP_FP64;
+  double omega = 0.0;
+  hipStream_t st = nullptr;
+  int device = 0;
+  ProblemPtrs d{};
+  FftPlanDev<double> fp64{};
+  FftPlanDev<float> fp32{};
+  int nb = 32;
+  bool factored = false;
+  double min_pivot_ratio = 0.0;
+  double* host_scal = nullptr;  // pinned
+  int* host_int = nullptr;      // pinned
+  int host_cap = 0;
+
+  ~lsp_problem() {
+    if (host_scal) (void)hipHostFree(host_scal);
+    if (host_int) (void)hipHostFree(host_int);
+  }
+
+  void ensure_host(int nrhs) {
+    if (nrhs <= host_cap) return;
+    if (host_scal) { (void)hipHostFree(host_scal); host_scal = nullptr; }
+    if (host_int) { (void)hipHostFree(host_int); host_int = nullptr; }
+    LSP_HIP(hipHostMalloc((void**)&host_scal, sizeof(double) * kScal * nrhs, hipHostMallocDefault));
+    LSP_HIP(hipHostMalloc((void**)&host_int, sizeof(int) * 2 * nrhs, hipHostMallocDefault));
+    host_cap = nrhs;
+  }
+};
+
+namespace {
+
+void build_class_geometry(lsp_plan* pl) {
+  const Plan& P = pl->p;
+  const int d = P.d, n = P.n, b = P.opts.buffer_b;
+  LSP_REQUIRE(b >= 1 && n - b - 1 >= 1, "buffer_b must satisfy 1 <= b <= n-2");
+  pl->nclass = ipow(3, d);
+  pl->geo.assign(pl->nclass, ClassGeom{});
+  pl->maxF = 0;
+  for (int c = 0; c < pl->nclass; ++c) {
+    ClassGeom& g = pl->geo[c];
+    int ct[3] = {0, 0, 0};
+    for (int a = 0; a < d; ++a) ct[a] = (c / ipow(3, a)) % 3;
+    int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+    bool interior = true;
+    for (int a = 0; a < d; ++a) {
+      if (ct[a] == 0) { lo[a] = 0; cnt[a] = 2; g.flo[a] = b + 1; g.fsz[a] = n - b - 1; interior = false; }
+      else if (ct[a] == 1) { lo[a] = -1; cnt[a] = 3; g.flo[a] = -n + 1; g.fsz[a] = 2 * n - 1; }
+      else { lo[a] = -1; cnt[a] = 2; g.flo[a] = -n + 1; g.fsz[a] = n - b - 1; interior = false; }
+    }
+    for (int a = d; a < 3; ++a) { g.flo[a] = 0; g.fsz[a] = 1; }
+    g.s = cnt[0] * cnt[1] * cnt[2];
+    for (int s = 0; s < g.s; ++s) {
+      int r = s;
+      for (int a = 0; a < 3; ++a) {
+        g.off[s][a] = a < d ? lo[a] + r % cnt[a] : 0;
+        r /= cnt[a];
+      }
+    }
+    g.F = 1;
+    for (int a = 0; a < d; ++a) g.F *= g.fsz[a];
+    g.interior = interior ? 1 : 0;
+    pl->maxF = std::max(pl->maxF, g.F);
+  }
+  long long nb = (pl->maxF + 4095) / 4096;
+  pl->gram_blocks = (int)std::max<long long>(1, std::min<long long>(nb, 512));
+}
+
+double2 self_term_host(double h, double omega, int d) {
+  const double pi = 3.14159265358979323846;
+  if (d == 2) {
+    double rho = h / std::sqrt(pi);
+    double z = omega * rho;
+    double j1 = std::cyl_bessel_j(1.0, z), y1 = std::cyl_neumann(1.0, z);
+    // (i pi rho / (2 w)) (J1 + i Y1) - 1/w^2
+    double s = pi * rho / (2.0 * omega);
+    return make_double2(-s * y1 - 1.0 / (omega * omega), s * j1);
+  }
+  double rho = h * std::cbrt(3.0 / (4.0 * pi));
+  double z = omega * rho;
+  double c = std::cos(z), sn = std::sin(z);
+  // (e^{iz}(1 - iz) - 1) / w^2
+  double re = c + z * sn - 1.0, im = sn - z * c;
+  return make_double2(re / (omega * omega), im / (omega * omega));
+}
+
+template <typename T>
+FftPlanDev<T> make_fft_plan(const Plan& P, const cplx<T>* tw, const cplx<T>* khat) {
+  FftPlanDev<T> f{};
+  f.n = P.n; f.d = P.d; f.L = P.L; f.N = P.N;
+  bool has3 = false;
+  for (int r : P.radices) has3 = has3 || r == 3;
+  if (!has3) f.ept = 8;
+  else {
+    int c2 = 0, L = P.L;
+    while (L % 2 == 0) { L /= 2; ++c2; }
+    f.ept = c2 >= 2 ? 12 : 6;
+  }
+  long long Ld = 1;
+  for (int a = 0; a < P.d; ++a) Ld *= P.L;
+  f.wstride = Ld;
+  f.rad.npass = (int)P.radices.size();
+  for (int i = 0; i < f.rad.npass; ++i) f.rad.r[i] = P.radices[i];
+  f.tw = tw; f.khat = khat;
+  return f;
+}
+
+// radices for lengths containing a factor 3 are 4s, a 2, then 3s (EPT 12 or 6)
+void fix_radices(Plan& P) {
+  bool has3 = false;
+  for (int r : P.radices) has3 = has3 || r == 3;
+  if (!has3) return;
+  int L = P.L, c2 = 0, c3 = 0;
+  while (L % 2 == 0) { L /= 2; ++c2; }
+  while (L % 3 == 0) { L /= 3; ++c3; }
+  std::vector<int> rad;
+  int t = c2;
+  while (t >= 2) { rad.push_back(4); t -= 2; }
+  if (t == 1) rad.push_back(2);
+  for (int k = 0; k < c3; ++k) rad.push_back(3);
+  P.radices = rad;
+}
+
+void apply_precond(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2* v, double2* out) {
+  const Plan& P = pb->plan->p;
+  hipStream_t st = pb->st;
+  if (pb->precision == LSP_FP64) {
+    launch_applyQ<double2>((double2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
+    MfDev<double> mf{(double2*)pb->d.F, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+                     pb->d.pivstat};
+    mf_solve<double>(mf, P, pb->nb, nrhs, (const double2*)s.zq, out, (double2*)s.vbuf, st);
+  } else {
+    launch_applyQ<float2>((float2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
+    MfDev<float> mf{(float2*)pb->d.F, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+                    pb->d.pivstat};
+    mf_solve<float>(mf, P, pb->nb, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st);
+    launch_widen(out, (const float2*)s.xs, (long long)nrhs * P.N, st);
+  }
+}
+
+void solve_M(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2* z, double2* x) {
+  const Plan& P = pb->plan->p;
+  hipStream_t st = pb->st;
+  if (pb->precision == LSP_FP64) {
+    MfDev<double> mf{(double2*)pb->d.F, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+                     pb->d.pivstat};
+    mf_solve<double>(mf, P, pb->nb, nrhs, z, x, (double2*)s.vbuf, st);
+  } else {
+    launch_narrow((float2*)s.zq, z, (long long)nrhs * P.N, st);
+    MfDev<float> mf{(float2*)pb->d.F, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+                    pb->d.pivstat};
+    mf_solve<float>(mf, P, pb->nb, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st);
+    launch_widen(x, (const float2*)s.xs, (long long)nrhs * P.N, st);
+  }
+}
+
+// y = x + K(w2m .* x) (op) or K x, in the given precision
+void apply_conv(lsp_problem* pb, const SolvePtrs& s, int nrhs, int precision, const double2* x, double2* y, bool op,
+                const double* w2m) {
+  if (precision == LSP_MIXED)
+    kmatvec<float>(pb->fp32, nrhs, x, y, w2m, op, (float2*)s.W, pb->st);
+  else
+    kmatvec<double>(pb->fp64, nrhs, x, y, w2m, op, (double2*)s.W, pb->st);
+}
+
+void check_ws(const lsp_problem* pb, int nrhs, bool krylov, void* ws, size_t bytes) {
+  LSP_REQUIRE(nrhs >= 1 && nrhs <= pb->plan->p.max_nrhs, "nrhs out of range for this plan");
+  LSP_REQUIRE(ws != nullptr, "null workspace");
+  size_t need = layout_solve(pb->plan->p, nrhs, pb->plan->p.opts.restart, krylov, nullptr, nullptr);
+  LSP_REQUIRE(bytes >= need, "solve workspace too small");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lsp_status_string(lsp_status s) {
+  switch (s) {
+    case LSP_OK: return "ok";
+    case LSP_ERR_ARG: return "invalid argument";
+    case LSP_ERR_OOM: return "out of memory";
+    case LSP_ERR_HIP: return "HIP runtime error";
+    case LSP_ERR_STATE: return "invalid call order";
+    case LSP_ERR_SINGULAR: return "singular pivot";
+    case LSP_ERR_NOCONV: return "GMRES did not converge";
+  }
+  return "unknown status";
+}
+
+void lsp_last_error(char* buf, size_t len) {
+  if (!buf || len == 0) return;
+  size_t k = std::min(len - 1, g_last_error.size());
+  std::memcpy(buf, g_last_error.data(), k);
+  buf[k] = 0;
+}
+
+lsp_status lsp_options_default(lsp_options* o) {
+  if (!o) return fail(LSP_ERR_ARG, "null options");
+  o->tol = 1e-8;
+  o->restart = 30;
+  o->max_iters = 1000;
+  o->precision = LSP_FP64;
+  o->buffer_b = 2;
+  o->leaf = 0;
+  o->panel = 0;
+  return LSP_OK;
+}
+
+lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts, lsp_plan** out) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(out != nullptr, "null plan pointer");
+    *out = nullptr;
+    lsp_options o;
+    if (opts) o = *opts; else lsp_options_default(&o);
+    LSP_REQUIRE(o.tol > 0 && std::isfinite(o.tol), "tol must be positive");
+    LSP_REQUIRE(o.restart >= 1 && o.restart < kMaxVec, "restart must be in [1, 31]");
+    LSP_REQUIRE(o.max_iters >= 1, "max_iters must be >= 1");
+    LSP_REQUIRE(o.precision == LSP_FP64 || o.precision == LSP_MIXED, "unknown precision");
+    LSP_REQUIRE(o.panel == 0 || (o.panel >= 4 && o.panel <= kNbMax), "panel must be 0 or in [4, 32]");
+    std::unique_ptr<lsp_plan> pl(new lsp_plan());
+    build_plan(pl->p, n, d, max_nrhs, o);
+    fix_radices(pl->p);
+    build_class_geometry(pl.get());
+    *out = pl.release();
+    return LSP_OK;
+  });
+}
+
+void lsp_plan_destroy(lsp_plan* plan) { delete plan; }
+
+lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* s) {
+  if (!plan || !s) return fail(LSP_ERR_ARG, "null argument");
+  const Plan& P = plan->p;
+  s->n = P.n; s->d = P.d; s->N = P.N; s->L = P.L;
+  s->nfronts = (int)P.fronts.size();
+  s->nlevels = P.nlevels;
+  s->max_front = P.max_front;
+  s->max_pivots = P.max_p;
+  s->factor_entries = P.factor_entries;
+  s->front_entries = (double)P.front_elems;
+  s->factor_flops = P.flops;
+  return LSP_OK;
+}
+
+lsp_status lsp_plan_bytes(const lsp_plan* plan, int precision, int nrhs, size_t* problem_bytes, size_t* solve_bytes) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(plan != nullptr, "null plan");
+    LSP_REQUIRE(precision == LSP_FP64 || precision == LSP_MIXED, "unknown precision");
+    LSP_REQUIRE(nrhs >= 1 && nrhs <= plan->p.max_nrhs, "nrhs out of range");
+    if (problem_bytes) *problem_bytes = layout_problem(plan, precision, nullptr, nullptr);
+    if (solve_bytes) *solve_bytes = layout_solve(plan->p, nrhs, plan->p.opts.restart, true, nullptr, nullptr);
+    return LSP_OK;
+  });
+}
+
+lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, void* ws_dev, size_t ws_bytes,
+                     void* stream, lsp_problem** out) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(out != nullptr, "null problem pointer");
+    *out = nullptr;
+    LSP_REQUIRE(plan != nullptr && m_dev != nullptr && ws_dev != nullptr, "null argument");
+    LSP_REQUIRE(std::isfinite(omega) && omega > 0, "omega must be positive and finite");
+    const Plan& P = plan->p;
+    const int prec = P.opts.precision;
+    size_t need = layout_problem(plan, prec, nullptr, nullptr);
+    LSP_REQUIRE(ws_bytes >= need, "problem workspace too small");
+    std::unique_ptr<lsp_problem> pb(new lsp_problem());
+    pb->plan = plan;
+    pb->precision = prec;
+    pb->omega = omega;
+    pb->st = (hipStream_t)stream;
+    LSP_HIP(hipGetDevice(&pb->device));
+    pb->nb = P.opts.panel > 0 ? P.opts.panel : kNbMax;
+    char* base = (char*)align_up((size_t)ws_dev, 256);
+    LSP_REQUIRE(ws_bytes - ((size_t)base - (size_t)ws_dev) >= need - 256, "problem workspace too small");
+    layout_problem(plan, prec, base, &pb->d);
+    hipStream_t st = pb->st;
+
+    // plan arrays and class geometry
+    LSP_HIP(hipMemcpyAsync(pb->d.fronts, P.fronts.data(), P.fronts.size() * sizeof(FrontDev), hipMemcpyHostToDevice, st));
+    LSP_HIP(hipMemcpyAsync(pb->d.idx, P.idx.data(), P.idx.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    LSP_HIP(hipMemcpyAsync(pb->d.cpos, P.cpos.data(), P.cpos.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    LSP_HIP(hipMemcpyAsync(pb->d.geo, plan->geo.data(), plan->geo.size() * sizeof(ClassGeom), hipMemcpyHostToDevice,
+                           st));
+    // twiddles exp(-2 pi i k / L) from long double
+    std::vector<double2> tw64(P.L);
+    std::vector<float2> tw32(P.L);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k < P.L; ++k) {
+      long double a = 2.0L * pi * (long double)k / (long double)P.L;
+      tw64[k] = make_double2((double)cosl(a), (double)-sinl(a));
+      tw32[k] = make_float2((float)cosl(a), (float)-sinl(a));
+    }
+    LSP_HIP(hipMemcpyAsync(pb->d.tw64, tw64.data(), P.L * sizeof(double2), hipMemcpyHostToDevice, st));
+    LSP_HIP(hipMemcpyAsync(pb->d.tw32, tw32.data(), P.L * sizeof(float2), hipMemcpyHostToDevice, st));
+    pb->fp64 = make_fft_plan<double>(P, pb->d.tw64, pb->d.khat64);
+    pb->fp32 = make_fft_plan<float>(P, pb->d.tw32, pb->d.khat32);
+
+    // kernel table, medium, spectrum
+    double h = 1.0 / P.n;
+    launch_ktable(pb->d.ktab, P.n, P.d, omega, self_term_host(h, omega, P.d), st);
+    k_w2m(pb->d.w2m, m_dev, omega * omega, P.N, st);
+    launch_embed(pb->d.E, pb->d.ktab, P.n, P.d, st);
+    full_fft_forward<double>(pb->fp64, pb->d.E, st);
+    launch_fold_khat(pb->d.khat64, pb->d.khat32, pb->d.E, P.n, P.d, st);
+    // stencils and the sparse matrix
+    compute_stencils(pb->d.ktab, P.n, P.d, pb->d.geo, plan->nclass, plan->maxF, pb->d.partial, plan->gram_blocks,
+                     pb->d.G, pb->d.U1, pb->d.alpha_pad, pb->d.C_pad, pb->d.sigma_pad, st);
+    launch_assemble(pb->d.Mval, pb->d.alpha_pad, pb->d.C_pad, pb->d.w2m, P.n, P.d, P.N, st);
+    // the host vectors above must stay alive until the copies are done
+    LSP_HIP(hipStreamSynchronize(st));
+    *out = pb.release();
+    return LSP_OK;
+  });
+}
+
+void lsp_problem_destroy(lsp_problem* pb) { delete pb; }
+
+lsp_status lsp_factor(lsp_problem* pb) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(pb != nullptr, "null problem");
+    const Plan& P = pb->plan->p;
+    k_fill_double(pb->d.pivstat, 1e300, (long long)P.fronts.size(), pb->st);
+    if (pb->precision == LSP_FP64) {
+      MfDev<double> mf{(double2*)pb->d.F, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+                       pb->d.pivstat};
+      mf_factor<double>(mf, P, pb->nb, pb->st);
+    } else {
+      MfDev<float> mf{(float2*)pb->d.F, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+                      pb->d.pivstat};
+      mf_factor<float>(mf, P, pb->nb, pb->st);
+    }
+    std::vector<double> ps(P.fronts.size());
+    LSP_HIP(hipMemcpyAsync(ps.data(), pb->d.pivstat, ps.size() * sizeof(double), hipMemcpyDeviceToHost, pb->st));
+    LSP_HIP(hipStreamSynchronize(pb->st));
+    double mn = 1e300;
+    for (double v : ps) mn = std::min(mn, v);
+    pb->min_pivot_ratio = mn;
+    if (!(mn > 0.0)) {
+      pb->factored = false;
+      throw Error(LSP_ERR_SINGULAR, "zero pivot in the multifrontal factorisation");
+    }
+    pb->factored = true;
+    return LSP_OK;
+  });
+}
+
+lsp_status lsp_apply_op(lsp_problem* pb, int nrhs, int precision, const void* x, void* y, void* ws, size_t bytes) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(pb && x && y, "null argument");
+    LSP_REQUIRE(precision == LSP_FP64 || precision == LSP_MIXED, "unknown precision");
+    check_ws(pb, nrhs, false, ws, bytes);
+    SolvePtrs s;
+    layout_solve(pb->plan->p, nrhs, pb->plan->p.opts.restart, false, (void*)align_up((size_t)ws, 256), &s);
+    apply_conv(pb, s, nrhs, precision, (const double2*)x, (double2*)y, true, pb->d.w2m);
+    return LSP_OK;
+  });
+}
+
+lsp_status lsp_apply_K(lsp_problem* pb, int nrhs, int precision, const void* x, void* y, void* ws, size_t bytes) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(pb && x && y, "null argument");
+    LSP_REQUIRE(precision == LSP_FP64 || precision == LSP_MIXED, "unknown precision");
+    check_ws(pb, nrhs, false, ws, bytes);
+    SolvePtrs s;
+    layout_solve(pb->plan->p, nrhs, pb->plan->p.opts.restart, false, (void*)align_up((size_t)ws, 256), &s);
+    apply_conv(pb, s, nrhs, precision, (const double2*)x, (double2*)y, false, nullptr);
+    return LSP_OK;
+  });
+}
+
+lsp_status lsp_apply_Q(lsp_problem* pb, int nrhs, const void* x, void* y) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(pb && x && y, "null argument");
+    LSP_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    const Plan& P = pb->plan->p;
+    launch_applyQ<double2>((double2*)y, (const double2*)x, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, pb->st);
+    return LSP_OK;
+  });
+}
+
+lsp_status lsp_solve_M(lsp_problem* pb, int nrhs, const void* z, void* x, void* ws, size_t bytes) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(pb && z && x, "null argument");
+    if (!pb->factored) throw Error(LSP_ERR_STATE, "lsp_factor has not succeeded on this problem");
+    check_ws(pb, nrhs, false, ws, bytes);
+    SolvePtrs s;
+    layout_solve(pb->plan->p, nrhs, pb->plan->p.opts.restart, false, (void*)align_up((size_t)ws, 256), &s);
+    solve_M(pb, s, nrhs, (const double2*)z, (double2*)x);
+    return LSP_OK;
+  });
+}
+
+lsp_status lsp_apply_precond(lsp_problem* pb, int nrhs, const void* v, void* x, void* ws, size_t bytes) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(pb && v && x, "null argument");
+    if (!pb->factored) throw Error(LSP_ERR_STATE, "lsp_factor has not succeeded on this problem");
+    check_ws(pb, nrhs, false, ws, bytes);
+    SolvePtrs s;
+    layout_solve(pb->plan->p, nrhs, pb->plan->p.opts.restart, false, (void*)align_up((size_t)ws, 256), &s);
+    apply_precond(pb, s, nrhs, (const double2*)v, (double2*)x);
+    return LSP_OK;
+  });
+}
+
+lsp_status lsp_get_kernel_table(lsp_problem* pb, void* k_dev) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(pb && k_dev, "null argument");
+    const Plan& P = pb->plan->p;
+    long long n1d = 1;
+    for (int a = 0; a < P.d; ++a) n1d *= P.n + 1;
+    LSP_HIP(hipMemcpyAsync(k_dev, pb->d.ktab, n1d * sizeof(double2), hipMemcpyDeviceToDevice, pb->st));
+    LSP_HIP(hipStreamSynchronize(pb->st));
+    return LSP_OK;
+  });
+}
+
+lsp_status lsp_get_stencils(lsp_problem* pb, double* alpha, double* sigma, double* C) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(pb != nullptr, "null problem");
+    const int nc = pb->plan->nclass, S = kMaxStencil;
+    if (alpha)
+      LSP_HIP(hipMemcpyAsync(alpha, pb->d.alpha_pad, (size_t)nc * S * sizeof(double2), hipMemcpyDeviceToHost, pb->st));
+    if (C) LSP_HIP(hipMemcpyAsync(C, pb->d.C_pad, (size_t)nc * S * sizeof(double2), hipMemcpyDeviceToHost, pb->st));
+    if (sigma)
+      LSP_HIP(hipMemcpyAsync(sigma, pb->d.sigma_pad, (size_t)nc * S * sizeof(double), hipMemcpyDeviceToHost, pb->st));
+    LSP_HIP(hipStreamSynchronize(pb->st));
+    return LSP_OK;
+  });
+}
+
+lsp_status lsp_get_matrix(lsp_problem* pb, void* mval) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(pb && mval, "null argument");
+    const Plan& P = pb->plan->p;
+    size_t bytes = (size_t)P.N * (P.d == 2 ? 9 : 27) * sizeof(double2);
+    LSP_HIP(hipMemcpyAsync(mval, pb->d.Mval, bytes, hipMemcpyDeviceToDevice, pb->st));
+    LSP_HIP(hipStreamSynchronize(pb->st));
+    return LSP_OK;
+  });
+}
+
+lsp_status lsp_solve(lsp_problem* pb, int nrhs, int rhs_kind, const void* rhs, void* u, void* ws, size_t bytes,
+                     lsp_rhs_info* info) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(pb && rhs && u, "null argument");
+    LSP_REQUIRE(rhs_kind == LSP_RHS_INCIDENT || rhs_kind == LSP_RHS_G, "unknown rhs kind");
+    if (!pb->factored) throw Error(LSP_ERR_STATE, "lsp_factor has not succeeded on this problem");
+    check_ws(pb, nrhs, true, ws, bytes);
+    const Plan& P = pb->plan->p;
+    const lsp_options& o = P.opts;
+    const int R = o.restart;
+    const long long N = P.N, NB = (long long)nrhs * N;
+    hipStream_t st = pb->st;
+    SolvePtrs s;
+    layout_solve(P, nrhs, R, true, (void*)align_up((size_t)ws, 256), &s);
+    pb->ensure_host(nrhs);
+    double2* x = (double2*)u;
+
+    // g
+    if (rhs_kind == LSP_RHS_INCIDENT) {
+      apply_conv(pb, s, nrhs, LSP_FP64, (const double2*)rhs, s.t, false, pb->d.w2m);
+      launch_scale_rhs(s.g, s.t, -1.0, NB, st);
+    } else {
+      LSP_HIP(hipMemcpyAsync(s.g, rhs, NB * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    }
+    k_fill_zero(x, NB * (long long)sizeof(double2), st);
+    LSP_HIP(hipMemcpyAsync(s.r, s.g, NB * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    k_norm(s.r, s.partial, s.h, s.H, s.scal, -1, R, N, nrhs, nullptr, st);
+    LSP_HIP(hipMemcpyAsync(pb->host_scal, s.scal, sizeof(double) * kScal * nrhs, hipMemcpyDeviceToHost, st));
+    LSP_HIP(hipStreamSynchronize(st));
+
+    std::vector<double> gnorm(nrhs), beta(nrhs), est(nrhs, 0.0), target(nrhs);
+    std::vector<int> iters(nrhs, 0), done(nrhs, 0), active(nrhs, 0), ksz(nrhs, 0);
+    for (int r = 0; r < nrhs; ++r) {
+      gnorm[r] = beta[r] = pb->host_scal[r * kScal + S_NORM];
+      done[r] = gnorm[r] == 0.0 || beta[r] <= o.tol * gnorm[r];
+    }
+    const double eta = pb->precision == LSP_MIXED ? 1e-5 : 0.0;
+    auto upload_active = [&]() {
+      for (int r = 0; r < nrhs; ++r) pb->host_int[r] = active[r];
+      LSP_HIP(hipMemcpyAsync(s.active, pb->host_int, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    };
+    while (true) {
+      int nact = 0;
+      for (int r = 0; r < nrhs; ++r) {
+        active[r] = !done[r] && iters[r] < o.max_iters;
+        nact += active[r];
+        ksz[r] = 0;
+        target[r] = std::max(o.tol * gnorm[r], eta * beta[r]);
+      }
+      if (nact == 0) break;
+      upload_active();
+      k_cycle_init(s.H, s.gam, s.scal, R, nrhs, st);
+      k_scale(s.V, s.r, s.scal, N, nrhs, s.active, st);
+      for (int k = 0; k < R; ++k) {
+        double2* Vk = s.V + (size_t)k * NB;
+        double2* Zk = s.Z + (size_t)k * NB;
+        apply_precond(pb, s, nrhs, Vk, Zk);
+        apply_conv(pb, s, nrhs, pb->precision, Zk, s.w, true, pb->d.w2m);
+        k_dots(s.V, s.w, s.partial, s.h, s.H, s.scal, k + 1, k, R, 0, N, nrhs, s.active, st);
+        k_axpy(s.V, s.w, s.h, k + 1, N, nrhs, s.active, st);
+        k_dots(s.V, s.w, s.partial, s.h, s.H, s.scal, k + 1, k, R, 1, N, nrhs, s.active, st);
+        k_axpy(s.V, s.w, s.h, k + 1, N, nrhs, s.active, st);
+        k_norm(s.w, s.partial, s.h, s.H, s.scal, k, R, N, nrhs, s.active, st);
+        k_scale(s.V + (size_t)(k + 1) * NB, s.w, s.scal, N, nrhs, s.active, st);
+        k_givens(s.H, s.cs, s.sn, s.gam, s.scal, k, R, nrhs, s.active, st);
+        LSP_HIP(hipMemcpyAsync(pb->host_scal, s.scal, sizeof(double) * kScal * nrhs, hipMemcpyDeviceToHost, st));
+        LSP_HIP(hipStreamSynchronize(st));
+        int still = 0;
+        for (int r = 0; r < nrhs; ++r) {
+          if (!active[r]) continue;
+          iters[r]++;
+          ksz[r] = k + 1;
+          est[r] = pb->host_scal[r * kScal + S_EST];
+          bool stop = !(est[r] > target[r]) || iters[r] >= o.max_iters || pb->host_scal[r * kScal + S_DEN] == 0.0;
+          if (stop) active[r] = 0;
+          still += active[r];
+        }
+        if (still == 0) break;
+        upload_active();
+      }
+      for (int r = 0; r < nrhs; ++r) pb->host_int[nrhs + r] = ksz[r];
+      LSP_HIP(hipMemcpyAsync(s.ksz, pb->host_int + nrhs, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+      k_backsolve_update(s.H, s.gam, s.y, s.ksz, x, s.Z, R, N, nrhs, st);
+      // true residual in complex128
+      apply_conv(pb, s, nrhs, LSP_FP64, x, s.t, true, pb->d.w2m);
+      k_sub(s.r, s.g, s.t, NB, st);
+      k_norm(s.r, s.partial, s.h, s.H, s.scal, -1, R, N, nrhs, nullptr, st);
+      LSP_HIP(hipMemcpyAsync(pb->host_scal, s.scal, sizeof(double) * kScal * nrhs, hipMemcpyDeviceToHost, st));
+      LSP_HIP(hipStreamSynchronize(st));
+      for (int r = 0; r < nrhs; ++r) {
+        if (done[r]) continue;
+        beta[r] = pb->host_scal[r * kScal + S_NORM];
+        if (beta[r] <= o.tol * gnorm[r]) done[r] = 1;
+      }
+    }
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) {
+      bool conv = gnorm[r] == 0.0 || beta[r] <= o.tol * gnorm[r];
+      all = all && conv;
+      if (info) {
+        info[r].iters = iters[r];
+        info[r].converged = conv ? 1 : 0;
+        info[r].relres_true = gnorm[r] > 0 ? beta[r] / gnorm[r] : 0.0;
+        info[r].relres_est = gnorm[r] > 0 ? est[r] / gnorm[r] : 0.0;
+      }
+    }
+    if (!all) throw Error(LSP_ERR_NOCONV, "GMRES reached max_iters before the tolerance");
+    return LSP_OK;
+  });
+}
+
+}  // extern "C"

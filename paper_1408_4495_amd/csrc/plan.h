@@ -1,0 +1,44 @@
+// Host-side plan: nested-dissection symbolic analysis of the 3^d stencil
+// graph on the n^d grid, and the FFT factorisation of L = 2n.
+#pragma once
+
+#include <vector>
+#include <cstdint>
+#include "lsp_common.h"
+
+namespace lsp {
+
+// One front (supernode) of the multifrontal factorisation.  Its index list
+// is [I | B]: I = the variables it eliminates (a separator plane, or a whole
+// leaf box), B = the halo of its box that lies on ancestor separators.
+// Front matrices are dense, column-major, order p + q.
+struct FrontDev {
+  int p, q;               // fully-summed (pivot) and boundary counts
+  int child0, child1;     // front ids of the children, -1 if absent
+  long long idx_off;      // offset into the concatenated index lists (p+q ints)
+  long long f_off;        // offset of the front matrix, in complex elements
+  long long piv_off;      // offset of its p pivot / permutation entries
+  int level, pad;
+};
+
+struct Plan {
+  int n = 0, d = 0, N = 0, L = 0, max_nrhs = 1;
+  lsp_options opts{};
+  std::vector<FrontDev> fronts;   // sorted by level (leaves first)
+  std::vector<int> idx;           // concatenated [I | B] lists, grid linear indices
+  std::vector<int> cpos;          // per front position: 2 ints, position of the
+                                  // same grid point in child 0 / child 1 front, or -1
+  std::vector<int> level_ptr;     // fronts of level l are [level_ptr[l], level_ptr[l+1])
+  std::vector<int> level_maxp, level_maxpq;
+  int nlevels = 0;
+  long long front_elems = 0;      // sum (p+q)^2
+  long long sum_p = 0, sum_pq = 0;
+  int max_front = 0, max_p = 0;
+  double flops = 0.0, factor_entries = 0.0;
+  std::vector<int> radices;       // FFT radices for L, in pass order
+};
+
+// Builds the plan; throws lsp::Error on invalid input.
+void build_plan(Plan& plan, int n, int d, int max_nrhs, const lsp_options& opts);
+
+}  // namespace lsp

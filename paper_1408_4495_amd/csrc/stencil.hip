@@ -1,0 +1,381 @@
+// Sparsifying stencils (Section 2.2 and Section 3.1).
+//
+// For each of the 3^d position classes c the stencil alpha_c is the unit row
+// vector minimising ||alpha X_c||, X_c = K(mu_c(0), F_c) (eq:Fmin, eq:Emin,
+// eq:Cmin, and the 3D interior / face / edge / corner sets), i.e. the
+// conjugate of the least left singular vector of X_c.  X_c has at most 27
+// rows and up to (2n-1)^d columns, generated on the fly from the |t| kernel
+// table.  It is reduced in two streamed passes:
+//   pass 1: G = X X^H (per-block partial sums, reduced in a fixed order),
+//           Jacobi eigen-decomposition G = U1 diag U1^H;
+//   pass 2: G2 = (U1^H X)(U1^H X)^H, which is nearly diagonal so the rounding
+//           of each entry is relative to its own eigenvalue; Jacobi again
+//           gives U2, and U = U1 U2.
+// Pass 2 restores full relative accuracy of the smallest singular value,
+// which a single Gram pass loses (sigma_min / sigma_max is about 1e-5 .. 1e-3
+// at eight points per wavelength).  sigma_k = sqrt(lambda_k).
+// Normalisation (a reading: the paper fixes alpha only up to a unit scalar):
+// ||alpha|| = 1 and the centre (offset 0) entry real and positive.
+//
+// Then C_c = alpha_c K(mu_c, mu_c) (Section 2.2), the Q apply (eq:PC) and
+// the stencil matrix M = [A + C w^2 m; B] (eq:ABop), stored as [N][3^d].
+#include "lsp_common.h"
+#include "kernels.h"
+
+namespace lsp {
+
+namespace {
+
+constexpr int S = kMaxStencil;  // padded stencil / matrix order
+constexpr int CH = 48;          // far-set columns staged per step
+
+__device__ inline long long ktab_index(const int* t, int n, int d) {
+  long long n1 = n + 1;
+  long long r = t[0] + n1 * t[1];
+  if (d == 3) r += n1 * n1 * t[2];
+  return r;
+}
+
+template <bool PASS2>
+__global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ ktab, int n, int d,
+                                                   const ClassGeom* __restrict__ geo,
+                                                   const double2* __restrict__ U1, double2* __restrict__ partial,
+                                                   int nblk) {
+  __shared__ double2 X[S][CH + 1];
+  __shared__ double2 Z[PASS2 ? S : 1][CH + 1];
+  __shared__ double2 Us[PASS2 ? S * S : 1];
+  const int c = blockIdx.y, blk = blockIdx.x, tid = threadIdx.x;
+  const ClassGeom g = geo[c];
+  const int s = g.s;
+  const long long F = g.F;
+  const long long j0 = F * blk / nblk, j1 = F * (blk + 1) / nblk;
+  if (PASS2) {
+    for (int e = tid; e < S * S; e += blockDim.x) Us[e] = U1[(long long)c * S * S + e];
+  }
+  const int npairs = s * (s + 1) / 2;
+  int pa[2] = {0, 0}, pb[2] = {0, 0};
+  bool own[2] = {false, false};
+  double2 acc[2] = {make_double2(0, 0), make_double2(0, 0)};
+  for (int k = 0; k < 2; ++k) {
+    int p = tid + k * blockDim.x;
+    if (p < npairs) {
+      int a = 0, rem = p;
+      while (rem >= s - a) { rem -= s - a; ++a; }
+      pa[k] = a; pb[k] = a + rem; own[k] = true;
+    }
+  }
+  for (long long base = j0; base < j1; base += CH) {
+    __syncthreads();
+    for (int e = tid; e < s * CH; e += blockDim.x) {
+      int a = e / CH, jj = e % CH;
+      long long jf = base + jj;
+      double2 v = make_double2(0, 0);
+      if (jf < j1) {
+        int j[3], t[3] = {0, 0, 0};
+        long long rem = jf;
+        bool near = true;
+        for (int ax = 0; ax < d; ++ax) {
+          j[ax] = g.flo[ax] + (int)(rem % g.fsz[ax]);
+          rem /= g.fsz[ax];
+          near = near && (j[ax] >= -1 && j[ax] <= 1);
+          t[ax] = abs(g.off[a][ax] - j[ax]);
+        }
+        if (!(g.interior && near)) v = ktab[ktab_index(t, n, d)];
+      }
+      X[a][jj] = v;
+    }
+    __syncthreads();
+    if (PASS2) {
+      for (int e = tid; e < s * CH; e += blockDim.x) {
+        int k = e / CH, jj = e % CH;
+        double2 z = make_double2(0, 0);
+        for (int a = 0; a < s; ++a) z = cadd(z, cmulc(Us[a + S * k], X[a][jj]));
+        Z[k][jj] = z;
+      }
+      __syncthreads();
+    }
+    for (int k = 0; k < 2; ++k) {
+      if (!own[k]) continue;
+      double2 sum = acc[k];
+      for (int jj = 0; jj < CH; ++jj) {
+        double2 u = PASS2 ? Z[pa[k]][jj] : X[pa[k]][jj];
+        double2 w = PASS2 ? Z[pb[k]][jj] : X[pb[k]][jj];
+        sum = cadd(sum, cmulc(w, u));  // u * conj(w)
+      }
+      acc[k] = sum;
+    }
+  }
+  double2* out = partial + ((long long)blk * gridDim.y + c) * S * S;
+  for (int k = 0; k < 2; ++k) {
+    if (!own[k]) continue;
+    out[pa[k] + S * pb[k]] = acc[k];
+    out[pb[k] + S * pa[k]] = cconj(acc[k]);
+  }
+}
+
+__global__ void gram_reduce_kernel(const double2* __restrict__ partial, double2* __restrict__ G, int nblk,
+                                   int nclass) {
+  const int c = blockIdx.x;
+  for (int e = threadIdx.x; e < S * S; e += blockDim.x) {
+    double2 sum = make_double2(0, 0);
+    for (int b = 0; b < nblk; ++b) sum = cadd(sum, partial[((long long)b * nclass + c) * S * S + e]);
+    G[(long long)c * S * S + e] = sum;
+  }
+}
+
+// Cyclic Jacobi on the s x s Hermitian matrix of class blockIdx.x, one wave.
+// A and U are column-major with leading dimension S.  Rotation of the pair
+// (p, q): with g = A(p,q) = |g| e^{i phi}, tau = (A(q,q) - A(p,p)) / (2|g|),
+// t = sign(tau) / (|tau| + sqrt(1 + tau^2)), c = 1/sqrt(1+t^2), s = t c,
+// V = [[c, s], [-s e^{-i phi}, c e^{-i phi}]]; A <- V^H A V, U <- U V.
+// A pair is skipped when |g| <= 1e-17 sqrt(A(p,p) A(q,q)) (relative criterion).
+__device__ void jacobi_eigen(double2* A, double2* U, int s, int lane) {
+  __shared__ int rotated;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (lane == 0) rotated = 0;
+    __syncthreads();
+    for (int p = 0; p < s - 1; ++p) {
+      for (int q = p + 1; q < s; ++q) {
+        double2 gpq = A[p + S * q];
+        double a = A[p + S * p].x, b = A[q + S * q].x;
+        double ag = sqrt(gpq.x * gpq.x + gpq.y * gpq.y);
+        bool skip = !(ag > 1e-17 * sqrt(fabs(a * b))) || ag == 0.0;
+        __syncthreads();
+        if (skip) continue;
+        double ex = gpq.x / ag, ey = gpq.y / ag;  // e^{i phi}
+        double tau = (b - a) / (2.0 * ag);
+        double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+        double2 v10 = make_double2(-sn * ex, sn * ey);   // -s e^{-i phi}
+        double2 v11 = make_double2(cs * ex, -cs * ey);   //  c e^{-i phi}
+        // columns: A(:,p) <- c A(:,p) + v10 A(:,q);  A(:,q) <- s A(:,p) + v11 A(:,q)
+        for (int k = lane; k < s; k += blockDim.x) {
+          double2 xp = A[k + S * p], xq = A[k + S * q];
+          A[k + S * p] = cadd(cscale(xp, cs), cmul(v10, xq));
+          A[k + S * q] = cadd(cscale(xp, sn), cmul(v11, xq));
+          double2 up = U[k + S * p], uq = U[k + S * q];
+          U[k + S * p] = cadd(cscale(up, cs), cmul(v10, uq));
+          U[k + S * q] = cadd(cscale(up, sn), cmul(v11, uq));
+        }
+        __syncthreads();
+        // rows: A(p,:) <- c A(p,:) + conj(v10) A(q,:);  A(q,:) <- s A(p,:) + conj(v11) A(q,:)
+        for (int k = lane; k < s; k += blockDim.x) {
+          double2 xp = A[p + S * k], xq = A[q + S * k];
+          A[p + S * k] = cadd(cscale(xp, cs), cmul(cconj(v10), xq));
+          A[q + S * k] = cadd(cscale(xp, sn), cmul(cconj(v11), xq));
+        }
+        __syncthreads();
+        if (lane == 0) {
+          A[p + S * q] = make_double2(0, 0);
+          A[q + S * p] = make_double2(0, 0);
+          A[p + S * p].y = 0.0;
+          A[q + S * q].y = 0.0;
+          rotated = 1;
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    if (!rotated) break;
+  }
+}
+
+__global__ void __launch_bounds__(64) eigen_kernel(const double2* __restrict__ G, const ClassGeom* __restrict__ geo,
+                                                   double2* __restrict__ Uout, const double2* __restrict__ U1,
+                                                   const double2* __restrict__ ktab, int n, int d, int final_pass,
+                                                   double2* __restrict__ alpha_pad, double2* __restrict__ C_pad,
+                                                   double* __restrict__ sigma_pad) {
+  __shared__ double2 A[S * S];
+  __shared__ double2 U[S * S];
+  __shared__ double2 Uf[S * S];
+  __shared__ double lam[S];
+  __shared__ int order[S];
+  __shared__ double2 alpha[S];
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const ClassGeom g = geo[c];
+  const int s = g.s;
+  for (int e = lane; e < S * S; e += blockDim.x) {
+    A[e] = G[(long long)c * S * S + e];
+    int i = e % S, j = e / S;
+    U[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  jacobi_eigen(A, U, s, lane);
+  if (!final_pass) {
+    for (int e = lane; e < S * S; e += blockDim.x) Uout[(long long)c * S * S + e] = U[e];
+    return;
+  }
+  // U_final = U1 U
+  for (int e = lane; e < S * S; e += blockDim.x) {
+    int i = e % S, j = e / S;
+    double2 sum = make_double2(0, 0);
+    if (i < s && j < s)
+      for (int k = 0; k < s; ++k) sum = cadd(sum, cmul(U1[(long long)c * S * S + i + S * k], U[k + S * j]));
+    Uf[e] = sum;
+  }
+  for (int k = lane; k < S; k += blockDim.x) lam[k] = k < s ? A[k + S * k].x : 0.0;
+  __syncthreads();
+  if (lane == 0) {
+    for (int k = 0; k < s; ++k) order[k] = k;
+    for (int i = 1; i < s; ++i) {  // insertion sort, descending
+      int v = order[i];
+      int j = i - 1;
+      while (j >= 0 && lam[order[j]] < lam[v]) { order[j + 1] = order[j]; --j; }
+      order[j + 1] = v;
+    }
+  }
+  __syncthreads();
+  const int kmin = order[s - 1];
+  // alpha = conj(u_min); locate the centre offset
+  int centre = 0;
+  for (int a = 0; a < s; ++a) {
+    bool z = true;
+    for (int ax = 0; ax < d; ++ax) z = z && g.off[a][ax] == 0;
+    if (z) centre = a;
+  }
+  double2 uc = cconj(Uf[centre + S * kmin]);
+  double mag = sqrt(uc.x * uc.x + uc.y * uc.y);
+  double2 ph = make_double2(uc.x / mag, -uc.y / mag);  // conj(uc)/|uc|
+  double nrm2 = 0.0;
+  for (int a = 0; a < s; ++a) { double2 u = Uf[a + S * kmin]; nrm2 += u.x * u.x + u.y * u.y; }
+  double inv = 1.0 / sqrt(nrm2);
+  for (int a = lane; a < s; a += blockDim.x) alpha[a] = cscale(cmul(cconj(Uf[a + S * kmin]), ph), inv);
+  __syncthreads();
+  // padded outputs
+  for (int e = lane; e < S; e += blockDim.x) {
+    alpha_pad[(long long)c * S + e] = make_double2(0, 0);
+    C_pad[(long long)c * S + e] = make_double2(0, 0);
+    sigma_pad[(long long)c * S + e] = e < s ? sqrt(fmax(lam[order[e]], 0.0)) : 0.0;
+  }
+  __syncthreads();
+  for (int a = lane; a < s; a += blockDim.x) {
+    int slot = 0, m3 = 1;
+    for (int ax = 0; ax < d; ++ax) { slot += (g.off[a][ax] + 1) * m3; m3 *= 3; }
+    alpha_pad[(long long)c * S + slot] = alpha[a];
+    // C(a') = sum_s alpha(s) k_{|s - a'|}
+    double2 sum = make_double2(0, 0);
+    for (int b2 = 0; b2 < s; ++b2) {
+      int t[3] = {0, 0, 0};
+      for (int ax = 0; ax < d; ++ax) t[ax] = abs(g.off[b2][ax] - g.off[a][ax]);
+      sum = cadd(sum, cmul(alpha[b2], ktab[ktab_index(t, n, d)]));
+    }
+    C_pad[(long long)c * S + slot] = sum;
+  }
+}
+
+__device__ inline int point_class(const int* i, int n, int d) {
+  int c = 0, m3 = 1;
+  for (int a = 0; a < d; ++a) {
+    int ca = i[a] == 0 ? 0 : (i[a] == n - 1 ? 2 : 1);
+    c += ca * m3; m3 *= 3;
+  }
+  return c;
+}
+
+// M(i, i+s) = alpha_c(s) + [c interior] C_c(s) w^2 m_{i+s}, as [N][3^d].
+__global__ void assemble_kernel(double2* __restrict__ Mval, const double2* __restrict__ alpha_pad,
+                                const double2* __restrict__ C_pad, const double* __restrict__ w2m, int n, int d,
+                                long long N) {
+  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ns = d == 2 ? 9 : 27;
+  if (id >= N * ns) return;
+  long long pt = id / ns;
+  int slot = (int)(id % ns);
+  int i[3] = {(int)(pt % n), (int)((pt / n) % n), d == 3 ? (int)(pt / ((long long)n * n)) : 0};
+  int c = point_class(i, n, d);
+  int icls = d == 2 ? 4 : 13;
+  int o[3] = {slot % 3 - 1, (slot / 3) % 3 - 1, slot / 9 - 1};
+  bool inside = true;
+  long long nb = 0, st = 1;
+  for (int a = 0; a < d; ++a) {
+    int j = i[a] + o[a];
+    inside = inside && j >= 0 && j < n;
+    nb += (long long)j * st;
+    st *= n;
+  }
+  double2 v = make_double2(0, 0);
+  if (inside) {
+    v = alpha_pad[c * S + slot];
+    if (c == icls) {
+      double2 cc = C_pad[c * S + slot];
+      double w = w2m[nb];
+      v.x += cc.x * w; v.y += cc.y * w;
+    }
+  }
+  Mval[id] = v;
+}
+
+// y_i = sum_s alpha_{c(i)}(s) x_{i+s}, complex128.
+template <typename Cx>
+__global__ void applyQ_kernel(Cx* __restrict__ y, const double2* __restrict__ x, const double2* __restrict__ alpha_pad,
+                              int n, int d, long long N, int nrhs) {
+  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= N * nrhs) return;
+  long long pt = id % N;
+  long long rbase = id - pt;
+  int i[3] = {(int)(pt % n), (int)((pt / n) % n), d == 3 ? (int)(pt / ((long long)n * n)) : 0};
+  int c = point_class(i, n, d);
+  const int ns = d == 2 ? 9 : 27;
+  double2 acc = make_double2(0, 0);
+  for (int slot = 0; slot < ns; ++slot) {
+    int o[3] = {slot % 3 - 1, (slot / 3) % 3 - 1, slot / 9 - 1};
+    bool inside = true;
+    long long nb = 0, st = 1;
+    for (int a = 0; a < d; ++a) {
+      int j = i[a] + o[a];
+      inside = inside && j >= 0 && j < n;
+      nb += (long long)j * st;
+      st *= n;
+    }
+    if (inside) acc = cadd(acc, cmul(alpha_pad[c * S + slot], x[rbase + nb]));
+  }
+  y[id] = from_c128<Cx>(acc);
+}
+
+}  // namespace
+
+void compute_stencils(const double2* ktab, int n, int d, const ClassGeom* geo_dev, int nclass, long long maxF,
+                      double2* partial, int nblk, double2* G, double2* U1, double2* alpha_pad, double2* C_pad,
+                      double* sigma_pad, hipStream_t st) {
+  (void)maxF;
+  dim3 grid(nblk, nclass);
+  hipLaunchKernelGGL(gram_kernel<false>, grid, dim3(256), 0, st, ktab, n, d, geo_dev, (const double2*)nullptr,
+                     partial, nblk);
+  LSP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(nclass), dim3(256), 0, st, partial, G, nblk, nclass);
+  LSP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(eigen_kernel, dim3(nclass), dim3(64), 0, st, G, geo_dev, U1, (const double2*)nullptr, ktab, n,
+                     d, 0, alpha_pad, C_pad, sigma_pad);
+  LSP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(gram_kernel<true>, grid, dim3(256), 0, st, ktab, n, d, geo_dev, U1, partial, nblk);
+  LSP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(nclass), dim3(256), 0, st, partial, G, nblk, nclass);
+  LSP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(eigen_kernel, dim3(nclass), dim3(64), 0, st, G, geo_dev, (double2*)nullptr, U1, ktab, n, d, 1,
+                     alpha_pad, C_pad, sigma_pad);
+  LSP_HIP(hipGetLastError());
+}
+
+void launch_assemble(double2* Mval, const double2* alpha_pad, const double2* C_pad, const double* w2m, int n, int d,
+                     long long N, hipStream_t st) {
+  long long total = N * (d == 2 ? 9 : 27);
+  int bs = 256;
+  hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, Mval, alpha_pad,
+                     C_pad, w2m, n, d, N);
+  LSP_HIP(hipGetLastError());
+}
+
+template <typename Cx>
+void launch_applyQ(Cx* y, const double2* x, const double2* alpha_pad, int n, int d, long long N, int nrhs,
+                   hipStream_t st) {
+  long long total = N * nrhs;
+  int bs = 256;
+  hipLaunchKernelGGL(applyQ_kernel<Cx>, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, y, x, alpha_pad,
+                     n, d, N, nrhs);
+  LSP_HIP(hipGetLastError());
+}
+
+template void launch_applyQ<double2>(double2*, const double2*, const double2*, int, int, long long, int, hipStream_t);
+template void launch_applyQ<float2>(float2*, const double2*, const double2*, int, int, long long, int, hipStream_t);
+
+}  // namespace lsp

@@ -1,0 +1,268 @@
+"""Thin ctypes binding of liblsp.so (the C ABI declared in include/lsp.h).
+
+Argument marshalling only: torch tensors provide device memory (problem and
+solve workspaces) and the HIP stream; every step of the solver runs in the
+library's HIP kernels.  Importing this module does not need a GPU; creating a
+Problem does, and fails loudly when the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblsp.so")
+
+LSP_FP64, LSP_MIXED = 0, 1
+LSP_RHS_INCIDENT, LSP_RHS_G = 0, 1
+STATUS = {0: "LSP_OK", 1: "LSP_ERR_ARG", 2: "LSP_ERR_OOM", 3: "LSP_ERR_HIP",
+          4: "LSP_ERR_STATE", 5: "LSP_ERR_SINGULAR", 6: "LSP_ERR_NOCONV"}
+EXPORTED = ["lsp_options_default", "lsp_plan_create", "lsp_plan_destroy", "lsp_plan_stats_get",
+            "lsp_plan_bytes", "lsp_setup", "lsp_problem_destroy", "lsp_factor", "lsp_solve",
+            "lsp_apply_op", "lsp_apply_K", "lsp_apply_Q", "lsp_solve_M", "lsp_apply_precond",
+            "lsp_get_kernel_table", "lsp_get_stencils", "lsp_get_matrix", "lsp_status_string",
+            "lsp_last_error"]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
+                ("precision", ctypes.c_int), ("buffer_b", ctypes.c_int), ("leaf", ctypes.c_int),
+                ("panel", ctypes.c_int)]
+
+
+class RhsInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int),
+                ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("d", ctypes.c_int), ("N", ctypes.c_int), ("L", ctypes.c_int),
+                ("nfronts", ctypes.c_int), ("nlevels", ctypes.c_int), ("max_front", ctypes.c_int),
+                ("max_pivots", ctypes.c_int), ("factor_entries", ctypes.c_double),
+                ("front_entries", ctypes.c_double), ("factor_flops", ctypes.c_double)]
+
+
+class LspError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load liblsp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1408_4495_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz, ci, cd = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_double
+    sigs = {
+        "lsp_options_default": [ctypes.POINTER(Options)],
+        "lsp_plan_create": [ci, ci, ci, ctypes.POINTER(Options), ctypes.POINTER(vp)],
+        "lsp_plan_stats_get": [vp, ctypes.POINTER(PlanStats)],
+        "lsp_plan_bytes": [vp, ci, ci, ctypes.POINTER(sz), ctypes.POINTER(sz)],
+        "lsp_setup": [vp, cd, vp, vp, sz, vp, ctypes.POINTER(vp)],
+        "lsp_factor": [vp],
+        "lsp_solve": [vp, ci, ci, vp, vp, vp, sz, ctypes.POINTER(RhsInfo)],
+        "lsp_apply_op": [vp, ci, ci, vp, vp, vp, sz],
+        "lsp_apply_K": [vp, ci, ci, vp, vp, vp, sz],
+        "lsp_apply_Q": [vp, ci, vp, vp],
+        "lsp_solve_M": [vp, ci, vp, vp, vp, sz],
+        "lsp_apply_precond": [vp, ci, vp, vp, vp, sz],
+        "lsp_get_kernel_table": [vp, vp],
+        "lsp_get_stencils": [vp, vp, vp, vp],
+        "lsp_get_matrix": [vp, vp],
+    }
+    for name, args in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ci
+    lib.lsp_plan_destroy.argtypes = [vp]
+    lib.lsp_plan_destroy.restype = None
+    lib.lsp_problem_destroy.argtypes = [vp]
+    lib.lsp_problem_destroy.restype = None
+    lib.lsp_status_string.argtypes = [ci]
+    lib.lsp_status_string.restype = ctypes.c_char_p
+    lib.lsp_last_error.argtypes = [ctypes.c_char_p, sz]
+    lib.lsp_last_error.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != 0:
+        buf = ctypes.create_string_buffer(1024)
+        _lib.lsp_last_error(buf, 1024)
+        raise LspError(status, buf.value.decode(errors="replace"))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Symbolic plan for an n^d grid (host-side nested dissection)."""
+
+    def __init__(self, n, d, max_nrhs=1, tol=1e-8, restart=30, max_iters=1000, precision="fp64",
+                 buffer_b=2, leaf=0, panel=0):
+        lib = load()
+        o = Options()
+        _check(lib.lsp_options_default(ctypes.byref(o)))
+        o.tol, o.restart, o.max_iters = tol, restart, max_iters
+        o.precision = LSP_MIXED if precision in ("mixed", LSP_MIXED) else LSP_FP64
+        o.buffer_b, o.leaf, o.panel = buffer_b, leaf, panel
+        self.opts = o
+        self.n, self.d, self.max_nrhs = n, d, max_nrhs
+        self.precision = o.precision
+        h = ctypes.c_void_p()
+        _check(lib.lsp_plan_create(n, d, max_nrhs, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def bytes(self, nrhs=1, precision=None):
+        prec = self.precision if precision is None else precision
+        pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_lib.lsp_plan_bytes(self._h, prec, nrhs, ctypes.byref(pb), ctypes.byref(sb)))
+        return pb.value, sb.value
+
+    def stats(self):
+        s = PlanStats()
+        _check(_lib.lsp_plan_stats_get(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in PlanStats._fields_}
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.lsp_plan_destroy(self._h)
+            self._h = None
+
+
+class Problem:
+    """Set-up (kernel table, spectrum, stencils, M) on the GPU; factor; solve.
+
+    m: real medium of length n^d (numpy or torch); device memory comes from
+    torch; work is enqueued on `stream` (default: torch's current stream)."""
+
+    def __init__(self, plan, omega, m, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.plan = plan
+        self.device = torch.device(device)
+        if not torch.cuda.is_available():
+            raise RuntimeError("a GPU is required")
+        lib = load()
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        N = plan.n ** plan.d
+        m_t = torch.as_tensor(np.asarray(m, dtype=np.float64) if not isinstance(m, torch.Tensor) else m)
+        m_t = m_t.to(device=self.device, dtype=torch.float64).contiguous()
+        if m_t.numel() != N:
+            raise ValueError("medium has the wrong length")
+        pbytes, _ = plan.bytes(1)
+        self.ws = torch.empty(pbytes, dtype=torch.uint8, device=self.device)
+        self._solve_ws = None
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.lsp_setup(plan._h, float(omega), _ptr(m_t), _ptr(self.ws), pbytes,
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.omega = float(omega)
+        self.N = N
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.lsp_problem_destroy(self._h)
+            self._h = None
+
+    # -- helpers
+    def _work(self, nrhs):
+        _, sb = self.plan.bytes(nrhs)
+        if self._solve_ws is None or self._solve_ws.numel() < sb:
+            self._solve_ws = self.torch.empty(sb, dtype=self.torch.uint8, device=self.device)
+        return self._solve_ws
+
+    def _field(self, x):
+        t = self.torch
+        x = t.as_tensor(x) if not isinstance(x, t.Tensor) else x
+        x = x.to(device=self.device, dtype=t.complex128).contiguous()
+        if x.dim() == 1:
+            x = x.reshape(1, -1)
+        if x.shape[1] != self.N:
+            raise ValueError("field has the wrong length")
+        return x
+
+    # -- API
+    def factor(self):
+        _check(_lib.lsp_factor(self._h))
+
+    def solve(self, rhs, kind="incident"):
+        x = self._field(rhs)
+        nrhs = x.shape[0]
+        u = self.torch.empty_like(x)
+        ws = self._work(nrhs)
+        info = (RhsInfo * nrhs)()
+        k = LSP_RHS_INCIDENT if kind == "incident" else LSP_RHS_G
+        st = _lib.lsp_solve(self._h, nrhs, k, _ptr(x), _ptr(u), _ptr(ws), ws.numel(), info)
+        infos = [{"iters": i.iters, "converged": bool(i.converged), "relres_true": i.relres_true,
+                  "relres_est": i.relres_est} for i in info]
+        if st != 0 and st != 6:
+            _check(st)
+        return u, infos, st
+
+    def apply_op(self, x, precision=LSP_FP64):
+        x = self._field(x)
+        y = self.torch.empty_like(x)
+        ws = self._work(x.shape[0])
+        _check(_lib.lsp_apply_op(self._h, x.shape[0], precision, _ptr(x), _ptr(y), _ptr(ws), ws.numel()))
+        return y
+
+    def apply_K(self, x, precision=LSP_FP64):
+        x = self._field(x)
+        y = self.torch.empty_like(x)
+        ws = self._work(x.shape[0])
+        _check(_lib.lsp_apply_K(self._h, x.shape[0], precision, _ptr(x), _ptr(y), _ptr(ws), ws.numel()))
+        return y
+
+    def apply_Q(self, x):
+        x = self._field(x)
+        y = self.torch.empty_like(x)
+        _check(_lib.lsp_apply_Q(self._h, x.shape[0], _ptr(x), _ptr(y)))
+        return y
+
+    def solve_M(self, z):
+        z = self._field(z)
+        x = self.torch.empty_like(z)
+        ws = self._work(z.shape[0])
+        _check(_lib.lsp_solve_M(self._h, z.shape[0], _ptr(z), _ptr(x), _ptr(ws), ws.numel()))
+        return x
+
+    def apply_precond(self, v):
+        v = self._field(v)
+        x = self.torch.empty_like(v)
+        ws = self._work(v.shape[0])
+        _check(_lib.lsp_apply_precond(self._h, v.shape[0], _ptr(v), _ptr(x), _ptr(ws), ws.numel()))
+        return x
+
+    def kernel_table(self):
+        t = self.torch
+        k = t.empty((self.plan.n + 1) ** self.plan.d, dtype=t.complex128, device=self.device)
+        _check(_lib.lsp_get_kernel_table(self._h, _ptr(k)))
+        return k
+
+    def stencils(self):
+        nc = 3 ** self.plan.d
+        alpha = np.zeros(nc * 27, dtype=np.complex128)
+        C = np.zeros(nc * 27, dtype=np.complex128)
+        sigma = np.zeros(nc * 27, dtype=np.float64)
+        _check(_lib.lsp_get_stencils(self._h, alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     sigma.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     C.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return alpha.reshape(nc, 27), sigma.reshape(nc, 27), C.reshape(nc, 27)
+
+    def matrix(self):
+        t = self.torch
+        ns = 3 ** self.plan.d
+        M = t.empty((self.N, ns), dtype=t.complex128, device=self.device)
+        _check(_lib.lsp_get_matrix(self._h, _ptr(M)))
+        return M

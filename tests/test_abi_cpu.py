@@ -1,0 +1,102 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol include/lsp.h declares, validates arguments, and plans nested
+dissection with the expected structure."""
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1408_4495_amd as pkg
+from paper_1408_4495_amd import lsp as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lsp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lsp_[A-Za-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_1408_4495_amd import build
+        build.build()
+    return L.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _declared()
+    assert set(declared) == set(L.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (lsp_[A-Za-z_]+)\b", out))
+    for name in declared:
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_status_strings(lib):
+    for code in range(7):
+        assert lib.lsp_status_string(code)
+
+
+@pytest.mark.parametrize("n,d,msg", [(3, 2, "n must"), (32, 4, "d must"), (5000, 2, "n must"),
+                                     (14, 2, "factor")])
+def test_plan_rejects_bad_shapes(lib, n, d, msg):
+    with pytest.raises(L.LspError) as e:
+        L.Plan(n, d)
+    assert e.value.status == 1 and msg in str(e.value)
+
+
+def test_plan_rejects_bad_options(lib):
+    with pytest.raises(L.LspError):
+        L.Plan(32, 2, restart=0)
+    with pytest.raises(L.LspError):
+        L.Plan(32, 2, restart=40)
+    with pytest.raises(L.LspError):
+        L.Plan(32, 2, buffer_b=31)
+    with pytest.raises(L.LspError):
+        L.Plan(32, 2, panel=64)
+    with pytest.raises(L.LspError):
+        L.Plan(32, 2, max_nrhs=0)
+
+
+@pytest.mark.parametrize("n,d,fronts,maxf", [(32, 2, 31, 81), (256, 2, 2047, 385),
+                                             (64, 3, 8191, 6144), (48, 3, 8191, 3456)])
+def test_nested_dissection_structure(lib, n, d, fronts, maxf):
+    """Geometric nested dissection with 1-wide separators: every grid point is
+    eliminated once (the plan checks sum p = N and that each child's boundary
+    lies in its parent front), and the tree matches the box recursion."""
+    s = L.Plan(n, d).stats()
+    assert s["N"] == n ** d and s["L"] == 2 * n
+    assert s["nfronts"] == fronts and s["max_front"] == maxf
+    assert s["max_pivots"] >= n ** (d - 1)      # the top separator is a full line / plane
+    assert s["factor_flops"] > 0 and s["factor_entries"] <= s["front_entries"]
+
+
+def test_plan_bytes_grow_with_rhs(lib):
+    p = L.Plan(64, 2, max_nrhs=8)
+    pb1, sb1 = p.bytes(1)
+    pb8, sb8 = p.bytes(8)
+    assert pb1 == pb8 and sb8 > 7 * sb1 * 0.9
+    pm, _ = p.bytes(1, precision=L.LSP_MIXED)
+    assert pm < pb1
+    with pytest.raises(L.LspError):
+        p.bytes(9)
+
+
+def test_setup_rejects_bad_arguments_without_touching_gpu(lib):
+    import ctypes
+    p = L.Plan(16, 2)
+    h = ctypes.c_void_p()
+    # null medium / workspace and non-positive omega are rejected before any HIP call
+    st = lib.lsp_setup(p._h, 5.0, None, None, 0, None, ctypes.byref(h))
+    assert st == 1
+    st = lib.lsp_setup(p._h, -1.0, ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 40, None, ctypes.byref(h))
+    assert st == 1
+    buf = ctypes.create_string_buffer(256)
+    lib.lsp_last_error(buf, 256)
+    assert b"omega" in buf.value
+    assert lib.lsp_factor(None) == 1

@@ -1,0 +1,174 @@
+"""GPU parity: each step of the HIP path, called through the C ABI, against
+the CPU oracle on the same seeded inputs.  Tolerances are relative and are
+derived from the arithmetic (FP64 rounding of each step, or FP32 for the
+mixed-precision convolution), as listed in each test."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.greens import kernel_table
+from oracle.operator import apply_K_direct, Operator, dense_K
+from oracle.stencil import all_stencils, slot, class_offsets
+from oracle.sparse import build_QM, Preconditioner
+from oracle.solve import OracleProblem
+
+pytestmark = pytest.mark.gpu
+
+
+def _lsp():
+    import torch
+    from paper_1408_4495_amd import lsp
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lsp.load()
+    return lsp, torch
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+def _problem(n, d, omega, m, **kw):
+    lsp, torch = _lsp()
+    plan = lsp.Plan(n, d, **kw)
+    return lsp, torch, plan, lsp.Problem(plan, omega, m)
+
+
+@pytest.mark.parametrize("n,d", [(32, 2), (256, 2), (16, 3), (48, 2)])
+def test_kernel_table(n, d):
+    """Own Bessel/Hankel evaluation vs scipy (AMOS): entries agree to 2e-13 of
+    max|k| and to 1e-11 relative entrywise (arguments up to 0.79 n sqrt(d))."""
+    omega = 2 * np.pi * n / 8
+    lsp, torch, plan, pb = _problem(n, d, omega, np.zeros(n ** d))
+    k_gpu = pb.kernel_table().cpu().numpy()
+    k_ref = kernel_table(n, d, omega).transpose(tuple(range(d))[::-1]).reshape(-1)
+    err = np.abs(k_gpu - k_ref)
+    assert err.max() <= 2e-13 * np.abs(k_ref).max()
+    assert np.max(err / np.abs(k_ref)) <= 1e-11
+
+
+@pytest.mark.parametrize("n,d", [(32, 2), (48, 2), (64, 2), (12, 3), (16, 3)])
+def test_K_matvec_fp64(n, d):
+    """FFT convolution (Stockham, radix 8/4/2/3) vs direct O(N^2) summation:
+    relative L2 error <= 1e-12 (FP64 FFT error ~ eps log2(L^d))."""
+    omega = 2 * np.pi * n / 8
+    lsp, torch, plan, pb = _problem(n, d, omega, np.zeros(n ** d), max_nrhs=3)
+    v = synth.random_complex((3, n ** d), seed=n + d)
+    y = pb.apply_K(v).cpu().numpy()
+    y_ref = apply_K_direct(v, n, d, omega)
+    assert _rel(y, y_ref) <= 1e-12
+
+
+@pytest.mark.parametrize("n,d", [(64, 2), (16, 3)])
+def test_K_matvec_mixed(n, d):
+    """complex64 convolution: relative L2 error <= 2e-6 (FP32 eps ~ 6e-8 times log2 L^d)."""
+    omega = 2 * np.pi * n / 8
+    lsp, torch, plan, pb = _problem(n, d, omega, np.zeros(n ** d), max_nrhs=2)
+    v = synth.random_complex((2, n ** d), seed=7)
+    y = pb.apply_K(v, precision=lsp.LSP_MIXED).cpu().numpy()
+    y_ref = apply_K_direct(v, n, d, omega)
+    assert _rel(y, y_ref) <= 2e-6
+
+
+@pytest.mark.parametrize("key", ["c1"])
+def test_operator_apply(key):
+    """y = x + K(w^2 m x) vs the oracle operator, FP64, <= 1e-12."""
+    w = synth.workload(key)
+    n, d, omega, m = w["n"], w["d"], w["omega"], w["m"]
+    lsp, torch, plan, pb = _problem(n, d, omega, m)
+    x = synth.random_complex(n ** d, seed=3)
+    y = pb.apply_op(x).cpu().numpy()[0]
+    y_ref = Operator(n, d, omega, m).apply(x)
+    assert _rel(y, y_ref) <= 1e-12
+
+
+def _gpu_stencil_checks(pb, n, d, omega, tol_sig=1e-9, tol_alpha=1e-9):
+    alpha, sigma, C = pb.stencils()
+    kt = kernel_table(n, d, omega)
+    sts = all_stencils(kt, d, n, b=2)
+    for st in sts:
+        sl = slot(st.offsets)
+        a_gpu = alpha[st.c, sl]
+        s = st.offsets.shape[0]
+        # singular values, all of them, relative to their own size
+        assert np.all(np.abs(sigma[st.c, :s] - st.sigma) <= tol_sig * st.sigma + 1e-15 * st.sigma[0])
+        # same normalisation (unit norm, real positive centre)
+        assert abs(abs(np.vdot(a_gpu, st.alpha)) - 1) <= 1e-12
+        assert np.max(np.abs(a_gpu - st.alpha)) <= tol_alpha
+        assert np.max(np.abs(C[st.c, sl] - st.C)) <= tol_alpha * np.max(np.abs(st.C))
+        other = np.setdiff1d(np.arange(27), sl)
+        assert np.all(alpha[st.c, other] == 0)
+    return sts
+
+
+@pytest.mark.parametrize("n,d", [(32, 2), (64, 2), (12, 3)])
+def test_stencils(n, d):
+    """Two-pass Gram + Jacobi null vectors vs dense SVD: every singular value to
+    1e-9 relative, alpha and C entrywise to 1e-9 (same phase convention)."""
+    omega = 2 * np.pi * n / 8
+    lsp, torch, plan, pb = _problem(n, d, omega, np.zeros(n ** d))
+    _gpu_stencil_checks(pb, n, d, omega)
+
+
+@pytest.mark.parametrize("n,d", [(32, 2), (12, 3)])
+def test_Q_and_M(n, d):
+    """Q apply and the assembled M = [A + C w^2 m; B] vs the oracle's sparse matrices."""
+    omega = 2 * np.pi * n / 8
+    m = synth.medium_single_bump(n, d, 0.2, 0.15)
+    lsp, torch, plan, pb = _problem(n, d, omega, m, max_nrhs=2)
+    sts = all_stencils(kernel_table(n, d, omega), d, n, b=2)
+    Q, M = build_QM(n, d, omega, m, sts)
+    x = synth.random_complex((2, n ** d), seed=5)
+    y = pb.apply_Q(x).cpu().numpy()
+    assert _rel(y, (Q @ x.T).T) <= 1e-12
+    Mv = pb.matrix().cpu().numpy()            # [N][3^d]
+    Md = M.toarray()
+    I = np.stack([(np.arange(n ** d) // n ** a) % n for a in range(d)], axis=1)
+    for i in range(0, n ** d, max(1, n ** d // 97)):
+        for q in range(3 ** d):
+            o = np.array([(q // 3 ** a) % 3 - 1 for a in range(d)])
+            j = I[i] + o
+            if np.all((j >= 0) & (j < n)):
+                jl = int(np.sum(j * n ** np.arange(d)))
+                assert abs(Mv[i, q] - Md[i, jl]) <= 1e-12 * np.abs(Md).max()
+            else:
+                assert Mv[i, q] == 0
+
+
+@pytest.mark.parametrize("n,d,prec,tol", [(32, 2, "fp64", 1e-10), (64, 2, "fp64", 1e-10), (12, 3, "fp64", 1e-10),
+                                          (64, 2, "mixed", 1e-4)])
+def test_solve_M_vs_superlu(n, d, prec, tol):
+    """Multifrontal LU + triangular solves vs SuperLU: M^{-1} z, FP64 to 1e-10
+    relative (kappa(M)-scaled rounding), complex64 fronts to 1e-4."""
+    omega = 2 * np.pi * n / 8
+    m = synth.medium_single_bump(n, d, 0.25, 0.12)
+    lsp, torch, plan, pb = _problem(n, d, omega, m, max_nrhs=2, precision=prec)
+    pb.factor()
+    sts = all_stencils(kernel_table(n, d, omega), d, n, b=2)
+    Q, M = build_QM(n, d, omega, m, sts)
+    P = Preconditioner(Q, M)
+    z = synth.random_complex((2, n ** d), seed=9)
+    x = pb.solve_M(z).cpu().numpy()
+    x_ref = np.stack([P.solve_M(z[r]) for r in range(2)])
+    assert _rel(x, x_ref) <= tol
+    v = pb.apply_precond(z).cpu().numpy()
+    v_ref = np.stack([P(z[r]) for r in range(2)])
+    assert _rel(v, v_ref) <= tol
+
+
+def test_c1_end_to_end_fp64():
+    """2D n=32 workload: GPU FP64 GMRES vs the oracle: solution to 1e-8
+    relative, iteration count within 1, true residual <= 1e-8."""
+    w = synth.workload("c1")
+    n, d, omega, m = w["n"], w["d"], w["omega"], w["m"]
+    lsp, torch, plan, pb = _problem(n, d, omega, m)
+    pb.factor()
+    u, info, st = pb.solve(w["uI"])
+    assert st == 0 and info[0]["converged"] and info[0]["relres_true"] <= 1e-8
+    ref = OracleProblem(n, d, omega, m).solve(w["uI"][0])
+    assert _rel(u.cpu().numpy()[0], ref.x) <= 1e-8
+    assert abs(info[0]["iters"] - ref.iters) <= 1
+    # the dense direct solve of the discrete system
+    K = dense_K(n, d, omega)
+    A = np.eye(n ** d) + K * (omega ** 2 * m)[None, :]
+    u_star = np.linalg.solve(A, K @ (-omega ** 2 * m * w["uI"][0]))
+    assert _rel(u.cpu().numpy()[0], u_star) <= np.linalg.cond(A) * 1e-8
