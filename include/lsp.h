@@ -69,13 +69,13 @@ typedef enum {
 
 typedef struct {
   double tol;        /* relative residual ||g - A u|| / ||g|| to reach (1e-8) */
-  int restart;       /* GMRES restart length (30), 1..64 */
+  int restart;       /* GMRES restart length (30), 1..31 */
   int max_iters;     /* total Arnoldi steps allowed per right-hand side (1000) */
   int precision;     /* lsp_precision (LSP_FP64) */
   int buffer_b;      /* b of Section 3.1: boundary far sets exclude offsets
                         within b of the boundary plane (2); 1 <= b < n/2 */
   int leaf;          /* nested-dissection leaf side in grid points (0 = auto) */
-  int panel;         /* frontal LU panel width, 0 = auto, else 8..64 */
+  int panel;         /* frontal LU panel width: 0 = auto (32) or 32 */
 } lsp_options;
 
 typedef struct {
@@ -92,6 +92,11 @@ typedef struct {
   double factor_entries;      /* stored L and U entries over all fronts */
   double front_entries;       /* sum of squared front orders (storage) */
   double factor_flops;        /* real flops of the numeric factorisation */
+  double sweep_entries;       /* factor entries one forward (or backward) sweep
+                                 reads: panels below / right of each diagonal
+                                 block plus the inverted diagonal blocks */
+  double update_flops;        /* real flops of the trailing-update products
+                                 F22 -= L21 U12 (the MFMA part of the factor) */
 } lsp_plan_stats;
 
 typedef struct lsp_plan lsp_plan;        /* opaque, host-side */
@@ -110,6 +115,17 @@ lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts,
                            lsp_plan** plan);
 void lsp_plan_destroy(lsp_plan* plan);
 lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* stats);
+
+/* Trailing-update tile shape (32, 64 or 128: square MFMA tile of the
+ * F22 -= L21 U12 products) per elimination-tree level, leaves first.  The
+ * plan starts with a size heuristic; an autotuner may replace it.  Setting
+ * tiles changes only the speed of later lsp_factor calls of problems built
+ * on this plan, never their results' meaning (the products are the same,
+ * rounding order aside).  get: copies min(cap, nlevels) entries and returns
+ * LSP_OK.  set: n must equal nlevels and every entry be 32, 64 or 128,
+ * else LSP_ERR_ARG.  Not thread-safe against a concurrent lsp_factor. */
+lsp_status lsp_plan_get_tiles(const lsp_plan* plan, int* tiles, int cap);
+lsp_status lsp_plan_set_tiles(lsp_plan* plan, const int* tiles, int n);
 
 /* Device bytes the caller must provide: *problem_bytes for lsp_setup (kernel
  * table, spectrum, stencils, matrix M, frontal factors, plan index arrays),
@@ -187,6 +203,19 @@ lsp_status lsp_get_kernel_table(lsp_problem* problem, void* k_dev);
 lsp_status lsp_get_stencils(lsp_problem* problem, double* alpha_host, double* sigma_host,
                             double* C_host);
 lsp_status lsp_get_matrix(lsp_problem* problem, void* mval_dev);
+
+/* ---- kernel timing (profiling aid) ----
+ * When enabled, every kernel launch of the library is bracketed by two HIP
+ * events recorded on the stream the kernel runs on.  lsp_timing_count()
+ * waits for the recorded events and returns the number of distinct kernels
+ * seen (-1 on a HIP error); lsp_timing_get(i, ...) reports kernel i's name
+ * (with a [c128]/[c64] tag for templated kernels), the summed event-to-event
+ * milliseconds and the launch count.  Process-wide, thread-safe; adds a few
+ * microseconds per launch while enabled. */
+lsp_status lsp_timing_enable(int enable);
+lsp_status lsp_timing_reset(void);
+int lsp_timing_count(void);
+lsp_status lsp_timing_get(int i, char* name, size_t len, double* total_ms, long long* launches);
 
 const char* lsp_status_string(lsp_status s);
 /* Copies the calling thread's last error message (NUL-terminated). */

@@ -137,6 +137,11 @@ __device__ inline void fft_line(cplx<T>* s, int L, int P, int t, const cplx<T>* 
 
 __device__ inline int fold(int k, int L) { return k <= L / 2 ? k : L - k; }
 
+inline const char* fft_mode_name(int mode) {
+  static const char* names[4] = {"fft_axis", "fft_first", "fft_conv", "fft_last"};
+  return names[mode & 3];
+}
+
 // Generic line kernel.  Lines are indexed by (c, o): c in [0, ncols) runs over
 // LPW consecutive lines per workgroup, o over blockIdx.y; rhs over blockIdx.z.
 // Element e of line (c, o) of the work array sits at c*cs + o*os + e*es.
@@ -283,10 +288,12 @@ __global__ void __launch_bounds__(1024) fft_lines_kernel(cplx<T>* __restrict__ W
 
 template <typename T>
 int lines_per_wg(int L, int P) {
+  // up to 132 KB of the 160 KB LDS a gfx950 workgroup may use; a power of two
+  // so that strided passes read aligned runs of consecutive lines
   size_t per_line = (size_t)(L + 1) * sizeof(cplx<T>);
-  int lpw = (int)((64 * 1024) / per_line);
-  lpw = std::max(1, std::min(lpw, 16));
-  while (lpw > 1 && lpw * P > 1024) --lpw;
+  int cap = (int)((132 * 1024) / per_line);
+  int lpw = 1;
+  while (lpw * 2 <= std::min(cap, 16) && lpw * 2 * P <= 1024) lpw *= 2;
   return lpw;
 }
 
@@ -303,9 +310,8 @@ void launch_lines(const FftPlanDev<T>& fp, cplx<T>* W, const double2* x, double2
   dim3 grid((ncols + a.LPW - 1) / a.LPW, nouter, nrhs);
   dim3 block(a.LPW * a.P);
   size_t lds = (size_t)a.LPW * a.Lp * sizeof(cplx<T>);
-  hipLaunchKernelGGL((fft_lines_kernel<T, EPT, MODE>), grid, block, lds, st, W, x, y, w2m, fp.khat, fp.tw,
+  LSP_LAUNCH(fft_mode_name(MODE), (int)sizeof(cplx<T>), (fft_lines_kernel<T, EPT, MODE>), grid, block, lds, st, W, x, y, w2m, fp.khat, fp.tw,
                      fp.rad, a);
-  LSP_HIP(hipGetLastError());
 }
 
 template <typename T, int EPT>

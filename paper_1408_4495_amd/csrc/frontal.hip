@@ -7,10 +7,10 @@
 //   F = [F_II F_IB; F_BI F_BB],
 // assembled from M's entries whose row or column is in I plus the children's
 // Schur complements (extend-add, written as a gather so no atomics are used).
-// The partial LU eliminates I in panels of width kb:
-//   1. LU of the kb x kb diagonal block with partial pivoting inside it,
-//   2. U12 = L11^{-1} P F12 (rows of the panel, all columns to the right) and
-//      L21 = F21 U11^{-1} (all rows below, panel columns),
+// The partial LU eliminates I in panels of width kb <= NB:
+//   1. LU of the kb x kb diagonal block with partial pivoting inside it, and
+//      the inverses L11^{-1}, U11^{-1} of its triangular factors (kept),
+//   2. U12 = L11^{-1} P F12 and L21 = F21 U11^{-1} as small dense products,
 //   3. trailing update F22 -= L21 U12 on MFMA (complex as four real products).
 // Pivoting is restricted to the panel's diagonal block (the paper leaves the
 // pivoting strategy open); each front records the smallest ratio
@@ -18,12 +18,16 @@
 // pivots.  After the last panel F_BB holds the Schur complement S handed to
 // the parent.  Row swaps are not applied to columns left of a panel; the
 // forward solve applies each panel's permutation when it reaches the panel.
+// The kept inverses turn every panel step of the triangular solves into a
+// small matrix-vector product, so no step has a sequential dependency chain.
 #include "lsp_common.h"
 #include "kernels.h"
 
 namespace lsp {
 
 namespace {
+
+constexpr int NB = kNbMax;
 
 // ---------------------------------------------------------------- assembly
 template <typename T>
@@ -38,11 +42,10 @@ __global__ void __launch_bounds__(256) assemble_front_kernel(cplx<T>* __restrict
   cplx<T>* F = Fbuf + f.f_off;
   const int* id = idx + f.idx_off;
   const int* cp = cpos + 2 * f.idx_off;
-  FrontDev ch[2];
   const cplx<T>* Fc[2] = {nullptr, nullptr};
   int mc[2] = {0, 0};
-  if (f.child0 >= 0) { ch[0] = fr[f.child0]; Fc[0] = Fbuf + ch[0].f_off; mc[0] = ch[0].p + ch[0].q; }
-  if (f.child1 >= 0) { ch[1] = fr[f.child1]; Fc[1] = Fbuf + ch[1].f_off; mc[1] = ch[1].p + ch[1].q; }
+  if (f.child0 >= 0) { FrontDev c = fr[f.child0]; Fc[0] = Fbuf + c.f_off; mc[0] = c.p + c.q; }
+  if (f.child1 >= 0) { FrontDev c = fr[f.child1]; Fc[1] = Fbuf + c.f_off; mc[1] = c.p + c.q; }
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < mm; e += (long long)gridDim.x * blockDim.x) {
     int r = (int)(e % m), c = (int)(e / m);
     double2 v = make_double2(0, 0);
@@ -70,116 +73,149 @@ __global__ void __launch_bounds__(256) assemble_front_kernel(cplx<T>* __restrict
   }
 }
 
-// ---------------------------------------------------------------- diagonal block LU
+// ---------------------------------------------------------------- diagonal block LU (one wave)
+// Also writes L11^{-1} (unit lower) and U11^{-1} to the front's inverse store:
+// panel b of a front keeps [Linv | Uinv], each NB x NB column-major, zero
+// outside the kb x kb block.
 template <typename T>
-__global__ void __launch_bounds__(256) diag_lu_kernel(cplx<T>* __restrict__ Fbuf, const FrontDev* __restrict__ fr,
-                                                      int* __restrict__ piv, int* __restrict__ perm,
-                                                      double* __restrict__ pivstat, int first, int k0, int nb) {
-  __shared__ cplx<T> Bk[kNbMax][kNbMax + 1];
-  __shared__ T redv[256];
-  __shared__ int redi[256];
-  __shared__ int permb[kNbMax];
+__global__ void __launch_bounds__(64) diag_lu_kernel(cplx<T>* __restrict__ Fbuf, cplx<T>* __restrict__ Dinv,
+                                                     const FrontDev* __restrict__ fr, int* __restrict__ piv,
+                                                     int* __restrict__ perm, double* __restrict__ pivstat, int first,
+                                                     int k0) {
+  __shared__ cplx<T> Bk[NB][NB + 1];
+  __shared__ cplx<T> X[NB][NB + 1];
+  __shared__ int permb[NB];
   const FrontDev f = fr[first + blockIdx.x];
   if (f.p <= k0) return;
-  const int kb = min(nb, f.p - k0);
+  const int kb = min(NB, f.p - k0);
   const int m = f.p + f.q;
   cplx<T>* F = Fbuf + f.f_off;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kb * kb; e += blockDim.x) {
+  const int lane = threadIdx.x;
+  for (int e = lane; e < kb * kb; e += 64) {
     int r = e % kb, c = e / kb;
     Bk[r][c] = F[(k0 + r) + (long long)(k0 + c) * m];
   }
-  if (tid < kb) permb[tid] = tid;
+  if (lane < NB) permb[lane] = lane;
   __syncthreads();
   double worst = 1e300;
   for (int j = 0; j < kb; ++j) {
     T best = (T)-1;
-    int bi = j;
-    for (int r = j + tid; r < kb; r += blockDim.x) {
-      T a = cabs1(Bk[r][j]);
-      if (a > best) { best = a; bi = r; }
+    int bi = kb;
+    if (lane >= j && lane < kb) { best = cabs1(Bk[lane][j]); bi = lane; }
+    for (int off = 32; off > 0; off >>= 1) {
+      T ob = __shfl_xor(best, off, 64);
+      int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
     }
-    redv[tid] = best; redi[tid] = bi;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        if (redv[tid + s] > redv[tid] || (redv[tid + s] == redv[tid] && redi[tid + s] < redi[tid])) {
-          redv[tid] = redv[tid + s]; redi[tid] = redi[tid + s];
-        }
-      }
-      __syncthreads();
-    }
-    const int pr = redi[0];
-    const T colmax = redv[0];
-    __syncthreads();
+    const int pr = bi;
+    const T colmax = best;
     if (pr != j) {
-      for (int c = tid; c < kb; c += blockDim.x) {
-        cplx<T> t = Bk[j][c]; Bk[j][c] = Bk[pr][c]; Bk[pr][c] = t;
-      }
-      if (tid == 0) { int t = permb[j]; permb[j] = permb[pr]; permb[pr] = t; }
+      if (lane < kb) { cplx<T> t = Bk[j][lane]; Bk[j][lane] = Bk[pr][lane]; Bk[pr][lane] = t; }
+      if (lane == 0) { int t = permb[j]; permb[j] = permb[pr]; permb[pr] = t; }
     }
-    if (tid == 0) piv[f.piv_off + k0 + j] = k0 + pr;
+    if (lane == 0) piv[f.piv_off + k0 + j] = k0 + pr;
     __syncthreads();
     cplx<T> dj = Bk[j][j];
     T dmag = cabs1(dj);
-    double ratio = colmax > 0 ? (double)dmag / (double)colmax : 0.0;
-    worst = fmin(worst, dmag > 0 ? ratio : 0.0);
+    worst = fmin(worst, (dmag > 0 && colmax > 0) ? (double)dmag / (double)colmax : 0.0);
     cplx<T> inv = dmag > 0 ? cdiv(mk<T>(1, 0), dj) : mk<T>(0, 0);
-    for (int r = j + 1 + tid; r < kb; r += blockDim.x) Bk[r][j] = cmul(Bk[r][j], inv);
-    __syncthreads();
-    for (int e = tid; e < (kb - j - 1) * (kb - j - 1); e += blockDim.x) {
-      int r = j + 1 + e % (kb - j - 1), c = j + 1 + e / (kb - j - 1);
-      Bk[r][c] = cfms(Bk[r][c], Bk[r][j], Bk[j][c]);
+    if (lane > j && lane < kb) {
+      cplx<T> l = cmul(Bk[lane][j], inv);
+      Bk[lane][j] = l;
+      for (int c = j + 1; c < kb; ++c) Bk[lane][c] = cfms(Bk[lane][c], l, Bk[j][c]);
     }
     __syncthreads();
   }
-  for (int e = tid; e < kb * kb; e += blockDim.x) {
+  for (int e = lane; e < kb * kb; e += 64) {
     int r = e % kb, c = e / kb;
     F[(k0 + r) + (long long)(k0 + c) * m] = Bk[r][c];
   }
-  if (tid < kb) perm[f.piv_off + k0 + tid] = k0 + permb[tid];
-  if (tid == 0) pivstat[first + blockIdx.x] = fmin(pivstat[first + blockIdx.x], worst);
+  if (lane < kb) perm[f.piv_off + k0 + lane] = k0 + permb[lane];
+  if (lane == 0) pivstat[first + blockIdx.x] = fmin(pivstat[first + blockIdx.x], worst);
+  cplx<T>* Li = Dinv + f.dinv_off + (long long)(k0 / NB) * 2 * NB * NB;
+  cplx<T>* Ui = Li + NB * NB;
+  // L11^{-1}: lane c solves L x = e_c by forward substitution
+  if (lane < NB) {
+    const int c = lane;
+    for (int i = 0; i < NB; ++i) {
+      cplx<T> s = mk<T>(i == c && c < kb ? 1 : 0, 0);
+      if (i < kb && c < kb)
+        for (int j = c; j < i; ++j) s = cfms(s, Bk[i][j], X[j][c]);
+      X[i][c] = (i < kb && c < kb) ? s : mk<T>(0, 0);
+    }
+    for (int i = 0; i < NB; ++i) Li[i + NB * c] = X[i][c];
+  }
+  __syncthreads();
+  // U11^{-1}: lane c solves U x = e_c by backward substitution
+  if (lane < NB) {
+    const int c = lane;
+    for (int i = NB - 1; i >= 0; --i) {
+      cplx<T> s = mk<T>(0, 0);
+      if (i < kb && c < kb && i <= c) {
+        s = mk<T>(i == c ? 1 : 0, 0);
+        for (int j = i + 1; j <= c; ++j) s = cfms(s, Bk[i][j], X[j][c]);
+        s = cdiv(s, Bk[i][i]);
+      }
+      X[i][c] = s;
+    }
+    for (int i = 0; i < NB; ++i) Ui[i + NB * c] = X[i][c];
+  }
 }
 
-// ---------------------------------------------------------------- panel triangular solves
-// blockIdx.z == 0: U12 = L11^{-1} P F12, one thread per column c >= k1.
-// blockIdx.z == 1: L21 = F21 U11^{-1}, one thread per row r >= k1.
+// ---------------------------------------------------------------- panel products
+// blockIdx.z == 0: U12(:, tile) = L11^{-1} P F12(:, tile), 64 columns per block.
+// blockIdx.z == 1: L21(tile, :) = F21(tile, :) U11^{-1}, 64 rows per block.
 template <typename T>
-__global__ void __launch_bounds__(256) panel_trsm_kernel(cplx<T>* __restrict__ Fbuf, const FrontDev* __restrict__ fr,
-                                                         const int* __restrict__ perm, int first, int k0, int nb) {
-  __shared__ cplx<T> D[kNbMax][kNbMax + 1];
-  __shared__ int pb[kNbMax];
+__global__ void __launch_bounds__(256) panel_trsm_kernel(cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
+                                                         const FrontDev* __restrict__ fr, const int* __restrict__ perm,
+                                                         int first, int k0) {
+  __shared__ cplx<T> Di[NB][NB + 1];
+  __shared__ cplx<T> Tt[64][NB + 1];
   const FrontDev f = fr[first + blockIdx.y];
   if (f.p <= k0) return;
-  const int kb = min(nb, f.p - k0);
+  const int kb = min(NB, f.p - k0);
   const int k1 = k0 + kb;
   const int m = f.p + f.q;
-  if (k1 >= m) return;
+  const int t0 = blockIdx.x * 64;
+  if (t0 >= m - k1) return;
+  const int cnt = min(64, m - k1 - t0);
   cplx<T>* F = Fbuf + f.f_off;
-  for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
-    int r = e % kb, c = e / kb;
-    D[r][c] = F[(k0 + r) + (long long)(k0 + c) * m];
-  }
-  if (threadIdx.x < kb) pb[threadIdx.x] = perm[f.piv_off + k0 + threadIdx.x];
-  __syncthreads();
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m - k1) return;
-  cplx<T> x[kNbMax];
+  const cplx<T>* Li = Dinv + f.dinv_off + (long long)(k0 / NB) * 2 * NB * NB;
+  const cplx<T>* Dm = blockIdx.z == 0 ? Li : Li + NB * NB;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NB * NB; e += 256) Di[e % NB][e / NB] = Dm[e];
   if (blockIdx.z == 0) {
-    const long long c = k1 + t;
-    for (int j = 0; j < kb; ++j) x[j] = F[pb[j] + c * m];
-    for (int j = 0; j < kb; ++j)
-      for (int i = j + 1; i < kb; ++i) x[i] = cfms(x[i], D[i][j], x[j]);
-    for (int j = 0; j < kb; ++j) F[(k0 + j) + c * m] = x[j];
-  } else {
-    const long long r = k1 + t;
-    for (int j = 0; j < kb; ++j) x[j] = F[r + (long long)(k0 + j) * m];
-    for (int j = 0; j < kb; ++j) {
-      cplx<T> s = x[j];
-      for (int i = 0; i < j; ++i) s = cfms(s, x[i], D[i][j]);
-      x[j] = cdiv(s, D[j][j]);
+    // Tt[c][j] = (P F12)(j, t0 + c)
+    for (int e = tid; e < 64 * NB; e += 256) {
+      int j = e % NB, c = e / NB;
+      cplx<T> v = mk<T>(0, 0);
+      if (j < kb && c < cnt) v = F[perm[f.piv_off + k0 + j] + (long long)(k1 + t0 + c) * m];
+      Tt[c][j] = v;
     }
-    for (int j = 0; j < kb; ++j) F[r + (long long)(k0 + j) * m] = x[j];
+    __syncthreads();
+    for (int e = tid; e < 64 * NB; e += 256) {
+      int i = e % NB, c = e / NB;
+      if (i >= kb || c >= cnt) continue;
+      cplx<T> s = mk<T>(0, 0);
+      for (int j = 0; j <= i; ++j) s = cfma(s, Di[i][j], Tt[c][j]);
+      F[(k0 + i) + (long long)(k1 + t0 + c) * m] = s;
+    }
+  } else {
+    // Tt[r][i] = F21(t0 + r, i)
+    for (int e = tid; e < 64 * NB; e += 256) {
+      int r = e % 64, i = e / 64;
+      cplx<T> v = mk<T>(0, 0);
+      if (i < kb && r < cnt) v = F[(k1 + t0 + r) + (long long)(k0 + i) * m];
+      Tt[r][i] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < 64 * NB; e += 256) {
+      int r = e % 64, j = e / 64;
+      if (j >= kb || r >= cnt) continue;
+      cplx<T> s = mk<T>(0, 0);
+      for (int i = 0; i <= j; ++i) s = cfma(s, Tt[r][i], Di[i][j]);
+      F[(k1 + t0 + r) + (long long)(k0 + j) * m] = s;
+    }
   }
 }
 
@@ -202,62 +238,59 @@ template <> struct Mfma<float> {
   __device__ static int row(int lk, int v) { return 4 * lk + v; }
 };
 
-template <typename T>
+template <typename T, int TM>
 __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ Fbuf, const FrontDev* __restrict__ fr,
-                                                          int first, int k0, int nb) {
-  constexpr int TM = 64, TN = 64, KMAX = kNbMax;
-  __shared__ T Ar[KMAX][TM], Ai[KMAX][TM], Br[KMAX][TN], Bi[KMAX][TN];
+                                                          int first, int k0) {
+  // TM x TM output tile, 4 waves in a 2x2 arrangement, each wave (TM/2)^2 as
+  // BW x BW MFMA 16x16 blocks.
+  constexpr int BW = TM / 32;
+  __shared__ T Ar[NB][TM], Ai[NB][TM], Br[NB][TM + 1], Bi[NB][TM + 1];
   const FrontDev f = fr[first + blockIdx.z];
   if (f.p <= k0) return;
-  const int kb = min(nb, f.p - k0);
+  const int kb = min(NB, f.p - k0);
   const int k1 = k0 + kb;
   const int m = f.p + f.q;
   const int rem = m - k1;
-  const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
+  const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TM;
   if (row0 >= rem || col0 >= rem) return;
   cplx<T>* F = Fbuf + f.f_off;
   const int tid = threadIdx.x;
-  // stage A (rows k1+row0.., cols k0..k1) and B (rows k0..k1, cols k1+col0..)
-  for (int e = tid; e < TM * kb; e += 256) {
+  const int kpad = (kb + 3) & ~3;
+  for (int e = tid; e < TM * kpad; e += 256) {
     int r = e % TM, kk = e / TM;
     cplx<T> v = mk<T>(0, 0);
-    if (row0 + r < rem) v = F[(k1 + row0 + r) + (long long)(k0 + kk) * m];
+    if (row0 + r < rem && kk < kb) v = F[(k1 + row0 + r) + (long long)(k0 + kk) * m];
     Ar[kk][r] = v.x; Ai[kk][r] = v.y;
   }
-  for (int e = tid; e < TN * kb; e += 256) {
-    int kk = e % kb, c = e / kb;
+  for (int e = tid; e < TM * kpad; e += 256) {
+    int kk = e % kpad, c = e / kpad;
     cplx<T> v = mk<T>(0, 0);
-    if (col0 + c < rem) v = F[(k0 + kk) + (long long)(k1 + col0 + c) * m];
+    if (col0 + c < rem && kk < kb) v = F[(k0 + kk) + (long long)(k1 + col0 + c) * m];
     Br[kk][c] = v.x; Bi[kk][c] = v.y;
-  }
-  const int kpad = (kb + 3) & ~3;
-  for (int e = tid; e < TM * (kpad - kb); e += 256) {
-    int r = e % TM, kk = kb + e / TM;
-    Ar[kk][r] = 0; Ai[kk][r] = 0; Br[kk][r] = 0; Bi[kk][r] = 0;
   }
   __syncthreads();
   using acc_t = typename Mfma<T>::acc_t;
   const int wave = tid / 64, lane = tid % 64;
-  const int wr = (wave / 2) * 32, wc = (wave % 2) * 32;
-  acc_t accr[2][2], acci[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
+  const int wr = (wave / 2) * (TM / 2), wc = (wave % 2) * (TM / 2);
+  acc_t accr[BW][BW], acci[BW][BW];
+  for (int i = 0; i < BW; ++i)
+    for (int j = 0; j < BW; ++j)
       for (int v = 0; v < 4; ++v) { accr[i][j][v] = 0; acci[i][j][v] = 0; }
   const int li = lane % 16, lk = lane / 16;
   for (int k4 = 0; k4 < kpad; k4 += 4) {
-    T ar[2], ai[2], br[2], bi[2];
-    for (int i = 0; i < 2; ++i) { ar[i] = Ar[k4 + lk][wr + 16 * i + li]; ai[i] = Ai[k4 + lk][wr + 16 * i + li]; }
-    for (int j = 0; j < 2; ++j) { br[j] = Br[k4 + lk][wc + 16 * j + li]; bi[j] = Bi[k4 + lk][wc + 16 * j + li]; }
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) {
+    T ar[BW], ai[BW], br[BW], bi[BW];
+    for (int i = 0; i < BW; ++i) { ar[i] = Ar[k4 + lk][wr + 16 * i + li]; ai[i] = Ai[k4 + lk][wr + 16 * i + li]; }
+    for (int j = 0; j < BW; ++j) { br[j] = Br[k4 + lk][wc + 16 * j + li]; bi[j] = Bi[k4 + lk][wc + 16 * j + li]; }
+    for (int i = 0; i < BW; ++i)
+      for (int j = 0; j < BW; ++j) {
         accr[i][j] = Mfma<T>::step(ar[i], br[j], accr[i][j]);
         accr[i][j] = Mfma<T>::step(-ai[i], bi[j], accr[i][j]);
         acci[i][j] = Mfma<T>::step(ar[i], bi[j], acci[i][j]);
         acci[i][j] = Mfma<T>::step(ai[i], br[j], acci[i][j]);
       }
   }
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
+  for (int i = 0; i < BW; ++i)
+    for (int j = 0; j < BW; ++j) {
       int col = col0 + wc + 16 * j + li;
       if (col >= rem) continue;
       for (int v = 0; v < 4; ++v) {
@@ -273,59 +306,78 @@ __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ 
 }
 
 // ---------------------------------------------------------------- solves
-// Forward sweep of one front for one right-hand side (blockIdx.y):
-//   v = [z(I); 0] + children's updates; per panel: v_b <- P_b v_b,
-//   y_b = L11^{-1} v_b, v(k1:m) -= L21 y_b.  v lives in the per-front vector
-//   buffer; afterwards v(0:p) = y_I and v(p:m) = update for the parent.
-template <typename T>
-__global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fbuf, const FrontDev* __restrict__ fr,
-                                                  const int* __restrict__ idx, const int* __restrict__ cpos,
-                                                  const int* __restrict__ perm, const cplx<T>* __restrict__ z,
-                                                  cplx<T>* __restrict__ vbuf, int first, int nb, long long N,
-                                                  long long vstride) {
-  __shared__ cplx<T> yb[kNbMax];
+// Right-hand sides are taken in groups of NR per workgroup (blockIdx.y), so
+// each factor entry is read once per group; a right-hand side's arithmetic
+// does not depend on the group it is in.
+//
+// Forward sweep of one front: v = [z(I); 0] + children's updates; per panel:
+//   y_b = L11^{-1} (P_b v_b),  v(k1:m) -= L21 y_b.
+// v lives in the per-front vector buffer; afterwards v(0:p) = y_I and
+// v(p:m) = the update handed to the parent.
+template <typename T, int NR>
+__global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
+                                                  const FrontDev* __restrict__ fr, const int* __restrict__ idx,
+                                                  const int* __restrict__ cpos, const int* __restrict__ perm,
+                                                  const cplx<T>* __restrict__ z, cplx<T>* __restrict__ vbuf, int first,
+                                                  int nrhs, long long N, long long vstride) {
+  __shared__ cplx<T> Li[NB][NB + 1];
+  __shared__ cplx<T> tb[NR][NB];
+  __shared__ cplx<T> yb[NR][NB];
   const FrontDev f = fr[first + blockIdx.x];
-  const int rhs = blockIdx.y;
+  const int r0 = blockIdx.y * NR;
+  const int nr = min(NR, nrhs - r0);
   const int m = f.p + f.q;
   const cplx<T>* F = Fbuf + f.f_off;
   const int* id = idx + f.idx_off;
   const int* cp = cpos + 2 * f.idx_off;
-  cplx<T>* v = vbuf + rhs * vstride + f.idx_off;
-  const cplx<T>* zr = z + rhs * N;
-  const cplx<T>* vc[2] = {nullptr, nullptr};
-  int pc[2] = {0, 0};
-  if (f.child0 >= 0) { FrontDev c = fr[f.child0]; vc[0] = vbuf + rhs * vstride + c.idx_off; pc[0] = c.p; }
-  if (f.child1 >= 0) { FrontDev c = fr[f.child1]; vc[1] = vbuf + rhs * vstride + c.idx_off; pc[1] = c.p; }
+  long long coff[2] = {-1, -1};
+  if (f.child0 >= 0) coff[0] = fr[f.child0].idx_off;
+  if (f.child1 >= 0) coff[1] = fr[f.child1].idx_off;
   const int tid = threadIdx.x;
-  for (int r = tid; r < m; r += blockDim.x) {
-    cplx<T> s = r < f.p ? zr[id[r]] : mk<T>(0, 0);
-    for (int k = 0; k < 2; ++k) {
-      if (!vc[k]) continue;
-      int q = cp[2 * r + k];
-      if (q >= 0) s = cadd(s, vc[k][q]);
+  for (int e = tid; e < m * nr; e += 256) {
+    int r = e % m, k = e / m;
+    long long rb = (long long)(r0 + k) * vstride;
+    cplx<T> s = r < f.p ? z[(long long)(r0 + k) * N + id[r]] : mk<T>(0, 0);
+    for (int c = 0; c < 2; ++c) {
+      if (coff[c] < 0) continue;
+      int q = cp[2 * r + c];
+      if (q >= 0) s = cadd(s, vbuf[rb + coff[c] + q]);
     }
-    v[r] = s;
+    vbuf[rb + f.idx_off + r] = s;
   }
   __syncthreads();
-  for (int k0 = 0; k0 < f.p; k0 += nb) {
-    const int kb = min(nb, f.p - k0);
+  for (int k0 = 0; k0 < f.p; k0 += NB) {
+    const int kb = min(NB, f.p - k0);
     const int k1 = k0 + kb;
-    if (tid < 64) {
-      cplx<T> val = mk<T>(0, 0);
-      if (tid < kb) val = v[perm[f.piv_off + k0 + tid]];
-      // unit lower solve with the diagonal block, one wave
-      for (int j = 0; j < kb; ++j) {
-        T yr = __shfl(val.x, j), yi = __shfl(val.y, j);
-        if (tid > j && tid < kb) val = cfms(val, F[(k0 + tid) + (long long)(k0 + j) * m], mk<T>(yr, yi));
-      }
-      if (tid < kb) yb[tid] = val;
+    const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(k0 / NB) * 2 * NB * NB;
+    for (int e = tid; e < NB * NB; e += 256) Li[e % NB][e / NB] = Lg[e];
+    for (int e = tid; e < NR * NB; e += 256) {
+      int j = e % NB, k = e / NB;
+      tb[k][j] = (k < nr && j < kb) ? vbuf[(long long)(r0 + k) * vstride + f.idx_off + perm[f.piv_off + k0 + j]]
+                                    : mk<T>(0, 0);
     }
     __syncthreads();
-    if (tid < kb) v[k0 + tid] = yb[tid];
-    for (int r = k1 + tid; r < m; r += blockDim.x) {
-      cplx<T> s = v[r];
-      for (int j = 0; j < kb; ++j) s = cfms(s, F[r + (long long)(k0 + j) * m], yb[j]);
-      v[r] = s;
+    for (int e = tid; e < NR * NB; e += 256) {
+      int i = e % NB, k = e / NB;
+      cplx<T> s = mk<T>(0, 0);
+      for (int j = 0; j <= i; ++j) s = cfma(s, Li[i][j], tb[k][j]);
+      yb[k][i] = s;
+      if (k < nr && i < kb) vbuf[(long long)(r0 + k) * vstride + f.idx_off + k0 + i] = s;
+    }
+    __syncthreads();
+    for (int r = k1 + tid; r < m; r += 256) {
+      cplx<T> acc[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k)
+        acc[k] = k < nr ? vbuf[(long long)(r0 + k) * vstride + f.idx_off + r] : mk<T>(0, 0);
+      for (int j = 0; j < kb; ++j) {
+        cplx<T> l = F[r + (long long)(k0 + j) * m];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] = cfms(acc[k], l, yb[k][j]);
+      }
+#pragma unroll
+      for (int k = 0; k < NR; ++k)
+        if (k < nr) vbuf[(long long)(r0 + k) * vstride + f.idx_off + r] = acc[k];
     }
     __syncthreads();
   }
@@ -333,63 +385,92 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
 
 // Backward sweep: x_B from the global solution, then per panel from the last:
 //   x_b = U11^{-1} (y_b - U12 x(k1:m)).  Writes x at the front's grid points.
-template <typename T>
-__global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fbuf, const FrontDev* __restrict__ fr,
-                                                  const int* __restrict__ idx, cplx<T>* __restrict__ x,
-                                                  cplx<T>* __restrict__ vbuf, int first, int nb, long long N,
-                                                  long long vstride) {
-  __shared__ cplx<T> part[256];
-  __shared__ cplx<T> xb[kNbMax];
+template <typename T, int NR>
+__global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
+                                                  const FrontDev* __restrict__ fr, const int* __restrict__ idx,
+                                                  cplx<T>* __restrict__ x, cplx<T>* __restrict__ vbuf, int first,
+                                                  int nrhs, long long N, long long vstride) {
+  constexpr int G = 256 / NB;  // column groups
+  __shared__ cplx<T> Ui[NB][NB + 1];
+  __shared__ cplx<T> part[G][NR][NB];
+  __shared__ cplx<T> rb[NR][NB];
   const FrontDev f = fr[first + blockIdx.x];
-  const int rhs = blockIdx.y;
+  const int r0 = blockIdx.y * NR;
+  const int nr = min(NR, nrhs - r0);
   const int m = f.p + f.q;
   const cplx<T>* F = Fbuf + f.f_off;
   const int* id = idx + f.idx_off;
-  cplx<T>* v = vbuf + rhs * vstride + f.idx_off;
-  cplx<T>* xr = x + rhs * N;
   const int tid = threadIdx.x;
-  for (int r = f.p + tid; r < m; r += blockDim.x) v[r] = xr[id[r]];
+  for (int e = tid; e < f.q * nr; e += 256) {
+    int r = f.p + e % f.q, k = e / f.q;
+    vbuf[(long long)(r0 + k) * vstride + f.idx_off + r] = x[(long long)(r0 + k) * N + id[r]];
+  }
   __syncthreads();
-  const int nblk = (f.p + nb - 1) / nb;
+  const int nblk = (f.p + NB - 1) / NB;
   for (int b = nblk - 1; b >= 0; --b) {
-    const int k0 = b * nb;
-    const int kb = min(nb, f.p - k0);
+    const int k0 = b * NB;
+    const int kb = min(NB, f.p - k0);
     const int k1 = k0 + kb;
-    // partial sums of U12 x over column groups
-    const int j = tid % 64, grp = tid / 64;
-    cplx<T> acc = mk<T>(0, 0);
-    if (j < kb)
-      for (int c = k1 + grp; c < m; c += 4) acc = cfma(acc, F[(k0 + j) + (long long)c * m], v[c]);
-    part[tid] = acc;
+    const cplx<T>* Ug = Dinv + f.dinv_off + (long long)b * 2 * NB * NB + NB * NB;
+    for (int e = tid; e < NB * NB; e += 256) Ui[e % NB][e / NB] = Ug[e];
+    const int j = tid % NB, grp = tid / NB;
+    cplx<T> acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
+    if (j < kb) {
+      for (int c = k1 + grp; c < m; c += G) {
+        cplx<T> u = F[(k0 + j) + (long long)c * m];
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+          if (k < nr) acc[k] = cfma(acc[k], u, vbuf[(long long)(r0 + k) * vstride + f.idx_off + c]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) part[grp][k][j] = acc[k];
     __syncthreads();
-    if (tid < 64) {
-      cplx<T> val = mk<T>(0, 0);
-      if (tid < kb) {
-        cplx<T> s = cadd(cadd(part[tid], part[tid + 64]), cadd(part[tid + 128], part[tid + 192]));
-        val = csub(v[k0 + tid], s);
-      }
-      // upper solve, backwards, one wave
-      for (int jj = kb - 1; jj >= 0; --jj) {
-        cplx<T> dj = F[(k0 + jj) + (long long)(k0 + jj) * m];
-        if (tid == jj) val = cdiv(val, dj);
-        T xr_ = __shfl(val.x, jj), xi_ = __shfl(val.y, jj);
-        if (tid < jj) val = cfms(val, F[(k0 + tid) + (long long)(k0 + jj) * m], mk<T>(xr_, xi_));
-      }
-      if (tid < kb) xb[tid] = val;
+    for (int e = tid; e < NR * NB; e += 256) {
+      int jj = e % NB, k = e / NB;
+      cplx<T> s = part[0][k][jj];
+      for (int g = 1; g < G; ++g) s = cadd(s, part[g][k][jj]);
+      rb[k][jj] = (k < nr && jj < kb) ? csub(vbuf[(long long)(r0 + k) * vstride + f.idx_off + k0 + jj], s)
+                                      : mk<T>(0, 0);
     }
     __syncthreads();
-    if (tid < kb) {
-      v[k0 + tid] = xb[tid];
-      xr[id[k0 + tid]] = xb[tid];
+    for (int e = tid; e < NR * NB; e += 256) {
+      int i = e % NB, k = e / NB;
+      if (k >= nr || i >= kb) continue;
+      cplx<T> s = mk<T>(0, 0);
+      for (int jj = i; jj < kb; ++jj) s = cfma(s, Ui[i][jj], rb[k][jj]);
+      vbuf[(long long)(r0 + k) * vstride + f.idx_off + k0 + i] = s;
+      x[(long long)(r0 + k) * N + id[k0 + i]] = s;
     }
     __syncthreads();
+  }
+}
+
+template <typename T, int NR>
+void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
+                  hipStream_t st) {
+  const long long vstride = plan.sum_pq;
+  const int groups = (nrhs + NR - 1) / NR;
+  for (int l = 0; l < plan.nlevels; ++l) {
+    const int first = plan.level_ptr[l];
+    const int cnt = plan.level_ptr[l + 1] - first;
+    LSP_LAUNCH("fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NR>), dim3(cnt, groups), dim3(256), 0, st, mf.F, mf.Dinv, mf.fronts, mf.idx,
+                       mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N, vstride);
+  }
+  for (int l = plan.nlevels - 1; l >= 0; --l) {
+    const int first = plan.level_ptr[l];
+    const int cnt = plan.level_ptr[l + 1] - first;
+    LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR>), dim3(cnt, groups), dim3(256), 0, st, mf.F, mf.Dinv, mf.fronts, mf.idx, x,
+                       vbuf, first, nrhs, (long long)plan.N, vstride);
   }
 }
 
 }  // namespace
 
 template <typename T>
-void mf_factor(const MfDev<T>& mf, const Plan& plan, int nb, hipStream_t st) {
+void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
   for (int l = 0; l < plan.nlevels; ++l) {
     const int first = plan.level_ptr[l];
     const int cnt = plan.level_ptr[l + 1] - first;
@@ -397,50 +478,43 @@ void mf_factor(const MfDev<T>& mf, const Plan& plan, int nb, hipStream_t st) {
     const int maxp = plan.level_maxp[l];
     long long mm = (long long)maxm * maxm;
     int gx = (int)std::min<long long>((mm + 255) / 256, 64);
-    hipLaunchKernelGGL(assemble_front_kernel<T>, dim3(gx, cnt), dim3(256), 0, st, mf.F, mf.fronts, mf.idx, mf.cpos,
+    LSP_LAUNCH("assemble_front", (int)sizeof(cplx<T>), assemble_front_kernel<T>, dim3(gx, cnt), dim3(256), 0, st, mf.F, mf.fronts, mf.idx, mf.cpos,
                        mf.Mval, first, plan.n, plan.d);
-    LSP_HIP(hipGetLastError());
-    for (int k0 = 0; k0 < maxp; k0 += nb) {
-      hipLaunchKernelGGL(diag_lu_kernel<T>, dim3(cnt), dim3(256), 0, st, mf.F, mf.fronts, mf.piv, mf.perm,
-                         mf.pivstat, first, k0, nb);
-      LSP_HIP(hipGetLastError());
+    for (int k0 = 0; k0 < maxp; k0 += NB) {
+      LSP_LAUNCH("diag_lu", (int)sizeof(cplx<T>), diag_lu_kernel<T>, dim3(cnt), dim3(64), 0, st, mf.F, mf.Dinv, mf.fronts, mf.piv, mf.perm,
+                         mf.pivstat, first, k0);
       int rem = maxm - k0 - 1;
       if (rem <= 0) continue;
-      hipLaunchKernelGGL(panel_trsm_kernel<T>, dim3((rem + 255) / 256, cnt, 2), dim3(256), 0, st, mf.F, mf.fronts,
-                         mf.perm, first, k0, nb);
-      LSP_HIP(hipGetLastError());
       int tiles = (rem + 63) / 64;
-      hipLaunchKernelGGL(gemm_update_kernel<T>, dim3(tiles, tiles, cnt), dim3(256), 0, st, mf.F, mf.fronts, first, k0,
-                         nb);
-      LSP_HIP(hipGetLastError());
+      LSP_LAUNCH("panel_trsm", (int)sizeof(cplx<T>), panel_trsm_kernel<T>, dim3(tiles, cnt, 2), dim3(256), 0, st, mf.F, mf.Dinv, mf.fronts,
+                         mf.perm, first, k0);
+      const int tile = plan.level_tile[l];
+      const int gt = (rem + tile - 1) / tile;
+      if (tile == 32)
+        LSP_LAUNCH("gemm_update", (int)sizeof(cplx<T>), (gemm_update_kernel<T, 32>), dim3(gt, gt, cnt), dim3(256), 0, st,
+                   mf.F, mf.fronts, first, k0);
+      else if (tile == 128)
+        LSP_LAUNCH("gemm_update", (int)sizeof(cplx<T>), (gemm_update_kernel<T, 128>), dim3(gt, gt, cnt), dim3(256), 0, st,
+                   mf.F, mf.fronts, first, k0);
+      else
+        LSP_LAUNCH("gemm_update", (int)sizeof(cplx<T>), (gemm_update_kernel<T, 64>), dim3(gt, gt, cnt), dim3(256), 0, st,
+                   mf.F, mf.fronts, first, k0);
     }
   }
 }
 
 template <typename T>
-void mf_solve(const MfDev<T>& mf, const Plan& plan, int nb, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
+void mf_solve(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
               hipStream_t st) {
-  const long long vstride = plan.sum_pq;
-  for (int l = 0; l < plan.nlevels; ++l) {
-    const int first = plan.level_ptr[l];
-    const int cnt = plan.level_ptr[l + 1] - first;
-    hipLaunchKernelGGL(fwd_kernel<T>, dim3(cnt, nrhs), dim3(256), 0, st, mf.F, mf.fronts, mf.idx, mf.cpos, mf.perm, z,
-                       vbuf, first, nb, (long long)plan.N, vstride);
-    LSP_HIP(hipGetLastError());
-  }
-  for (int l = plan.nlevels - 1; l >= 0; --l) {
-    const int first = plan.level_ptr[l];
-    const int cnt = plan.level_ptr[l + 1] - first;
-    hipLaunchKernelGGL(bwd_kernel<T>, dim3(cnt, nrhs), dim3(256), 0, st, mf.F, mf.fronts, mf.idx, x, vbuf, first, nb,
-                       (long long)plan.N, vstride);
-    LSP_HIP(hipGetLastError());
-  }
+  if (nrhs >= 8) solve_levels<T, 8>(mf, plan, nrhs, z, x, vbuf, st);
+  else if (nrhs >= 4) solve_levels<T, 4>(mf, plan, nrhs, z, x, vbuf, st);
+  else if (nrhs >= 2) solve_levels<T, 2>(mf, plan, nrhs, z, x, vbuf, st);
+  else solve_levels<T, 1>(mf, plan, nrhs, z, x, vbuf, st);
 }
 
-template void mf_factor<double>(const MfDev<double>&, const Plan&, int, hipStream_t);
-template void mf_factor<float>(const MfDev<float>&, const Plan&, int, hipStream_t);
-template void mf_solve<double>(const MfDev<double>&, const Plan&, int, int, const double2*, double2*, double2*,
-                               hipStream_t);
-template void mf_solve<float>(const MfDev<float>&, const Plan&, int, int, const float2*, float2*, float2*, hipStream_t);
+template void mf_factor<double>(const MfDev<double>&, const Plan&, hipStream_t);
+template void mf_factor<float>(const MfDev<float>&, const Plan&, hipStream_t);
+template void mf_solve<double>(const MfDev<double>&, const Plan&, int, const double2*, double2*, double2*, hipStream_t);
+template void mf_solve<float>(const MfDev<float>&, const Plan&, int, const float2*, float2*, float2*, hipStream_t);
 
 }  // namespace lsp

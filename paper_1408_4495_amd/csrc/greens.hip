@@ -135,18 +135,16 @@ void launch_ktable(double2* k, int n, int d, double omega, double2 k0, hipStream
   long long total = 1;
   for (int a = 0; a < d; ++a) total *= (n + 1);
   int bs = 256;
-  hipLaunchKernelGGL(ktable_kernel, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st,
+  LSP_LAUNCH("ktable", 0, ktable_kernel, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st,
                      k, n, d, 1.0 / n, omega, k0, total);
-  LSP_HIP(hipGetLastError());
 }
 
 void launch_embed(double2* E, const double2* k, int n, int d, hipStream_t st) {
   long long total = 1;
   for (int a = 0; a < d; ++a) total *= 2 * n;
   int bs = 256;
-  hipLaunchKernelGGL(embed_kernel, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st,
+  LSP_LAUNCH("embed", 0, embed_kernel, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st,
                      E, k, n, d, total);
-  LSP_HIP(hipGetLastError());
 }
 
 void launch_fold_khat(double2* kh64, float2* kh32, const double2* E, int n, int d, hipStream_t st) {
@@ -154,9 +152,8 @@ void launch_fold_khat(double2* kh64, float2* kh32, const double2* E, int n, int 
   double scale = 1.0;
   for (int a = 0; a < d; ++a) { total *= n + 1; scale /= 2.0 * n; }
   int bs = 256;
-  hipLaunchKernelGGL(fold_khat_kernel, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st,
+  LSP_LAUNCH("fold_khat", 0, fold_khat_kernel, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st,
                      kh64, kh32, E, n, d, scale, total);
-  LSP_HIP(hipGetLastError());
 }
 
 }  // namespace lsp

@@ -59,6 +59,7 @@ void launch_applyQ(Cx* y, const double2* x, const double2* alpha_pad, int n, int
 template <typename T>
 struct MfDev {
   cplx<T>* F;               // front matrices
+  cplx<T>* Dinv;            // inverted diagonal panel blocks
   const FrontDev* fronts;
   const int* idx;
   const int* cpos;
@@ -69,9 +70,9 @@ struct MfDev {
 };
 
 template <typename T>
-void mf_factor(const MfDev<T>& mf, const Plan& plan, int nb, hipStream_t st);
+void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st);
 template <typename T>
-void mf_solve(const MfDev<T>& mf, const Plan& plan, int nb, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
+void mf_solve(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
               hipStream_t st);
 
 // ---- Krylov helpers (complex128 vectors, [nrhs][N] blocks)

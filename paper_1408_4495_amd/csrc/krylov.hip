@@ -232,72 +232,58 @@ int dot_blocks(long long N) {
 void k_dots(const double2* V, const double2* w, double2* partial, double2* h, double2* H, double* scal, int nvec,
             int k, int restart, int mode, long long N, int nrhs, const int* active, hipStream_t st) {
   int nblk = dot_blocks(N);
-  hipLaunchKernelGGL(dots_partial_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, V, w, partial, nvec, N, nrhs, active);
-  LSP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(dots_final_kernel, dim3(nrhs), dim3(64), 0, st, partial, h, H, scal, nvec, nblk, k, restart, mode,
+  LSP_LAUNCH("dots_partial", 0, dots_partial_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, V, w, partial, nvec, N, nrhs, active);
+  LSP_LAUNCH("dots_final", 0, dots_final_kernel, dim3(nrhs), dim3(64), 0, st, partial, h, H, scal, nvec, nblk, k, restart, mode,
                      active);
-  LSP_HIP(hipGetLastError());
 }
 
 void k_norm(const double2* w, double2* partial, double2* h, double2* H, double* scal, int k, int restart, long long N,
             int nrhs, const int* active, hipStream_t st) {
   // ||w||^2 = sum conj(w) w: the dot kernel with V = w and nrhs-strided layout
   int nblk = dot_blocks(N);
-  hipLaunchKernelGGL(dots_partial_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, w, w, partial, 1, N, nrhs, active);
-  LSP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(dots_final_kernel, dim3(nrhs), dim3(64), 0, st, partial, h, H, scal, 1, nblk, k, restart, 2,
+  LSP_LAUNCH("dots_partial", 0, dots_partial_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, w, w, partial, 1, N, nrhs, active);
+  LSP_LAUNCH("dots_final", 0, dots_final_kernel, dim3(nrhs), dim3(64), 0, st, partial, h, H, scal, 1, nblk, k, restart, 2,
                      active);
-  LSP_HIP(hipGetLastError());
 }
 
 void k_axpy(const double2* V, double2* w, const double2* h, int nvec, long long N, int nrhs, const int* active,
             hipStream_t st) {
-  hipLaunchKernelGGL(axpy_kernel, dim3(grid1(N, KB, 1024), nrhs), dim3(KB), 0, st, V, w, h, nvec, N, nrhs, active);
-  LSP_HIP(hipGetLastError());
+  LSP_LAUNCH("axpy", 0, axpy_kernel, dim3(grid1(N, KB, 1024), nrhs), dim3(KB), 0, st, V, w, h, nvec, N, nrhs, active);
 }
 
 void k_scale(double2* y, const double2* x, const double* scal, long long N, int nrhs, const int* active,
              hipStream_t st) {
-  hipLaunchKernelGGL(scale_kernel, dim3(grid1(N, 256, 1024), nrhs), dim3(256), 0, st, y, x, scal, N, active);
-  LSP_HIP(hipGetLastError());
+  LSP_LAUNCH("scale", 0, scale_kernel, dim3(grid1(N, 256, 1024), nrhs), dim3(256), 0, st, y, x, scal, N, active);
 }
 
 void k_givens(double2* H, double2* cs, double2* sn, double2* gam, double* scal, int k, int restart, int nrhs,
               const int* active, hipStream_t st) {
-  hipLaunchKernelGGL(givens_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, H, cs, sn, gam, scal, k, restart, nrhs,
+  LSP_LAUNCH("givens", 0, givens_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, H, cs, sn, gam, scal, k, restart, nrhs,
                      active);
-  LSP_HIP(hipGetLastError());
 }
 
 void k_backsolve_update(const double2* H, const double2* gam, double2* y, const int* ksz, double2* x, const double2* Z,
                         int restart, long long N, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(backsolve_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, H, gam, y, ksz, restart, nrhs);
-  LSP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(update_kernel, dim3(grid1(N, 256, 1024), nrhs), dim3(256), 0, st, x, Z, y, ksz, N, nrhs);
-  LSP_HIP(hipGetLastError());
+  LSP_LAUNCH("backsolve", 0, backsolve_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, H, gam, y, ksz, restart, nrhs);
+  LSP_LAUNCH("update", 0, update_kernel, dim3(grid1(N, 256, 1024), nrhs), dim3(256), 0, st, x, Z, y, ksz, N, nrhs);
 }
 
 void k_sub(double2* r, const double2* g, const double2* t, long long count, hipStream_t st) {
-  hipLaunchKernelGGL(sub_kernel, dim3(grid1(count)), dim3(256), 0, st, r, g, t, count);
-  LSP_HIP(hipGetLastError());
+  LSP_LAUNCH("sub", 0, sub_kernel, dim3(grid1(count)), dim3(256), 0, st, r, g, t, count);
 }
 
 void k_cycle_init(double2* H, double2* gam, const double* scal, int restart, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(cycle_init_kernel, dim3(nrhs), dim3(256), 0, st, H, gam, scal, restart, nrhs);
-  LSP_HIP(hipGetLastError());
+  LSP_LAUNCH("cycle_init", 0, cycle_init_kernel, dim3(nrhs), dim3(256), 0, st, H, gam, scal, restart, nrhs);
 }
 
 void launch_widen(double2* y, const float2* x, long long count, hipStream_t st) {
-  hipLaunchKernelGGL(widen_kernel, dim3(grid1(count)), dim3(256), 0, st, y, x, count);
-  LSP_HIP(hipGetLastError());
+  LSP_LAUNCH("widen", 0, widen_kernel, dim3(grid1(count)), dim3(256), 0, st, y, x, count);
 }
 void launch_narrow(float2* y, const double2* x, long long count, hipStream_t st) {
-  hipLaunchKernelGGL(narrow_kernel, dim3(grid1(count)), dim3(256), 0, st, y, x, count);
-  LSP_HIP(hipGetLastError());
+  LSP_LAUNCH("narrow", 0, narrow_kernel, dim3(grid1(count)), dim3(256), 0, st, y, x, count);
 }
 void launch_scale_rhs(double2* y, const double2* x, double s, long long count, hipStream_t st) {
-  hipLaunchKernelGGL(scale_rhs_kernel, dim3(grid1(count)), dim3(256), 0, st, y, x, s, count);
-  LSP_HIP(hipGetLastError());
+  LSP_LAUNCH("scale_rhs", 0, scale_rhs_kernel, dim3(grid1(count)), dim3(256), 0, st, y, x, s, count);
 }
 
 }  // namespace lsp
@@ -325,16 +311,13 @@ inline unsigned grid_cap(long long count) {
 void k_fill_zero(void* p, long long bytes, hipStream_t st) {
   long long words = bytes / 4;
   if (words <= 0) return;
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_cap(words)), dim3(256), 0, st, (unsigned int*)p, words);
-  LSP_HIP(hipGetLastError());
+  LSP_LAUNCH("fill_zero", 0, fill_zero_kernel, dim3(grid_cap(words)), dim3(256), 0, st, (unsigned int*)p, words);
 }
 void k_fill_double(double* p, double v, long long count, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(fill_double_kernel, dim3(grid_cap(count)), dim3(256), 0, st, p, v, count);
-  LSP_HIP(hipGetLastError());
+  LSP_LAUNCH("fill_double", 0, fill_double_kernel, dim3(grid_cap(count)), dim3(256), 0, st, p, v, count);
 }
 void k_w2m(double* out, const double* m, double w2, long long N, hipStream_t st) {
-  hipLaunchKernelGGL(w2m_kernel, dim3(grid_cap(N)), dim3(256), 0, st, out, m, w2, N);
-  LSP_HIP(hipGetLastError());
+  LSP_LAUNCH("w2m", 0, w2m_kernel, dim3(grid_cap(N)), dim3(256), 0, st, out, m, w2, N);
 }
 }  // namespace lsp

@@ -82,6 +82,7 @@ struct ProblemPtrs {
   double2* partial;
   double2* E;
   void* F;
+  void* Dinv;
   FrontDev* fronts;
   int* idx;
   int* cpos;
@@ -114,6 +115,7 @@ size_t layout_problem(const lsp_plan* pl, int precision, void* base, ProblemPtrs
   q.E = cv.take<double2>(Ld);
   size_t esz = precision == LSP_MIXED ? sizeof(float2) : sizeof(double2);
   q.F = cv.take<char>((size_t)P.front_elems * esz);
+  q.Dinv = cv.take<char>((size_t)P.dinv_elems * esz);
   q.fronts = cv.take<FrontDev>(P.fronts.size());
   q.idx = cv.take<int>(P.idx.size());
   q.cpos = cv.take<int>(P.cpos.size());
@@ -190,7 +192,6 @@ struct lsp_problem {
   ProblemPtrs d{};
   FftPlanDev<double> fp64{};
   FftPlanDev<float> fp32{};
-  int nb = 32;
   bool factored = false;
   double min_pivot_ratio = 0.0;
   double* host_scal = nullptr;  // pinned
@@ -310,14 +311,14 @@ void apply_precond(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2*
   hipStream_t st = pb->st;
   if (pb->precision == LSP_FP64) {
     launch_applyQ<double2>((double2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
-    MfDev<double> mf{(double2*)pb->d.F, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+    MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
                      pb->d.pivstat};
-    mf_solve<double>(mf, P, pb->nb, nrhs, (const double2*)s.zq, out, (double2*)s.vbuf, st);
+    mf_solve<double>(mf, P, nrhs, (const double2*)s.zq, out, (double2*)s.vbuf, st);
   } else {
     launch_applyQ<float2>((float2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
-    MfDev<float> mf{(float2*)pb->d.F, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+    MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
                     pb->d.pivstat};
-    mf_solve<float>(mf, P, pb->nb, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st);
+    mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st);
     launch_widen(out, (const float2*)s.xs, (long long)nrhs * P.N, st);
   }
 }
@@ -326,14 +327,14 @@ void solve_M(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2* z, do
   const Plan& P = pb->plan->p;
   hipStream_t st = pb->st;
   if (pb->precision == LSP_FP64) {
-    MfDev<double> mf{(double2*)pb->d.F, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+    MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
                      pb->d.pivstat};
-    mf_solve<double>(mf, P, pb->nb, nrhs, z, x, (double2*)s.vbuf, st);
+    mf_solve<double>(mf, P, nrhs, z, x, (double2*)s.vbuf, st);
   } else {
     launch_narrow((float2*)s.zq, z, (long long)nrhs * P.N, st);
-    MfDev<float> mf{(float2*)pb->d.F, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+    MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
                     pb->d.pivstat};
-    mf_solve<float>(mf, P, pb->nb, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st);
+    mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st);
     launch_widen(x, (const float2*)s.xs, (long long)nrhs * P.N, st);
   }
 }
@@ -400,7 +401,7 @@ lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts, 
     LSP_REQUIRE(o.restart >= 1 && o.restart < kMaxVec, "restart must be in [1, 31]");
     LSP_REQUIRE(o.max_iters >= 1, "max_iters must be >= 1");
     LSP_REQUIRE(o.precision == LSP_FP64 || o.precision == LSP_MIXED, "unknown precision");
-    LSP_REQUIRE(o.panel == 0 || (o.panel >= 4 && o.panel <= kNbMax), "panel must be 0 or in [4, 32]");
+    LSP_REQUIRE(o.panel == 0 || o.panel == kNbMax, "panel must be 0 (auto) or 32");
     std::unique_ptr<lsp_plan> pl(new lsp_plan());
     build_plan(pl->p, n, d, max_nrhs, o);
     fix_radices(pl->p);
@@ -423,6 +424,25 @@ lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* s) {
   s->factor_entries = P.factor_entries;
   s->front_entries = (double)P.front_elems;
   s->factor_flops = P.flops;
+  s->sweep_entries = P.sweep_entries;
+  s->update_flops = P.update_flops;
+  return LSP_OK;
+}
+
+lsp_status lsp_plan_get_tiles(const lsp_plan* plan, int* tiles, int cap) {
+  if (!plan || (!tiles && cap > 0) || cap < 0) return fail(LSP_ERR_ARG, "null argument");
+  const Plan& P = plan->p;
+  for (int l = 0; l < std::min(cap, P.nlevels); ++l) tiles[l] = P.level_tile[l];
+  return LSP_OK;
+}
+
+lsp_status lsp_plan_set_tiles(lsp_plan* plan, const int* tiles, int n) {
+  if (!plan || !tiles) return fail(LSP_ERR_ARG, "null argument");
+  Plan& P = plan->p;
+  if (n != P.nlevels) return fail(LSP_ERR_ARG, "tile count must equal the number of levels");
+  for (int l = 0; l < n; ++l)
+    if (tiles[l] != 32 && tiles[l] != 64 && tiles[l] != 128) return fail(LSP_ERR_ARG, "tiles must be 32, 64 or 128");
+  for (int l = 0; l < n; ++l) P.level_tile[l] = tiles[l];
   return LSP_OK;
 }
 
@@ -454,7 +474,6 @@ lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, vo
     pb->omega = omega;
     pb->st = (hipStream_t)stream;
     LSP_HIP(hipGetDevice(&pb->device));
-    pb->nb = P.opts.panel > 0 ? P.opts.panel : kNbMax;
     char* base = (char*)align_up((size_t)ws_dev, 256);
     LSP_REQUIRE(ws_bytes - ((size_t)base - (size_t)ws_dev) >= need - 256, "problem workspace too small");
     layout_problem(plan, prec, base, &pb->d);
@@ -506,13 +525,13 @@ lsp_status lsp_factor(lsp_problem* pb) {
     const Plan& P = pb->plan->p;
     k_fill_double(pb->d.pivstat, 1e300, (long long)P.fronts.size(), pb->st);
     if (pb->precision == LSP_FP64) {
-      MfDev<double> mf{(double2*)pb->d.F, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+      MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
                        pb->d.pivstat};
-      mf_factor<double>(mf, P, pb->nb, pb->st);
+      mf_factor<double>(mf, P, pb->st);
     } else {
-      MfDev<float> mf{(float2*)pb->d.F, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+      MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
                       pb->d.pivstat};
-      mf_factor<float>(mf, P, pb->nb, pb->st);
+      mf_factor<float>(mf, P, pb->st);
     }
     std::vector<double> ps(P.fronts.size());
     LSP_HIP(hipMemcpyAsync(ps.data(), pb->d.pivstat, ps.size() * sizeof(double), hipMemcpyDeviceToHost, pb->st));

@@ -80,6 +80,28 @@ template <> __host__ __device__ inline float2 from_c128<float2>(double2 a) { ret
 __host__ __device__ inline double2 widen(double2 a) { return a; }
 __host__ __device__ inline double2 widen(float2 a) { return to_c128(a); }
 
+// Brackets one kernel launch with HIP events when timing is enabled
+// (lsp_timing_enable); a no-op otherwise.  esize tags the element type.
+class KTimer {
+ public:
+  KTimer(const char* name, int esize, hipStream_t st);
+  ~KTimer();
+  KTimer(const KTimer&) = delete;
+  KTimer& operator=(const KTimer&) = delete;
+
+ private:
+  hipStream_t st_;
+  hipEvent_t a_, b_;
+  std::string key_;
+};
+
+#define LSP_LAUNCH(name, esize, kernel, grid, block, shm, st, ...)     \
+  do {                                                                 \
+    ::lsp::KTimer kt_((name), (esize), (st));                          \
+    hipLaunchKernelGGL(kernel, grid, block, shm, st, __VA_ARGS__);     \
+    LSP_HIP(hipGetLastError());                                        \
+  } while (0)
+
 inline int ipow(int b, int e) { int r = 1; while (e-- > 0) r *= b; return r; }
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

@@ -149,7 +149,8 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
   P.level_maxpq.assign(P.nlevels, 0);
   P.fronts.resize(nodes.size());
   P.idx.clear();
-  long long f_off = 0, piv_off = 0;
+  long long f_off = 0, piv_off = 0, dinv_off = 0;
+  P.nb = opts.panel > 0 ? opts.panel : 32;
   P.flops = 0.0; P.factor_entries = 0.0; P.max_front = 0; P.max_p = 0;
   for (size_t k = 0; k < order.size(); ++k) {
     const Node& nd = nodes[order[k]];
@@ -161,6 +162,8 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
     f.idx_off = (long long)P.idx.size();
     f.f_off = f_off;
     f.piv_off = piv_off;
+    f.dinv_off = dinv_off;
+    dinv_off += (long long)((f.p + P.nb - 1) / P.nb) * 2 * P.nb * P.nb;
     f.level = nd.height;
     f.pad = 0;
     P.idx.insert(P.idx.end(), nd.I.begin(), nd.I.end());
@@ -179,9 +182,19 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
     for (long long j = 0; j < f.p; ++j) cm += (double)(m - j - 1) * (double)(m - j - 1);
     P.flops += 8.0 * cm;
     P.factor_entries += (double)m * m - (double)f.q * f.q;
+    for (int k0 = 0; k0 < f.p; k0 += P.nb) {
+      int kb = std::min(P.nb, f.p - k0);
+      P.sweep_entries += (double)(m - k0 - kb) * kb + (double)P.nb * P.nb;
+      P.update_flops += 8.0 * (double)(m - k0 - kb) * (double)(m - k0 - kb) * kb;
+    }
   }
   for (int l = 0; l < P.nlevels; ++l) P.level_ptr[l + 1] += P.level_ptr[l];
+  // default trailing-update tiles by front order; an autotuner may replace them
+  P.level_tile.assign(P.nlevels, 64);
+  for (int l = 0; l < P.nlevels; ++l)
+    P.level_tile[l] = P.level_maxpq[l] <= 160 ? 32 : (P.level_maxpq[l] >= 1024 ? 128 : 64);
   P.front_elems = f_off;
+  P.dinv_elems = dinv_off;
   P.sum_p = piv_off;
   P.sum_pq = (long long)P.idx.size();
   LSP_REQUIRE(P.sum_p == P.N, "nested dissection lost grid points");

@@ -18,6 +18,7 @@ struct FrontDev {
   long long idx_off;      // offset into the concatenated index lists (p+q ints)
   long long f_off;        // offset of the front matrix, in complex elements
   long long piv_off;      // offset of its p pivot / permutation entries
+  long long dinv_off;     // offset of its inverted diagonal panel blocks
   int level, pad;
 };
 
@@ -30,11 +31,14 @@ struct Plan {
                                   // same grid point in child 0 / child 1 front, or -1
   std::vector<int> level_ptr;     // fronts of level l are [level_ptr[l], level_ptr[l+1])
   std::vector<int> level_maxp, level_maxpq;
+  std::vector<int> level_tile;    // trailing-update tile (32, 64 or 128) per level
   int nlevels = 0;
   long long front_elems = 0;      // sum (p+q)^2
+  long long dinv_elems = 0;       // sum over panels of 2 nb^2
+  int nb = 32;                    // frontal panel width
   long long sum_p = 0, sum_pq = 0;
   int max_front = 0, max_p = 0;
-  double flops = 0.0, factor_entries = 0.0;
+  double flops = 0.0, factor_entries = 0.0, sweep_entries = 0.0, update_flops = 0.0;
   std::vector<int> radices;       // FFT radices for L, in pass order
 };
 

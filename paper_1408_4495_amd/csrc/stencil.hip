@@ -339,30 +339,23 @@ void compute_stencils(const double2* ktab, int n, int d, const ClassGeom* geo_de
                       double* sigma_pad, hipStream_t st) {
   (void)maxF;
   dim3 grid(nblk, nclass);
-  hipLaunchKernelGGL(gram_kernel<false>, grid, dim3(256), 0, st, ktab, n, d, geo_dev, (const double2*)nullptr,
+  LSP_LAUNCH("gram", 0, gram_kernel<false>, grid, dim3(256), 0, st, ktab, n, d, geo_dev, (const double2*)nullptr,
                      partial, nblk);
-  LSP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(nclass), dim3(256), 0, st, partial, G, nblk, nclass);
-  LSP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(eigen_kernel, dim3(nclass), dim3(64), 0, st, G, geo_dev, U1, (const double2*)nullptr, ktab, n,
+  LSP_LAUNCH("gram_reduce", 0, gram_reduce_kernel, dim3(nclass), dim3(256), 0, st, partial, G, nblk, nclass);
+  LSP_LAUNCH("eigen", 0, eigen_kernel, dim3(nclass), dim3(64), 0, st, G, geo_dev, U1, (const double2*)nullptr, ktab, n,
                      d, 0, alpha_pad, C_pad, sigma_pad);
-  LSP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(gram_kernel<true>, grid, dim3(256), 0, st, ktab, n, d, geo_dev, U1, partial, nblk);
-  LSP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(nclass), dim3(256), 0, st, partial, G, nblk, nclass);
-  LSP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(eigen_kernel, dim3(nclass), dim3(64), 0, st, G, geo_dev, (double2*)nullptr, U1, ktab, n, d, 1,
+  LSP_LAUNCH("gram", 0, gram_kernel<true>, grid, dim3(256), 0, st, ktab, n, d, geo_dev, U1, partial, nblk);
+  LSP_LAUNCH("gram_reduce", 0, gram_reduce_kernel, dim3(nclass), dim3(256), 0, st, partial, G, nblk, nclass);
+  LSP_LAUNCH("eigen", 0, eigen_kernel, dim3(nclass), dim3(64), 0, st, G, geo_dev, (double2*)nullptr, U1, ktab, n, d, 1,
                      alpha_pad, C_pad, sigma_pad);
-  LSP_HIP(hipGetLastError());
 }
 
 void launch_assemble(double2* Mval, const double2* alpha_pad, const double2* C_pad, const double* w2m, int n, int d,
                      long long N, hipStream_t st) {
   long long total = N * (d == 2 ? 9 : 27);
   int bs = 256;
-  hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, Mval, alpha_pad,
+  LSP_LAUNCH("assemble", 0, assemble_kernel, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, Mval, alpha_pad,
                      C_pad, w2m, n, d, N);
-  LSP_HIP(hipGetLastError());
 }
 
 template <typename Cx>
@@ -370,9 +363,8 @@ void launch_applyQ(Cx* y, const double2* x, const double2* alpha_pad, int n, int
                    hipStream_t st) {
   long long total = N * nrhs;
   int bs = 256;
-  hipLaunchKernelGGL(applyQ_kernel<Cx>, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, y, x, alpha_pad,
+  LSP_LAUNCH("applyQ", (int)sizeof(Cx), applyQ_kernel<Cx>, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, y, x, alpha_pad,
                      n, d, N, nrhs);
-  LSP_HIP(hipGetLastError());
 }
 
 template void launch_applyQ<double2>(double2*, const double2*, const double2*, int, int, long long, int, hipStream_t);

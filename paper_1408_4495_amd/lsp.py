@@ -21,7 +21,8 @@ EXPORTED = ["lsp_options_default", "lsp_plan_create", "lsp_plan_destroy", "lsp_p
             "lsp_plan_bytes", "lsp_setup", "lsp_problem_destroy", "lsp_factor", "lsp_solve",
             "lsp_apply_op", "lsp_apply_K", "lsp_apply_Q", "lsp_solve_M", "lsp_apply_precond",
             "lsp_get_kernel_table", "lsp_get_stencils", "lsp_get_matrix", "lsp_status_string",
-            "lsp_last_error"]
+            "lsp_last_error", "lsp_timing_enable", "lsp_timing_reset", "lsp_timing_count",
+            "lsp_timing_get", "lsp_plan_get_tiles", "lsp_plan_set_tiles"]
 
 
 class Options(ctypes.Structure):
@@ -39,7 +40,8 @@ class PlanStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("d", ctypes.c_int), ("N", ctypes.c_int), ("L", ctypes.c_int),
                 ("nfronts", ctypes.c_int), ("nlevels", ctypes.c_int), ("max_front", ctypes.c_int),
                 ("max_pivots", ctypes.c_int), ("factor_entries", ctypes.c_double),
-                ("front_entries", ctypes.c_double), ("factor_flops", ctypes.c_double)]
+                ("front_entries", ctypes.c_double), ("factor_flops", ctypes.c_double),
+                ("sweep_entries", ctypes.c_double), ("update_flops", ctypes.c_double)]
 
 
 class LspError(RuntimeError):
@@ -76,6 +78,8 @@ def load():
         "lsp_get_kernel_table": [vp, vp],
         "lsp_get_stencils": [vp, vp, vp, vp],
         "lsp_get_matrix": [vp, vp],
+        "lsp_plan_get_tiles": [vp, ctypes.POINTER(ci), ci],
+        "lsp_plan_set_tiles": [vp, ctypes.POINTER(ci), ci],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -89,6 +93,15 @@ def load():
     lib.lsp_status_string.restype = ctypes.c_char_p
     lib.lsp_last_error.argtypes = [ctypes.c_char_p, sz]
     lib.lsp_last_error.restype = None
+    lib.lsp_timing_enable.argtypes = [ci]
+    lib.lsp_timing_enable.restype = ci
+    lib.lsp_timing_reset.argtypes = []
+    lib.lsp_timing_reset.restype = ci
+    lib.lsp_timing_count.argtypes = []
+    lib.lsp_timing_count.restype = ci
+    lib.lsp_timing_get.argtypes = [ci, ctypes.c_char_p, sz, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_longlong)]
+    lib.lsp_timing_get.restype = ci
     _lib = lib
     return lib
 
@@ -102,6 +115,30 @@ def _check(status):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def timing_enable(on=True):
+    """Bracket every library kernel launch with HIP events (see lsp.h)."""
+    _check(load().lsp_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    _check(load().lsp_timing_reset())
+
+
+def timing_read():
+    """{kernel name: (total ms, launches)} recorded since the last reset."""
+    lib = load()
+    n = lib.lsp_timing_count()
+    if n < 0:
+        raise LspError(3, "HIP error while reading kernel timings")
+    out = {}
+    buf = ctypes.create_string_buffer(256)
+    for i in range(n):
+        ms, cnt = ctypes.c_double(), ctypes.c_longlong()
+        _check(lib.lsp_timing_get(i, buf, 256, ctypes.byref(ms), ctypes.byref(cnt)))
+        out[buf.value.decode()] = (ms.value, cnt.value)
+    return out
 
 
 class Plan:
@@ -127,6 +164,16 @@ class Plan:
         pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
         _check(_lib.lsp_plan_bytes(self._h, prec, nrhs, ctypes.byref(pb), ctypes.byref(sb)))
         return pb.value, sb.value
+
+    def tiles(self):
+        nl = self.stats()["nlevels"]
+        arr = (ctypes.c_int * nl)()
+        _check(_lib.lsp_plan_get_tiles(self._h, arr, nl))
+        return list(arr)
+
+    def set_tiles(self, tiles):
+        arr = (ctypes.c_int * len(tiles))(*tiles)
+        _check(_lib.lsp_plan_set_tiles(self._h, arr, len(tiles)))
 
     def stats(self):
         s = PlanStats()

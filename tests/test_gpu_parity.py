@@ -172,3 +172,126 @@ def test_c1_end_to_end_fp64():
     A = np.eye(n ** d) + K * (omega ** 2 * m)[None, :]
     u_star = np.linalg.solve(A, K @ (-omega ** 2 * m * w["uI"][0]))
     assert _rel(u.cpu().numpy()[0], u_star) <= np.linalg.cond(A) * 1e-8
+
+
+def test_c1_end_to_end_mixed():
+    """Mixed path (complex64 preconditioner and Arnoldi operator, complex128
+    Arnoldi/residual/update): true residual <= 1e-8 (hard), and the error to
+    the oracle solution is bounded by cond(A) * 1e-8."""
+    w = synth.workload("c1")
+    n, d, omega, m = w["n"], w["d"], w["omega"], w["m"]
+    lsp, torch, plan, pb = _problem(n, d, omega, m, precision="mixed")
+    pb.factor()
+    u, info, st = pb.solve(w["uI"])
+    assert st == 0 and info[0]["converged"] and info[0]["relres_true"] <= 1e-8
+    ref = OracleProblem(n, d, omega, m).solve(w["uI"][0], tol=1e-12)
+    assert _rel(u.cpu().numpy()[0], ref.x) <= 1e-7
+    op = Operator(n, d, omega, m)
+    g = op.rhs(w["uI"][0])
+    assert np.linalg.norm(g - op.apply(u.cpu().numpy()[0])) <= 1e-8 * np.linalg.norm(g)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_equals_solo_bitwise(prec):
+    """Lockstep batching: each right-hand side of a block of 5 (groups of 4 + 1
+    in the triangular sweeps) is bit-identical to its solo solve."""
+    n, d = 48, 2
+    omega = 2 * np.pi * n / 8
+    rng = np.random.default_rng([14084495, 77])
+    m = synth.medium_bumps(n, d, rng, 4, 0.2, 0.8, 0.05, 0.1, 0.0, 0.3)
+    uI = synth.plane_waves(n, d, omega, synth.directions_2d(5, 0.3))
+    lsp, torch, plan, pb = _problem(n, d, omega, m, max_nrhs=5, precision=prec)
+    pb.factor()
+    u_all, info_all, st = pb.solve(uI)
+    assert st == 0
+    for r in (0, 3, 4):
+        u1, info1, st1 = pb.solve(uI[r:r + 1])
+        assert st1 == 0
+        assert torch.equal(u1[0], u_all[r])
+        assert info1[0]["iters"] == info_all[r]["iters"]
+
+
+def test_c2_full_size_fp64_and_mixed():
+    """2D n=256 workload (the benchmark's): both paths reach a true residual
+    <= 1e-8 as measured by the oracle's own FFT operator; FP64 matches the
+    oracle's solution to 1e-8 with iterations within 1; mixed differs from it
+    by at most cond-scaled 1e-7."""
+    w = synth.workload("c2")
+    n, d, omega, m = w["n"], w["d"], w["omega"], w["m"]
+    ref = OracleProblem(n, d, omega, m).solve(w["uI"][0])
+    op = Operator(n, d, omega, m)
+    g = op.rhs(w["uI"][0])
+    for prec in ("fp64", "mixed"):
+        lsp, torch, plan, pb = _problem(n, d, omega, m, precision=prec)
+        pb.factor()
+        u, info, st = pb.solve(w["uI"])
+        assert st == 0 and info[0]["converged"]
+        u = u.cpu().numpy()[0]
+        assert np.linalg.norm(g - op.apply(u)) <= 1e-8 * np.linalg.norm(g)
+        if prec == "fp64":
+            assert _rel(u, ref.x) <= 1e-8
+            assert abs(info[0]["iters"] - ref.iters) <= 1
+        else:
+            assert _rel(u, ref.x) <= 1e-6
+
+
+@pytest.mark.parametrize("n", [16, 24])
+def test_3d_end_to_end(n):
+    """3D Gaussian-bump medium, 2 directions: FP64 GPU vs oracle (1e-8,
+    iterations within 1); n=24 uses FFT length 48 = 2^4 3 (radix 3)."""
+    d = 3
+    omega = 2 * np.pi * n / 8
+    rng = np.random.default_rng([14084495, 3, n])
+    m = synth.medium_bumps(n, d, rng, 3, 0.3, 0.7, 0.08, 0.12, 0.0, 0.3)
+    uI = synth.plane_waves(n, d, omega, synth.directions_fibonacci(2, rng))
+    lsp, torch, plan, pb = _problem(n, d, omega, m, max_nrhs=2)
+    pb.factor()
+    u, info, st = pb.solve(uI)
+    assert st == 0
+    prob = OracleProblem(n, d, omega, m)
+    for r in range(2):
+        ref = prob.solve(uI[r])
+        assert _rel(u.cpu().numpy()[r], ref.x) <= 1e-8
+        assert abs(info[r]["iters"] - ref.iters) <= 1
+
+
+def test_kernel_timing_registry():
+    """Per-kernel HIP-event timing records the library's launches by name."""
+    lsp, torch = _lsp()
+    w = synth.workload("c1")
+    lsp.timing_reset()
+    lsp.timing_enable(True)
+    try:
+        plan = lsp.Plan(w["n"], w["d"])
+        pb = lsp.Problem(plan, w["omega"], w["m"])
+        pb.factor()
+        pb.solve(w["uI"])
+    finally:
+        lsp.timing_enable(False)
+    t = lsp.timing_read()
+    names = {k.split(" ")[0] for k in t}
+    assert {"ktable", "gram", "eigen", "diag_lu", "gemm_update", "fwd", "bwd", "fft_conv"} <= names
+    assert all(ms > 0 and cnt > 0 for ms, cnt in t.values())
+
+
+def test_tile_tables_give_same_factor():
+    """Every trailing-update tile shape (32/64/128) yields the same M^{-1} z up
+    to rounding (1e-12), and the autotuner returns a valid per-level table."""
+    n, d = 64, 2
+    omega = 2 * np.pi * n / 8
+    m = synth.medium_single_bump(n, d, 0.25, 0.12)
+    lsp, torch, plan, pb = _problem(n, d, omega, m)
+    nl = plan.stats()["nlevels"]
+    z = synth.random_complex((1, n ** d), seed=21)
+    ref = None
+    for t in (32, 64, 128):
+        plan.set_tiles([t] * nl)
+        pb.factor()
+        x = pb.solve_M(z).cpu().numpy()
+        if ref is None:
+            ref = x
+        assert _rel(x, ref) <= 1e-12
+    from paper_1408_4495_amd.autotune import tune_tiles
+    res = tune_tiles(48, 2, "fp64", reps=1)
+    assert len(res["tiles"]) > 0 and all(t in (32, 64, 128) for t in res["tiles"])
+    assert res["factor_ms"] <= min(res["uniform_ms"].values()) * 1.05
