@@ -287,13 +287,15 @@ __global__ void __launch_bounds__(1024) fft_lines_kernel(cplx<T>* __restrict__ W
 }
 
 template <typename T>
-int lines_per_wg(int L, int P) {
+int lines_per_wg(int L, int P, long long total_lines) {
   // up to 132 KB of the 160 KB LDS a gfx950 workgroup may use; a power of two
-  // so that strided passes read aligned runs of consecutive lines
+  // so that strided passes read aligned runs of consecutive lines; and no more
+  // lines per workgroup than keeps about 512 workgroups in flight
   size_t per_line = (size_t)(L + 1) * sizeof(cplx<T>);
   int cap = (int)((132 * 1024) / per_line);
+  long long want = std::max<long long>(1, total_lines / 512);
   int lpw = 1;
-  while (lpw * 2 <= std::min(cap, 16) && lpw * 2 * P <= 1024) lpw *= 2;
+  while (lpw * 2 <= std::min<long long>(std::min(cap, 16), want) && lpw * 2 * P <= 1024) lpw *= 2;
   return lpw;
 }
 
@@ -303,7 +305,7 @@ void launch_lines(const FftPlanDev<T>& fp, cplx<T>* W, const double2* x, double2
                   int nrhs, hipStream_t st) {
   LineArgs a;
   a.n = fp.n; a.d = fp.d; a.L = fp.L; a.P = fp.L / EPT;
-  a.LPW = lines_per_wg<T>(fp.L, a.P);
+  a.LPW = lines_per_wg<T>(fp.L, a.P, (long long)ncols * nouter * nrhs);
   a.Lp = fp.L + 1;
   a.ncols = ncols; a.cs = cs; a.os = os; a.es = es; a.rl = rl; a.wl = wl; a.inv = inv;
   a.wstride = fp.wstride; a.fstride = fp.N;

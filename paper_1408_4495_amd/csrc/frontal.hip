@@ -28,6 +28,7 @@ namespace lsp {
 namespace {
 
 constexpr int NB = kNbMax;
+constexpr size_t kVecLds = 80 * 1024;  // LDS for a front's working vectors in the sweeps
 
 // ---------------------------------------------------------------- assembly
 template <typename T>
@@ -73,93 +74,97 @@ __global__ void __launch_bounds__(256) assemble_front_kernel(cplx<T>* __restrict
   }
 }
 
-// ---------------------------------------------------------------- diagonal block LU (one wave)
-// Also writes L11^{-1} (unit lower) and U11^{-1} to the front's inverse store:
-// panel b of a front keeps [Linv | Uinv], each NB x NB column-major, zero
-// outside the kb x kb block.
+// ---------------------------------------------------------------- diagonal block LU
+// LU with partial pivoting of a panel's NB x NB diagonal block (padded with
+// the identity when kb < NB, which leaves the kb x kb LU unchanged), plus the
+// inverses L11^{-1} (unit lower) and U11^{-1} of its triangular factors,
+// written to the front's inverse store: panel b keeps [Linv | Uinv], each
+// NB x NB column-major, zero outside the kb x kb block.
+// 1024 threads, one element each: thread t holds entry (r, c), r = t % 32,
+// c = t / 32, so each column is one half-wave; the pivot row and the
+// multipliers of each step go through LDS.
 template <typename T>
-__global__ void __launch_bounds__(64) diag_lu_kernel(cplx<T>* __restrict__ Fbuf, cplx<T>* __restrict__ Dinv,
-                                                     const FrontDev* __restrict__ fr, int* __restrict__ piv,
-                                                     int* __restrict__ perm, double* __restrict__ pivstat, int first,
-                                                     int k0) {
-  __shared__ cplx<T> Bk[NB][NB + 1];
-  __shared__ cplx<T> X[NB][NB + 1];
-  __shared__ int permb[NB];
+__global__ void __launch_bounds__(1024) diag_lu_kernel(cplx<T>* __restrict__ Fbuf, cplx<T>* __restrict__ Dinv,
+                                                           const FrontDev* __restrict__ fr, int* __restrict__ piv,
+                                                           int* __restrict__ perm, double* __restrict__ pivstat,
+                                                           int first, int k0) {
+  static_assert(NB == 32, "thread layout assumes 32-wide panels");
+  __shared__ cplx<T> A[NB][NB + 1];
+  __shared__ cplx<T> rowU[NB], colL[NB];
+  __shared__ cplx<T> xrow[2][NB];
+  __shared__ int origs[NB];
+  __shared__ int s_pr;
+  __shared__ T s_best;
+  __shared__ cplx<T> s_inv;
   const FrontDev f = fr[first + blockIdx.x];
   if (f.p <= k0) return;
   const int kb = min(NB, f.p - k0);
   const int m = f.p + f.q;
   cplx<T>* F = Fbuf + f.f_off;
-  const int lane = threadIdx.x;
-  for (int e = lane; e < kb * kb; e += 64) {
-    int r = e % kb, c = e / kb;
-    Bk[r][c] = F[(k0 + r) + (long long)(k0 + c) * m];
-  }
-  if (lane < NB) permb[lane] = lane;
-  __syncthreads();
+  const int tid = threadIdx.x;
+  const int r = tid & 31, c = tid >> 5;
+  cplx<T> a = mk<T>(r == c ? 1 : 0, 0);
+  if (r < kb && c < kb) a = F[(k0 + r) + (long long)(k0 + c) * m];
+  if (tid < NB) origs[tid] = tid;
   double worst = 1e300;
-  for (int j = 0; j < kb; ++j) {
-    T best = (T)-1;
-    int bi = kb;
-    if (lane >= j && lane < kb) { best = cabs1(Bk[lane][j]); bi = lane; }
-    for (int off = 32; off > 0; off >>= 1) {
-      T ob = __shfl_xor(best, off, 64);
-      int oi = __shfl_xor(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  for (int j = 0; j < NB; ++j) {
+    if (c == j) {
+      T best = r >= j ? cabs1(a) : (T)-1;
+      int bi = r;
+      for (int off = 16; off > 0; off >>= 1) {
+        T ob = __shfl_xor(best, off, 32);
+        int oi = __shfl_xor(bi, off, 32);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (r == 0) { s_pr = bi; s_best = best; }
     }
-    const int pr = bi;
-    const T colmax = best;
+    __syncthreads();
+    const int pr = s_pr;
+    const T colmax = s_best;
     if (pr != j) {
-      if (lane < kb) { cplx<T> t = Bk[j][lane]; Bk[j][lane] = Bk[pr][lane]; Bk[pr][lane] = t; }
-      if (lane == 0) { int t = permb[j]; permb[j] = permb[pr]; permb[pr] = t; }
+      if (r == j || r == pr) A[r][c] = a;
+      __syncthreads();
+      if (r == j) a = A[pr][c];
+      else if (r == pr) a = A[j][c];
+      if (tid == 0) { int t = origs[j]; origs[j] = origs[pr]; origs[pr] = t; }
     }
-    if (lane == 0) piv[f.piv_off + k0 + j] = k0 + pr;
-    __syncthreads();
-    cplx<T> dj = Bk[j][j];
-    T dmag = cabs1(dj);
-    worst = fmin(worst, (dmag > 0 && colmax > 0) ? (double)dmag / (double)colmax : 0.0);
-    cplx<T> inv = dmag > 0 ? cdiv(mk<T>(1, 0), dj) : mk<T>(0, 0);
-    if (lane > j && lane < kb) {
-      cplx<T> l = cmul(Bk[lane][j], inv);
-      Bk[lane][j] = l;
-      for (int c = j + 1; c < kb; ++c) Bk[lane][c] = cfms(Bk[lane][c], l, Bk[j][c]);
+    if (tid == 0 && j < kb) piv[f.piv_off + k0 + j] = k0 + pr;
+    if (r == j) {
+      rowU[c] = a;
+      if (c == j) {
+        T dmag = cabs1(a);
+        s_inv = dmag > 0 ? cdiv(mk<T>(1, 0), a) : mk<T>(0, 0);
+        if (j < kb) s_best = (dmag > 0 && colmax > 0) ? (T)(dmag / colmax) : (T)0;
+      }
     }
     __syncthreads();
+    if (j < kb) worst = fmin(worst, (double)s_best);
+    if (c == j && r > j) { a = cmul(a, s_inv); colL[r] = a; }
+    __syncthreads();
+    if (c > j && r > j) a = cfms(a, colL[r], rowU[c]);
   }
-  for (int e = lane; e < kb * kb; e += 64) {
-    int r = e % kb, c = e / kb;
-    F[(k0 + r) + (long long)(k0 + c) * m] = Bk[r][c];
-  }
-  if (lane < kb) perm[f.piv_off + k0 + lane] = k0 + permb[lane];
-  if (lane == 0) pivstat[first + blockIdx.x] = fmin(pivstat[first + blockIdx.x], worst);
+  A[r][c] = a;
+  if (r < kb && c < kb) F[(k0 + r) + (long long)(k0 + c) * m] = a;
+  __syncthreads();
+  if (tid < kb) perm[f.piv_off + k0 + tid] = k0 + origs[tid];
+  if (tid == 0) pivstat[first + blockIdx.x] = fmin(pivstat[first + blockIdx.x], worst);
   cplx<T>* Li = Dinv + f.dinv_off + (long long)(k0 / NB) * 2 * NB * NB;
   cplx<T>* Ui = Li + NB * NB;
-  // L11^{-1}: lane c solves L x = e_c by forward substitution
-  if (lane < NB) {
-    const int c = lane;
-    for (int i = 0; i < NB; ++i) {
-      cplx<T> s = mk<T>(i == c && c < kb ? 1 : 0, 0);
-      if (i < kb && c < kb)
-        for (int j = c; j < i; ++j) s = cfms(s, Bk[i][j], X[j][c]);
-      X[i][c] = (i < kb && c < kb) ? s : mk<T>(0, 0);
-    }
-    for (int i = 0; i < NB; ++i) Li[i + NB * c] = X[i][c];
+  cplx<T> x = mk<T>(r == c ? 1 : 0, 0);
+  for (int j = 0; j < NB; ++j) {
+    if (r == j) xrow[j & 1][c] = x;
+    __syncthreads();
+    if (r > j) x = cfms(x, A[r][j], xrow[j & 1][c]);
   }
+  Li[r + NB * c] = (r < kb && c < kb) ? x : mk<T>(0, 0);
   __syncthreads();
-  // U11^{-1}: lane c solves U x = e_c by backward substitution
-  if (lane < NB) {
-    const int c = lane;
-    for (int i = NB - 1; i >= 0; --i) {
-      cplx<T> s = mk<T>(0, 0);
-      if (i < kb && c < kb && i <= c) {
-        s = mk<T>(i == c ? 1 : 0, 0);
-        for (int j = i + 1; j <= c; ++j) s = cfms(s, Bk[i][j], X[j][c]);
-        s = cdiv(s, Bk[i][i]);
-      }
-      X[i][c] = s;
-    }
-    for (int i = 0; i < NB; ++i) Ui[i + NB * c] = X[i][c];
+  x = mk<T>(r == c ? 1 : 0, 0);
+  for (int j = NB - 1; j >= 0; --j) {
+    if (r == j) { x = cdiv(x, A[j][j]); xrow[j & 1][c] = x; }
+    __syncthreads();
+    if (r < j) x = cfms(x, A[r][j], xrow[j & 1][c]);
   }
+  Ui[r + NB * c] = (r < kb && c < kb) ? x : mk<T>(0, 0);
 }
 
 // ---------------------------------------------------------------- panel products
@@ -308,19 +313,23 @@ __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ 
 // ---------------------------------------------------------------- solves
 // Right-hand sides are taken in groups of NR per workgroup (blockIdx.y), so
 // each factor entry is read once per group; a right-hand side's arithmetic
-// does not depend on the group it is in.
+// does not depend on the group it is in.  The front's working vectors live in
+// LDS when the level's largest front fits (vlds != 0), else in the per-front
+// vector buffer in HBM; either way the per-front vector buffer holds them at
+// the end (y_I for the backward sweep, the update for the parent).  The next
+// panel's inverted diagonal block is loaded while the current panel's
+// off-diagonal update runs.
 //
 // Forward sweep of one front: v = [z(I); 0] + children's updates; per panel:
 //   y_b = L11^{-1} (P_b v_b),  v(k1:m) -= L21 y_b.
-// v lives in the per-front vector buffer; afterwards v(0:p) = y_I and
-// v(p:m) = the update handed to the parent.
 template <typename T, int NR>
 __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
                                                   const FrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                   const int* __restrict__ cpos, const int* __restrict__ perm,
                                                   const cplx<T>* __restrict__ z, cplx<T>* __restrict__ vbuf, int first,
-                                                  int nrhs, long long N, long long vstride) {
-  __shared__ cplx<T> Li[NB][NB + 1];
+                                                  int nrhs, long long N, long long vstride, int vlds) {
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ cplx<T> Li[2][NB][NB + 1];
   __shared__ cplx<T> tb[NR][NB];
   __shared__ cplx<T> yb[NR][NB];
   const FrontDev f = fr[first + blockIdx.x];
@@ -333,6 +342,9 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
   long long coff[2] = {-1, -1};
   if (f.child0 >= 0) coff[0] = fr[f.child0].idx_off;
   if (f.child1 >= 0) coff[1] = fr[f.child1].idx_off;
+  cplx<T>* vg = vbuf + (long long)r0 * vstride + f.idx_off;   // HBM copy, stride vstride
+  cplx<T>* vp = vlds ? reinterpret_cast<cplx<T>*>(smem_raw) : vg;
+  const long long vs = vlds ? m : vstride;
   const int tid = threadIdx.x;
   for (int e = tid; e < m * nr; e += 256) {
     int r = e % m, k = e / m;
@@ -343,44 +355,60 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
       int q = cp[2 * r + c];
       if (q >= 0) s = cadd(s, vbuf[rb + coff[c] + q]);
     }
-    vbuf[rb + f.idx_off + r] = s;
+    vp[k * vs + r] = s;
   }
+  const cplx<T>* Lg0 = Dinv + f.dinv_off;
+  for (int e = tid; e < NB * NB; e += 256) Li[0][e % NB][e / NB] = Lg0[e];
   __syncthreads();
-  for (int k0 = 0; k0 < f.p; k0 += NB) {
+  for (int k0 = 0, b = 0; k0 < f.p; k0 += NB, ++b) {
     const int kb = min(NB, f.p - k0);
     const int k1 = k0 + kb;
-    const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(k0 / NB) * 2 * NB * NB;
-    for (int e = tid; e < NB * NB; e += 256) Li[e % NB][e / NB] = Lg[e];
+    const int cur = b & 1;
     for (int e = tid; e < NR * NB; e += 256) {
       int j = e % NB, k = e / NB;
-      tb[k][j] = (k < nr && j < kb) ? vbuf[(long long)(r0 + k) * vstride + f.idx_off + perm[f.piv_off + k0 + j]]
-                                    : mk<T>(0, 0);
+      tb[k][j] = (k < nr && j < kb) ? vp[k * vs + perm[f.piv_off + k0 + j]] : mk<T>(0, 0);
     }
     __syncthreads();
     for (int e = tid; e < NR * NB; e += 256) {
       int i = e % NB, k = e / NB;
       cplx<T> s = mk<T>(0, 0);
-      for (int j = 0; j <= i; ++j) s = cfma(s, Li[i][j], tb[k][j]);
+      for (int j = 0; j <= i; ++j) s = cfma(s, Li[cur][i][j], tb[k][j]);
       yb[k][i] = s;
-      if (k < nr && i < kb) vbuf[(long long)(r0 + k) * vstride + f.idx_off + k0 + i] = s;
+      if (k < nr && i < kb) vp[k * vs + k0 + i] = s;
     }
     __syncthreads();
+    if (k1 < f.p) {
+      const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(b + 1) * 2 * NB * NB;
+      for (int e = tid; e < NB * NB; e += 256) Li[cur ^ 1][e % NB][e / NB] = Lg[e];
+    }
     for (int r = k1 + tid; r < m; r += 256) {
       cplx<T> acc[NR];
 #pragma unroll
-      for (int k = 0; k < NR; ++k)
-        acc[k] = k < nr ? vbuf[(long long)(r0 + k) * vstride + f.idx_off + r] : mk<T>(0, 0);
-      for (int j = 0; j < kb; ++j) {
-        cplx<T> l = F[r + (long long)(k0 + j) * m];
+      for (int k = 0; k < NR; ++k) acc[k] = k < nr ? vp[k * vs + r] : mk<T>(0, 0);
+      // batches of 8 independent loads of the L21 row, then their updates
+      for (int j0 = 0; j0 < kb; j0 += 8) {
+        cplx<T> l[8];
 #pragma unroll
-        for (int k = 0; k < NR; ++k) acc[k] = cfms(acc[k], l, yb[k][j]);
+        for (int u = 0; u < 8; ++u)
+          l[u] = j0 + u < kb ? F[r + (long long)(k0 + j0 + u) * m] : mk<T>(0, 0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (j0 + u < kb) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) acc[k] = cfms(acc[k], l[u], yb[k][j0 + u]);
+          }
       }
 #pragma unroll
       for (int k = 0; k < NR; ++k)
-        if (k < nr) vbuf[(long long)(r0 + k) * vstride + f.idx_off + r] = acc[k];
+        if (k < nr) vp[k * vs + r] = acc[k];
     }
     __syncthreads();
   }
+  if (vlds)
+    for (int e = tid; e < m * nr; e += 256) {
+      int r = e % m, k = e / m;
+      vg[(long long)k * vstride + r] = vp[k * vs + r];
+    }
 }
 
 // Backward sweep: x_B from the global solution, then per panel from the last:
@@ -389,9 +417,10 @@ template <typename T, int NR>
 __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
                                                   const FrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                   cplx<T>* __restrict__ x, cplx<T>* __restrict__ vbuf, int first,
-                                                  int nrhs, long long N, long long vstride) {
+                                                  int nrhs, long long N, long long vstride, int vlds) {
   constexpr int G = 256 / NB;  // column groups
-  __shared__ cplx<T> Ui[NB][NB + 1];
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ cplx<T> Ui[2][NB][NB + 1];
   __shared__ cplx<T> part[G][NR][NB];
   __shared__ cplx<T> rb[NR][NB];
   const FrontDev f = fr[first + blockIdx.x];
@@ -400,29 +429,52 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
   const int m = f.p + f.q;
   const cplx<T>* F = Fbuf + f.f_off;
   const int* id = idx + f.idx_off;
+  cplx<T>* vg = vbuf + (long long)r0 * vstride + f.idx_off;
+  cplx<T>* vp = vlds ? reinterpret_cast<cplx<T>*>(smem_raw) : vg;
+  const long long vs = vlds ? m : vstride;
   const int tid = threadIdx.x;
-  for (int e = tid; e < f.q * nr; e += 256) {
-    int r = f.p + e % f.q, k = e / f.q;
-    vbuf[(long long)(r0 + k) * vstride + f.idx_off + r] = x[(long long)(r0 + k) * N + id[r]];
+  for (int e = tid; e < m * nr; e += 256) {
+    int r = e % m, k = e / m;
+    if (r >= f.p) vp[k * vs + r] = x[(long long)(r0 + k) * N + id[r]];
+    else if (vlds) vp[k * vs + r] = vg[(long long)k * vstride + r];
+  }
+  const int nblk = (f.p + NB - 1) / NB;
+  {
+    const cplx<T>* Ug = Dinv + f.dinv_off + (long long)(nblk - 1) * 2 * NB * NB + NB * NB;
+    for (int e = tid; e < NB * NB; e += 256) Ui[(nblk - 1) & 1][e % NB][e / NB] = Ug[e];
   }
   __syncthreads();
-  const int nblk = (f.p + NB - 1) / NB;
   for (int b = nblk - 1; b >= 0; --b) {
     const int k0 = b * NB;
     const int kb = min(NB, f.p - k0);
     const int k1 = k0 + kb;
-    const cplx<T>* Ug = Dinv + f.dinv_off + (long long)b * 2 * NB * NB + NB * NB;
-    for (int e = tid; e < NB * NB; e += 256) Ui[e % NB][e / NB] = Ug[e];
+    const int cur = b & 1;
+    if (b > 0) {
+      const cplx<T>* Ug = Dinv + f.dinv_off + (long long)(b - 1) * 2 * NB * NB + NB * NB;
+      for (int e = tid; e < NB * NB; e += 256) Ui[cur ^ 1][e % NB][e / NB] = Ug[e];
+    }
     const int j = tid % NB, grp = tid / NB;
     cplx<T> acc[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
     if (j < kb) {
-      for (int c = k1 + grp; c < m; c += G) {
-        cplx<T> u = F[(k0 + j) + (long long)c * m];
+      // batches of 4 independent loads of U12 (columns c, c+G, ...), then updates
+      for (int c0 = k1 + grp; c0 < m; c0 += 4 * G) {
+        cplx<T> u[4];
 #pragma unroll
-        for (int k = 0; k < NR; ++k)
-          if (k < nr) acc[k] = cfma(acc[k], u, vbuf[(long long)(r0 + k) * vstride + f.idx_off + c]);
+        for (int t = 0; t < 4; ++t) {
+          const int c = c0 + t * G;
+          u[t] = c < m ? F[(k0 + j) + (long long)c * m] : mk<T>(0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int c = c0 + t * G;
+          if (c < m) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k)
+              if (k < nr) acc[k] = cfma(acc[k], u[t], vp[k * vs + c]);
+          }
+        }
       }
     }
 #pragma unroll
@@ -432,16 +484,15 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
       int jj = e % NB, k = e / NB;
       cplx<T> s = part[0][k][jj];
       for (int g = 1; g < G; ++g) s = cadd(s, part[g][k][jj]);
-      rb[k][jj] = (k < nr && jj < kb) ? csub(vbuf[(long long)(r0 + k) * vstride + f.idx_off + k0 + jj], s)
-                                      : mk<T>(0, 0);
+      rb[k][jj] = (k < nr && jj < kb) ? csub(vp[k * vs + k0 + jj], s) : mk<T>(0, 0);
     }
     __syncthreads();
     for (int e = tid; e < NR * NB; e += 256) {
       int i = e % NB, k = e / NB;
       if (k >= nr || i >= kb) continue;
       cplx<T> s = mk<T>(0, 0);
-      for (int jj = i; jj < kb; ++jj) s = cfma(s, Ui[i][jj], rb[k][jj]);
-      vbuf[(long long)(r0 + k) * vstride + f.idx_off + k0 + i] = s;
+      for (int jj = i; jj < kb; ++jj) s = cfma(s, Ui[cur][i][jj], rb[k][jj]);
+      vp[k * vs + k0 + i] = s;
       x[(long long)(r0 + k) * N + id[k0 + i]] = s;
     }
     __syncthreads();
@@ -456,14 +507,18 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
   for (int l = 0; l < plan.nlevels; ++l) {
     const int first = plan.level_ptr[l];
     const int cnt = plan.level_ptr[l + 1] - first;
-    LSP_LAUNCH("fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NR>), dim3(cnt, groups), dim3(256), 0, st, mf.F, mf.Dinv, mf.fronts, mf.idx,
-                       mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N, vstride);
+    const size_t vb = (size_t)plan.level_maxpq[l] * NR * sizeof(cplx<T>);
+    const int vlds = vb <= kVecLds ? 1 : 0;
+    LSP_LAUNCH("fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NR>), dim3(cnt, groups), dim3(256), vlds ? vb : 0, st, mf.F,
+               mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N, vstride, vlds);
   }
   for (int l = plan.nlevels - 1; l >= 0; --l) {
     const int first = plan.level_ptr[l];
     const int cnt = plan.level_ptr[l + 1] - first;
-    LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR>), dim3(cnt, groups), dim3(256), 0, st, mf.F, mf.Dinv, mf.fronts, mf.idx, x,
-                       vbuf, first, nrhs, (long long)plan.N, vstride);
+    const size_t vb = (size_t)plan.level_maxpq[l] * NR * sizeof(cplx<T>);
+    const int vlds = vb <= kVecLds ? 1 : 0;
+    LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR>), dim3(cnt, groups), dim3(256), vlds ? vb : 0, st, mf.F,
+               mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, vstride, vlds);
   }
 }
 
@@ -481,14 +536,15 @@ void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
     LSP_LAUNCH("assemble_front", (int)sizeof(cplx<T>), assemble_front_kernel<T>, dim3(gx, cnt), dim3(256), 0, st, mf.F, mf.fronts, mf.idx, mf.cpos,
                        mf.Mval, first, plan.n, plan.d);
     for (int k0 = 0; k0 < maxp; k0 += NB) {
-      LSP_LAUNCH("diag_lu", (int)sizeof(cplx<T>), diag_lu_kernel<T>, dim3(cnt), dim3(64), 0, st, mf.F, mf.Dinv, mf.fronts, mf.piv, mf.perm,
-                         mf.pivstat, first, k0);
+LSP_LAUNCH("diag_lu", (int)sizeof(cplx<T>), diag_lu_kernel<T>, dim3(cnt), dim3(1024), 0, st, mf.F, mf.Dinv,
+                 mf.fronts, mf.piv, mf.perm, mf.pivstat, first, k0);
       int rem = maxm - k0 - 1;
       if (rem <= 0) continue;
       int tiles = (rem + 63) / 64;
       LSP_LAUNCH("panel_trsm", (int)sizeof(cplx<T>), panel_trsm_kernel<T>, dim3(tiles, cnt, 2), dim3(256), 0, st, mf.F, mf.Dinv, mf.fronts,
                          mf.perm, first, k0);
-      const int tile = plan.level_tile[l];
+      // complex128 128-wide tiles would need more than 256 VGPRs; use 64 there
+      const int tile = (sizeof(T) == 8 && plan.level_tile[l] == 128) ? 64 : plan.level_tile[l];
       const int gt = (rem + tile - 1) / tile;
       if (tile == 32)
         LSP_LAUNCH("gemm_update", (int)sizeof(cplx<T>), (gemm_update_kernel<T, 32>), dim3(gt, gt, cnt), dim3(256), 0, st,

@@ -72,8 +72,18 @@ __global__ void dots_final_kernel(const double2* __restrict__ partial, double2* 
   const int r = blockIdx.x;
   if (active && !active[r]) return;
   for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
-    double2 s = make_double2(0, 0);
-    for (int b = 0; b < nblk; ++b) s = cadd(s, partial[((long long)r * nblk + b) * kMaxVec + i]);
+    // eight interleaved partial sums (independent loads), combined in order
+    double2 acc8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc8[u] = make_double2(0, 0);
+    for (int b0 = 0; b0 < nblk; b0 += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (b0 + u < nblk) acc8[u] = cadd(acc8[u], partial[((long long)r * nblk + b0 + u) * kMaxVec + i]);
+    }
+    double2 s = acc8[0];
+#pragma unroll
+    for (int u = 1; u < 8; ++u) s = cadd(s, acc8[u]);
     h[(long long)r * kMaxVec + i] = s;
     double2* Hr = H + (long long)r * (restart + 1) * restart;
     if (mode == 0) Hr[i + (restart + 1) * k] = s;
@@ -225,8 +235,8 @@ inline unsigned grid1(long long count, int bs = 256, long long cap = 8192) {
 }  // namespace
 
 int dot_blocks(long long N) {
-  long long b = (N + 4095) / 4096;
-  return (int)std::max<long long>(1, std::min<long long>(b, 128));
+  long long b = (N + 1023) / 1024;
+  return (int)std::max<long long>(1, std::min<long long>(b, 256));
 }
 
 void k_dots(const double2* V, const double2* w, double2* partial, double2* h, double2* H, double* scal, int nvec,

@@ -247,7 +247,7 @@ void build_class_geometry(lsp_plan* pl) {
     g.interior = interior ? 1 : 0;
     pl->maxF = std::max(pl->maxF, g.F);
   }
-  long long nb = (pl->maxF + 4095) / 4096;
+  long long nb = (pl->maxF + 1023) / 1024;
   pl->gram_blocks = (int)std::max<long long>(1, std::min<long long>(nb, 512));
 }
 

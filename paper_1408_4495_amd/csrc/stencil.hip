@@ -29,10 +29,10 @@ namespace {
 constexpr int S = kMaxStencil;  // padded stencil / matrix order
 constexpr int CH = 48;          // far-set columns staged per step
 
-__device__ inline long long ktab_index(const int* t, int n, int d) {
+__device__ inline long long ktab_index(int t0, int t1, int t2, int n, int d) {
   long long n1 = n + 1;
-  long long r = t[0] + n1 * t[1];
-  if (d == 3) r += n1 * n1 * t[2];
+  long long r = t0 + n1 * t1;
+  if (d == 3) r += n1 * n1 * t2;
   return r;
 }
 
@@ -45,20 +45,30 @@ __global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ k
   __shared__ double2 Z[PASS2 ? S : 1][CH + 1];
   __shared__ double2 Us[PASS2 ? S * S : 1];
   const int c = blockIdx.y, blk = blockIdx.x, tid = threadIdx.x;
-  const ClassGeom g = geo[c];
+  const ClassGeom& g = geo[c];
+  __shared__ int soff[S][3];
+  for (int e = tid; e < S * 3; e += blockDim.x) soff[e / 3][e % 3] = g.off[e / 3][e % 3];
   const int s = g.s;
   const long long F = g.F;
+  const int flo[3] = {g.flo[0], g.flo[1], g.flo[2]};
+  const int fsz[3] = {g.fsz[0], g.fsz[1], g.fsz[2]};
+  const int interior = g.interior;
   const long long j0 = F * blk / nblk, j1 = F * (blk + 1) / nblk;
   if (PASS2) {
     for (int e = tid; e < S * S; e += blockDim.x) Us[e] = U1[(long long)c * S * S + e];
   }
+  // thread -> (pair, column group): small classes (few pairs) split the
+  // staged columns over several groups so that every thread accumulates
   const int npairs = s * (s + 1) / 2;
+  const int G = npairs <= 128 ? 256 / npairs : 1;
+  const int per = npairs <= 128 ? 1 : 2;
   int pa[2] = {0, 0}, pb[2] = {0, 0};
   bool own[2] = {false, false};
+  const int grp = npairs <= 128 ? tid / npairs : 0;
   double2 acc[2] = {make_double2(0, 0), make_double2(0, 0)};
-  for (int k = 0; k < 2; ++k) {
-    int p = tid + k * blockDim.x;
-    if (p < npairs) {
+  for (int k = 0; k < per; ++k) {
+    int p = npairs <= 128 ? tid % npairs : tid + k * blockDim.x;
+    if (p < npairs && grp < G) {
       int a = 0, rem = p;
       while (rem >= s - a) { rem -= s - a; ++a; }
       pa[k] = a; pb[k] = a + rem; own[k] = true;
@@ -74,13 +84,16 @@ __global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ k
         int j[3], t[3] = {0, 0, 0};
         long long rem = jf;
         bool near = true;
-        for (int ax = 0; ax < d; ++ax) {
-          j[ax] = g.flo[ax] + (int)(rem % g.fsz[ax]);
-          rem /= g.fsz[ax];
-          near = near && (j[ax] >= -1 && j[ax] <= 1);
-          t[ax] = abs(g.off[a][ax] - j[ax]);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          if (ax < d) {
+            j[ax] = flo[ax] + (int)(rem % fsz[ax]);
+            rem /= fsz[ax];
+            near = near && (j[ax] >= -1 && j[ax] <= 1);
+            t[ax] = abs(soff[a][ax] - j[ax]);
+          }
         }
-        if (!(g.interior && near)) v = ktab[ktab_index(t, n, d)];
+        if (!(interior && near)) v = ktab[ktab_index(t[0], t[1], t[2], n, d)];
       }
       X[a][jj] = v;
     }
@@ -94,10 +107,10 @@ __global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ k
       }
       __syncthreads();
     }
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < per; ++k) {
       if (!own[k]) continue;
       double2 sum = acc[k];
-      for (int jj = 0; jj < CH; ++jj) {
+      for (int jj = grp; jj < CH; jj += G) {
         double2 u = PASS2 ? Z[pa[k]][jj] : X[pa[k]][jj];
         double2 w = PASS2 ? Z[pb[k]][jj] : X[pb[k]][jj];
         sum = cadd(sum, cmulc(w, u));  // u * conj(w)
@@ -105,9 +118,22 @@ __global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ k
       acc[k] = sum;
     }
   }
+  // reduce the column groups in a fixed order
+  __syncthreads();
+  double2* red = &X[0][0];  // reuse the staging buffer: G x npairs <= 256 entries
+  if (npairs <= 128) {
+    if (own[0]) red[grp * npairs + (tid % npairs)] = acc[0];
+    __syncthreads();
+    if (tid < npairs) {
+      double2 sum = red[tid];
+      for (int q = 1; q < G; ++q) sum = cadd(sum, red[q * npairs + tid]);
+      acc[0] = sum;
+    }
+  }
   double2* out = partial + ((long long)blk * gridDim.y + c) * S * S;
-  for (int k = 0; k < 2; ++k) {
-    if (!own[k]) continue;
+  const bool writer = npairs <= 128 ? tid < npairs : true;
+  for (int k = 0; k < per; ++k) {
+    if (!own[k] || !writer) continue;
     out[pa[k] + S * pb[k]] = acc[k];
     out[pb[k] + S * pa[k]] = cconj(acc[k]);
   }
@@ -117,8 +143,18 @@ __global__ void gram_reduce_kernel(const double2* __restrict__ partial, double2*
                                    int nclass) {
   const int c = blockIdx.x;
   for (int e = threadIdx.x; e < S * S; e += blockDim.x) {
-    double2 sum = make_double2(0, 0);
-    for (int b = 0; b < nblk; ++b) sum = cadd(sum, partial[((long long)b * nclass + c) * S * S + e]);
+    // eight interleaved partial sums (independent loads), combined in order
+    double2 acc8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc8[u] = make_double2(0, 0);
+    for (int b0 = 0; b0 < nblk; b0 += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (b0 + u < nblk) acc8[u] = cadd(acc8[u], partial[((long long)(b0 + u) * nclass + c) * S * S + e]);
+    }
+    double2 sum = acc8[0];
+#pragma unroll
+    for (int u = 1; u < 8; ++u) sum = cadd(sum, acc8[u]);
     G[(long long)c * S * S + e] = sum;
   }
 }
@@ -192,7 +228,9 @@ __global__ void __launch_bounds__(64) eigen_kernel(const double2* __restrict__ G
   __shared__ int order[S];
   __shared__ double2 alpha[S];
   const int c = blockIdx.x, lane = threadIdx.x;
-  const ClassGeom g = geo[c];
+  const ClassGeom& g = geo[c];
+  __shared__ int soff[S][3];
+  for (int e = lane; e < S * 3; e += blockDim.x) soff[e / 3][e % 3] = g.off[e / 3][e % 3];
   const int s = g.s;
   for (int e = lane; e < S * S; e += blockDim.x) {
     A[e] = G[(long long)c * S * S + e];
@@ -230,7 +268,7 @@ __global__ void __launch_bounds__(64) eigen_kernel(const double2* __restrict__ G
   int centre = 0;
   for (int a = 0; a < s; ++a) {
     bool z = true;
-    for (int ax = 0; ax < d; ++ax) z = z && g.off[a][ax] == 0;
+    for (int ax = 0; ax < d; ++ax) z = z && soff[a][ax] == 0;
     if (z) centre = a;
   }
   double2 uc = cconj(Uf[centre + S * kmin]);
@@ -250,14 +288,14 @@ __global__ void __launch_bounds__(64) eigen_kernel(const double2* __restrict__ G
   __syncthreads();
   for (int a = lane; a < s; a += blockDim.x) {
     int slot = 0, m3 = 1;
-    for (int ax = 0; ax < d; ++ax) { slot += (g.off[a][ax] + 1) * m3; m3 *= 3; }
+    for (int ax = 0; ax < d; ++ax) { slot += (soff[a][ax] + 1) * m3; m3 *= 3; }
     alpha_pad[(long long)c * S + slot] = alpha[a];
     // C(a') = sum_s alpha(s) k_{|s - a'|}
     double2 sum = make_double2(0, 0);
     for (int b2 = 0; b2 < s; ++b2) {
       int t[3] = {0, 0, 0};
-      for (int ax = 0; ax < d; ++ax) t[ax] = abs(g.off[b2][ax] - g.off[a][ax]);
-      sum = cadd(sum, cmul(alpha[b2], ktab[ktab_index(t, n, d)]));
+      for (int ax = 0; ax < d; ++ax) t[ax] = abs(soff[b2][ax] - soff[a][ax]);
+      sum = cadd(sum, cmul(alpha[b2], ktab[ktab_index(t[0], t[1], t[2], n, d)]));
     }
     C_pad[(long long)c * S + slot] = sum;
   }
@@ -341,11 +379,11 @@ void compute_stencils(const double2* ktab, int n, int d, const ClassGeom* geo_de
   dim3 grid(nblk, nclass);
   LSP_LAUNCH("gram", 0, gram_kernel<false>, grid, dim3(256), 0, st, ktab, n, d, geo_dev, (const double2*)nullptr,
                      partial, nblk);
-  LSP_LAUNCH("gram_reduce", 0, gram_reduce_kernel, dim3(nclass), dim3(256), 0, st, partial, G, nblk, nclass);
+  LSP_LAUNCH("gram_reduce", 0, gram_reduce_kernel, dim3(nclass), dim3(768), 0, st, partial, G, nblk, nclass);
   LSP_LAUNCH("eigen", 0, eigen_kernel, dim3(nclass), dim3(64), 0, st, G, geo_dev, U1, (const double2*)nullptr, ktab, n,
                      d, 0, alpha_pad, C_pad, sigma_pad);
   LSP_LAUNCH("gram", 0, gram_kernel<true>, grid, dim3(256), 0, st, ktab, n, d, geo_dev, U1, partial, nblk);
-  LSP_LAUNCH("gram_reduce", 0, gram_reduce_kernel, dim3(nclass), dim3(256), 0, st, partial, G, nblk, nclass);
+  LSP_LAUNCH("gram_reduce", 0, gram_reduce_kernel, dim3(nclass), dim3(768), 0, st, partial, G, nblk, nclass);
   LSP_LAUNCH("eigen", 0, eigen_kernel, dim3(nclass), dim3(64), 0, st, G, geo_dev, (double2*)nullptr, U1, ktab, n, d, 1,
                      alpha_pad, C_pad, sigma_pad);
 }
