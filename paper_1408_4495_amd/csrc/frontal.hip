@@ -20,6 +20,8 @@
 // forward solve applies each panel's permutation when it reaches the panel.
 // The kept inverses turn every panel step of the triangular solves into a
 // small matrix-vector product, so no step has a sequential dependency chain.
+#include <climits>
+
 #include "lsp_common.h"
 #include "kernels.h"
 
@@ -80,91 +82,177 @@ __global__ void __launch_bounds__(256) assemble_front_kernel(cplx<T>* __restrict
 // inverses L11^{-1} (unit lower) and U11^{-1} of its triangular factors,
 // written to the front's inverse store: panel b keeps [Linv | Uinv], each
 // NB x NB column-major, zero outside the kb x kb block.
-// 1024 threads, one element each: thread t holds entry (r, c), r = t % 32,
-// c = t / 32, so each column is one half-wave; the pivot row and the
-// multipliers of each step go through LDS.
+//
+// One wave per front.  Elimination is row per lane (lanes 32..63 mirror
+// 0..31) and pivots by relabelling: a row keeps its lane and records the
+// step that chose it, so nothing moves.  Each step reduces a 32-bit key over
+// the candidate rows with DPP (the magnitude |re| + |im| as a float, its five
+// low mantissa bits replaced by 31 - row, so the largest wins and ties go to
+// the lowest row: the chosen pivot is within a factor 1 - 2^-18 of the
+// column maximum), reads the pivot row from a write-through LDS copy of the
+// rows, and updates every row with a multiplier that is zero for rows that
+// are already pivotal.  The two triangular inverses then come from one
+// substitution sweep: lanes 0..31 solve L x = e_c, lanes 32..63 solve
+// R y = e_c with R the row- and column-reversed U (lower triangular), both
+// reading their operand from LDS in the same instruction stream.
+
+// Largest key over lanes 0..31 (lane 31 ends with it): prefix maxima over
+// each 16-lane row by right shifts, then row 0's maximum broadcast into row 1.
+__device__ __forceinline__ int lane_max32(int k) {
+  k = max(k, __builtin_amdgcn_update_dpp(INT_MIN, k, 0x111, 0xf, 0xf, false));  // row_shr:1
+  k = max(k, __builtin_amdgcn_update_dpp(INT_MIN, k, 0x112, 0xf, 0xf, false));  // row_shr:2
+  k = max(k, __builtin_amdgcn_update_dpp(INT_MIN, k, 0x114, 0xf, 0xf, false));  // row_shr:4
+  k = max(k, __builtin_amdgcn_update_dpp(INT_MIN, k, 0x118, 0xf, 0xf, false));  // row_shr:8
+  k = max(k, __builtin_amdgcn_update_dpp(INT_MIN, k, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  return __builtin_amdgcn_readlane(k, 31);
+}
+
+// m[0]: rows by lane during elimination, then L by pivot step (unit
+// diagonal stored); m[1]: reversed U with the reciprocal pivots on its
+// diagonal.  One array, so a lane picks its half by offset (a pointer select
+// would be compiled into loads from both halves).
 template <typename T>
-__global__ void __launch_bounds__(1024) diag_lu_kernel(cplx<T>* __restrict__ Fbuf, cplx<T>* __restrict__ Dinv,
-                                                           const FrontDev* __restrict__ fr, int* __restrict__ piv,
-                                                           int* __restrict__ perm, double* __restrict__ pivstat,
-                                                           int first, int k0) {
-  static_assert(NB == 32, "thread layout assumes 32-wide panels");
-  __shared__ cplx<T> A[NB][NB + 1];
-  __shared__ cplx<T> rowU[NB], colL[NB];
-  __shared__ cplx<T> xrow[2][NB];
-  __shared__ int origs[NB];
-  __shared__ int s_pr;
-  __shared__ T s_best;
-  __shared__ cplx<T> s_inv;
+struct DiagLds {
+  cplx<T> m[2][NB][NB + 1];
+};
+
+// v[c] -= coef * opnd[c * STRIDE] for c = C0 .. NB-1, operands read from LDS
+// eight at a time with one chunk of lookahead (bounds the registers held by
+// loads in flight); STORE also writes each updated v[c] back to dst[c].
+template <typename T, int C0, int STRIDE, bool STORE>
+__device__ __forceinline__ void lds_axpy(cplx<T> (&v)[NB], const cplx<T> coef, const cplx<T>* opnd, cplx<T>* dst) {
+  constexpr int W = 8;
+  constexpr int nq = (NB - C0 + W - 1) / W;
+  if constexpr (nq > 0) {
+    cplx<T> buf[2][W];
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+      if (C0 + j < NB) buf[0][j] = opnd[(C0 + j) * STRIDE];
+#pragma unroll
+    for (int q = 0; q < nq; ++q) {
+      if (q + 1 < nq) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          const int c = C0 + (q + 1) * W + j;
+          if (c < NB) buf[(q + 1) & 1][j] = opnd[c * STRIDE];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        const int c = C0 + q * W + j;
+        if (c < NB) {
+          v[c] = cfms(v[c], coef, buf[q & 1][j]);
+          if constexpr (STORE) dst[c] = v[c];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+template <typename T, int J>
+__device__ __forceinline__ void diag_elim(cplx<T> (&row)[NB], int& rlog, cplx<T>& myinv, T& dmin, T& dmax,
+                                          DiagLds<T>& S, const int r, const int kb) {
+  if constexpr (J < NB) {
+    const int key = rlog < 0 ? ((__float_as_int((float)cabs1(row[J])) & 0x7fffffe0) | (NB - 1 - r)) : -1;
+    const int pl = NB - 1 - (lane_max32(key) & (NB - 1));
+    __syncthreads();  // rows written by the previous step are visible
+    const cplx<T> d = S.m[0][pl][J];
+    const T den = d.x * d.x + d.y * d.y;
+    const T rden = den > (T)0 ? (T)1 / den : (T)0;
+    const cplx<T> inv = mk<T>(d.x * rden, -d.y * rden);
+    if (J < kb) {
+      const T mag = cabs1(d);
+      dmin = fmin(dmin, mag);
+      dmax = fmax(dmax, mag);
+    }
+    const bool upd = rlog < 0 && r != pl;
+    if (r == pl) { rlog = J; myinv = inv; }
+    const cplx<T> l0 = cmul(row[J], inv);
+    const cplx<T> l = upd ? l0 : mk<T>(0, 0);
+    if (upd) row[J] = l0;
+    lds_axpy<T, J + 1, 1, true>(row, l, &S.m[0][pl][0], &S.m[0][r][0]);
+    diag_elim<T, J + 1>(row, rlog, myinv, dmin, dmax, S, r, kb);
+  }
+}
+
+// Column sweep of the substitution: x_k = acc_k M(k,k), then
+// acc_i -= M(i,k) x_k for i > k (independent updates, no dependent chain).
+template <typename T, int K>
+__device__ __forceinline__ void diag_subst(cplx<T> (&x)[NB], const cplx<T>* M) {
+  if constexpr (K < NB) {
+    x[K] = cmul(x[K], M[K * (NB + 1) + K]);
+    lds_axpy<T, K + 1, NB + 1, false>(x, x[K], M + K, nullptr);
+    diag_subst<T, K + 1>(x, M);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) diag_lu_kernel(cplx<T>* __restrict__ Fbuf, cplx<T>* __restrict__ Dinv,
+                                                     const FrontDev* __restrict__ fr, int* __restrict__ perm,
+                                                     double* __restrict__ pivstat, int first, int k0) {
+  static_assert(NB == 32, "lane layout assumes 32-wide panels");
+  __shared__ DiagLds<T> S;
   const FrontDev f = fr[first + blockIdx.x];
   if (f.p <= k0) return;
   const int kb = min(NB, f.p - k0);
   const int m = f.p + f.q;
   cplx<T>* F = Fbuf + f.f_off;
-  const int tid = threadIdx.x;
-  const int r = tid & 31, c = tid >> 5;
-  cplx<T> a = mk<T>(r == c ? 1 : 0, 0);
-  if (r < kb && c < kb) a = F[(k0 + r) + (long long)(k0 + c) * m];
-  if (tid < NB) origs[tid] = tid;
-  double worst = 1e300;
-  for (int j = 0; j < NB; ++j) {
-    if (c == j) {
-      T best = r >= j ? cabs1(a) : (T)-1;
-      int bi = r;
-      for (int off = 16; off > 0; off >>= 1) {
-        T ob = __shfl_xor(best, off, 32);
-        int oi = __shfl_xor(bi, off, 32);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (r == 0) { s_pr = bi; s_best = best; }
-    }
-    __syncthreads();
-    const int pr = s_pr;
-    const T colmax = s_best;
-    if (pr != j) {
-      if (r == j || r == pr) A[r][c] = a;
-      __syncthreads();
-      if (r == j) a = A[pr][c];
-      else if (r == pr) a = A[j][c];
-      if (tid == 0) { int t = origs[j]; origs[j] = origs[pr]; origs[pr] = t; }
-    }
-    if (tid == 0 && j < kb) piv[f.piv_off + k0 + j] = k0 + pr;
-    if (r == j) {
-      rowU[c] = a;
-      if (c == j) {
-        T dmag = cabs1(a);
-        s_inv = dmag > 0 ? cdiv(mk<T>(1, 0), a) : mk<T>(0, 0);
-        if (j < kb) s_best = (dmag > 0 && colmax > 0) ? (T)(dmag / colmax) : (T)0;
-      }
-    }
-    __syncthreads();
-    if (j < kb) worst = fmin(worst, (double)s_best);
-    if (c == j && r > j) { a = cmul(a, s_inv); colL[r] = a; }
-    __syncthreads();
-    if (c > j && r > j) a = cfms(a, colL[r], rowU[c]);
+  const int lane = threadIdx.x;
+  const int r = lane & (NB - 1);
+  cplx<T> row[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    row[c] = mk<T>(r == c ? 1 : 0, 0);
+    if (r < kb && c < kb) row[c] = F[(k0 + r) + (long long)(k0 + c) * m];
+    S.m[0][r][c] = row[c];
   }
-  A[r][c] = a;
-  if (r < kb && c < kb) F[(k0 + r) + (long long)(k0 + c) * m] = a;
+  int rlog = -1;
+  cplx<T> myinv = mk<T>(0, 0);
+  T dmin = (T)INFINITY, dmax = (T)0;
+  diag_elim<T, 0>(row, rlog, myinv, dmin, dmax, S, r, kb);
+  rlog &= NB - 1;  // every row is chosen exactly once, so this is already in range
   __syncthreads();
-  if (tid < kb) perm[f.piv_off + k0 + tid] = k0 + origs[tid];
-  if (tid == 0) pivstat[first + blockIdx.x] = fmin(pivstat[first + blockIdx.x], worst);
+  if (lane < NB) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      S.m[0][rlog][c] = row[c];
+      S.m[1][NB - 1 - rlog][NB - 1 - c] = row[c];
+    }
+    S.m[0][rlog][rlog] = mk<T>(1, 0);
+    S.m[1][NB - 1 - rlog][NB - 1 - rlog] = myinv;
+    if (rlog < kb) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < kb) F[(k0 + rlog) + (long long)(k0 + c) * m] = row[c];
+      perm[f.piv_off + k0 + rlog] = k0 + r;
+    }
+    if (lane == 0) {
+      const double ratio = dmax > (T)0 ? (double)(dmin / dmax) : 0.0;
+      pivstat[first + blockIdx.x] = fmin(pivstat[first + blockIdx.x], ratio);
+    }
+  }
+  __syncthreads();
+  // forward substitution M x = e_r with M = L (unit diagonal stored as 1)
+  // or the reversed U (reciprocal pivots stored on its diagonal)
+  cplx<T> x[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) x[i] = mk<T>(r == i ? 1 : 0, 0);
+  diag_subst<T, 0>(x, &S.m[lane / NB][0][0]);
+  __syncthreads();
+  // stage column r of each result at [r][i] (L^{-1}(i, r); reversed U^{-1})
+#pragma unroll
+  for (int i = 0; i < NB; ++i) S.m[lane / NB][r][i] = x[i];
+  __syncthreads();
   cplx<T>* Li = Dinv + f.dinv_off + (long long)(k0 / NB) * 2 * NB * NB;
-  cplx<T>* Ui = Li + NB * NB;
-  cplx<T> x = mk<T>(r == c ? 1 : 0, 0);
-  for (int j = 0; j < NB; ++j) {
-    if (r == j) xrow[j & 1][c] = x;
-    __syncthreads();
-    if (r > j) x = cfms(x, A[r][j], xrow[j & 1][c]);
+#pragma unroll 4
+  for (int e = lane; e < NB * NB; e += 64) {
+    const int a = e % NB, b = e / NB;  // entry (a, b) of L^{-1}, then of U^{-1}
+    const bool in = a < kb && b < kb;
+    Li[e] = in ? S.m[0][b][a] : mk<T>(0, 0);
+    Li[NB * NB + e] = in ? S.m[1][NB - 1 - b][NB - 1 - a] : mk<T>(0, 0);
   }
-  Li[r + NB * c] = (r < kb && c < kb) ? x : mk<T>(0, 0);
-  __syncthreads();
-  x = mk<T>(r == c ? 1 : 0, 0);
-  for (int j = NB - 1; j >= 0; --j) {
-    if (r == j) { x = cdiv(x, A[j][j]); xrow[j & 1][c] = x; }
-    __syncthreads();
-    if (r < j) x = cfms(x, A[r][j], xrow[j & 1][c]);
-  }
-  Ui[r + NB * c] = (r < kb && c < kb) ? x : mk<T>(0, 0);
 }
 
 // ---------------------------------------------------------------- panel products
@@ -536,8 +624,8 @@ void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
     LSP_LAUNCH("assemble_front", (int)sizeof(cplx<T>), assemble_front_kernel<T>, dim3(gx, cnt), dim3(256), 0, st, mf.F, mf.fronts, mf.idx, mf.cpos,
                        mf.Mval, first, plan.n, plan.d);
     for (int k0 = 0; k0 < maxp; k0 += NB) {
-LSP_LAUNCH("diag_lu", (int)sizeof(cplx<T>), diag_lu_kernel<T>, dim3(cnt), dim3(1024), 0, st, mf.F, mf.Dinv,
-                 mf.fronts, mf.piv, mf.perm, mf.pivstat, first, k0);
+      LSP_LAUNCH("diag_lu", (int)sizeof(cplx<T>), diag_lu_kernel<T>, dim3(cnt), dim3(64), 0, st, mf.F, mf.Dinv,
+                 mf.fronts, mf.perm, mf.pivstat, first, k0);
       int rem = maxm - k0 - 1;
       if (rem <= 0) continue;
       int tiles = (rem + 63) / 64;

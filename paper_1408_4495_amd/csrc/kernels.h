@@ -64,9 +64,8 @@ struct MfDev {
   const int* idx;
   const int* cpos;
   const double2* Mval;      // [N][3^d]
-  int* piv;
-  int* perm;
-  double* pivstat;          // per front: smallest pivot ratio
+  int* perm;                // per panel row: the front row it came from
+  double* pivstat;          // per front: smallest / largest pivot magnitude
 };
 
 template <typename T>

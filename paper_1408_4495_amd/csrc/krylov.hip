@@ -41,11 +41,22 @@ __global__ void __launch_bounds__(KB) dots_partial_kernel(const double2* __restr
 #pragma unroll
   for (int i = 0; i < kMaxVec; ++i) acc[i] = make_double2(0, 0);
   const double2* wr = w + (long long)r * N;
-  for (long long e = e0 + threadIdx.x; e < e1; e += KB) {
-    double2 we = wr[e];
+  // four elements per thread per pass, their loads issued together
+  for (long long eb = e0 + threadIdx.x; eb < e1; eb += 4 * KB) {
+    double2 we[4];
 #pragma unroll
-    for (int i = 0; i < kMaxVec; ++i)
-      if (i < nvec) acc[i] = cadd(acc[i], cmulc(V[((long long)i * nrhs + r) * N + e], we));
+    for (int u = 0; u < 4; ++u) we[u] = eb + u * KB < e1 ? wr[eb + u * KB] : make_double2(0, 0);
+#pragma unroll
+    for (int i = 0; i < kMaxVec; ++i) {
+      if (i < nvec) {
+        const double2* Vi = V + ((long long)i * nrhs + r) * N;
+        double2 ve[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ve[u] = eb + u * KB < e1 ? Vi[eb + u * KB] : make_double2(0, 0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[i] = cadd(acc[i], cmulc(ve[u], we[u]));
+      }
+    }
   }
   __shared__ double2 ws[KB / 64][kMaxVec];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -66,34 +77,46 @@ __global__ void __launch_bounds__(KB) dots_partial_kernel(const double2* __restr
 
 // h[rhs][i] = sum_blk partial; mode 0: H(i,k) = h, mode 1: H(i,k) += h,
 // mode 2: norm -> H(k+1,k) = sqrt(re h0), inv[r] = 1/that (0 if zero).
-__global__ void dots_final_kernel(const double2* __restrict__ partial, double2* __restrict__ h,
-                                  double2* __restrict__ H, double* __restrict__ scal, int nvec, int nblk, int k,
-                                  int restart, int mode, const int* __restrict__ active) {
+// 256 threads: thread (s, i) sums the partials of blocks s, s+8, ... of
+// vector i with all its loads in flight at once; the eight slice sums are
+// then combined in slice order, so the result depends only on nblk.
+constexpr int kFinSlices = 8;
+__global__ void __launch_bounds__(kFinSlices * kMaxVec) dots_final_kernel(
+    const double2* __restrict__ partial, double2* __restrict__ h, double2* __restrict__ H, double* __restrict__ scal,
+    int nvec, int nblk, int k, int restart, int mode, const int* __restrict__ active) {
   const int r = blockIdx.x;
   if (active && !active[r]) return;
-  for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
-    // eight interleaved partial sums (independent loads), combined in order
-    double2 acc8[8];
+  const int i = threadIdx.x % kMaxVec, sl = threadIdx.x / kMaxVec;
+  __shared__ double2 red[kFinSlices][kMaxVec];
+  double2 acc = make_double2(0, 0);
+  if (i < nvec) {
+    const double2* pr = partial + (long long)r * nblk * kMaxVec + i;
+    double2 v[8];
+    for (int b0 = sl; b0 < nblk; b0 += 8 * kFinSlices) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc8[u] = make_double2(0, 0);
-    for (int b0 = 0; b0 < nblk; b0 += 8) {
+      for (int u = 0; u < 8; ++u) {
+        const int b = b0 + u * kFinSlices;
+        v[u] = b < nblk ? pr[(long long)b * kMaxVec] : make_double2(0, 0);
+      }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (b0 + u < nblk) acc8[u] = cadd(acc8[u], partial[((long long)r * nblk + b0 + u) * kMaxVec + i]);
+      for (int u = 0; u < 8; ++u) acc = cadd(acc, v[u]);
     }
-    double2 s = acc8[0];
+  }
+  red[sl][i] = acc;
+  __syncthreads();
+  if (sl != 0 || i >= nvec) return;
+  double2 s = red[0][i];
 #pragma unroll
-    for (int u = 1; u < 8; ++u) s = cadd(s, acc8[u]);
-    h[(long long)r * kMaxVec + i] = s;
-    double2* Hr = H + (long long)r * (restart + 1) * restart;
-    if (mode == 0) Hr[i + (restart + 1) * k] = s;
-    else if (mode == 1) Hr[i + (restart + 1) * k] = cadd(Hr[i + (restart + 1) * k], s);
-    else {
-      double nrm = sqrt(fmax(s.x, 0.0));
-      if (k >= 0) Hr[(k + 1) + (restart + 1) * k] = make_double2(nrm, 0.0);
-      scal[r * kScal + S_NORM] = nrm;
-      scal[r * kScal + S_INV] = nrm > 0 ? 1.0 / nrm : 0.0;
-    }
+  for (int q = 1; q < kFinSlices; ++q) s = cadd(s, red[q][i]);
+  h[(long long)r * kMaxVec + i] = s;
+  double2* Hr = H + (long long)r * (restart + 1) * restart;
+  if (mode == 0) Hr[i + (restart + 1) * k] = s;
+  else if (mode == 1) Hr[i + (restart + 1) * k] = cadd(Hr[i + (restart + 1) * k], s);
+  else {
+    double nrm = sqrt(fmax(s.x, 0.0));
+    if (k >= 0) Hr[(k + 1) + (restart + 1) * k] = make_double2(nrm, 0.0);
+    scal[r * kScal + S_NORM] = nrm;
+    scal[r * kScal + S_INV] = nrm > 0 ? 1.0 / nrm : 0.0;
   }
 }
 
@@ -243,7 +266,7 @@ void k_dots(const double2* V, const double2* w, double2* partial, double2* h, do
             int k, int restart, int mode, long long N, int nrhs, const int* active, hipStream_t st) {
   int nblk = dot_blocks(N);
   LSP_LAUNCH("dots_partial", 0, dots_partial_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, V, w, partial, nvec, N, nrhs, active);
-  LSP_LAUNCH("dots_final", 0, dots_final_kernel, dim3(nrhs), dim3(64), 0, st, partial, h, H, scal, nvec, nblk, k, restart, mode,
+  LSP_LAUNCH("dots_final", 0, dots_final_kernel, dim3(nrhs), dim3(kFinSlices * kMaxVec), 0, st, partial, h, H, scal, nvec, nblk, k, restart, mode,
                      active);
 }
 
@@ -252,7 +275,7 @@ void k_norm(const double2* w, double2* partial, double2* h, double2* H, double* 
   // ||w||^2 = sum conj(w) w: the dot kernel with V = w and nrhs-strided layout
   int nblk = dot_blocks(N);
   LSP_LAUNCH("dots_partial", 0, dots_partial_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, w, w, partial, 1, N, nrhs, active);
-  LSP_LAUNCH("dots_final", 0, dots_final_kernel, dim3(nrhs), dim3(64), 0, st, partial, h, H, scal, 1, nblk, k, restart, 2,
+  LSP_LAUNCH("dots_final", 0, dots_final_kernel, dim3(nrhs), dim3(kFinSlices * kMaxVec), 0, st, partial, h, H, scal, 1, nblk, k, restart, 2,
                      active);
 }
 

@@ -86,7 +86,6 @@ struct ProblemPtrs {
   FrontDev* fronts;
   int* idx;
   int* cpos;
-  int* piv;
   int* perm;
   double* pivstat;
 };
@@ -119,7 +118,6 @@ size_t layout_problem(const lsp_plan* pl, int precision, void* base, ProblemPtrs
   q.fronts = cv.take<FrontDev>(P.fronts.size());
   q.idx = cv.take<int>(P.idx.size());
   q.cpos = cv.take<int>(P.cpos.size());
-  q.piv = cv.take<int>(P.sum_p);
   q.perm = cv.take<int>(P.sum_p);
   q.pivstat = cv.take<double>(P.fronts.size());
   if (out) *out = q;
@@ -311,12 +309,12 @@ void apply_precond(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2*
   hipStream_t st = pb->st;
   if (pb->precision == LSP_FP64) {
     launch_applyQ<double2>((double2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
-    MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+    MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.perm,
                      pb->d.pivstat};
     mf_solve<double>(mf, P, nrhs, (const double2*)s.zq, out, (double2*)s.vbuf, st);
   } else {
     launch_applyQ<float2>((float2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
-    MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+    MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.perm,
                     pb->d.pivstat};
     mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st);
     launch_widen(out, (const float2*)s.xs, (long long)nrhs * P.N, st);
@@ -327,12 +325,12 @@ void solve_M(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2* z, do
   const Plan& P = pb->plan->p;
   hipStream_t st = pb->st;
   if (pb->precision == LSP_FP64) {
-    MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+    MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.perm,
                      pb->d.pivstat};
     mf_solve<double>(mf, P, nrhs, z, x, (double2*)s.vbuf, st);
   } else {
     launch_narrow((float2*)s.zq, z, (long long)nrhs * P.N, st);
-    MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+    MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.perm,
                     pb->d.pivstat};
     mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st);
     launch_widen(x, (const float2*)s.xs, (long long)nrhs * P.N, st);
@@ -525,11 +523,11 @@ lsp_status lsp_factor(lsp_problem* pb) {
     const Plan& P = pb->plan->p;
     k_fill_double(pb->d.pivstat, 1e300, (long long)P.fronts.size(), pb->st);
     if (pb->precision == LSP_FP64) {
-      MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+      MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.perm,
                        pb->d.pivstat};
       mf_factor<double>(mf, P, pb->st);
     } else {
-      MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.piv, pb->d.perm,
+      MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.perm,
                       pb->d.pivstat};
       mf_factor<float>(mf, P, pb->st);
     }

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <cmath>
 #include <cstdint>
 #include <cstddef>
 #include <stdexcept>
@@ -50,13 +51,13 @@ template <typename C> __host__ __device__ inline C cmulc(C a, C b) {
 }
 template <typename C> __host__ __device__ inline C cconj(C a) { C r; r.x = a.x; r.y = -a.y; return r; }
 template <typename C, typename T> __host__ __device__ inline C cscale(C a, T s) { C r; r.x = a.x * s; r.y = a.y * s; return r; }
-// a - b*c
+// a - b*c as two fused multiply-adds per component
 template <typename C> __host__ __device__ inline C cfms(C a, C b, C c) {
-  C r; r.x = a.x - (b.x * c.x - b.y * c.y); r.y = a.y - (b.x * c.y + b.y * c.x); return r;
+  C r; r.x = fma(b.y, c.y, fma(-b.x, c.x, a.x)); r.y = fma(-b.y, c.x, fma(-b.x, c.y, a.y)); return r;
 }
-// a + b*c
+// a + b*c as two fused multiply-adds per component
 template <typename C> __host__ __device__ inline C cfma(C a, C b, C c) {
-  C r; r.x = a.x + (b.x * c.x - b.y * c.y); r.y = a.y + (b.x * c.y + b.y * c.x); return r;
+  C r; r.x = fma(-b.y, c.y, fma(b.x, c.x, a.x)); r.y = fma(b.y, c.x, fma(b.x, c.y, a.y)); return r;
 }
 template <typename C> __host__ __device__ inline C cdiv(C a, C b) {
   // Smith's algorithm
