@@ -402,20 +402,90 @@ __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ 
 // Right-hand sides are taken in groups of NR per workgroup (blockIdx.y), so
 // each factor entry is read once per group; a right-hand side's arithmetic
 // does not depend on the group it is in.  The front's working vectors live in
-// LDS when the level's largest front fits (vlds != 0), else in the per-front
+// LDS when the level's largest front fits (VL), else in the per-front
 // vector buffer in HBM; either way the per-front vector buffer holds them at
-// the end (y_I for the backward sweep, the update for the parent).  The next
-// panel's inverted diagonal block is loaded while the current panel's
-// off-diagonal update runs.
+// the end (y_I for the backward sweep, the update for the parent).
 //
+// Per panel the data-independent loads go out first and stay in flight: the
+// panel's off-diagonal block (L21 rows or U12 columns) for the first 256
+// rows or columns, and the next panel's inverted diagonal block and
+// permutation, which are kept in registers until they can be stored.  The
+// 32-wide triangular products use eight threads per row.
+
+// Runs use(i, load(i)) for i = 0 .. N-1 (N and i compile-time after
+// unrolling), loading W items ahead of their use: bounds the registers held
+// by LDS reads in flight while still hiding their latency.
+template <int N, int W, typename Load, typename Use>
+__device__ __forceinline__ void chunked(Load&& load, Use&& use) {
+  using V = decltype(load(0));
+  constexpr int nq = (N + W - 1) / W;
+  V buf[2][W];
+#pragma unroll
+  for (int j = 0; j < W; ++j)
+    if (j < N) buf[0][j] = load(j);
+#pragma unroll
+  for (int q = 0; q < nq; ++q) {
+    if (q + 1 < nq) {
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        const int i = (q + 1) * W + j;
+        if (i < N) buf[(q + 1) & 1][j] = load(i);
+      }
+    }
+    asm volatile("" ::: "memory");  // keeps IR passes from merging or hoisting loads across chunks
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int i = q * W + j;
+      if (i < N) use(i, buf[q & 1][j]);
+    }
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+
+// out[k] = sum_j D(i, j) in(k, j) for k < NR, i = tid / 8: eight threads per
+// row i each sum every eighth j (s = tid % 8, in j order, two interleaved
+// partial sums), and an xor butterfly combines the eight.  The order is the
+// same for every NR, so a right-hand side's result does not depend on the
+// group it is solved in.
+template <typename T, int NR>
+__device__ __forceinline__ void tri_apply(const cplx<T> (*D)[NB + 1], const cplx<T> (*in)[NB], const int tid,
+                                          cplx<T> (&out)[NR]) {
+  constexpr int G = 256 / NB;
+  static_assert(G == 8, "256 threads over 32 rows");
+  const int i = tid / G, s = tid % G;
+  cplx<T> dv[NB / G];
+#pragma unroll
+  for (int t = 0; t < NB / G; ++t) dv[t] = D[i][s + G * t];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    cplx<T> a0 = mk<T>(0, 0), a1 = mk<T>(0, 0);
+#pragma unroll
+    for (int t = 0; t < NB / G; ++t) {
+      if (t & 1) a1 = cfma(a1, dv[t], in[k][s + G * t]);
+      else a0 = cfma(a0, dv[t], in[k][s + G * t]);
+    }
+    cplx<T> a = cadd(a0, a1);
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+      a.x += __shfl_xor(a.x, off, 64);
+      a.y += __shfl_xor(a.y, off, 64);
+    }
+    out[k] = a;
+  }
+}
+
 // Forward sweep of one front: v = [z(I); 0] + children's updates; per panel:
 //   y_b = L11^{-1} (P_b v_b),  v(k1:m) -= L21 y_b.
-template <typename T, int NR>
+template <typename T, int NR, bool VL>
 __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
                                                   const FrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                   const int* __restrict__ cpos, const int* __restrict__ perm,
                                                   const cplx<T>* __restrict__ z, cplx<T>* __restrict__ vbuf, int first,
-                                                  int nrhs, long long N, long long vstride, int vlds) {
+                                                  int nrhs, long long N, long long vstride) {
+  static_assert(NR * NB <= 256, "one gather thread per panel entry");
   extern __shared__ unsigned char smem_raw[];
   __shared__ cplx<T> Li[2][NB][NB + 1];
   __shared__ cplx<T> tb[NR][NB];
@@ -427,13 +497,23 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
   const cplx<T>* F = Fbuf + f.f_off;
   const int* id = idx + f.idx_off;
   const int* cp = cpos + 2 * f.idx_off;
+  const int* pm = perm + f.piv_off;
   long long coff[2] = {-1, -1};
   if (f.child0 >= 0) coff[0] = fr[f.child0].idx_off;
   if (f.child1 >= 0) coff[1] = fr[f.child1].idx_off;
   cplx<T>* vg = vbuf + (long long)r0 * vstride + f.idx_off;   // HBM copy, stride vstride
-  cplx<T>* vp = vlds ? reinterpret_cast<cplx<T>*>(smem_raw) : vg;
-  const long long vs = vlds ? m : vstride;
+  // a typed LDS or global pointer (a run-time choice would make every access
+  // a flat one, with conservative waits)
+  cplx<T>* vp;
+  if constexpr (VL) vp = reinterpret_cast<cplx<T>*>(smem_raw);
+  else vp = vg;
+  const long long vs = VL ? m : vstride;
   const int tid = threadIdx.x;
+  const int gk = tid / NB, gj = tid % NB;  // gather slot of this thread (tid < NR NB)
+  // loads below use clamped in-range indices instead of branches (padded
+  // entries meet exact zeros, and padded rows are never stored), so the
+  // wait counts stay exact and the prefetches stay in flight
+  int pnext = pm[min(gj, f.p - 1)];
   for (int e = tid; e < m * nr; e += 256) {
     int r = e % m, k = e / m;
     long long rb = (long long)(r0 + k) * vstride;
@@ -452,39 +532,80 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
     const int kb = min(NB, f.p - k0);
     const int k1 = k0 + kb;
     const int cur = b & 1;
-    for (int e = tid; e < NR * NB; e += 256) {
-      int j = e % NB, k = e / NB;
-      tb[k][j] = (k < nr && j < kb) ? vp[k * vs + perm[f.piv_off + k0 + j]] : mk<T>(0, 0);
+    const bool more = k1 < f.p;
+    // gather P_b v_b (issued before the prefetches, so waiting for it does not wait for them)
+    const cplx<T> gv = vp[min(gk, nr - 1) * vs + pnext];
+    const cplx<T> g = tid < NR * NB && gk < nr && gj < kb ? gv : mk<T>(0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    // next panel's L11^{-1} (the last panel reloads its own: unused, but it
+    // keeps these loads unconditional so they stay in registers)
+    cplx<T> lin[NB * NB / 256];
+    {
+      const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(more ? b + 1 : b) * 2 * NB * NB;
+#pragma unroll
+      for (int u = 0; u < NB * NB / 256; ++u) lin[u] = Lg[tid + 256 * u];
+      pnext = pm[min(k1 + gj, f.p - 1)];
+    }
+    // the L21 row is prefetched when the registers allow (NR right-hand
+    // sides of at most 16 bytes in all); with more right-hand sides each
+    // entry carries NR times the arithmetic, and rows are loaded eight
+    // entries at a time after the product
+    constexpr bool PRE = sizeof(cplx<T>) * NR <= 16;
+    const int rfirst = k1 + tid;
+    cplx<T> l[PRE ? NB : 1];
+    if constexpr (PRE) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) l[j] = F[(long long)(k0 + min(j, kb - 1)) * m + (unsigned)min(rfirst, m - 1)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (tid < NR * NB) tb[gk][gj] = g;
+    // Li[cur ^ 1] was last read before the previous panel's final barrier
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+      const int e = tid + 256 * u;
+      Li[cur ^ 1][e % NB][e / NB] = lin[u];
     }
     __syncthreads();
-    for (int e = tid; e < NR * NB; e += 256) {
-      int i = e % NB, k = e / NB;
-      cplx<T> s = mk<T>(0, 0);
-      for (int j = 0; j <= i; ++j) s = cfma(s, Li[cur][i][j], tb[k][j]);
-      yb[k][i] = s;
-      if (k < nr && i < kb) vp[k * vs + k0 + i] = s;
+    {
+      cplx<T> y[NR];
+      tri_apply<T, NR>(Li[cur], tb, tid, y);
+      const int i = tid / 8;
+      if (tid % 8 == 0) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          yb[k][i] = y[k];
+          if (k < nr && i < kb) vp[k * vs + k0 + i] = y[k];
+        }
+      }
     }
     __syncthreads();
-    if (k1 < f.p) {
-      const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(b + 1) * 2 * NB * NB;
-      for (int e = tid; e < NB * NB; e += 256) Li[cur ^ 1][e % NB][e / NB] = Lg[e];
-    }
-    for (int r = k1 + tid; r < m; r += 256) {
+    auto update_row = [&](const int r, const cplx<T>* lr) {
       cplx<T> acc[NR];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) acc[k] = k < nr ? vp[k * vs + r] : mk<T>(0, 0);
-      // batches of 8 independent loads of the L21 row, then their updates
-      for (int j0 = 0; j0 < kb; j0 += 8) {
-        cplx<T> l[8];
+      for (int k = 0; k < NR; ++k) acc[k] = vp[min(k, nr - 1) * vs + r];
+      chunked<NB * NR, sizeof(T) == 8 ? 4 : 8>(
+          [&](int q) { return yb[q % NR][q / NR]; },
+          [&](int q, const cplx<T>& y) { acc[q % NR] = cfms(acc[q % NR], lr[q / NR], y); });
+#pragma unroll
+      for (int k = 0; k < NR; ++k)
+        if (k < nr) vp[k * vs + r] = acc[k];
+    };
+    if constexpr (PRE) {
+      if (rfirst < m) update_row(rfirst, l);
+    }
+    for (int r = PRE ? rfirst + 256 : rfirst; r < m; r += 256) {  // rows not prefetched
+      cplx<T> acc[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] = vp[min(k, nr - 1) * vs + r];
+#pragma unroll 1
+      for (int j0 = 0; j0 < NB; j0 += 8) {
+        cplx<T> l8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) l8[u] = F[(long long)(k0 + min(j0 + u, kb - 1)) * m + (unsigned)r];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          l[u] = j0 + u < kb ? F[r + (long long)(k0 + j0 + u) * m] : mk<T>(0, 0);
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (j0 + u < kb) {
-#pragma unroll
-            for (int k = 0; k < NR; ++k) acc[k] = cfms(acc[k], l[u], yb[k][j0 + u]);
-          }
+          for (int k = 0; k < NR; ++k) acc[k] = cfms(acc[k], l8[u], yb[k][j0 + u]);
       }
 #pragma unroll
       for (int k = 0; k < NR; ++k)
@@ -492,7 +613,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
     }
     __syncthreads();
   }
-  if (vlds)
+  if constexpr (VL)
     for (int e = tid; e < m * nr; e += 256) {
       int r = e % m, k = e / m;
       vg[(long long)k * vstride + r] = vp[k * vs + r];
@@ -501,12 +622,15 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
 
 // Backward sweep: x_B from the global solution, then per panel from the last:
 //   x_b = U11^{-1} (y_b - U12 x(k1:m)).  Writes x at the front's grid points.
-template <typename T, int NR>
+// Thread (j, grp) = (tid % NB, tid / NB) forms the U12 row j product over
+// the columns k1 + grp + 8t; the eight column groups are added in order.
+template <typename T, int NR, bool VL>
 __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
                                                   const FrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                   cplx<T>* __restrict__ x, cplx<T>* __restrict__ vbuf, int first,
-                                                  int nrhs, long long N, long long vstride, int vlds) {
+                                                  int nrhs, long long N, long long vstride) {
   constexpr int G = 256 / NB;  // column groups
+  constexpr int TU = sizeof(T) == 8 ? 16 : 32;  // U12 columns per thread held in flight
   extern __shared__ unsigned char smem_raw[];
   __shared__ cplx<T> Ui[2][NB][NB + 1];
   __shared__ cplx<T> part[G][NR][NB];
@@ -518,52 +642,61 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
   const cplx<T>* F = Fbuf + f.f_off;
   const int* id = idx + f.idx_off;
   cplx<T>* vg = vbuf + (long long)r0 * vstride + f.idx_off;
-  cplx<T>* vp = vlds ? reinterpret_cast<cplx<T>*>(smem_raw) : vg;
-  const long long vs = vlds ? m : vstride;
+  // a typed LDS or global pointer (a run-time choice would make every access
+  // a flat one, with conservative waits)
+  cplx<T>* vp;
+  if constexpr (VL) vp = reinterpret_cast<cplx<T>*>(smem_raw);
+  else vp = vg;
+  const long long vs = VL ? m : vstride;
   const int tid = threadIdx.x;
   for (int e = tid; e < m * nr; e += 256) {
     int r = e % m, k = e / m;
     if (r >= f.p) vp[k * vs + r] = x[(long long)(r0 + k) * N + id[r]];
-    else if (vlds) vp[k * vs + r] = vg[(long long)k * vstride + r];
+    else if (VL) vp[k * vs + r] = vg[(long long)k * vstride + r];
   }
   const int nblk = (f.p + NB - 1) / NB;
   {
     const cplx<T>* Ug = Dinv + f.dinv_off + (long long)(nblk - 1) * 2 * NB * NB + NB * NB;
     for (int e = tid; e < NB * NB; e += 256) Ui[(nblk - 1) & 1][e % NB][e / NB] = Ug[e];
   }
-  __syncthreads();
+  const int j = tid % NB, grp = tid / NB;
   for (int b = nblk - 1; b >= 0; --b) {
     const int k0 = b * NB;
     const int kb = min(NB, f.p - k0);
     const int k1 = k0 + kb;
     const int cur = b & 1;
-    if (b > 0) {
-      const cplx<T>* Ug = Dinv + f.dinv_off + (long long)(b - 1) * 2 * NB * NB + NB * NB;
-      for (int e = tid; e < NB * NB; e += 256) Ui[cur ^ 1][e % NB][e / NB] = Ug[e];
-    }
-    const int j = tid % NB, grp = tid / NB;
+    // next (lower) panel's U11^{-1}, four entries per thread (panel 0
+    // reloads its own); named scalars, since a small array here was left in
+    // scratch memory by the compiler
+    static_assert(NB * NB == 4 * 256, "four inverse entries per thread");
+    const cplx<T>* Ugn = Dinv + f.dinv_off + (long long)(b > 0 ? b - 1 : 0) * 2 * NB * NB + NB * NB;
+    const cplx<T> uin0 = Ugn[tid], uin1 = Ugn[tid + 256], uin2 = Ugn[tid + 512], uin3 = Ugn[tid + 768];
+    cplx<T> u[TU];
+#pragma unroll
+    for (int t = 0; t < TU; ++t) u[t] = F[(k0 + min(j, kb - 1)) + (long long)min(k1 + grp + G * t, m - 1) * m];
+    __syncthreads();  // x(k1:m) of the previous panel is in place; Ui[cur ^ 1] is free
+    Ui[cur ^ 1][tid % NB][tid / NB] = uin0;
+    Ui[cur ^ 1][tid % NB][tid / NB + 8] = uin1;
+    Ui[cur ^ 1][tid % NB][tid / NB + 16] = uin2;
+    Ui[cur ^ 1][tid % NB][tid / NB + 24] = uin3;
     cplx<T> acc[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
-    if (j < kb) {
-      // batches of 4 independent loads of U12 (columns c, c+G, ...), then updates
-      for (int c0 = k1 + grp; c0 < m; c0 += 4 * G) {
-        cplx<T> u[4];
+    auto product = [&](const int c0, const cplx<T>(&uc)[TU]) {
+      chunked<TU * NR, (sizeof(T) == 8 && NR >= 4) ? 4 : 8>(
+          [&](int q) {
+            const int c = c0 + G * (q / NR), k = q % NR;
+            const cplx<T> v = vp[min(k, nr - 1) * vs + min(c, m - 1)];
+            return c < m && k < nr ? v : mk<T>(0, 0);
+          },
+          [&](int q, const cplx<T>& xv) { acc[q % NR] = cfma(acc[q % NR], uc[q / NR], xv); });
+    };
+    if (k1 + grp < m) product(k1 + grp, u);
+    for (int c0 = k1 + grp + G * TU; c0 < m; c0 += G * TU) {  // more than 256 columns right of the panel
+      cplx<T> u2[TU];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int c = c0 + t * G;
-          u[t] = c < m ? F[(k0 + j) + (long long)c * m] : mk<T>(0, 0);
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int c = c0 + t * G;
-          if (c < m) {
-#pragma unroll
-            for (int k = 0; k < NR; ++k)
-              if (k < nr) acc[k] = cfma(acc[k], u[t], vp[k * vs + c]);
-          }
-        }
-      }
+      for (int t = 0; t < TU; ++t) u2[t] = F[(k0 + min(j, kb - 1)) + (long long)min(c0 + G * t, m - 1) * m];
+      product(c0, u2);
     }
 #pragma unroll
     for (int k = 0; k < NR; ++k) part[grp][k][j] = acc[k];
@@ -575,15 +708,21 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
       rb[k][jj] = (k < nr && jj < kb) ? csub(vp[k * vs + k0 + jj], s) : mk<T>(0, 0);
     }
     __syncthreads();
-    for (int e = tid; e < NR * NB; e += 256) {
-      int i = e % NB, k = e / NB;
-      if (k >= nr || i >= kb) continue;
-      cplx<T> s = mk<T>(0, 0);
-      for (int jj = i; jj < kb; ++jj) s = cfma(s, Ui[cur][i][jj], rb[k][jj]);
-      vp[k * vs + k0 + i] = s;
-      x[(long long)(r0 + k) * N + id[k0 + i]] = s;
+    {
+      cplx<T> xs[NR];
+      tri_apply<T, NR>(Ui[cur], rb, tid, xs);
+      const int i = tid / 8;
+      if (tid % 8 == 0 && i < kb) {
+        const int gi = id[k0 + i];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          if (k < nr) {
+            vp[k * vs + k0 + i] = xs[k];
+            x[(long long)(r0 + k) * N + gi] = xs[k];
+          }
+        }
+      }
     }
-    __syncthreads();
   }
 }
 
@@ -596,17 +735,23 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
     const int first = plan.level_ptr[l];
     const int cnt = plan.level_ptr[l + 1] - first;
     const size_t vb = (size_t)plan.level_maxpq[l] * NR * sizeof(cplx<T>);
-    const int vlds = vb <= kVecLds ? 1 : 0;
-    LSP_LAUNCH("fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NR>), dim3(cnt, groups), dim3(256), vlds ? vb : 0, st, mf.F,
-               mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N, vstride, vlds);
+    if (vb <= kVecLds)
+      LSP_LAUNCH("fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NR, true>), dim3(cnt, groups), dim3(256), vb, st, mf.F,
+                 mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N, vstride);
+    else
+      LSP_LAUNCH("fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NR, false>), dim3(cnt, groups), dim3(256), 0, st, mf.F,
+                 mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N, vstride);
   }
   for (int l = plan.nlevels - 1; l >= 0; --l) {
     const int first = plan.level_ptr[l];
     const int cnt = plan.level_ptr[l + 1] - first;
     const size_t vb = (size_t)plan.level_maxpq[l] * NR * sizeof(cplx<T>);
-    const int vlds = vb <= kVecLds ? 1 : 0;
-    LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR>), dim3(cnt, groups), dim3(256), vlds ? vb : 0, st, mf.F,
-               mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, vstride, vlds);
+    if (vb <= kVecLds)
+      LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR, true>), dim3(cnt, groups), dim3(256), vb, st, mf.F,
+                 mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, vstride);
+    else
+      LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR, false>), dim3(cnt, groups), dim3(256), 0, st, mf.F,
+                 mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, vstride);
   }
 }
 

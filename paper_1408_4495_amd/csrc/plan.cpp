@@ -156,6 +156,7 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
     const Node& nd = nodes[order[k]];
     FrontDev& f = P.fronts[k];
     f.p = (int)nd.I.size();
+    LSP_REQUIRE(f.p > 0, "empty separator in the dissection");
     f.q = (int)nd.B.size();
     f.child0 = nd.nchild > 0 ? newid[nd.child[0]] : -1;
     f.child1 = nd.nchild > 1 ? newid[nd.child[1]] : -1;
