@@ -255,9 +255,46 @@ __global__ void __launch_bounds__(64) diag_lu_kernel(cplx<T>* __restrict__ Fbuf,
   }
 }
 
+// Runs use(i, load(i)) for i = 0 .. N-1 (N and i compile-time after
+// unrolling), loading W items ahead of their use: bounds the registers held
+// by LDS reads in flight while still hiding their latency.
+template <int N, int W, typename Load, typename Use>
+__device__ __forceinline__ void chunked(Load&& load, Use&& use) {
+  using V = decltype(load(0));
+  constexpr int nq = (N + W - 1) / W;
+  V buf[2][W];
+#pragma unroll
+  for (int j = 0; j < W; ++j)
+    if (j < N) buf[0][j] = load(j);
+#pragma unroll
+  for (int q = 0; q < nq; ++q) {
+    if (q + 1 < nq) {
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        const int i = (q + 1) * W + j;
+        if (i < N) buf[(q + 1) & 1][j] = load(i);
+      }
+    }
+    asm volatile("" ::: "memory");  // keeps IR passes from merging or hoisting loads across chunks
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int i = q * W + j;
+      if (i < N) use(i, buf[q & 1][j]);
+    }
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+
 // ---------------------------------------------------------------- panel products
 // blockIdx.z == 0: U12(:, tile) = L11^{-1} P F12(:, tile), 64 columns per block.
 // blockIdx.z == 1: L21(tile, :) = F21(tile, :) U11^{-1}, 64 rows per block.
+// Every load is issued before the first LDS store (clamped in-range indices,
+// invalid entries zeroed after the load); each thread then forms eight
+// outputs with full 32-term sums (the inverses are exactly zero outside
+// their triangle and outside the kb x kb block).
 template <typename T>
 __global__ void __launch_bounds__(256) panel_trsm_kernel(cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
                                                          const FrontDev* __restrict__ fr, const int* __restrict__ perm,
@@ -274,40 +311,74 @@ __global__ void __launch_bounds__(256) panel_trsm_kernel(cplx<T>* __restrict__ F
   const int cnt = min(64, m - k1 - t0);
   cplx<T>* F = Fbuf + f.f_off;
   const cplx<T>* Li = Dinv + f.dinv_off + (long long)(k0 / NB) * 2 * NB * NB;
-  const cplx<T>* Dm = blockIdx.z == 0 ? Li : Li + NB * NB;
+  const bool upper = blockIdx.z == 0;
+  const cplx<T>* Dm = upper ? Li : Li + NB * NB;
   const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += 256) Di[e % NB][e / NB] = Dm[e];
-  if (blockIdx.z == 0) {
-    // Tt[c][j] = (P F12)(j, t0 + c)
-    for (int e = tid; e < 64 * NB; e += 256) {
-      int j = e % NB, c = e / NB;
-      cplx<T> v = mk<T>(0, 0);
-      if (j < kb && c < cnt) v = F[perm[f.piv_off + k0 + j] + (long long)(k1 + t0 + c) * m];
-      Tt[c][j] = v;
+  cplx<T> dv[4], tv[8];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) dv[u] = Dm[tid + 256 * u];
+  if (upper) {
+    // Tt[c][j] = (P F12)(j, t0 + c): j = tid % 32 is fixed per thread
+    const int j = tid % NB;
+    const int pj = perm[f.piv_off + k0 + min(j, kb - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = tid / NB + 8 * u;
+      const cplx<T> v = F[pj + (long long)(k1 + t0 + min(c, cnt - 1)) * m];
+      tv[u] = j < kb && c < cnt ? v : mk<T>(0, 0);
     }
-    __syncthreads();
-    for (int e = tid; e < 64 * NB; e += 256) {
-      int i = e % NB, c = e / NB;
-      if (i >= kb || c >= cnt) continue;
-      cplx<T> s = mk<T>(0, 0);
-      for (int j = 0; j <= i; ++j) s = cfma(s, Di[i][j], Tt[c][j]);
-      F[(k0 + i) + (long long)(k1 + t0 + c) * m] = s;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) Tt[tid / NB + 8 * u][j] = tv[u];
+  } else {
+    // Tt[r][i] = F21(t0 + r, i): r = tid % 64 is fixed per thread
+    const int r = tid % 64;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = tid / 64 + 4 * u;
+      const cplx<T> v = F[(k1 + t0 + min(r, cnt - 1)) + (long long)(k0 + min(i, kb - 1)) * m];
+      tv[u] = r < cnt && i < kb ? v : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) Tt[r][tid / 64 + 4 * u] = tv[u];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u;
+    Di[e % NB][e / NB] = dv[u];
+  }
+  __syncthreads();
+  cplx<T> acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = mk<T>(0, 0);
+  // runtime loops over the term index (unrolled by 4) keep the LDS reads in
+  // flight bounded; the eight accumulators are independent
+  if (upper) {
+    // U12(i, c) = sum_j Linv(i, j) Tt[c][j], c = tid / 32 + 8u
+    const int i = tid % NB;
+#pragma unroll 4
+    for (int j = 0; j < NB; ++j) {
+      const cplx<T> dij = Di[i][j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = cfma(acc[u], dij, Tt[tid / NB + 8 * u][j]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = tid / NB + 8 * u;
+      if (i < kb && c < cnt) F[(k0 + i) + (long long)(k1 + t0 + c) * m] = acc[u];
     }
   } else {
-    // Tt[r][i] = F21(t0 + r, i)
-    for (int e = tid; e < 64 * NB; e += 256) {
-      int r = e % 64, i = e / 64;
-      cplx<T> v = mk<T>(0, 0);
-      if (i < kb && r < cnt) v = F[(k1 + t0 + r) + (long long)(k0 + i) * m];
-      Tt[r][i] = v;
+    // L21(r, j) = sum_i Tt[r][i] Uinv(i, j), j = tid / 64 + 4u (uniform per wave)
+    const int r = tid % 64;
+#pragma unroll 4
+    for (int i = 0; i < NB; ++i) {
+      const cplx<T> tri = Tt[r][i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = cfma(acc[u], tri, Di[i][tid / 64 + 4 * u]);
     }
-    __syncthreads();
-    for (int e = tid; e < 64 * NB; e += 256) {
-      int r = e % 64, j = e / 64;
-      if (j >= kb || r >= cnt) continue;
-      cplx<T> s = mk<T>(0, 0);
-      for (int i = 0; i <= j; ++i) s = cfma(s, Tt[r][i], Di[i][j]);
-      F[(k1 + t0 + r) + (long long)(k0 + j) * m] = s;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = tid / 64 + 4 * u;
+      if (r < cnt && j < kb) F[(k1 + t0 + r) + (long long)(k0 + j) * m] = acc[u];
     }
   }
 }
@@ -349,17 +420,29 @@ __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ 
   cplx<T>* F = Fbuf + f.f_off;
   const int tid = threadIdx.x;
   const int kpad = (kb + 3) & ~3;
-  for (int e = tid; e < TM * kpad; e += 256) {
-    int r = e % TM, kk = e / TM;
-    cplx<T> v = mk<T>(0, 0);
-    if (row0 + r < rem && kk < kb) v = F[(k1 + row0 + r) + (long long)(k0 + kk) * m];
-    Ar[kk][r] = v.x; Ai[kk][r] = v.y;
+  // both operand tiles are loaded before the first LDS store (clamped
+  // in-range indices, zero outside the block), so the loads overlap
+  constexpr int LA = TM * NB / 256;
+  cplx<T> va[LA], vb[LA];
+#pragma unroll
+  for (int u = 0; u < LA; ++u) {
+    const int e = tid + 256 * u, r = e % TM, kk = e / TM;
+    const cplx<T> v = F[(k1 + min(row0 + r, rem - 1)) + (long long)(k0 + min(kk, kb - 1)) * m];
+    va[u] = row0 + r < rem && kk < kb ? v : mk<T>(0, 0);
   }
-  for (int e = tid; e < TM * kpad; e += 256) {
-    int kk = e % kpad, c = e / kpad;
-    cplx<T> v = mk<T>(0, 0);
-    if (col0 + c < rem && kk < kb) v = F[(k0 + kk) + (long long)(k1 + col0 + c) * m];
-    Br[kk][c] = v.x; Bi[kk][c] = v.y;
+#pragma unroll
+  for (int u = 0; u < LA; ++u) {
+    const int e = tid + 256 * u, kk = e % NB, c = e / NB;
+    const cplx<T> v = F[(k0 + min(kk, kb - 1)) + (long long)(k1 + min(col0 + c, rem - 1)) * m];
+    vb[u] = col0 + c < rem && kk < kb ? v : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int u = 0; u < LA; ++u) {
+    const int e = tid + 256 * u;
+    Ar[e / TM][e % TM] = va[u].x;
+    Ai[e / TM][e % TM] = va[u].y;
+    Br[e % NB][e / NB] = vb[u].x;
+    Bi[e % NB][e / NB] = vb[u].y;
   }
   __syncthreads();
   using acc_t = typename Mfma<T>::acc_t;
@@ -382,20 +465,32 @@ __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ 
         acci[i][j] = Mfma<T>::step(ai[i], br[j], acci[i][j]);
       }
   }
-  for (int i = 0; i < BW; ++i)
-    for (int j = 0; j < BW; ++j) {
-      int col = col0 + wc + 16 * j + li;
-      if (col >= rem) continue;
+  // C -= A B: per 16-row block i, all BW x 4 loads of C first, then the stores
+#pragma unroll
+  for (int i = 0; i < BW; ++i) {
+    cplx<T> cv[BW][4];
+#pragma unroll
+    for (int j = 0; j < BW; ++j)
+#pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int row = row0 + wr + 16 * i + Mfma<T>::row(lk, v);
-        if (row >= rem) continue;
-        long long e = (k1 + row) + (long long)(k1 + col) * m;
-        cplx<T> c = F[e];
-        c.x -= accr[i][j][v];
-        c.y -= acci[i][j][v];
-        F[e] = c;
+        const int col = min(col0 + wc + 16 * j + li, rem - 1);
+        const int row = min(row0 + wr + 16 * i + Mfma<T>::row(lk, v), rem - 1);
+        cv[j][v] = F[(k1 + row) + (long long)(k1 + col) * m];
       }
-    }
+#pragma unroll
+    for (int j = 0; j < BW; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = col0 + wc + 16 * j + li;
+        const int row = row0 + wr + 16 * i + Mfma<T>::row(lk, v);
+        if (col < rem && row < rem) {
+          cplx<T> c = cv[j][v];
+          c.x -= accr[i][j][v];
+          c.y -= acci[i][j][v];
+          F[(k1 + row) + (long long)(k1 + col) * m] = c;
+        }
+      }
+  }
 }
 
 // ---------------------------------------------------------------- solves
@@ -411,39 +506,6 @@ __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ 
 // rows or columns, and the next panel's inverted diagonal block and
 // permutation, which are kept in registers until they can be stored.  The
 // 32-wide triangular products use eight threads per row.
-
-// Runs use(i, load(i)) for i = 0 .. N-1 (N and i compile-time after
-// unrolling), loading W items ahead of their use: bounds the registers held
-// by LDS reads in flight while still hiding their latency.
-template <int N, int W, typename Load, typename Use>
-__device__ __forceinline__ void chunked(Load&& load, Use&& use) {
-  using V = decltype(load(0));
-  constexpr int nq = (N + W - 1) / W;
-  V buf[2][W];
-#pragma unroll
-  for (int j = 0; j < W; ++j)
-    if (j < N) buf[0][j] = load(j);
-#pragma unroll
-  for (int q = 0; q < nq; ++q) {
-    if (q + 1 < nq) {
-#pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const int i = (q + 1) * W + j;
-        if (i < N) buf[(q + 1) & 1][j] = load(i);
-      }
-    }
-    asm volatile("" ::: "memory");  // keeps IR passes from merging or hoisting loads across chunks
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
-      const int i = q * W + j;
-      if (i < N) use(i, buf[q & 1][j]);
-    }
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
-  }
-}
-
 
 // out[k] = sum_j D(i, j) in(k, j) for k < NR, i = tid / 8: eight threads per
 // row i each sum every eighth j (s = tid % 8, in j order, two interleaved
@@ -765,7 +827,7 @@ void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
     const int maxm = plan.level_maxpq[l];
     const int maxp = plan.level_maxp[l];
     long long mm = (long long)maxm * maxm;
-    int gx = (int)std::min<long long>((mm + 255) / 256, 64);
+    int gx = (int)std::min<long long>((mm + 255) / 256, 4096);  // one element per thread up to 1M-entry fronts
     LSP_LAUNCH("assemble_front", (int)sizeof(cplx<T>), assemble_front_kernel<T>, dim3(gx, cnt), dim3(256), 0, st, mf.F, mf.fronts, mf.idx, mf.cpos,
                        mf.Mval, first, plan.n, plan.d);
     for (int k0 = 0; k0 < maxp; k0 += NB) {
