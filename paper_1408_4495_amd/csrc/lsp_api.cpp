@@ -243,6 +243,7 @@ void build_class_geometry(lsp_plan* pl) {
     g.F = 1;
     for (int a = 0; a < d; ++a) g.F *= g.fsz[a];
     g.interior = interior ? 1 : 0;
+    LSP_REQUIRE(g.F < (1LL << 31), "far set too large for 32-bit column indices");
     pl->maxF = std::max(pl->maxF, g.F);
   }
   long long nb = (pl->maxF + 1023) / 1024;

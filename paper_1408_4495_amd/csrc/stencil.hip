@@ -66,7 +66,9 @@ __global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ k
   bool own[2] = {false, false};
   const int grp = npairs <= 128 ? tid / npairs : 0;
   double2 acc[2] = {make_double2(0, 0), make_double2(0, 0)};
-  for (int k = 0; k < per; ++k) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (k >= per) break;
     int p = npairs <= 128 ? tid % npairs : tid + k * blockDim.x;
     if (p < npairs && grp < G) {
       int a = 0, rem = p;
@@ -74,29 +76,62 @@ __global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ k
       pa[k] = a; pb[k] = a + rem; own[k] = true;
     }
   }
+  // the next chunk's table entries are loaded while the current one is
+  // reduced.  Thread tid stages entries e = tid + 256u (row a = e / CH,
+  // column jj = e % CH of the chunk, both fixed across chunks); the far-set
+  // coordinates of column base + jj are kept as mixed-radix digits and
+  // advanced by CH per chunk (no divisions in the loop).  Entries outside the
+  // block's range load table entry 0 and are zeroed.
+  constexpr int EPT = (S * CH + 255) / 256;
+  int dig[EPT][3];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    unsigned rem = (unsigned)(j0 + (tid + 256 * u) % CH);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      dig[u][ax] = ax < d ? (int)(rem % (unsigned)fsz[ax]) : 0;
+      if (ax < d) rem /= (unsigned)fsz[ax];
+    }
+  }
+  auto fetch = [&](long long base, double2 (&v)[EPT]) {
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
+      const int a = min(e / CH, s - 1);
+      const bool valid = e < s * CH && base + e % CH < j1;
+      int t[3] = {0, 0, 0};
+      bool near = true;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        if (ax < d) {
+          const int j = flo[ax] + dig[u][ax];
+          near = near && (j >= -1 && j <= 1);
+          t[ax] = abs(soff[a][ax] - j);
+        }
+      }
+      const double2 kv = ktab[valid ? ktab_index(t[0], t[1], t[2], n, d) : 0];
+      v[u] = valid && !(interior && near) ? kv : make_double2(0, 0);
+      // advance to the same column of the next chunk
+      dig[u][0] += CH;
+#pragma unroll
+      for (int ax = 0; ax < 2; ++ax) {
+        if (ax + 1 < d) {
+          while (dig[u][ax] >= fsz[ax]) { dig[u][ax] -= fsz[ax]; ++dig[u][ax + 1]; }
+        }
+      }
+    }
+  };
+  double2 vnext[EPT];
+  __syncthreads();  // soff staged
+  if (j0 < j1) fetch(j0, vnext);  // (an empty block range loads nothing)
   for (long long base = j0; base < j1; base += CH) {
     __syncthreads();
-    for (int e = tid; e < s * CH; e += blockDim.x) {
-      int a = e / CH, jj = e % CH;
-      long long jf = base + jj;
-      double2 v = make_double2(0, 0);
-      if (jf < j1) {
-        int j[3], t[3] = {0, 0, 0};
-        long long rem = jf;
-        bool near = true;
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          if (ax < d) {
-            j[ax] = flo[ax] + (int)(rem % fsz[ax]);
-            rem /= fsz[ax];
-            near = near && (j[ax] >= -1 && j[ax] <= 1);
-            t[ax] = abs(soff[a][ax] - j[ax]);
-          }
-        }
-        if (!(interior && near)) v = ktab[ktab_index(t[0], t[1], t[2], n, d)];
-      }
-      X[a][jj] = v;
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
+      if (e < s * CH) X[e / CH][e % CH] = vnext[u];
     }
+    if (base + CH < j1) fetch(base + CH, vnext);
     __syncthreads();
     if (PASS2) {
       for (int e = tid; e < s * CH; e += blockDim.x) {
@@ -107,8 +142,9 @@ __global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ k
       }
       __syncthreads();
     }
-    for (int k = 0; k < per; ++k) {
-      if (!own[k]) continue;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (k >= per || !own[k]) continue;
       double2 sum = acc[k];
       for (int jj = grp; jj < CH; jj += G) {
         double2 u = PASS2 ? Z[pa[k]][jj] : X[pa[k]][jj];
@@ -132,86 +168,139 @@ __global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ k
   }
   double2* out = partial + ((long long)blk * gridDim.y + c) * S * S;
   const bool writer = npairs <= 128 ? tid < npairs : true;
-  for (int k = 0; k < per; ++k) {
-    if (!own[k] || !writer) continue;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (k >= per || !own[k] || !writer) continue;
     out[pa[k] + S * pb[k]] = acc[k];
     out[pb[k] + S * pa[k]] = cconj(acc[k]);
   }
 }
 
-__global__ void gram_reduce_kernel(const double2* __restrict__ partial, double2* __restrict__ G, int nblk,
-                                   int nclass) {
-  const int c = blockIdx.x;
-  for (int e = threadIdx.x; e < S * S; e += blockDim.x) {
-    // eight interleaved partial sums (independent loads), combined in order
-    double2 acc8[8];
+// G_c = sum over blocks of the partial Gram matrices, for the s x s entries
+// of class c only (zero elsewhere).  Thread t works on entry t % s^2 and
+// block slice t / s^2 (every slices-th block, eight loads in flight); the
+// slice sums are added in slice order.
+__global__ void __launch_bounds__(768) gram_reduce_kernel(const double2* __restrict__ partial,
+                                                          double2* __restrict__ G, int nblk, int nclass,
+                                                          const ClassGeom* __restrict__ geo) {
+  __shared__ double2 red[768];
+  const int c = blockIdx.x, t = threadIdx.x;
+  const int s = geo[c].s;
+  const int ne = s * s;
+  const int slices = max(1, (int)blockDim.x / ne);
+  const int e = t % ne, sl = t / ne;
+  const int off = (e % s) + S * (e / s);
+  double2 acc = make_double2(0, 0);
+  if (sl < slices) {
+    for (int b0 = sl; b0 < nblk; b0 += 8 * slices) {
+      double2 v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc8[u] = make_double2(0, 0);
-    for (int b0 = 0; b0 < nblk; b0 += 8) {
+      for (int u = 0; u < 8; ++u) {
+        const int b = b0 + u * slices;
+        v[u] = b < nblk ? partial[((long long)b * nclass + c) * S * S + off] : make_double2(0, 0);
+      }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (b0 + u < nblk) acc8[u] = cadd(acc8[u], partial[((long long)(b0 + u) * nclass + c) * S * S + e]);
+      for (int u = 0; u < 8; ++u) acc = cadd(acc, v[u]);
     }
-    double2 sum = acc8[0];
-#pragma unroll
-    for (int u = 1; u < 8; ++u) sum = cadd(sum, acc8[u]);
-    G[(long long)c * S * S + e] = sum;
   }
+  red[t] = acc;
+  __syncthreads();
+  if (t < ne) {
+    double2 sum = red[t];
+    for (int q = 1; q < slices; ++q) sum = cadd(sum, red[q * ne + t]);
+    G[(long long)c * S * S + off] = sum;
+  }
+  for (int z = t; z < S * S; z += blockDim.x)
+    if (z % S >= s || z / S >= s) G[(long long)c * S * S + z] = make_double2(0, 0);
 }
 
-// Cyclic Jacobi on the s x s Hermitian matrix of class blockIdx.x, one wave.
-// A and U are column-major with leading dimension S.  Rotation of the pair
-// (p, q): with g = A(p,q) = |g| e^{i phi}, tau = (A(q,q) - A(p,p)) / (2|g|),
-// t = sign(tau) / (|tau| + sqrt(1 + tau^2)), c = 1/sqrt(1+t^2), s = t c,
-// V = [[c, s], [-s e^{-i phi}, c e^{-i phi}]]; A <- V^H A V, U <- U V.
-// A pair is skipped when |g| <= 1e-17 sqrt(A(p,p) A(q,q)) (relative criterion).
+// Parallel cyclic Jacobi on the s x s Hermitian matrix of class blockIdx.x,
+// one wave.  A and U are column-major with leading dimension S.  A sweep is
+// s' - 1 rounds (s' = s rounded up to even) of s'/2 disjoint pairs in the
+// round-robin order (position 0 fixed, the others shifted by the round; the
+// index s, when s is odd, is a dummy that pairs with nobody), all rotated
+// at once: their parameters come from A before the round, the column update
+// A V and U V touches disjoint column pairs, the row update V^H (A V)
+// disjoint row pairs.  Rotation of (p, q): with g = A(p,q) = |g| e^{i phi},
+// tau = (A(q,q) - A(p,p)) / (2|g|), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+// c = 1/sqrt(1+t^2), s = t c, V = [[c, s], [-s e^{-i phi}, c e^{-i phi}]].
+// A pair is skipped when |g| <= 1e-17 sqrt(A(p,p) A(q,q)) (relative
+// criterion); the sweeps stop when a whole sweep rotates nothing.
 __device__ void jacobi_eigen(double2* A, double2* U, int s, int lane) {
+  constexpr int NP = (S + 1) / 2;
   __shared__ int rotated;
+  __shared__ int rp[NP], rq[NP], ract[NP];
+  __shared__ double rcs[NP], rsn[NP];
+  __shared__ double2 rv10[NP], rv11[NP];
+  const int sp = s + (s & 1);
+  const int npair = sp / 2;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (lane == 0) rotated = 0;
     __syncthreads();
-    for (int p = 0; p < s - 1; ++p) {
-      for (int q = p + 1; q < s; ++q) {
-        double2 gpq = A[p + S * q];
-        double a = A[p + S * p].x, b = A[q + S * q].x;
-        double ag = sqrt(gpq.x * gpq.x + gpq.y * gpq.y);
-        bool skip = !(ag > 1e-17 * sqrt(fabs(a * b))) || ag == 0.0;
-        __syncthreads();
-        if (skip) continue;
-        double ex = gpq.x / ag, ey = gpq.y / ag;  // e^{i phi}
-        double tau = (b - a) / (2.0 * ag);
-        double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
-        double2 v10 = make_double2(-sn * ex, sn * ey);   // -s e^{-i phi}
-        double2 v11 = make_double2(cs * ex, -cs * ey);   //  c e^{-i phi}
-        // columns: A(:,p) <- c A(:,p) + v10 A(:,q);  A(:,q) <- s A(:,p) + v11 A(:,q)
-        for (int k = lane; k < s; k += blockDim.x) {
-          double2 xp = A[k + S * p], xq = A[k + S * q];
-          A[k + S * p] = cadd(cscale(xp, cs), cmul(v10, xq));
-          A[k + S * q] = cadd(cscale(xp, sn), cmul(v11, xq));
-          double2 up = U[k + S * p], uq = U[k + S * q];
-          U[k + S * p] = cadd(cscale(up, cs), cmul(v10, uq));
-          U[k + S * q] = cadd(cscale(up, sn), cmul(v11, uq));
+    for (int r = 0; r < sp - 1; ++r) {
+      if (lane < npair) {
+        auto who = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + r) % (sp - 1); };
+        int p = who(lane), q = who(sp - 1 - lane);
+        if (p > q) { const int t = p; p = q; q = t; }
+        int act = 0;
+        if (q < s) {
+          const double2 gpq = A[p + S * q];
+          const double a = A[p + S * p].x, b = A[q + S * q].x;
+          const double ag = sqrt(gpq.x * gpq.x + gpq.y * gpq.y);
+          if (ag > 1e-17 * sqrt(fabs(a * b)) && ag != 0.0) {
+            const double ex = gpq.x / ag, ey = gpq.y / ag;  // e^{i phi}
+            const double tau = (b - a) / (2.0 * ag);
+            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+            rcs[lane] = cs;
+            rsn[lane] = sn;
+            rv10[lane] = make_double2(-sn * ex, sn * ey);  // -s e^{-i phi}
+            rv11[lane] = make_double2(cs * ex, -cs * ey);  //  c e^{-i phi}
+            act = 1;
+            rotated = 1;
+          }
         }
-        __syncthreads();
-        // rows: A(p,:) <- c A(p,:) + conj(v10) A(q,:);  A(q,:) <- s A(p,:) + conj(v11) A(q,:)
-        for (int k = lane; k < s; k += blockDim.x) {
-          double2 xp = A[p + S * k], xq = A[q + S * k];
-          A[p + S * k] = cadd(cscale(xp, cs), cmul(cconj(v10), xq));
-          A[q + S * k] = cadd(cscale(xp, sn), cmul(cconj(v11), xq));
-        }
-        __syncthreads();
-        if (lane == 0) {
-          A[p + S * q] = make_double2(0, 0);
-          A[q + S * p] = make_double2(0, 0);
-          A[p + S * p].y = 0.0;
-          A[q + S * q].y = 0.0;
-          rotated = 1;
-        }
-        __syncthreads();
+        rp[lane] = p;
+        rq[lane] = q;
+        ract[lane] = act;
       }
+      __syncthreads();
+      // columns: A(:,p) <- c A(:,p) + v10 A(:,q);  A(:,q) <- s A(:,p) + v11 A(:,q); same for U
+      for (int it = lane; it < npair * s; it += blockDim.x) {
+        const int k = it / s, i = it % s;
+        if (!ract[k]) continue;
+        const int p = rp[k], q = rq[k];
+        const double cs = rcs[k], sn = rsn[k];
+        const double2 v10 = rv10[k], v11 = rv11[k];
+        const double2 xp = A[i + S * p], xq = A[i + S * q];
+        A[i + S * p] = cadd(cscale(xp, cs), cmul(v10, xq));
+        A[i + S * q] = cadd(cscale(xp, sn), cmul(v11, xq));
+        const double2 up = U[i + S * p], uq = U[i + S * q];
+        U[i + S * p] = cadd(cscale(up, cs), cmul(v10, uq));
+        U[i + S * q] = cadd(cscale(up, sn), cmul(v11, uq));
+      }
+      __syncthreads();
+      // rows: A(p,:) <- c A(p,:) + conj(v10) A(q,:);  A(q,:) <- s A(p,:) + conj(v11) A(q,:)
+      for (int it = lane; it < npair * s; it += blockDim.x) {
+        const int k = it / s, j = it % s;
+        if (!ract[k]) continue;
+        const int p = rp[k], q = rq[k];
+        const double cs = rcs[k], sn = rsn[k];
+        const double2 v10 = rv10[k], v11 = rv11[k];
+        const double2 xp = A[p + S * j], xq = A[q + S * j];
+        A[p + S * j] = cadd(cscale(xp, cs), cmul(cconj(v10), xq));
+        A[q + S * j] = cadd(cscale(xp, sn), cmul(cconj(v11), xq));
+      }
+      __syncthreads();
+      if (lane < npair && ract[lane]) {
+        const int p = rp[lane], q = rq[lane];
+        A[p + S * q] = make_double2(0, 0);
+        A[q + S * p] = make_double2(0, 0);
+        A[p + S * p].y = 0.0;
+        A[q + S * q].y = 0.0;
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (!rotated) break;
   }
 }
@@ -379,11 +468,11 @@ void compute_stencils(const double2* ktab, int n, int d, const ClassGeom* geo_de
   dim3 grid(nblk, nclass);
   LSP_LAUNCH("gram", 0, gram_kernel<false>, grid, dim3(256), 0, st, ktab, n, d, geo_dev, (const double2*)nullptr,
                      partial, nblk);
-  LSP_LAUNCH("gram_reduce", 0, gram_reduce_kernel, dim3(nclass), dim3(768), 0, st, partial, G, nblk, nclass);
+  LSP_LAUNCH("gram_reduce", 0, gram_reduce_kernel, dim3(nclass), dim3(768), 0, st, partial, G, nblk, nclass, geo_dev);
   LSP_LAUNCH("eigen", 0, eigen_kernel, dim3(nclass), dim3(64), 0, st, G, geo_dev, U1, (const double2*)nullptr, ktab, n,
                      d, 0, alpha_pad, C_pad, sigma_pad);
   LSP_LAUNCH("gram", 0, gram_kernel<true>, grid, dim3(256), 0, st, ktab, n, d, geo_dev, U1, partial, nblk);
-  LSP_LAUNCH("gram_reduce", 0, gram_reduce_kernel, dim3(nclass), dim3(768), 0, st, partial, G, nblk, nclass);
+  LSP_LAUNCH("gram_reduce", 0, gram_reduce_kernel, dim3(nclass), dim3(768), 0, st, partial, G, nblk, nclass, geo_dev);
   LSP_LAUNCH("eigen", 0, eigen_kernel, dim3(nclass), dim3(64), 0, st, G, geo_dev, (double2*)nullptr, U1, ktab, n, d, 1,
                      alpha_pad, C_pad, sigma_pad);
 }
