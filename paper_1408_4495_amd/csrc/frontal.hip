@@ -83,34 +83,34 @@ __global__ void __launch_bounds__(256) assemble_front_kernel(cplx<T>* __restrict
 // written to the front's inverse store: panel b keeps [Linv | Uinv], each
 // NB x NB column-major, zero outside the kb x kb block.
 //
-// One wave per front.  Elimination is row per lane (lanes 32..63 mirror
-// 0..31) and pivots by relabelling: a row keeps its lane and records the
-// step that chose it, so nothing moves.  Each step reduces a 32-bit key over
-// the candidate rows with DPP (the magnitude |re| + |im| as a float, its five
-// low mantissa bits replaced by 31 - row, so the largest wins and ties go to
-// the lowest row: the chosen pivot is within a factor 1 - 2^-18 of the
-// column maximum), reads the pivot row from a write-through LDS copy of the
-// rows, and updates every row with a multiplier that is zero for rows that
-// are already pivotal.  The two triangular inverses then come from one
-// substitution sweep: lanes 0..31 solve L x = e_c, lanes 32..63 solve
-// R y = e_c with R the row- and column-reversed U (lower triangular), both
-// reading their operand from LDS in the same instruction stream.
+// One wave per front.  Elimination is row per lane pair: lane r holds the
+// even columns of row r and lane 32 + r the odd ones, so each step updates
+// at most 16 columns per lane.  Pivoting is by relabelling: a row keeps its
+// lanes and records the step that chose it, so nothing moves.  Each step
+// reduces a 32-bit key over the candidate rows with DPP (the magnitude
+// |re| + |im| as a float, its five low mantissa bits replaced by 31 - row, so
+// the largest wins and ties go to the lowest row: the chosen pivot is within
+// a factor 1 - 2^-18 of the column maximum), reads the pivot row from a
+// write-through LDS copy of the rows, and updates every row with a
+// multiplier that is zero for rows that are already pivotal.  The two
+// triangular inverses then come from one substitution sweep: lanes 0..31
+// solve L x = e_c, lanes 32..63 solve R y = e_c with R the row- and
+// column-reversed U (lower triangular), both reading their operand from LDS
+// in the same instruction stream.  Only the inverses and the permutation are
+// stored: no later step reads the diagonal block of F itself.
 
-// Largest key over lanes 0..31 (lane 31 ends with it): prefix maxima over
-// each 16-lane row by right shifts, then row 0's maximum broadcast into row 1.
-__device__ __forceinline__ int lane_max32(int k) {
+// Largest key over the 64 lanes (lane 63 ends with it): prefix maxima over
+// each 16-lane row by right shifts, then row maxima broadcast forward.
+__device__ __forceinline__ int lane_max64(int k) {
   k = max(k, __builtin_amdgcn_update_dpp(INT_MIN, k, 0x111, 0xf, 0xf, false));  // row_shr:1
   k = max(k, __builtin_amdgcn_update_dpp(INT_MIN, k, 0x112, 0xf, 0xf, false));  // row_shr:2
   k = max(k, __builtin_amdgcn_update_dpp(INT_MIN, k, 0x114, 0xf, 0xf, false));  // row_shr:4
   k = max(k, __builtin_amdgcn_update_dpp(INT_MIN, k, 0x118, 0xf, 0xf, false));  // row_shr:8
   k = max(k, __builtin_amdgcn_update_dpp(INT_MIN, k, 0x142, 0xa, 0xf, false));  // row_bcast:15
-  return __builtin_amdgcn_readlane(k, 31);
+  k = max(k, __builtin_amdgcn_update_dpp(INT_MIN, k, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(k, 63);
 }
 
-// m[0]: rows by lane during elimination, then L by pivot step (unit
-// diagonal stored); m[1]: reversed U with the reciprocal pivots on its
-// diagonal.  One array, so a lane picks its half by offset (a pointer select
-// would be compiled into loads from both halves).
 template <typename T>
 struct DiagLds {
   cplx<T> m[2][NB][NB + 1];
@@ -151,12 +151,55 @@ __device__ __forceinline__ void lds_axpy(cplx<T> (&v)[NB], const cplx<T> coef, c
   }
 }
 
+// Elimination step J.  Lane (h, r) holds columns c = 2i + h of row r in
+// rowh[i]; column J is held by half J % 2 at index J / 2.
+// Half-row version for the elimination: v[i] -= coef_i * opnd[2i] for
+// i = I0 .. NB/2-1 (coef_I0 = first, the rest coef), each updated v[i]
+// written back to dst[2i]; eight operands at a time with one chunk of lookahead.
+template <typename T, int I0>
+__device__ __forceinline__ void lds_axpy_h(cplx<T> (&v)[NB / 2], const cplx<T> coef, const cplx<T> first,
+                                           const cplx<T>* opnd, cplx<T>* dst) {
+  constexpr int W = 8, NH = NB / 2;
+  constexpr int nq = (NH - I0 + W - 1) / W;
+  cplx<T> buf[2][W];
+#pragma unroll
+  for (int j = 0; j < W; ++j)
+    if (I0 + j < NH) buf[0][j] = opnd[2 * (I0 + j)];
+#pragma unroll
+  for (int q = 0; q < nq; ++q) {
+    if (q + 1 < nq) {
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        const int i = I0 + (q + 1) * W + j;
+        if (i < NH) buf[(q + 1) & 1][j] = opnd[2 * i];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int i = I0 + q * W + j;
+      if (i < NH) {
+        v[i] = cfms(v[i], i == I0 ? first : coef, buf[q & 1][j]);
+        dst[2 * i] = v[i];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 template <typename T, int J>
-__device__ __forceinline__ void diag_elim(cplx<T> (&row)[NB], int& rlog, cplx<T>& myinv, T& dmin, T& dmax,
-                                          DiagLds<T>& S, const int r, const int kb) {
+__device__ __forceinline__ void diag_elim(cplx<T> (&rowh)[NB / 2], int& rlog, cplx<T>& myinv, T& dmin, T& dmax,
+                                          DiagLds<T>& S, const int r, const int h, const int kb) {
   if constexpr (J < NB) {
-    const int key = rlog < 0 ? ((__float_as_int((float)cabs1(row[J])) & 0x7fffffe0) | (NB - 1 - r)) : -1;
-    const int pl = NB - 1 - (lane_max32(key) & (NB - 1));
+    constexpr int hJ = J & 1, iJ = J >> 1;
+    const cplx<T> own = rowh[iJ];
+    const int key = (h == hJ && rlog < 0) ? ((__float_as_int((float)cabs1(own)) & 0x7fffffe0) | (NB - 1 - r)) : -1;
+    const int pl = NB - 1 - (lane_max64(key) & (NB - 1));
+    // the row's column-J entry, from whichever half holds it
+    cplx<T> other;
+    other.x = __shfl_xor(own.x, 32, 64);
+    other.y = __shfl_xor(own.y, 32, 64);
+    const cplx<T> aJ = h == hJ ? own : other;
     __syncthreads();  // rows written by the previous step are visible
     const cplx<T> d = S.m[0][pl][J];
     const T den = d.x * d.x + d.y * d.y;
@@ -169,11 +212,17 @@ __device__ __forceinline__ void diag_elim(cplx<T> (&row)[NB], int& rlog, cplx<T>
     }
     const bool upd = rlog < 0 && r != pl;
     if (r == pl) { rlog = J; myinv = inv; }
-    const cplx<T> l0 = cmul(row[J], inv);
+    const cplx<T> l0 = cmul(aJ, inv);
     const cplx<T> l = upd ? l0 : mk<T>(0, 0);
-    if (upd) row[J] = l0;
-    lds_axpy<T, J + 1, 1, true>(row, l, &S.m[0][pl][0], &S.m[0][r][0]);
-    diag_elim<T, J + 1>(row, rlog, myinv, dmin, dmax, S, r, kb);
+    if (h == hJ && upd) rowh[iJ] = l0;
+    // columns 2i + h > J; for even J the first index is column J itself in
+    // half 0 (the multiplier just stored), which takes a zero coefficient
+    constexpr int i0 = (J + 1) / 2;
+    if constexpr (i0 < NB / 2) {
+      const cplx<T> l_first = ((J & 1) == 0 && h == 0) ? mk<T>(0, 0) : l;
+      lds_axpy_h<T, i0>(rowh, l, l_first, &S.m[0][pl][h], &S.m[0][r][h]);
+    }
+    diag_elim<T, J + 1>(rowh, rlog, myinv, dmin, dmax, S, r, h, kb);
   }
 }
 
@@ -200,34 +249,31 @@ __global__ void __launch_bounds__(64) diag_lu_kernel(cplx<T>* __restrict__ Fbuf,
   const int m = f.p + f.q;
   cplx<T>* F = Fbuf + f.f_off;
   const int lane = threadIdx.x;
-  const int r = lane & (NB - 1);
-  cplx<T> row[NB];
+  const int r = lane & (NB - 1), h = lane / NB;
+  cplx<T> rowh[NB / 2];
 #pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    row[c] = mk<T>(r == c ? 1 : 0, 0);
-    if (r < kb && c < kb) row[c] = F[(k0 + r) + (long long)(k0 + c) * m];
-    S.m[0][r][c] = row[c];
+  for (int i = 0; i < NB / 2; ++i) {
+    const int c = 2 * i + h;
+    const cplx<T> v = F[(k0 + min(r, kb - 1)) + (long long)(k0 + min(c, kb - 1)) * m];
+    rowh[i] = r < kb && c < kb ? v : mk<T>(r == c ? 1 : 0, 0);
+    S.m[0][r][c] = rowh[i];
   }
   int rlog = -1;
   cplx<T> myinv = mk<T>(0, 0);
   T dmin = (T)INFINITY, dmax = (T)0;
-  diag_elim<T, 0>(row, rlog, myinv, dmin, dmax, S, r, kb);
+  diag_elim<T, 0>(rowh, rlog, myinv, dmin, dmax, S, r, h, kb);
   rlog &= NB - 1;  // every row is chosen exactly once, so this is already in range
   __syncthreads();
-  if (lane < NB) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      S.m[0][rlog][c] = row[c];
-      S.m[1][NB - 1 - rlog][NB - 1 - c] = row[c];
-    }
+  for (int i = 0; i < NB / 2; ++i) {
+    const int c = 2 * i + h;
+    S.m[0][rlog][c] = rowh[i];
+    S.m[1][NB - 1 - rlog][NB - 1 - c] = rowh[i];
+  }
+  if (h == 0) {  // after the row writes above, in issue order
     S.m[0][rlog][rlog] = mk<T>(1, 0);
     S.m[1][NB - 1 - rlog][NB - 1 - rlog] = myinv;
-    if (rlog < kb) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c)
-        if (c < kb) F[(k0 + rlog) + (long long)(k0 + c) * m] = row[c];
-      perm[f.piv_off + k0 + rlog] = k0 + r;
-    }
+    if (rlog < kb) perm[f.piv_off + k0 + rlog] = k0 + r;
     if (lane == 0) {
       const double ratio = dmax > (T)0 ? (double)(dmin / dmax) : 0.0;
       pivstat[first + blockIdx.x] = fmin(pivstat[first + blockIdx.x], ratio);
