@@ -45,10 +45,8 @@ __global__ void __launch_bounds__(256) assemble_front_kernel(cplx<T>* __restrict
   cplx<T>* F = Fbuf + f.f_off;
   const int* id = idx + f.idx_off;
   const int* cp = cpos + 2 * f.idx_off;
-  const cplx<T>* Fc[2] = {nullptr, nullptr};
-  int mc[2] = {0, 0};
-  if (f.child0 >= 0) { FrontDev c = fr[f.child0]; Fc[0] = Fbuf + c.f_off; mc[0] = c.p + c.q; }
-  if (f.child1 >= 0) { FrontDev c = fr[f.child1]; Fc[1] = Fbuf + c.f_off; mc[1] = c.p + c.q; }
+  const cplx<T>* Fc[2] = {f.cfoff[0] >= 0 ? Fbuf + f.cfoff[0] : nullptr, f.cfoff[1] >= 0 ? Fbuf + f.cfoff[1] : nullptr};
+  const int mc[2] = {f.cm[0], f.cm[1]};
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < mm; e += (long long)gridDim.x * blockDim.x) {
     int r = (int)(e % m), c = (int)(e / m);
     double2 v = make_double2(0, 0);
@@ -606,9 +604,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
   const int* id = idx + f.idx_off;
   const int* cp = cpos + 2 * f.idx_off;
   const int* pm = perm + f.piv_off;
-  long long coff[2] = {-1, -1};
-  if (f.child0 >= 0) coff[0] = fr[f.child0].idx_off;
-  if (f.child1 >= 0) coff[1] = fr[f.child1].idx_off;
+  const long long coff[2] = {f.cidx[0], f.cidx[1]};
   cplx<T>* vg = vbuf + (long long)r0 * vstride + f.idx_off;   // HBM copy, stride vstride
   // a typed LDS or global pointer (a run-time choice would make every access
   // a flat one, with conservative waits)
@@ -621,22 +617,66 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
   // loads below use clamped in-range indices instead of branches (padded
   // entries meet exact zeros, and padded rows are never stored), so the
   // wait counts stay exact and the prefetches stay in flight
-  int pnext = pm[min(gj, f.p - 1)];
-  for (int e = tid; e < m * nr; e += 256) {
-    int r = e % m, k = e / m;
-    long long rb = (long long)(r0 + k) * vstride;
-    cplx<T> s = r < f.p ? z[(long long)(r0 + k) * N + id[r]] : mk<T>(0, 0);
-    for (int c = 0; c < 2; ++c) {
-      if (coff[c] < 0) continue;
-      int q = cp[2 * r + c];
-      if (q >= 0) s = cadd(s, vbuf[rb + coff[c] + q]);
+  // The L21 rows are prefetched when the registers allow (NR right-hand
+  // sides of at most 16 bytes in all), and double-buffered (the next
+  // panel's rows load during this panel) when they take at most 8 bytes;
+  // with more right-hand sides each entry carries NR times the arithmetic,
+  // and rows are loaded eight entries at a time after the product.
+  constexpr bool PRE = sizeof(cplx<T>) * NR <= 16;
+  constexpr bool DB = sizeof(cplx<T>) * NR <= 8;
+  constexpr int LN = PRE ? NB : 1;
+  auto load_l = [&](const int k0p, cplx<T>(&dst)[LN]) {
+    if constexpr (PRE) {
+      const int kbp = min(NB, f.p - k0p);
+      const unsigned rr = (unsigned)min(k0p + kbp + tid, m - 1);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) dst[j] = F[(long long)(k0p + min(j, kbp - 1)) * m + rr];
     }
-    vp[k * vs + r] = s;
-  }
+  };
+  cplx<T> lA[LN], lB[LN];
+  load_l(0, lA);  // panel 0's rows go out before the gather of v below
+  int pnext = pm[min(gj, f.p - 1)];
   const cplx<T>* Lg0 = Dinv + f.dinv_off;
-  for (int e = tid; e < NB * NB; e += 256) Li[0][e % NB][e / NB] = Lg0[e];
+  const cplx<T> li0 = Lg0[tid], li1 = Lg0[tid + 256], li2 = Lg0[tid + 512], li3 = Lg0[tid + 768];
+  // v = [z(I); 0] + children's updates: four entries per thread per pass,
+  // the index loads of all four, then their value loads, in flight together
+  for (int e0 = 0; e0 < m * nr; e0 += 1024) {
+    int gidx[4], q0[4], q1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = min(e0 + tid + 256 * u, m * nr - 1), r = e % m;
+      gidx[u] = id[min(r, f.p - 1)];
+      q0[u] = coff[0] >= 0 ? cp[2 * r] : -1;
+      q1[u] = coff[1] >= 0 ? cp[2 * r + 1] : -1;
+    }
+    cplx<T> sv[4], c0v[4], c1v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = min(e0 + tid + 256 * u, m * nr - 1), r = e % m, k = e / m;
+      const long long rb = (long long)(r0 + k) * vstride;
+      sv[u] = z[(long long)(r0 + k) * N + gidx[u]];
+      c0v[u] = vbuf[rb + (q0[u] >= 0 ? coff[0] + q0[u] : 0)];
+      c1v[u] = vbuf[rb + (q1[u] >= 0 ? coff[1] + q1[u] : 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + tid + 256 * u;
+      if (e < m * nr) {
+        const int r = e % m, k = e / m;
+        cplx<T> s = r < f.p ? sv[u] : mk<T>(0, 0);
+        if (q0[u] >= 0) s = cadd(s, c0v[u]);
+        if (q1[u] >= 0) s = cadd(s, c1v[u]);
+        vp[k * vs + r] = s;
+      }
+    }
+  }
+  Li[0][tid % NB][tid / NB] = li0;
+  Li[0][tid % NB][tid / NB + 8] = li1;
+  Li[0][tid % NB][tid / NB + 16] = li2;
+  Li[0][tid % NB][tid / NB + 24] = li3;
   __syncthreads();
-  for (int k0 = 0, b = 0; k0 < f.p; k0 += NB, ++b) {
+  auto panel = [&](const int b, cplx<T>(&lc)[LN], cplx<T>(&ln)[LN]) {
+    const int k0 = b * NB;
     const int kb = min(NB, f.p - k0);
     const int k1 = k0 + kb;
     const int cur = b & 1;
@@ -647,32 +687,22 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
     __builtin_amdgcn_sched_barrier(0);
     // next panel's L11^{-1} (the last panel reloads its own: unused, but it
     // keeps these loads unconditional so they stay in registers)
-    cplx<T> lin[NB * NB / 256];
-    {
-      const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(more ? b + 1 : b) * 2 * NB * NB;
-#pragma unroll
-      for (int u = 0; u < NB * NB / 256; ++u) lin[u] = Lg[tid + 256 * u];
-      pnext = pm[min(k1 + gj, f.p - 1)];
-    }
-    // the L21 row is prefetched when the registers allow (NR right-hand
-    // sides of at most 16 bytes in all); with more right-hand sides each
-    // entry carries NR times the arithmetic, and rows are loaded eight
-    // entries at a time after the product
-    constexpr bool PRE = sizeof(cplx<T>) * NR <= 16;
-    const int rfirst = k1 + tid;
-    cplx<T> l[PRE ? NB : 1];
-    if constexpr (PRE) {
-#pragma unroll
-      for (int j = 0; j < NB; ++j) l[j] = F[(long long)(k0 + min(j, kb - 1)) * m + (unsigned)min(rfirst, m - 1)];
+    // (named scalars: a small array here is left in scratch by the compiler)
+    const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(more ? b + 1 : b) * 2 * NB * NB;
+    const cplx<T> lin0 = Lg[tid], lin1 = Lg[tid + 256], lin2 = Lg[tid + 512], lin3 = Lg[tid + 768];
+    pnext = pm[min(k1 + gj, f.p - 1)];
+    if constexpr (DB) {
+      if (more) load_l(k1, ln);
+    } else {
+      if (b > 0) load_l(k0, lc);
     }
     __builtin_amdgcn_sched_barrier(0);
     if (tid < NR * NB) tb[gk][gj] = g;
     // Li[cur ^ 1] was last read before the previous panel's final barrier
-#pragma unroll
-    for (int u = 0; u < NB * NB / 256; ++u) {
-      const int e = tid + 256 * u;
-      Li[cur ^ 1][e % NB][e / NB] = lin[u];
-    }
+    Li[cur ^ 1][tid % NB][tid / NB] = lin0;
+    Li[cur ^ 1][tid % NB][tid / NB + 8] = lin1;
+    Li[cur ^ 1][tid % NB][tid / NB + 16] = lin2;
+    Li[cur ^ 1][tid % NB][tid / NB + 24] = lin3;
     __syncthreads();
     {
       cplx<T> y[NR];
@@ -687,19 +717,19 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
       }
     }
     __syncthreads();
-    auto update_row = [&](const int r, const cplx<T>* lr) {
-      cplx<T> acc[NR];
-#pragma unroll
-      for (int k = 0; k < NR; ++k) acc[k] = vp[min(k, nr - 1) * vs + r];
-      chunked<NB * NR, sizeof(T) == 8 ? 4 : 8>(
-          [&](int q) { return yb[q % NR][q / NR]; },
-          [&](int q, const cplx<T>& y) { acc[q % NR] = cfms(acc[q % NR], lr[q / NR], y); });
-#pragma unroll
-      for (int k = 0; k < NR; ++k)
-        if (k < nr) vp[k * vs + r] = acc[k];
-    };
+    const int rfirst = k1 + tid;
     if constexpr (PRE) {
-      if (rfirst < m) update_row(rfirst, l);
+      if (rfirst < m) {
+        cplx<T> acc[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] = vp[min(k, nr - 1) * vs + rfirst];
+        chunked<NB * NR, sizeof(T) == 8 ? 4 : 8>(
+            [&](int q) { return yb[q % NR][q / NR]; },
+            [&](int q, const cplx<T>& y) { acc[q % NR] = cfms(acc[q % NR], lc[q / NR], y); });
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+          if (k < nr) vp[k * vs + rfirst] = acc[k];
+      }
     }
     for (int r = PRE ? rfirst + 256 : rfirst; r < m; r += 256) {  // rows not prefetched
       cplx<T> acc[NR];
@@ -720,6 +750,15 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
         if (k < nr) vp[k * vs + r] = acc[k];
     }
     __syncthreads();
+  };
+  // panels in pairs, so the two row buffers alternate by name
+  const int nblk = (f.p + NB - 1) / NB;
+  for (int b = 0; b < nblk; b += 2) {
+    panel(b, lA, lB);
+    if (b + 1 < nblk) {
+      if constexpr (DB) panel(b + 1, lB, lA);
+      else panel(b + 1, lA, lA);
+    }
   }
   if constexpr (VL)
     for (int e = tid; e < m * nr; e += 256) {
@@ -757,18 +796,35 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
   else vp = vg;
   const long long vs = VL ? m : vstride;
   const int tid = threadIdx.x;
-  for (int e = tid; e < m * nr; e += 256) {
-    int r = e % m, k = e / m;
-    if (r >= f.p) vp[k * vs + r] = x[(long long)(r0 + k) * N + id[r]];
-    else if (VL) vp[k * vs + r] = vg[(long long)k * vstride + r];
-  }
   const int nblk = (f.p + NB - 1) / NB;
+  const cplx<T>* Ug0 = Dinv + f.dinv_off + (long long)(nblk - 1) * 2 * NB * NB + NB * NB;
+  const cplx<T> ui0 = Ug0[tid], ui1 = Ug0[tid + 256], ui2 = Ug0[tid + 512], ui3 = Ug0[tid + 768];
+  // v = [y(I) from the forward sweep; x(B) from the ancestors]
+  for (int e = tid; e < m * nr; e += 256) {
+    const int r = e % m, k = e / m;
+    if (r >= f.p) vp[k * vs + r] = x[(long long)(r0 + k) * N + id[r]];
+    else if constexpr (VL) vp[k * vs + r] = vg[(long long)k * vstride + r];
+  }
   {
-    const cplx<T>* Ug = Dinv + f.dinv_off + (long long)(nblk - 1) * 2 * NB * NB + NB * NB;
-    for (int e = tid; e < NB * NB; e += 256) Ui[(nblk - 1) & 1][e % NB][e / NB] = Ug[e];
+    const int cb = (nblk - 1) & 1;
+    Ui[cb][tid % NB][tid / NB] = ui0;
+    Ui[cb][tid % NB][tid / NB + 8] = ui1;
+    Ui[cb][tid % NB][tid / NB + 16] = ui2;
+    Ui[cb][tid % NB][tid / NB + 24] = ui3;
   }
   const int j = tid % NB, grp = tid / NB;
-  for (int b = nblk - 1; b >= 0; --b) {
+  // U12 block of a panel (first TU columns of this thread); double-buffered
+  // (the next panel's block loads during this one) when one right-hand side
+  // of at most 8 bytes leaves the registers for it
+  constexpr bool DB = sizeof(cplx<T>) * NR <= 8;
+  auto load_u = [&](const int bp, cplx<T>(&dst)[TU]) {
+    const int k0p = bp * NB, kbp = min(NB, f.p - k0p), k1p = k0p + kbp;
+#pragma unroll
+    for (int t = 0; t < TU; ++t) dst[t] = F[(k0p + min(j, kbp - 1)) + (long long)min(k1p + grp + G * t, m - 1) * m];
+  };
+  cplx<T> uA[TU], uB[TU];
+  if constexpr (DB) load_u(nblk - 1, uA);
+  auto panel = [&](const int b, cplx<T>(&u)[TU], cplx<T>(&un)[TU]) {
     const int k0 = b * NB;
     const int kb = min(NB, f.p - k0);
     const int k1 = k0 + kb;
@@ -779,9 +835,12 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
     static_assert(NB * NB == 4 * 256, "four inverse entries per thread");
     const cplx<T>* Ugn = Dinv + f.dinv_off + (long long)(b > 0 ? b - 1 : 0) * 2 * NB * NB + NB * NB;
     const cplx<T> uin0 = Ugn[tid], uin1 = Ugn[tid + 256], uin2 = Ugn[tid + 512], uin3 = Ugn[tid + 768];
-    cplx<T> u[TU];
-#pragma unroll
-    for (int t = 0; t < TU; ++t) u[t] = F[(k0 + min(j, kb - 1)) + (long long)min(k1 + grp + G * t, m - 1) * m];
+    const int gi = id[k0 + min(tid / 8, kb - 1)];  // grid index of row tid / 8, for writing x
+    if constexpr (DB) {
+      if (b > 0) load_u(b - 1, un);
+    } else {
+      load_u(b, u);
+    }
     __syncthreads();  // x(k1:m) of the previous panel is in place; Ui[cur ^ 1] is free
     Ui[cur ^ 1][tid % NB][tid / NB] = uin0;
     Ui[cur ^ 1][tid % NB][tid / NB + 8] = uin1;
@@ -821,7 +880,6 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
       tri_apply<T, NR>(Ui[cur], rb, tid, xs);
       const int i = tid / 8;
       if (tid % 8 == 0 && i < kb) {
-        const int gi = id[k0 + i];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
           if (k < nr) {
@@ -830,6 +888,14 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
           }
         }
       }
+    }
+  };
+  // panels in pairs from the last, so the two buffers alternate by name
+  for (int b = nblk - 1; b >= 0; b -= 2) {
+    panel(b, uA, uB);
+    if (b - 1 >= 0) {
+      if constexpr (DB) panel(b - 1, uB, uA);
+      else panel(b - 1, uA, uA);
     }
   }
 }

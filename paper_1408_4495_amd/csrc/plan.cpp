@@ -189,6 +189,15 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
       P.update_flops += 8.0 * (double)(m - k0 - kb) * (double)(m - k0 - kb) * kb;
     }
   }
+  for (FrontDev& f : P.fronts) {
+    const int kids[2] = {f.child0, f.child1};
+    for (int c = 0; c < 2; ++c) {
+      const bool has = kids[c] >= 0;
+      f.cidx[c] = has ? P.fronts[kids[c]].idx_off : -1;
+      f.cfoff[c] = has ? P.fronts[kids[c]].f_off : -1;
+      f.cm[c] = has ? P.fronts[kids[c]].p + P.fronts[kids[c]].q : 0;
+    }
+  }
   for (int l = 0; l < P.nlevels; ++l) P.level_ptr[l + 1] += P.level_ptr[l];
   // default trailing-update tiles by front order; an autotuner may replace them
   P.level_tile.assign(P.nlevels, 64);

@@ -20,6 +20,11 @@ struct FrontDev {
   long long piv_off;      // offset of its p pivot / permutation entries
   long long dinv_off;     // offset of its inverted diagonal panel blocks
   int level, pad;
+  // the children's idx_off, f_off and order (p + q), so kernels need no
+  // dependent load of the child's descriptor; -1 / 0 if absent
+  long long cidx[2];
+  long long cfoff[2];
+  int cm[2];
 };
 
 struct Plan {
