@@ -109,8 +109,12 @@ lsp_status lsp_options_default(lsp_options* opts);
 /* Host-side symbolic analysis (Section 2.2: nested dissection of the 3^d
  * stencil graph): recursive 1-wide separator planes, elimination tree,
  * front index lists and extend-add maps.  Integer work only; no device
- * memory is touched.  max_nrhs bounds the right-hand sides of one solve.
- * The plan is immutable once created and may be shared by problems. */
+ * memory is touched here.  max_nrhs bounds the right-hand sides of one solve.
+ * The plan is immutable once created and may be shared by problems (also
+ * from several threads).  The first lsp_setup on a device uploads the plan's
+ * constant arrays (front descriptors, index lists, extend-add maps, class
+ * geometry, FFT twiddles) to that device once; the plan owns that memory and
+ * lsp_plan_destroy frees it, so destroy a plan only after its problems. */
 lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts,
                            lsp_plan** plan);
 void lsp_plan_destroy(lsp_plan* plan);
@@ -128,7 +132,7 @@ lsp_status lsp_plan_get_tiles(const lsp_plan* plan, int* tiles, int cap);
 lsp_status lsp_plan_set_tiles(lsp_plan* plan, const int* tiles, int n);
 
 /* Device bytes the caller must provide: *problem_bytes for lsp_setup (kernel
- * table, spectrum, stencils, matrix M, frontal factors, plan index arrays),
+ * table, spectrum, stencils, matrix M, frontal factors),
  * *solve_bytes for lsp_solve with nrhs right-hand sides (Krylov basis,
  * FFT work arrays, solve buffers).  precision selects the factor type. */
 lsp_status lsp_plan_bytes(const lsp_plan* plan, int precision, int nrhs,
@@ -144,7 +148,8 @@ lsp_status lsp_plan_bytes(const lsp_plan* plan, int precision, int nrhs,
  * ws_dev / ws_bytes: device workspace of at least problem_bytes; it must
  * outlive the problem.  stream: a hipStream_t (NULL = default stream).
  * precision comes from the plan's options.  Errors: LSP_ERR_ARG (w <= 0 or
- * not finite, null pointers, small workspace), LSP_ERR_HIP. */
+ * not finite, null pointers, small workspace), LSP_ERR_OOM (the plan's
+ * first upload to this device), LSP_ERR_HIP.  Only enqueues device work. */
 lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev,
                      void* ws_dev, size_t ws_bytes, void* stream,
                      lsp_problem** problem);
@@ -153,8 +158,9 @@ void lsp_problem_destroy(lsp_problem* problem);
 /* Numeric multifrontal LU of M (Section 2.2, nested dissection and the
  * multifrontal method), level by level from the leaves, with partial
  * pivoting inside each front's fully-summed block.  Synchronises the
- * stream to read the pivot-health flag.  Errors: LSP_ERR_SINGULAR (a pivot
- * of modulus <= 64 eps times the block's largest entry), LSP_ERR_HIP. */
+ * stream to read the pivot-health flag.  Errors: LSP_ERR_SINGULAR (in some
+ * 32-wide panel the smallest pivot modulus |re| + |im| is at most 64 eps
+ * times the largest, eps of the factor precision), LSP_ERR_HIP. */
 lsp_status lsp_factor(lsp_problem* problem);
 
 /* Restarted right-preconditioned GMRES (Section 3.3), one independent

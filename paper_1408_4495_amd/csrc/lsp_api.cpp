@@ -15,10 +15,26 @@
 
 #include "kernels.h"
 #include "krylov.h"
+#include <map>
+#include <mutex>
+
 #include "lsp_common.h"
 #include "plan.h"
 
 using namespace lsp;
+
+// Device copy of a plan's constant arrays (front descriptors, index lists,
+// extend-add maps, class geometry, FFT twiddles), one per device the plan is
+// used on: uploaded once, at the first lsp_setup on that device.
+struct PlanDev {
+  void* block = nullptr;
+  FrontDev* fronts = nullptr;
+  int* idx = nullptr;
+  int* cpos = nullptr;
+  ClassGeom* geo = nullptr;
+  double2* tw64 = nullptr;
+  float2* tw32 = nullptr;
+};
 
 struct lsp_plan {
   Plan p;
@@ -26,6 +42,16 @@ struct lsp_plan {
   int nclass = 0;
   long long maxF = 0;
   int gram_blocks = 1;
+  mutable std::mutex dev_mu;
+  mutable std::map<int, PlanDev> dev;
+  ~lsp_plan() {
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return;
+    for (auto& kv : dev) {
+      if (hipSetDevice(kv.first) == hipSuccess) (void)hipFree(kv.second.block);
+    }
+    (void)hipSetDevice(cur);
+  }
 };
 
 namespace {
@@ -100,11 +126,8 @@ size_t layout_problem(const lsp_plan* pl, int precision, void* base, ProblemPtrs
   q.ktab = cv.take<double2>(n1d);
   q.khat64 = cv.take<double2>(hd);
   q.khat32 = cv.take<float2>(hd);
-  q.tw64 = cv.take<double2>(P.L);
-  q.tw32 = cv.take<float2>(P.L);
   q.w2m = cv.take<double>(P.N);
   q.Mval = cv.take<double2>((size_t)P.N * (P.d == 2 ? 9 : 27));
-  q.geo = cv.take<ClassGeom>(pl->nclass);
   q.alpha_pad = cv.take<double2>((size_t)pl->nclass * S);
   q.C_pad = cv.take<double2>((size_t)pl->nclass * S);
   q.sigma_pad = cv.take<double>((size_t)pl->nclass * S);
@@ -115,13 +138,55 @@ size_t layout_problem(const lsp_plan* pl, int precision, void* base, ProblemPtrs
   size_t esz = precision == LSP_MIXED ? sizeof(float2) : sizeof(double2);
   q.F = cv.take<char>((size_t)P.front_elems * esz);
   q.Dinv = cv.take<char>((size_t)P.dinv_elems * esz);
-  q.fronts = cv.take<FrontDev>(P.fronts.size());
-  q.idx = cv.take<int>(P.idx.size());
-  q.cpos = cv.take<int>(P.cpos.size());
   q.perm = cv.take<int>(P.sum_p);
   q.pivstat = cv.take<double>(P.fronts.size());
   if (out) *out = q;
   return cv.off + 256;
+}
+
+// The plan's device copy on `device` (current), created on first use.
+const PlanDev& plan_device(const lsp_plan* pl, int device) {
+  std::lock_guard<std::mutex> lock(pl->dev_mu);
+  auto it = pl->dev.find(device);
+  if (it != pl->dev.end()) return it->second;
+  const Plan& P = pl->p;
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t bf = up(P.fronts.size() * sizeof(FrontDev)), bi = up(P.idx.size() * sizeof(int)),
+               bc = up(P.cpos.size() * sizeof(int)), bg = up(pl->geo.size() * sizeof(ClassGeom)),
+               bt = up(P.L * sizeof(double2)), bt32 = up(P.L * sizeof(float2));
+  PlanDev d;
+  if (hipMalloc(&d.block, bf + bi + bc + bg + bt + bt32) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(LSP_ERR_OOM, "device allocation of the plan arrays failed");
+  }
+  char* b = (char*)d.block;
+  d.fronts = (FrontDev*)b; b += bf;
+  d.idx = (int*)b; b += bi;
+  d.cpos = (int*)b; b += bc;
+  d.geo = (ClassGeom*)b; b += bg;
+  d.tw64 = (double2*)b; b += bt;
+  d.tw32 = (float2*)b;
+  // twiddles exp(-2 pi i k / L) from long double
+  std::vector<double2> tw64(P.L);
+  std::vector<float2> tw32(P.L);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int k = 0; k < P.L; ++k) {
+    long double a = 2.0L * pi * (long double)k / (long double)P.L;
+    tw64[k] = make_double2((double)cosl(a), (double)-sinl(a));
+    tw32[k] = make_float2((float)cosl(a), (float)-sinl(a));
+  }
+  try {
+    LSP_HIP(hipMemcpy(d.fronts, P.fronts.data(), P.fronts.size() * sizeof(FrontDev), hipMemcpyHostToDevice));
+    LSP_HIP(hipMemcpy(d.idx, P.idx.data(), P.idx.size() * sizeof(int), hipMemcpyHostToDevice));
+    LSP_HIP(hipMemcpy(d.cpos, P.cpos.data(), P.cpos.size() * sizeof(int), hipMemcpyHostToDevice));
+    LSP_HIP(hipMemcpy(d.geo, pl->geo.data(), pl->geo.size() * sizeof(ClassGeom), hipMemcpyHostToDevice));
+    LSP_HIP(hipMemcpy(d.tw64, tw64.data(), P.L * sizeof(double2), hipMemcpyHostToDevice));
+    LSP_HIP(hipMemcpy(d.tw32, tw32.data(), P.L * sizeof(float2), hipMemcpyHostToDevice));
+  } catch (...) {
+    (void)hipFree(d.block);
+    throw;
+  }
+  return pl->dev.emplace(device, d).first->second;
 }
 
 struct SolvePtrs {
@@ -478,23 +543,14 @@ lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, vo
     layout_problem(plan, prec, base, &pb->d);
     hipStream_t st = pb->st;
 
-    // plan arrays and class geometry
-    LSP_HIP(hipMemcpyAsync(pb->d.fronts, P.fronts.data(), P.fronts.size() * sizeof(FrontDev), hipMemcpyHostToDevice, st));
-    LSP_HIP(hipMemcpyAsync(pb->d.idx, P.idx.data(), P.idx.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    LSP_HIP(hipMemcpyAsync(pb->d.cpos, P.cpos.data(), P.cpos.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    LSP_HIP(hipMemcpyAsync(pb->d.geo, plan->geo.data(), plan->geo.size() * sizeof(ClassGeom), hipMemcpyHostToDevice,
-                           st));
-    // twiddles exp(-2 pi i k / L) from long double
-    std::vector<double2> tw64(P.L);
-    std::vector<float2> tw32(P.L);
-    const long double pi = 3.141592653589793238462643383279502884L;
-    for (int k = 0; k < P.L; ++k) {
-      long double a = 2.0L * pi * (long double)k / (long double)P.L;
-      tw64[k] = make_double2((double)cosl(a), (double)-sinl(a));
-      tw32[k] = make_float2((float)cosl(a), (float)-sinl(a));
-    }
-    LSP_HIP(hipMemcpyAsync(pb->d.tw64, tw64.data(), P.L * sizeof(double2), hipMemcpyHostToDevice, st));
-    LSP_HIP(hipMemcpyAsync(pb->d.tw32, tw32.data(), P.L * sizeof(float2), hipMemcpyHostToDevice, st));
+    // the plan's constant arrays (uploaded once per device)
+    const PlanDev& pd = plan_device(plan, pb->device);
+    pb->d.fronts = pd.fronts;
+    pb->d.idx = pd.idx;
+    pb->d.cpos = pd.cpos;
+    pb->d.geo = pd.geo;
+    pb->d.tw64 = pd.tw64;
+    pb->d.tw32 = pd.tw32;
     pb->fp64 = make_fft_plan<double>(P, pb->d.tw64, pb->d.khat64);
     pb->fp32 = make_fft_plan<float>(P, pb->d.tw32, pb->d.khat32);
 
@@ -509,8 +565,6 @@ lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, vo
     compute_stencils(pb->d.ktab, P.n, P.d, pb->d.geo, plan->nclass, plan->maxF, pb->d.partial, plan->gram_blocks,
                      pb->d.G, pb->d.U1, pb->d.alpha_pad, pb->d.C_pad, pb->d.sigma_pad, st);
     launch_assemble(pb->d.Mval, pb->d.alpha_pad, pb->d.C_pad, pb->d.w2m, P.n, P.d, P.N, st);
-    // the host vectors above must stay alive until the copies are done
-    LSP_HIP(hipStreamSynchronize(st));
     *out = pb.release();
     return LSP_OK;
   });
@@ -538,7 +592,8 @@ lsp_status lsp_factor(lsp_problem* pb) {
     double mn = 1e300;
     for (double v : ps) mn = std::min(mn, v);
     pb->min_pivot_ratio = mn;
-    if (!(mn > 0.0)) {
+    const double eps = pb->precision == LSP_FP64 ? 2.220446049250313e-16 : 1.1920928955078125e-07;
+    if (!(mn > 64.0 * eps)) {
       pb->factored = false;
       throw Error(LSP_ERR_SINGULAR, "zero pivot in the multifrontal factorisation");
     }
