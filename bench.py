@@ -95,10 +95,42 @@ def run_path(lsp, torch, w, m_dev, u_dev, prec, steps, warmup):
     }
 
 
+# HBM traffic per launch measured with hardware counters (FETCH_SIZE and
+# WRITE_SIZE, scaled by a device-to-device copy of known size); a record is
+# used only while the source file of the kernel is unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_2d_n256.md")
+CSRC = os.path.join(ROOT, "paper_1408_4495_amd", "csrc")
+
+
+def source_sha256(fname):
+    import hashlib
+    with open(os.path.join(CSRC, fname), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def recorded_traffic(name):
+    """(bytes per launch, record) for kernel `name` from the counter summary,
+    or (None, reason) when absent or taken on a different kernel source."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None, "no counter summary"
+    marker = "<!-- traffic-json:"
+    if marker not in text:
+        return None, "no counter summary"
+    rec = json.loads(text.split(marker, 1)[1].split("-->", 1)[0])
+    k = rec["kernels"].get(name)
+    if k is None:
+        return None, "kernel not in the counter summary"
+    if source_sha256(k["source"]) != k["sha256"]:
+        return None, f"{k['source']} changed since the counters were taken"
+    return k["bytes_per_launch"], rec
+
+
 def kernel_model(name, st, w, nrhs):
     """Algorithmic work of one launch of a library kernel, from the plan:
-    (bound, amount per launch function of the launch count per application,
-    unit).  Returns None for kernels without a model."""
+    (bound, amount per launch, unit), amount None where it is summed over the
+    launches instead.  Returns None for kernels without a model."""
     esz = 8 if "[c64]" in name else 16
     n, d, N, L, nlev = st["n"], st["d"], st["N"], st["L"], st["nlevels"]
     base = name.split(" ")[0]
@@ -110,6 +142,11 @@ def kernel_model(name, st, w, nrhs):
         return "hbm", per_app / nlev, "GB/s"
     if base == "gemm_update":
         return "mfma", None, "TFLOP/s"
+    if base == "diag_lu":
+        # per 32 x 32 block: complex LU (sum_j (31-j)^2 multiply-adds) and the
+        # two triangular inverses (about 32^3/6 multiply-adds each), 8 real
+        # flops per complex multiply-add; summed over the plan's panel blocks
+        return "alu", None, "TFLOP/s"
     if base.startswith("fft_"):
         lines = {"fft_first": n ** (d - 1), "fft_last": n ** (d - 1)}
         if base in lines:
@@ -122,9 +159,13 @@ def kernel_model(name, st, w, nrhs):
     return None
 
 
+DIAG_FLOPS_PER_BLOCK = 8.0 * (sum((31 - j) ** 2 for j in range(32)) + 2 * 32 ** 3 / 6.0)
+
+
 def measure_roofline(lsp, torch, w, m_dev, u_dev, prec):
     """Live per-kernel timing (HIP events on the kernel's stream) over one
-    extra step; returns the roofline record of the kernel with the most time."""
+    extra step; returns the roofline record of the kernel with the most time
+    (among those with a work model) and the per-kernel table."""
     n, d, omega = w["n"], w["d"], w["omega"]
     nrhs = u_dev.shape[0]
     plan = lsp.Plan(n, d, max_nrhs=nrhs, precision=prec)
@@ -150,19 +191,31 @@ def measure_roofline(lsp, torch, w, m_dev, u_dev, prec):
             continue
         bound, per_launch, unit = model
         avg_s = ms / cnt / 1e3
+        fp64 = "[c64]" not in name
         if bound == "mfma":
             flops = st["update_flops"]          # all launches of one factorisation
             achieved = flops / (ms / 1e3) / 1e12
-            peak = 157.3 if "[c64]" in name else 78.6
+            peak = 78.6 if fp64 else 157.3      # dense FP64 / FP32 matrix cores
+            amount = flops / cnt
+        elif bound == "alu":
+            flops = DIAG_FLOPS_PER_BLOCK * st["panel_blocks"]
+            achieved = flops / (ms / 1e3) / 1e12
+            peak = 78.6 if fp64 else 157.3      # FP64 / FP32 vector ALUs
             amount = flops / cnt
         else:
             achieved = per_launch / avg_s / 1e9
-            peak = 8000.0
+            peak = HBM_PEAK_GBS
             amount = per_launch
-        return {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": None, "avg_launch_us": 1e6 * avg_s,
-                "launches": cnt, "algorithmic_per_launch": amount,
-                "share_of_kernel_time": ms / total}, table
+        traffic, rec = recorded_traffic(name)
+        out = {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+               "frac": achieved / peak, "traffic": traffic, "avg_launch_us": 1e6 * avg_s,
+               "launches": cnt, "algorithmic_per_launch": amount, "share_of_kernel_time": ms / total}
+        if traffic is None:
+            out["traffic_note"] = rec
+        else:
+            out["traffic_note"] = (f"HBM bytes per launch from rocprofv3 FETCH_SIZE x {rec['fetch_scale']:.3f} + "
+                                   f"WRITE_SIZE x {rec['write_scale']:.3f} (copy-calibrated), {rec['command']}")
+        return out, table
     return None, table
 
 

@@ -97,9 +97,12 @@ typedef struct {
                                  block plus the inverted diagonal blocks */
   double update_flops;        /* real flops of the trailing-update products
                                  F22 -= L21 U12 (the MFMA part of the factor) */
+  double panel_blocks;        /* diagonal-block factorisations per lsp_factor:
+                                 the sum over fronts of ceil(p / panel) */
 } lsp_plan_stats;
 
-typedef struct lsp_plan lsp_plan;        /* opaque, host-side */
+typedef struct lsp_plan lsp_plan;        /* opaque; host-side, plus one device copy of
+                                           its constant arrays per device used */
 typedef struct lsp_problem lsp_problem;  /* opaque, owns no device memory */
 
 /* Defaults: tol 1e-8, restart 30, max_iters 1000, FP64, b = 2, auto leaf and

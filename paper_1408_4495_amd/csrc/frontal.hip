@@ -617,13 +617,12 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
   // loads below use clamped in-range indices instead of branches (padded
   // entries meet exact zeros, and padded rows are never stored), so the
   // wait counts stay exact and the prefetches stay in flight
-  // The L21 rows are prefetched when the registers allow (NR right-hand
-  // sides of at most 16 bytes in all), and double-buffered (the next
-  // panel's rows load during this panel) when they take at most 8 bytes;
-  // with more right-hand sides each entry carries NR times the arithmetic,
-  // and rows are loaded eight entries at a time after the product.
+  // The L21 rows are prefetched at the panel start when the registers allow
+  // (NR right-hand sides of at most 16 bytes in all); with more right-hand
+  // sides each entry carries NR times the arithmetic, and rows are loaded
+  // eight entries at a time after the product.  (Loading the next panel's
+  // rows during the current panel was measured slower.)
   constexpr bool PRE = sizeof(cplx<T>) * NR <= 16;
-  constexpr bool DB = sizeof(cplx<T>) * NR <= 8;
   constexpr int LN = PRE ? NB : 1;
   auto load_l = [&](const int k0p, cplx<T>(&dst)[LN]) {
     if constexpr (PRE) {
@@ -633,8 +632,8 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
       for (int j = 0; j < NB; ++j) dst[j] = F[(long long)(k0p + min(j, kbp - 1)) * m + rr];
     }
   };
-  cplx<T> lA[LN], lB[LN];
-  load_l(0, lA);  // panel 0's rows go out before the gather of v below
+  cplx<T> lrow[LN];
+  load_l(0, lrow);  // panel 0's rows go out before the gather of v below
   int pnext = pm[min(gj, f.p - 1)];
   const cplx<T>* Lg0 = Dinv + f.dinv_off;
   const cplx<T> li0 = Lg0[tid], li1 = Lg0[tid + 256], li2 = Lg0[tid + 512], li3 = Lg0[tid + 768];
@@ -675,7 +674,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
   Li[0][tid % NB][tid / NB + 16] = li2;
   Li[0][tid % NB][tid / NB + 24] = li3;
   __syncthreads();
-  auto panel = [&](const int b, cplx<T>(&lc)[LN], cplx<T>(&ln)[LN]) {
+  auto panel = [&](const int b, cplx<T>(&lc)[LN]) {
     const int k0 = b * NB;
     const int kb = min(NB, f.p - k0);
     const int k1 = k0 + kb;
@@ -691,11 +690,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
     const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(more ? b + 1 : b) * 2 * NB * NB;
     const cplx<T> lin0 = Lg[tid], lin1 = Lg[tid + 256], lin2 = Lg[tid + 512], lin3 = Lg[tid + 768];
     pnext = pm[min(k1 + gj, f.p - 1)];
-    if constexpr (DB) {
-      if (more) load_l(k1, ln);
-    } else {
-      if (b > 0) load_l(k0, lc);
-    }
+    if (b > 0) load_l(k0, lc);
     __builtin_amdgcn_sched_barrier(0);
     if (tid < NR * NB) tb[gk][gj] = g;
     // Li[cur ^ 1] was last read before the previous panel's final barrier
@@ -751,15 +746,8 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
     }
     __syncthreads();
   };
-  // panels in pairs, so the two row buffers alternate by name
   const int nblk = (f.p + NB - 1) / NB;
-  for (int b = 0; b < nblk; b += 2) {
-    panel(b, lA, lB);
-    if (b + 1 < nblk) {
-      if constexpr (DB) panel(b + 1, lB, lA);
-      else panel(b + 1, lA, lA);
-    }
-  }
+  for (int b = 0; b < nblk; ++b) panel(b, lrow);
   if constexpr (VL)
     for (int e = tid; e < m * nr; e += 256) {
       int r = e % m, k = e / m;
@@ -813,18 +801,16 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
     Ui[cb][tid % NB][tid / NB + 24] = ui3;
   }
   const int j = tid % NB, grp = tid / NB;
-  // U12 block of a panel (first TU columns of this thread); double-buffered
-  // (the next panel's block loads during this one) when one right-hand side
-  // of at most 8 bytes leaves the registers for it
-  constexpr bool DB = sizeof(cplx<T>) * NR <= 8;
+  // U12 block of a panel (first TU columns of this thread), loaded at the
+  // panel start (loading the next panel's block during the current one was
+  // measured slower: the second buffer spills)
   auto load_u = [&](const int bp, cplx<T>(&dst)[TU]) {
     const int k0p = bp * NB, kbp = min(NB, f.p - k0p), k1p = k0p + kbp;
 #pragma unroll
     for (int t = 0; t < TU; ++t) dst[t] = F[(k0p + min(j, kbp - 1)) + (long long)min(k1p + grp + G * t, m - 1) * m];
   };
-  cplx<T> uA[TU], uB[TU];
-  if constexpr (DB) load_u(nblk - 1, uA);
-  auto panel = [&](const int b, cplx<T>(&u)[TU], cplx<T>(&un)[TU]) {
+  cplx<T> ucol[TU];
+  auto panel = [&](const int b, cplx<T>(&u)[TU]) {
     const int k0 = b * NB;
     const int kb = min(NB, f.p - k0);
     const int k1 = k0 + kb;
@@ -836,11 +822,7 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
     const cplx<T>* Ugn = Dinv + f.dinv_off + (long long)(b > 0 ? b - 1 : 0) * 2 * NB * NB + NB * NB;
     const cplx<T> uin0 = Ugn[tid], uin1 = Ugn[tid + 256], uin2 = Ugn[tid + 512], uin3 = Ugn[tid + 768];
     const int gi = id[k0 + min(tid / 8, kb - 1)];  // grid index of row tid / 8, for writing x
-    if constexpr (DB) {
-      if (b > 0) load_u(b - 1, un);
-    } else {
-      load_u(b, u);
-    }
+    load_u(b, u);
     __syncthreads();  // x(k1:m) of the previous panel is in place; Ui[cur ^ 1] is free
     Ui[cur ^ 1][tid % NB][tid / NB] = uin0;
     Ui[cur ^ 1][tid % NB][tid / NB + 8] = uin1;
@@ -890,14 +872,7 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
       }
     }
   };
-  // panels in pairs from the last, so the two buffers alternate by name
-  for (int b = nblk - 1; b >= 0; b -= 2) {
-    panel(b, uA, uB);
-    if (b - 1 >= 0) {
-      if constexpr (DB) panel(b - 1, uB, uA);
-      else panel(b - 1, uA, uA);
-    }
-  }
+  for (int b = nblk - 1; b >= 0; --b) panel(b, ucol);
 }
 
 template <typename T, int NR>

@@ -490,6 +490,7 @@ lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* s) {
   s->factor_flops = P.flops;
   s->sweep_entries = P.sweep_entries;
   s->update_flops = P.update_flops;
+  s->panel_blocks = P.panel_blocks;
   return LSP_OK;
 }
 

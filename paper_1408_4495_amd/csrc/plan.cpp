@@ -187,6 +187,7 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
       int kb = std::min(P.nb, f.p - k0);
       P.sweep_entries += (double)(m - k0 - kb) * kb + (double)P.nb * P.nb;
       P.update_flops += 8.0 * (double)(m - k0 - kb) * (double)(m - k0 - kb) * kb;
+      P.panel_blocks += 1.0;
     }
   }
   for (FrontDev& f : P.fronts) {

@@ -44,6 +44,7 @@ struct Plan {
   long long sum_p = 0, sum_pq = 0;
   int max_front = 0, max_p = 0;
   double flops = 0.0, factor_entries = 0.0, sweep_entries = 0.0, update_flops = 0.0;
+  double panel_blocks = 0.0;  // sum over fronts of ceil(p / nb)
   std::vector<int> radices;       // FFT radices for L, in pass order
 };
 

@@ -41,7 +41,8 @@ class PlanStats(ctypes.Structure):
                 ("nfronts", ctypes.c_int), ("nlevels", ctypes.c_int), ("max_front", ctypes.c_int),
                 ("max_pivots", ctypes.c_int), ("factor_entries", ctypes.c_double),
                 ("front_entries", ctypes.c_double), ("factor_flops", ctypes.c_double),
-                ("sweep_entries", ctypes.c_double), ("update_flops", ctypes.c_double)]
+                ("sweep_entries", ctypes.c_double), ("update_flops", ctypes.c_double),
+                ("panel_blocks", ctypes.c_double)]
 
 
 class LspError(RuntimeError):

@@ -1,0 +1,117 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+    python -m paper_1408_4495_amd.profile_summary stats <kernel_stats.csv> <title> <command>
+        per-kernel time table (markdown) from a --kernel-trace --stats run;
+    python -m paper_1408_4495_amd.profile_summary traffic <fetch.csv> <write.csv> <title> <cmd_fetch> <cmd_write>
+        per-kernel HBM bytes from two --pmc runs (FETCH_SIZE, then WRITE_SIZE,
+        counter_collection.csv each) of profile_probe, which ends with a
+        device-to-device copy of known size: each counter is scaled by what
+        it reads for that copy.  Kernels are keyed like the library's timing
+        registry ("bwd [c64]"), with the SHA-256 of the source file holding
+        the kernel, so a reader can tell whether the record still applies.
+"""
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+SOURCE = {"fwd": "frontal.hip", "bwd": "frontal.hip", "diag_lu": "frontal.hip", "panel_trsm": "frontal.hip",
+          "gemm_update": "frontal.hip", "assemble_front": "frontal.hip", "fft_lines": "fft.hip",
+          "gram": "stencil.hip", "gram_reduce": "stencil.hip", "eigen": "stencil.hip", "applyQ": "stencil.hip",
+          "dots_partial": "krylov.hip", "dots_final": "krylov.hip", "axpy": "krylov.hip"}
+FFT_MODE = {"0": "fft_axis", "1": "fft_first", "2": "fft_conv", "3": "fft_last"}
+
+
+def short(name):
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "").replace("lsp::", "")
+    return re.sub(r"\(.*", "", name).strip()
+
+
+def registry_key(name):
+    """Kernel symbol -> the timing-registry name, e.g. bwd_kernel<float, 1, true> -> 'bwd [c64]'."""
+    s = short(name)
+    m = re.match(r"(\w+?)_kernel(?:<(.*)>)?$", s)
+    if not m:
+        return None, None
+    base, targs = m.group(1), (m.group(2) or "")
+    args = [a.strip() for a in targs.split(",")] if targs else []
+    if base == "fft_lines" and len(args) == 3:
+        base = FFT_MODE.get(args[2], base)
+    prec = ""
+    if args:
+        if re.match(r"(HIP_vector_type<)?float\b", args[0]):
+            prec = " [c64]"
+        elif re.match(r"(HIP_vector_type<)?double\b", args[0]):
+            prec = " [c128]"
+    src = SOURCE.get(base) or SOURCE.get(base.split("_")[0]) or ("fft.hip" if base.startswith("fft_") else None)
+    return base + prec, src
+
+
+def stats(path, title, cmd):
+    rows = list(csv.DictReader(open(path)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = [f"# {title}", "", "Command (from the repository root on the GPU box):", "", "```", cmd, "```", "",
+           f"Total kernel time {tot / 1e6:.3f} ms.", "",
+           "| kernel | calls | total ms | avg us | min us | max us | share |", "|---|---|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:25]:
+        t = float(r["TotalDurationNs"])
+        out.append(f"| `{short(r['Name'])}` | {r['Calls']} | {t / 1e6:.3f} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {100 * t / tot:.1f}% |")
+    return "\n".join(out) + "\n"
+
+
+def traffic(fetch_csv, write_csv, title, cmd_f, cmd_w):
+    def load(path):
+        rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Dispatch_Id"]))
+        return [(r["Kernel_Name"], float(r["Counter_Value"])) for r in rows]
+    f, w = load(fetch_csv), load(write_csv)
+    if [a for a, _ in f] != [a for a, _ in w]:
+        raise SystemExit("the two runs dispatched different kernel sequences")
+    # calibration: the last dispatch is the device-to-device copy of known size
+    copy_name, copy_f = f[-1]
+    copy_w = w[-1][1]
+    copy_bytes = int(os.environ.get("LSP_COPY_BYTES", str(256 << 20)))
+    fs = copy_bytes / (copy_f * 1024.0)
+    ws = copy_bytes / (copy_w * 1024.0)
+    agg = {}
+    for (name, fv), (_, wv) in zip(f[:-1], w[:-1]):
+        key, src = registry_key(name)
+        if key is None or src is None:
+            continue
+        a = agg.setdefault(key, {"launches": 0, "fetch_kib": 0.0, "write_kib": 0.0, "source": src})
+        a["launches"] += 1
+        a["fetch_kib"] += fv
+        a["write_kib"] += wv
+    kernels = {}
+    lines = [f"# {title}", "", "Commands (from the repository root on the GPU box):", "", "```", cmd_f, cmd_w, "```", "",
+             f"Calibration: the final `{short(copy_name)}` moves {copy_bytes} bytes each way and reads "
+             f"FETCH_SIZE {copy_f:.1f} KiB, WRITE_SIZE {copy_w:.1f} KiB, so HBM bytes = "
+             f"FETCH_SIZE x 1024 x {fs:.3f} + WRITE_SIZE x 1024 x {ws:.3f}.", "",
+             "| kernel | launches | read MB | written MB | bytes per launch |", "|---|---|---|---|---|"]
+    for key, a in sorted(agg.items(), key=lambda kv: -(kv[1]["fetch_kib"] * fs + kv[1]["write_kib"] * ws)):
+        rd = a["fetch_kib"] * 1024 * fs
+        wr = a["write_kib"] * 1024 * ws
+        per = (rd + wr) / a["launches"]
+        sha = hashlib.sha256(open(os.path.join(CSRC, a["source"]), "rb").read()).hexdigest()
+        kernels[key] = {"launches": a["launches"], "bytes_per_launch": per, "source": a["source"], "sha256": sha}
+        lines.append(f"| `{key}` | {a['launches']} | {rd / 1e6:.2f} | {wr / 1e6:.2f} | {per:.0f} |")
+    rec = {"fetch_scale": fs, "write_scale": ws, "command": cmd_f + " ; " + cmd_w, "kernels": kernels}
+    lines += ["", "<!-- traffic-json: " + json.dumps(rec) + " -->"]
+    return "\n".join(lines) + "\n"
+
+
+def main():
+    mode = sys.argv[1]
+    if mode == "stats":
+        sys.stdout.write(stats(*sys.argv[2:5]))
+    elif mode == "traffic":
+        sys.stdout.write(traffic(*sys.argv[2:7]))
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main()
