@@ -76,17 +76,27 @@ __global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ k
       pa[k] = a; pb[k] = a + rem; own[k] = true;
     }
   }
-  // the next chunk's table entries are loaded while the current one is
-  // reduced.  Thread tid stages entries e = tid + 256u (row a = e / CH,
-  // column jj = e % CH of the chunk, both fixed across chunks); the far-set
-  // coordinates of column base + jj are kept as mixed-radix digits and
-  // advanced by CH per chunk (no divisions in the loop).  Entries outside the
-  // block's range load table entry 0 and are zeroed.
-  constexpr int EPT = (S * CH + 255) / 256;
+  // Chunks of CHs columns: the staging arrays hold S (CH + 1) entries, used
+  // as s rows of stride ld = CHs + 1, so classes with few rows take wider
+  // chunks (fewer memory round trips per block).  The next chunk's table
+  // entries are loaded while the current one is reduced.  Thread tid stages
+  // entries e = tid + 256u (row ea = e / CHs, column ej = e % CHs, both fixed
+  // across chunks); the far-set coordinates of column base + ej are kept as
+  // mixed-radix digits and advanced by CHs per chunk (no divisions in the
+  // loop).  Entries outside the block's range load table entry 0 and are zeroed.
+  const int ld = (S * (CH + 1)) / s;
+  const int CHs = ld - 1;
+  double2* Xf = &X[0][0];
+  double2* Zf = &Z[0][0];
+  constexpr int EPT = (S * (CH + 1) + 255) / 256;
+  int ea[EPT], ej[EPT];
   int dig[EPT][3];
 #pragma unroll
   for (int u = 0; u < EPT; ++u) {
-    unsigned rem = (unsigned)(j0 + (tid + 256 * u) % CH);
+    const int e = tid + 256 * u;
+    ea[u] = min(e / CHs, s - 1);
+    ej[u] = e % CHs;
+    unsigned rem = (unsigned)(j0 + ej[u]);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       dig[u][ax] = ax < d ? (int)(rem % (unsigned)fsz[ax]) : 0;
@@ -97,8 +107,8 @@ __global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ k
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       const int e = tid + 256 * u;
-      const int a = min(e / CH, s - 1);
-      const bool valid = e < s * CH && base + e % CH < j1;
+      const int a = ea[u];
+      const bool valid = e < s * CHs && base + ej[u] < j1;
       int t[3] = {0, 0, 0};
       bool near = true;
 #pragma unroll
@@ -112,7 +122,7 @@ __global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ k
       const double2 kv = ktab[valid ? ktab_index(t[0], t[1], t[2], n, d) : 0];
       v[u] = valid && !(interior && near) ? kv : make_double2(0, 0);
       // advance to the same column of the next chunk
-      dig[u][0] += CH;
+      dig[u][0] += CHs;
 #pragma unroll
       for (int ax = 0; ax < 2; ++ax) {
         if (ax + 1 < d) {
@@ -124,31 +134,32 @@ __global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ k
   double2 vnext[EPT];
   __syncthreads();  // soff staged
   if (j0 < j1) fetch(j0, vnext);  // (an empty block range loads nothing)
-  for (long long base = j0; base < j1; base += CH) {
+  for (long long base = j0; base < j1; base += CHs) {
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       const int e = tid + 256 * u;
-      if (e < s * CH) X[e / CH][e % CH] = vnext[u];
+      if (e < s * CHs) Xf[ea[u] * ld + ej[u]] = vnext[u];
     }
-    if (base + CH < j1) fetch(base + CH, vnext);
+    if (base + CHs < j1) fetch(base + CHs, vnext);
     __syncthreads();
     if (PASS2) {
-      for (int e = tid; e < s * CH; e += blockDim.x) {
-        int k = e / CH, jj = e % CH;
+      for (int e = tid; e < s * CHs; e += blockDim.x) {
+        int k = e / CHs, jj = e % CHs;
         double2 z = make_double2(0, 0);
-        for (int a = 0; a < s; ++a) z = cadd(z, cmulc(Us[a + S * k], X[a][jj]));
-        Z[k][jj] = z;
+        for (int a = 0; a < s; ++a) z = cadd(z, cmulc(Us[a + S * k], Xf[a * ld + jj]));
+        Zf[k * ld + jj] = z;
       }
       __syncthreads();
     }
+    const double2* Yf = PASS2 ? Zf : Xf;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       if (k >= per || !own[k]) continue;
       double2 sum = acc[k];
-      for (int jj = grp; jj < CH; jj += G) {
-        double2 u = PASS2 ? Z[pa[k]][jj] : X[pa[k]][jj];
-        double2 w = PASS2 ? Z[pb[k]][jj] : X[pb[k]][jj];
+      for (int jj = grp; jj < CHs; jj += G) {
+        const double2 u = Yf[pa[k] * ld + jj];
+        const double2 w = Yf[pb[k] * ld + jj];
         sum = cadd(sum, cmulc(w, u));  // u * conj(w)
       }
       acc[k] = sum;
@@ -156,7 +167,7 @@ __global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ k
   }
   // reduce the column groups in a fixed order
   __syncthreads();
-  double2* red = &X[0][0];  // reuse the staging buffer: G x npairs <= 256 entries
+  double2* red = Xf;  // reuse the staging buffer: G x npairs <= 256 entries
   if (npairs <= 128) {
     if (own[0]) red[grp * npairs + (tid % npairs)] = acc[0];
     __syncthreads();
