@@ -17,6 +17,10 @@ void k_norm(const double2* w, double2* partial, double2* h, double2* H, double* 
             int nrhs, const int* active, hipStream_t st);
 void k_axpy(const double2* V, double2* w, const double2* h, int nvec, long long N, int nrhs, const int* active,
             hipStream_t st);
+// Arnoldi step k: CGS2 of w against V_0..V_k, H(0:k+1, k), the norm scalars,
+// and vnext = w / ||w||; pA, pB: two partial-sum buffers [nrhs][dot_blocks(N)][kMaxVec].
+void k_arnoldi_orth(const double2* V, double2* w, double2* pA, double2* pB, double2* h, double2* H, double* scal,
+                    double2* vnext, int k, int restart, long long N, int nrhs, const int* active, hipStream_t st);
 void k_scale(double2* y, const double2* x, const double* scal, long long N, int nrhs, const int* active,
              hipStream_t st);
 void k_givens(double2* H, double2* cs, double2* sn, double2* gam, double* scal, int k, int restart, int nrhs,

@@ -120,6 +120,129 @@ __global__ void __launch_bounds__(kFinSlices * kMaxVec) dots_final_kernel(
   }
 }
 
+// ---- fused Arnoldi orthogonalisation (CGS2 and the norm, five launches per
+// step instead of ten): a kernel that consumes a reduction forms its final
+// sums itself, identically in every block (fixed order), instead of a
+// separate final launch.
+
+// hs[i] = sum over blocks of pin[r][blk][i], i < nvec: thread (i, sl) sums
+// blocks sl, sl + 8, ... with its loads in flight together; the eight slice
+// sums are then added in slice order.  256 threads; ends with a barrier.
+__device__ void final_sums(const double2* __restrict__ pin, int r, int nblk, int nvec, double2* hs,
+                           double2 (*red)[kMaxVec]) {
+  const int i = threadIdx.x % kMaxVec, sl = threadIdx.x / kMaxVec;
+  double2 acc = make_double2(0, 0);
+  if (i < nvec) {
+    const double2* pr = pin + (long long)r * nblk * kMaxVec + i;
+    double2 v[8];
+    for (int b0 = sl; b0 < nblk; b0 += 8 * kFinSlices) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int b = b0 + u * kFinSlices;
+        v[u] = b < nblk ? pr[(long long)b * kMaxVec] : make_double2(0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = cadd(acc, v[u]);
+    }
+  }
+  red[sl][i] = acc;
+  __syncthreads();
+  if (sl == 0 && i < nvec) {
+    double2 t = red[0][i];
+#pragma unroll
+    for (int q = 1; q < kFinSlices; ++q) t = cadd(t, red[q][i]);
+    hs[i] = t;
+  }
+  __syncthreads();
+}
+
+// This block's partial sums acc[i], i < nvec, combined over its waves in a
+// fixed order and written to pout[r][blk][i].
+__device__ void block_partials(const double2 (&acc)[kMaxVec], int nvec, double2* __restrict__ pout, int r, int blk,
+                               int nblk) {
+  __shared__ double2 ws[KB / 64][kMaxVec];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll
+  for (int i = 0; i < kMaxVec; ++i) {
+    if (i < nvec) {
+      double2 s = wave_sum(acc[i]);
+      if (lane == 0) ws[wave][i] = s;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nvec; i += KB) {
+    double2 s = ws[0][i];
+    for (int q = 1; q < KB / 64; ++q) s = cadd(s, ws[q][i]);
+    pout[((long long)r * nblk + blk) * kMaxVec + i] = s;
+  }
+}
+
+// One Gram-Schmidt pass of Arnoldi step k: h = V^H w from the partial sums
+// pin (block 0 records it: mode 0 sets H(0:k, k), mode 1 adds), w -= V h over
+// this block's elements, then this block's partial sums of the next
+// reduction to pout: V^H w (NEXT == 0) or ||w||^2 (NEXT == 1).  The element
+// partition and the per-thread order match dots_partial_kernel.
+template <int NEXT>
+__global__ void __launch_bounds__(KB) cgs_kernel(const double2* __restrict__ V, double2* __restrict__ w,
+                                                 const double2* __restrict__ pin, double2* __restrict__ pout,
+                                                 double2* __restrict__ h, double2* __restrict__ H, int nvec, long long N,
+                                                 int nrhs, int k, int restart, int mode,
+                                                 const int* __restrict__ active) {
+  const int r = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  if (active && !active[r]) return;
+  __shared__ double2 hs[kMaxVec];
+  __shared__ double2 red[kFinSlices][kMaxVec];
+  final_sums(pin, r, nblk, nvec, hs, red);
+  if (blk == 0 && threadIdx.x < nvec) {
+    const int i = threadIdx.x;
+    h[(long long)r * kMaxVec + i] = hs[i];
+    double2* Hc = H + (long long)r * (restart + 1) * restart + (restart + 1) * k;
+    Hc[i] = mode == 0 ? hs[i] : cadd(Hc[i], hs[i]);
+  }
+  const long long e0 = N * blk / nblk, e1 = N * (blk + 1) / nblk;
+  double2 acc[kMaxVec];
+#pragma unroll
+  for (int i = 0; i < kMaxVec; ++i) acc[i] = make_double2(0, 0);
+  double2* wr = w + (long long)r * N;
+  for (long long e = e0 + threadIdx.x; e < e1; e += KB) {
+    double2 s = wr[e];
+#pragma unroll
+    for (int i = 0; i < kMaxVec; ++i)
+      if (i < nvec) s = cfms(s, hs[i], V[((long long)i * nrhs + r) * N + e]);
+    wr[e] = s;
+    if constexpr (NEXT == 0) {
+#pragma unroll
+      for (int i = 0; i < kMaxVec; ++i)
+        if (i < nvec) acc[i] = cadd(acc[i], cmulc(V[((long long)i * nrhs + r) * N + e], s));
+    } else {
+      acc[0] = cadd(acc[0], cmulc(s, s));
+    }
+  }
+  block_partials(acc, NEXT == 0 ? nvec : 1, pout, r, blk, nblk);
+}
+
+// ||w|| from the partial sums pin; block 0 records H(k+1, k) and the
+// scalars; every block writes y = w / ||w|| (0 if ||w|| = 0) over its elements.
+__global__ void __launch_bounds__(KB) scale_norm_kernel(double2* __restrict__ y, const double2* __restrict__ w,
+                                                        const double2* __restrict__ pin, double2* __restrict__ H,
+                                                        double* __restrict__ scal, long long N, int k, int restart,
+                                                        const int* __restrict__ active) {
+  const int r = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  if (active && !active[r]) return;
+  __shared__ double2 hs[kMaxVec];
+  __shared__ double2 red[kFinSlices][kMaxVec];
+  final_sums(pin, r, nblk, 1, hs, red);
+  const double nrm = sqrt(fmax(hs[0].x, 0.0));
+  const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
+  if (blk == 0 && threadIdx.x == 0) {
+    if (k >= 0) H[(long long)r * (restart + 1) * restart + (k + 1) + (restart + 1) * k] = make_double2(nrm, 0.0);
+    scal[r * kScal + S_NORM] = nrm;
+    scal[r * kScal + S_INV] = inv;
+  }
+  const long long e0 = N * blk / nblk, e1 = N * (blk + 1) / nblk;
+  for (long long e = e0 + threadIdx.x; e < e1; e += KB) y[(long long)r * N + e] = cscale(w[(long long)r * N + e], inv);
+}
+
 // w -= sum_i h_i V_i
 __global__ void __launch_bounds__(KB) axpy_kernel(const double2* __restrict__ V, double2* __restrict__ w,
                                                   const double2* __restrict__ h, int nvec, long long N, int nrhs,
@@ -277,6 +400,18 @@ void k_norm(const double2* w, double2* partial, double2* h, double2* H, double* 
   LSP_LAUNCH("dots_partial", 0, dots_partial_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, w, w, partial, 1, N, nrhs, active);
   LSP_LAUNCH("dots_final", 0, dots_final_kernel, dim3(nrhs), dim3(kFinSlices * kMaxVec), 0, st, partial, h, H, scal, 1, nblk, k, restart, 2,
                      active);
+}
+
+void k_arnoldi_orth(const double2* V, double2* w, double2* pA, double2* pB, double2* h, double2* H, double* scal,
+                    double2* vnext, int k, int restart, long long N, int nrhs, const int* active, hipStream_t st) {
+  const int nblk = dot_blocks(N), nvec = k + 1;
+  LSP_LAUNCH("dots_partial", 0, dots_partial_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, V, w, pA, nvec, N, nrhs, active);
+  LSP_LAUNCH("cgs", 0, cgs_kernel<0>, dim3(nblk, nrhs), dim3(KB), 0, st, V, w, pA, pB, h, H, nvec, N, nrhs, k, restart, 0,
+             active);
+  LSP_LAUNCH("cgs", 0, cgs_kernel<1>, dim3(nblk, nrhs), dim3(KB), 0, st, V, w, pB, pA, h, H, nvec, N, nrhs, k, restart, 1,
+             active);
+  LSP_LAUNCH("scale_norm", 0, scale_norm_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, vnext, w, pA, H, scal, N, k, restart,
+             active);
 }
 
 void k_axpy(const double2* V, double2* w, const double2* h, int nvec, long long N, int nrhs, const int* active,

@@ -207,6 +207,7 @@ struct SolvePtrs {
   double2* h;     // [nrhs][kMaxVec]
   double2* y;
   double2* partial;
+  double2* partial2;
   double* scal;   // [nrhs][kScal]
   int* active;
   int* ksz;
@@ -236,6 +237,7 @@ size_t layout_solve(const Plan& P, int nrhs, int restart, bool krylov, void* bas
     s.h = cv.take<double2>((size_t)nrhs * kMaxVec);
     s.y = cv.take<double2>((size_t)nrhs * kMaxVec);
     s.partial = cv.take<double2>((size_t)nrhs * dot_blocks((long long)N) * kMaxVec);
+    s.partial2 = cv.take<double2>((size_t)nrhs * dot_blocks((long long)N) * kMaxVec);
     s.scal = cv.take<double>((size_t)nrhs * kScal);
     s.active = cv.take<int>(nrhs);
     s.ksz = cv.take<int>(nrhs);
@@ -756,12 +758,8 @@ lsp_status lsp_solve(lsp_problem* pb, int nrhs, int rhs_kind, const void* rhs, v
         double2* Zk = s.Z + (size_t)k * NB;
         apply_precond(pb, s, nrhs, Vk, Zk);
         apply_conv(pb, s, nrhs, pb->precision, Zk, s.w, true, pb->d.w2m);
-        k_dots(s.V, s.w, s.partial, s.h, s.H, s.scal, k + 1, k, R, 0, N, nrhs, s.active, st);
-        k_axpy(s.V, s.w, s.h, k + 1, N, nrhs, s.active, st);
-        k_dots(s.V, s.w, s.partial, s.h, s.H, s.scal, k + 1, k, R, 1, N, nrhs, s.active, st);
-        k_axpy(s.V, s.w, s.h, k + 1, N, nrhs, s.active, st);
-        k_norm(s.w, s.partial, s.h, s.H, s.scal, k, R, N, nrhs, s.active, st);
-        k_scale(s.V + (size_t)(k + 1) * NB, s.w, s.scal, N, nrhs, s.active, st);
+        k_arnoldi_orth(s.V, s.w, s.partial, s.partial2, s.h, s.H, s.scal, s.V + (size_t)(k + 1) * NB, k, R, N, nrhs,
+                       s.active, st);
         k_givens(s.H, s.cs, s.sn, s.gam, s.scal, k, R, nrhs, s.active, st);
         LSP_HIP(hipMemcpyAsync(pb->host_scal, s.scal, sizeof(double) * kScal * nrhs, hipMemcpyDeviceToHost, st));
         LSP_HIP(hipStreamSynchronize(st));
