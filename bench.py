@@ -231,7 +231,7 @@ def cpu_baseline(w, budget_s=12.0):
         prob = OracleProblem(w["n"], w["d"], w["omega"], w["m"])
         res = prob.solve(w["uI"][0])
         done += 1
-        if time.perf_counter() - t0 >= budget_s or done >= 5:
+        if time.perf_counter() - t0 >= budget_s or done >= 12:
             break
     el = time.perf_counter() - t0
     return {"value": done / el, "unit": "solves/s", "cores": cores, "kind": "oracle",

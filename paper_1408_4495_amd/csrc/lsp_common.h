@@ -2,6 +2,7 @@
 // error handling, and the sizes that every translation unit agrees on.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include <cstdint>
@@ -83,24 +84,36 @@ __host__ __device__ inline double2 widen(float2 a) { return to_c128(a); }
 
 // Brackets one kernel launch with HIP events when timing is enabled
 // (lsp_timing_enable); a no-op otherwise.  esize tags the element type.
+// When timing is enabled, a launch takes a start and a stop event that the
+// runtime records at the kernel's own start and end (hipExtLaunchKernelGGL),
+// so the measured time is the kernel's execution, as a profiler sees it.
 class KTimer {
  public:
   KTimer(const char* name, int esize, hipStream_t st);
   ~KTimer();
   KTimer(const KTimer&) = delete;
   KTimer& operator=(const KTimer&) = delete;
+  bool active() const { return a_ != nullptr; }
+  hipEvent_t start() const { return a_; }
+  hipEvent_t stop() const { return b_; }
+  void launched() { launched_ = true; }
 
  private:
   hipStream_t st_;
   hipEvent_t a_, b_;
+  bool launched_ = false;
   std::string key_;
 };
 
-#define LSP_LAUNCH(name, esize, kernel, grid, block, shm, st, ...)     \
-  do {                                                                 \
-    ::lsp::KTimer kt_((name), (esize), (st));                          \
-    hipLaunchKernelGGL(kernel, grid, block, shm, st, __VA_ARGS__);     \
-    LSP_HIP(hipGetLastError());                                        \
+#define LSP_LAUNCH(name, esize, kernel, grid, block, shm, st, ...)                                      \
+  do {                                                                                                  \
+    ::lsp::KTimer kt_((name), (esize), (st));                                                           \
+    if (kt_.active())                                                                                   \
+      hipExtLaunchKernelGGL(kernel, grid, block, shm, st, kt_.start(), kt_.stop(), 0u, __VA_ARGS__);   \
+    else                                                                                                \
+      hipLaunchKernelGGL(kernel, grid, block, shm, st, __VA_ARGS__);                                    \
+    LSP_HIP(hipGetLastError());                                                                         \
+    kt_.launched();                                                                                     \
   } while (0)
 
 inline int ipow(int b, int e) { int r = 1; while (e-- > 0) r *= b; return r; }

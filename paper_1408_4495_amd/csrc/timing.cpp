@@ -1,7 +1,8 @@
 // Optional per-kernel timing: when enabled, every launch made through
-// LSP_LAUNCH is bracketed by two HIP events recorded on the launch's own
-// stream; lsp_timing_get() waits for the recorded events and reports, per
-// kernel name and element size, the summed event-to-event time and count.
+// LSP_LAUNCH carries two HIP events that the runtime records at the kernel's
+// start and end on the launch's own stream; lsp_timing_get() waits for them
+// and reports, per kernel name and element size, the summed kernel time and
+// the launch count.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -67,14 +68,18 @@ KTimer::KTimer(const char* name, int esize, hipStream_t st) : st_(st), a_(nullpt
   key_ = std::string(name) + (esize == 16 ? " [c128]" : esize == 8 ? " [c64]" : "");
   a_ = r.take();
   b_ = r.take();
-  LSP_HIP(hipEventRecord(a_, st_));
 }
 
 KTimer::~KTimer() {
   if (!a_) return;
   Registry& r = reg();
   std::lock_guard<std::mutex> g(r.mu);
-  if (hipEventRecord(b_, st_) == hipSuccess) r.pending.push_back({key_, a_, b_});
+  if (launched_) {
+    r.pending.push_back({key_, a_, b_});
+  } else {  // the launch failed: the events were never recorded
+    r.pool.push_back(a_);
+    r.pool.push_back(b_);
+  }
 }
 
 }  // namespace lsp
