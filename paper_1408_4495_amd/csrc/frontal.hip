@@ -585,13 +585,15 @@ __device__ __forceinline__ void tri_apply(const cplx<T> (*D)[NB + 1], const cplx
 
 // Forward sweep of one front: v = [z(I); 0] + children's updates; per panel:
 //   y_b = L11^{-1} (P_b v_b),  v(k1:m) -= L21 y_b.
-template <typename T, int NR, bool VL>
-__global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
+template <typename T, int NR, bool VL, int TPB>
+__global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
                                                   const FrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                   const int* __restrict__ cpos, const int* __restrict__ perm,
                                                   const cplx<T>* __restrict__ z, cplx<T>* __restrict__ vbuf, int first,
                                                   int nrhs, long long N, long long vstride) {
   static_assert(NR * NB <= 256, "one gather thread per panel entry");
+  static_assert(TPB == 256 || TPB == 512, "256 or 512 threads");
+  constexpr int IPT = NB * NB / TPB;  // inverse-block entries per thread
   extern __shared__ unsigned char smem_raw[];
   __shared__ cplx<T> Li[2][NB][NB + 1];
   __shared__ cplx<T> tb[NR][NB];
@@ -622,7 +624,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
   // sides each entry carries NR times the arithmetic, and rows are loaded
   // eight entries at a time after the product.  (Loading the next panel's
   // rows during the current panel was measured slower.)
-  constexpr bool PRE = sizeof(cplx<T>) * NR <= 16;
+  constexpr bool PRE = sizeof(cplx<T>) * NR <= 16 && (TPB == 256 || sizeof(T) == 4);
   constexpr int LN = PRE ? NB : 1;
   auto load_l = [&](const int k0p, cplx<T>(&dst)[LN]) {
     if constexpr (PRE) {
@@ -636,14 +638,15 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
   load_l(0, lrow);  // panel 0's rows go out before the gather of v below
   int pnext = pm[min(gj, f.p - 1)];
   const cplx<T>* Lg0 = Dinv + f.dinv_off;
-  const cplx<T> li0 = Lg0[tid], li1 = Lg0[tid + 256], li2 = Lg0[tid + 512], li3 = Lg0[tid + 768];
+  const cplx<T> li0 = Lg0[tid], li1 = Lg0[tid + TPB];
+  const cplx<T> li2 = IPT > 2 ? Lg0[tid + 2 * TPB] : li0, li3 = IPT > 2 ? Lg0[tid + 3 * TPB] : li0;
   // v = [z(I); 0] + children's updates: four entries per thread per pass,
   // the index loads of all four, then their value loads, in flight together
-  for (int e0 = 0; e0 < m * nr; e0 += 1024) {
+  for (int e0 = 0; e0 < m * nr; e0 += 4 * TPB) {
     int gidx[4], q0[4], q1[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int e = min(e0 + tid + 256 * u, m * nr - 1), r = e % m;
+      const int e = min(e0 + tid + TPB * u, m * nr - 1), r = e % m;
       gidx[u] = id[min(r, f.p - 1)];
       q0[u] = coff[0] >= 0 ? cp[2 * r] : -1;
       q1[u] = coff[1] >= 0 ? cp[2 * r + 1] : -1;
@@ -651,7 +654,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
     cplx<T> sv[4], c0v[4], c1v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int e = min(e0 + tid + 256 * u, m * nr - 1), r = e % m, k = e / m;
+      const int e = min(e0 + tid + TPB * u, m * nr - 1), r = e % m, k = e / m;
       const long long rb = (long long)(r0 + k) * vstride;
       sv[u] = z[(long long)(r0 + k) * N + gidx[u]];
       c0v[u] = vbuf[rb + (q0[u] >= 0 ? coff[0] + q0[u] : 0)];
@@ -659,7 +662,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int e = e0 + tid + 256 * u;
+      const int e = e0 + tid + TPB * u;
       if (e < m * nr) {
         const int r = e % m, k = e / m;
         cplx<T> s = r < f.p ? sv[u] : mk<T>(0, 0);
@@ -670,9 +673,11 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
     }
   }
   Li[0][tid % NB][tid / NB] = li0;
-  Li[0][tid % NB][tid / NB + 8] = li1;
-  Li[0][tid % NB][tid / NB + 16] = li2;
-  Li[0][tid % NB][tid / NB + 24] = li3;
+  Li[0][tid % NB][tid / NB + TPB / NB] = li1;
+  if constexpr (IPT > 2) {
+    Li[0][tid % NB][tid / NB + 2 * TPB / NB] = li2;
+    Li[0][tid % NB][tid / NB + 3 * TPB / NB] = li3;
+  }
   __syncthreads();
   auto panel = [&](const int b, cplx<T>(&lc)[LN]) {
     const int k0 = b * NB;
@@ -688,18 +693,21 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
     // keeps these loads unconditional so they stay in registers)
     // (named scalars: a small array here is left in scratch by the compiler)
     const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(more ? b + 1 : b) * 2 * NB * NB;
-    const cplx<T> lin0 = Lg[tid], lin1 = Lg[tid + 256], lin2 = Lg[tid + 512], lin3 = Lg[tid + 768];
+    const cplx<T> lin0 = Lg[tid], lin1 = Lg[tid + TPB];
+    const cplx<T> lin2 = IPT > 2 ? Lg[tid + 2 * TPB] : lin0, lin3 = IPT > 2 ? Lg[tid + 3 * TPB] : lin0;
     pnext = pm[min(k1 + gj, f.p - 1)];
     if (b > 0) load_l(k0, lc);
     __builtin_amdgcn_sched_barrier(0);
     if (tid < NR * NB) tb[gk][gj] = g;
     // Li[cur ^ 1] was last read before the previous panel's final barrier
     Li[cur ^ 1][tid % NB][tid / NB] = lin0;
-    Li[cur ^ 1][tid % NB][tid / NB + 8] = lin1;
-    Li[cur ^ 1][tid % NB][tid / NB + 16] = lin2;
-    Li[cur ^ 1][tid % NB][tid / NB + 24] = lin3;
+    Li[cur ^ 1][tid % NB][tid / NB + TPB / NB] = lin1;
+    if constexpr (IPT > 2) {
+      Li[cur ^ 1][tid % NB][tid / NB + 2 * TPB / NB] = lin2;
+      Li[cur ^ 1][tid % NB][tid / NB + 3 * TPB / NB] = lin3;
+    }
     __syncthreads();
-    {
+    if (tid < 256) {  // the 32-row product uses the first four waves
       cplx<T> y[NR];
       tri_apply<T, NR>(Li[cur], tb, tid, y);
       const int i = tid / 8;
@@ -726,7 +734,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
           if (k < nr) vp[k * vs + rfirst] = acc[k];
       }
     }
-    for (int r = PRE ? rfirst + 256 : rfirst; r < m; r += 256) {  // rows not prefetched
+    for (int r = PRE ? rfirst + TPB : rfirst; r < m; r += TPB) {  // rows not prefetched
       cplx<T> acc[NR];
 #pragma unroll
       for (int k = 0; k < NR; ++k) acc[k] = vp[min(k, nr - 1) * vs + r];
@@ -749,7 +757,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
   const int nblk = (f.p + NB - 1) / NB;
   for (int b = 0; b < nblk; ++b) panel(b, lrow);
   if constexpr (VL)
-    for (int e = tid; e < m * nr; e += 256) {
+    for (int e = tid; e < m * nr; e += TPB) {
       int r = e % m, k = e / m;
       vg[(long long)k * vstride + r] = vp[k * vs + r];
     }
@@ -759,12 +767,14 @@ __global__ void __launch_bounds__(256) fwd_kernel(const cplx<T>* __restrict__ Fb
 //   x_b = U11^{-1} (y_b - U12 x(k1:m)).  Writes x at the front's grid points.
 // Thread (j, grp) = (tid % NB, tid / NB) forms the U12 row j product over
 // the columns k1 + grp + 8t; the eight column groups are added in order.
-template <typename T, int NR, bool VL>
-__global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
+template <typename T, int NR, bool VL, int TPB>
+__global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
                                                   const FrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                   cplx<T>* __restrict__ x, cplx<T>* __restrict__ vbuf, int first,
                                                   int nrhs, long long N, long long vstride) {
-  constexpr int G = 256 / NB;  // column groups
+  static_assert(TPB == 256 || TPB == 512, "256 or 512 threads");
+  constexpr int G = TPB / NB;  // column groups
+  constexpr int IPT = NB * NB / TPB;  // inverse-block entries per thread
   constexpr int TU = sizeof(T) == 8 ? 16 : 32;  // U12 columns per thread held in flight
   extern __shared__ unsigned char smem_raw[];
   __shared__ cplx<T> Ui[2][NB][NB + 1];
@@ -786,9 +796,10 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
   const int tid = threadIdx.x;
   const int nblk = (f.p + NB - 1) / NB;
   const cplx<T>* Ug0 = Dinv + f.dinv_off + (long long)(nblk - 1) * 2 * NB * NB + NB * NB;
-  const cplx<T> ui0 = Ug0[tid], ui1 = Ug0[tid + 256], ui2 = Ug0[tid + 512], ui3 = Ug0[tid + 768];
+  const cplx<T> ui0 = Ug0[tid], ui1 = Ug0[tid + TPB];
+  const cplx<T> ui2 = IPT > 2 ? Ug0[tid + 2 * TPB] : ui0, ui3 = IPT > 2 ? Ug0[tid + 3 * TPB] : ui0;
   // v = [y(I) from the forward sweep; x(B) from the ancestors]
-  for (int e = tid; e < m * nr; e += 256) {
+  for (int e = tid; e < m * nr; e += TPB) {
     const int r = e % m, k = e / m;
     if (r >= f.p) vp[k * vs + r] = x[(long long)(r0 + k) * N + id[r]];
     else if constexpr (VL) vp[k * vs + r] = vg[(long long)k * vstride + r];
@@ -796,9 +807,11 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
   {
     const int cb = (nblk - 1) & 1;
     Ui[cb][tid % NB][tid / NB] = ui0;
-    Ui[cb][tid % NB][tid / NB + 8] = ui1;
-    Ui[cb][tid % NB][tid / NB + 16] = ui2;
-    Ui[cb][tid % NB][tid / NB + 24] = ui3;
+    Ui[cb][tid % NB][tid / NB + TPB / NB] = ui1;
+    if constexpr (IPT > 2) {
+      Ui[cb][tid % NB][tid / NB + 2 * TPB / NB] = ui2;
+      Ui[cb][tid % NB][tid / NB + 3 * TPB / NB] = ui3;
+    }
   }
   const int j = tid % NB, grp = tid / NB;
   // U12 block of a panel (first TU columns of this thread), loaded at the
@@ -818,16 +831,18 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
     // next (lower) panel's U11^{-1}, four entries per thread (panel 0
     // reloads its own); named scalars, since a small array here was left in
     // scratch memory by the compiler
-    static_assert(NB * NB == 4 * 256, "four inverse entries per thread");
     const cplx<T>* Ugn = Dinv + f.dinv_off + (long long)(b > 0 ? b - 1 : 0) * 2 * NB * NB + NB * NB;
-    const cplx<T> uin0 = Ugn[tid], uin1 = Ugn[tid + 256], uin2 = Ugn[tid + 512], uin3 = Ugn[tid + 768];
+    const cplx<T> uin0 = Ugn[tid], uin1 = Ugn[tid + TPB];
+    const cplx<T> uin2 = IPT > 2 ? Ugn[tid + 2 * TPB] : uin0, uin3 = IPT > 2 ? Ugn[tid + 3 * TPB] : uin0;
     const int gi = id[k0 + min(tid / 8, kb - 1)];  // grid index of row tid / 8, for writing x
     load_u(b, u);
     __syncthreads();  // x(k1:m) of the previous panel is in place; Ui[cur ^ 1] is free
     Ui[cur ^ 1][tid % NB][tid / NB] = uin0;
-    Ui[cur ^ 1][tid % NB][tid / NB + 8] = uin1;
-    Ui[cur ^ 1][tid % NB][tid / NB + 16] = uin2;
-    Ui[cur ^ 1][tid % NB][tid / NB + 24] = uin3;
+    Ui[cur ^ 1][tid % NB][tid / NB + TPB / NB] = uin1;
+    if constexpr (IPT > 2) {
+      Ui[cur ^ 1][tid % NB][tid / NB + 2 * TPB / NB] = uin2;
+      Ui[cur ^ 1][tid % NB][tid / NB + 3 * TPB / NB] = uin3;
+    }
     cplx<T> acc[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
@@ -850,14 +865,14 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
 #pragma unroll
     for (int k = 0; k < NR; ++k) part[grp][k][j] = acc[k];
     __syncthreads();
-    for (int e = tid; e < NR * NB; e += 256) {
+    for (int e = tid; e < NR * NB; e += TPB) {
       int jj = e % NB, k = e / NB;
       cplx<T> s = part[0][k][jj];
       for (int g = 1; g < G; ++g) s = cadd(s, part[g][k][jj]);
       rb[k][jj] = (k < nr && jj < kb) ? csub(vp[k * vs + k0 + jj], s) : mk<T>(0, 0);
     }
     __syncthreads();
-    {
+    if (tid < 256) {  // the 32-row product uses the first four waves
       cplx<T> xs[NR];
       tri_apply<T, NR>(Ui[cur], rb, tid, xs);
       const int i = tid / 8;
@@ -875,32 +890,74 @@ __global__ void __launch_bounds__(256) bwd_kernel(const cplx<T>* __restrict__ Fb
   for (int b = nblk - 1; b >= 0; --b) panel(b, ucol);
 }
 
+inline bool wide_level(const Plan& plan, int l) { return plan.level_maxpq[l] > 256 + NB; }
+
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one workgroup on gfx950
+
+// static LDS of the sweep kernels (inverse blocks, panel vectors, partial sums)
+template <typename T, int NR, int TPB>
+constexpr size_t fwd_static_lds() {
+  return sizeof(cplx<T>) * (2 * NB * (NB + 1) + 2 * NR * NB);
+}
+template <typename T, int NR, int TPB>
+constexpr size_t bwd_static_lds() {
+  return sizeof(cplx<T>) * (2 * NB * (NB + 1) + (TPB / NB) * NR * NB + NR * NB);
+}
+
+// the front vectors go to LDS when they fit beside the static arrays
+inline bool vec_in_lds(size_t vb, size_t stat) { return vb <= kVecLds && vb + stat <= kLdsBytes; }
+
+// Levels whose fronts have more than 256 rows beside the first panel get
+// 512-thread workgroups (a thread per row or column, all in flight at the
+// panel start).  The choice depends on the level only, never on the number
+// of right-hand sides, so a right-hand side's result does not depend on the
+// group it is solved in.
+template <typename T, int NR, int TPB>
+void sweep_fwd(const MfDev<T>& mf, const Plan& plan, int l, int groups, int nrhs, const cplx<T>* z, cplx<T>* vbuf,
+               hipStream_t st) {
+  const int first = plan.level_ptr[l];
+  const int cnt = plan.level_ptr[l + 1] - first;
+  const size_t vb = (size_t)plan.level_maxpq[l] * NR * sizeof(cplx<T>);
+  constexpr size_t stat = fwd_static_lds<T, NR, TPB>();
+  static_assert(stat <= kLdsBytes, "sweep arrays exceed the LDS");
+  if (vec_in_lds(vb, stat))
+    LSP_LAUNCH("fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NR, true, TPB>), dim3(cnt, groups), dim3(TPB), vb, st,
+               mf.F, mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N,
+               (long long)plan.sum_pq);
+  else
+    LSP_LAUNCH("fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NR, false, TPB>), dim3(cnt, groups), dim3(TPB), 0, st,
+               mf.F, mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N,
+               (long long)plan.sum_pq);
+}
+
+template <typename T, int NR, int TPB>
+void sweep_bwd(const MfDev<T>& mf, const Plan& plan, int l, int groups, int nrhs, cplx<T>* x, cplx<T>* vbuf,
+               hipStream_t st) {
+  const int first = plan.level_ptr[l];
+  const int cnt = plan.level_ptr[l + 1] - first;
+  const size_t vb = (size_t)plan.level_maxpq[l] * NR * sizeof(cplx<T>);
+  constexpr size_t stat = bwd_static_lds<T, NR, TPB>();
+  static_assert(stat <= kLdsBytes, "sweep arrays exceed the LDS");
+  if (vec_in_lds(vb, stat))
+    LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR, true, TPB>), dim3(cnt, groups), dim3(TPB), vb, st,
+               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq);
+  else
+    LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR, false, TPB>), dim3(cnt, groups), dim3(TPB), 0, st,
+               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq);
+}
+
+
 template <typename T, int NR>
 void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
                   hipStream_t st) {
-  const long long vstride = plan.sum_pq;
   const int groups = (nrhs + NR - 1) / NR;
   for (int l = 0; l < plan.nlevels; ++l) {
-    const int first = plan.level_ptr[l];
-    const int cnt = plan.level_ptr[l + 1] - first;
-    const size_t vb = (size_t)plan.level_maxpq[l] * NR * sizeof(cplx<T>);
-    if (vb <= kVecLds)
-      LSP_LAUNCH("fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NR, true>), dim3(cnt, groups), dim3(256), vb, st, mf.F,
-                 mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N, vstride);
-    else
-      LSP_LAUNCH("fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NR, false>), dim3(cnt, groups), dim3(256), 0, st, mf.F,
-                 mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N, vstride);
+    if (wide_level(plan, l)) sweep_fwd<T, NR, 512>(mf, plan, l, groups, nrhs, z, vbuf, st);
+    else sweep_fwd<T, NR, 256>(mf, plan, l, groups, nrhs, z, vbuf, st);
   }
   for (int l = plan.nlevels - 1; l >= 0; --l) {
-    const int first = plan.level_ptr[l];
-    const int cnt = plan.level_ptr[l + 1] - first;
-    const size_t vb = (size_t)plan.level_maxpq[l] * NR * sizeof(cplx<T>);
-    if (vb <= kVecLds)
-      LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR, true>), dim3(cnt, groups), dim3(256), vb, st, mf.F,
-                 mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, vstride);
-    else
-      LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR, false>), dim3(cnt, groups), dim3(256), 0, st, mf.F,
-                 mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, vstride);
+    if (wide_level(plan, l)) sweep_bwd<T, NR, 512>(mf, plan, l, groups, nrhs, x, vbuf, st);
+    else sweep_bwd<T, NR, 256>(mf, plan, l, groups, nrhs, x, vbuf, st);
   }
 }
 
