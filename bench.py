@@ -140,7 +140,9 @@ def kernel_model(name, st, w, nrhs):
         # and the N-vector it produces; spread over nlevels launches
         per_app = st["sweep_entries"] * esz + 2 * N * esz * nrhs
         return "hbm", per_app / nlev, "GB/s"
-    if base == "gemm_update":
+    if base in ("gemm_update", "update_lu"):
+        # update_lu: trailing update fused with the next panel's diagonal
+        # block factorisation (one extra workgroup, its work not counted)
         return "mfma", None, "TFLOP/s"
     if base == "diag_lu":
         # per 32 x 32 block: complex LU (sum_j (31-j)^2 multiply-adds) and the
@@ -193,12 +195,15 @@ def measure_roofline(lsp, torch, w, m_dev, u_dev, prec):
         avg_s = ms / cnt / 1e3
         fp64 = "[c64]" not in name
         if bound == "mfma":
-            flops = st["update_flops"]          # all launches of one factorisation
+            # all launches of one factorisation, split between the plain and
+            # the fused (lookahead) update launches
+            fused = st["fused_update_flops"]
+            flops = fused if name.startswith("update_lu") else st["update_flops"] - fused
             achieved = flops / (ms / 1e3) / 1e12
             peak = 78.6 if fp64 else 157.3      # dense FP64 / FP32 matrix cores
             amount = flops / cnt
         elif bound == "alu":
-            flops = DIAG_FLOPS_PER_BLOCK * st["panel_blocks"]
+            flops = DIAG_FLOPS_PER_BLOCK * (st["panel_blocks"] - st["fused_blocks"])
             achieved = flops / (ms / 1e3) / 1e12
             peak = 78.6 if fp64 else 157.3      # FP64 / FP32 vector ALUs
             amount = flops / cnt

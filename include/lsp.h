@@ -99,6 +99,11 @@ typedef struct {
                                  F22 -= L21 U12 (the MFMA part of the factor) */
   double panel_blocks;        /* diagonal-block factorisations per lsp_factor:
                                  the sum over fronts of ceil(p / panel) */
+  double fused_blocks;        /* of those, the ones factored inside the
+                                 previous panel's trailing-update launch
+                                 (lookahead; depends on the tile table and
+                                 the plan's precision) */
+  double fused_update_flops;  /* of update_flops, the part in those launches */
 } lsp_plan_stats;
 
 typedef struct lsp_plan lsp_plan;        /* opaque; host-side, plus one device copy of

@@ -114,6 +114,17 @@ struct DiagLds {
   cplx<T> m[2][NB][NB + 1];
 };
 
+// The block factorisation runs in one wave.  LDS operations of a wave are
+// performed in issue order, so a wave-scope fence (which only keeps the
+// compiler from moving memory operations across it) makes one lane's LDS
+// writes visible to the other lanes' later reads.
+struct WaveSync {
+  __device__ void operator()() const {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+};
+
 // v[c] -= coef * opnd[c * STRIDE] for c = C0 .. NB-1, operands read from LDS
 // eight at a time with one chunk of lookahead (bounds the registers held by
 // loads in flight); STORE also writes each updated v[c] back to dst[c].
@@ -188,6 +199,7 @@ __device__ __forceinline__ void lds_axpy_h(cplx<T> (&v)[NB / 2], const cplx<T> c
 template <typename T, int J>
 __device__ __forceinline__ void diag_elim(cplx<T> (&rowh)[NB / 2], int& rlog, cplx<T>& myinv, T& dmin, T& dmax,
                                           DiagLds<T>& S, const int r, const int h, const int kb) {
+  const WaveSync sync;
   if constexpr (J < NB) {
     constexpr int hJ = J & 1, iJ = J >> 1;
     const cplx<T> own = rowh[iJ];
@@ -198,7 +210,7 @@ __device__ __forceinline__ void diag_elim(cplx<T> (&rowh)[NB / 2], int& rlog, cp
     other.x = __shfl_xor(own.x, 32, 64);
     other.y = __shfl_xor(own.y, 32, 64);
     const cplx<T> aJ = h == hJ ? own : other;
-    __syncthreads();  // rows written by the previous step are visible
+    sync();  // rows written by the previous step are visible
     const cplx<T> d = S.m[0][pl][J];
     const T den = d.x * d.x + d.y * d.y;
     const T rden = den > (T)0 ? (T)1 / den : (T)0;
@@ -235,33 +247,24 @@ __device__ __forceinline__ void diag_subst(cplx<T> (&x)[NB], const cplx<T>* M) {
   }
 }
 
+// Pivoted LU of the diagonal block of panel k0 and the inverses of its
+// factors, in one wave (lane = 0..63): on entry S.m[0][r][c] and rowh (lane
+// (h, r) holds columns 2i + h of row r) hold the updated block, padded with
+// the identity beyond kb.  Writes the inverses to Dinv, the row order to
+// perm and the pivot ratio into *pivstat.
 template <typename T>
-__global__ void __launch_bounds__(64) diag_lu_kernel(cplx<T>* __restrict__ Fbuf, cplx<T>* __restrict__ Dinv,
-                                                     const FrontDev* __restrict__ fr, int* __restrict__ perm,
-                                                     double* __restrict__ pivstat, int first, int k0) {
-  static_assert(NB == 32, "lane layout assumes 32-wide panels");
-  __shared__ DiagLds<T> S;
-  const FrontDev f = fr[first + blockIdx.x];
-  if (f.p <= k0) return;
-  const int kb = min(NB, f.p - k0);
-  const int m = f.p + f.q;
-  cplx<T>* F = Fbuf + f.f_off;
-  const int lane = threadIdx.x;
+__device__ __forceinline__ void diag_factor_block(DiagLds<T>& S, cplx<T> (&rowh)[NB / 2], const FrontDev& f,
+                                                  const int k0, const int kb, const int lane,
+                                                  cplx<T>* __restrict__ Dinv, int* __restrict__ perm,
+                                                  double* __restrict__ pivstat) {
+  const WaveSync sync;
   const int r = lane & (NB - 1), h = lane / NB;
-  cplx<T> rowh[NB / 2];
-#pragma unroll
-  for (int i = 0; i < NB / 2; ++i) {
-    const int c = 2 * i + h;
-    const cplx<T> v = F[(k0 + min(r, kb - 1)) + (long long)(k0 + min(c, kb - 1)) * m];
-    rowh[i] = r < kb && c < kb ? v : mk<T>(r == c ? 1 : 0, 0);
-    S.m[0][r][c] = rowh[i];
-  }
   int rlog = -1;
   cplx<T> myinv = mk<T>(0, 0);
   T dmin = (T)INFINITY, dmax = (T)0;
   diag_elim<T, 0>(rowh, rlog, myinv, dmin, dmax, S, r, h, kb);
   rlog &= NB - 1;  // every row is chosen exactly once, so this is already in range
-  __syncthreads();
+  sync();
 #pragma unroll
   for (int i = 0; i < NB / 2; ++i) {
     const int c = 2 * i + h;
@@ -274,21 +277,21 @@ __global__ void __launch_bounds__(64) diag_lu_kernel(cplx<T>* __restrict__ Fbuf,
     if (rlog < kb) perm[f.piv_off + k0 + rlog] = k0 + r;
     if (lane == 0) {
       const double ratio = dmax > (T)0 ? (double)(dmin / dmax) : 0.0;
-      pivstat[first + blockIdx.x] = fmin(pivstat[first + blockIdx.x], ratio);
+      *pivstat = fmin(*pivstat, ratio);
     }
   }
-  __syncthreads();
+  sync();
   // forward substitution M x = e_r with M = L (unit diagonal stored as 1)
   // or the reversed U (reciprocal pivots stored on its diagonal)
   cplx<T> x[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) x[i] = mk<T>(r == i ? 1 : 0, 0);
   diag_subst<T, 0>(x, &S.m[lane / NB][0][0]);
-  __syncthreads();
+  sync();
   // stage column r of each result at [r][i] (L^{-1}(i, r); reversed U^{-1})
 #pragma unroll
   for (int i = 0; i < NB; ++i) S.m[lane / NB][r][i] = x[i];
-  __syncthreads();
+  sync();
   cplx<T>* Li = Dinv + f.dinv_off + (long long)(k0 / NB) * 2 * NB * NB;
 #pragma unroll 4
   for (int e = lane; e < NB * NB; e += 64) {
@@ -297,6 +300,32 @@ __global__ void __launch_bounds__(64) diag_lu_kernel(cplx<T>* __restrict__ Fbuf,
     Li[e] = in ? S.m[0][b][a] : mk<T>(0, 0);
     Li[NB * NB + e] = in ? S.m[1][NB - 1 - b][NB - 1 - a] : mk<T>(0, 0);
   }
+}
+
+// First panel of a level (later panels are factored inside the previous
+// panel's trailing update, gemm_update_kernel with FUSE).
+template <typename T>
+__global__ void __launch_bounds__(64) diag_lu_kernel(cplx<T>* __restrict__ Fbuf, cplx<T>* __restrict__ Dinv,
+                                                     const FrontDev* __restrict__ fr, int* __restrict__ perm,
+                                                     double* __restrict__ pivstat, int first, int k0) {
+  static_assert(NB == 32, "lane layout assumes 32-wide panels");
+  __shared__ DiagLds<T> S;
+  const FrontDev f = fr[first + blockIdx.x];
+  if (f.p <= k0) return;
+  const int kb = min(NB, f.p - k0);
+  const int m = f.p + f.q;
+  const cplx<T>* F = Fbuf + f.f_off;
+  const int lane = threadIdx.x;
+  const int r = lane & (NB - 1), h = lane / NB;
+  cplx<T> rowh[NB / 2];
+#pragma unroll
+  for (int i = 0; i < NB / 2; ++i) {
+    const int c = 2 * i + h;
+    const cplx<T> v = F[(k0 + min(r, kb - 1)) + (long long)(k0 + min(c, kb - 1)) * m];
+    rowh[i] = r < kb && c < kb ? v : mk<T>(r == c ? 1 : 0, 0);
+    S.m[0][r][c] = rowh[i];
+  }
+  diag_factor_block<T>(S, rowh, f, k0, kb, lane, Dinv, perm, pivstat + first + blockIdx.x);
 }
 
 // Runs use(i, load(i)) for i = 0 .. N-1 (N and i compile-time after
@@ -447,21 +476,100 @@ template <> struct Mfma<float> {
 };
 
 template <typename T, int TM>
+struct GemmLds {
+  T Ar[NB][TM], Ai[NB][TM], Br[NB][TM + 1], Bi[NB][TM + 1];
+};
+
+// Lookahead (FUSE): the next panel's diagonal block depends only on this
+// update of its own 32 x 32 entries, so workgroup (0, 0) of each front
+// applies that part of the update itself (block = F - L21 U12 over the
+// block's rows and columns, a sequential 32-term sum per entry) and then
+// factors the block in its first wave, while the other workgroups update
+// the rest of the trailing matrix on MFMA, leaving that block alone (no
+// later step reads the diagonal blocks of F: the factorisation keeps only
+// their inverses and the row order).
+template <typename T>
+__device__ __forceinline__ void update_and_factor_next(unsigned char* raw, const FrontDev& f, const cplx<T>* F,
+                                                       const int k0, const int k1, const int m,
+                                                       cplx<T>* __restrict__ Dinv, int* __restrict__ perm,
+                                                       double* __restrict__ pivstat) {
+  DiagLds<T>& S = *reinterpret_cast<DiagLds<T>*>(raw);
+  const int kb = k1 - k0;
+  const int kbn = min(NB, f.p - k1);  // > 0: the front has a next panel
+  const int tid = threadIdx.x;
+  cplx<T> la[4], ub[4], ov[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u, r = e % NB, c = e / NB;
+    const cplx<T> a = F[(k1 + min(r, kbn - 1)) + (long long)(k0 + min(c, kb - 1)) * m];   // L21(r, c)
+    const cplx<T> b = F[(k0 + min(r, kb - 1)) + (long long)(k1 + min(c, kbn - 1)) * m];   // U12(r, c)
+    const cplx<T> o = F[(k1 + min(r, kbn - 1)) + (long long)(k1 + min(c, kbn - 1)) * m];  // block (r, c)
+    la[u] = r < kbn && c < kb ? a : mk<T>(0, 0);
+    ub[u] = r < kb && c < kbn ? b : mk<T>(0, 0);
+    ov[u] = r < kbn && c < kbn ? o : mk<T>(r == c ? 1 : 0, 0);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u, r = e % NB, c = e / NB;
+    S.m[0][r][c] = la[u];
+    S.m[1][r][c] = ub[u];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u, r = e % NB, c = e / NB;
+#pragma unroll 8
+    for (int kk = 0; kk < NB; ++kk) ov[u] = cfms(ov[u], S.m[0][r][kk], S.m[1][kk][c]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u;
+    S.m[0][e % NB][e / NB] = ov[u];
+  }
+  __syncthreads();
+  if (tid >= 64) return;  // the factorisation is one wave's work
+  const int r = tid & (NB - 1), h = tid / NB;
+  cplx<T> rowh[NB / 2];
+#pragma unroll
+  for (int i = 0; i < NB / 2; ++i) rowh[i] = S.m[0][r][2 * i + h];
+  diag_factor_block<T>(S, rowh, f, k1, kbn, tid, Dinv, perm, pivstat);
+}
+
+template <typename T, int TM, bool FUSE>
 __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ Fbuf, const FrontDev* __restrict__ fr,
-                                                          int first, int k0) {
+                                                          int first, int k0, cplx<T>* __restrict__ Dinv,
+                                                          int* __restrict__ perm, double* __restrict__ pivstat) {
   // TM x TM output tile, 4 waves in a 2x2 arrangement, each wave (TM/2)^2 as
-  // BW x BW MFMA 16x16 blocks.
+  // BW x BW MFMA 16x16 blocks.  With FUSE, block row 0 is the lookahead
+  // factorisation of the next diagonal block and the tiles start at row 1.
   constexpr int BW = TM / 32;
-  __shared__ T Ar[NB][TM], Ai[NB][TM], Br[NB][TM + 1], Bi[NB][TM + 1];
+  constexpr size_t kRaw = sizeof(GemmLds<T, TM>) > sizeof(DiagLds<T>) ? sizeof(GemmLds<T, TM>) : sizeof(DiagLds<T>);
+  __shared__ __align__(16) unsigned char raw[kRaw];
+  GemmLds<T, TM>& G = *reinterpret_cast<GemmLds<T, TM>*>(raw);
+  auto& Ar = G.Ar;
+  auto& Ai = G.Ai;
+  auto& Br = G.Br;
+  auto& Bi = G.Bi;
   const FrontDev f = fr[first + blockIdx.z];
   if (f.p <= k0) return;
   const int kb = min(NB, f.p - k0);
   const int k1 = k0 + kb;
   const int m = f.p + f.q;
   const int rem = m - k1;
-  const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TM;
-  if (row0 >= rem || col0 >= rem) return;
   cplx<T>* F = Fbuf + f.f_off;
+  const int brow = FUSE ? (int)blockIdx.y - 1 : (int)blockIdx.y;
+  if constexpr (FUSE) {
+    if (brow < 0) {
+      if (blockIdx.x == 0 && f.p > k1)
+        update_and_factor_next<T>(raw, f, F, k0, k1, m, Dinv, perm, pivstat + first + blockIdx.z);
+      return;
+    }
+  }
+  // entries of the next diagonal block, left to the lookahead workgroup
+  const int skip = FUSE ? max(0, min(NB, f.p - k1)) : 0;
+  const int row0 = brow * TM, col0 = blockIdx.x * TM;
+  if (row0 >= rem || col0 >= rem) return;
   const int tid = threadIdx.x;
   const int kpad = (kb + 3) & ~3;
   // both operand tiles are loaded before the first LDS store (clamped
@@ -527,7 +635,7 @@ __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ 
       for (int v = 0; v < 4; ++v) {
         const int col = col0 + wc + 16 * j + li;
         const int row = row0 + wr + 16 * i + Mfma<T>::row(lk, v);
-        if (col < rem && row < rem) {
+        if (col < rem && row < rem && !(row < skip && col < skip)) {
           cplx<T> c = cv[j][v];
           c.x -= accr[i][j][v];
           c.y -= acci[i][j][v];
@@ -963,6 +1071,39 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
 
 }  // namespace
 
+// Trailing update of panel k0 over tiles of TM; with FUSE (see fuse_next)
+// also the next panel's diagonal-block factorisation (one extra block row).
+template <typename T, int TM>
+void update_launch(const MfDev<T>& mf, bool fuse, int rem, int cnt, int first, int k0, hipStream_t st) {
+  const int gt = (rem + TM - 1) / TM;
+  if (fuse)
+    LSP_LAUNCH("update_lu", (int)sizeof(cplx<T>), (gemm_update_kernel<T, TM, true>), dim3(gt, gt + 1, cnt), dim3(256),
+               0, st, mf.F, mf.fronts, first, k0, mf.Dinv, mf.perm, mf.pivstat);
+  else
+    LSP_LAUNCH("gemm_update", (int)sizeof(cplx<T>), (gemm_update_kernel<T, TM, false>), dim3(gt, gt, cnt), dim3(256),
+               0, st, mf.F, mf.fronts, first, k0, mf.Dinv, mf.perm, mf.pivstat);
+}
+
+// trailing-update tile of level l (complex128 128-wide tiles would need more
+// than 256 VGPRs; 64 there)
+static int update_tile(const Plan& plan, int l, bool fp64) {
+  return (fp64 && plan.level_tile[l] == 128) ? 64 : plan.level_tile[l];
+}
+
+// Whether panel k0's trailing update of level l also factors the next
+// panel's diagonal block: when some front has a next panel and the update
+// has few enough tiles that every workgroup of the launch is resident at
+// once (the fused kernel carries the factorisation's register count, so its
+// tiles run at low occupancy).
+static bool fuse_next(const Plan& plan, int l, int k0, bool fp64) {
+  const int cnt = plan.level_ptr[l + 1] - plan.level_ptr[l];
+  if (k0 + NB >= plan.level_maxp[l]) return false;
+  const int rem = plan.level_maxpq[l] - k0 - 1;  // > NB when a next panel exists
+  const int tile = update_tile(plan, l, fp64);
+  const long long gt = (rem + tile - 1) / tile;
+  return cnt * gt * gt <= 256;
+}
+
 template <typename T>
 void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
   for (int l = 0; l < plan.nlevels; ++l) {
@@ -974,28 +1115,41 @@ void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
     int gx = (int)std::min<long long>((mm + 255) / 256, 4096);  // one element per thread up to 1M-entry fronts
     LSP_LAUNCH("assemble_front", (int)sizeof(cplx<T>), assemble_front_kernel<T>, dim3(gx, cnt), dim3(256), 0, st, mf.F, mf.fronts, mf.idx, mf.cpos,
                        mf.Mval, first, plan.n, plan.d);
+    const bool fp64 = sizeof(T) == 8;
+    bool factored = false;  // panel k0's diagonal block done by the previous update
     for (int k0 = 0; k0 < maxp; k0 += NB) {
-      LSP_LAUNCH("diag_lu", (int)sizeof(cplx<T>), diag_lu_kernel<T>, dim3(cnt), dim3(64), 0, st, mf.F, mf.Dinv,
-                 mf.fronts, mf.perm, mf.pivstat, first, k0);
-      int rem = maxm - k0 - 1;
+      if (!factored)
+        LSP_LAUNCH("diag_lu", (int)sizeof(cplx<T>), diag_lu_kernel<T>, dim3(cnt), dim3(64), 0, st, mf.F, mf.Dinv,
+                   mf.fronts, mf.perm, mf.pivstat, first, k0);
+      const int rem = maxm - k0 - 1;
       if (rem <= 0) continue;
-      int tiles = (rem + 63) / 64;
-      LSP_LAUNCH("panel_trsm", (int)sizeof(cplx<T>), panel_trsm_kernel<T>, dim3(tiles, cnt, 2), dim3(256), 0, st, mf.F, mf.Dinv, mf.fronts,
-                         mf.perm, first, k0);
-      // complex128 128-wide tiles would need more than 256 VGPRs; use 64 there
-      const int tile = (sizeof(T) == 8 && plan.level_tile[l] == 128) ? 64 : plan.level_tile[l];
-      const int gt = (rem + tile - 1) / tile;
-      if (tile == 32)
-        LSP_LAUNCH("gemm_update", (int)sizeof(cplx<T>), (gemm_update_kernel<T, 32>), dim3(gt, gt, cnt), dim3(256), 0, st,
-                   mf.F, mf.fronts, first, k0);
-      else if (tile == 128)
-        LSP_LAUNCH("gemm_update", (int)sizeof(cplx<T>), (gemm_update_kernel<T, 128>), dim3(gt, gt, cnt), dim3(256), 0, st,
-                   mf.F, mf.fronts, first, k0);
-      else
-        LSP_LAUNCH("gemm_update", (int)sizeof(cplx<T>), (gemm_update_kernel<T, 64>), dim3(gt, gt, cnt), dim3(256), 0, st,
-                   mf.F, mf.fronts, first, k0);
+      const int tiles = (rem + 63) / 64;
+      LSP_LAUNCH("panel_trsm", (int)sizeof(cplx<T>), panel_trsm_kernel<T>, dim3(tiles, cnt, 2), dim3(256), 0, st, mf.F,
+                 mf.Dinv, mf.fronts, mf.perm, first, k0);
+      const int tile = update_tile(plan, l, fp64);
+      factored = fuse_next(plan, l, k0, fp64);
+      if (tile == 32) update_launch<T, 32>(mf, factored, rem, cnt, first, k0, st);
+      else if (tile == 128) update_launch<T, 128>(mf, factored, rem, cnt, first, k0, st);
+      else update_launch<T, 64>(mf, factored, rem, cnt, first, k0, st);
     }
   }
+}
+
+FactorSchedule factor_schedule(const Plan& plan, bool fp64) {
+  FactorSchedule s;
+  for (int l = 0; l < plan.nlevels; ++l)
+    for (int k0 = 0; k0 < plan.level_maxp[l]; k0 += NB) {
+      if (!fuse_next(plan, l, k0, fp64)) continue;
+      for (int i = plan.level_ptr[l]; i < plan.level_ptr[l + 1]; ++i) {
+        const FrontDev& f = plan.fronts[i];
+        if (f.p <= k0) continue;
+        const int kb = std::min(NB, f.p - k0);
+        const double rem = (double)(f.p + f.q - k0 - kb);
+        s.fused_update_flops += 8.0 * rem * rem * kb;
+        if (f.p > k0 + kb) s.fused_blocks += 1.0;
+      }
+    }
+  return s;
 }
 
 template <typename T>

@@ -70,6 +70,15 @@ struct MfDev {
 
 template <typename T>
 void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st);
+
+// Of one factorisation: the diagonal blocks factored inside the previous
+// panel's trailing-update launch (lookahead), and the trailing-update flops
+// of those fused launches.
+struct FactorSchedule {
+  double fused_blocks = 0.0;
+  double fused_update_flops = 0.0;
+};
+FactorSchedule factor_schedule(const Plan& plan, bool fp64);
 template <typename T>
 void mf_solve(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
               hipStream_t st);

@@ -493,6 +493,9 @@ lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* s) {
   s->sweep_entries = P.sweep_entries;
   s->update_flops = P.update_flops;
   s->panel_blocks = P.panel_blocks;
+  const FactorSchedule fs = factor_schedule(P, P.opts.precision == LSP_FP64);
+  s->fused_blocks = fs.fused_blocks;
+  s->fused_update_flops = fs.fused_update_flops;
   return LSP_OK;
 }
 

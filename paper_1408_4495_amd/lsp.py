@@ -42,7 +42,8 @@ class PlanStats(ctypes.Structure):
                 ("max_pivots", ctypes.c_int), ("factor_entries", ctypes.c_double),
                 ("front_entries", ctypes.c_double), ("factor_flops", ctypes.c_double),
                 ("sweep_entries", ctypes.c_double), ("update_flops", ctypes.c_double),
-                ("panel_blocks", ctypes.c_double)]
+                ("panel_blocks", ctypes.c_double),
+                ("fused_blocks", ctypes.c_double), ("fused_update_flops", ctypes.c_double)]
 
 
 class LspError(RuntimeError):

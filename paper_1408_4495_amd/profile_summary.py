@@ -19,7 +19,8 @@ import sys
 
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 SOURCE = {"fwd": "frontal.hip", "bwd": "frontal.hip", "diag_lu": "frontal.hip", "panel_trsm": "frontal.hip",
-          "gemm_update": "frontal.hip", "assemble_front": "frontal.hip", "fft_lines": "fft.hip",
+          "gemm_update": "frontal.hip", "update_lu": "frontal.hip", "assemble_front": "frontal.hip",
+          "fft_lines": "fft.hip",
           "gram": "stencil.hip", "gram_reduce": "stencil.hip", "eigen": "stencil.hip", "applyQ": "stencil.hip",
           "dots_partial": "krylov.hip", "dots_final": "krylov.hip", "axpy": "krylov.hip"}
 FFT_MODE = {"0": "fft_axis", "1": "fft_first", "2": "fft_conv", "3": "fft_last"}
@@ -40,6 +41,8 @@ def registry_key(name):
     args = [a.strip() for a in targs.split(",")] if targs else []
     if base == "fft_lines" and len(args) == 3:
         base = FFT_MODE.get(args[2], base)
+    if base == "gemm_update" and args and args[-1] == "true":
+        base = "update_lu"  # fused with the next diagonal-block factorisation
     prec = ""
     if args:
         if re.match(r"(HIP_vector_type<)?float\b", args[0]):
