@@ -175,8 +175,13 @@ lsp_status lsp_factor(lsp_problem* problem);
  * Krylov process per right-hand side run in lockstep, each identical to
  * its solo run.  rhs_dev: [nrhs][N] complex128 (u_I or g per rhs_kind);
  * u_dev: [nrhs][N] complex128 output; ws_dev: >= solve_bytes for nrhs;
- * info_host: [nrhs] (may be NULL).  Synchronises the stream.
- * Errors: LSP_ERR_STATE (not factored), LSP_ERR_ARG, LSP_ERR_NOCONV. */
+ * info_host: [nrhs] (may be NULL).  Synchronises the stream: the stopping
+ * decisions are taken on the device, which reports the number of right-hand
+ * sides still iterating into pinned host memory (allocated per problem on
+ * the first solve, and again when nrhs grows); the calling thread polls it
+ * after each Arnoldi step and cycle (a busy wait, no device-to-host copy).
+ * Errors: LSP_ERR_STATE (not factored), LSP_ERR_ARG, LSP_ERR_NOCONV,
+ * LSP_ERR_HIP (also when the stream ends without the report). */
 lsp_status lsp_solve(lsp_problem* problem, int nrhs, int rhs_kind,
                      const void* rhs_dev, void* u_dev, void* ws_dev,
                      size_t ws_bytes, lsp_rhs_info* info_host);

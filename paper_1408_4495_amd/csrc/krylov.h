@@ -8,7 +8,38 @@ namespace lsp {
 
 constexpr int kMaxVec = 32;  // restart length limit (basis vectors per cycle)
 constexpr int kScal = 8;     // per right-hand-side scalars
-enum { S_NORM = 0, S_INV = 1, S_EST = 2, S_DEN = 3 };
+// S_GNORM: ||g||; S_BETA: latest true residual norm; S_TARGET: this cycle's
+// stopping level of the GMRES estimate
+enum { S_NORM = 0, S_INV = 1, S_EST = 2, S_DEN = 3, S_GNORM = 4, S_BETA = 5, S_TARGET = 6 };
+
+// GMRES control decided on the device, reported to the host through pinned,
+// coherent host memory: after writing the per-right-hand-side fields and the
+// number of right-hand sides still iterating, a kernel stores `tag` (release,
+// system scope); the host waits for the tag it expects.
+struct HostCtl {
+  unsigned tag;
+  int nact;
+  int pad[2];
+};
+struct CtlView {       // device-visible pointers into one pinned allocation
+  HostCtl* hdr;
+  int* iters;          // [nrhs] Arnoldi steps taken
+  double* est;         // [nrhs] latest GMRES residual estimate
+  double* beta;        // [nrhs] latest true residual norm
+  double* gnorm;       // [nrhs] ||g||
+};
+struct GmresState {    // device arrays of the solve workspace
+  double* scal;        // [nrhs][kScal]
+  int* active;         // [nrhs] iterating in this cycle
+  int* ksz;            // [nrhs] Krylov size of this cycle
+  int* iters;          // [nrhs] Arnoldi steps over all cycles
+  int* done;           // [nrhs] converged
+};
+struct GmresParams {
+  double tol;          // relative true-residual tolerance
+  double eta;          // cycle stops when the estimate falls below eta * beta
+  int max_iters;
+};
 
 int dot_blocks(long long N);
 void k_dots(const double2* V, const double2* w, double2* partial, double2* h, double2* H, double* scal, int nvec,
@@ -23,8 +54,16 @@ void k_arnoldi_orth(const double2* V, double2* w, double2* pA, double2* pB, doub
                     double2* vnext, int k, int restart, long long N, int nrhs, const int* active, hipStream_t st);
 void k_scale(double2* y, const double2* x, const double* scal, long long N, int nrhs, const int* active,
              hipStream_t st);
-void k_givens(double2* H, double2* cs, double2* sn, double2* gam, double* scal, int k, int restart, int nrhs,
-              const int* active, hipStream_t st);
+// Givens update of column k and the stopping decision of step k: a right-
+// hand side stops when its estimate is not above S_TARGET, at max_iters, or
+// on a zero column; reports the number still iterating under `tag`.
+void k_givens(double2* H, double2* cs, double2* sn, double2* gam, int k, int restart, int nrhs, const GmresState& gs,
+              const GmresParams& gp, const CtlView& host, unsigned tag, hipStream_t st);
+// Start of the solve (cycle_end false: S_NORM holds ||g||) or end of a cycle
+// (S_NORM holds the true residual norm): convergence, then the next cycle's
+// active set, Krylov sizes and targets; reports under `tag`.
+void k_gmres_control(bool cycle_end, int nrhs, const GmresState& gs, const GmresParams& gp, const CtlView& host,
+                     unsigned tag, hipStream_t st);
 void k_backsolve_update(const double2* H, const double2* gam, double2* y, const int* ksz, double2* x, const double2* Z,
                         int restart, long long N, int nrhs, hipStream_t st);
 void k_sub(double2* r, const double2* g, const double2* t, long long count, hipStream_t st);

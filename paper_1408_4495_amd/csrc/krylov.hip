@@ -272,12 +272,25 @@ __global__ void scale_kernel(double2* __restrict__ y, const double2* __restrict_
     y[(long long)r * N + e] = cscale(x[(long long)r * N + e], s);
 }
 
-// Givens update of column k, one thread per right-hand side.
-__global__ void givens_kernel(double2* __restrict__ H, double2* __restrict__ cs, double2* __restrict__ sn,
-                              double2* __restrict__ gam, double* __restrict__ scal, int k, int restart, int nrhs,
-                              const int* __restrict__ active) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs || (active && !active[r])) return;
+// Counts the right-hand sides still iterating over the block, then stores
+// the count and the tag into the host control block (after this thread's
+// own host writes: each thread fences them at system scope first).
+__device__ void report(int mine, const CtlView& host, unsigned tag) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __threadfence_system();
+  __syncthreads();
+  if (mine) atomicAdd(&cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&host.hdr->nact, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&host.hdr->tag, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+// Givens update of column k for one right-hand side.
+__device__ void givens_one(double2* __restrict__ H, double2* __restrict__ cs, double2* __restrict__ sn,
+                           double2* __restrict__ gam, double* __restrict__ scal, int k, int restart, int r) {
   double2* Hc = H + (long long)r * (restart + 1) * restart + (restart + 1) * k;
   double2* c = cs + (long long)r * restart;
   double2* s = sn + (long long)r * restart;
@@ -307,6 +320,60 @@ __global__ void givens_kernel(double2* __restrict__ H, double2* __restrict__ cs,
   double2 gn = g[k + 1];
   scal[r * kScal + S_EST] = sqrt(gn.x * gn.x + gn.y * gn.y);
   scal[r * kScal + S_DEN] = den;
+}
+
+// One workgroup, right-hand sides strided over its threads.
+__global__ void __launch_bounds__(256) givens_kernel(double2* __restrict__ H, double2* __restrict__ cs,
+                                                     double2* __restrict__ sn, double2* __restrict__ gam, int k,
+                                                     int restart, int nrhs, GmresState gs, GmresParams gp,
+                                                     CtlView host, unsigned tag) {
+  int mine = 0;
+  for (int r = threadIdx.x; r < nrhs; r += blockDim.x) {
+    double* sc = gs.scal + r * kScal;
+    if (gs.active[r]) {
+      givens_one(H, cs, sn, gam, gs.scal, k, restart, r);
+      const int it = gs.iters[r] + 1;
+      gs.iters[r] = it;
+      gs.ksz[r] = k + 1;
+      const double est = sc[S_EST];
+      const bool stop = !(est > sc[S_TARGET]) || it >= gp.max_iters || sc[S_DEN] == 0.0;
+      if (stop) gs.active[r] = 0;
+      else mine += 1;
+    }
+    host.iters[r] = gs.iters[r];
+    host.est[r] = sc[S_EST];
+  }
+  report(mine, host, tag);
+}
+
+// Start of the solve or end of a cycle (S_NORM from the norm kernel).
+__global__ void __launch_bounds__(256) control_kernel(int cycle_end, int nrhs, GmresState gs, GmresParams gp,
+                                                      CtlView host, unsigned tag) {
+  int mine = 0;
+  for (int r = threadIdx.x; r < nrhs; r += blockDim.x) {
+    double* sc = gs.scal + r * kScal;
+    const double nrm = sc[S_NORM];
+    if (!cycle_end) {
+      sc[S_GNORM] = nrm;
+      sc[S_BETA] = nrm;
+      sc[S_EST] = 0.0;
+      gs.iters[r] = 0;
+      gs.done[r] = nrm == 0.0 || nrm <= gp.tol * nrm;
+    } else if (!gs.done[r]) {
+      sc[S_BETA] = nrm;
+      if (nrm <= gp.tol * sc[S_GNORM]) gs.done[r] = 1;
+    }
+    const int act = !gs.done[r] && gs.iters[r] < gp.max_iters;
+    gs.active[r] = act;
+    gs.ksz[r] = 0;
+    sc[S_TARGET] = fmax(gp.tol * sc[S_GNORM], gp.eta * sc[S_BETA]);
+    mine += act;
+    host.iters[r] = gs.iters[r];
+    host.est[r] = sc[S_EST];
+    host.beta[r] = sc[S_BETA];
+    host.gnorm[r] = sc[S_GNORM];
+  }
+  report(mine, host, tag);
 }
 
 // y = triu(H(0:k,0:k))^{-1} gam(0:k); ksz[r] = number of steps of rhs r.
@@ -424,10 +491,14 @@ void k_scale(double2* y, const double2* x, const double* scal, long long N, int 
   LSP_LAUNCH("scale", 0, scale_kernel, dim3(grid1(N, 256, 1024), nrhs), dim3(256), 0, st, y, x, scal, N, active);
 }
 
-void k_givens(double2* H, double2* cs, double2* sn, double2* gam, double* scal, int k, int restart, int nrhs,
-              const int* active, hipStream_t st) {
-  LSP_LAUNCH("givens", 0, givens_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, H, cs, sn, gam, scal, k, restart, nrhs,
-                     active);
+void k_givens(double2* H, double2* cs, double2* sn, double2* gam, int k, int restart, int nrhs, const GmresState& gs,
+              const GmresParams& gp, const CtlView& host, unsigned tag, hipStream_t st) {
+  LSP_LAUNCH("givens", 0, givens_kernel, dim3(1), dim3(256), 0, st, H, cs, sn, gam, k, restart, nrhs, gs, gp, host, tag);
+}
+
+void k_gmres_control(bool cycle_end, int nrhs, const GmresState& gs, const GmresParams& gp, const CtlView& host,
+                     unsigned tag, hipStream_t st) {
+  LSP_LAUNCH("gmres_control", 0, control_kernel, dim3(1), dim3(256), 0, st, cycle_end ? 1 : 0, nrhs, gs, gp, host, tag);
 }
 
 void k_backsolve_update(const double2* H, const double2* gam, double2* y, const int* ksz, double2* x, const double2* Z,

@@ -211,6 +211,8 @@ struct SolvePtrs {
   double* scal;   // [nrhs][kScal]
   int* active;
   int* ksz;
+  int* iters;
+  int* done;
 };
 
 size_t layout_solve(const Plan& P, int nrhs, int restart, bool krylov, void* base, SolvePtrs* out) {
@@ -241,6 +243,8 @@ size_t layout_solve(const Plan& P, int nrhs, int restart, bool krylov, void* bas
     s.scal = cv.take<double>((size_t)nrhs * kScal);
     s.active = cv.take<int>(nrhs);
     s.ksz = cv.take<int>(nrhs);
+    s.iters = cv.take<int>(nrhs);
+    s.done = cv.take<int>(nrhs);
   }
   if (out) *out = s;
   return cv.off + 256;
@@ -259,22 +263,60 @@ struct lsp_problem {
   FftPlanDev<float> fp32{};
   bool factored = false;
   double min_pivot_ratio = 0.0;
-  double* host_scal = nullptr;  // pinned
-  int* host_int = nullptr;      // pinned
+  // GMRES control block in pinned, coherent host memory (HostCtl, then
+  // iters, est, beta, gnorm for host_cap right-hand sides)
+  void* ctl_host = nullptr;
+  void* ctl_dev = nullptr;
   int host_cap = 0;
+  unsigned ctl_tag = 0;
 
   ~lsp_problem() {
-    if (host_scal) (void)hipHostFree(host_scal);
-    if (host_int) (void)hipHostFree(host_int);
+    if (ctl_host) (void)hipHostFree(ctl_host);
+  }
+
+  static size_t ctl_bytes(int cap) { return sizeof(HostCtl) + 8 * (size_t)cap + 3 * sizeof(double) * (size_t)cap; }
+
+  static CtlView ctl_view(void* base, int cap) {
+    char* b = static_cast<char*>(base);
+    CtlView v;
+    v.hdr = reinterpret_cast<HostCtl*>(b);
+    v.iters = reinterpret_cast<int*>(b + sizeof(HostCtl));
+    double* dv = reinterpret_cast<double*>(b + sizeof(HostCtl) + 8 * (size_t)cap);
+    v.est = dv;
+    v.beta = dv + cap;
+    v.gnorm = dv + 2 * (size_t)cap;
+    return v;
   }
 
   void ensure_host(int nrhs) {
     if (nrhs <= host_cap) return;
-    if (host_scal) { (void)hipHostFree(host_scal); host_scal = nullptr; }
-    if (host_int) { (void)hipHostFree(host_int); host_int = nullptr; }
-    LSP_HIP(hipHostMalloc((void**)&host_scal, sizeof(double) * kScal * nrhs, hipHostMallocDefault));
-    LSP_HIP(hipHostMalloc((void**)&host_int, sizeof(int) * 2 * nrhs, hipHostMallocDefault));
+    if (ctl_host) { (void)hipHostFree(ctl_host); ctl_host = ctl_dev = nullptr; host_cap = 0; }
+    LSP_HIP(hipHostMalloc(&ctl_host, ctl_bytes(nrhs), hipHostMallocMapped | hipHostMallocCoherent));
+    std::memset(ctl_host, 0, ctl_bytes(nrhs));
+    LSP_HIP(hipHostGetDevicePointer(&ctl_dev, ctl_host, 0));
     host_cap = nrhs;
+    ctl_tag = 0;
+  }
+
+  // Waits until the device has reported `tag` (the stream's work up to the
+  // reporting kernel is then done) and returns the number of right-hand
+  // sides still iterating.  Polls the pinned block; every few thousand polls
+  // it asks the stream for errors, and a stream that has finished without
+  // the tag is an error.
+  int wait_ctl(unsigned tag) {
+    HostCtl* h = ctl_view(ctl_host, host_cap).hdr;
+    long polls = 0, idle_polls = -1;
+    while (__atomic_load_n(&h->tag, __ATOMIC_ACQUIRE) != tag) {
+      if (idle_polls >= 0) {
+        if (++idle_polls > (1L << 24)) throw Error(LSP_ERR_HIP, "solver control report did not arrive");
+      } else if ((++polls & 4095) == 0) {
+        const hipError_t e = hipStreamQuery(st);
+        if (e == hipSuccess) idle_polls = 0;  // stream done: the report must be in flight
+        else if (e != hipErrorNotReady) LSP_HIP(e);
+      }
+      __builtin_ia32_pause();
+    }
+    return __atomic_load_n(&h->nact, __ATOMIC_ACQUIRE);
   }
 };
 
@@ -730,30 +772,16 @@ lsp_status lsp_solve(lsp_problem* pb, int nrhs, int rhs_kind, const void* rhs, v
     k_fill_zero(x, NB * (long long)sizeof(double2), st);
     LSP_HIP(hipMemcpyAsync(s.r, s.g, NB * sizeof(double2), hipMemcpyDeviceToDevice, st));
     k_norm(s.r, s.partial, s.h, s.H, s.scal, -1, R, N, nrhs, nullptr, st);
-    LSP_HIP(hipMemcpyAsync(pb->host_scal, s.scal, sizeof(double) * kScal * nrhs, hipMemcpyDeviceToHost, st));
-    LSP_HIP(hipStreamSynchronize(st));
 
-    std::vector<double> gnorm(nrhs), beta(nrhs), est(nrhs, 0.0), target(nrhs);
-    std::vector<int> iters(nrhs, 0), done(nrhs, 0), active(nrhs, 0), ksz(nrhs, 0);
-    for (int r = 0; r < nrhs; ++r) {
-      gnorm[r] = beta[r] = pb->host_scal[r * kScal + S_NORM];
-      done[r] = gnorm[r] == 0.0 || beta[r] <= o.tol * gnorm[r];
-    }
-    const double eta = pb->precision == LSP_MIXED ? 1e-5 : 0.0;
-    auto upload_active = [&]() {
-      for (int r = 0; r < nrhs; ++r) pb->host_int[r] = active[r];
-      LSP_HIP(hipMemcpyAsync(s.active, pb->host_int, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
-    };
-    while (true) {
-      int nact = 0;
-      for (int r = 0; r < nrhs; ++r) {
-        active[r] = !done[r] && iters[r] < o.max_iters;
-        nact += active[r];
-        ksz[r] = 0;
-        target[r] = std::max(o.tol * gnorm[r], eta * beta[r]);
-      }
-      if (nact == 0) break;
-      upload_active();
+    // Restarted GMRES; every stopping decision is taken on the device (same
+    // rules as the host would apply) and the host only waits for the count
+    // of right-hand sides still iterating.
+    const GmresState gs{s.scal, s.active, s.ksz, s.iters, s.done};
+    const GmresParams gp{o.tol, pb->precision == LSP_MIXED ? 1e-5 : 0.0, o.max_iters};
+    const CtlView hv = lsp_problem::ctl_view(pb->ctl_dev, pb->host_cap);
+    k_gmres_control(false, nrhs, gs, gp, hv, ++pb->ctl_tag, st);
+    int nact = pb->wait_ctl(pb->ctl_tag);
+    while (nact > 0) {
       k_cycle_init(s.H, s.gam, s.scal, R, nrhs, st);
       k_scale(s.V, s.r, s.scal, N, nrhs, s.active, st);
       for (int k = 0; k < R; ++k) {
@@ -763,46 +791,28 @@ lsp_status lsp_solve(lsp_problem* pb, int nrhs, int rhs_kind, const void* rhs, v
         apply_conv(pb, s, nrhs, pb->precision, Zk, s.w, true, pb->d.w2m);
         k_arnoldi_orth(s.V, s.w, s.partial, s.partial2, s.h, s.H, s.scal, s.V + (size_t)(k + 1) * NB, k, R, N, nrhs,
                        s.active, st);
-        k_givens(s.H, s.cs, s.sn, s.gam, s.scal, k, R, nrhs, s.active, st);
-        LSP_HIP(hipMemcpyAsync(pb->host_scal, s.scal, sizeof(double) * kScal * nrhs, hipMemcpyDeviceToHost, st));
-        LSP_HIP(hipStreamSynchronize(st));
-        int still = 0;
-        for (int r = 0; r < nrhs; ++r) {
-          if (!active[r]) continue;
-          iters[r]++;
-          ksz[r] = k + 1;
-          est[r] = pb->host_scal[r * kScal + S_EST];
-          bool stop = !(est[r] > target[r]) || iters[r] >= o.max_iters || pb->host_scal[r * kScal + S_DEN] == 0.0;
-          if (stop) active[r] = 0;
-          still += active[r];
-        }
-        if (still == 0) break;
-        upload_active();
+        k_givens(s.H, s.cs, s.sn, s.gam, k, R, nrhs, gs, gp, hv, ++pb->ctl_tag, st);
+        if (pb->wait_ctl(pb->ctl_tag) == 0) break;
       }
-      for (int r = 0; r < nrhs; ++r) pb->host_int[nrhs + r] = ksz[r];
-      LSP_HIP(hipMemcpyAsync(s.ksz, pb->host_int + nrhs, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
       k_backsolve_update(s.H, s.gam, s.y, s.ksz, x, s.Z, R, N, nrhs, st);
       // true residual in complex128
       apply_conv(pb, s, nrhs, LSP_FP64, x, s.t, true, pb->d.w2m);
       k_sub(s.r, s.g, s.t, NB, st);
       k_norm(s.r, s.partial, s.h, s.H, s.scal, -1, R, N, nrhs, nullptr, st);
-      LSP_HIP(hipMemcpyAsync(pb->host_scal, s.scal, sizeof(double) * kScal * nrhs, hipMemcpyDeviceToHost, st));
-      LSP_HIP(hipStreamSynchronize(st));
-      for (int r = 0; r < nrhs; ++r) {
-        if (done[r]) continue;
-        beta[r] = pb->host_scal[r * kScal + S_NORM];
-        if (beta[r] <= o.tol * gnorm[r]) done[r] = 1;
-      }
+      k_gmres_control(true, nrhs, gs, gp, hv, ++pb->ctl_tag, st);
+      nact = pb->wait_ctl(pb->ctl_tag);
     }
+    const CtlView hh = lsp_problem::ctl_view(pb->ctl_host, pb->host_cap);
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
-      bool conv = gnorm[r] == 0.0 || beta[r] <= o.tol * gnorm[r];
+      const double gnorm = hh.gnorm[r], beta = hh.beta[r];
+      bool conv = gnorm == 0.0 || beta <= o.tol * gnorm;
       all = all && conv;
       if (info) {
-        info[r].iters = iters[r];
+        info[r].iters = hh.iters[r];
         info[r].converged = conv ? 1 : 0;
-        info[r].relres_true = gnorm[r] > 0 ? beta[r] / gnorm[r] : 0.0;
-        info[r].relres_est = gnorm[r] > 0 ? est[r] / gnorm[r] : 0.0;
+        info[r].relres_true = gnorm > 0 ? beta / gnorm : 0.0;
+        info[r].relres_est = gnorm > 0 ? hh.est[r] / gnorm : 0.0;
       }
     }
     if (!all) throw Error(LSP_ERR_NOCONV, "GMRES reached max_iters before the tolerance");
