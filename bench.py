@@ -67,9 +67,12 @@ def run_path(lsp, torch, w, m_dev, u_dev, prec, steps, warmup):
     total_ms = tot0.elapsed_time(tot1)
     if st != 0 or not all(i["converged"] for i in info):
         raise RuntimeError(f"{prec} path failed: status {st}, {info}")
-    # phase split (untimed extra step; each call synchronises the stream)
+    # phase split (untimed extra step; set-up only enqueues, so it is
+    # followed by a synchronisation; factor and solve synchronise themselves)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     pb = lsp.Problem(plan, omega, m_dev)
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
     pb.factor()
     t2 = time.perf_counter()

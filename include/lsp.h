@@ -165,10 +165,12 @@ void lsp_problem_destroy(lsp_problem* problem);
 
 /* Numeric multifrontal LU of M (Section 2.2, nested dissection and the
  * multifrontal method), level by level from the leaves, with partial
- * pivoting inside each front's fully-summed block.  Synchronises the
- * stream to read the pivot-health flag.  Errors: LSP_ERR_SINGULAR (in some
- * 32-wide panel the smallest pivot modulus |re| + |im| is at most 64 eps
- * times the largest, eps of the factor precision), LSP_ERR_HIP. */
+ * pivoting inside each front's fully-summed block.  Waits for the stream
+ * to report the pivot-health figure (reduced on the device into pinned host
+ * memory, which the calling thread polls).  Errors: LSP_ERR_SINGULAR (in
+ * some 32-wide panel the smallest pivot modulus |re| + |im| is at most 64
+ * eps times the largest, or is NaN; eps of the factor precision),
+ * LSP_ERR_HIP. */
 lsp_status lsp_factor(lsp_problem* problem);
 
 /* Restarted right-preconditioned GMRES (Section 3.3), one independent

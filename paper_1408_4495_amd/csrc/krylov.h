@@ -19,7 +19,7 @@ enum { S_NORM = 0, S_INV = 1, S_EST = 2, S_DEN = 3, S_GNORM = 4, S_BETA = 5, S_T
 struct HostCtl {
   unsigned tag;
   int nact;
-  int pad[2];
+  double value;        // a reduced scalar (k_min_report)
 };
 struct CtlView {       // device-visible pointers into one pinned allocation
   HostCtl* hdr;
@@ -68,6 +68,8 @@ void k_backsolve_update(const double2* H, const double2* gam, double2* y, const 
                         int restart, long long N, int nrhs, hipStream_t st);
 void k_sub(double2* r, const double2* g, const double2* t, long long count, hipStream_t st);
 void k_cycle_init(double2* H, double2* gam, const double* scal, int restart, int nrhs, hipStream_t st);
+// host.hdr->value = min over v[0..n) (-1 if any entry is NaN), reported under tag.
+void k_min_report(const double* v, long long n, const CtlView& host, unsigned tag, hipStream_t st);
 void k_fill_zero(void* p, long long bytes, hipStream_t st);
 void k_fill_double(double* p, double v, long long count, hipStream_t st);
 void k_w2m(double* out, const double* m, double w2, long long N, hipStream_t st);

@@ -346,6 +346,27 @@ __global__ void __launch_bounds__(256) givens_kernel(double2* __restrict__ H, do
   report(mine, host, tag);
 }
 
+// Minimum of v (NaN entries give -1), one workgroup, reported to the host.
+__global__ void __launch_bounds__(256) min_report_kernel(const double* __restrict__ v, long long n, CtlView host,
+                                                         unsigned tag) {
+  __shared__ double red[256];
+  double mn = 1e300;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+    const double x = v[i];
+    mn = x == x ? fmin(mn, x) : -1.0;
+  }
+  red[threadIdx.x] = mn;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&host.hdr->value, red[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&host.hdr->tag, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 // Start of the solve or end of a cycle (S_NORM from the norm kernel).
 __global__ void __launch_bounds__(256) control_kernel(int cycle_end, int nrhs, GmresState gs, GmresParams gp,
                                                       CtlView host, unsigned tag) {
@@ -494,6 +515,10 @@ void k_scale(double2* y, const double2* x, const double* scal, long long N, int 
 void k_givens(double2* H, double2* cs, double2* sn, double2* gam, int k, int restart, int nrhs, const GmresState& gs,
               const GmresParams& gp, const CtlView& host, unsigned tag, hipStream_t st) {
   LSP_LAUNCH("givens", 0, givens_kernel, dim3(1), dim3(256), 0, st, H, cs, sn, gam, k, restart, nrhs, gs, gp, host, tag);
+}
+
+void k_min_report(const double* v, long long n, const CtlView& host, unsigned tag, hipStream_t st) {
+  LSP_LAUNCH("min_report", 0, min_report_kernel, dim3(1), dim3(256), 0, st, v, n, host, tag);
 }
 
 void k_gmres_control(bool cycle_end, int nrhs, const GmresState& gs, const GmresParams& gp, const CtlView& host,

@@ -263,18 +263,62 @@ struct lsp_problem {
   FftPlanDev<float> fp32{};
   bool factored = false;
   double min_pivot_ratio = 0.0;
-  // GMRES control block in pinned, coherent host memory (HostCtl, then
-  // iters, est, beta, gnorm for host_cap right-hand sides)
+  // control block in pinned, coherent host memory (HostCtl, then iters,
+  // est, beta, gnorm for host_cap right-hand sides), taken from a process-
+  // wide pool so that creating a problem does not pin memory each time
   void* ctl_host = nullptr;
   void* ctl_dev = nullptr;
   int host_cap = 0;
   unsigned ctl_tag = 0;
 
   ~lsp_problem() {
-    if (ctl_host) (void)hipHostFree(ctl_host);
+    if (ctl_host) ctl_pool().put({ctl_host, ctl_dev, host_cap});
   }
 
   static size_t ctl_bytes(int cap) { return sizeof(HostCtl) + 8 * (size_t)cap + 3 * sizeof(double) * (size_t)cap; }
+
+  struct CtlBlock {
+    void* host;
+    void* dev;
+    int cap;
+  };
+  // Blocks are returned only by destroyed problems, whose every report has
+  // been waited for, so no device write to a pooled block is in flight.  The
+  // pool lives until the process ends.
+  struct CtlPool {
+    std::mutex mu;
+    std::vector<CtlBlock> free;
+    CtlBlock get(int cap) {
+      {
+        std::lock_guard<std::mutex> g(mu);
+        int best = -1;
+        for (int i = 0; i < (int)free.size(); ++i)
+          if (free[i].cap >= cap && (best < 0 || free[i].cap < free[best].cap)) best = i;
+        if (best >= 0) {
+          CtlBlock b = free[best];
+          free.erase(free.begin() + best);
+          return b;
+        }
+      }
+      CtlBlock b{nullptr, nullptr, std::max(cap, 8)};
+      LSP_HIP(hipHostMalloc(&b.host, ctl_bytes(b.cap),
+                            hipHostMallocMapped | hipHostMallocCoherent | hipHostMallocPortable));
+      const hipError_t e = hipHostGetDevicePointer(&b.dev, b.host, 0);
+      if (e != hipSuccess) {
+        (void)hipHostFree(b.host);
+        LSP_HIP(e);
+      }
+      return b;
+    }
+    void put(const CtlBlock& b) {
+      std::lock_guard<std::mutex> g(mu);
+      free.push_back(b);
+    }
+  };
+  static CtlPool& ctl_pool() {
+    static CtlPool* pool = new CtlPool();
+    return *pool;
+  }
 
   static CtlView ctl_view(void* base, int cap) {
     char* b = static_cast<char*>(base);
@@ -290,11 +334,12 @@ struct lsp_problem {
 
   void ensure_host(int nrhs) {
     if (nrhs <= host_cap) return;
-    if (ctl_host) { (void)hipHostFree(ctl_host); ctl_host = ctl_dev = nullptr; host_cap = 0; }
-    LSP_HIP(hipHostMalloc(&ctl_host, ctl_bytes(nrhs), hipHostMallocMapped | hipHostMallocCoherent));
-    std::memset(ctl_host, 0, ctl_bytes(nrhs));
-    LSP_HIP(hipHostGetDevicePointer(&ctl_dev, ctl_host, 0));
-    host_cap = nrhs;
+    const CtlBlock b = ctl_pool().get(nrhs);
+    if (ctl_host) ctl_pool().put({ctl_host, ctl_dev, host_cap});
+    ctl_host = b.host;
+    ctl_dev = b.dev;
+    host_cap = b.cap;
+    std::memset(ctl_host, 0, ctl_bytes(host_cap));
     ctl_tag = 0;
   }
 
@@ -634,11 +679,13 @@ lsp_status lsp_factor(lsp_problem* pb) {
                       pb->d.pivstat};
       mf_factor<float>(mf, P, pb->st);
     }
-    std::vector<double> ps(P.fronts.size());
-    LSP_HIP(hipMemcpyAsync(ps.data(), pb->d.pivstat, ps.size() * sizeof(double), hipMemcpyDeviceToHost, pb->st));
-    LSP_HIP(hipStreamSynchronize(pb->st));
-    double mn = 1e300;
-    for (double v : ps) mn = std::min(mn, v);
+    // smallest pivot ratio over the fronts (a NaN counts as -1), reported
+    // into the pinned control block
+    pb->ensure_host(1);
+    k_min_report(pb->d.pivstat, (long long)P.fronts.size(), lsp_problem::ctl_view(pb->ctl_dev, pb->host_cap),
+                 ++pb->ctl_tag, pb->st);
+    pb->wait_ctl(pb->ctl_tag);
+    const double mn = lsp_problem::ctl_view(pb->ctl_host, pb->host_cap).hdr->value;
     pb->min_pivot_ratio = mn;
     const double eps = pb->precision == LSP_FP64 ? 2.220446049250313e-16 : 1.1920928955078125e-07;
     if (!(mn > 64.0 * eps)) {
