@@ -91,10 +91,11 @@ __global__ void __launch_bounds__(256) assemble_front_kernel(cplx<T>* __restrict
 // a factor 1 - 2^-18 of the column maximum), reads the pivot row from a
 // write-through LDS copy of the rows, and updates every row with a
 // multiplier that is zero for rows that are already pivotal.  The two
-// triangular inverses then come from one substitution sweep: lanes 0..31
-// solve L x = e_c, lanes 32..63 solve R y = e_c with R the row- and
-// column-reversed U (lower triangular), both reading their operand from LDS
-// in the same instruction stream.  Only the inverses and the permutation are
+// triangular inverses are then formed by the whole workgroup, blockwise
+// with 8 x 8 blocks, for L and for R, the row- and column-reversed U (lower
+// triangular): first the four diagonal blocks (forward substitution), then
+// the blocks at distance 1, 2 and 3 below the diagonal, each from the
+// blocks nearer the diagonal.  Only the inverses and the permutation are
 // stored: no later step reads the diagonal block of F itself.
 
 // Largest key over the 64 lanes (lane 63 ends with it): prefix maxima over
@@ -111,7 +112,8 @@ __device__ __forceinline__ int lane_max64(int k) {
 
 template <typename T>
 struct DiagLds {
-  cplx<T> m[2][NB][NB + 1];
+  cplx<T> m[2][NB][NB + 1];  // the block's rows, then the factors L and R
+  cplx<T> x[2][NB][NB + 1];  // L^{-1} and R^{-1}
 };
 
 // The block factorisation runs in one wave.  LDS operations of a wave are
@@ -125,95 +127,57 @@ struct WaveSync {
   }
 };
 
-// v[c] -= coef * opnd[c * STRIDE] for c = C0 .. NB-1, operands read from LDS
-// eight at a time with one chunk of lookahead (bounds the registers held by
-// loads in flight); STORE also writes each updated v[c] back to dst[c].
-template <typename T, int C0, int STRIDE, bool STORE>
-__device__ __forceinline__ void lds_axpy(cplx<T> (&v)[NB], const cplx<T> coef, const cplx<T>* opnd, cplx<T>* dst) {
-  constexpr int W = 8;
-  constexpr int nq = (NB - C0 + W - 1) / W;
-  if constexpr (nq > 0) {
-    cplx<T> buf[2][W];
-#pragma unroll
-    for (int j = 0; j < W; ++j)
-      if (C0 + j < NB) buf[0][j] = opnd[(C0 + j) * STRIDE];
-#pragma unroll
-    for (int q = 0; q < nq; ++q) {
-      if (q + 1 < nq) {
-#pragma unroll
-        for (int j = 0; j < W; ++j) {
-          const int c = C0 + (q + 1) * W + j;
-          if (c < NB) buf[(q + 1) & 1][j] = opnd[c * STRIDE];
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const int c = C0 + q * W + j;
-        if (c < NB) {
-          v[c] = cfms(v[c], coef, buf[q & 1][j]);
-          if constexpr (STORE) dst[c] = v[c];
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
+// Elimination.  Lane (h, r) holds columns c = 2i + h of row r in rowh[i];
+// column J is held by half J % 2 at index J / 2.  Pivot key of a candidate
+// entry: its magnitude |re| + |im| as a float with the five low mantissa
+// bits replaced by 31 - row.
+template <typename T>
+__device__ __forceinline__ int pivot_key(const cplx<T>& v, int r) {
+  return (__float_as_int((float)cabs1(v)) & 0x7fffffe0) | (NB - 1 - r);
 }
 
-// Elimination step J.  Lane (h, r) holds columns c = 2i + h of row r in
-// rowh[i]; column J is held by half J % 2 at index J / 2.
-// Half-row version for the elimination: v[i] -= coef_i * opnd[2i] for
-// i = I0 .. NB/2-1 (coef_I0 = first, the rest coef), each updated v[i]
-// written back to dst[2i]; eight operands at a time with one chunk of lookahead.
-template <typename T, int I0>
-__device__ __forceinline__ void lds_axpy_h(cplx<T> (&v)[NB / 2], const cplx<T> coef, const cplx<T> first,
-                                           const cplx<T>* opnd, cplx<T>* dst) {
-  constexpr int W = 8, NH = NB / 2;
-  constexpr int nq = (NH - I0 + W - 1) / W;
-  cplx<T> buf[2][W];
-#pragma unroll
-  for (int j = 0; j < W; ++j)
-    if (I0 + j < NH) buf[0][j] = opnd[2 * (I0 + j)];
-#pragma unroll
-  for (int q = 0; q < nq; ++q) {
-    if (q + 1 < nq) {
-#pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const int i = I0 + (q + 1) * W + j;
-        if (i < NH) buf[(q + 1) & 1][j] = opnd[2 * i];
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
-      const int i = I0 + q * W + j;
-      if (i < NH) {
-        v[i] = cfms(v[i], i == I0 ? first : coef, buf[q & 1][j]);
-        dst[2 * i] = v[i];
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-  }
+__device__ __forceinline__ float lane_value(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// 1 / den for den > 0 (0 otherwise): hardware reciprocal refined by Newton
+// steps (one in single, two in double precision)
+__device__ __forceinline__ float recip(float den) {
+  float r = __builtin_amdgcn_rcpf(den);
+  r = fmaf(r, fmaf(-den, r, 1.0f), r);
+  return den > 0.0f ? r : 0.0f;
+}
+__device__ __forceinline__ double recip(double den) {
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(r, fma(-den, r, 1.0), r);
+  r = fma(r, fma(-den, r, 1.0), r);
+  return den > 0.0 ? r : 0.0;
+}
+
+// Step J with the pivot already chosen: pivot row pl, pivot value d, and aJ
+// the column-J entry of this lane's row.  The pivot row's entries are read
+// from the LDS copy first; column J + 1 is updated before the others, so the
+// next pivot (a DPP maximum of the keys, then the pivot value read from its
+// lane) is found while the remaining columns are updated and written back.
 template <typename T, int J>
 __device__ __forceinline__ void diag_elim(cplx<T> (&rowh)[NB / 2], int& rlog, cplx<T>& myinv, T& dmin, T& dmax,
-                                          DiagLds<T>& S, const int r, const int h, const int kb) {
-  const WaveSync sync;
+                                          DiagLds<T>& S, const int r, const int h, const int kb, const int pl,
+                                          const cplx<T> d, const cplx<T> aJ) {
   if constexpr (J < NB) {
+    const WaveSync sync;
     constexpr int hJ = J & 1, iJ = J >> 1;
-    const cplx<T> own = rowh[iJ];
-    const int key = (h == hJ && rlog < 0) ? ((__float_as_int((float)cabs1(own)) & 0x7fffffe0) | (NB - 1 - r)) : -1;
-    const int pl = NB - 1 - (lane_max64(key) & (NB - 1));
-    // the row's column-J entry, from whichever half holds it
-    cplx<T> other;
-    other.x = __shfl_xor(own.x, 32, 64);
-    other.y = __shfl_xor(own.y, 32, 64);
-    const cplx<T> aJ = h == hJ ? own : other;
-    sync();  // rows written by the previous step are visible
-    const cplx<T> d = S.m[0][pl][J];
-    const T den = d.x * d.x + d.y * d.y;
-    const T rden = den > (T)0 ? (T)1 / den : (T)0;
+    constexpr int i0 = (J + 1) / 2;  // first index holding a column > J (in some half)
+    constexpr int NP = NB / 2 - i0 > 0 ? NB / 2 - i0 : 1;
+    cplx<T> prow[NP];
+#pragma unroll
+    for (int i = i0; i < NB / 2; ++i) prow[i - i0] = S.m[0][pl][2 * i + h];
+    const T rden = recip(d.x * d.x + d.y * d.y);
     const cplx<T> inv = mk<T>(d.x * rden, -d.y * rden);
     if (J < kb) {
       const T mag = cabs1(d);
@@ -224,90 +188,217 @@ __device__ __forceinline__ void diag_elim(cplx<T> (&rowh)[NB / 2], int& rlog, cp
     if (r == pl) { rlog = J; myinv = inv; }
     const cplx<T> l0 = cmul(aJ, inv);
     const cplx<T> l = upd ? l0 : mk<T>(0, 0);
-    if (h == hJ && upd) rowh[iJ] = l0;
-    // columns 2i + h > J; for even J the first index is column J itself in
-    // half 0 (the multiplier just stored), which takes a zero coefficient
-    constexpr int i0 = (J + 1) / 2;
-    if constexpr (i0 < NB / 2) {
-      const cplx<T> l_first = ((J & 1) == 0 && h == 0) ? mk<T>(0, 0) : l;
-      lds_axpy_h<T, i0>(rowh, l, l_first, &S.m[0][pl][h], &S.m[0][r][h]);
+    if (h == hJ && upd) rowh[iJ] = l0;  // the multiplier
+    if constexpr (J + 1 < NB) {
+      constexpr int h1 = (J + 1) & 1, i1 = (J + 1) >> 1;
+      static_assert(i1 == i0, "column J + 1 sits at the first updated index");
+      // index i1: column J + 1 in half h1; in the other half column J (even
+      // J: the multiplier, coefficient zero) or J + 2
+      const cplx<T> c1 = ((J & 1) == 0 && h == 0) ? mk<T>(0, 0) : l;
+      rowh[i1] = cfms(rowh[i1], c1, prow[0]);
+      S.m[0][r][2 * i1 + h] = rowh[i1];
+      const int key = (h == h1 && rlog < 0) ? pivot_key<T>(rowh[i1], r) : -1;
+      const int pln = NB - 1 - (lane_max64(key) & (NB - 1));
+      const int src = pln + NB * h1;
+      cplx<T> dn;
+      dn.x = lane_value(rowh[i1].x, src);
+      dn.y = lane_value(rowh[i1].y, src);
+      cplx<T> other;
+      other.x = __shfl_xor(rowh[i1].x, 32, 64);
+      other.y = __shfl_xor(rowh[i1].y, 32, 64);
+      const cplx<T> an = h == h1 ? rowh[i1] : other;
+#pragma unroll
+      for (int i = i1 + 1; i < NB / 2; ++i) {
+        rowh[i] = cfms(rowh[i], l, prow[i - i0]);
+        S.m[0][r][2 * i + h] = rowh[i];
+      }
+      sync();  // the rows written above are what the next step reads
+      diag_elim<T, J + 1>(rowh, rlog, myinv, dmin, dmax, S, r, h, kb, pln, dn, an);
     }
-    diag_elim<T, J + 1>(rowh, rlog, myinv, dmin, dmax, S, r, h, kb);
   }
 }
 
-// Column sweep of the substitution: x_k = acc_k M(k,k), then
-// acc_i -= M(i,k) x_k for i > k (independent updates, no dependent chain).
-template <typename T, int K>
-__device__ __forceinline__ void diag_subst(cplx<T> (&x)[NB], const cplx<T>* M) {
-  if constexpr (K < NB) {
-    x[K] = cmul(x[K], M[K * (NB + 1) + K]);
-    lds_axpy<T, K + 1, NB + 1, false>(x, x[K], M + K, nullptr);
-    diag_subst<T, K + 1>(x, M);
+// First pivot, then the 32 steps.
+template <typename T>
+__device__ __forceinline__ void diag_eliminate(cplx<T> (&rowh)[NB / 2], int& rlog, cplx<T>& myinv, T& dmin, T& dmax,
+                                               DiagLds<T>& S, const int r, const int h, const int kb) {
+  const int key = h == 0 ? pivot_key<T>(rowh[0], r) : -1;
+  const int pl = NB - 1 - (lane_max64(key) & (NB - 1));
+  cplx<T> d;
+  d.x = lane_value(rowh[0].x, pl);
+  d.y = lane_value(rowh[0].y, pl);
+  cplx<T> other;
+  other.x = __shfl_xor(rowh[0].x, 32, 64);
+  other.y = __shfl_xor(rowh[0].y, 32, 64);
+  const cplx<T> a0 = h == 0 ? rowh[0] : other;
+  diag_elim<T, 0>(rowh, rlog, myinv, dmin, dmax, S, r, h, kb, pl, d, a0);
+}
+
+// Inverse of the lower-triangular T (T = L, or R = reversed U) held in M
+// with the reciprocals of its diagonal on the diagonal, into X (entries on
+// and below the diagonal; blocks above it are not written).  Blockwise with
+// KB = 8: X_bb = T_bb^{-1} by forward substitution, then for d = 1, 2, 3
+// X_ij = -X_ii sum_{k=j..i-1} T_ik X_kj with i = j + d.  Called by all 256
+// threads of the workgroup for both matrices at once (mat = 0, 1).
+constexpr int KB = 8;
+
+// Blocks (j + D, j) of both inverses: P = sum_{k=j..j+D-1} T_{j+D,k} X_kj
+// (stored where X_{j+D,j} goes), then X_{j+D,j} = -X_{j+D,j+D} P.  Entry e
+// of the 2 (4 - D) 64 entries: matrix, block j, row r, column c; at most two
+// per thread; the sums use two interleaved partial sums.
+template <typename T, int D>
+__device__ __forceinline__ void inv_level(DiagLds<T>& S, const int tid) {
+  constexpr int nbk = 4 - D, E = 2 * nbk * KB * KB;
+  cplx<T> v[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + 256 * u;
+    if (e < E) {
+      const int mat = e / (nbk * KB * KB), q = e % (nbk * KB * KB);
+      const int j = q / (KB * KB), r = (q / KB) % KB, c = q % KB, i = j + D;
+      cplx<T> ta[KB * D], xb[KB * D];  // all operand reads in flight before the sums
+#pragma unroll
+      for (int t = 0; t < KB * D; ++t) {
+        ta[t] = S.m[mat][KB * i + r][KB * j + t];
+        xb[t] = S.x[mat][KB * j + t][KB * j + c];
+      }
+      cplx<T> a0 = mk<T>(0, 0), a1 = mk<T>(0, 0);
+#pragma unroll
+      for (int t = 0; t < KB * D; t += 2) {
+        a0 = cfma(a0, ta[t], xb[t]);
+        a1 = cfma(a1, ta[t + 1], xb[t + 1]);
+      }
+      v[u] = cadd(a0, a1);
+    }
   }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + 256 * u;
+    if (e < E) {
+      const int mat = e / (nbk * KB * KB), q = e % (nbk * KB * KB);
+      const int j = q / (KB * KB), r = (q / KB) % KB, c = q % KB, i = j + D;
+      S.x[mat][KB * i + r][KB * j + c] = v[u];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + 256 * u;
+    if (e < E) {
+      const int mat = e / (nbk * KB * KB), q = e % (nbk * KB * KB);
+      const int j = q / (KB * KB), r = (q / KB) % KB, c = q % KB, i = j + D;
+      cplx<T> xa[KB], pb[KB];
+#pragma unroll
+      for (int t = 0; t < KB; ++t) {
+        xa[t] = S.x[mat][KB * i + r][KB * i + t];
+        pb[t] = S.x[mat][KB * i + t][KB * j + c];
+      }
+      cplx<T> a0 = mk<T>(0, 0), a1 = mk<T>(0, 0);
+#pragma unroll
+      for (int t = 0; t < KB; t += 2) {
+        a0 = cfms(a0, xa[t], pb[t]);
+        a1 = cfms(a1, xa[t + 1], pb[t + 1]);
+      }
+      v[u] = cadd(a0, a1);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + 256 * u;
+    if (e < E) {
+      const int mat = e / (nbk * KB * KB), q = e % (nbk * KB * KB);
+      const int j = q / (KB * KB), r = (q / KB) % KB, c = q % KB, i = j + D;
+      S.x[mat][KB * i + r][KB * j + c] = v[u];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void tri_inverses(DiagLds<T>& S, const int tid) {
+  static_assert(NB == 4 * KB, "four diagonal blocks");
+  if (tid < 64) {  // 2 matrices x 4 blocks x 8 columns
+    const int mat = tid / 32, base = KB * ((tid / KB) % 4), col = tid % KB;
+    const cplx<T>(*M)[NB + 1] = S.m[mat];
+    cplx<T> x[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) x[i] = mk<T>(i == col ? 1 : 0, 0);
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      x[k] = cmul(x[k], M[base + k][base + k]);
+#pragma unroll
+      for (int i = k + 1; i < KB; ++i) x[i] = cfms(x[i], M[base + i][base + k], x[k]);
+    }
+#pragma unroll
+    for (int i = 0; i < KB; ++i) S.x[mat][base + i][base + col] = x[i];
+  }
+  __syncthreads();
+  inv_level<T, 1>(S, tid);
+  inv_level<T, 2>(S, tid);
+  inv_level<T, 3>(S, tid);
 }
 
 // Pivoted LU of the diagonal block of panel k0 and the inverses of its
-// factors, in one wave (lane = 0..63): on entry S.m[0][r][c] and rowh (lane
-// (h, r) holds columns 2i + h of row r) hold the updated block, padded with
-// the identity beyond kb.  Writes the inverses to Dinv, the row order to
-// perm and the pivot ratio into *pivstat.
+// factors, by a workgroup of 256 threads: on entry S.m[0][r][c] holds the
+// updated block, padded with the identity beyond kb (visible to the whole
+// workgroup).  The elimination runs in the first wave (lane (h, r) holds
+// columns 2i + h of row r), the inverses in all four.  Writes the inverses
+// to Dinv, the row order to perm and the block's smallest / largest pivot
+// magnitude to its pivstat slot.
 template <typename T>
-__device__ __forceinline__ void diag_factor_block(DiagLds<T>& S, cplx<T> (&rowh)[NB / 2], const FrontDev& f,
-                                                  const int k0, const int kb, const int lane,
+__device__ __forceinline__ void diag_factor_block(DiagLds<T>& S, const FrontDev& f, const int k0, const int kb,
                                                   cplx<T>* __restrict__ Dinv, int* __restrict__ perm,
                                                   double* __restrict__ pivstat) {
-  const WaveSync sync;
-  const int r = lane & (NB - 1), h = lane / NB;
+  const int tid = threadIdx.x;
+  const int r = tid & (NB - 1), h = tid / NB;
   int rlog = -1;
-  cplx<T> myinv = mk<T>(0, 0);
   T dmin = (T)INFINITY, dmax = (T)0;
-  diag_elim<T, 0>(rowh, rlog, myinv, dmin, dmax, S, r, h, kb);
-  rlog &= NB - 1;  // every row is chosen exactly once, so this is already in range
-  sync();
+  if (tid < 64) {
+    const WaveSync sync;
+    const int lane = tid;
+    cplx<T> rowh[NB / 2];
 #pragma unroll
-  for (int i = 0; i < NB / 2; ++i) {
-    const int c = 2 * i + h;
-    S.m[0][rlog][c] = rowh[i];
-    S.m[1][NB - 1 - rlog][NB - 1 - c] = rowh[i];
-  }
-  if (h == 0) {  // after the row writes above, in issue order
-    S.m[0][rlog][rlog] = mk<T>(1, 0);
-    S.m[1][NB - 1 - rlog][NB - 1 - rlog] = myinv;
-    if (rlog < kb) perm[f.piv_off + k0 + rlog] = k0 + r;
-    if (lane == 0) {
-      const double ratio = dmax > (T)0 ? (double)(dmin / dmax) : 0.0;
-      *pivstat = fmin(*pivstat, ratio);
+    for (int i = 0; i < NB / 2; ++i) rowh[i] = S.m[0][r][2 * i + h];
+    cplx<T> myinv = mk<T>(0, 0);
+    diag_eliminate<T>(rowh, rlog, myinv, dmin, dmax, S, r, h, kb);
+    rlog &= NB - 1;  // every row is chosen exactly once, so this is already in range
+    sync();
+#pragma unroll
+    for (int i = 0; i < NB / 2; ++i) {
+      const int c = 2 * i + h;
+      S.m[0][rlog][c] = rowh[i];
+      S.m[1][NB - 1 - rlog][NB - 1 - c] = rowh[i];
+    }
+    if (h == 0) {  // after the row writes above, in issue order
+      S.m[0][rlog][rlog] = mk<T>(1, 0);
+      S.m[1][NB - 1 - rlog][NB - 1 - rlog] = myinv;
     }
   }
-  sync();
-  // forward substitution M x = e_r with M = L (unit diagonal stored as 1)
-  // or the reversed U (reciprocal pivots stored on its diagonal)
-  cplx<T> x[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) x[i] = mk<T>(r == i ? 1 : 0, 0);
-  diag_subst<T, 0>(x, &S.m[lane / NB][0][0]);
-  sync();
-  // stage column r of each result at [r][i] (L^{-1}(i, r); reversed U^{-1})
-#pragma unroll
-  for (int i = 0; i < NB; ++i) S.m[lane / NB][r][i] = x[i];
-  sync();
+  __syncthreads();
+  tri_inverses<T>(S, tid);
+  // global stores only now: a barrier waits for the stores issued before it
+  if (tid < NB && rlog < kb) perm[f.piv_off + k0 + rlog] = k0 + r;
+  if (tid == 0)  // one slot per diagonal block, in the order of the inverted blocks
+    pivstat[f.dinv_off / (2 * NB * NB) + k0 / NB] = dmax > (T)0 ? (double)(dmin / dmax) : 0.0;
+  // L^{-1}(a, b) = X_L(a, b) for a >= b; U^{-1}(a, b) = X_R(31-a, 31-b) for a <= b
   cplx<T>* Li = Dinv + f.dinv_off + (long long)(k0 / NB) * 2 * NB * NB;
-#pragma unroll 4
-  for (int e = lane; e < NB * NB; e += 64) {
-    const int a = e % NB, b = e / NB;  // entry (a, b) of L^{-1}, then of U^{-1}
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = tid + 256 * u;
+    const int a = e % NB, b = e / NB;
     const bool in = a < kb && b < kb;
-    Li[e] = in ? S.m[0][b][a] : mk<T>(0, 0);
-    Li[NB * NB + e] = in ? S.m[1][NB - 1 - b][NB - 1 - a] : mk<T>(0, 0);
+    Li[e] = in && a >= b ? S.x[0][a][b] : mk<T>(0, 0);
+    Li[NB * NB + e] = in && a <= b ? S.x[1][NB - 1 - a][NB - 1 - b] : mk<T>(0, 0);
   }
 }
 
 // First panel of a level (later panels are factored inside the previous
 // panel's trailing update, gemm_update_kernel with FUSE).
 template <typename T>
-__global__ void __launch_bounds__(64) diag_lu_kernel(cplx<T>* __restrict__ Fbuf, cplx<T>* __restrict__ Dinv,
-                                                     const FrontDev* __restrict__ fr, int* __restrict__ perm,
-                                                     double* __restrict__ pivstat, int first, int k0) {
+__global__ void __launch_bounds__(256) diag_lu_kernel(cplx<T>* __restrict__ Fbuf, cplx<T>* __restrict__ Dinv,
+                                                      const FrontDev* __restrict__ fr, int* __restrict__ perm,
+                                                      double* __restrict__ pivstat, int first, int k0) {
   static_assert(NB == 32, "lane layout assumes 32-wide panels");
   __shared__ DiagLds<T> S;
   const FrontDev f = fr[first + blockIdx.x];
@@ -315,17 +406,20 @@ __global__ void __launch_bounds__(64) diag_lu_kernel(cplx<T>* __restrict__ Fbuf,
   const int kb = min(NB, f.p - k0);
   const int m = f.p + f.q;
   const cplx<T>* F = Fbuf + f.f_off;
-  const int lane = threadIdx.x;
-  const int r = lane & (NB - 1), h = lane / NB;
-  cplx<T> rowh[NB / 2];
+  const int tid = threadIdx.x;
+  cplx<T> v[NB * NB / 256];
 #pragma unroll
-  for (int i = 0; i < NB / 2; ++i) {
-    const int c = 2 * i + h;
-    const cplx<T> v = F[(k0 + min(r, kb - 1)) + (long long)(k0 + min(c, kb - 1)) * m];
-    rowh[i] = r < kb && c < kb ? v : mk<T>(r == c ? 1 : 0, 0);
-    S.m[0][r][c] = rowh[i];
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = tid + 256 * u, r = e % NB, c = e / NB;
+    v[u] = F[(k0 + min(r, kb - 1)) + (long long)(k0 + min(c, kb - 1)) * m];
   }
-  diag_factor_block<T>(S, rowh, f, k0, kb, lane, Dinv, perm, pivstat + first + blockIdx.x);
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = tid + 256 * u, r = e % NB, c = e / NB;
+    S.m[0][r][c] = r < kb && c < kb ? v[u] : mk<T>(r == c ? 1 : 0, 0);
+  }
+  __syncthreads();
+  diag_factor_block<T>(S, f, k0, kb, Dinv, perm, pivstat);
 }
 
 // Runs use(i, load(i)) for i = 0 .. N-1 (N and i compile-time after
@@ -528,12 +622,7 @@ __device__ __forceinline__ void update_and_factor_next(unsigned char* raw, const
     S.m[0][e % NB][e / NB] = ov[u];
   }
   __syncthreads();
-  if (tid >= 64) return;  // the factorisation is one wave's work
-  const int r = tid & (NB - 1), h = tid / NB;
-  cplx<T> rowh[NB / 2];
-#pragma unroll
-  for (int i = 0; i < NB / 2; ++i) rowh[i] = S.m[0][r][2 * i + h];
-  diag_factor_block<T>(S, rowh, f, k1, kbn, tid, Dinv, perm, pivstat);
+  diag_factor_block<T>(S, f, k1, kbn, Dinv, perm, pivstat);
 }
 
 template <typename T, int TM, bool FUSE>
@@ -544,7 +633,8 @@ __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ 
   // BW x BW MFMA 16x16 blocks.  With FUSE, block row 0 is the lookahead
   // factorisation of the next diagonal block and the tiles start at row 1.
   constexpr int BW = TM / 32;
-  constexpr size_t kRaw = sizeof(GemmLds<T, TM>) > sizeof(DiagLds<T>) ? sizeof(GemmLds<T, TM>) : sizeof(DiagLds<T>);
+  constexpr size_t kRaw = FUSE && sizeof(DiagLds<T>) > sizeof(GemmLds<T, TM>) ? sizeof(DiagLds<T>)
+                                                                             : sizeof(GemmLds<T, TM>);
   __shared__ __align__(16) unsigned char raw[kRaw];
   GemmLds<T, TM>& G = *reinterpret_cast<GemmLds<T, TM>*>(raw);
   auto& Ar = G.Ar;
@@ -562,7 +652,7 @@ __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ 
   if constexpr (FUSE) {
     if (brow < 0) {
       if (blockIdx.x == 0 && f.p > k1)
-        update_and_factor_next<T>(raw, f, F, k0, k1, m, Dinv, perm, pivstat + first + blockIdx.z);
+        update_and_factor_next<T>(raw, f, F, k0, k1, m, Dinv, perm, pivstat);
       return;
     }
   }
@@ -1119,7 +1209,7 @@ void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
     bool factored = false;  // panel k0's diagonal block done by the previous update
     for (int k0 = 0; k0 < maxp; k0 += NB) {
       if (!factored)
-        LSP_LAUNCH("diag_lu", (int)sizeof(cplx<T>), diag_lu_kernel<T>, dim3(cnt), dim3(64), 0, st, mf.F, mf.Dinv,
+        LSP_LAUNCH("diag_lu", (int)sizeof(cplx<T>), diag_lu_kernel<T>, dim3(cnt), dim3(256), 0, st, mf.F, mf.Dinv,
                    mf.fronts, mf.perm, mf.pivstat, first, k0);
       const int rem = maxm - k0 - 1;
       if (rem <= 0) continue;
@@ -1129,7 +1219,9 @@ void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
       const int tile = update_tile(plan, l, fp64);
       factored = fuse_next(plan, l, k0, fp64);
       if (tile == 32) update_launch<T, 32>(mf, factored, rem, cnt, first, k0, st);
-      else if (tile == 128) update_launch<T, 128>(mf, factored, rem, cnt, first, k0, st);
+      else if (tile == 128) {
+        if constexpr (sizeof(T) == 4) update_launch<T, 128>(mf, factored, rem, cnt, first, k0, st);
+      }
       else update_launch<T, 64>(mf, factored, rem, cnt, first, k0, st);
     }
   }

@@ -65,7 +65,7 @@ struct MfDev {
   const int* cpos;
   const double2* Mval;      // [N][3^d]
   int* perm;                // per panel row: the front row it came from
-  double* pivstat;          // per front: smallest / largest pivot magnitude
+  double* pivstat;          // per diagonal block: smallest / largest pivot magnitude
 };
 
 template <typename T>

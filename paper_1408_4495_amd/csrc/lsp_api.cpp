@@ -139,7 +139,7 @@ size_t layout_problem(const lsp_plan* pl, int precision, void* base, ProblemPtrs
   q.F = cv.take<char>((size_t)P.front_elems * esz);
   q.Dinv = cv.take<char>((size_t)P.dinv_elems * esz);
   q.perm = cv.take<int>(P.sum_p);
-  q.pivstat = cv.take<double>(P.fronts.size());
+  q.pivstat = cv.take<double>((size_t)P.panel_blocks);
   if (out) *out = q;
   return cv.off + 256;
 }
@@ -669,7 +669,6 @@ lsp_status lsp_factor(lsp_problem* pb) {
   return guarded([&]() -> lsp_status {
     LSP_REQUIRE(pb != nullptr, "null problem");
     const Plan& P = pb->plan->p;
-    k_fill_double(pb->d.pivstat, 1e300, (long long)P.fronts.size(), pb->st);
     if (pb->precision == LSP_FP64) {
       MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.perm,
                        pb->d.pivstat};
@@ -679,10 +678,10 @@ lsp_status lsp_factor(lsp_problem* pb) {
                       pb->d.pivstat};
       mf_factor<float>(mf, P, pb->st);
     }
-    // smallest pivot ratio over the fronts (a NaN counts as -1), reported
+    // smallest pivot ratio over the diagonal blocks (a NaN counts as -1), reported
     // into the pinned control block
     pb->ensure_host(1);
-    k_min_report(pb->d.pivstat, (long long)P.fronts.size(), lsp_problem::ctl_view(pb->ctl_dev, pb->host_cap),
+    k_min_report(pb->d.pivstat, (long long)P.panel_blocks, lsp_problem::ctl_view(pb->ctl_dev, pb->host_cap),
                  ++pb->ctl_tag, pb->st);
     pb->wait_ctl(pb->ctl_tag);
     const double mn = lsp_problem::ctl_view(pb->ctl_host, pb->host_cap).hdr->value;
