@@ -114,6 +114,7 @@ template <typename T>
 struct DiagLds {
   cplx<T> m[2][NB][NB + 1];  // the block's rows, then the factors L and R
   cplx<T> x[2][NB][NB + 1];  // L^{-1} and R^{-1}
+  cplx<T> p[2][3][8][8];     // partial products of the blockwise inversion
 };
 
 // The block factorisation runs in one wave.  LDS operations of a wave are
@@ -242,80 +243,53 @@ __device__ __forceinline__ void diag_eliminate(cplx<T> (&rowh)[NB / 2], int& rlo
 // threads of the workgroup for both matrices at once (mat = 0, 1).
 constexpr int KB = 8;
 
-// Blocks (j + D, j) of both inverses: P = sum_{k=j..j+D-1} T_{j+D,k} X_kj
-// (stored where X_{j+D,j} goes), then X_{j+D,j} = -X_{j+D,j+D} P.  Entry e
-// of the 2 (4 - D) 64 entries: matrix, block j, row r, column c; at most two
-// per thread; the sums use two interleaved partial sums.
-template <typename T, int D>
+// Blocks (j + D, j) of both inverses, by NT threads, one entry (matrix,
+// block j, row r, column c) per thread at a time: first P = sum over
+// k = j..j+D-1 of T_{j+D,k} X_kj into S.p, then X_{j+D,j} = -X_{j+D,j+D} P.
+template <typename T, int D, int NT>
 __device__ __forceinline__ void inv_level(DiagLds<T>& S, const int tid) {
   constexpr int nbk = 4 - D, E = 2 * nbk * KB * KB;
-  cplx<T> v[2];
+#pragma unroll 1
+  for (int e = tid; e < E; e += NT) {
+    const int mat = e / (nbk * KB * KB), q = e % (nbk * KB * KB);
+    const int j = q / (KB * KB), r = (q / KB) % KB, c = q % KB, i = j + D;
+    cplx<T> ta[KB * D], xb[KB * D];  // all operand reads in flight before the sums
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int e = tid + 256 * u;
-    if (e < E) {
-      const int mat = e / (nbk * KB * KB), q = e % (nbk * KB * KB);
-      const int j = q / (KB * KB), r = (q / KB) % KB, c = q % KB, i = j + D;
-      cplx<T> ta[KB * D], xb[KB * D];  // all operand reads in flight before the sums
-#pragma unroll
-      for (int t = 0; t < KB * D; ++t) {
-        ta[t] = S.m[mat][KB * i + r][KB * j + t];
-        xb[t] = S.x[mat][KB * j + t][KB * j + c];
-      }
-      cplx<T> a0 = mk<T>(0, 0), a1 = mk<T>(0, 0);
-#pragma unroll
-      for (int t = 0; t < KB * D; t += 2) {
-        a0 = cfma(a0, ta[t], xb[t]);
-        a1 = cfma(a1, ta[t + 1], xb[t + 1]);
-      }
-      v[u] = cadd(a0, a1);
+    for (int t = 0; t < KB * D; ++t) {
+      ta[t] = S.m[mat][KB * i + r][KB * j + t];
+      xb[t] = S.x[mat][KB * j + t][KB * j + c];
     }
-  }
+    cplx<T> a0 = mk<T>(0, 0), a1 = mk<T>(0, 0);
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int e = tid + 256 * u;
-    if (e < E) {
-      const int mat = e / (nbk * KB * KB), q = e % (nbk * KB * KB);
-      const int j = q / (KB * KB), r = (q / KB) % KB, c = q % KB, i = j + D;
-      S.x[mat][KB * i + r][KB * j + c] = v[u];
+    for (int t = 0; t < KB * D; t += 2) {
+      a0 = cfma(a0, ta[t], xb[t]);
+      a1 = cfma(a1, ta[t + 1], xb[t + 1]);
     }
+    S.p[mat][j][r][c] = cadd(a0, a1);
   }
   __syncthreads();
+#pragma unroll 1
+  for (int e = tid; e < E; e += NT) {
+    const int mat = e / (nbk * KB * KB), q = e % (nbk * KB * KB);
+    const int j = q / (KB * KB), r = (q / KB) % KB, c = q % KB, i = j + D;
+    cplx<T> xa[KB], pb[KB];  // X_ii is exactly zero above its diagonal
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int e = tid + 256 * u;
-    if (e < E) {
-      const int mat = e / (nbk * KB * KB), q = e % (nbk * KB * KB);
-      const int j = q / (KB * KB), r = (q / KB) % KB, c = q % KB, i = j + D;
-      cplx<T> xa[KB], pb[KB];
-#pragma unroll
-      for (int t = 0; t < KB; ++t) {
-        xa[t] = S.x[mat][KB * i + r][KB * i + t];
-        pb[t] = S.x[mat][KB * i + t][KB * j + c];
-      }
-      cplx<T> a0 = mk<T>(0, 0), a1 = mk<T>(0, 0);
-#pragma unroll
-      for (int t = 0; t < KB; t += 2) {
-        a0 = cfms(a0, xa[t], pb[t]);
-        a1 = cfms(a1, xa[t + 1], pb[t + 1]);
-      }
-      v[u] = cadd(a0, a1);
+    for (int t = 0; t < KB; ++t) {
+      xa[t] = S.x[mat][KB * i + r][KB * i + t];
+      pb[t] = S.p[mat][j][t][c];
     }
-  }
-  __syncthreads();
+    cplx<T> a0 = mk<T>(0, 0), a1 = mk<T>(0, 0);
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int e = tid + 256 * u;
-    if (e < E) {
-      const int mat = e / (nbk * KB * KB), q = e % (nbk * KB * KB);
-      const int j = q / (KB * KB), r = (q / KB) % KB, c = q % KB, i = j + D;
-      S.x[mat][KB * i + r][KB * j + c] = v[u];
+    for (int t = 0; t < KB; t += 2) {
+      a0 = cfms(a0, xa[t], pb[t]);
+      a1 = cfms(a1, xa[t + 1], pb[t + 1]);
     }
+    S.x[mat][KB * i + r][KB * j + c] = cadd(a0, a1);
   }
   __syncthreads();
 }
 
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void tri_inverses(DiagLds<T>& S, const int tid) {
   static_assert(NB == 4 * KB, "four diagonal blocks");
   if (tid < 64) {  // 2 matrices x 4 blocks x 8 columns
@@ -334,19 +308,19 @@ __device__ __forceinline__ void tri_inverses(DiagLds<T>& S, const int tid) {
     for (int i = 0; i < KB; ++i) S.x[mat][base + i][base + col] = x[i];
   }
   __syncthreads();
-  inv_level<T, 1>(S, tid);
-  inv_level<T, 2>(S, tid);
-  inv_level<T, 3>(S, tid);
+  inv_level<T, 1, NT>(S, tid);
+  inv_level<T, 2, NT>(S, tid);
+  inv_level<T, 3, NT>(S, tid);
 }
 
 // Pivoted LU of the diagonal block of panel k0 and the inverses of its
-// factors, by a workgroup of 256 threads: on entry S.m[0][r][c] holds the
-// updated block, padded with the identity beyond kb (visible to the whole
-// workgroup).  The elimination runs in the first wave (lane (h, r) holds
-// columns 2i + h of row r), the inverses in all four.  Writes the inverses
+// factors, by a workgroup of NT = 64 or 256 threads: on entry S.m[0][r][c]
+// holds the updated block, padded with the identity beyond kb (visible to
+// the whole workgroup).  The elimination runs in the first wave (lane (h, r)
+// holds columns 2i + h of row r), the inverses in all NT threads.  Writes the inverses
 // to Dinv, the row order to perm and the block's smallest / largest pivot
 // magnitude to its pivstat slot.
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void diag_factor_block(DiagLds<T>& S, const FrontDev& f, const int k0, const int kb,
                                                   cplx<T>* __restrict__ Dinv, int* __restrict__ perm,
                                                   double* __restrict__ pivstat) {
@@ -376,7 +350,7 @@ __device__ __forceinline__ void diag_factor_block(DiagLds<T>& S, const FrontDev&
     }
   }
   __syncthreads();
-  tri_inverses<T>(S, tid);
+  tri_inverses<T, NT>(S, tid);
   // global stores only now: a barrier waits for the stores issued before it
   if (tid < NB && rlog < kb) perm[f.piv_off + k0 + rlog] = k0 + r;
   if (tid == 0)  // one slot per diagonal block, in the order of the inverted blocks
@@ -384,8 +358,8 @@ __device__ __forceinline__ void diag_factor_block(DiagLds<T>& S, const FrontDev&
   // L^{-1}(a, b) = X_L(a, b) for a >= b; U^{-1}(a, b) = X_R(31-a, 31-b) for a <= b
   cplx<T>* Li = Dinv + f.dinv_off + (long long)(k0 / NB) * 2 * NB * NB;
 #pragma unroll
-  for (int u = 0; u < NB * NB / 256; ++u) {
-    const int e = tid + 256 * u;
+  for (int u = 0; u < NB * NB / NT; ++u) {
+    const int e = tid + NT * u;
     const int a = e % NB, b = e / NB;
     const bool in = a < kb && b < kb;
     Li[e] = in && a >= b ? S.x[0][a][b] : mk<T>(0, 0);
@@ -393,10 +367,13 @@ __device__ __forceinline__ void diag_factor_block(DiagLds<T>& S, const FrontDev&
   }
 }
 
-// First panel of a level (later panels are factored inside the previous
-// panel's trailing update, gemm_update_kernel with FUSE).
-template <typename T>
-__global__ void __launch_bounds__(256) diag_lu_kernel(cplx<T>* __restrict__ Fbuf, cplx<T>* __restrict__ Dinv,
+// Diagonal block of panel k0 (except those factored inside the previous
+// panel's trailing update, gemm_update_kernel with FUSE), one workgroup of
+// NT threads per front: 64 on levels with more than two fronts per CU (the
+// elimination is one wave's work, so one-wave workgroups spread the fronts
+// over all SIMDs), else 256 (the inverses then use four waves).
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) diag_lu_kernel(cplx<T>* __restrict__ Fbuf, cplx<T>* __restrict__ Dinv,
                                                       const FrontDev* __restrict__ fr, int* __restrict__ perm,
                                                       double* __restrict__ pivstat, int first, int k0) {
   static_assert(NB == 32, "lane layout assumes 32-wide panels");
@@ -407,19 +384,19 @@ __global__ void __launch_bounds__(256) diag_lu_kernel(cplx<T>* __restrict__ Fbuf
   const int m = f.p + f.q;
   const cplx<T>* F = Fbuf + f.f_off;
   const int tid = threadIdx.x;
-  cplx<T> v[NB * NB / 256];
+  cplx<T> v[NB * NB / NT];
 #pragma unroll
-  for (int u = 0; u < NB * NB / 256; ++u) {
-    const int e = tid + 256 * u, r = e % NB, c = e / NB;
+  for (int u = 0; u < NB * NB / NT; ++u) {
+    const int e = tid + NT * u, r = e % NB, c = e / NB;
     v[u] = F[(k0 + min(r, kb - 1)) + (long long)(k0 + min(c, kb - 1)) * m];
   }
 #pragma unroll
-  for (int u = 0; u < NB * NB / 256; ++u) {
-    const int e = tid + 256 * u, r = e % NB, c = e / NB;
+  for (int u = 0; u < NB * NB / NT; ++u) {
+    const int e = tid + NT * u, r = e % NB, c = e / NB;
     S.m[0][r][c] = r < kb && c < kb ? v[u] : mk<T>(r == c ? 1 : 0, 0);
   }
   __syncthreads();
-  diag_factor_block<T>(S, f, k0, kb, Dinv, perm, pivstat);
+  diag_factor_block<T, NT>(S, f, k0, kb, Dinv, perm, pivstat);
 }
 
 // Runs use(i, load(i)) for i = 0 .. N-1 (N and i compile-time after
@@ -622,7 +599,7 @@ __device__ __forceinline__ void update_and_factor_next(unsigned char* raw, const
     S.m[0][e % NB][e / NB] = ov[u];
   }
   __syncthreads();
-  diag_factor_block<T>(S, f, k1, kbn, Dinv, perm, pivstat);
+  diag_factor_block<T, 256>(S, f, k1, kbn, Dinv, perm, pivstat);
 }
 
 template <typename T, int TM, bool FUSE>
@@ -1208,9 +1185,14 @@ void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
     const bool fp64 = sizeof(T) == 8;
     bool factored = false;  // panel k0's diagonal block done by the previous update
     for (int k0 = 0; k0 < maxp; k0 += NB) {
-      if (!factored)
-        LSP_LAUNCH("diag_lu", (int)sizeof(cplx<T>), diag_lu_kernel<T>, dim3(cnt), dim3(256), 0, st, mf.F, mf.Dinv,
-                   mf.fronts, mf.perm, mf.pivstat, first, k0);
+      if (!factored) {
+        if (cnt > 512)  // more than two fronts per CU
+          LSP_LAUNCH("diag_lu", (int)sizeof(cplx<T>), (diag_lu_kernel<T, 64>), dim3(cnt), dim3(64), 0, st, mf.F,
+                     mf.Dinv, mf.fronts, mf.perm, mf.pivstat, first, k0);
+        else
+          LSP_LAUNCH("diag_lu", (int)sizeof(cplx<T>), (diag_lu_kernel<T, 256>), dim3(cnt), dim3(256), 0, st, mf.F,
+                     mf.Dinv, mf.fronts, mf.perm, mf.pivstat, first, k0);
+      }
       const int rem = maxm - k0 - 1;
       if (rem <= 0) continue;
       const int tiles = (rem + 63) / 64;

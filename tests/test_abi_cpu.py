@@ -100,3 +100,28 @@ def test_setup_rejects_bad_arguments_without_touching_gpu(lib):
     lib.lsp_last_error(buf, 256)
     assert b"omega" in buf.value
     assert lib.lsp_factor(None) == 1
+
+
+def test_lookahead_schedule_stats(lib):
+    """Lookahead bookkeeping of the factorisation schedule: a level's first
+    panel is never factored inside an update launch, so at most
+    panel_blocks - nfronts blocks are fused; the fused launches carry part of
+    the update flops; and smaller update tiles (more workgroups per launch)
+    never fuse more, since fusion needs every tile of the launch resident."""
+    p = L.Plan(256, 2, precision="mixed")
+    s = p.stats()
+    assert 0 < s["fused_blocks"] <= s["panel_blocks"] - s["nfronts"]
+    assert 0 < s["fused_update_flops"] < s["update_flops"]
+    nl = s["nlevels"]
+    fused = {}
+    for t in (32, 64, 128):
+        p.set_tiles([t] * nl)
+        fused[t] = p.stats()["fused_blocks"]
+    assert fused[32] <= fused[64] <= fused[128]
+    # n = 8 in 2D is a single front of 64 pivots (two panels, no boundary):
+    # the second panel's block is factored inside the first panel's update,
+    # which is the only update with any flops: 8 x 32^2 x 32
+    q = L.Plan(8, 2).stats()
+    assert q["nfronts"] == 1 and q["max_pivots"] == 64 and q["panel_blocks"] == 2
+    assert q["fused_blocks"] == 1
+    assert q["fused_update_flops"] == q["update_flops"] == 8 * 32 ** 2 * 32

@@ -135,10 +135,13 @@ def test_Q_and_M(n, d):
 
 
 @pytest.mark.parametrize("n,d,prec,tol", [(32, 2, "fp64", 1e-10), (64, 2, "fp64", 1e-10), (12, 3, "fp64", 1e-10),
-                                          (64, 2, "mixed", 1e-4)])
+                                          (64, 2, "mixed", 1e-4), (256, 2, "fp64", 1e-10), (256, 2, "mixed", 1e-4)])
 def test_solve_M_vs_superlu(n, d, prec, tol):
     """Multifrontal LU + triangular solves vs SuperLU: M^{-1} z, FP64 to 1e-10
-    relative (kappa(M)-scaled rounding), complex64 fronts to 1e-4."""
+    relative (kappa(M)-scaled rounding), complex64 fronts to 1e-4.  n = 256
+    covers the one-wave diagonal-block factorisation (levels of 1024 fronts),
+    the lookahead factorisation inside the trailing updates of the upper
+    levels and the 512-thread sweeps of the wide levels."""
     omega = 2 * np.pi * n / 8
     m = synth.medium_single_bump(n, d, 0.25, 0.12)
     lsp, torch, plan, pb = _problem(n, d, omega, m, max_nrhs=2, precision=prec)
