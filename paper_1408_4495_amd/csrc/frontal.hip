@@ -33,42 +33,54 @@ constexpr int NB = kNbMax;
 constexpr size_t kVecLds = 80 * 1024;  // LDS for a front's working vectors in the sweeps
 
 // ---------------------------------------------------------------- assembly
+// F = the rows / columns of M of the front's pivots (entry (r, c) with r or
+// c a pivot: M(i, j) when grid point j is a stencil neighbour of i, read
+// from the [N][3^d] stencil values) plus the children's Schur complements
+// (extend-add through their positions in this front).  One entry per thread,
+// 32-bit entry indices (the plan bounds m^2), neighbour test and stencil
+// slot from packed grid coordinates (no division by n).
 template <typename T>
 __global__ void __launch_bounds__(256) assemble_front_kernel(cplx<T>* __restrict__ Fbuf, const FrontDev* __restrict__ fr,
-                                                             const int* __restrict__ idx, const int* __restrict__ cpos,
-                                                             const double2* __restrict__ Mval, int first, int n,
-                                                             int d) {
+                                                             const int* __restrict__ idx,
+                                                             const unsigned* __restrict__ gpos,
+                                                             const int* __restrict__ cpos,
+                                                             const double2* __restrict__ Mval, int first, int d) {
   const FrontDev f = fr[first + blockIdx.y];
   const int m = f.p + f.q;
-  const long long mm = (long long)m * m;
+  const int mm = m * m;
   const int ns = d == 2 ? 9 : 27;
+  const int sh = d == 2 ? 16 : 10;
+  const unsigned mask = (1u << sh) - 1;
   cplx<T>* F = Fbuf + f.f_off;
   const int* id = idx + f.idx_off;
+  const unsigned* gp = gpos + f.idx_off;
   const int* cp = cpos + 2 * f.idx_off;
-  const cplx<T>* Fc[2] = {f.cfoff[0] >= 0 ? Fbuf + f.cfoff[0] : nullptr, f.cfoff[1] >= 0 ? Fbuf + f.cfoff[1] : nullptr};
-  const int mc[2] = {f.cm[0], f.cm[1]};
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < mm; e += (long long)gridDim.x * blockDim.x) {
-    int r = (int)(e % m), c = (int)(e / m);
+  const cplx<T>* Fc0 = Fbuf + (f.cfoff[0] >= 0 ? f.cfoff[0] : 0);
+  const cplx<T>* Fc1 = Fbuf + (f.cfoff[1] >= 0 ? f.cfoff[1] : 0);
+  const bool h0 = f.cfoff[0] >= 0, h1 = f.cfoff[1] >= 0;
+  const int mc0 = f.cm[0], mc1 = f.cm[1];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < mm; e += gridDim.x * blockDim.x) {
+    const int c = e / m, r = e - c * m;
     double2 v = make_double2(0, 0);
     if (r < f.p || c < f.p) {
-      int gi = id[r], gj = id[c];
+      const unsigned pi = gp[r], pj = gp[c];
       int slot = 0, m3 = 1;
       bool near = true;
-      int ai = gi, aj = gj;
       for (int a = 0; a < d; ++a) {
-        int di = aj % n - ai % n;
+        const int di = (int)((pj >> (sh * a)) & mask) - (int)((pi >> (sh * a)) & mask);
         near = near && di >= -1 && di <= 1;
         slot += (di + 1) * m3;
         m3 *= 3;
-        ai /= n; aj /= n;
       }
-      if (near) v = Mval[(long long)gi * ns + slot];
+      if (near) v = Mval[(long long)id[r] * ns + slot];
     }
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      if (!Fc[k]) continue;
-      int pr = cp[2 * r + k], pc = cp[2 * c + k];
-      if (pr >= 0 && pc >= 0) v = cadd(v, widen(Fc[k][pr + (long long)pc * mc[k]]));
+    if (h0) {
+      const int pr = cp[2 * r], pc = cp[2 * c];
+      if (pr >= 0 && pc >= 0) v = cadd(v, widen(Fc0[pr + pc * mc0]));
+    }
+    if (h1) {
+      const int pr = cp[2 * r + 1], pc = cp[2 * c + 1];
+      if (pr >= 0 && pc >= 0) v = cadd(v, widen(Fc1[pr + pc * mc1]));
     }
     F[e] = from_c128<cplx<T>>(v);
   }
@@ -1180,8 +1192,8 @@ void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
     const int maxp = plan.level_maxp[l];
     long long mm = (long long)maxm * maxm;
     int gx = (int)std::min<long long>((mm + 255) / 256, 4096);  // one element per thread up to 1M-entry fronts
-    LSP_LAUNCH("assemble_front", (int)sizeof(cplx<T>), assemble_front_kernel<T>, dim3(gx, cnt), dim3(256), 0, st, mf.F, mf.fronts, mf.idx, mf.cpos,
-                       mf.Mval, first, plan.n, plan.d);
+    LSP_LAUNCH("assemble_front", (int)sizeof(cplx<T>), assemble_front_kernel<T>, dim3(gx, cnt), dim3(256), 0, st, mf.F,
+               mf.fronts, mf.idx, mf.gpos, mf.cpos, mf.Mval, first, plan.d);
     const bool fp64 = sizeof(T) == 8;
     bool factored = false;  // panel k0's diagonal block done by the previous update
     for (int k0 = 0; k0 < maxp; k0 += NB) {

@@ -62,6 +62,7 @@ struct MfDev {
   cplx<T>* Dinv;            // inverted diagonal panel blocks
   const FrontDev* fronts;
   const int* idx;
+  const unsigned* gpos;     // packed grid coordinates of the idx entries
   const int* cpos;
   const double2* Mval;      // [N][3^d]
   int* perm;                // per panel row: the front row it came from

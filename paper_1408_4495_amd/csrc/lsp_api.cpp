@@ -30,6 +30,7 @@ struct PlanDev {
   void* block = nullptr;
   FrontDev* fronts = nullptr;
   int* idx = nullptr;
+  unsigned* gpos = nullptr;
   int* cpos = nullptr;
   ClassGeom* geo = nullptr;
   double2* tw64 = nullptr;
@@ -111,6 +112,7 @@ struct ProblemPtrs {
   void* Dinv;
   FrontDev* fronts;
   int* idx;
+  unsigned* gpos;
   int* cpos;
   int* perm;
   double* pivstat;
@@ -152,16 +154,18 @@ const PlanDev& plan_device(const lsp_plan* pl, int device) {
   const Plan& P = pl->p;
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t bf = up(P.fronts.size() * sizeof(FrontDev)), bi = up(P.idx.size() * sizeof(int)),
-               bc = up(P.cpos.size() * sizeof(int)), bg = up(pl->geo.size() * sizeof(ClassGeom)),
-               bt = up(P.L * sizeof(double2)), bt32 = up(P.L * sizeof(float2));
+               bp = up(P.gpos.size() * sizeof(unsigned)), bc = up(P.cpos.size() * sizeof(int)),
+               bg = up(pl->geo.size() * sizeof(ClassGeom)), bt = up(P.L * sizeof(double2)),
+               bt32 = up(P.L * sizeof(float2));
   PlanDev d;
-  if (hipMalloc(&d.block, bf + bi + bc + bg + bt + bt32) != hipSuccess) {
+  if (hipMalloc(&d.block, bf + bi + bp + bc + bg + bt + bt32) != hipSuccess) {
     (void)hipGetLastError();
     throw Error(LSP_ERR_OOM, "device allocation of the plan arrays failed");
   }
   char* b = (char*)d.block;
   d.fronts = (FrontDev*)b; b += bf;
   d.idx = (int*)b; b += bi;
+  d.gpos = (unsigned*)b; b += bp;
   d.cpos = (int*)b; b += bc;
   d.geo = (ClassGeom*)b; b += bg;
   d.tw64 = (double2*)b; b += bt;
@@ -178,6 +182,7 @@ const PlanDev& plan_device(const lsp_plan* pl, int device) {
   try {
     LSP_HIP(hipMemcpy(d.fronts, P.fronts.data(), P.fronts.size() * sizeof(FrontDev), hipMemcpyHostToDevice));
     LSP_HIP(hipMemcpy(d.idx, P.idx.data(), P.idx.size() * sizeof(int), hipMemcpyHostToDevice));
+    LSP_HIP(hipMemcpy(d.gpos, P.gpos.data(), P.gpos.size() * sizeof(unsigned), hipMemcpyHostToDevice));
     LSP_HIP(hipMemcpy(d.cpos, P.cpos.data(), P.cpos.size() * sizeof(int), hipMemcpyHostToDevice));
     LSP_HIP(hipMemcpy(d.geo, pl->geo.data(), pl->geo.size() * sizeof(ClassGeom), hipMemcpyHostToDevice));
     LSP_HIP(hipMemcpy(d.tw64, tw64.data(), P.L * sizeof(double2), hipMemcpyHostToDevice));
@@ -464,12 +469,12 @@ void apply_precond(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2*
   hipStream_t st = pb->st;
   if (pb->precision == LSP_FP64) {
     launch_applyQ<double2>((double2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
-    MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.perm,
+    MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                      pb->d.pivstat};
     mf_solve<double>(mf, P, nrhs, (const double2*)s.zq, out, (double2*)s.vbuf, st);
   } else {
     launch_applyQ<float2>((float2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
-    MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.perm,
+    MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                     pb->d.pivstat};
     mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st);
     launch_widen(out, (const float2*)s.xs, (long long)nrhs * P.N, st);
@@ -480,12 +485,12 @@ void solve_M(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2* z, do
   const Plan& P = pb->plan->p;
   hipStream_t st = pb->st;
   if (pb->precision == LSP_FP64) {
-    MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.perm,
+    MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                      pb->d.pivstat};
     mf_solve<double>(mf, P, nrhs, z, x, (double2*)s.vbuf, st);
   } else {
     launch_narrow((float2*)s.zq, z, (long long)nrhs * P.N, st);
-    MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.perm,
+    MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                     pb->d.pivstat};
     mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st);
     launch_widen(x, (const float2*)s.xs, (long long)nrhs * P.N, st);
@@ -640,6 +645,7 @@ lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, vo
     const PlanDev& pd = plan_device(plan, pb->device);
     pb->d.fronts = pd.fronts;
     pb->d.idx = pd.idx;
+    pb->d.gpos = pd.gpos;
     pb->d.cpos = pd.cpos;
     pb->d.geo = pd.geo;
     pb->d.tw64 = pd.tw64;
@@ -670,11 +676,11 @@ lsp_status lsp_factor(lsp_problem* pb) {
     LSP_REQUIRE(pb != nullptr, "null problem");
     const Plan& P = pb->plan->p;
     if (pb->precision == LSP_FP64) {
-      MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.perm,
+      MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                        pb->d.pivstat};
       mf_factor<double>(mf, P, pb->st);
     } else {
-      MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.cpos, pb->d.Mval, pb->d.perm,
+      MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                       pb->d.pivstat};
       mf_factor<float>(mf, P, pb->st);
     }

@@ -208,6 +208,20 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
   P.dinv_elems = dinv_off;
   P.sum_p = piv_off;
   P.sum_pq = (long long)P.idx.size();
+  LSP_REQUIRE((long long)P.max_front * P.max_front < (1LL << 31), "front too large for 32-bit entry indices");
+  {
+    const int sh = gpos_shift(d);
+    P.gpos.resize(P.idx.size());
+    for (size_t k = 0; k < P.idx.size(); ++k) {
+      long long g = P.idx[k];
+      unsigned packed = 0;
+      for (int a = 0; a < d; ++a) {
+        packed |= (unsigned)(g % n) << (sh * a);
+        g /= n;
+      }
+      P.gpos[k] = packed;
+    }
+  }
   LSP_REQUIRE(P.sum_p == P.N, "nested dissection lost grid points");
 
   // Extend-add maps: for each front position, where the same grid point sits

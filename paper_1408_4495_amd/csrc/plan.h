@@ -32,6 +32,8 @@ struct Plan {
   lsp_options opts{};
   std::vector<FrontDev> fronts;   // sorted by level (leaves first)
   std::vector<int> idx;           // concatenated [I | B] lists, grid linear indices
+  std::vector<unsigned> gpos;     // grid coordinates of each idx entry, packed
+                                  // (gpos_shift(d) bits per axis, axis 0 lowest)
   std::vector<int> cpos;          // per front position: 2 ints, position of the
                                   // same grid point in child 0 / child 1 front, or -1
   std::vector<int> level_ptr;     // fronts of level l are [level_ptr[l], level_ptr[l+1])
@@ -47,6 +49,10 @@ struct Plan {
   double panel_blocks = 0.0;  // sum over fronts of ceil(p / nb)
   std::vector<int> radices;       // FFT radices for L, in pass order
 };
+
+// Bits per axis of a packed grid position: 16 in 2D (n <= 4096), 10 in 3D
+// (N <= 2^28, so n <= 645).
+inline int gpos_shift(int d) { return d == 2 ? 16 : 10; }
 
 // Builds the plan; throws lsp::Error on invalid input.
 void build_plan(Plan& plan, int n, int d, int max_nrhs, const lsp_options& opts);
