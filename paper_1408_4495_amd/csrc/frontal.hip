@@ -962,7 +962,13 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
   static_assert(TPB == 256 || TPB == 512, "256 or 512 threads");
   constexpr int G = TPB / NB;  // column groups
   constexpr int IPT = NB * NB / TPB;  // inverse-block entries per thread
-  constexpr int TU = sizeof(T) == 8 ? 16 : 32;  // U12 columns per thread held in flight
+  // With 512 threads, complex64, one right-hand side and the vectors in LDS
+  // the registers allow a second U12 buffer of 24 columns per thread (384
+  // per pass): each panel
+  // then loads the next (lower) panel's block, so its latency overlaps the
+  // current panel.
+  constexpr bool DB = TPB == 512 && NR == 1 && sizeof(T) == 4 && VL;
+  constexpr int TU = DB ? 24 : (sizeof(T) == 8 ? 16 : 32);  // U12 columns per thread held in flight
   extern __shared__ unsigned char smem_raw[];
   __shared__ cplx<T> Ui[2][NB][NB + 1];
   __shared__ cplx<T> part[G][NR][NB];
@@ -985,6 +991,17 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
   const cplx<T>* Ug0 = Dinv + f.dinv_off + (long long)(nblk - 1) * 2 * NB * NB + NB * NB;
   const cplx<T> ui0 = Ug0[tid], ui1 = Ug0[tid + TPB];
   const cplx<T> ui2 = IPT > 2 ? Ug0[tid + 2 * TPB] : ui0, ui3 = IPT > 2 ? Ug0[tid + 3 * TPB] : ui0;
+  const int j = tid % NB, grp = tid / NB;
+  // U12 block of a panel (first TU columns of this thread): loaded at the
+  // panel start, or with DB one panel ahead (with 256 threads a second
+  // buffer would spill)
+  auto load_u = [&](const int bp, cplx<T>(&dst)[TU]) {
+    const int k0p = bp * NB, kbp = min(NB, f.p - k0p), k1p = k0p + kbp;
+#pragma unroll
+    for (int t = 0; t < TU; ++t) dst[t] = F[(k0p + min(j, kbp - 1)) + (long long)min(k1p + grp + G * t, m - 1) * m];
+  };
+  cplx<T> ucol[TU], ucol2[DB ? TU : 1];
+  if constexpr (DB) load_u(nblk - 1, ucol);  // before the gathers below, so the two overlap
   // v = [y(I) from the forward sweep; x(B) from the ancestors]
   for (int e = tid; e < m * nr; e += TPB) {
     const int r = e % m, k = e / m;
@@ -1000,17 +1017,7 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
       Ui[cb][tid % NB][tid / NB + 3 * TPB / NB] = ui3;
     }
   }
-  const int j = tid % NB, grp = tid / NB;
-  // U12 block of a panel (first TU columns of this thread), loaded at the
-  // panel start (loading the next panel's block during the current one was
-  // measured slower: the second buffer spills)
-  auto load_u = [&](const int bp, cplx<T>(&dst)[TU]) {
-    const int k0p = bp * NB, kbp = min(NB, f.p - k0p), k1p = k0p + kbp;
-#pragma unroll
-    for (int t = 0; t < TU; ++t) dst[t] = F[(k0p + min(j, kbp - 1)) + (long long)min(k1p + grp + G * t, m - 1) * m];
-  };
-  cplx<T> ucol[TU];
-  auto panel = [&](const int b, cplx<T>(&u)[TU]) {
+  auto panel = [&](const int b, cplx<T>(&u)[TU], cplx<T>(&un)[DB ? TU : 1]) {
     const int k0 = b * NB;
     const int kb = min(NB, f.p - k0);
     const int k1 = k0 + kb;
@@ -1022,7 +1029,10 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
     const cplx<T> uin0 = Ugn[tid], uin1 = Ugn[tid + TPB];
     const cplx<T> uin2 = IPT > 2 ? Ugn[tid + 2 * TPB] : uin0, uin3 = IPT > 2 ? Ugn[tid + 3 * TPB] : uin0;
     const int gi = id[k0 + min(tid / 8, kb - 1)];  // grid index of row tid / 8, for writing x
-    load_u(b, u);
+    if constexpr (DB)
+      load_u(b > 0 ? b - 1 : b, un);  // unconditional: the last panel reloads its own block (unused)
+    else
+      load_u(b, u);
     __syncthreads();  // x(k1:m) of the previous panel is in place; Ui[cur ^ 1] is free
     Ui[cur ^ 1][tid % NB][tid / NB] = uin0;
     Ui[cur ^ 1][tid % NB][tid / NB + TPB / NB] = uin1;
@@ -1074,7 +1084,14 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
       }
     }
   };
-  for (int b = nblk - 1; b >= 0; --b) panel(b, ucol);
+  if constexpr (DB) {
+    for (int b = nblk - 1; b >= 0; b -= 2) {
+      panel(b, ucol, ucol2);
+      if (b >= 1) panel(b - 1, ucol2, ucol);
+    }
+  } else {
+    for (int b = nblk - 1; b >= 0; --b) panel(b, ucol, ucol2);
+  }
 }
 
 inline bool wide_level(const Plan& plan, int l) { return plan.level_maxpq[l] > 256 + NB; }
