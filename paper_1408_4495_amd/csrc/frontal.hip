@@ -445,18 +445,37 @@ __device__ __forceinline__ void chunked(Load&& load, Use&& use) {
 
 
 // ---------------------------------------------------------------- panel products
+// ---------------------------------------------------------------- MFMA helpers
+// Operand layout of the 16x16x4 MFMAs: lane l supplies A(l%16, l/16) and
+// B(l/16, l%16).  Results: the FP32 form returns D(4*(l/16)+v, l%16), the
+// FP64 form D(l/16+4v, l%16), v = 0..3 (checked on gfx950).
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  using acc_t = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+  __device__ static acc_t step(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lk, int v) { return lk + 4 * v; }
+};
+template <> struct Mfma<float> {
+  using acc_t = __attribute__((__vector_size__(4 * sizeof(float)))) float;
+  __device__ static acc_t step(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lk, int v) { return 4 * lk + v; }
+};
+
+
 // blockIdx.z == 0: U12(:, tile) = L11^{-1} P F12(:, tile), 64 columns per block.
 // blockIdx.z == 1: L21(tile, :) = F21(tile, :) U11^{-1}, 64 rows per block.
 // Every load is issued before the first LDS store (clamped in-range indices,
-// invalid entries zeroed after the load); each thread then forms eight
-// outputs with full 32-term sums (the inverses are exactly zero outside
-// their triangle and outside the kb x kb block).
+// invalid entries zeroed after the load); the products run on the 16x16x4
+// MFMAs (complex as four real products; the inverses are exactly zero
+// outside their triangle and outside the kb x kb block), each wave one
+// 16-wide slice of the tile, and the results go back through LDS so the
+// stores are coalesced.
 template <typename T>
 __global__ void __launch_bounds__(256) panel_trsm_kernel(cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
                                                          const FrontDev* __restrict__ fr, const int* __restrict__ perm,
                                                          int first, int k0) {
-  __shared__ cplx<T> Di[NB][NB + 1];
-  __shared__ cplx<T> Tt[64][NB + 1];
+  __shared__ T Dr[NB][NB + 1], Dq[NB][NB + 1];  // inverse block [row][col], real / imaginary parts
+  __shared__ T Tr[64][NB + 1], Tq[64][NB + 1];  // upper: [c][j] = (P F12)(j, c); lower: [r][i] = F21(r, i)
   const FrontDev f = fr[first + blockIdx.y];
   if (f.p <= k0) return;
   const int kb = min(NB, f.p - k0);
@@ -474,7 +493,6 @@ __global__ void __launch_bounds__(256) panel_trsm_kernel(cplx<T>* __restrict__ F
 #pragma unroll
   for (int u = 0; u < 4; ++u) dv[u] = Dm[tid + 256 * u];
   if (upper) {
-    // Tt[c][j] = (P F12)(j, t0 + c): j = tid % 32 is fixed per thread
     const int j = tid % NB;
     const int pj = perm[f.piv_off + k0 + min(j, kb - 1)];
 #pragma unroll
@@ -484,9 +502,11 @@ __global__ void __launch_bounds__(256) panel_trsm_kernel(cplx<T>* __restrict__ F
       tv[u] = j < kb && c < cnt ? v : mk<T>(0, 0);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) Tt[tid / NB + 8 * u][j] = tv[u];
+    for (int u = 0; u < 8; ++u) {
+      Tr[tid / NB + 8 * u][j] = tv[u].x;
+      Tq[tid / NB + 8 * u][j] = tv[u].y;
+    }
   } else {
-    // Tt[r][i] = F21(t0 + r, i): r = tid % 64 is fixed per thread
     const int r = tid % 64;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -495,46 +515,84 @@ __global__ void __launch_bounds__(256) panel_trsm_kernel(cplx<T>* __restrict__ F
       tv[u] = r < cnt && i < kb ? v : mk<T>(0, 0);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) Tt[r][tid / 64 + 4 * u] = tv[u];
+    for (int u = 0; u < 8; ++u) {
+      Tr[r][tid / 64 + 4 * u] = tv[u].x;
+      Tq[r][tid / 64 + 4 * u] = tv[u].y;
+    }
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int e = tid + 256 * u;
-    Di[e % NB][e / NB] = dv[u];
+    const int e = tid + 256 * u;  // the inverse is stored column-major
+    Dr[e % NB][e / NB] = dv[u].x;
+    Dq[e % NB][e / NB] = dv[u].y;
   }
   __syncthreads();
-  cplx<T> acc[8];
+  using acc_t = typename Mfma<T>::acc_t;
+  const int wave = tid / 64, lane = tid % 64, li = lane % 16, lk = lane / 16;
+  acc_t cr[2], ci[2];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) acc[u] = mk<T>(0, 0);
-  // runtime loops over the term index (unrolled by 4) keep the LDS reads in
-  // flight bounded; the eight accumulators are independent
+  for (int blk = 0; blk < 2; ++blk)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { cr[blk][v] = 0; ci[blk][v] = 0; }
   if (upper) {
-    // U12(i, c) = sum_j Linv(i, j) Tt[c][j], c = tid / 32 + 8u
-    const int i = tid % NB;
-#pragma unroll 4
-    for (int j = 0; j < NB; ++j) {
-      const cplx<T> dij = Di[i][j];
+    // U12(i, c) = sum_j Linv(i, j) Tt[c][j]: this wave's columns c = 16 wave + li, rows in two blocks
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] = cfma(acc[u], dij, Tt[tid / NB + 8 * u][j]);
+    for (int k4 = 0; k4 < NB; k4 += 4) {
+      const int kk = k4 + lk;
+      const T br = Tr[16 * wave + li][kk], bi = Tq[16 * wave + li][kk];
+#pragma unroll
+      for (int blk = 0; blk < 2; ++blk) {
+        const T ar = Dr[16 * blk + li][kk], ai = Dq[16 * blk + li][kk];
+        cr[blk] = Mfma<T>::step(ar, br, cr[blk]);
+        cr[blk] = Mfma<T>::step(-ai, bi, cr[blk]);
+        ci[blk] = Mfma<T>::step(ar, bi, ci[blk]);
+        ci[blk] = Mfma<T>::step(ai, br, ci[blk]);
+      }
     }
+  } else {
+    // L21(r, j) = sum_i Tt[r][i] Uinv(i, j): this wave's rows r = 16 wave + li, columns in two blocks
+#pragma unroll
+    for (int k4 = 0; k4 < NB; k4 += 4) {
+      const int kk = k4 + lk;
+      const T ar = Tr[16 * wave + li][kk], ai = Tq[16 * wave + li][kk];
+#pragma unroll
+      for (int blk = 0; blk < 2; ++blk) {
+        const T br = Dr[kk][16 * blk + li], bi = Dq[kk][16 * blk + li];
+        cr[blk] = Mfma<T>::step(ar, br, cr[blk]);
+        cr[blk] = Mfma<T>::step(-ai, bi, cr[blk]);
+        ci[blk] = Mfma<T>::step(ar, bi, ci[blk]);
+        ci[blk] = Mfma<T>::step(ai, br, ci[blk]);
+      }
+    }
+  }
+  __syncthreads();  // the tile has been read: its LDS now stages the results
+#pragma unroll
+  for (int blk = 0; blk < 2; ++blk)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rr = Mfma<T>::row(lk, v);
+      if (upper) {  // result (row 16 blk + rr, column 16 wave + li), staged as [column][row]
+        Tr[16 * wave + li][16 * blk + rr] = cr[blk][v];
+        Tq[16 * wave + li][16 * blk + rr] = ci[blk][v];
+      } else {  // result (row 16 wave + rr, column 16 blk + li), staged as [row][column]
+        Tr[16 * wave + rr][16 * blk + li] = cr[blk][v];
+        Tq[16 * wave + rr][16 * blk + li] = ci[blk][v];
+      }
+    }
+  __syncthreads();
+  if (upper) {
+    const int i = tid % NB;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int c = tid / NB + 8 * u;
-      if (i < kb && c < cnt) F[(k0 + i) + (long long)(k1 + t0 + c) * m] = acc[u];
+      if (i < kb && c < cnt) F[(k0 + i) + (long long)(k1 + t0 + c) * m] = mk<T>(Tr[c][i], Tq[c][i]);
     }
   } else {
-    // L21(r, j) = sum_i Tt[r][i] Uinv(i, j), j = tid / 64 + 4u (uniform per wave)
     const int r = tid % 64;
-#pragma unroll 4
-    for (int i = 0; i < NB; ++i) {
-      const cplx<T> tri = Tt[r][i];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] = cfma(acc[u], tri, Di[i][tid / 64 + 4 * u]);
-    }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int j = tid / 64 + 4 * u;
-      if (r < cnt && j < kb) F[(k1 + t0 + r) + (long long)(k0 + j) * m] = acc[u];
+      if (r < cnt && j < kb) F[(k1 + t0 + r) + (long long)(k0 + j) * m] = mk<T>(Tr[r][j], Tq[r][j]);
     }
   }
 }
@@ -543,21 +601,6 @@ __global__ void __launch_bounds__(256) panel_trsm_kernel(cplx<T>* __restrict__ F
 // C (m-k1 x m-k1 block at (k1,k1)) -= A (panel rows below, m-k1 x kb) * B (kb x m-k1).
 // 64x64 output tile per workgroup of 4 waves; each wave owns 32x32 as 2x2
 // MFMA 16x16 blocks with separate real and imaginary accumulators.
-// Operand layout of the 16x16x4 MFMAs: lane l supplies A(l%16, l/16) and
-// B(l/16, l%16).  Results: the FP32 form returns D(4*(l/16)+v, l%16), the
-// FP64 form D(l/16+4v, l%16), v = 0..3 (checked on gfx950).
-template <typename T> struct Mfma;
-template <> struct Mfma<double> {
-  using acc_t = __attribute__((__vector_size__(4 * sizeof(double)))) double;
-  __device__ static acc_t step(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  __device__ static int row(int lk, int v) { return lk + 4 * v; }
-};
-template <> struct Mfma<float> {
-  using acc_t = __attribute__((__vector_size__(4 * sizeof(float)))) float;
-  __device__ static acc_t step(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  __device__ static int row(int lk, int v) { return 4 * lk + v; }
-};
-
 template <typename T, int TM>
 struct GemmLds {
   T Ar[NB][TM], Ai[NB][TM], Br[NB][TM + 1], Bi[NB][TM + 1];
