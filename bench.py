@@ -143,9 +143,10 @@ def kernel_model(name, st, w, nrhs):
         # and the N-vector it produces; spread over nlevels launches
         per_app = st["sweep_entries"] * esz + 2 * N * esz * nrhs
         return "hbm", per_app / nlev, "GB/s"
-    if base in ("gemm_update", "update_lu"):
-        # update_lu: trailing update fused with the next panel's diagonal
-        # block factorisation (one extra workgroup, its work not counted)
+    if base == "gemm_update":
+        # the plain trailing-update launches (the update launches that also
+        # factor a diagonal block, update_lu and panel_step, are bound by
+        # that factorisation's latency and carry no separate model)
         return "mfma", None, "TFLOP/s"
     if base == "diag_lu":
         # per 32 x 32 block: complex LU (sum_j (31-j)^2 multiply-adds) and the
@@ -198,10 +199,9 @@ def measure_roofline(lsp, torch, w, m_dev, u_dev, prec):
         avg_s = ms / cnt / 1e3
         fp64 = "[c64]" not in name
         if bound == "mfma":
-            # all launches of one factorisation, split between the plain and
-            # the fused (lookahead) update launches
-            fused = st["fused_update_flops"]
-            flops = fused if name.startswith("update_lu") else st["update_flops"] - fused
+            # the update flops of one factorisation outside the launches
+            # that also factor a diagonal block
+            flops = st["update_flops"] - st["fused_update_flops"]
             achieved = flops / (ms / 1e3) / 1e12
             peak = 78.6 if fp64 else 157.3      # dense FP64 / FP32 matrix cores
             amount = flops / cnt

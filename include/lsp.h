@@ -99,11 +99,14 @@ typedef struct {
                                  F22 -= L21 U12 (the MFMA part of the factor) */
   double panel_blocks;        /* diagonal-block factorisations per lsp_factor:
                                  the sum over fronts of ceil(p / panel) */
-  double fused_blocks;        /* of those, the ones factored inside the
-                                 previous panel's trailing-update launch
-                                 (lookahead; depends on the tile table and
-                                 the plan's precision) */
-  double fused_update_flops;  /* of update_flops, the part in those launches */
+  double fused_blocks;        /* of those, the ones not factored by a
+                                 diagonal-block launch of their own: inside
+                                 the previous panel's update launch
+                                 (lookahead) or by the panel-strip launches
+                                 of the upper levels (complex64); depends on
+                                 the tile table and the plan's precision */
+  double fused_update_flops;  /* of update_flops, the part in update
+                                 launches that also factor a block */
 } lsp_plan_stats;
 
 typedef struct lsp_plan lsp_plan;        /* opaque; host-side, plus one device copy of

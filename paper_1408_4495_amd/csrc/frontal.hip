@@ -127,6 +127,7 @@ struct DiagLds {
   cplx<T> m[2][NB][NB + 1];  // the block's rows, then the factors L and R
   cplx<T> x[2][NB][NB + 1];  // L^{-1} and R^{-1}
   cplx<T> p[2][3][8][8];     // partial products of the blockwise inversion
+  int src[NB];               // src[j]: the block row chosen as the j-th pivot
 };
 
 // The block factorisation runs in one wave.  LDS operations of a wave are
@@ -335,7 +336,7 @@ __device__ __forceinline__ void tri_inverses(DiagLds<T>& S, const int tid) {
 template <typename T, int NT>
 __device__ __forceinline__ void diag_factor_block(DiagLds<T>& S, const FrontDev& f, const int k0, const int kb,
                                                   cplx<T>* __restrict__ Dinv, int* __restrict__ perm,
-                                                  double* __restrict__ pivstat) {
+                                                  double* __restrict__ pivstat, const bool write = true) {
   const int tid = threadIdx.x;
   const int r = tid & (NB - 1), h = tid / NB;
   int rlog = -1;
@@ -359,10 +360,12 @@ __device__ __forceinline__ void diag_factor_block(DiagLds<T>& S, const FrontDev&
     if (h == 0) {  // after the row writes above, in issue order
       S.m[0][rlog][rlog] = mk<T>(1, 0);
       S.m[1][NB - 1 - rlog][NB - 1 - rlog] = myinv;
+      S.src[rlog] = r;
     }
   }
   __syncthreads();
   tri_inverses<T, NT>(S, tid);
+  if (!write) return;
   // global stores only now: a barrier waits for the stores issued before it
   if (tid < NB && rlog < kb) perm[f.piv_off + k0 + rlog] = k0 + r;
   if (tid == 0)  // one slot per diagonal block, in the order of the inverted blocks
@@ -606,6 +609,96 @@ struct GemmLds {
   T Ar[NB][TM], Ai[NB][TM], Br[NB][TM + 1], Bi[NB][TM + 1];
 };
 
+// One TM x TM tile of C -= A B over the block [base, m)^2 of a front's
+// trailing matrix: A = the L21 rows (columns k0 .. k0+kb), B = the U12
+// columns (rows k0 .. k0+kb) of the panel; (row0, col0) relative to base;
+// entries with row < skip and column < skip are left alone.  4 waves in a
+// 2x2 arrangement, each wave (TM/2)^2 as BW x BW MFMA 16x16 blocks.
+template <typename T, int TM>
+__device__ __forceinline__ void update_tile(GemmLds<T, TM>& G, cplx<T>* __restrict__ F, const int k0, const int kb,
+                                            const int base, const int m, const int row0, const int col0,
+                                            const int skip) {
+  constexpr int BW = TM / 32;
+  auto& Ar = G.Ar;
+  auto& Ai = G.Ai;
+  auto& Br = G.Br;
+  auto& Bi = G.Bi;
+  const int rem = m - base;
+  const int tid = threadIdx.x;
+  const int kpad = (kb + 3) & ~3;
+  // both operand tiles are loaded before the first LDS store (clamped
+  // in-range indices, zero outside the block), so the loads overlap
+  constexpr int LA = TM * NB / 256;
+  cplx<T> va[LA], vb[LA];
+#pragma unroll
+  for (int u = 0; u < LA; ++u) {
+    const int e = tid + 256 * u, r = e % TM, kk = e / TM;
+    const cplx<T> v = F[(base + min(row0 + r, rem - 1)) + (long long)(k0 + min(kk, kb - 1)) * m];
+    va[u] = row0 + r < rem && kk < kb ? v : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int u = 0; u < LA; ++u) {
+    const int e = tid + 256 * u, kk = e % NB, c = e / NB;
+    const cplx<T> v = F[(k0 + min(kk, kb - 1)) + (long long)(base + min(col0 + c, rem - 1)) * m];
+    vb[u] = col0 + c < rem && kk < kb ? v : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int u = 0; u < LA; ++u) {
+    const int e = tid + 256 * u;
+    Ar[e / TM][e % TM] = va[u].x;
+    Ai[e / TM][e % TM] = va[u].y;
+    Br[e % NB][e / NB] = vb[u].x;
+    Bi[e % NB][e / NB] = vb[u].y;
+  }
+  __syncthreads();
+  using acc_t = typename Mfma<T>::acc_t;
+  const int wave = tid / 64, lane = tid % 64;
+  const int wr = (wave / 2) * (TM / 2), wc = (wave % 2) * (TM / 2);
+  acc_t accr[BW][BW], acci[BW][BW];
+  for (int i = 0; i < BW; ++i)
+    for (int j = 0; j < BW; ++j)
+      for (int v = 0; v < 4; ++v) { accr[i][j][v] = 0; acci[i][j][v] = 0; }
+  const int li = lane % 16, lk = lane / 16;
+  for (int k4 = 0; k4 < kpad; k4 += 4) {
+    T ar[BW], ai[BW], br[BW], bi[BW];
+    for (int i = 0; i < BW; ++i) { ar[i] = Ar[k4 + lk][wr + 16 * i + li]; ai[i] = Ai[k4 + lk][wr + 16 * i + li]; }
+    for (int j = 0; j < BW; ++j) { br[j] = Br[k4 + lk][wc + 16 * j + li]; bi[j] = Bi[k4 + lk][wc + 16 * j + li]; }
+    for (int i = 0; i < BW; ++i)
+      for (int j = 0; j < BW; ++j) {
+        accr[i][j] = Mfma<T>::step(ar[i], br[j], accr[i][j]);
+        accr[i][j] = Mfma<T>::step(-ai[i], bi[j], accr[i][j]);
+        acci[i][j] = Mfma<T>::step(ar[i], bi[j], acci[i][j]);
+        acci[i][j] = Mfma<T>::step(ai[i], br[j], acci[i][j]);
+      }
+  }
+  // C -= A B: per 16-row block i, all BW x 4 loads of C first, then the stores
+#pragma unroll
+  for (int i = 0; i < BW; ++i) {
+    cplx<T> cv[BW][4];
+#pragma unroll
+    for (int j = 0; j < BW; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = min(col0 + wc + 16 * j + li, rem - 1);
+        const int row = min(row0 + wr + 16 * i + Mfma<T>::row(lk, v), rem - 1);
+        cv[j][v] = F[(base + row) + (long long)(base + col) * m];
+      }
+#pragma unroll
+    for (int j = 0; j < BW; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = col0 + wc + 16 * j + li;
+        const int row = row0 + wr + 16 * i + Mfma<T>::row(lk, v);
+        if (col < rem && row < rem && !(row < skip && col < skip)) {
+          cplx<T> c = cv[j][v];
+          c.x -= accr[i][j][v];
+          c.y -= acci[i][j][v];
+          F[(base + row) + (long long)(base + col) * m] = c;
+        }
+      }
+  }
+}
+
 // Lookahead (FUSE): the next panel's diagonal block depends only on this
 // update of its own 32 x 32 entries, so workgroup (0, 0) of each front
 // applies that part of the update itself (block = F - L21 U12 over the
@@ -669,10 +762,6 @@ __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ 
                                                                              : sizeof(GemmLds<T, TM>);
   __shared__ __align__(16) unsigned char raw[kRaw];
   GemmLds<T, TM>& G = *reinterpret_cast<GemmLds<T, TM>*>(raw);
-  auto& Ar = G.Ar;
-  auto& Ai = G.Ai;
-  auto& Br = G.Br;
-  auto& Bi = G.Bi;
   const FrontDev f = fr[first + blockIdx.z];
   if (f.p <= k0) return;
   const int kb = min(NB, f.p - k0);
@@ -692,79 +781,201 @@ __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ 
   const int skip = FUSE ? max(0, min(NB, f.p - k1)) : 0;
   const int row0 = brow * TM, col0 = blockIdx.x * TM;
   if (row0 >= rem || col0 >= rem) return;
+  update_tile<T, TM>(G, F, k0, kb, k1, m, row0, col0, skip);
+}
+
+// ---------------------------------------------------------------- panel strips
+// One launch per panel step on levels where every workgroup of the step is
+// resident at once (few fronts, the upper levels).  The step of panel b
+// updates the trailing matrix outside panel b+1's rows and columns on MFMA
+// tiles, while "strip" workgroups, one per 32-wide chunk of panel b+1's
+// column strip (rows below the panel) or row strip (columns right of it),
+// each apply panel b's update to their chunk and to panel b+1's diagonal
+// block, factor that block (every strip workgroup of the front computes the
+// same factorisation, so none waits for another; the first one stores it),
+// and solve their chunk: L21 = chunk U11^{-1} or U12 = L11^{-1} P chunk.
+// The step of panel b+1 then finds everything it reads in memory.
+
+template <typename T>
+struct StripLds {
+  DiagLds<T> d;
+  cplx<T> a[NB][NB + 1];  // previous panel's L21 rows of this panel  [row][k]
+  cplx<T> b[NB][NB + 1];  // previous panel's U12 columns of this panel [k][column]
+  cplx<T> t[NB][NB + 1];  // this workgroup's chunk [row][column]
+  cplx<T> o[NB][NB + 1];  // the chunk's previous-panel operand, then the solved chunk
+};
+
+// (cr, ci) = the wave's 16 x 16 block (row block wave / 2, column block
+// wave % 2) of the 32 x 32 product A B, A(i, k) and B(k, j) given by
+// accessors; element v of a lane is (16 (wave / 2) + row(lk, v), 16 (wave % 2) + li).
+template <typename T, typename FA, typename FB>
+__device__ __forceinline__ void cgemm32(FA A, FB B, typename Mfma<T>::acc_t& cr, typename Mfma<T>::acc_t& ci) {
+  const int lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16, wave = threadIdx.x / 64;
+  const int bi = wave / 2, bj = wave % 2;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) { cr[v] = 0; ci[v] = 0; }
+#pragma unroll
+  for (int k4 = 0; k4 < NB; k4 += 4) {
+    const int kk = k4 + lk;
+    const cplx<T> a = A(16 * bi + li, kk), b = B(kk, 16 * bj + li);
+    cr = Mfma<T>::step(a.x, b.x, cr);
+    cr = Mfma<T>::step(-a.y, b.y, cr);
+    ci = Mfma<T>::step(a.x, b.y, ci);
+    ci = Mfma<T>::step(a.y, b.x, ci);
+  }
+}
+
+// Strip workgroup s of panel kp (kbp = its width) of one front: chunks
+// s < nch of the column strip, nch <= s < 2 nch of the row strip; s = 0
+// also stores the block factorisation (and, with nch = 0, is the only one).
+// PREV: first apply the update of the previous panel kprev (full width).
+template <typename T, bool PREV>
+__device__ __forceinline__ void strip_work(StripLds<T>& L, const FrontDev& f, cplx<T>* __restrict__ F,
+                                           const int kprev, const int kp, const int m, const int s, const int nch,
+                                           cplx<T>* __restrict__ Dinv, int* __restrict__ perm,
+                                           double* __restrict__ pivstat) {
   const int tid = threadIdx.x;
-  const int kpad = (kb + 3) & ~3;
-  // both operand tiles are loaded before the first LDS store (clamped
-  // in-range indices, zero outside the block), so the loads overlap
-  constexpr int LA = TM * NB / 256;
-  cplx<T> va[LA], vb[LA];
+  const int kbp = min(NB, f.p - kp);
+  const int k2 = kp + kbp, rem = m - k2;
+  const bool colstrip = s < nch;
+  const int t0 = NB * (colstrip ? s : s - nch);
+  const int cnt = max(0, min(NB, rem - t0));
+  const int cc = max(cnt, 1);
+  // every load first (clamped in-range indices, masked after the load)
+  cplx<T> vd[4], va[4], vb[4], vt[4], vo[4];
 #pragma unroll
-  for (int u = 0; u < LA; ++u) {
-    const int e = tid + 256 * u, r = e % TM, kk = e / TM;
-    const cplx<T> v = F[(k1 + min(row0 + r, rem - 1)) + (long long)(k0 + min(kk, kb - 1)) * m];
-    va[u] = row0 + r < rem && kk < kb ? v : mk<T>(0, 0);
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u, r = e % NB, c = e / NB;
+    const int rp = min(r, kbp - 1), cp_ = min(c, kbp - 1);
+    vd[u] = F[(kp + rp) + (long long)(kp + cp_) * m];
+    if constexpr (PREV) {
+      va[u] = F[(kp + rp) + (long long)(kprev + c) * m];
+      vb[u] = F[(kprev + r) + (long long)(kp + cp_) * m];
+    }
+    // chunk row / column, clamped into the front (an empty chunk has none)
+    const int xr = min(k2 + t0 + min(r, cc - 1), m - 1), xc = min(k2 + t0 + min(c, cc - 1), m - 1);
+    if (colstrip) {
+      vt[u] = F[xr + (long long)(kp + cp_) * m];
+      if constexpr (PREV) vo[u] = F[xr + (long long)(kprev + c) * m];
+    } else {
+      vt[u] = F[(kp + rp) + (long long)xc * m];
+      if constexpr (PREV) vo[u] = F[(kprev + r) + (long long)xc * m];
+    }
   }
+  const cplx<T> zero = mk<T>(0, 0);
 #pragma unroll
-  for (int u = 0; u < LA; ++u) {
-    const int e = tid + 256 * u, kk = e % NB, c = e / NB;
-    const cplx<T> v = F[(k0 + min(kk, kb - 1)) + (long long)(k1 + min(col0 + c, rem - 1)) * m];
-    vb[u] = col0 + c < rem && kk < kb ? v : mk<T>(0, 0);
-  }
-#pragma unroll
-  for (int u = 0; u < LA; ++u) {
-    const int e = tid + 256 * u;
-    Ar[e / TM][e % TM] = va[u].x;
-    Ai[e / TM][e % TM] = va[u].y;
-    Br[e % NB][e / NB] = vb[u].x;
-    Bi[e % NB][e / NB] = vb[u].y;
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u, r = e % NB, c = e / NB;
+    L.d.m[0][r][c] = r < kbp && c < kbp ? vd[u] : mk<T>(r == c ? 1 : 0, 0);
+    if constexpr (PREV) {
+      L.a[r][c] = r < kbp ? va[u] : zero;
+      L.b[r][c] = c < kbp ? vb[u] : zero;
+    }
+    if (colstrip) {
+      L.t[r][c] = r < cnt && c < kbp ? vt[u] : zero;
+      if constexpr (PREV) L.o[r][c] = r < cnt ? vo[u] : zero;
+    } else {
+      L.t[r][c] = r < kbp && c < cnt ? vt[u] : zero;
+      if constexpr (PREV) L.o[r][c] = c < cnt ? vo[u] : zero;
+    }
   }
   __syncthreads();
   using acc_t = typename Mfma<T>::acc_t;
-  const int wave = tid / 64, lane = tid % 64;
-  const int wr = (wave / 2) * (TM / 2), wc = (wave % 2) * (TM / 2);
-  acc_t accr[BW][BW], acci[BW][BW];
-  for (int i = 0; i < BW; ++i)
-    for (int j = 0; j < BW; ++j)
-      for (int v = 0; v < 4; ++v) { accr[i][j][v] = 0; acci[i][j][v] = 0; }
-  const int li = lane % 16, lk = lane / 16;
-  for (int k4 = 0; k4 < kpad; k4 += 4) {
-    T ar[BW], ai[BW], br[BW], bi[BW];
-    for (int i = 0; i < BW; ++i) { ar[i] = Ar[k4 + lk][wr + 16 * i + li]; ai[i] = Ai[k4 + lk][wr + 16 * i + li]; }
-    for (int j = 0; j < BW; ++j) { br[j] = Br[k4 + lk][wc + 16 * j + li]; bi[j] = Bi[k4 + lk][wc + 16 * j + li]; }
-    for (int i = 0; i < BW; ++i)
-      for (int j = 0; j < BW; ++j) {
-        accr[i][j] = Mfma<T>::step(ar[i], br[j], accr[i][j]);
-        accr[i][j] = Mfma<T>::step(-ai[i], bi[j], accr[i][j]);
-        acci[i][j] = Mfma<T>::step(ar[i], bi[j], acci[i][j]);
-        acci[i][j] = Mfma<T>::step(ai[i], br[j], acci[i][j]);
-      }
+  const int lane = tid % 64, li = lane % 16, lk = lane / 16, wave = tid / 64;
+  const int orow = 16 * (wave / 2), ocol = 16 * (wave % 2) + li;
+  if constexpr (PREV) {
+    // block -= A B; chunk -= O B (column strip) or A O (row strip).  Each
+    // element is updated by the lane that computed it, and no product reads m or t.
+    acc_t dr, di, tr, ti;
+    cgemm32<T>([&](int i, int k) { return L.a[i][k]; }, [&](int k, int j) { return L.b[k][j]; }, dr, di);
+    if (colstrip)
+      cgemm32<T>([&](int i, int k) { return L.o[i][k]; }, [&](int k, int j) { return L.b[k][j]; }, tr, ti);
+    else
+      cgemm32<T>([&](int i, int k) { return L.a[i][k]; }, [&](int k, int j) { return L.o[k][j]; }, tr, ti);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = orow + Mfma<T>::row(lk, v);
+      cplx<T> x = L.d.m[0][row][ocol];
+      x.x -= dr[v];
+      x.y -= di[v];
+      L.d.m[0][row][ocol] = x;
+      cplx<T> y = L.t[row][ocol];
+      y.x -= tr[v];
+      y.y -= ti[v];
+      L.t[row][ocol] = y;
+    }
+    __syncthreads();
   }
-  // C -= A B: per 16-row block i, all BW x 4 loads of C first, then the stores
-#pragma unroll
-  for (int i = 0; i < BW; ++i) {
-    cplx<T> cv[BW][4];
-#pragma unroll
-    for (int j = 0; j < BW; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int col = min(col0 + wc + 16 * j + li, rem - 1);
-        const int row = min(row0 + wr + 16 * i + Mfma<T>::row(lk, v), rem - 1);
-        cv[j][v] = F[(k1 + row) + (long long)(k1 + col) * m];
-      }
-#pragma unroll
-    for (int j = 0; j < BW; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int col = col0 + wc + 16 * j + li;
-        const int row = row0 + wr + 16 * i + Mfma<T>::row(lk, v);
-        if (col < rem && row < rem && !(row < skip && col < skip)) {
-          cplx<T> c = cv[j][v];
-          c.x -= accr[i][j][v];
-          c.y -= acci[i][j][v];
-          F[(k1 + row) + (long long)(k1 + col) * m] = c;
-        }
-      }
+  diag_factor_block<T, 256>(L.d, f, kp, kbp, Dinv, perm, pivstat, s == 0);
+  if (cnt == 0) return;
+  acc_t ur, ui;
+  if (colstrip) {
+    // L21(row, j) = sum_k chunk(row, k) U^{-1}(k, j), U^{-1}(k, j) = X_R(31-k, 31-j) for k <= j
+    cgemm32<T>([&](int i, int k) { return L.t[i][k]; },
+               [&](int k, int j) { return k <= j ? L.d.x[1][NB - 1 - k][NB - 1 - j] : mk<T>(0, 0); }, ur, ui);
+  } else {
+    // U12(i, c) = sum_k L^{-1}(i, k) chunk(src[k], c), L^{-1}(i, k) = X_L(i, k) for i >= k
+    cgemm32<T>([&](int i, int k) { return i >= k ? L.d.x[0][i][k] : mk<T>(0, 0); },
+               [&](int k, int j) { return L.t[L.d.src[k]][j]; }, ur, ui);
   }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) L.o[orow + Mfma<T>::row(lk, v)][ocol] = mk<T>(ur[v], ui[v]);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u, r = e % NB, c = e / NB;
+    if (colstrip) {
+      if (r < cnt && c < kbp) F[(k2 + t0 + r) + (long long)(kp + c) * m] = L.o[r][c];
+    } else {
+      if (r < kbp && c < cnt) F[(kp + r) + (long long)(k2 + t0 + c) * m] = L.o[r][c];
+    }
+  }
+}
+
+// Panel 0 of every front of a level: strip workgroups (blockIdx.x) only.
+template <typename T>
+__global__ void __launch_bounds__(256) strip_first_kernel(cplx<T>* __restrict__ Fbuf, const FrontDev* __restrict__ fr,
+                                                          int first, cplx<T>* __restrict__ Dinv,
+                                                          int* __restrict__ perm, double* __restrict__ pivstat) {
+  __shared__ StripLds<T> L;
+  const FrontDev f = fr[first + blockIdx.y];
+  const int m = f.p + f.q;
+  const int k2 = min(NB, f.p);
+  const int nch = (m - k2 + NB - 1) / NB;
+  const int s = blockIdx.x;
+  if (s >= max(1, 2 * nch)) return;
+  strip_work<T, false>(L, f, Fbuf + f.f_off, 0, 0, m, s, nch, Dinv, perm, pivstat);
+}
+
+// Panel step k0: block row 0 holds the strip workgroups of the next panel
+// (fronts that have one), rows 1.. the update tiles, over [k2, m)^2 when
+// the front has a next panel (k2 = its end) and over [k1, m)^2 otherwise.
+template <typename T, int TM>
+__global__ void __launch_bounds__(256) panel_step_kernel(cplx<T>* __restrict__ Fbuf, const FrontDev* __restrict__ fr,
+                                                         int first, int k0, cplx<T>* __restrict__ Dinv,
+                                                         int* __restrict__ perm, double* __restrict__ pivstat) {
+  constexpr size_t kRaw = sizeof(StripLds<T>) > sizeof(GemmLds<T, TM>) ? sizeof(StripLds<T>) : sizeof(GemmLds<T, TM>);
+  __shared__ __align__(16) unsigned char raw[kRaw];
+  const FrontDev f = fr[first + blockIdx.z];
+  if (f.p <= k0) return;
+  const int kb = min(NB, f.p - k0);
+  const int k1 = k0 + kb;
+  const int m = f.p + f.q;
+  cplx<T>* F = Fbuf + f.f_off;
+  const bool next = f.p > k1;
+  const int k2 = next ? k1 + min(NB, f.p - k1) : k1;
+  if (blockIdx.y == 0) {
+    if (!next) return;
+    const int nch = (m - k2 + NB - 1) / NB;
+    const int s = blockIdx.x;
+    if (s >= max(1, 2 * nch)) return;
+    strip_work<T, true>(*reinterpret_cast<StripLds<T>*>(raw), f, F, k0, k1, m, s, nch, Dinv, perm, pivstat);
+    return;
+  }
+  const int base = k2;
+  const int row0 = ((int)blockIdx.y - 1) * TM, col0 = blockIdx.x * TM;
+  if (row0 >= m - base || col0 >= m - base) return;
+  update_tile<T, TM>(*reinterpret_cast<GemmLds<T, TM>*>(raw), F, k0, kb, base, m, row0, col0, 0);
 }
 
 // ---------------------------------------------------------------- solves
@@ -1243,6 +1454,30 @@ static bool fuse_next(const Plan& plan, int l, int k0, bool fp64) {
   return cnt * gt * gt <= 256;
 }
 
+// Whether level l runs one launch per panel step (strip workgroups, see
+// panel_step_kernel): complex64 factors (the complex128 strip workgroup
+// would spill registers), and every workgroup of the level's largest step
+// (the first: gt^2 tiles and 2 nch strip chunks per front) resident at once.
+static bool strip_level(const Plan& plan, int l, bool fp64) {
+  if (fp64) return false;
+  const long long cnt = plan.level_ptr[l + 1] - plan.level_ptr[l];
+  const int maxm = plan.level_maxpq[l];
+  const int tile = update_tile(plan, l, fp64);
+  const long long gt = (maxm - 1 + tile - 1) / tile;
+  const long long nch = (maxm - 1 + NB - 1) / NB;
+  return cnt * (gt * gt + 2 * nch) <= 256;
+}
+
+// Panel step k0 of a strip level (a later panel exists in some front):
+// grid row 0 the strip chunks of the next panel, rows 1.. the update tiles.
+template <typename T, int TM>
+void step_launch(const MfDev<T>& mf, int rem, int maxm, int cnt, int first, int k0, hipStream_t st) {
+  const int gt = (rem + TM - 1) / TM;
+  const int nch = (std::max(0, maxm - k0 - NB - 1) + NB - 1) / NB;  // chunks of the largest next panel
+  LSP_LAUNCH("panel_step", (int)sizeof(cplx<T>), (panel_step_kernel<T, TM>), dim3(std::max(gt, std::max(1, 2 * nch)), gt + 1, cnt),
+             dim3(256), 0, st, mf.F, mf.fronts, first, k0, mf.Dinv, mf.perm, mf.pivstat);
+}
+
 template <typename T>
 void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
   for (int l = 0; l < plan.nlevels; ++l) {
@@ -1255,6 +1490,30 @@ void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
     LSP_LAUNCH("assemble_front", (int)sizeof(cplx<T>), assemble_front_kernel<T>, dim3(gx, cnt), dim3(256), 0, st, mf.F,
                mf.fronts, mf.idx, mf.gpos, mf.cpos, mf.Mval, first, plan.d);
     const bool fp64 = sizeof(T) == 8;
+    if constexpr (sizeof(T) == 4) {
+    if (strip_level(plan, l, fp64)) {
+      const int nch0 = (maxm - 1 + NB - 1) / NB;
+      LSP_LAUNCH("strip_first", (int)sizeof(cplx<T>), strip_first_kernel<T>, dim3(std::max(1, 2 * nch0), cnt),
+                 dim3(256), 0, st, mf.F, mf.fronts, first, mf.Dinv, mf.perm, mf.pivstat);
+      for (int k0 = 0; k0 < maxp; k0 += NB) {
+        const int rem = maxm - k0 - 1;
+        if (rem <= 0) continue;
+        const int tile = update_tile(plan, l, fp64);
+        const bool next = k0 + NB < maxp;
+        if (tile == 32) {
+          if (next) step_launch<T, 32>(mf, rem, maxm, cnt, first, k0, st);
+          else update_launch<T, 32>(mf, false, rem, cnt, first, k0, st);
+        } else if (tile == 128) {
+          if (next) step_launch<T, 128>(mf, rem, maxm, cnt, first, k0, st);
+          else update_launch<T, 128>(mf, false, rem, cnt, first, k0, st);
+        } else {
+          if (next) step_launch<T, 64>(mf, rem, maxm, cnt, first, k0, st);
+          else update_launch<T, 64>(mf, false, rem, cnt, first, k0, st);
+        }
+      }
+      continue;
+    }
+    }
     bool factored = false;  // panel k0's diagonal block done by the previous update
     for (int k0 = 0; k0 < maxp; k0 += NB) {
       if (!factored) {
@@ -1283,18 +1542,24 @@ void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
 
 FactorSchedule factor_schedule(const Plan& plan, bool fp64) {
   FactorSchedule s;
-  for (int l = 0; l < plan.nlevels; ++l)
+  for (int l = 0; l < plan.nlevels; ++l) {
+    const bool strips = strip_level(plan, l, fp64);
     for (int k0 = 0; k0 < plan.level_maxp[l]; k0 += NB) {
-      if (!fuse_next(plan, l, k0, fp64)) continue;
+      // update launches other than gemm_update: the panel steps of a strip
+      // level (all but the last panel) and the lookahead launches
+      const bool step = strips ? k0 + NB < plan.level_maxp[l] : fuse_next(plan, l, k0, fp64);
       for (int i = plan.level_ptr[l]; i < plan.level_ptr[l + 1]; ++i) {
         const FrontDev& f = plan.fronts[i];
         if (f.p <= k0) continue;
         const int kb = std::min(NB, f.p - k0);
         const double rem = (double)(f.p + f.q - k0 - kb);
+        if (strips && k0 == 0) s.fused_blocks += 1.0;  // panel 0 in the first strip launch
+        if (!step) continue;
         s.fused_update_flops += 8.0 * rem * rem * kb;
         if (f.p > k0 + kb) s.fused_blocks += 1.0;
       }
     }
+  }
   return s;
 }
 

@@ -72,9 +72,9 @@ struct MfDev {
 template <typename T>
 void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st);
 
-// Of one factorisation: the diagonal blocks factored inside the previous
-// panel's trailing-update launch (lookahead), and the trailing-update flops
-// of those fused launches.
+// Of one factorisation: the diagonal blocks not factored by a diagonal-block
+// launch of their own (lookahead or panel-strip launches), and the
+// trailing-update flops of the update launches that also factor a block.
 struct FactorSchedule {
   double fused_blocks = 0.0;
   double fused_update_flops = 0.0;

@@ -103,14 +103,18 @@ def test_setup_rejects_bad_arguments_without_touching_gpu(lib):
 
 
 def test_lookahead_schedule_stats(lib):
-    """Lookahead bookkeeping of the factorisation schedule: a level's first
-    panel is never factored inside an update launch, so at most
-    panel_blocks - nfronts blocks are fused; the fused launches carry part of
-    the update flops; and smaller update tiles (more workgroups per launch)
-    never fuse more, since fusion needs every tile of the launch resident."""
+    """Bookkeeping of the factorisation schedule: with complex128 factors a
+    level's first panel is always factored by a launch of its own, so at
+    most panel_blocks - nfronts blocks are fused (lookahead); complex64
+    factors also run the upper levels as panel-strip launches, which factor
+    first panels too; the fused launches carry part of the update flops;
+    and smaller update tiles (more workgroups per launch) never fuse more,
+    since fusion needs every workgroup of the launch resident."""
+    p64 = L.Plan(256, 2).stats()
+    assert 0 < p64["fused_blocks"] <= p64["panel_blocks"] - p64["nfronts"]
     p = L.Plan(256, 2, precision="mixed")
     s = p.stats()
-    assert 0 < s["fused_blocks"] <= s["panel_blocks"] - s["nfronts"]
+    assert p64["fused_blocks"] < s["fused_blocks"] <= s["panel_blocks"]
     assert 0 < s["fused_update_flops"] < s["update_flops"]
     nl = s["nlevels"]
     fused = {}
@@ -125,3 +129,7 @@ def test_lookahead_schedule_stats(lib):
     assert q["nfronts"] == 1 and q["max_pivots"] == 64 and q["panel_blocks"] == 2
     assert q["fused_blocks"] == 1
     assert q["fused_update_flops"] == q["update_flops"] == 8 * 32 ** 2 * 32
+    # complex64: a one-front level is a strip level, so both blocks are
+    # factored by the strip launches
+    q = L.Plan(8, 2, precision="mixed").stats()
+    assert q["fused_blocks"] == 2 and q["fused_update_flops"] == q["update_flops"]
