@@ -93,7 +93,8 @@ __global__ void __launch_bounds__(256) assemble_front_kernel(cplx<T>* __restrict
 // written to the front's inverse store: panel b keeps [Linv | Uinv], each
 // NB x NB column-major, zero outside the kb x kb block.
 //
-// One wave per front.  Elimination is row per lane pair: lane r holds the
+// The elimination is one wave's work (the first wave of the workgroup).
+// Elimination is row per lane pair: lane r holds the
 // even columns of row r and lane 32 + r the odd ones, so each step updates
 // at most 16 columns per lane.  Pivoting is by relabelling: a row keeps its
 // lanes and records the step that chose it, so nothing moves.  Each step
@@ -343,7 +344,6 @@ __device__ __forceinline__ void diag_factor_block(DiagLds<T>& S, const FrontDev&
   T dmin = (T)INFINITY, dmax = (T)0;
   if (tid < 64) {
     const WaveSync sync;
-    const int lane = tid;
     cplx<T> rowh[NB / 2];
 #pragma unroll
     for (int i = 0; i < NB / 2; ++i) rowh[i] = S.m[0][r][2 * i + h];
@@ -754,10 +754,9 @@ template <typename T, int TM, bool FUSE>
 __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ Fbuf, const FrontDev* __restrict__ fr,
                                                           int first, int k0, cplx<T>* __restrict__ Dinv,
                                                           int* __restrict__ perm, double* __restrict__ pivstat) {
-  // TM x TM output tile, 4 waves in a 2x2 arrangement, each wave (TM/2)^2 as
-  // BW x BW MFMA 16x16 blocks.  With FUSE, block row 0 is the lookahead
-  // factorisation of the next diagonal block and the tiles start at row 1.
-  constexpr int BW = TM / 32;
+  // TM x TM output tiles (update_tile).  With FUSE, block row 0 is the
+  // lookahead factorisation of the next diagonal block and the tiles start
+  // at row 1.
   constexpr size_t kRaw = FUSE && sizeof(DiagLds<T>) > sizeof(GemmLds<T, TM>) ? sizeof(DiagLds<T>)
                                                                              : sizeof(GemmLds<T, TM>);
   __shared__ __align__(16) unsigned char raw[kRaw];
@@ -1095,7 +1094,7 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
     cplx<T> sv[4], c0v[4], c1v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int e = min(e0 + tid + TPB * u, m * nr - 1), r = e % m, k = e / m;
+      const int e = min(e0 + tid + TPB * u, m * nr - 1), k = e / m;
       const long long rb = (long long)(r0 + k) * vstride;
       sv[u] = z[(long long)(r0 + k) * N + gidx[u]];
       c0v[u] = vbuf[rb + (q0[u] >= 0 ? coff[0] + q0[u] : 0)];
