@@ -236,7 +236,17 @@ __global__ void __launch_bounds__(768) gram_reduce_kernel(const double2* __restr
 // tau = (A(q,q) - A(p,p)) / (2|g|), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
 // c = 1/sqrt(1+t^2), s = t c, V = [[c, s], [-s e^{-i phi}, c e^{-i phi}]].
 // A pair is skipped when |g| <= 1e-17 sqrt(A(p,p) A(q,q)) (relative
-// criterion); the sweeps stop when a whole sweep rotates nothing.
+// criterion, compared squared); the sweeps stop when a whole sweep rotates
+// nothing.
+// 1 / sqrt(x), x > 0: the hardware estimate refined by two Newton steps
+// r <- r (3 - x r^2) / 2 (each roughly doubles the correct bits).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * fma(-0.5 * x, r * r, 1.5);
+  r = r * fma(-0.5 * x, r * r, 1.5);
+  return r;
+}
+
 __device__ void jacobi_eigen(double2* A, double2* U, int s, int lane) {
   constexpr int NP = (S + 1) / 2;
   __shared__ int rotated;
@@ -257,12 +267,13 @@ __device__ void jacobi_eigen(double2* A, double2* U, int s, int lane) {
         if (q < s) {
           const double2 gpq = A[p + S * q];
           const double a = A[p + S * p].x, b = A[q + S * q].x;
-          const double ag = sqrt(gpq.x * gpq.x + gpq.y * gpq.y);
-          if (ag > 1e-17 * sqrt(fabs(a * b)) && ag != 0.0) {
-            const double ex = gpq.x / ag, ey = gpq.y / ag;  // e^{i phi}
-            const double tau = (b - a) / (2.0 * ag);
+          const double ag2 = gpq.x * gpq.x + gpq.y * gpq.y;  // |g|^2
+          if (ag2 > 1e-34 * fabs(a * b) && ag2 != 0.0) {
+            const double ri = rsqrt_nr(ag2);                 // 1 / |g|
+            const double ex = gpq.x * ri, ey = gpq.y * ri;  // e^{i phi}
+            const double tau = (b - a) * 0.5 * ri;
             const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+            const double cs = rsqrt_nr(1.0 + t * t), sn = t * cs;
             rcs[lane] = cs;
             rsn[lane] = sn;
             rv10[lane] = make_double2(-sn * ex, sn * ey);  // -s e^{-i phi}
@@ -291,7 +302,9 @@ __device__ void jacobi_eigen(double2* A, double2* U, int s, int lane) {
         U[i + S * q] = cadd(cscale(up, sn), cmul(v11, uq));
       }
       __syncthreads();
-      // rows: A(p,:) <- c A(p,:) + conj(v10) A(q,:);  A(q,:) <- s A(p,:) + conj(v11) A(q,:)
+      // rows: A(p,:) <- c A(p,:) + conj(v10) A(q,:);  A(q,:) <- s A(p,:) + conj(v11) A(q,:);
+      // the rotated pair's off-diagonal entries are set to zero and its
+      // diagonal entries to their real parts by the thread that writes them
       for (int it = lane; it < npair * s; it += blockDim.x) {
         const int k = it / s, j = it % s;
         if (!ract[k]) continue;
@@ -299,16 +312,13 @@ __device__ void jacobi_eigen(double2* A, double2* U, int s, int lane) {
         const double cs = rcs[k], sn = rsn[k];
         const double2 v10 = rv10[k], v11 = rv11[k];
         const double2 xp = A[p + S * j], xq = A[q + S * j];
-        A[p + S * j] = cadd(cscale(xp, cs), cmul(cconj(v10), xq));
-        A[q + S * j] = cadd(cscale(xp, sn), cmul(cconj(v11), xq));
-      }
-      __syncthreads();
-      if (lane < npair && ract[lane]) {
-        const int p = rp[lane], q = rq[lane];
-        A[p + S * q] = make_double2(0, 0);
-        A[q + S * p] = make_double2(0, 0);
-        A[p + S * p].y = 0.0;
-        A[q + S * q].y = 0.0;
+        double2 np = cadd(cscale(xp, cs), cmul(cconj(v10), xq));
+        double2 nq = cadd(cscale(xp, sn), cmul(cconj(v11), xq));
+        if (j == q) np = make_double2(0, 0);
+        if (j == p) { nq = make_double2(0, 0); np.y = 0.0; }
+        if (j == q) nq.y = 0.0;
+        A[p + S * j] = np;
+        A[q + S * j] = nq;
       }
       __syncthreads();
     }
