@@ -137,12 +137,18 @@ def kernel_model(name, st, w, nrhs):
     esz = 8 if "[c64]" in name else 16
     n, d, N, L, nlev = st["n"], st["d"], st["N"], st["L"], st["nlevels"]
     base = name.split(" ")[0]
-    if base in ("fwd", "bwd"):
+    if base in ("fwd", "bwd", "fwd_dense", "bwd_dense"):
         # one sweep reads every L (or U) panel entry and inverted diagonal
-        # block once per right-hand-side group, plus the N-vector it consumes
-        # and the N-vector it produces; spread over nlevels launches
-        per_app = st["sweep_entries"] * esz + 2 * N * esz * nrhs
-        return "hbm", per_app / nlev, "GB/s"
+        # block of the chain levels, and the formed operators of the dense
+        # levels, once per right-hand-side group (one group here), plus the
+        # N-vector it consumes and the N-vector it produces, shared out by
+        # level; spread over the launches of each kind
+        dl = st["dense_levels"]
+        lev, entries = (dl, st["dense_entries"]) if base.endswith("_dense") else (nlev - dl, st["sweep_entries"])
+        if lev == 0:
+            return None
+        per_app = entries * esz + 2 * N * esz * nrhs * lev / nlev
+        return "hbm", per_app / lev, "GB/s"
     if base == "gemm_update":
         # the plain trailing-update launches (the update launches that also
         # factor a diagonal block, update_lu and panel_step, are bound by

@@ -76,6 +76,12 @@ typedef struct {
                         within b of the boundary plane (2); 1 <= b < n/2 */
   int leaf;          /* nested-dissection leaf side in grid points (0 = auto) */
   int panel;         /* frontal LU panel width: 0 = auto (32) or 32 */
+  int dense_sweeps;  /* 1 (default): on the tree levels with at most 16
+                        fronts, at least two panels and fronts of at most
+                        1024 rows, lsp_factor also forms each front's
+                        forward and backward sweep operators (2 m p entries
+                        per front) and the sweeps apply them as dense
+                        products; 0: every level uses the panel chain */
 } lsp_options;
 
 typedef struct {
@@ -107,6 +113,11 @@ typedef struct {
                                  the tile table and the plan's precision */
   double fused_update_flops;  /* of update_flops, the part in update
                                  launches that also factor a block */
+  double dense_entries;       /* entries of the formed dense sweep operators
+                                 one forward (or backward) sweep reads (sum
+                                 of m p over the dense levels' fronts; those
+                                 levels' panels are not in sweep_entries) */
+  int dense_levels;           /* tree levels swept with dense operators */
 } lsp_plan_stats;
 
 typedef struct lsp_plan lsp_plan;        /* opaque; host-side, plus one device copy of

@@ -1025,14 +1025,19 @@ __device__ __forceinline__ void tri_apply(const cplx<T> (*D)[NB + 1], const cplx
 
 // Forward sweep of one front: v = [z(I); 0] + children's updates; per panel:
 //   y_b = L11^{-1} (P_b v_b),  v(k1:m) -= L21 y_b.
-template <typename T, int NR, bool VL, int TPB>
+// FORM: the same chain on the unit vectors e_j, j < p (NR per workgroup,
+// blockIdx.y the group), written as the columns of the front's forward
+// operator Gf (m x p, column-major, at Gop + g_off): the sweep's output for
+// any input is then [0; v_B] + Gf v_I.
+template <typename T, int NR, bool VL, int TPB, bool FORM = false>
 __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
                                                   const FrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                   const int* __restrict__ cpos, const int* __restrict__ perm,
                                                   const cplx<T>* __restrict__ z, cplx<T>* __restrict__ vbuf, int first,
-                                                  int nrhs, long long N, long long vstride) {
+                                                  int nrhs, long long N, long long vstride, cplx<T>* __restrict__ Gop) {
   static_assert(NR * NB <= 256, "one gather thread per panel entry");
   static_assert(TPB == 256 || TPB == 512, "256 or 512 threads");
+  static_assert(!FORM || VL, "operators are formed with the vectors in LDS");
   constexpr int IPT = NB * NB / TPB;  // inverse-block entries per thread
   extern __shared__ unsigned char smem_raw[];
   __shared__ cplx<T> Li[2][NB][NB + 1];
@@ -1040,14 +1045,17 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
   __shared__ cplx<T> yb[NR][NB];
   const FrontDev f = fr[first + blockIdx.x];
   const int r0 = blockIdx.y * NR;
-  const int nr = min(NR, nrhs - r0);
+  if (FORM && r0 >= f.p) return;  // the level's largest front sets the grid
+  const int nr = min(NR, (FORM ? f.p : nrhs) - r0);
   const int m = f.p + f.q;
   const cplx<T>* F = Fbuf + f.f_off;
   const int* id = idx + f.idx_off;
   const int* cp = cpos + 2 * f.idx_off;
   const int* pm = perm + f.piv_off;
   const long long coff[2] = {f.cidx[0], f.cidx[1]};
-  cplx<T>* vg = vbuf + (long long)r0 * vstride + f.idx_off;   // HBM copy, stride vstride
+  // HBM copy, stride vstride (FORM: columns r0.. of Gf, stride m)
+  cplx<T>* vg = FORM ? Gop + f.g_off + (long long)r0 * m : vbuf + (long long)r0 * vstride + f.idx_off;
+  const long long gstride = FORM ? m : vstride;
   // a typed LDS or global pointer (a run-time choice would make every access
   // a flat one, with conservative waits)
   cplx<T>* vp;
@@ -1082,6 +1090,12 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
   const cplx<T> li2 = IPT > 2 ? Lg0[tid + 2 * TPB] : li0, li3 = IPT > 2 ? Lg0[tid + 3 * TPB] : li0;
   // v = [z(I); 0] + children's updates: four entries per thread per pass,
   // the index loads of all four, then their value loads, in flight together
+  if constexpr (FORM)
+    for (int e = tid; e < m * nr; e += TPB) {
+      const int r = e % m, k = e / m;
+      vp[k * vs + r] = mk<T>(r == r0 + k ? 1 : 0, 0);
+    }
+  else
   for (int e0 = 0; e0 < m * nr; e0 += 4 * TPB) {
     int gidx[4], q0[4], q1[4];
 #pragma unroll
@@ -1199,7 +1213,7 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
   if constexpr (VL)
     for (int e = tid; e < m * nr; e += TPB) {
       int r = e % m, k = e / m;
-      vg[(long long)k * vstride + r] = vp[k * vs + r];
+      vg[(long long)k * gstride + r] = vp[k * vs + r];
     }
 }
 
@@ -1207,12 +1221,16 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
 //   x_b = U11^{-1} (y_b - U12 x(k1:m)).  Writes x at the front's grid points.
 // Thread (j, grp) = (tid % NB, tid / NB) forms the U12 row j product over
 // the columns k1 + grp + 8t; the eight column groups are added in order.
-template <typename T, int NR, bool VL, int TPB>
+// FORM: the same chain on the unit vectors e_c, c < m (v = [y_I; x_B] = e_c),
+// the results x_I written as the columns of the front's backward operator
+// Gb (p x m, column-major, at Gop + g_off + m p): x_I = Gb [y_I; x_B].
+template <typename T, int NR, bool VL, int TPB, bool FORM = false>
 __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
                                                   const FrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                   cplx<T>* __restrict__ x, cplx<T>* __restrict__ vbuf, int first,
-                                                  int nrhs, long long N, long long vstride) {
+                                                  int nrhs, long long N, long long vstride, cplx<T>* __restrict__ Gop) {
   static_assert(TPB == 256 || TPB == 512, "256 or 512 threads");
+  static_assert(!FORM || VL, "operators are formed with the vectors in LDS");
   constexpr int G = TPB / NB;  // column groups
   constexpr int IPT = NB * NB / TPB;  // inverse-block entries per thread
   // With 512 threads, complex64, one right-hand side and the vectors in LDS
@@ -1228,8 +1246,9 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
   __shared__ cplx<T> rb[NR][NB];
   const FrontDev f = fr[first + blockIdx.x];
   const int r0 = blockIdx.y * NR;
-  const int nr = min(NR, nrhs - r0);
   const int m = f.p + f.q;
+  if (FORM && r0 >= m) return;  // the level's largest front sets the grid
+  const int nr = min(NR, (FORM ? m : nrhs) - r0);
   const cplx<T>* F = Fbuf + f.f_off;
   const int* id = idx + f.idx_off;
   cplx<T>* vg = vbuf + (long long)r0 * vstride + f.idx_off;
@@ -1258,7 +1277,8 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
   // v = [y(I) from the forward sweep; x(B) from the ancestors]
   for (int e = tid; e < m * nr; e += TPB) {
     const int r = e % m, k = e / m;
-    if (r >= f.p) vp[k * vs + r] = x[(long long)(r0 + k) * N + id[r]];
+    if constexpr (FORM) vp[k * vs + r] = mk<T>(r == r0 + k ? 1 : 0, 0);
+    else if (r >= f.p) vp[k * vs + r] = x[(long long)(r0 + k) * N + id[r]];
     else if constexpr (VL) vp[k * vs + r] = vg[(long long)k * vstride + r];
   }
   {
@@ -1331,7 +1351,7 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
         for (int k = 0; k < NR; ++k) {
           if (k < nr) {
             vp[k * vs + k0 + i] = xs[k];
-            x[(long long)(r0 + k) * N + gi] = xs[k];
+            if constexpr (!FORM) x[(long long)(r0 + k) * N + gi] = xs[k];
           }
         }
       }
@@ -1344,6 +1364,145 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
     }
   } else {
     for (int b = nblk - 1; b >= 0; --b) panel(b, ucol, ucol2);
+  }
+  if constexpr (FORM) {
+    __syncthreads();
+    cplx<T>* gb = Gop + f.g_off + (long long)m * f.p + (long long)r0 * f.p;
+    for (int e = tid; e < f.p * nr; e += TPB) {
+      const int i = e % f.p, k = e / f.p;
+      gb[(long long)k * f.p + i] = vp[k * vs + i];
+    }
+  }
+}
+
+// ---- Sweeps of the dense levels: the formed operators as matrix-vector
+// products.  Workgroup (front, chunk of DR rows, right-hand-side group):
+// thread (row tid % DR, column class tid / DR) sums the columns of its class
+// (c = class mod DJ) for NR right-hand sides, the input staged through LDS
+// DC columns at a time; the DJ class sums are added in class order, so a
+// right-hand side's result does not depend on the group it is solved in.
+constexpr int DR = 16, DJ = 256 / DR, DC = 256;
+
+// Partial products of the staged columns [c0, c0 + cn) for row r of an
+// operator with leading dimension ld: DC / DJ loads per thread, all issued
+// before the first multiply (clamped columns, multiplied only when in range).
+template <typename T, int NR>
+__device__ __forceinline__ void dense_chunk(const cplx<T>* __restrict__ G, const long long ld, const int r,
+                                            const int c0, const int cn, const int jg, const cplx<T> (*vs)[DC],
+                                            cplx<T> (&acc)[NR]) {
+  constexpr int U = DC / DJ;
+  cplx<T> g[U];
+#pragma unroll
+  for (int t = 0; t < U; ++t) g[t] = G[(long long)(c0 + min(jg + DJ * t, cn - 1)) * ld + r];
+#pragma unroll
+  for (int t = 0; t < U; ++t) {
+    const int c = jg + DJ * t;
+    if (c < cn)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] = cfma(acc[k], g[t], vs[k][c]);
+  }
+}
+
+// Forward sweep of a dense level: out = [0; v_B] + Gf v_I with
+// v = [z(I); 0] + children's updates, written where the panel chain writes
+// its output (y_I in pivot order, then the updated v_B).
+template <typename T, int NR>
+__global__ void __launch_bounds__(256) fwd_dense_kernel(const cplx<T>* __restrict__ Gop, const FrontDev* __restrict__ fr,
+                                                        const int* __restrict__ idx, const int* __restrict__ cpos,
+                                                        const cplx<T>* __restrict__ z, cplx<T>* __restrict__ vbuf,
+                                                        int first, int chunks, int nrhs, long long N, long long vstride) {
+  __shared__ cplx<T> vs[NR][DC];
+  __shared__ cplx<T> part[DJ][NR][DR];
+  const FrontDev f = fr[first + blockIdx.x / chunks];
+  const int m = f.p + f.q;
+  const int row0 = (blockIdx.x % chunks) * DR;
+  if (row0 >= m) return;  // the level's largest front sets the grid
+  const int r0 = blockIdx.y * NR;
+  const int nr = min(NR, nrhs - r0);
+  const int tid = threadIdx.x, rl = tid % DR, jg = tid / DR;
+  const int r = min(row0 + rl, m - 1);  // rows past m compute a copy of row m - 1, never stored
+  const int* id = idx + f.idx_off;
+  const int* cp = cpos + 2 * f.idx_off;
+  const cplx<T>* G = Gop + f.g_off;
+  // v at front row j (< p, or >= p without the z term) of right-hand side k
+  auto vin = [&](const int j, const int k) {
+    const long long rb = (long long)(r0 + k) * vstride;
+    cplx<T> s = j < f.p ? z[(long long)(r0 + k) * N + id[j]] : mk<T>(0, 0);
+    const int q0 = f.cidx[0] >= 0 ? cp[2 * j] : -1, q1 = f.cidx[1] >= 0 ? cp[2 * j + 1] : -1;
+    if (q0 >= 0) s = cadd(s, vbuf[rb + f.cidx[0] + q0]);
+    if (q1 >= 0) s = cadd(s, vbuf[rb + f.cidx[1] + q1]);
+    return s;
+  };
+  cplx<T> acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
+  for (int c0 = 0; c0 < f.p; c0 += DC) {
+    const int cn = min(DC, f.p - c0);
+    if (c0 > 0) __syncthreads();  // the previous columns' reads are done
+    for (int e = tid; e < NR * DC; e += 256) {
+      const int j = e % DC, k = e / DC;
+      if (j < cn && k < nr) vs[k][j] = vin(c0 + j, k);
+    }
+    __syncthreads();
+    dense_chunk<T, NR>(G, m, r, c0, cn, jg, vs, acc);
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k) part[jg][k][rl] = acc[k];
+  __syncthreads();
+  if (tid < NR * DR) {
+    const int k = tid / DR, rr = row0 + tid % DR;
+    if (k < nr && rr < m) {
+      cplx<T> s = part[0][k][tid % DR];
+      for (int g = 1; g < DJ; ++g) s = cadd(s, part[g][k][tid % DR]);
+      if (rr >= f.p) s = cadd(vin(rr, k), s);
+      vbuf[(long long)(r0 + k) * vstride + f.idx_off + rr] = s;
+    }
+  }
+}
+
+// Backward sweep of a dense level: x_I = Gb [y_I; x_B], y_I from the
+// forward sweep's output, x_B from the ancestors' solution.
+template <typename T, int NR>
+__global__ void __launch_bounds__(256) bwd_dense_kernel(const cplx<T>* __restrict__ Gop, const FrontDev* __restrict__ fr,
+                                                        const int* __restrict__ idx, cplx<T>* __restrict__ x,
+                                                        const cplx<T>* __restrict__ vbuf, int first, int chunks,
+                                                        int nrhs, long long N, long long vstride) {
+  __shared__ cplx<T> vs[NR][DC];
+  __shared__ cplx<T> part[DJ][NR][DR];
+  const FrontDev f = fr[first + blockIdx.x / chunks];
+  const int m = f.p + f.q;
+  const int row0 = (blockIdx.x % chunks) * DR;
+  if (row0 >= f.p) return;  // the level's largest front sets the grid
+  const int r0 = blockIdx.y * NR;
+  const int nr = min(NR, nrhs - r0);
+  const int tid = threadIdx.x, rl = tid % DR, jg = tid / DR;
+  const int i = min(row0 + rl, f.p - 1);  // rows past p compute a copy of row p - 1, never stored
+  const int* id = idx + f.idx_off;
+  const cplx<T>* G = Gop + f.g_off + (long long)m * f.p;
+  cplx<T> acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
+  for (int c0 = 0; c0 < m; c0 += DC) {
+    const int cn = min(DC, m - c0);
+    if (c0 > 0) __syncthreads();  // the previous columns' reads are done
+    for (int e = tid; e < NR * DC; e += 256) {
+      const int j = e % DC, k = e / DC, c = c0 + j;
+      if (j < cn && k < nr)
+        vs[k][j] = c < f.p ? vbuf[(long long)(r0 + k) * vstride + f.idx_off + c] : x[(long long)(r0 + k) * N + id[c]];
+    }
+    __syncthreads();
+    dense_chunk<T, NR>(G, f.p, i, c0, cn, jg, vs, acc);
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k) part[jg][k][rl] = acc[k];
+  __syncthreads();
+  if (tid < NR * DR) {
+    const int k = tid / DR, ii = row0 + tid % DR;
+    if (k < nr && ii < f.p) {
+      cplx<T> s = part[0][k][tid % DR];
+      for (int g = 1; g < DJ; ++g) s = cadd(s, part[g][k][tid % DR]);
+      x[(long long)(r0 + k) * N + id[ii]] = s;
+    }
   }
 }
 
@@ -1380,11 +1539,11 @@ void sweep_fwd(const MfDev<T>& mf, const Plan& plan, int l, int groups, int nrhs
   if (vec_in_lds(vb, stat))
     LSP_LAUNCH("fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NR, true, TPB>), dim3(cnt, groups), dim3(TPB), vb, st,
                mf.F, mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N,
-               (long long)plan.sum_pq);
+               (long long)plan.sum_pq, mf.G);
   else
     LSP_LAUNCH("fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NR, false, TPB>), dim3(cnt, groups), dim3(TPB), 0, st,
                mf.F, mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N,
-               (long long)plan.sum_pq);
+               (long long)plan.sum_pq, mf.G);
 }
 
 template <typename T, int NR, int TPB>
@@ -1397,23 +1556,86 @@ void sweep_bwd(const MfDev<T>& mf, const Plan& plan, int l, int groups, int nrhs
   static_assert(stat <= kLdsBytes, "sweep arrays exceed the LDS");
   if (vec_in_lds(vb, stat))
     LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR, true, TPB>), dim3(cnt, groups), dim3(TPB), vb, st,
-               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq);
+               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq,
+               mf.G);
   else
     LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR, false, TPB>), dim3(cnt, groups), dim3(TPB), 0, st,
-               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq);
+               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq,
+               mf.G);
 }
 
 
+// The dense levels' sweeps: one workgroup per (front, DR rows, group).
+template <typename T, int NR>
+void dense_fwd(const MfDev<T>& mf, const Plan& plan, int l, int groups, int nrhs, const cplx<T>* z, cplx<T>* vbuf,
+               hipStream_t st) {
+  const int first = plan.level_ptr[l];
+  const int cnt = plan.level_ptr[l + 1] - first;
+  const int chunks = (plan.level_maxpq[l] + DR - 1) / DR;
+  LSP_LAUNCH("fwd_dense", (int)sizeof(cplx<T>), (fwd_dense_kernel<T, NR>), dim3(cnt * chunks, groups), dim3(256), 0,
+             st, mf.G, mf.fronts, mf.idx, mf.cpos, z, vbuf, first, chunks, nrhs, (long long)plan.N,
+             (long long)plan.sum_pq);
+}
+
+template <typename T, int NR>
+void dense_bwd(const MfDev<T>& mf, const Plan& plan, int l, int groups, int nrhs, cplx<T>* x, const cplx<T>* vbuf,
+               hipStream_t st) {
+  const int first = plan.level_ptr[l];
+  const int cnt = plan.level_ptr[l + 1] - first;
+  const int chunks = (plan.level_maxp[l] + DR - 1) / DR;
+  LSP_LAUNCH("bwd_dense", (int)sizeof(cplx<T>), (bwd_dense_kernel<T, NR>), dim3(cnt * chunks, groups), dim3(256), 0,
+             st, mf.G, mf.fronts, mf.idx, x, vbuf, first, chunks, nrhs, (long long)plan.N, (long long)plan.sum_pq);
+}
+
+// Forms the sweep operators of dense level l from its factor: the panel
+// chains of both sweeps run on unit vectors, NF per workgroup.
+template <typename T, int TPB>
+void form_level(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st) {
+  constexpr int NF = sizeof(T) == 4 ? 8 : 4;
+  const int first = plan.level_ptr[l];
+  const int cnt = plan.level_ptr[l + 1] - first;
+  const int maxm = plan.level_maxpq[l], maxp = plan.level_maxp[l];
+  const size_t vb = (size_t)maxm * NF * sizeof(cplx<T>);
+  LSP_REQUIRE(vec_in_lds(vb, fwd_static_lds<T, NF, TPB>()) && vec_in_lds(vb, bwd_static_lds<T, NF, TPB>()),
+              "dense sweep level exceeds the LDS");
+  LSP_LAUNCH("form_fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NF, true, TPB, true>), dim3(cnt, (maxp + NF - 1) / NF),
+             dim3(TPB), vb, st, mf.F, mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm, nullptr, nullptr, first, 0,
+             (long long)plan.N, 0LL, mf.G);
+  LSP_LAUNCH("form_bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NF, true, TPB, true>), dim3(cnt, (maxm + NF - 1) / NF),
+             dim3(TPB), vb, st, mf.F, mf.Dinv, mf.fronts, mf.idx, nullptr, nullptr, first, 0, (long long)plan.N, 0LL,
+             mf.G);
+}
+
+// Formation of dense level l once its factorisation is enqueued on st.
+template <typename T>
+void form_after(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st, const FormStream* fs) {
+  if (!plan.level_dense[l]) return;
+  hipStream_t fst = st;
+  if (fs) {
+    LSP_HIP(hipEventRecord(fs->level, st));
+    LSP_HIP(hipStreamWaitEvent(fs->aux, fs->level, 0));
+    fst = fs->aux;
+  }
+  if (wide_level(plan, l)) form_level<T, 512>(mf, plan, l, fst);
+  else form_level<T, 256>(mf, plan, l, fst);
+}
+
 template <typename T, int NR>
 void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
-                  hipStream_t st) {
+                  hipStream_t st, hipEvent_t form_done) {
   const int groups = (nrhs + NR - 1) / NR;
   for (int l = 0; l < plan.nlevels; ++l) {
-    if (wide_level(plan, l)) sweep_fwd<T, NR, 512>(mf, plan, l, groups, nrhs, z, vbuf, st);
+    if (plan.level_dense[l] && form_done) {
+      LSP_HIP(hipStreamWaitEvent(st, form_done, 0));
+      form_done = nullptr;
+    }
+    if (plan.level_dense[l]) dense_fwd<T, NR>(mf, plan, l, groups, nrhs, z, vbuf, st);
+    else if (wide_level(plan, l)) sweep_fwd<T, NR, 512>(mf, plan, l, groups, nrhs, z, vbuf, st);
     else sweep_fwd<T, NR, 256>(mf, plan, l, groups, nrhs, z, vbuf, st);
   }
   for (int l = plan.nlevels - 1; l >= 0; --l) {
-    if (wide_level(plan, l)) sweep_bwd<T, NR, 512>(mf, plan, l, groups, nrhs, x, vbuf, st);
+    if (plan.level_dense[l]) dense_bwd<T, NR>(mf, plan, l, groups, nrhs, x, vbuf, st);
+    else if (wide_level(plan, l)) sweep_bwd<T, NR, 512>(mf, plan, l, groups, nrhs, x, vbuf, st);
     else sweep_bwd<T, NR, 256>(mf, plan, l, groups, nrhs, x, vbuf, st);
   }
 }
@@ -1477,9 +1699,27 @@ void step_launch(const MfDev<T>& mf, int rem, int maxm, int cnt, int first, int 
              dim3(256), 0, st, mf.F, mf.fronts, first, k0, mf.Dinv, mf.perm, mf.pivstat);
 }
 
+// the levels' factorisation launches on st, each dense level's formation
+// after its own (on fs->aux when given)
 template <typename T>
-void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
+void mf_factor_levels(const MfDev<T>& mf, const Plan& plan, hipStream_t st, const FormStream* fs);
+
+template <typename T>
+void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st, const FormStream* fs) {
+  if (fs) LSP_HIP(hipStreamWaitEvent(st, fs->done, 0));  // the previous formation reads the factors
+  try {
+    mf_factor_levels(mf, plan, st, fs);
+  } catch (...) {
+    if (fs) (void)hipEventRecord(fs->done, fs->aux);  // covers whatever formation was enqueued
+    throw;
+  }
+  if (fs) LSP_HIP(hipEventRecord(fs->done, fs->aux));
+}
+
+template <typename T>
+void mf_factor_levels(const MfDev<T>& mf, const Plan& plan, hipStream_t st, const FormStream* fs) {
   for (int l = 0; l < plan.nlevels; ++l) {
+    if (l > 0) form_after(mf, plan, l - 1, st, fs);
     const int first = plan.level_ptr[l];
     const int cnt = plan.level_ptr[l + 1] - first;
     const int maxm = plan.level_maxpq[l];
@@ -1537,6 +1777,7 @@ void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st) {
       else update_launch<T, 64>(mf, factored, rem, cnt, first, k0, st);
     }
   }
+  form_after(mf, plan, plan.nlevels - 1, st, fs);
 }
 
 FactorSchedule factor_schedule(const Plan& plan, bool fp64) {
@@ -1564,16 +1805,18 @@ FactorSchedule factor_schedule(const Plan& plan, bool fp64) {
 
 template <typename T>
 void mf_solve(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
-              hipStream_t st) {
-  if (nrhs >= 8) solve_levels<T, 8>(mf, plan, nrhs, z, x, vbuf, st);
-  else if (nrhs >= 4) solve_levels<T, 4>(mf, plan, nrhs, z, x, vbuf, st);
-  else if (nrhs >= 2) solve_levels<T, 2>(mf, plan, nrhs, z, x, vbuf, st);
-  else solve_levels<T, 1>(mf, plan, nrhs, z, x, vbuf, st);
+              hipStream_t st, hipEvent_t form_done) {
+  if (nrhs >= 8) solve_levels<T, 8>(mf, plan, nrhs, z, x, vbuf, st, form_done);
+  else if (nrhs >= 4) solve_levels<T, 4>(mf, plan, nrhs, z, x, vbuf, st, form_done);
+  else if (nrhs >= 2) solve_levels<T, 2>(mf, plan, nrhs, z, x, vbuf, st, form_done);
+  else solve_levels<T, 1>(mf, plan, nrhs, z, x, vbuf, st, form_done);
 }
 
-template void mf_factor<double>(const MfDev<double>&, const Plan&, hipStream_t);
-template void mf_factor<float>(const MfDev<float>&, const Plan&, hipStream_t);
-template void mf_solve<double>(const MfDev<double>&, const Plan&, int, const double2*, double2*, double2*, hipStream_t);
-template void mf_solve<float>(const MfDev<float>&, const Plan&, int, const float2*, float2*, float2*, hipStream_t);
+template void mf_factor<double>(const MfDev<double>&, const Plan&, hipStream_t, const FormStream*);
+template void mf_factor<float>(const MfDev<float>&, const Plan&, hipStream_t, const FormStream*);
+template void mf_solve<double>(const MfDev<double>&, const Plan&, int, const double2*, double2*, double2*, hipStream_t,
+                               hipEvent_t);
+template void mf_solve<float>(const MfDev<float>&, const Plan&, int, const float2*, float2*, float2*, hipStream_t,
+                              hipEvent_t);
 
 }  // namespace lsp

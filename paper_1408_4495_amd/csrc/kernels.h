@@ -67,10 +67,25 @@ struct MfDev {
   const double2* Mval;      // [N][3^d]
   int* perm;                // per panel row: the front row it came from
   double* pivstat;          // per diagonal block: smallest / largest pivot magnitude
+  cplx<T>* G;               // formed sweep operators of the dense levels (FrontDev::g_off)
 };
 
+// Second stream for the dense levels' operator formation: each level's
+// formation waits (event `level`) for that level's factorisation on the main
+// stream and then runs beside the factorisation of the levels above it;
+// `done` is recorded after the last.
+struct FormStream {
+  hipStream_t aux;
+  hipEvent_t level, done;
+};
+
+// Numeric factorisation, level by level, and the dense levels' sweep
+// operators: on fs->aux when fs is given (the caller makes the sweeps wait
+// for fs->done), else on st after the factorisation.  Waits on st for a
+// previous formation (all work enqueued on fs->aux), which still reads the
+// factors.
 template <typename T>
-void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st);
+void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st, const FormStream* fs);
 
 // Of one factorisation: the diagonal blocks not factored by a diagonal-block
 // launch of their own (lookahead or panel-strip launches), and the
@@ -80,9 +95,11 @@ struct FactorSchedule {
   double fused_update_flops = 0.0;
 };
 FactorSchedule factor_schedule(const Plan& plan, bool fp64);
+// Forward and backward sweeps; form_done (may be null): an event the first
+// dense level's sweep waits for (the operators' formation).
 template <typename T>
 void mf_solve(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
-              hipStream_t st);
+              hipStream_t st, hipEvent_t form_done);
 
 // ---- Krylov helpers (complex128 vectors, [nrhs][N] blocks)
 void launch_widen(double2* y, const float2* x, long long count, hipStream_t st);

@@ -116,6 +116,7 @@ struct ProblemPtrs {
   int* cpos;
   int* perm;
   double* pivstat;
+  void* Gop;  // formed dense sweep operators
 };
 
 size_t layout_problem(const lsp_plan* pl, int precision, void* base, ProblemPtrs* out) {
@@ -142,6 +143,7 @@ size_t layout_problem(const lsp_plan* pl, int precision, void* base, ProblemPtrs
   q.Dinv = cv.take<char>((size_t)P.dinv_elems * esz);
   q.perm = cv.take<int>(P.sum_p);
   q.pivstat = cv.take<double>((size_t)P.panel_blocks);
+  q.Gop = cv.take<char>((size_t)P.dense_elems * esz);
   if (out) *out = q;
   return cv.off + 256;
 }
@@ -275,9 +277,66 @@ struct lsp_problem {
   void* ctl_dev = nullptr;
   int host_cap = 0;
   unsigned ctl_tag = 0;
+  // formation stream (shared by the problems of a device) and this
+  // problem's events for the dense levels' operator formation, taken at the
+  // first factorisation that forms any; form_pending: the next sweeps must
+  // wait for fs.done
+  FormStream fs{};
+  bool form_pending = false;
 
   ~lsp_problem() {
     if (ctl_host) ctl_pool().put({ctl_host, ctl_dev, host_cap});
+    if (fs.aux) {
+      // the caller may release the workspace next: the formation must be over
+      (void)hipEventSynchronize(fs.done);
+      form_pool().put(device, fs);
+    }
+  }
+
+  // One formation stream per device, shared by its problems (creating a
+  // stream costs milliseconds), and pooled event pairs; all live until the
+  // process ends.
+  struct FormPool {
+    std::mutex mu;
+    std::vector<std::pair<int, hipStream_t>> streams;
+    std::vector<std::pair<int, FormStream>> free;
+    FormStream get(int dev) {
+      std::lock_guard<std::mutex> g(mu);
+      for (size_t i = 0; i < free.size(); ++i)
+        if (free[i].first == dev) {
+          FormStream f = free[i].second;
+          free.erase(free.begin() + i);
+          return f;
+        }
+      FormStream f{};
+      for (const auto& e : streams)
+        if (e.first == dev) f.aux = e.second;
+      if (!f.aux) {
+        LSP_HIP(hipStreamCreateWithFlags(&f.aux, hipStreamNonBlocking));
+        streams.emplace_back(dev, f.aux);
+      }
+      LSP_HIP(hipEventCreateWithFlags(&f.level, hipEventDisableTiming));
+      if (hipEventCreateWithFlags(&f.done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(f.level);
+        throw Error(LSP_ERR_HIP, "event creation for the formation stream failed");
+      }
+      LSP_HIP(hipEventRecord(f.done, f.aux));  // so that a first wait on it returns once the stream's work so far is done
+      return f;
+    }
+    void put(int dev, const FormStream& f) {
+      std::lock_guard<std::mutex> g(mu);
+      free.emplace_back(dev, f);
+    }
+  };
+  static FormPool& form_pool() {
+    static FormPool* pool = new FormPool();
+    return *pool;
+  }
+  // the event the next sweeps wait for, once after each factorisation
+  hipEvent_t take_form_wait() {
+    if (!form_pending) return nullptr;
+    form_pending = false;
+    return fs.done;
   }
 
   static size_t ctl_bytes(int cap) { return sizeof(HostCtl) + 8 * (size_t)cap + 3 * sizeof(double) * (size_t)cap; }
@@ -472,13 +531,13 @@ void apply_precond(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2*
   if (pb->precision == LSP_FP64) {
     launch_applyQ<double2>((double2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
     MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
-                     pb->d.pivstat};
-    mf_solve<double>(mf, P, nrhs, (const double2*)s.zq, out, (double2*)s.vbuf, st);
+                     pb->d.pivstat, (double2*)pb->d.Gop};
+    mf_solve<double>(mf, P, nrhs, (const double2*)s.zq, out, (double2*)s.vbuf, st, pb->take_form_wait());
   } else {
     launch_applyQ<float2>((float2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
     MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
-                    pb->d.pivstat};
-    mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st);
+                    pb->d.pivstat, (float2*)pb->d.Gop};
+    mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st, pb->take_form_wait());
     launch_widen(out, (const float2*)s.xs, (long long)nrhs * P.N, st);
   }
 }
@@ -488,13 +547,13 @@ void solve_M(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2* z, do
   hipStream_t st = pb->st;
   if (pb->precision == LSP_FP64) {
     MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
-                     pb->d.pivstat};
-    mf_solve<double>(mf, P, nrhs, z, x, (double2*)s.vbuf, st);
+                     pb->d.pivstat, (double2*)pb->d.Gop};
+    mf_solve<double>(mf, P, nrhs, z, x, (double2*)s.vbuf, st, pb->take_form_wait());
   } else {
     launch_narrow((float2*)s.zq, z, (long long)nrhs * P.N, st);
     MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
-                    pb->d.pivstat};
-    mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st);
+                    pb->d.pivstat, (float2*)pb->d.Gop};
+    mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st, pb->take_form_wait());
     launch_widen(x, (const float2*)s.xs, (long long)nrhs * P.N, st);
   }
 }
@@ -548,6 +607,7 @@ lsp_status lsp_options_default(lsp_options* o) {
   o->buffer_b = 2;
   o->leaf = 0;
   o->panel = 0;
+  o->dense_sweeps = 1;
   return LSP_OK;
 }
 
@@ -562,6 +622,7 @@ lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts, 
     LSP_REQUIRE(o.max_iters >= 1, "max_iters must be >= 1");
     LSP_REQUIRE(o.precision == LSP_FP64 || o.precision == LSP_MIXED, "unknown precision");
     LSP_REQUIRE(o.panel == 0 || o.panel == kNbMax, "panel must be 0 (auto) or 32");
+    LSP_REQUIRE(o.dense_sweeps == 0 || o.dense_sweeps == 1, "dense_sweeps must be 0 or 1");
     std::unique_ptr<lsp_plan> pl(new lsp_plan());
     build_plan(pl->p, n, d, max_nrhs, o);
     fix_radices(pl->p);
@@ -590,6 +651,8 @@ lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* s) {
   const FactorSchedule fs = factor_schedule(P, P.opts.precision == LSP_FP64);
   s->fused_blocks = fs.fused_blocks;
   s->fused_update_flops = fs.fused_update_flops;
+  s->dense_entries = P.dense_entries;
+  s->dense_levels = P.dense_levels;
   return LSP_OK;
 }
 
@@ -677,14 +740,28 @@ lsp_status lsp_factor(lsp_problem* pb) {
   return guarded([&]() -> lsp_status {
     LSP_REQUIRE(pb != nullptr, "null problem");
     const Plan& P = pb->plan->p;
+    if (P.dense_levels > 0 && !pb->fs.aux) {
+      int cur = 0;
+      LSP_HIP(hipGetDevice(&cur));
+      if (cur != pb->device) LSP_HIP(hipSetDevice(pb->device));
+      try {
+        pb->fs = lsp_problem::form_pool().get(pb->device);
+      } catch (...) {
+        if (cur != pb->device) (void)hipSetDevice(cur);
+        throw;
+      }
+      if (cur != pb->device) LSP_HIP(hipSetDevice(cur));
+    }
+    const FormStream* fsp = pb->fs.aux ? &pb->fs : nullptr;
+    pb->form_pending = fsp != nullptr;
     if (pb->precision == LSP_FP64) {
       MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
-                       pb->d.pivstat};
-      mf_factor<double>(mf, P, pb->st);
+                       pb->d.pivstat, (double2*)pb->d.Gop};
+      mf_factor<double>(mf, P, pb->st, fsp);
     } else {
       MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
-                      pb->d.pivstat};
-      mf_factor<float>(mf, P, pb->st);
+                      pb->d.pivstat, (float2*)pb->d.Gop};
+      mf_factor<float>(mf, P, pb->st, fsp);
     }
     // smallest pivot ratio over the diagonal blocks (a NaN counts as -1), reported
     // into the pinned control block

@@ -204,6 +204,32 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
   P.level_tile.assign(P.nlevels, 64);
   for (int l = 0; l < P.nlevels; ++l)
     P.level_tile[l] = P.level_maxpq[l] <= 160 ? 32 : (P.level_maxpq[l] >= 1024 ? 128 : 64);
+  // Dense sweep levels: few fronts (a front's panel chain runs on one
+  // workgroup per right-hand-side group, so with few fronts the chain's
+  // latency is the level's time), at least two panels, at most 1024 rows.
+  P.level_dense.assign(P.nlevels, 0);
+  P.dense_elems = 0;
+  P.dense_entries = 0.0;
+  P.dense_levels = 0;
+  for (int l = 0; l < P.nlevels; ++l) {
+    const int cnt = P.level_ptr[l + 1] - P.level_ptr[l];
+    if (opts.dense_sweeps != 0 && cnt <= 16 && P.level_maxp[l] > P.nb && P.level_maxpq[l] <= 1024) {
+      P.level_dense[l] = 1;
+      ++P.dense_levels;
+    }
+  }
+  for (FrontDev& f : P.fronts) {
+    const long long m = f.p + f.q;
+    f.g_off = -1;
+    if (!P.level_dense[f.level]) continue;
+    f.g_off = P.dense_elems;
+    P.dense_elems += 2 * m * f.p;
+    P.dense_entries += (double)m * f.p;
+    for (int k0 = 0; k0 < f.p; k0 += P.nb) {  // these panels are not read by the sweeps
+      const int kb = std::min(P.nb, f.p - k0);
+      P.sweep_entries -= (double)(m - k0 - kb) * kb + (double)P.nb * P.nb;
+    }
+  }
   P.front_elems = f_off;
   P.dinv_elems = dinv_off;
   P.sum_p = piv_off;

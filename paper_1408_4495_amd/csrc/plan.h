@@ -25,6 +25,8 @@ struct FrontDev {
   long long cidx[2];
   long long cfoff[2];
   int cm[2];
+  long long g_off;        // offset of its formed sweep operators (dense
+                          // levels, see Plan::level_dense), -1 elsewhere
 };
 
 struct Plan {
@@ -39,6 +41,13 @@ struct Plan {
   std::vector<int> level_ptr;     // fronts of level l are [level_ptr[l], level_ptr[l+1])
   std::vector<int> level_maxp, level_maxpq;
   std::vector<int> level_tile;    // trailing-update tile (32, 64 or 128) per level
+  // Levels whose sweeps apply formed dense operators instead of the panel
+  // chain: per front the forward operator Gf (m x p, column-major) and the
+  // backward operator Gb (p x m, column-major) at g_off, 2 m p entries.
+  std::vector<char> level_dense;
+  long long dense_elems = 0;      // sum over dense fronts of 2 m p
+  double dense_entries = 0.0;     // sum over dense fronts of m p (one sweep's reads)
+  int dense_levels = 0;
   int nlevels = 0;
   long long front_elems = 0;      // sum (p+q)^2
   long long dinv_elems = 0;       // sum over panels of 2 nb^2

@@ -20,7 +20,8 @@ import sys
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 SOURCE = {"fwd": "frontal.hip", "bwd": "frontal.hip", "diag_lu": "frontal.hip", "panel_trsm": "frontal.hip",
           "gemm_update": "frontal.hip", "update_lu": "frontal.hip", "assemble_front": "frontal.hip",
-          "strip_first": "frontal.hip", "panel_step": "frontal.hip",
+          "strip_first": "frontal.hip", "panel_step": "frontal.hip", "form_fwd": "frontal.hip",
+          "form_bwd": "frontal.hip",
           "fft_lines": "fft.hip",
           "gram": "stencil.hip", "gram_reduce": "stencil.hip", "eigen": "stencil.hip", "applyQ": "stencil.hip",
           "dots_partial": "krylov.hip", "dots_final": "krylov.hip", "axpy": "krylov.hip"}
@@ -44,6 +45,8 @@ def registry_key(name):
         base = FFT_MODE.get(args[2], base)
     if base == "gemm_update" and args and args[-1] == "true":
         base = "update_lu"  # fused with the next diagonal-block factorisation
+    if base in ("fwd", "bwd") and args and args[-1] == "true":
+        base = "form_" + base  # the sweep chain run on unit vectors (operator formation)
     prec = ""
     if args:
         if re.match(r"(HIP_vector_type<)?float\b", args[0]):

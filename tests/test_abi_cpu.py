@@ -102,6 +102,26 @@ def test_setup_rejects_bad_arguments_without_touching_gpu(lib):
     assert lib.lsp_factor(None) == 1
 
 
+def test_dense_sweep_levels(lib):
+    """Dense sweep levels (at most 16 fronts, more than one panel, at most
+    1024 rows): n = 8 in 2D is one front of 64 pivots and no boundary, so
+    its operators hold 2 x 64^2 entries and no panel is left to the chains,
+    whose reads would be two 32 x 32 inverse blocks and the 32 x 32 block
+    below the first; at n = 256 the top five levels (16, 8, 4, 2, 1 fronts)
+    are dense, and the problem's device memory grows by exactly the
+    operators (2 entries per m p)."""
+    q1, q0 = L.Plan(8, 2).stats(), L.Plan(8, 2, dense_sweeps=0).stats()
+    assert q1["dense_levels"] == 1 and q1["dense_entries"] == 64 * 64 and q1["sweep_entries"] == 0
+    assert q0["dense_levels"] == 0 and q0["dense_entries"] == 0 and q0["sweep_entries"] == 3 * 32 * 32
+    p1, p0 = L.Plan(256, 2), L.Plan(256, 2, dense_sweeps=0)
+    s1, s0 = p1.stats(), p0.stats()
+    assert s1["dense_levels"] == 5 and s0["dense_levels"] == 0
+    assert s1["sweep_entries"] < s0["sweep_entries"] and s1["dense_entries"] > 0
+    for prec, esz in ((L.LSP_FP64, 16), (L.LSP_MIXED, 8)):
+        grow = p1.bytes(1, prec)[0] - p0.bytes(1, prec)[0]
+        assert 0 <= grow - 2 * s1["dense_entries"] * esz < 256
+
+
 def test_lookahead_schedule_stats(lib):
     """Bookkeeping of the factorisation schedule: with complex128 factors a
     level's first panel is always factored by a launch of its own, so at

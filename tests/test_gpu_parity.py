@@ -134,17 +134,22 @@ def test_Q_and_M(n, d):
                 assert Mv[i, q] == 0
 
 
-@pytest.mark.parametrize("n,d,prec,tol", [(32, 2, "fp64", 1e-10), (64, 2, "fp64", 1e-10), (12, 3, "fp64", 1e-10),
-                                          (64, 2, "mixed", 1e-4), (256, 2, "fp64", 1e-10), (256, 2, "mixed", 1e-4)])
-def test_solve_M_vs_superlu(n, d, prec, tol):
+@pytest.mark.parametrize("n,d,prec,tol,dense", [(32, 2, "fp64", 1e-10, 1), (64, 2, "fp64", 1e-10, 1),
+                                                (12, 3, "fp64", 1e-10, 1), (64, 2, "mixed", 1e-4, 1),
+                                                (256, 2, "fp64", 1e-10, 1), (256, 2, "mixed", 1e-4, 1),
+                                                (256, 2, "fp64", 1e-10, 0), (256, 2, "mixed", 1e-4, 0)])
+def test_solve_M_vs_superlu(n, d, prec, tol, dense):
     """Multifrontal LU + triangular solves vs SuperLU: M^{-1} z, FP64 to 1e-10
     relative (kappa(M)-scaled rounding), complex64 fronts to 1e-4.  n = 256
     covers the one-wave diagonal-block factorisation (levels of 1024 fronts),
     the lookahead factorisation inside the trailing updates of the upper
-    levels and the 512-thread sweeps of the wide levels."""
+    levels, and either the formed dense operators of the top five levels
+    (dense = 1) or, on every level, the panel chains, with 512-thread
+    workgroups on the wide levels (dense = 0)."""
     omega = 2 * np.pi * n / 8
     m = synth.medium_single_bump(n, d, 0.25, 0.12)
-    lsp, torch, plan, pb = _problem(n, d, omega, m, max_nrhs=2, precision=prec)
+    lsp, torch, plan, pb = _problem(n, d, omega, m, max_nrhs=2, precision=prec, dense_sweeps=dense)
+    assert (plan.stats()["dense_levels"] > 0) == bool(dense)
     pb.factor()
     sts = all_stencils(kernel_table(n, d, omega), d, n, b=2)
     Q, M = build_QM(n, d, omega, m, sts)
@@ -192,6 +197,25 @@ def test_c1_end_to_end_mixed():
     op = Operator(n, d, omega, m)
     g = op.rhs(w["uI"][0])
     assert np.linalg.norm(g - op.apply(u.cpu().numpy()[0])) <= 1e-8 * np.linalg.norm(g)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 2e-5)])
+def test_dense_sweeps_match_panel_chains(prec, tol):
+    """The dense levels' formed operators applied as matrix-vector products
+    give the panel chains' M^{-1} z up to rounding: FP64 to 1e-12, complex64
+    to 2e-5 (both sides round a complex64 chain of the same factor); three
+    right-hand sides, so the sweeps run a group of two and a ragged one."""
+    n, d = 128, 2
+    omega = 2 * np.pi * n / 8
+    m = synth.medium_single_bump(n, d, 0.25, 0.12)
+    z = synth.random_complex((3, n ** d), seed=31)
+    out = []
+    for dense in (1, 0):
+        lsp, torch, plan, pb = _problem(n, d, omega, m, max_nrhs=3, precision=prec, dense_sweeps=dense)
+        assert (plan.stats()["dense_levels"] > 0) == bool(dense)
+        pb.factor()
+        out.append(pb.solve_M(z).cpu().numpy())
+    assert _rel(out[0], out[1]) <= tol
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
