@@ -1029,7 +1029,12 @@ __device__ __forceinline__ void tri_apply(const cplx<T> (*D)[NB + 1], const cplx
 // blockIdx.y the group), written as the columns of the front's forward
 // operator Gf (m x p, column-major, at Gop + g_off): the sweep's output for
 // any input is then [0; v_B] + Gf v_I.
-template <typename T, int NR, bool VL, int TPB, bool FORM = false>
+// FORM and TRANS: the same chain with U^T in place of P^T L (U11^T is lower
+// triangular in the (column, pivot-row) order, no permutation, the block
+// inverses transposed, U12^T below), whose output for e_i is row i of the
+// backward sweep's operator [U11^{-1}, -U11^{-1} U12]: the rows are written
+// as the columns of GbT (m x p, column-major, at Gop + g_off + m p).
+template <typename T, int NR, bool VL, int TPB, bool FORM = false, bool TRANS = false>
 __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
                                                   const FrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                   const int* __restrict__ cpos, const int* __restrict__ perm,
@@ -1038,9 +1043,16 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
   static_assert(NR * NB <= 256, "one gather thread per panel entry");
   static_assert(TPB == 256 || TPB == 512, "256 or 512 threads");
   static_assert(!FORM || VL, "operators are formed with the vectors in LDS");
+  static_assert(FORM || !TRANS, "the transposed chain only forms operators");
   constexpr int IPT = NB * NB / TPB;  // inverse-block entries per thread
   extern __shared__ unsigned char smem_raw[];
   __shared__ cplx<T> Li[2][NB][NB + 1];
+  // entry e of a column-major inverse block (e = tid + k TPB) into LDS,
+  // transposed for TRANS
+  auto put_inv = [](cplx<T> (*D)[NB + 1], const int e, const cplx<T>& v) {
+    if constexpr (TRANS) D[e / NB][e % NB] = v;
+    else D[e % NB][e / NB] = v;
+  };
   __shared__ cplx<T> tb[NR][NB];
   __shared__ cplx<T> yb[NR][NB];
   const FrontDev f = fr[first + blockIdx.x];
@@ -1054,7 +1066,8 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
   const int* pm = perm + f.piv_off;
   const long long coff[2] = {f.cidx[0], f.cidx[1]};
   // HBM copy, stride vstride (FORM: columns r0.. of Gf, stride m)
-  cplx<T>* vg = FORM ? Gop + f.g_off + (long long)r0 * m : vbuf + (long long)r0 * vstride + f.idx_off;
+  cplx<T>* vg = FORM ? Gop + f.g_off + (TRANS ? (long long)m * f.p : 0LL) + (long long)r0 * m
+                     : vbuf + (long long)r0 * vstride + f.idx_off;
   const long long gstride = FORM ? m : vstride;
   // a typed LDS or global pointer (a run-time choice would make every access
   // a flat one, with conservative waits)
@@ -1074,18 +1087,23 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
   // rows during the current panel was measured slower.)
   constexpr bool PRE = sizeof(cplx<T>) * NR <= 16 && (TPB == 256 || sizeof(T) == 4);
   constexpr int LN = PRE ? NB : 1;
+  // entry (r, k0 + j) of L21, or of U12^T for TRANS
+  auto lentry = [&](const int r, const int kj) {
+    if constexpr (TRANS) return F[(long long)r * m + kj];
+    else return F[(long long)kj * m + (unsigned)r];
+  };
   auto load_l = [&](const int k0p, cplx<T>(&dst)[LN]) {
     if constexpr (PRE) {
       const int kbp = min(NB, f.p - k0p);
-      const unsigned rr = (unsigned)min(k0p + kbp + tid, m - 1);
+      const int rr = min(k0p + kbp + tid, m - 1);
 #pragma unroll
-      for (int j = 0; j < NB; ++j) dst[j] = F[(long long)(k0p + min(j, kbp - 1)) * m + rr];
+      for (int j = 0; j < NB; ++j) dst[j] = lentry(rr, k0p + min(j, kbp - 1));
     }
   };
   cplx<T> lrow[LN];
   load_l(0, lrow);  // panel 0's rows go out before the gather of v below
-  int pnext = pm[min(gj, f.p - 1)];
-  const cplx<T>* Lg0 = Dinv + f.dinv_off;
+  int pnext = TRANS ? min(gj, f.p - 1) : pm[min(gj, f.p - 1)];
+  const cplx<T>* Lg0 = Dinv + f.dinv_off + (TRANS ? NB * NB : 0);
   const cplx<T> li0 = Lg0[tid], li1 = Lg0[tid + TPB];
   const cplx<T> li2 = IPT > 2 ? Lg0[tid + 2 * TPB] : li0, li3 = IPT > 2 ? Lg0[tid + 3 * TPB] : li0;
   // v = [z(I); 0] + children's updates: four entries per thread per pass,
@@ -1126,11 +1144,11 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
       }
     }
   }
-  Li[0][tid % NB][tid / NB] = li0;
-  Li[0][tid % NB][tid / NB + TPB / NB] = li1;
+  put_inv(Li[0], tid, li0);
+  put_inv(Li[0], tid + TPB, li1);
   if constexpr (IPT > 2) {
-    Li[0][tid % NB][tid / NB + 2 * TPB / NB] = li2;
-    Li[0][tid % NB][tid / NB + 3 * TPB / NB] = li3;
+    put_inv(Li[0], tid + 2 * TPB, li2);
+    put_inv(Li[0], tid + 3 * TPB, li3);
   }
   __syncthreads();
   auto panel = [&](const int b, cplx<T>(&lc)[LN]) {
@@ -1146,19 +1164,19 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
     // next panel's L11^{-1} (the last panel reloads its own: unused, but it
     // keeps these loads unconditional so they stay in registers)
     // (named scalars: a small array here is left in scratch by the compiler)
-    const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(more ? b + 1 : b) * 2 * NB * NB;
+    const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(more ? b + 1 : b) * 2 * NB * NB + (TRANS ? NB * NB : 0);
     const cplx<T> lin0 = Lg[tid], lin1 = Lg[tid + TPB];
     const cplx<T> lin2 = IPT > 2 ? Lg[tid + 2 * TPB] : lin0, lin3 = IPT > 2 ? Lg[tid + 3 * TPB] : lin0;
-    pnext = pm[min(k1 + gj, f.p - 1)];
+    pnext = TRANS ? min(k1 + gj, f.p - 1) : pm[min(k1 + gj, f.p - 1)];
     if (b > 0) load_l(k0, lc);
     __builtin_amdgcn_sched_barrier(0);
     if (tid < NR * NB) tb[gk][gj] = g;
     // Li[cur ^ 1] was last read before the previous panel's final barrier
-    Li[cur ^ 1][tid % NB][tid / NB] = lin0;
-    Li[cur ^ 1][tid % NB][tid / NB + TPB / NB] = lin1;
+    put_inv(Li[cur ^ 1], tid, lin0);
+    put_inv(Li[cur ^ 1], tid + TPB, lin1);
     if constexpr (IPT > 2) {
-      Li[cur ^ 1][tid % NB][tid / NB + 2 * TPB / NB] = lin2;
-      Li[cur ^ 1][tid % NB][tid / NB + 3 * TPB / NB] = lin3;
+      put_inv(Li[cur ^ 1], tid + 2 * TPB, lin2);
+      put_inv(Li[cur ^ 1], tid + 3 * TPB, lin3);
     }
     __syncthreads();
     if (tid < 256) {  // the 32-row product uses the first four waves
@@ -1196,7 +1214,7 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
       for (int j0 = 0; j0 < NB; j0 += 8) {
         cplx<T> l8[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) l8[u] = F[(long long)(k0 + min(j0 + u, kb - 1)) * m + (unsigned)r];
+        for (int u = 0; u < 8; ++u) l8[u] = lentry(r, k0 + min(j0 + u, kb - 1));
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
@@ -1221,16 +1239,12 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
 //   x_b = U11^{-1} (y_b - U12 x(k1:m)).  Writes x at the front's grid points.
 // Thread (j, grp) = (tid % NB, tid / NB) forms the U12 row j product over
 // the columns k1 + grp + 8t; the eight column groups are added in order.
-// FORM: the same chain on the unit vectors e_c, c < m (v = [y_I; x_B] = e_c),
-// the results x_I written as the columns of the front's backward operator
-// Gb (p x m, column-major, at Gop + g_off + m p): x_I = Gb [y_I; x_B].
-template <typename T, int NR, bool VL, int TPB, bool FORM = false>
+template <typename T, int NR, bool VL, int TPB>
 __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
                                                   const FrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                   cplx<T>* __restrict__ x, cplx<T>* __restrict__ vbuf, int first,
-                                                  int nrhs, long long N, long long vstride, cplx<T>* __restrict__ Gop) {
+                                                  int nrhs, long long N, long long vstride) {
   static_assert(TPB == 256 || TPB == 512, "256 or 512 threads");
-  static_assert(!FORM || VL, "operators are formed with the vectors in LDS");
   constexpr int G = TPB / NB;  // column groups
   constexpr int IPT = NB * NB / TPB;  // inverse-block entries per thread
   // With 512 threads, complex64, one right-hand side and the vectors in LDS
@@ -1246,9 +1260,8 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
   __shared__ cplx<T> rb[NR][NB];
   const FrontDev f = fr[first + blockIdx.x];
   const int r0 = blockIdx.y * NR;
+  const int nr = min(NR, nrhs - r0);
   const int m = f.p + f.q;
-  if (FORM && r0 >= m) return;  // the level's largest front sets the grid
-  const int nr = min(NR, (FORM ? m : nrhs) - r0);
   const cplx<T>* F = Fbuf + f.f_off;
   const int* id = idx + f.idx_off;
   cplx<T>* vg = vbuf + (long long)r0 * vstride + f.idx_off;
@@ -1277,8 +1290,7 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
   // v = [y(I) from the forward sweep; x(B) from the ancestors]
   for (int e = tid; e < m * nr; e += TPB) {
     const int r = e % m, k = e / m;
-    if constexpr (FORM) vp[k * vs + r] = mk<T>(r == r0 + k ? 1 : 0, 0);
-    else if (r >= f.p) vp[k * vs + r] = x[(long long)(r0 + k) * N + id[r]];
+    if (r >= f.p) vp[k * vs + r] = x[(long long)(r0 + k) * N + id[r]];
     else if constexpr (VL) vp[k * vs + r] = vg[(long long)k * vstride + r];
   }
   {
@@ -1351,7 +1363,7 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
         for (int k = 0; k < NR; ++k) {
           if (k < nr) {
             vp[k * vs + k0 + i] = xs[k];
-            if constexpr (!FORM) x[(long long)(r0 + k) * N + gi] = xs[k];
+            x[(long long)(r0 + k) * N + gi] = xs[k];
           }
         }
       }
@@ -1365,14 +1377,6 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
   } else {
     for (int b = nblk - 1; b >= 0; --b) panel(b, ucol, ucol2);
   }
-  if constexpr (FORM) {
-    __syncthreads();
-    cplx<T>* gb = Gop + f.g_off + (long long)m * f.p + (long long)r0 * f.p;
-    for (int e = tid; e < f.p * nr; e += TPB) {
-      const int i = e % f.p, k = e / f.p;
-      gb[(long long)k * f.p + i] = vp[k * vs + i];
-    }
-  }
 }
 
 // ---- Sweeps of the dense levels: the formed operators as matrix-vector
@@ -1384,16 +1388,20 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
 constexpr int DR = 16, DJ = 256 / DR, DC = 256;
 
 // Partial products of the staged columns [c0, c0 + cn) for row r of an
-// operator with leading dimension ld: DC / DJ loads per thread, all issued
+// operator stored column-major (ROWS false: entry (r, c) at c ld + r) or
+// row-major (ROWS true: at r ld + c): DC / DJ loads per thread, all issued
 // before the first multiply (clamped columns, multiplied only when in range).
-template <typename T, int NR>
+template <typename T, int NR, bool ROWS>
 __device__ __forceinline__ void dense_chunk(const cplx<T>* __restrict__ G, const long long ld, const int r,
                                             const int c0, const int cn, const int jg, const cplx<T> (*vs)[DC],
                                             cplx<T> (&acc)[NR]) {
   constexpr int U = DC / DJ;
   cplx<T> g[U];
 #pragma unroll
-  for (int t = 0; t < U; ++t) g[t] = G[(long long)(c0 + min(jg + DJ * t, cn - 1)) * ld + r];
+  for (int t = 0; t < U; ++t) {
+    const long long c = c0 + min(jg + DJ * t, cn - 1);
+    g[t] = ROWS ? G[(long long)r * ld + c] : G[c * ld + r];
+  }
 #pragma unroll
   for (int t = 0; t < U; ++t) {
     const int c = jg + DJ * t;
@@ -1444,7 +1452,7 @@ __global__ void __launch_bounds__(256) fwd_dense_kernel(const cplx<T>* __restric
       if (j < cn && k < nr) vs[k][j] = vin(c0 + j, k);
     }
     __syncthreads();
-    dense_chunk<T, NR>(G, m, r, c0, cn, jg, vs, acc);
+    dense_chunk<T, NR, false>(G, m, r, c0, cn, jg, vs, acc);
   }
 #pragma unroll
   for (int k = 0; k < NR; ++k) part[jg][k][rl] = acc[k];
@@ -1461,7 +1469,9 @@ __global__ void __launch_bounds__(256) fwd_dense_kernel(const cplx<T>* __restric
 }
 
 // Backward sweep of a dense level: x_I = Gb [y_I; x_B], y_I from the
-// forward sweep's output, x_B from the ancestors' solution.
+// forward sweep's output, x_B from the ancestors' solution; Gb is stored by
+// rows (GbT column-major), so here a thread's column class is tid mod DJ
+// and DJ consecutive lanes read one row's consecutive entries.
 template <typename T, int NR>
 __global__ void __launch_bounds__(256) bwd_dense_kernel(const cplx<T>* __restrict__ Gop, const FrontDev* __restrict__ fr,
                                                         const int* __restrict__ idx, cplx<T>* __restrict__ x,
@@ -1475,7 +1485,7 @@ __global__ void __launch_bounds__(256) bwd_dense_kernel(const cplx<T>* __restric
   if (row0 >= f.p) return;  // the level's largest front sets the grid
   const int r0 = blockIdx.y * NR;
   const int nr = min(NR, nrhs - r0);
-  const int tid = threadIdx.x, rl = tid % DR, jg = tid / DR;
+  const int tid = threadIdx.x, rl = tid / DJ, jg = tid % DJ;
   const int i = min(row0 + rl, f.p - 1);  // rows past p compute a copy of row p - 1, never stored
   const int* id = idx + f.idx_off;
   const cplx<T>* G = Gop + f.g_off + (long long)m * f.p;
@@ -1491,7 +1501,7 @@ __global__ void __launch_bounds__(256) bwd_dense_kernel(const cplx<T>* __restric
         vs[k][j] = c < f.p ? vbuf[(long long)(r0 + k) * vstride + f.idx_off + c] : x[(long long)(r0 + k) * N + id[c]];
     }
     __syncthreads();
-    dense_chunk<T, NR>(G, f.p, i, c0, cn, jg, vs, acc);
+    dense_chunk<T, NR, true>(G, m, i, c0, cn, jg, vs, acc);
   }
 #pragma unroll
   for (int k = 0; k < NR; ++k) part[jg][k][rl] = acc[k];
@@ -1556,12 +1566,10 @@ void sweep_bwd(const MfDev<T>& mf, const Plan& plan, int l, int groups, int nrhs
   static_assert(stat <= kLdsBytes, "sweep arrays exceed the LDS");
   if (vec_in_lds(vb, stat))
     LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR, true, TPB>), dim3(cnt, groups), dim3(TPB), vb, st,
-               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq,
-               mf.G);
+               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq);
   else
     LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR, false, TPB>), dim3(cnt, groups), dim3(TPB), 0, st,
-               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq,
-               mf.G);
+               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq);
 }
 
 
@@ -1587,8 +1595,9 @@ void dense_bwd(const MfDev<T>& mf, const Plan& plan, int l, int groups, int nrhs
              st, mf.G, mf.fronts, mf.idx, x, vbuf, first, chunks, nrhs, (long long)plan.N, (long long)plan.sum_pq);
 }
 
-// Forms the sweep operators of dense level l from its factor: the panel
-// chains of both sweeps run on unit vectors, NF per workgroup.
+// Forms the sweep operators of dense level l from its factor: the forward
+// chain and the transposed backward chain run on the unit vectors e_j,
+// j < p, NF per workgroup.
 template <typename T, int TPB>
 void form_level(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st) {
   constexpr int NF = sizeof(T) == 4 ? 8 : 4;
@@ -1596,14 +1605,13 @@ void form_level(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st) {
   const int cnt = plan.level_ptr[l + 1] - first;
   const int maxm = plan.level_maxpq[l], maxp = plan.level_maxp[l];
   const size_t vb = (size_t)maxm * NF * sizeof(cplx<T>);
-  LSP_REQUIRE(vec_in_lds(vb, fwd_static_lds<T, NF, TPB>()) && vec_in_lds(vb, bwd_static_lds<T, NF, TPB>()),
-              "dense sweep level exceeds the LDS");
-  LSP_LAUNCH("form_fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NF, true, TPB, true>), dim3(cnt, (maxp + NF - 1) / NF),
-             dim3(TPB), vb, st, mf.F, mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm, nullptr, nullptr, first, 0,
-             (long long)plan.N, 0LL, mf.G);
-  LSP_LAUNCH("form_bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NF, true, TPB, true>), dim3(cnt, (maxm + NF - 1) / NF),
-             dim3(TPB), vb, st, mf.F, mf.Dinv, mf.fronts, mf.idx, nullptr, nullptr, first, 0, (long long)plan.N, 0LL,
-             mf.G);
+  LSP_REQUIRE(vec_in_lds(vb, fwd_static_lds<T, NF, TPB>()), "dense sweep level exceeds the LDS");
+  LSP_LAUNCH("form_fwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NF, true, TPB, true, false>),
+             dim3(cnt, (maxp + NF - 1) / NF), dim3(TPB), vb, st, mf.F, mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm,
+             nullptr, nullptr, first, 0, (long long)plan.N, 0LL, mf.G);
+  LSP_LAUNCH("form_bwd", (int)sizeof(cplx<T>), (fwd_kernel<T, NF, true, TPB, true, true>),
+             dim3(cnt, (maxp + NF - 1) / NF), dim3(TPB), vb, st, mf.F, mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm,
+             nullptr, nullptr, first, 0, (long long)plan.N, 0LL, mf.G);
 }
 
 // Formation of dense level l once its factorisation is enqueued on st.

@@ -42,8 +42,9 @@ struct Plan {
   std::vector<int> level_maxp, level_maxpq;
   std::vector<int> level_tile;    // trailing-update tile (32, 64 or 128) per level
   // Levels whose sweeps apply formed dense operators instead of the panel
-  // chain: per front the forward operator Gf (m x p, column-major) and the
-  // backward operator Gb (p x m, column-major) at g_off, 2 m p entries.
+  // chain: per front the forward operator Gf (m x p, column-major) at g_off
+  // and the backward operator Gb (p x m) stored by rows (Gb^T, m x p,
+  // column-major) after it, 2 m p entries.
   std::vector<char> level_dense;
   long long dense_elems = 0;      // sum over dense fronts of 2 m p
   double dense_entries = 0.0;     // sum over dense fronts of m p (one sweep's reads)

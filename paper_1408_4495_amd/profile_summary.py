@@ -45,8 +45,10 @@ def registry_key(name):
         base = FFT_MODE.get(args[2], base)
     if base == "gemm_update" and args and args[-1] == "true":
         base = "update_lu"  # fused with the next diagonal-block factorisation
-    if base in ("fwd", "bwd") and args and args[-1] == "true":
-        base = "form_" + base  # the sweep chain run on unit vectors (operator formation)
+    if base == "fwd" and len(args) >= 2 and args[-2] == "true":
+        # the forward chain (or the transposed backward one) run on unit
+        # vectors: formation of a dense level's operators
+        base = "form_bwd" if args[-1] == "true" else "form_fwd"
     prec = ""
     if args:
         if re.match(r"(HIP_vector_type<)?float\b", args[0]):
