@@ -1379,6 +1379,230 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
   }
 }
 
+// ---- Sweeps of the small-front levels (Plan::level_small_sweep): fronts of
+// at most two panels whose rows below (columns right of) the first panel
+// fit 128 threads.  Every load of a front (both inverse blocks, both
+// panels' L21 rows or U12 columns, the row order) is issued at the start,
+// so the chain waits for memory once instead of once per panel; vectors in
+// LDS.  The arithmetic is that of fwd_kernel / bwd_kernel with 256 threads
+// in the same order (gather sums, 32-term row products in j order, column
+// groups added in order), so the results are the same bit for bit and the
+// choice between them may depend on the group size: these run for complex64
+// groups of one right-hand side, where their registers allow three or more
+// workgroups per CU.
+constexpr int SM = 160;  // front rows a small-front sweep holds in LDS
+
+// v = [z(I); 0] + children's updates of a front into LDS (k < nr)
+template <typename T, int NR>
+__device__ __forceinline__ void gather_front_input(cplx<T> (*vl)[SM], const FrontDev& f, const int* __restrict__ id,
+                                                   const int* __restrict__ cp, const cplx<T>* __restrict__ z,
+                                                   const cplx<T>* __restrict__ vbuf, const int r0, const int nr,
+                                                   const long long N, const long long vstride) {
+  const int m = f.p + f.q, tid = threadIdx.x;
+  for (int e0 = 0; e0 < m * nr; e0 += 2 * 256) {
+    int gidx[2], q0[2], q1[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = min(e0 + tid + 256 * u, m * nr - 1), r = e % m;
+      gidx[u] = id[min(r, f.p - 1)];
+      q0[u] = f.cidx[0] >= 0 ? cp[2 * r] : -1;
+      q1[u] = f.cidx[1] >= 0 ? cp[2 * r + 1] : -1;
+    }
+    cplx<T> sv[2], c0v[2], c1v[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = min(e0 + tid + 256 * u, m * nr - 1), k = e / m;
+      const long long rb = (long long)(r0 + k) * vstride;
+      sv[u] = z[(long long)(r0 + k) * N + gidx[u]];
+      c0v[u] = vbuf[rb + (q0[u] >= 0 ? f.cidx[0] + q0[u] : 0)];
+      c1v[u] = vbuf[rb + (q1[u] >= 0 ? f.cidx[1] + q1[u] : 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = e0 + tid + 256 * u;
+      if (e < m * nr) {
+        const int r = e % m, k = e / m;
+        cplx<T> s = r < f.p ? sv[u] : mk<T>(0, 0);
+        if (q0[u] >= 0) s = cadd(s, c0v[u]);
+        if (q1[u] >= 0) s = cadd(s, c1v[u]);
+        vl[k][r] = s;
+      }
+    }
+  }
+}
+
+// Forward sweep of a small front: threads 0-127 hold the L21 rows of panel
+// 0 (row kb0 + t), threads 128-255 those of panel 1 (row p + t - 128).
+template <typename T, int NR>
+__global__ void __launch_bounds__(256) fwd_small_kernel(const cplx<T>* __restrict__ Fbuf,
+                                                        const cplx<T>* __restrict__ Dinv,
+                                                        const FrontDev* __restrict__ fr, const int* __restrict__ idx,
+                                                        const int* __restrict__ cpos, const int* __restrict__ perm,
+                                                        const cplx<T>* __restrict__ z, cplx<T>* __restrict__ vbuf,
+                                                        int first, int nrhs, long long N, long long vstride) {
+  static_assert(NR * NB <= 256, "one gather thread per panel entry");
+  __shared__ cplx<T> Li[2][NB][NB + 1];
+  __shared__ cplx<T> vl[NR][SM];
+  __shared__ cplx<T> tb[NR][NB];
+  __shared__ cplx<T> yb[NR][NB];
+  const FrontDev f = fr[first + blockIdx.x];
+  const int r0 = blockIdx.y * NR, nr = min(NR, nrhs - r0);
+  const int m = f.p + f.q, nblk = (f.p + NB - 1) / NB;
+  const cplx<T>* F = Fbuf + f.f_off;
+  const int* id = idx + f.idx_off;
+  const int* cp = cpos + 2 * f.idx_off;
+  const int* pm = perm + f.piv_off;
+  const int tid = threadIdx.x, half = tid / 128, t = tid % 128;
+  const int gk = tid / NB, gj = tid % NB;
+  // this thread's L21 row (a front of one panel: the upper half reloads
+  // panel 0's rows, unused)
+  const int hk0 = min(half, nblk - 1) * NB, hkb = min(NB, f.p - hk0);
+  const int hr = min(hk0 + hkb + t, m - 1);
+  cplx<T> lr[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) lr[j] = F[(long long)(hk0 + min(j, hkb - 1)) * m + hr];
+  const int pn0 = pm[min(gj, f.p - 1)], pn1 = pm[min(NB + gj, f.p - 1)];
+  const cplx<T>* Lg = Dinv + f.dinv_off;
+  const cplx<T>* Lg1 = Lg + (nblk > 1 ? 2 * NB * NB : 0);
+  cplx<T> l0[4], l1[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    l0[u] = Lg[tid + 256 * u];
+    l1[u] = Lg1[tid + 256 * u];
+  }
+  gather_front_input<T, NR>(vl, f, id, cp, z, vbuf, r0, nr, N, vstride);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u;
+    Li[0][e % NB][e / NB] = l0[u];
+    Li[1][e % NB][e / NB] = l1[u];
+  }
+  __syncthreads();
+  for (int b = 0; b < nblk; ++b) {
+    const int k0 = b * NB, kb = min(NB, f.p - k0), k1 = k0 + kb;
+    if (tid < NR * NB) tb[gk][gj] = gk < nr && gj < kb ? vl[min(gk, nr - 1)][b ? pn1 : pn0] : mk<T>(0, 0);
+    __syncthreads();
+    cplx<T> y[NR];
+    tri_apply<T, NR>(Li[b], tb, tid, y);
+    if (tid % 8 == 0) {
+      const int i = tid / 8;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        yb[k][i] = y[k];
+        if (k < nr && i < kb) vl[k][k0 + i] = y[k];
+      }
+    }
+    __syncthreads();
+    const int r = k1 + t;
+    if (half == b && r < m) {
+      cplx<T> acc[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] = vl[min(k, nr - 1)][r];
+      chunked<NB * NR, sizeof(T) == 8 ? 4 : 8>(
+          [&](int q) { return yb[q % NR][q / NR]; },
+          [&](int q, const cplx<T>& yv) { acc[q % NR] = cfms(acc[q % NR], lr[q / NR], yv); });
+#pragma unroll
+      for (int k = 0; k < NR; ++k)
+        if (k < nr) vl[k][r] = acc[k];
+    }
+    __syncthreads();
+  }
+  cplx<T>* vg = vbuf + (long long)r0 * vstride + f.idx_off;
+  for (int e = tid; e < m * nr; e += 256) {
+    const int r = e % m, k = e / m;
+    vg[(long long)k * vstride + r] = vl[k][r];
+  }
+}
+
+// Backward sweep of a small front: thread (j, grp) = (tid % 32, tid / 32)
+// holds, for each panel, the U12 row j entries of the columns k1 + grp + 8t
+// (t < 16); the eight column groups are added in order.
+template <typename T, int NR>
+__global__ void __launch_bounds__(256) bwd_small_kernel(const cplx<T>* __restrict__ Fbuf,
+                                                        const cplx<T>* __restrict__ Dinv,
+                                                        const FrontDev* __restrict__ fr, const int* __restrict__ idx,
+                                                        cplx<T>* __restrict__ x, cplx<T>* __restrict__ vbuf, int first,
+                                                        int nrhs, long long N, long long vstride) {
+  constexpr int G = 8, TU = 128 / G;
+  __shared__ cplx<T> Ui[2][NB][NB + 1];
+  __shared__ cplx<T> vl[NR][SM];
+  __shared__ cplx<T> part[G][NR][NB];
+  __shared__ cplx<T> rb[NR][NB];
+  const FrontDev f = fr[first + blockIdx.x];
+  const int r0 = blockIdx.y * NR, nr = min(NR, nrhs - r0);
+  const int m = f.p + f.q, nblk = (f.p + NB - 1) / NB;
+  const cplx<T>* F = Fbuf + f.f_off;
+  const int* id = idx + f.idx_off;
+  const int tid = threadIdx.x, j = tid % NB, grp = tid / NB;
+  cplx<T> uc[2][TU];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int k0 = min(b, nblk - 1) * NB, kb = min(NB, f.p - k0), k1 = k0 + kb;
+#pragma unroll
+    for (int t = 0; t < TU; ++t) uc[b][t] = F[(k0 + min(j, kb - 1)) + (long long)min(k1 + grp + G * t, m - 1) * m];
+  }
+  const cplx<T>* Ug = Dinv + f.dinv_off + NB * NB;
+  const cplx<T>* Ug1 = Ug + (nblk > 1 ? 2 * NB * NB : 0);
+  cplx<T> u0[4], u1[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    u0[u] = Ug[tid + 256 * u];
+    u1[u] = Ug1[tid + 256 * u];
+  }
+  const int gi0 = id[min(tid / 8, f.p - 1)], gi1 = id[min(NB + tid / 8, f.p - 1)];
+  // v = [y(I) from the forward sweep; x(B) from the ancestors]
+  const cplx<T>* vg = vbuf + (long long)r0 * vstride + f.idx_off;
+  for (int e = tid; e < m * nr; e += 256) {
+    const int r = e % m, k = e / m;
+    vl[k][r] = r >= f.p ? x[(long long)(r0 + k) * N + id[r]] : vg[(long long)k * vstride + r];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u;
+    Ui[0][e % NB][e / NB] = u0[u];
+    Ui[1][e % NB][e / NB] = u1[u];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 1; b >= 0; --b) {  // compile-time b: uc stays in registers
+    if (b >= nblk) continue;
+    const int k0 = b * NB, kb = min(NB, f.p - k0), k1 = k0 + kb;
+    cplx<T> acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
+    chunked<TU * NR, (sizeof(T) == 8 && NR >= 4) ? 4 : 8>(
+        [&](int q) {
+          const int c = k1 + grp + G * (q / NR), k = q % NR;
+          const cplx<T> v = vl[min(k, nr - 1)][min(c, m - 1)];
+          return c < m && k < nr ? v : mk<T>(0, 0);
+        },
+        [&](int q, const cplx<T>& xv) { acc[q % NR] = cfma(acc[q % NR], uc[b][q / NR], xv); });
+#pragma unroll
+    for (int k = 0; k < NR; ++k) part[grp][k][j] = acc[k];
+    __syncthreads();
+    for (int e = tid; e < NR * NB; e += 256) {
+      const int jj = e % NB, k = e / NB;
+      cplx<T> s = part[0][k][jj];
+      for (int g = 1; g < G; ++g) s = cadd(s, part[g][k][jj]);
+      rb[k][jj] = (k < nr && jj < kb) ? csub(vl[k][k0 + jj], s) : mk<T>(0, 0);
+    }
+    __syncthreads();
+    cplx<T> xs[NR];
+    tri_apply<T, NR>(Ui[b], rb, tid, xs);
+    const int i = tid / 8;
+    if (tid % 8 == 0 && i < kb) {
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        if (k < nr) {
+          vl[k][k0 + i] = xs[k];
+          x[(long long)(r0 + k) * N + (b ? gi1 : gi0)] = xs[k];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ---- Sweeps of the dense levels: the formed operators as matrix-vector
 // products.  Workgroup (front, chunk of DR rows, right-hand-side group):
 // thread (row tid % DR, column class tid / DR) sums the columns of its class
@@ -1637,11 +1861,28 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
       LSP_HIP(hipStreamWaitEvent(st, form_done, 0));
       form_done = nullptr;
     }
+    if constexpr (sizeof(T) == 4 && NR == 1) {
+      if (plan.level_small_sweep[l]) {
+        LSP_LAUNCH("fwd", (int)sizeof(cplx<T>), (fwd_small_kernel<T, NR>),
+                   dim3(plan.level_ptr[l + 1] - plan.level_ptr[l], groups), dim3(256), 0, st, mf.F, mf.Dinv, mf.fronts,
+                   mf.idx, mf.cpos, mf.perm, z, vbuf, plan.level_ptr[l], nrhs, (long long)plan.N,
+                   (long long)plan.sum_pq);
+        continue;
+      }
+    }
     if (plan.level_dense[l]) dense_fwd<T, NR>(mf, plan, l, groups, nrhs, z, vbuf, st);
     else if (wide_level(plan, l)) sweep_fwd<T, NR, 512>(mf, plan, l, groups, nrhs, z, vbuf, st);
     else sweep_fwd<T, NR, 256>(mf, plan, l, groups, nrhs, z, vbuf, st);
   }
   for (int l = plan.nlevels - 1; l >= 0; --l) {
+    if constexpr (sizeof(T) == 4 && NR == 1) {
+      if (plan.level_small_sweep[l]) {
+        LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_small_kernel<T, NR>),
+                   dim3(plan.level_ptr[l + 1] - plan.level_ptr[l], groups), dim3(256), 0, st, mf.F, mf.Dinv, mf.fronts,
+                   mf.idx, x, vbuf, plan.level_ptr[l], nrhs, (long long)plan.N, (long long)plan.sum_pq);
+        continue;
+      }
+    }
     if (plan.level_dense[l]) dense_bwd<T, NR>(mf, plan, l, groups, nrhs, x, vbuf, st);
     else if (wide_level(plan, l)) sweep_bwd<T, NR, 512>(mf, plan, l, groups, nrhs, x, vbuf, st);
     else sweep_bwd<T, NR, 256>(mf, plan, l, groups, nrhs, x, vbuf, st);

@@ -230,6 +230,13 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
       P.sweep_entries -= (double)(m - k0 - kb) * kb + (double)P.nb * P.nb;
     }
   }
+  P.level_small_sweep.assign(P.nlevels, 0);
+  for (int l = 0; l < P.nlevels; ++l) {
+    bool ok = !P.level_dense[l] && P.level_maxp[l] <= 2 * P.nb && P.level_maxpq[l] <= 160;
+    for (int i = P.level_ptr[l]; ok && i < P.level_ptr[l + 1]; ++i)
+      ok = P.fronts[i].q + P.fronts[i].p - std::min(P.fronts[i].p, P.nb) <= 128;
+    P.level_small_sweep[l] = ok;
+  }
   P.front_elems = f_off;
   P.dinv_elems = dinv_off;
   P.sum_p = piv_off;

@@ -49,6 +49,9 @@ struct Plan {
   long long dense_elems = 0;      // sum over dense fronts of 2 m p
   double dense_entries = 0.0;     // sum over dense fronts of m p (one sweep's reads)
   int dense_levels = 0;
+  // Levels swept by the small-front kernels (not dense; at most two panels,
+  // at most 160 rows, at most 128 rows below each front's first panel).
+  std::vector<char> level_small_sweep;
   int nlevels = 0;
   long long front_elems = 0;      // sum (p+q)^2
   long long dinv_elems = 0;       // sum over panels of 2 nb^2

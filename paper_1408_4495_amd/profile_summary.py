@@ -45,6 +45,8 @@ def registry_key(name):
         base = FFT_MODE.get(args[2], base)
     if base == "gemm_update" and args and args[-1] == "true":
         base = "update_lu"  # fused with the next diagonal-block factorisation
+    if base in ("fwd_small", "bwd_small"):
+        base = base[:3]  # the small-front levels' sweeps, timed under the same name
     if base == "fwd" and len(args) >= 2 and args[-2] == "true":
         # the forward chain (or the transposed backward one) run on unit
         # vectors: formation of a dense level's operators
