@@ -172,7 +172,12 @@ __global__ void __launch_bounds__(1024) fft_lines_kernel(cplx<T>* __restrict__ W
   cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
-  const int c0 = blockIdx.x * a.LPW;
+  // Workgroups go to the 8 XCDs round-robin (workgroup b to XCD b mod 8),
+  // each XCD with its own L2: give each XCD a contiguous range of line
+  // blocks, so that the lines sharing cache lines in a strided pass (16
+  // complex64 or 8 complex128 per 128 bytes) are read through one L2.
+  const int bx = gridDim.x % 8 == 0 ? (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int c0 = bx * a.LPW;
   const int o = blockIdx.y;
   const int rhs = blockIdx.z;
   const int nl = min(a.LPW, a.ncols - c0);

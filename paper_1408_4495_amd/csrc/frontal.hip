@@ -1611,21 +1611,27 @@ __global__ void __launch_bounds__(256) bwd_small_kernel(const cplx<T>* __restric
 // right-hand side's result does not depend on the group it is solved in.
 constexpr int DR = 16, DJ = 256 / DR, DC = 256;
 
-// Partial products of the staged columns [c0, c0 + cn) for row r of an
-// operator stored column-major (ROWS false: entry (r, c) at c ld + r) or
-// row-major (ROWS true: at r ld + c): DC / DJ loads per thread, all issued
-// before the first multiply (clamped columns, multiplied only when in range).
-template <typename T, int NR, bool ROWS>
-__device__ __forceinline__ void dense_chunk(const cplx<T>* __restrict__ G, const long long ld, const int r,
-                                            const int c0, const int cn, const int jg, const cplx<T> (*vs)[DC],
-                                            cplx<T> (&acc)[NR]) {
-  constexpr int U = DC / DJ;
-  cplx<T> g[U];
+// Operator entries of the columns [c0, c0 + cn) of this thread's class for
+// row r, stored column-major (ROWS false: entry (r, c) at c ld + r) or
+// row-major (ROWS true: at r ld + c): DC / DJ loads per thread (clamped
+// columns, multiplied only when in range), issued before the input is
+// staged so that the two overlap.
+constexpr int DU = DC / DJ;
+template <typename T, bool ROWS>
+__device__ __forceinline__ void dense_load(const cplx<T>* __restrict__ G, const long long ld, const int r,
+                                           const int c0, const int cn, const int jg, cplx<T> (&g)[DU]) {
 #pragma unroll
-  for (int t = 0; t < U; ++t) {
+  for (int t = 0; t < DU; ++t) {
     const long long c = c0 + min(jg + DJ * t, cn - 1);
     g[t] = ROWS ? G[(long long)r * ld + c] : G[c * ld + r];
   }
+}
+
+// Partial products of the staged columns with the loaded entries.
+template <typename T, int NR>
+__device__ __forceinline__ void dense_chunk(const cplx<T> (&g)[DU], const int cn, const int jg,
+                                            const cplx<T> (*vs)[DC], cplx<T> (&acc)[NR]) {
+  constexpr int U = DU;
 #pragma unroll
   for (int t = 0; t < U; ++t) {
     const int c = jg + DJ * t;
@@ -1665,18 +1671,19 @@ __global__ void __launch_bounds__(256) fwd_dense_kernel(const cplx<T>* __restric
     if (q1 >= 0) s = cadd(s, vbuf[rb + f.cidx[1] + q1]);
     return s;
   };
-  cplx<T> acc[NR];
+  cplx<T> acc[NR], g[DU];
 #pragma unroll
   for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
   for (int c0 = 0; c0 < f.p; c0 += DC) {
     const int cn = min(DC, f.p - c0);
     if (c0 > 0) __syncthreads();  // the previous columns' reads are done
+    dense_load<T, false>(G, m, r, c0, cn, jg, g);
     for (int e = tid; e < NR * DC; e += 256) {
       const int j = e % DC, k = e / DC;
       if (j < cn && k < nr) vs[k][j] = vin(c0 + j, k);
     }
     __syncthreads();
-    dense_chunk<T, NR, false>(G, m, r, c0, cn, jg, vs, acc);
+    dense_chunk<T, NR>(g, cn, jg, vs, acc);
   }
 #pragma unroll
   for (int k = 0; k < NR; ++k) part[jg][k][rl] = acc[k];
@@ -1713,19 +1720,20 @@ __global__ void __launch_bounds__(256) bwd_dense_kernel(const cplx<T>* __restric
   const int i = min(row0 + rl, f.p - 1);  // rows past p compute a copy of row p - 1, never stored
   const int* id = idx + f.idx_off;
   const cplx<T>* G = Gop + f.g_off + (long long)m * f.p;
-  cplx<T> acc[NR];
+  cplx<T> acc[NR], g[DU];
 #pragma unroll
   for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
   for (int c0 = 0; c0 < m; c0 += DC) {
     const int cn = min(DC, m - c0);
     if (c0 > 0) __syncthreads();  // the previous columns' reads are done
+    dense_load<T, true>(G, m, i, c0, cn, jg, g);
     for (int e = tid; e < NR * DC; e += 256) {
       const int j = e % DC, k = e / DC, c = c0 + j;
       if (j < cn && k < nr)
         vs[k][j] = c < f.p ? vbuf[(long long)(r0 + k) * vstride + f.idx_off + c] : x[(long long)(r0 + k) * N + id[c]];
     }
     __syncthreads();
-    dense_chunk<T, NR, true>(G, m, i, c0, cn, jg, vs, acc);
+    dense_chunk<T, NR>(g, cn, jg, vs, acc);
   }
 #pragma unroll
   for (int k = 0; k < NR; ++k) part[jg][k][rl] = acc[k];
