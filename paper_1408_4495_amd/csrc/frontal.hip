@@ -1387,9 +1387,9 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
 // LDS.  The arithmetic is that of fwd_kernel / bwd_kernel with 256 threads
 // in the same order (gather sums, 32-term row products in j order, column
 // groups added in order), so the results are the same bit for bit and the
-// choice between them may depend on the group size: these run for complex64
-// groups of one right-hand side, where their registers allow three or more
-// workgroups per CU.
+// choice between them may depend on the group size: these run for groups
+// of one right-hand side (the backward one in complex64 only: in complex128
+// its registers allow fewer workgroups per CU than the chain kernel's).
 constexpr int SM = 160;  // front rows a small-front sweep holds in LDS
 
 // v = [z(I); 0] + children's updates of a front into LDS (k < nr)
@@ -1869,7 +1869,7 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
       LSP_HIP(hipStreamWaitEvent(st, form_done, 0));
       form_done = nullptr;
     }
-    if constexpr (sizeof(T) == 4 && NR == 1) {
+    if constexpr (NR == 1) {
       if (plan.level_small_sweep[l]) {
         LSP_LAUNCH("fwd", (int)sizeof(cplx<T>), (fwd_small_kernel<T, NR>),
                    dim3(plan.level_ptr[l + 1] - plan.level_ptr[l], groups), dim3(256), 0, st, mf.F, mf.Dinv, mf.fronts,
