@@ -179,9 +179,15 @@ void lsp_problem_destroy(lsp_problem* problem);
 
 /* Numeric multifrontal LU of M (Section 2.2, nested dissection and the
  * multifrontal method), level by level from the leaves, with partial
- * pivoting inside each front's fully-summed block.  Waits for the stream
- * to report the pivot-health figure (reduced on the device into pinned host
- * memory, which the calling thread polls).  Errors: LSP_ERR_SINGULAR (in
+ * pivoting inside each front's fully-summed block.  On the dense sweep
+ * levels (lsp_options.dense_sweeps) it then forms each front's forward and
+ * backward sweep operators from the factor, on a side stream the library
+ * keeps per device (default priority; each level's formation waits for that
+ * level's factorisation through an event); the next sweeps on the problem's
+ * stream, the next lsp_factor and lsp_problem_destroy wait for it.  Waits
+ * for the stream to report the pivot-health figure (reduced on the device
+ * into pinned host memory, which the calling thread polls), not for the
+ * formation.  Errors: LSP_ERR_SINGULAR (in
  * some 32-wide panel the smallest pivot modulus |re| + |im| is at most 64
  * eps times the largest, or is NaN; eps of the factor precision),
  * LSP_ERR_HIP. */
