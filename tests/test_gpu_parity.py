@@ -221,7 +221,12 @@ def test_dense_sweeps_match_panel_chains(prec, tol):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batched_equals_solo_bitwise(prec):
     """Lockstep batching: each right-hand side of a block of 5 (groups of 4 + 1
-    in the triangular sweeps) is bit-identical to its solo solve."""
+    in the triangular sweeps) is bit-identical to its solo solve.  The solo
+    solves sweep the small-front levels with the one-right-hand-side kernels
+    (`fwd_small_kernel`, and `bwd_small_kernel` in complex64), the block
+    with the panel-chain kernels, so this also checks that the two compute
+    in the same order; the top levels use the formed dense operators in
+    both."""
     n, d = 48, 2
     omega = 2 * np.pi * n / 8
     rng = np.random.default_rng([14084495, 77])
