@@ -218,6 +218,29 @@ def test_dense_sweeps_match_panel_chains(prec, tol):
     assert _rel(out[0], out[1]) <= tol
 
 
+def test_dense_formation_lifecycle():
+    """The dense levels' operators are formed on the library's side stream
+    after lsp_factor returns: destroying a problem right after its
+    factorisation, and factoring a problem twice before solving, leave
+    every later solve bit-identical to a plain factor-then-solve."""
+    n, d = 64, 2
+    omega = 2 * np.pi * n / 8
+    m = synth.medium_single_bump(n, d, 0.25, 0.12)
+    z = synth.random_complex((1, n ** d), seed=41)
+    lsp, torch, plan, pb = _problem(n, d, omega, m, precision="mixed")
+    assert plan.stats()["dense_levels"] > 0
+    pb.factor()
+    ref = pb.solve_M(z).cpu().numpy()
+    other = lsp.Problem(plan, omega, m)
+    other.factor()
+    del other  # destroyed while its formation may still run
+    pb2 = lsp.Problem(plan, omega, m)
+    pb2.factor()
+    pb2.factor()  # the second factorisation waits for the first one's formation
+    x = pb2.solve_M(z).cpu().numpy()
+    assert np.array_equal(x, ref)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batched_equals_solo_bitwise(prec):
     """Lockstep batching: each right-hand side of a block of 5 (groups of 4 + 1
