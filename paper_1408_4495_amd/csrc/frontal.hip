@@ -1243,7 +1243,8 @@ template <typename T, int NR, bool VL, int TPB>
 __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fbuf, const cplx<T>* __restrict__ Dinv,
                                                   const FrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                   cplx<T>* __restrict__ x, cplx<T>* __restrict__ vbuf, int first,
-                                                  int nrhs, long long N, long long vstride) {
+                                                  int nrhs, long long N, long long vstride,
+                                                  double2* __restrict__ xw) {
   static_assert(TPB == 256 || TPB == 512, "256 or 512 threads");
   constexpr int G = TPB / NB;  // column groups
   constexpr int IPT = NB * NB / TPB;  // inverse-block entries per thread
@@ -1364,6 +1365,7 @@ __global__ void __launch_bounds__(TPB) bwd_kernel(const cplx<T>* __restrict__ Fb
           if (k < nr) {
             vp[k * vs + k0 + i] = xs[k];
             x[(long long)(r0 + k) * N + gi] = xs[k];
+            if (xw) xw[(long long)(r0 + k) * N + gi] = widen(xs[k]);
           }
         }
       }
@@ -1522,7 +1524,8 @@ __global__ void __launch_bounds__(256) bwd_small_kernel(const cplx<T>* __restric
                                                         const cplx<T>* __restrict__ Dinv,
                                                         const FrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                         cplx<T>* __restrict__ x, cplx<T>* __restrict__ vbuf, int first,
-                                                        int nrhs, long long N, long long vstride) {
+                                                        int nrhs, long long N, long long vstride,
+                                                        double2* __restrict__ xw) {
   constexpr int G = 8, TU = 128 / G;
   __shared__ cplx<T> Ui[2][NB][NB + 1];
   __shared__ cplx<T> vl[NR][SM];
@@ -1596,6 +1599,7 @@ __global__ void __launch_bounds__(256) bwd_small_kernel(const cplx<T>* __restric
         if (k < nr) {
           vl[k][k0 + i] = xs[k];
           x[(long long)(r0 + k) * N + (b ? gi1 : gi0)] = xs[k];
+          if (xw) xw[(long long)(r0 + k) * N + (b ? gi1 : gi0)] = widen(xs[k]);
         }
       }
     }
@@ -1707,7 +1711,8 @@ template <typename T, int NR>
 __global__ void __launch_bounds__(256) bwd_dense_kernel(const cplx<T>* __restrict__ Gop, const FrontDev* __restrict__ fr,
                                                         const int* __restrict__ idx, cplx<T>* __restrict__ x,
                                                         const cplx<T>* __restrict__ vbuf, int first, int chunks,
-                                                        int nrhs, long long N, long long vstride) {
+                                                        int nrhs, long long N, long long vstride,
+                                                        double2* __restrict__ xw) {
   __shared__ cplx<T> vs[NR][DC];
   __shared__ cplx<T> part[DJ][NR][DR];
   const FrontDev f = fr[first + blockIdx.x / chunks];
@@ -1744,6 +1749,7 @@ __global__ void __launch_bounds__(256) bwd_dense_kernel(const cplx<T>* __restric
       cplx<T> s = part[0][k][tid % DR];
       for (int g = 1; g < DJ; ++g) s = cadd(s, part[g][k][tid % DR]);
       x[(long long)(r0 + k) * N + id[ii]] = s;
+      if (xw) xw[(long long)(r0 + k) * N + id[ii]] = widen(s);
     }
   }
 }
@@ -1790,7 +1796,7 @@ void sweep_fwd(const MfDev<T>& mf, const Plan& plan, int l, int groups, int nrhs
 
 template <typename T, int NR, int TPB>
 void sweep_bwd(const MfDev<T>& mf, const Plan& plan, int l, int groups, int nrhs, cplx<T>* x, cplx<T>* vbuf,
-               hipStream_t st) {
+               hipStream_t st, double2* xw) {
   const int first = plan.level_ptr[l];
   const int cnt = plan.level_ptr[l + 1] - first;
   const size_t vb = (size_t)plan.level_maxpq[l] * NR * sizeof(cplx<T>);
@@ -1798,10 +1804,10 @@ void sweep_bwd(const MfDev<T>& mf, const Plan& plan, int l, int groups, int nrhs
   static_assert(stat <= kLdsBytes, "sweep arrays exceed the LDS");
   if (vec_in_lds(vb, stat))
     LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR, true, TPB>), dim3(cnt, groups), dim3(TPB), vb, st,
-               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq);
+               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq, xw);
   else
     LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_kernel<T, NR, false, TPB>), dim3(cnt, groups), dim3(TPB), 0, st,
-               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq);
+               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq, xw);
 }
 
 
@@ -1819,12 +1825,12 @@ void dense_fwd(const MfDev<T>& mf, const Plan& plan, int l, int groups, int nrhs
 
 template <typename T, int NR>
 void dense_bwd(const MfDev<T>& mf, const Plan& plan, int l, int groups, int nrhs, cplx<T>* x, const cplx<T>* vbuf,
-               hipStream_t st) {
+               hipStream_t st, double2* xw) {
   const int first = plan.level_ptr[l];
   const int cnt = plan.level_ptr[l + 1] - first;
   const int chunks = (plan.level_maxp[l] + DR - 1) / DR;
   LSP_LAUNCH("bwd_dense", (int)sizeof(cplx<T>), (bwd_dense_kernel<T, NR>), dim3(cnt * chunks, groups), dim3(256), 0,
-             st, mf.G, mf.fronts, mf.idx, x, vbuf, first, chunks, nrhs, (long long)plan.N, (long long)plan.sum_pq);
+             st, mf.G, mf.fronts, mf.idx, x, vbuf, first, chunks, nrhs, (long long)plan.N, (long long)plan.sum_pq, xw);
 }
 
 // Forms the sweep operators of dense level l from its factor: the forward
@@ -1862,7 +1868,7 @@ void form_after(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st, con
 
 template <typename T, int NR>
 void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
-                  hipStream_t st, hipEvent_t form_done) {
+                  hipStream_t st, hipEvent_t form_done, double2* xw) {
   const int groups = (nrhs + NR - 1) / NR;
   for (int l = 0; l < plan.nlevels; ++l) {
     if (plan.level_dense[l] && form_done) {
@@ -1887,13 +1893,13 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
       if (plan.level_small_sweep[l]) {
         LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_small_kernel<T, NR>),
                    dim3(plan.level_ptr[l + 1] - plan.level_ptr[l], groups), dim3(256), 0, st, mf.F, mf.Dinv, mf.fronts,
-                   mf.idx, x, vbuf, plan.level_ptr[l], nrhs, (long long)plan.N, (long long)plan.sum_pq);
+                   mf.idx, x, vbuf, plan.level_ptr[l], nrhs, (long long)plan.N, (long long)plan.sum_pq, xw);
         continue;
       }
     }
-    if (plan.level_dense[l]) dense_bwd<T, NR>(mf, plan, l, groups, nrhs, x, vbuf, st);
-    else if (wide_level(plan, l)) sweep_bwd<T, NR, 512>(mf, plan, l, groups, nrhs, x, vbuf, st);
-    else sweep_bwd<T, NR, 256>(mf, plan, l, groups, nrhs, x, vbuf, st);
+    if (plan.level_dense[l]) dense_bwd<T, NR>(mf, plan, l, groups, nrhs, x, vbuf, st, xw);
+    else if (wide_level(plan, l)) sweep_bwd<T, NR, 512>(mf, plan, l, groups, nrhs, x, vbuf, st, xw);
+    else sweep_bwd<T, NR, 256>(mf, plan, l, groups, nrhs, x, vbuf, st, xw);
   }
 }
 
@@ -2062,18 +2068,18 @@ FactorSchedule factor_schedule(const Plan& plan, bool fp64) {
 
 template <typename T>
 void mf_solve(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
-              hipStream_t st, hipEvent_t form_done) {
-  if (nrhs >= 8) solve_levels<T, 8>(mf, plan, nrhs, z, x, vbuf, st, form_done);
-  else if (nrhs >= 4) solve_levels<T, 4>(mf, plan, nrhs, z, x, vbuf, st, form_done);
-  else if (nrhs >= 2) solve_levels<T, 2>(mf, plan, nrhs, z, x, vbuf, st, form_done);
-  else solve_levels<T, 1>(mf, plan, nrhs, z, x, vbuf, st, form_done);
+              hipStream_t st, hipEvent_t form_done, double2* xw) {
+  if (nrhs >= 8) solve_levels<T, 8>(mf, plan, nrhs, z, x, vbuf, st, form_done, xw);
+  else if (nrhs >= 4) solve_levels<T, 4>(mf, plan, nrhs, z, x, vbuf, st, form_done, xw);
+  else if (nrhs >= 2) solve_levels<T, 2>(mf, plan, nrhs, z, x, vbuf, st, form_done, xw);
+  else solve_levels<T, 1>(mf, plan, nrhs, z, x, vbuf, st, form_done, xw);
 }
 
 template void mf_factor<double>(const MfDev<double>&, const Plan&, hipStream_t, const FormStream*);
 template void mf_factor<float>(const MfDev<float>&, const Plan&, hipStream_t, const FormStream*);
 template void mf_solve<double>(const MfDev<double>&, const Plan&, int, const double2*, double2*, double2*, hipStream_t,
-                               hipEvent_t);
+                               hipEvent_t, double2*);
 template void mf_solve<float>(const MfDev<float>&, const Plan&, int, const float2*, float2*, float2*, hipStream_t,
-                              hipEvent_t);
+                              hipEvent_t, double2*);
 
 }  // namespace lsp

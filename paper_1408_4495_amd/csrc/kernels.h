@@ -96,13 +96,13 @@ struct FactorSchedule {
 };
 FactorSchedule factor_schedule(const Plan& plan, bool fp64);
 // Forward and backward sweeps; form_done (may be null): an event the first
-// dense level's sweep waits for (the operators' formation).
+// dense level's sweep waits for (the operators' formation); xw (may be
+// null): the solution also written there in complex128.
 template <typename T>
 void mf_solve(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
-              hipStream_t st, hipEvent_t form_done);
+              hipStream_t st, hipEvent_t form_done, double2* xw);
 
 // ---- Krylov helpers (complex128 vectors, [nrhs][N] blocks)
-void launch_widen(double2* y, const float2* x, long long count, hipStream_t st);
 void launch_narrow(float2* y, const double2* x, long long count, hipStream_t st);
 void launch_scale_rhs(double2* y, const double2* x, double s, long long count, hipStream_t st);
 

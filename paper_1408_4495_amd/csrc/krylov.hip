@@ -448,10 +448,6 @@ __global__ void cycle_init_kernel(double2* __restrict__ H, double2* __restrict__
     gam[(long long)r * (restart + 1) + i] = make_double2(i == 0 ? scal[r * kScal + S_NORM] : 0.0, 0.0);
 }
 
-__global__ void widen_kernel(double2* __restrict__ y, const float2* __restrict__ x, long long count) {
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (long long)gridDim.x * blockDim.x)
-    y[e] = to_c128(x[e]);
-}
 __global__ void narrow_kernel(float2* __restrict__ y, const double2* __restrict__ x, long long count) {
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (long long)gridDim.x * blockDim.x)
     y[e] = to_c64(x[e]);
@@ -540,9 +536,6 @@ void k_cycle_init(double2* H, double2* gam, const double* scal, int restart, int
   LSP_LAUNCH("cycle_init", 0, cycle_init_kernel, dim3(nrhs), dim3(256), 0, st, H, gam, scal, restart, nrhs);
 }
 
-void launch_widen(double2* y, const float2* x, long long count, hipStream_t st) {
-  LSP_LAUNCH("widen", 0, widen_kernel, dim3(grid1(count)), dim3(256), 0, st, y, x, count);
-}
 void launch_narrow(float2* y, const double2* x, long long count, hipStream_t st) {
   LSP_LAUNCH("narrow", 0, narrow_kernel, dim3(grid1(count)), dim3(256), 0, st, y, x, count);
 }

@@ -532,13 +532,13 @@ void apply_precond(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2*
     launch_applyQ<double2>((double2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
     MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                      pb->d.pivstat, (double2*)pb->d.Gop};
-    mf_solve<double>(mf, P, nrhs, (const double2*)s.zq, out, (double2*)s.vbuf, st, pb->take_form_wait());
+    mf_solve<double>(mf, P, nrhs, (const double2*)s.zq, out, (double2*)s.vbuf, st, pb->take_form_wait(), nullptr);
   } else {
     launch_applyQ<float2>((float2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
     MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                     pb->d.pivstat, (float2*)pb->d.Gop};
-    mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st, pb->take_form_wait());
-    launch_widen(out, (const float2*)s.xs, (long long)nrhs * P.N, st);
+    // the backward sweeps also store the solution widened into out
+    mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st, pb->take_form_wait(), out);
   }
 }
 
@@ -548,13 +548,12 @@ void solve_M(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2* z, do
   if (pb->precision == LSP_FP64) {
     MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                      pb->d.pivstat, (double2*)pb->d.Gop};
-    mf_solve<double>(mf, P, nrhs, z, x, (double2*)s.vbuf, st, pb->take_form_wait());
+    mf_solve<double>(mf, P, nrhs, z, x, (double2*)s.vbuf, st, pb->take_form_wait(), nullptr);
   } else {
     launch_narrow((float2*)s.zq, z, (long long)nrhs * P.N, st);
     MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                     pb->d.pivstat, (float2*)pb->d.Gop};
-    mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st, pb->take_form_wait());
-    launch_widen(x, (const float2*)s.xs, (long long)nrhs * P.N, st);
+    mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st, pb->take_form_wait(), x);
   }
 }
 
