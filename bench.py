@@ -264,7 +264,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only: the solver has no multi-GPU path "
-              "(right-hand sides and requests shard across GPUs with no exchange; see DESIGN.md)",
+              "(right-hand sides and requests would shard across GPUs with no exchange)",
               file=sys.stderr)
         sys.exit(2)
 
