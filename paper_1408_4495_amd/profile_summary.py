@@ -64,7 +64,7 @@ def registry_key(name):
 def stats(path, title, cmd):
     rows = list(csv.DictReader(open(path)))
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
-    out = [f"# {title}", "", "Command (from the repository root on the GPU box):", "", "```", cmd, "```", "",
+    out = [f"# {title}", "", "Command (from the repository root, on the MI355X):", "", "```", cmd, "```", "",
            f"Total kernel time {tot / 1e6:.3f} ms.", "",
            "| kernel | calls | total ms | avg us | min us | max us | share |", "|---|---|---|---|---|---|---|"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:25]:
@@ -97,7 +97,7 @@ def traffic(fetch_csv, write_csv, title, cmd_f, cmd_w):
         a["fetch_kib"] += fv
         a["write_kib"] += wv
     kernels = {}
-    lines = [f"# {title}", "", "Commands (from the repository root on the GPU box):", "", "```", cmd_f, cmd_w, "```", "",
+    lines = [f"# {title}", "", "Commands (from the repository root, on the MI355X):", "", "```", cmd_f, cmd_w, "```", "",
              f"Calibration: the final `{short(copy_name)}` moves {copy_bytes} bytes each way and reads "
              f"FETCH_SIZE {copy_f:.1f} KiB, WRITE_SIZE {copy_w:.1f} KiB, so HBM bytes = "
              f"FETCH_SIZE x 1024 x {fs:.3f} + WRITE_SIZE x 1024 x {ws:.3f}.", "",
