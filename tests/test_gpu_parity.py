@@ -199,13 +199,14 @@ def test_c1_end_to_end_mixed():
     assert np.linalg.norm(g - op.apply(u.cpu().numpy()[0])) <= 1e-8 * np.linalg.norm(g)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 2e-5)])
-def test_dense_sweeps_match_panel_chains(prec, tol):
+@pytest.mark.parametrize("n,d,prec,tol", [(128, 2, "fp64", 1e-12), (128, 2, "mixed", 2e-5),
+                                          (16, 3, "fp64", 1e-12), (16, 3, "mixed", 2e-5)])
+def test_dense_sweeps_match_panel_chains(n, d, prec, tol):
     """The dense levels' formed operators applied as matrix-vector products
     give the panel chains' M^{-1} z up to rounding: FP64 to 1e-12, complex64
     to 2e-5 (both sides round a complex64 chain of the same factor); three
-    right-hand sides, so the sweeps run a group of two and a ragged one."""
-    n, d = 128, 2
+    right-hand sides, so the sweeps run a group of two and a ragged one.  In
+    3D (n = 16) the dense levels are the top four, fronts of up to 384 rows."""
     omega = 2 * np.pi * n / 8
     m = synth.medium_single_bump(n, d, 0.25, 0.12)
     z = synth.random_complex((3, n ** d), seed=31)
