@@ -82,6 +82,13 @@ typedef struct {
                         forward and backward sweep operators (2 m p entries
                         per front) and the sweeps apply them as dense
                         products; 0: every level uses the panel chain */
+  int blocked_sweeps; /* 1 (default): on the levels (not swept with dense
+                        operators) whose fronts have more than 1024 rows,
+                        or with at most 32 fronts of more than two panels,
+                        the sweeps run blocked: a panel chain per 256-row
+                        super-block of the pivots and wide matrix-vector
+                        products for the rest of the front; 0: the panel
+                        chain of one workgroup per front */
 } lsp_options;
 
 typedef struct {

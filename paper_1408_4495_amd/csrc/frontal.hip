@@ -1884,7 +1884,8 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
         continue;
       }
     }
-    if (plan.level_dense[l]) dense_fwd<T, NR>(mf, plan, l, groups, nrhs, z, vbuf, st);
+    if (plan.level_blocked[l]) blocked_sweep<T>(true, mf, plan, l, nrhs, z, x, vbuf, st, xw);
+    else if (plan.level_dense[l]) dense_fwd<T, NR>(mf, plan, l, groups, nrhs, z, vbuf, st);
     else if (wide_level(plan, l)) sweep_fwd<T, NR, 512>(mf, plan, l, groups, nrhs, z, vbuf, st);
     else sweep_fwd<T, NR, 256>(mf, plan, l, groups, nrhs, z, vbuf, st);
   }
@@ -1897,7 +1898,8 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
         continue;
       }
     }
-    if (plan.level_dense[l]) dense_bwd<T, NR>(mf, plan, l, groups, nrhs, x, vbuf, st, xw);
+    if (plan.level_blocked[l]) blocked_sweep<T>(false, mf, plan, l, nrhs, z, x, vbuf, st, xw);
+    else if (plan.level_dense[l]) dense_bwd<T, NR>(mf, plan, l, groups, nrhs, x, vbuf, st, xw);
     else if (wide_level(plan, l)) sweep_bwd<T, NR, 512>(mf, plan, l, groups, nrhs, x, vbuf, st, xw);
     else sweep_bwd<T, NR, 256>(mf, plan, l, groups, nrhs, x, vbuf, st, xw);
   }

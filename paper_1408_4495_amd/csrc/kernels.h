@@ -7,6 +7,7 @@
 namespace lsp {
 
 constexpr int kNbMax = 32;  // widest frontal panel
+constexpr int kSweepBlock = 256;  // rows of a super-block of the blocked sweeps
 
 // ---- Green's table
 void launch_ktable(double2* k, int n, int d, double omega, double2 k0, hipStream_t st);
@@ -101,6 +102,15 @@ FactorSchedule factor_schedule(const Plan& plan, bool fp64);
 template <typename T>
 void mf_solve(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
               hipStream_t st, hipEvent_t form_done, double2* xw);
+
+// Blocked forward (fwd) or backward sweep of level l (Plan::level_blocked):
+// a gather, then per 256-row super-block of the pivots a one-workgroup panel
+// chain and a wide matrix-vector product over the rest of the front; the
+// backward sweep starts with the product of the boundary columns.  Same
+// inputs and outputs as the panel-chain sweeps of that level.
+template <typename T>
+void blocked_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
+                   cplx<T>* vbuf, hipStream_t st, double2* xw);
 
 // ---- Krylov helpers (complex128 vectors, [nrhs][N] blocks)
 void launch_narrow(float2* y, const double2* x, long long count, hipStream_t st);

@@ -607,6 +607,7 @@ lsp_status lsp_options_default(lsp_options* o) {
   o->leaf = 0;
   o->panel = 0;
   o->dense_sweeps = 1;
+  o->blocked_sweeps = 1;
   return LSP_OK;
 }
 
@@ -622,6 +623,7 @@ lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts, 
     LSP_REQUIRE(o.precision == LSP_FP64 || o.precision == LSP_MIXED, "unknown precision");
     LSP_REQUIRE(o.panel == 0 || o.panel == kNbMax, "panel must be 0 (auto) or 32");
     LSP_REQUIRE(o.dense_sweeps == 0 || o.dense_sweeps == 1, "dense_sweeps must be 0 or 1");
+    LSP_REQUIRE(o.blocked_sweeps == 0 || o.blocked_sweeps == 1, "blocked_sweeps must be 0 or 1");
     std::unique_ptr<lsp_plan> pl(new lsp_plan());
     build_plan(pl->p, n, d, max_nrhs, o);
     fix_radices(pl->p);

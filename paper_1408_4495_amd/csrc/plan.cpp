@@ -237,6 +237,12 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
       ok = P.fronts[i].q + P.fronts[i].p - std::min(P.fronts[i].p, P.nb) <= 128;
     P.level_small_sweep[l] = ok;
   }
+  P.level_blocked.assign(P.nlevels, 0);
+  for (int l = 0; l < P.nlevels; ++l) {
+    const int cnt = P.level_ptr[l + 1] - P.level_ptr[l];
+    if (opts.blocked_sweeps == 0 || P.level_dense[l] || P.level_small_sweep[l]) continue;
+    P.level_blocked[l] = P.level_maxpq[l] > 1024 || (cnt <= 32 && P.level_maxp[l] > 2 * P.nb);
+  }
   P.front_elems = f_off;
   P.dinv_elems = dinv_off;
   P.sum_p = piv_off;

@@ -52,6 +52,10 @@ struct Plan {
   // Levels swept by the small-front kernels (not dense; at most two panels,
   // at most 160 rows, at most 128 rows below each front's first panel).
   std::vector<char> level_small_sweep;
+  // Levels swept by the blocked kernels (sweep.hip): not dense, not small,
+  // and either fronts of more than 1024 rows or at most 32 fronts with more
+  // than two panels.
+  std::vector<char> level_blocked;
   int nlevels = 0;
   long long front_elems = 0;      // sum (p+q)^2
   long long dinv_elems = 0;       // sum over panels of 2 nb^2

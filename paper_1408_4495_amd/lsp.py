@@ -28,7 +28,7 @@ EXPORTED = ["lsp_options_default", "lsp_plan_create", "lsp_plan_destroy", "lsp_p
 class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
                 ("precision", ctypes.c_int), ("buffer_b", ctypes.c_int), ("leaf", ctypes.c_int),
-                ("panel", ctypes.c_int), ("dense_sweeps", ctypes.c_int)]
+                ("panel", ctypes.c_int), ("dense_sweeps", ctypes.c_int), ("blocked_sweeps", ctypes.c_int)]
 
 
 class RhsInfo(ctypes.Structure):
@@ -148,13 +148,14 @@ class Plan:
     """Symbolic plan for an n^d grid (host-side nested dissection)."""
 
     def __init__(self, n, d, max_nrhs=1, tol=1e-8, restart=30, max_iters=1000, precision="fp64",
-                 buffer_b=2, leaf=0, panel=0, dense_sweeps=1):
+                 buffer_b=2, leaf=0, panel=0, dense_sweeps=1, blocked_sweeps=1):
         lib = load()
         o = Options()
         _check(lib.lsp_options_default(ctypes.byref(o)))
         o.tol, o.restart, o.max_iters = tol, restart, max_iters
         o.precision = LSP_MIXED if precision in ("mixed", LSP_MIXED) else LSP_FP64
         o.buffer_b, o.leaf, o.panel, o.dense_sweeps = buffer_b, leaf, panel, dense_sweeps
+        o.blocked_sweeps = blocked_sweeps
         self.opts = o
         self.n, self.d, self.max_nrhs = n, d, max_nrhs
         self.precision = o.precision

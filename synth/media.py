@@ -136,7 +136,18 @@ def _c4():
     return dict(name="3d_n64_6bumps_8rhs", n=n, d=d, omega=omega, m=m, uI=uI)
 
 
-WORKLOADS = {"c1": _c1, "c2": _c2, "c3": _c3, "c4": _c4}
+def _c4s():
+    """The 3D recipe of the n=64 workload (same draws: bumps, rotation) on a
+    32-point grid at 8 points per wavelength (omega = 8 pi)."""
+    n, d = 32, 3
+    omega = 2 * np.pi * 4
+    rng = np.random.default_rng([SEED_BASE, 3])
+    m = medium_bumps(n, d, rng, 6, 0.2, 0.8, 0.05, 0.12, 0.0, 0.3)
+    uI = plane_waves(n, d, omega, directions_fibonacci(8, rng))
+    return dict(name="3d_n32_6bumps_8rhs", n=n, d=d, omega=omega, m=m, uI=uI)
+
+
+WORKLOADS = {"c1": _c1, "c2": _c2, "c3": _c3, "c4": _c4, "c4s": _c4s}
 
 
 def workload(key):

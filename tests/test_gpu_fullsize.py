@@ -33,7 +33,7 @@ def _check(key, precs):
             assert info[r]["converged"] and info[r]["relres_true"] <= 1e-8
             g = op.rhs(uI[r])
             res = np.linalg.norm(g - op.apply(u[r])) / np.linalg.norm(g)
-            assert res <= 1.5e-8, (prec, r, res)
+            assert res <= 1e-8, (prec, r, res)
         sols[prec] = u
         del pb
         torch.cuda.empty_cache()
