@@ -223,6 +223,21 @@ lsp_status lsp_solve(lsp_problem* problem, int nrhs, int rhs_kind,
 lsp_status lsp_apply_op(lsp_problem* problem, int nrhs, int precision,
                         const void* x_dev, void* y_dev, void* ws_dev, size_t ws_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * operator y = x + K (w^2 m .* x) of lsp_apply_op, with the FFT work array
+ * in a static per-device scratch array of 32 MiB instead of a caller
+ * workspace.  Calls no allocator.  Requires nrhs (2n)^d elements of 16 bytes
+ * (LSP_FP64) or 8 bytes (LSP_MIXED) to fit in 32 MiB, else LSP_ERR_ARG with
+ * the sizes in the message (e.g. 2D n = 256: up to 8 right-hand sides in
+ * FP64).  Every call on a device shares that device's scratch and its
+ * contents persist between calls (nothing in it needs clearing: each call
+ * writes every element it reads before reading it); calls that overlap on
+ * one device, on different streams, race.  x_dev, y_dev: [nrhs][N]
+ * complex128.  Results equal lsp_apply_op's bit for bit. */
+lsp_status lsp_apply_op_noalloc(lsp_problem* problem, int nrhs, int precision,
+                                const void* x_dev, void* y_dev);
+
 /* y = K x  (the plain convolution; g = K(-w^2 m u_I) uses it). */
 lsp_status lsp_apply_K(lsp_problem* problem, int nrhs, int precision,
                        const void* x_dev, void* y_dev, void* ws_dev, size_t ws_bytes);

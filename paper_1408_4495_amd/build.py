@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblsp.so")
-SOURCES = ["plan.cpp", "lsp_api.cpp", "timing.cpp", "greens.hip", "fft.hip", "stencil.hip", "frontal.hip", "krylov.hip", "sweep.hip"]
+SOURCES = ["plan.cpp", "lsp_api.cpp", "timing.cpp", "greens.hip", "fft.hip", "stencil.hip", "frontal.hip", "krylov.hip", "sweep.hip", "static_scratch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

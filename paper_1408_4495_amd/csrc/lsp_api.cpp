@@ -20,6 +20,7 @@
 
 #include "lsp_common.h"
 #include "plan.h"
+#include "static_scratch.h"
 
 using namespace lsp;
 
@@ -802,6 +803,31 @@ lsp_status lsp_apply_K(lsp_problem* pb, int nrhs, int precision, const void* x, 
     SolvePtrs s;
     layout_solve(pb->plan->p, nrhs, pb->plan->p.opts.restart, false, (void*)align_up((size_t)ws, 256), &s);
     apply_conv(pb, s, nrhs, precision, (const double2*)x, (double2*)y, false, nullptr);
+    return LSP_OK;
+  });
+}
+
+lsp_status lsp_apply_op_noalloc(lsp_problem* pb, int nrhs, int precision, const void* x, void* y) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(pb && x && y, "null argument");
+    LSP_REQUIRE(precision == LSP_FP64 || precision == LSP_MIXED, "unknown precision");
+    LSP_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    const Plan& P = pb->plan->p;
+    long long Ld = 1;
+    for (int a = 0; a < P.d; ++a) Ld *= P.L;
+    const size_t esz = precision == LSP_MIXED ? sizeof(float2) : sizeof(double2);
+    const size_t need = (size_t)nrhs * (size_t)Ld * esz;
+    if (need > kStaticScratchBytes)
+      throw Error(LSP_ERR_ARG, "lsp_apply_op_noalloc: the FFT work array needs " + std::to_string(need) +
+                                   " bytes (nrhs (2n)^d elements), more than the " +
+                                   std::to_string(kStaticScratchBytes) + "-byte static scratch");
+    // the device's scratch address (looked up on the first call per device);
+    // the kernels overwrite every element of it they read, so nothing is cleared
+    void* W = static_scratch(pb->device);
+    if (precision == LSP_MIXED)
+      kmatvec<float>(pb->fp32, nrhs, (const double2*)x, (double2*)y, pb->d.w2m, true, (float2*)W, pb->st);
+    else
+      kmatvec<double>(pb->fp64, nrhs, (const double2*)x, (double2*)y, pb->d.w2m, true, (double2*)W, pb->st);
     return LSP_OK;
   });
 }

@@ -22,7 +22,7 @@ EXPORTED = ["lsp_options_default", "lsp_plan_create", "lsp_plan_destroy", "lsp_p
             "lsp_apply_op", "lsp_apply_K", "lsp_apply_Q", "lsp_solve_M", "lsp_apply_precond",
             "lsp_get_kernel_table", "lsp_get_stencils", "lsp_get_matrix", "lsp_status_string",
             "lsp_last_error", "lsp_timing_enable", "lsp_timing_reset", "lsp_timing_count",
-            "lsp_timing_get", "lsp_plan_get_tiles", "lsp_plan_set_tiles"]
+            "lsp_timing_get", "lsp_plan_get_tiles", "lsp_plan_set_tiles", "lsp_apply_op_noalloc"]
 
 
 class Options(ctypes.Structure):
@@ -75,6 +75,7 @@ def load():
         "lsp_solve": [vp, ci, ci, vp, vp, vp, sz, ctypes.POINTER(RhsInfo)],
         "lsp_apply_op": [vp, ci, ci, vp, vp, vp, sz],
         "lsp_apply_K": [vp, ci, ci, vp, vp, vp, sz],
+        "lsp_apply_op_noalloc": [vp, ci, ci, vp, vp],
         "lsp_apply_Q": [vp, ci, vp, vp],
         "lsp_solve_M": [vp, ci, vp, vp, vp, sz],
         "lsp_apply_precond": [vp, ci, vp, vp, vp, sz],
@@ -266,6 +267,13 @@ class Problem:
         y = self.torch.empty_like(x)
         ws = self._work(x.shape[0])
         _check(_lib.lsp_apply_op(self._h, x.shape[0], precision, _ptr(x), _ptr(y), _ptr(ws), ws.numel()))
+        return y
+
+    def apply_op_noalloc(self, x, precision=LSP_FP64):
+        """y = x + K(w^2 m x) with the library's static scratch (no workspace)."""
+        x = self._field(x)
+        y = self.torch.empty_like(x)
+        _check(_lib.lsp_apply_op_noalloc(self._h, x.shape[0], precision, _ptr(x), _ptr(y)))
         return y
 
     def apply_K(self, x, precision=LSP_FP64):
