@@ -87,8 +87,10 @@ typedef struct {
                         or with at most 32 fronts of more than two panels,
                         the sweeps run blocked: a panel chain per 256-row
                         super-block of the pivots and wide matrix-vector
-                        products for the rest of the front; 0: the panel
-                        chain of one workgroup per front */
+                        products for the rest of the front; 2: every
+                        level that is neither swept densely nor by the
+                        small-front kernels; 0: the panel chain of one
+                        workgroup per front */
 } lsp_options;
 
 typedef struct {
@@ -125,6 +127,12 @@ typedef struct {
                                  of m p over the dense levels' fronts; those
                                  levels' panels are not in sweep_entries) */
   int dense_levels;           /* tree levels swept with dense operators */
+  int blocked_levels;         /* tree levels swept blocked (blocked_sweeps) */
+  double blocked_entries;     /* entries of the formed 256 x 256 super-block
+                                 operators one forward (or backward) sweep
+                                 reads on the blocked levels (their panels
+                                 outside the super-blocks' diagonal blocks
+                                 are in sweep_entries) */
 } lsp_plan_stats;
 
 typedef struct lsp_plan lsp_plan;        /* opaque; host-side, plus one device copy of

@@ -1855,23 +1855,24 @@ void form_level(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st) {
 // Formation of dense level l once its factorisation is enqueued on st.
 template <typename T>
 void form_after(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st, const FormStream* fs) {
-  if (!plan.level_dense[l]) return;
+  if (!plan.level_dense[l] && !plan.level_blocked[l]) return;
   hipStream_t fst = st;
   if (fs) {
     LSP_HIP(hipEventRecord(fs->level, st));
     LSP_HIP(hipStreamWaitEvent(fs->aux, fs->level, 0));
     fst = fs->aux;
   }
-  if (wide_level(plan, l)) form_level<T, 512>(mf, plan, l, fst);
+  if (plan.level_blocked[l]) blocked_form<T>(mf, plan, l, fst);
+  else if (wide_level(plan, l)) form_level<T, 512>(mf, plan, l, fst);
   else form_level<T, 256>(mf, plan, l, fst);
 }
 
 template <typename T, int NR>
 void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
-                  hipStream_t st, hipEvent_t form_done, double2* xw) {
+                  const SweepBufs<T>& sb, hipStream_t st, hipEvent_t form_done, double2* xw) {
   const int groups = (nrhs + NR - 1) / NR;
   for (int l = 0; l < plan.nlevels; ++l) {
-    if (plan.level_dense[l] && form_done) {
+    if ((plan.level_dense[l] || plan.level_blocked[l]) && form_done) {
       LSP_HIP(hipStreamWaitEvent(st, form_done, 0));
       form_done = nullptr;
     }
@@ -1884,7 +1885,7 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
         continue;
       }
     }
-    if (plan.level_blocked[l]) blocked_sweep<T>(true, mf, plan, l, nrhs, z, x, vbuf, st, xw);
+    if (plan.level_blocked[l]) blocked_sweep<T>(true, mf, plan, l, nrhs, z, x, vbuf, sb, st, xw);
     else if (plan.level_dense[l]) dense_fwd<T, NR>(mf, plan, l, groups, nrhs, z, vbuf, st);
     else if (wide_level(plan, l)) sweep_fwd<T, NR, 512>(mf, plan, l, groups, nrhs, z, vbuf, st);
     else sweep_fwd<T, NR, 256>(mf, plan, l, groups, nrhs, z, vbuf, st);
@@ -1898,7 +1899,7 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
         continue;
       }
     }
-    if (plan.level_blocked[l]) blocked_sweep<T>(false, mf, plan, l, nrhs, z, x, vbuf, st, xw);
+    if (plan.level_blocked[l]) blocked_sweep<T>(false, mf, plan, l, nrhs, z, x, vbuf, sb, st, xw);
     else if (plan.level_dense[l]) dense_bwd<T, NR>(mf, plan, l, groups, nrhs, x, vbuf, st, xw);
     else if (wide_level(plan, l)) sweep_bwd<T, NR, 512>(mf, plan, l, groups, nrhs, x, vbuf, st, xw);
     else sweep_bwd<T, NR, 256>(mf, plan, l, groups, nrhs, x, vbuf, st, xw);
@@ -2070,18 +2071,18 @@ FactorSchedule factor_schedule(const Plan& plan, bool fp64) {
 
 template <typename T>
 void mf_solve(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
-              hipStream_t st, hipEvent_t form_done, double2* xw) {
-  if (nrhs >= 8) solve_levels<T, 8>(mf, plan, nrhs, z, x, vbuf, st, form_done, xw);
-  else if (nrhs >= 4) solve_levels<T, 4>(mf, plan, nrhs, z, x, vbuf, st, form_done, xw);
-  else if (nrhs >= 2) solve_levels<T, 2>(mf, plan, nrhs, z, x, vbuf, st, form_done, xw);
-  else solve_levels<T, 1>(mf, plan, nrhs, z, x, vbuf, st, form_done, xw);
+              const SweepBufs<T>& sb, hipStream_t st, hipEvent_t form_done, double2* xw) {
+  if (nrhs >= 8) solve_levels<T, 8>(mf, plan, nrhs, z, x, vbuf, sb, st, form_done, xw);
+  else if (nrhs >= 4) solve_levels<T, 4>(mf, plan, nrhs, z, x, vbuf, sb, st, form_done, xw);
+  else if (nrhs >= 2) solve_levels<T, 2>(mf, plan, nrhs, z, x, vbuf, sb, st, form_done, xw);
+  else solve_levels<T, 1>(mf, plan, nrhs, z, x, vbuf, sb, st, form_done, xw);
 }
 
 template void mf_factor<double>(const MfDev<double>&, const Plan&, hipStream_t, const FormStream*);
 template void mf_factor<float>(const MfDev<float>&, const Plan&, hipStream_t, const FormStream*);
-template void mf_solve<double>(const MfDev<double>&, const Plan&, int, const double2*, double2*, double2*, hipStream_t,
-                               hipEvent_t, double2*);
-template void mf_solve<float>(const MfDev<float>&, const Plan&, int, const float2*, float2*, float2*, hipStream_t,
-                              hipEvent_t, double2*);
+template void mf_solve<double>(const MfDev<double>&, const Plan&, int, const double2*, double2*, double2*,
+                               const SweepBufs<double>&, hipStream_t, hipEvent_t, double2*);
+template void mf_solve<float>(const MfDev<float>&, const Plan&, int, const float2*, float2*, float2*,
+                              const SweepBufs<float>&, hipStream_t, hipEvent_t, double2*);
 
 }  // namespace lsp

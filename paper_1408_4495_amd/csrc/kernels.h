@@ -7,7 +7,8 @@
 namespace lsp {
 
 constexpr int kNbMax = 32;  // widest frontal panel
-constexpr int kSweepBlock = 256;  // rows of a super-block of the blocked sweeps
+constexpr int kSweepBlock = kSweepRows;  // rows of a super-block of the blocked sweeps
+constexpr int kSweepChunk = kSweepCols;  // boundary columns per partial sum of the blocked backward sweep
 
 // ---- Green's table
 void launch_ktable(double2* k, int n, int d, double omega, double2 k0, hipStream_t st);
@@ -68,7 +69,18 @@ struct MfDev {
   const double2* Mval;      // [N][3^d]
   int* perm;                // per panel row: the front row it came from
   double* pivstat;          // per diagonal block: smallest / largest pivot magnitude
-  cplx<T>* G;               // formed sweep operators of the dense levels (FrontDev::g_off)
+  cplx<T>* G;               // formed sweep operators of the dense and blocked levels (FrontDev::g_off)
+};
+
+// Work buffers of the blocked sweeps (in the solve workspace): ybuf holds a
+// super-block's output per front, [nrhs][ystride]; pbuf the boundary
+// columns' partial sums, [chunks][nrhs][ystride] (Plan::bsweep_ystride,
+// Plan::bsweep_chunks).
+template <typename T>
+struct SweepBufs {
+  cplx<T>* ybuf;
+  cplx<T>* pbuf;
+  long long ystride;
 };
 
 // Second stream for the dense levels' operator formation: each level's
@@ -101,16 +113,20 @@ FactorSchedule factor_schedule(const Plan& plan, bool fp64);
 // null): the solution also written there in complex128.
 template <typename T>
 void mf_solve(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
-              hipStream_t st, hipEvent_t form_done, double2* xw);
+              const SweepBufs<T>& sb, hipStream_t st, hipEvent_t form_done, double2* xw);
 
 // Blocked forward (fwd) or backward sweep of level l (Plan::level_blocked):
-// a gather, then per 256-row super-block of the pivots a one-workgroup panel
-// chain and a wide matrix-vector product over the rest of the front; the
-// backward sweep starts with the product of the boundary columns.  Same
-// inputs and outputs as the panel-chain sweeps of that level.
+// per 256-row super-block of the pivots its formed operator and a wide
+// matrix-vector product over the rest of the front; the backward sweep
+// starts with the boundary columns' product.  Same inputs and outputs as the
+// panel-chain sweeps of that level.
 template <typename T>
 void blocked_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
-                   cplx<T>* vbuf, hipStream_t st, double2* xw);
+                   cplx<T>* vbuf, const SweepBufs<T>& sb, hipStream_t st, double2* xw);
+// Forms the super-block operators of blocked level l from its factor (the
+// panel chains on the unit vectors), into mf.G at each front's g_off.
+template <typename T>
+void blocked_form(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st);
 
 // ---- Krylov helpers (complex128 vectors, [nrhs][N] blocks)
 void launch_narrow(float2* y, const double2* x, long long count, hipStream_t st);

@@ -202,6 +202,8 @@ struct SolvePtrs {
   void* vbuf;     // front vectors [nrhs][sum(p+q)]
   void* zq;       // Q-apply output [nrhs][N]
   void* xs;       // M^{-1} output [nrhs][N]
+  void* ybuf;     // blocked sweeps: super-block outputs [nrhs][bsweep_ystride]
+  void* pbuf;     // blocked sweeps: boundary partial sums [chunks][nrhs][bsweep_ystride]
   double2* V;     // [restart+1][nrhs][N]
   double2* Z;     // [restart][nrhs][N]
   double2* w;     // [nrhs][N]
@@ -233,6 +235,8 @@ size_t layout_solve(const Plan& P, int nrhs, int restart, bool krylov, void* bas
   s.vbuf = cv.take<double2>((size_t)nrhs * P.sum_pq);
   s.zq = cv.take<double2>((size_t)nrhs * N);
   s.xs = cv.take<double2>((size_t)nrhs * N);
+  s.ybuf = cv.take<double2>((size_t)nrhs * P.bsweep_ystride);
+  s.pbuf = cv.take<double2>((size_t)P.bsweep_chunks * nrhs * P.bsweep_ystride);
   if (krylov) {
     s.V = cv.take<double2>((size_t)(restart + 1) * nrhs * N);
     s.Z = cv.take<double2>((size_t)restart * nrhs * N);
@@ -533,13 +537,15 @@ void apply_precond(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2*
     launch_applyQ<double2>((double2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
     MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                      pb->d.pivstat, (double2*)pb->d.Gop};
-    mf_solve<double>(mf, P, nrhs, (const double2*)s.zq, out, (double2*)s.vbuf, st, pb->take_form_wait(), nullptr);
+    const SweepBufs<double> sb{(double2*)s.ybuf, (double2*)s.pbuf, P.bsweep_ystride};
+    mf_solve<double>(mf, P, nrhs, (const double2*)s.zq, out, (double2*)s.vbuf, sb, st, pb->take_form_wait(), nullptr);
   } else {
     launch_applyQ<float2>((float2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
     MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                     pb->d.pivstat, (float2*)pb->d.Gop};
     // the backward sweeps also store the solution widened into out
-    mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st, pb->take_form_wait(), out);
+    const SweepBufs<float> sb{(float2*)s.ybuf, (float2*)s.pbuf, P.bsweep_ystride};
+    mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, sb, st, pb->take_form_wait(), out);
   }
 }
 
@@ -549,12 +555,14 @@ void solve_M(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2* z, do
   if (pb->precision == LSP_FP64) {
     MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                      pb->d.pivstat, (double2*)pb->d.Gop};
-    mf_solve<double>(mf, P, nrhs, z, x, (double2*)s.vbuf, st, pb->take_form_wait(), nullptr);
+    const SweepBufs<double> sb{(double2*)s.ybuf, (double2*)s.pbuf, P.bsweep_ystride};
+    mf_solve<double>(mf, P, nrhs, z, x, (double2*)s.vbuf, sb, st, pb->take_form_wait(), nullptr);
   } else {
     launch_narrow((float2*)s.zq, z, (long long)nrhs * P.N, st);
     MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                     pb->d.pivstat, (float2*)pb->d.Gop};
-    mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, st, pb->take_form_wait(), x);
+    const SweepBufs<float> sb{(float2*)s.ybuf, (float2*)s.pbuf, P.bsweep_ystride};
+    mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, sb, st, pb->take_form_wait(), x);
   }
 }
 
@@ -624,7 +632,7 @@ lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts, 
     LSP_REQUIRE(o.precision == LSP_FP64 || o.precision == LSP_MIXED, "unknown precision");
     LSP_REQUIRE(o.panel == 0 || o.panel == kNbMax, "panel must be 0 (auto) or 32");
     LSP_REQUIRE(o.dense_sweeps == 0 || o.dense_sweeps == 1, "dense_sweeps must be 0 or 1");
-    LSP_REQUIRE(o.blocked_sweeps == 0 || o.blocked_sweeps == 1, "blocked_sweeps must be 0 or 1");
+    LSP_REQUIRE(o.blocked_sweeps >= 0 && o.blocked_sweeps <= 2, "blocked_sweeps must be 0, 1 or 2");
     std::unique_ptr<lsp_plan> pl(new lsp_plan());
     build_plan(pl->p, n, d, max_nrhs, o);
     fix_radices(pl->p);
@@ -655,6 +663,8 @@ lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* s) {
   s->fused_update_flops = fs.fused_update_flops;
   s->dense_entries = P.dense_entries;
   s->dense_levels = P.dense_levels;
+  s->blocked_levels = P.blocked_levels;
+  s->blocked_entries = P.blocked_entries;
   return LSP_OK;
 }
 
@@ -742,7 +752,7 @@ lsp_status lsp_factor(lsp_problem* pb) {
   return guarded([&]() -> lsp_status {
     LSP_REQUIRE(pb != nullptr, "null problem");
     const Plan& P = pb->plan->p;
-    if (P.dense_levels > 0 && !pb->fs.aux) {
+    if (P.dense_levels + P.blocked_levels > 0 && !pb->fs.aux) {
       int cur = 0;
       LSP_HIP(hipGetDevice(&cur));
       if (cur != pb->device) LSP_HIP(hipSetDevice(pb->device));

@@ -241,7 +241,33 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
   for (int l = 0; l < P.nlevels; ++l) {
     const int cnt = P.level_ptr[l + 1] - P.level_ptr[l];
     if (opts.blocked_sweeps == 0 || P.level_dense[l] || P.level_small_sweep[l]) continue;
-    P.level_blocked[l] = P.level_maxpq[l] > 1024 || (cnt <= 32 && P.level_maxp[l] > 2 * P.nb);
+    P.level_blocked[l] = opts.blocked_sweeps == 2 || P.level_maxpq[l] > 1024 ||
+                         (cnt <= 32 && P.level_maxp[l] > 2 * P.nb);
+  }
+  // storage of the blocked levels' super-block operators (forward then
+  // backward, SB x SB each), after the dense levels' operators
+  {
+    const long long SB = kSweepRows;
+    P.blocked_levels = 0;
+    P.blocked_entries = 0.0;
+    P.bsweep_ystride = 0;
+    P.bsweep_chunks = 0;
+    for (int l = 0; l < P.nlevels; ++l) {
+      if (!P.level_blocked[l]) continue;
+      ++P.blocked_levels;
+      const long long cnt = P.level_ptr[l + 1] - P.level_ptr[l];
+      int maxq = 0;
+      for (int i = P.level_ptr[l]; i < P.level_ptr[l + 1]; ++i) {
+        FrontDev& f = P.fronts[i];
+        const long long nsb = (f.p + SB - 1) / SB;
+        f.g_off = P.dense_elems;
+        P.dense_elems += 2 * nsb * SB * SB;
+        P.blocked_entries += (double)(nsb * SB * SB);
+        maxq = std::max(maxq, f.q);
+      }
+      P.bsweep_ystride = std::max(P.bsweep_ystride, cnt * std::max<long long>(SB, P.level_maxp[l]));
+      P.bsweep_chunks = std::max(P.bsweep_chunks, (maxq + kSweepCols - 1) / kSweepCols);
+    }
   }
   P.front_elems = f_off;
   P.dinv_elems = dinv_off;

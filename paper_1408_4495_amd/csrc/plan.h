@@ -8,6 +8,11 @@
 
 namespace lsp {
 
+// Blocked sweeps: rows of a super-block of pivots, and boundary columns per
+// partial sum of the backward sweep's boundary product.
+constexpr int kSweepRows = 256;
+constexpr int kSweepCols = 512;
+
 // One front (supernode) of the multifrontal factorisation.  Its index list
 // is [I | B]: I = the variables it eliminates (a separator plane, or a whole
 // leaf box), B = the halo of its box that lies on ancestor separators.
@@ -26,7 +31,8 @@ struct FrontDev {
   long long cfoff[2];
   int cm[2];
   long long g_off;        // offset of its formed sweep operators (dense
-                          // levels, see Plan::level_dense), -1 elsewhere
+                          // levels, see Plan::level_dense; blocked levels,
+                          // see Plan::level_blocked), -1 elsewhere
 };
 
 struct Plan {
@@ -56,6 +62,12 @@ struct Plan {
   // and either fronts of more than 1024 rows or at most 32 fronts with more
   // than two panels.
   std::vector<char> level_blocked;
+  int blocked_levels = 0;
+  double blocked_entries = 0.0;   // formed super-block operator entries one
+                                  // sweep reads (sum over fronts of nsb SB^2)
+  long long bsweep_ystride = 0;   // per right-hand side: max over blocked
+                                  // levels of fronts x max(SB, largest p)
+  int bsweep_chunks = 0;          // max over blocked levels of boundary column chunks
   int nlevels = 0;
   long long front_elems = 0;      // sum (p+q)^2
   long long dinv_elems = 0;       // sum over panels of 2 nb^2

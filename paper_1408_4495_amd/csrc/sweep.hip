@@ -4,28 +4,36 @@
 // factors of Section 2.2's nested dissection) walks every front twice.  The
 // panel-chain kernels give each front one workgroup, which on the upper
 // levels (a handful of fronts with thousands of rows) leaves the chip idle
-// and streams megabytes of factor through one compute unit.  Here a front's
-// sweep is split into a short sequential part and wide parallel parts:
+// and streams megabytes of factor through one compute unit.  Here the
+// pivots of a front are grouped in super-blocks of SB = 256 rows (8 panels
+// of 32), and the sweep becomes a short sequence of wide matrix-vector
+// products:
 //
-// forward, front rows [I | B], p pivots, panels of 32 grouped in super-blocks
-// of SB = 256 rows:
-//   gather   v = [z(I); 0] + children's updates             (one launch)
-//   for each super-block s = [s0, s1):
-//     chain  the panels of s on their own rows:              (one workgroup
-//            y_b = L11_b^{-1} (P_b v_b),                      per front and
-//            v(k1:s1) -= L(k1:s1, b) y_b                      right-hand-side
-//                                                             group)
-//     gemv   v(s1:m) -= L(s1:m, s0:s1) y_s                   (64-row tiles)
-// backward:
-//   gemv     t_I = y_I - U(0:p, p:m) x_B, x_B read from the solution
-//   for each super-block s from the last:
-//     chain  x_b = U11_b^{-1} (t_b - U(b, k1:s1) x(k1:s1))
-//     gemv   t(0:s0) -= U(0:s0, s0:s1) x_s
+//   forward (front rows [I | B], p pivots):
+//     gather  v = [z(I); 0] + children's updates
+//     for each super-block s = [s0, s1):
+//       y_s = W_s v(s0:s1)                       (formed operator, SB x SB)
+//       v(s1:m) -= L(s1:m, s0:s1) y_s,  v(s0:s1) = y_s
+//   backward:
+//     t_I = y_I - U(0:p, p:m) x_B                 (x_B from the solution;
+//                                                  columns split in chunks
+//                                                  of KC, partial sums added
+//                                                  in chunk order)
+//     for each super-block s from the last:
+//       x_s = V_s t(s0:s1)                        (formed operator)
+//       t(0:s0) -= U(0:s0, s0:s1) x_s
 //
-// The arithmetic is the panel chain's, regrouped: every factor entry is read
-// once per right-hand-side group and each right-hand side's sums run in an
-// order that does not depend on the group, so a right-hand side solved in a
-// batch gets its solo result bit for bit.
+// W_s and V_s are the panel chains of the super-block (forward: per panel
+// y_b = L11_b^{-1} P_b v_b, then the rows below inside the super-block
+// updated; backward: x_b = U11_b^{-1} (t_b - U(b, k1:s1) x(k1:s1))) run on
+// the unit vectors, once per factorisation, on the formation stream beside
+// the upper levels' factorisation.  They are stored SB x SB column-major at
+// the front's g_off: the forward operators of its super-blocks, then the
+// backward ones.
+//
+// Every right-hand side's sums run in an order that does not depend on the
+// group it is solved in, so a batched right-hand side gets its solo result
+// bit for bit.
 #include <algorithm>
 
 #include "lsp_common.h"
@@ -35,10 +43,12 @@ namespace lsp {
 
 namespace {
 
-constexpr int PB = kNbMax;   // panel width
+constexpr int PB = kNbMax;       // panel width
 constexpr int SB = kSweepBlock;  // super-block rows (8 panels)
-constexpr int GR = 64;       // gemv rows per workgroup (one per lane of a wave)
-constexpr int GU = 16;       // gemv column loads in flight per lane
+constexpr int KC = kSweepChunk;  // boundary columns per partial sum
+constexpr int GR = 64;           // gemv rows per workgroup (one per lane of a wave)
+constexpr int GU = 16;           // gemv column loads in flight per lane
+constexpr int NF = 8;            // unit vectors per formation workgroup
 
 // out[k] = sum_j D(i, j) in(k, j) for k < NR, i = tid / 8: eight threads per
 // row, each summing every eighth j in two interleaved partial sums, combined
@@ -91,38 +101,41 @@ __global__ void __launch_bounds__(256) bsweep_gather_kernel(const FrontDev* __re
   vbuf[rb + f.idx_off + r] = s;
 }
 
-// Forward chain over the panels of super-block [s0, s1) of each front
-// (blockIdx.x), right-hand sides r0 .. r0 + NR (blockIdx.y), the rows of the
-// super-block staged in LDS.
-template <typename T, int NR>
-__global__ void __launch_bounds__(256) bsweep_fwd_chain_kernel(const cplx<T>* __restrict__ Fbuf,
-                                                               const cplx<T>* __restrict__ Dinv,
-                                                               const FrontDev* __restrict__ fr,
-                                                               const int* __restrict__ perm, cplx<T>* __restrict__ vbuf,
-                                                               int first, int s0, int nrhs, long long vstride) {
-  __shared__ cplx<T> v[NR][SB];
+// ---- formation of the super-block operators
+
+// Forward operator W_s of super-block s = blockIdx.x % nsb of front
+// blockIdx.x / nsb: the forward panel chain of the super-block run on the
+// unit vectors e_j, j = NF blockIdx.y .. + NF, written as columns j of W_s.
+template <typename T>
+__global__ void __launch_bounds__(256) bsweep_form_fwd_kernel(const cplx<T>* __restrict__ Fbuf,
+                                                              const cplx<T>* __restrict__ Dinv,
+                                                              const FrontDev* __restrict__ fr,
+                                                              const int* __restrict__ perm, cplx<T>* __restrict__ Gop,
+                                                              int first, int nsbmax) {
+  __shared__ cplx<T> v[NF][SB];
   __shared__ cplx<T> Li[PB][PB + 1];
-  __shared__ cplx<T> tb[NR][PB];
-  __shared__ cplx<T> yb[NR][PB];
-  const FrontDev f = fr[first + blockIdx.x];
+  __shared__ cplx<T> tb[NF][PB];
+  __shared__ cplx<T> yb[NF][PB];
+  const FrontDev f = fr[first + blockIdx.x / nsbmax];
+  const int s = blockIdx.x % nsbmax, s0 = s * SB;
   if (f.p <= s0) return;
   const int s1 = min(s0 + SB, f.p), len = s1 - s0;
+  const int j0 = blockIdx.y * NF;
+  if (j0 >= len) return;
+  const int nr = min(NF, len - j0);
   const int m = f.p + f.q;
-  const int r0 = blockIdx.y * NR, nr = min(NR, nrhs - r0);
   const cplx<T>* F = Fbuf + f.f_off;
   const int* pm = perm + f.piv_off;
-  cplx<T>* vg = vbuf + (long long)r0 * vstride + f.idx_off;
   const int tid = threadIdx.x;
-  for (int e = tid; e < NR * SB; e += 256) {
+  for (int e = tid; e < NF * SB; e += 256) {
     const int k = e / SB, r = e % SB;
-    if (k < nr && r < len) v[k][r] = vg[(long long)k * vstride + s0 + r];
+    v[k][r] = mk<T>(r == j0 + k ? 1 : 0, 0);
   }
   for (int k0 = s0; k0 < s1; k0 += PB) {
     const int kb = min(PB, f.p - k0), k1 = k0 + kb;
     const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(k0 / PB) * 2 * PB * PB;
     const cplx<T> l0 = Lg[tid], l1 = Lg[tid + 256], l2 = Lg[tid + 512], l3 = Lg[tid + 768];
-    // the rows below this panel inside the super-block: one row per thread
-    const int r = k1 + tid;
+    const int r = k1 + tid;  // rows below this panel inside the super-block, one per thread
     const int rr = min(r, s1 - 1);
     cplx<T> lrow[PB];
 #pragma unroll
@@ -132,28 +145,27 @@ __global__ void __launch_bounds__(256) bsweep_fwd_chain_kernel(const cplx<T>* __
     Li[tid % PB][tid / PB + 8] = l1;
     Li[tid % PB][tid / PB + 16] = l2;
     Li[tid % PB][tid / PB + 24] = l3;
-    if (tid < NR * PB) {
-      const int k = tid / PB, j = tid % PB;
-      tb[k][j] = (k < nr && j < kb) ? v[k][pm[k0 + j] - s0] : mk<T>(0, 0);
+    {
+      const int k = tid / PB, j = tid % PB;  // NF * PB == 256
+      tb[k][j] = j < kb ? v[k][pm[k0 + j] - s0] : mk<T>(0, 0);
     }
     __syncthreads();
     {
-      cplx<T> y[NR];
-      tri_apply<T, NR>(Li, tb, tid, y);
+      cplx<T> y[NF];
+      tri_apply<T, NF>(Li, tb, tid, y);
       const int i = tid / 8;
       if (tid % 8 == 0) {
 #pragma unroll
-        for (int k = 0; k < NR; ++k) {
+        for (int k = 0; k < NF; ++k) {
           yb[k][i] = y[k];
-          if (k < nr && i < kb) v[k][k0 - s0 + i] = y[k];
+          if (i < kb) v[k][k0 - s0 + i] = y[k];
         }
       }
     }
     __syncthreads();
     if (r < s1) {
 #pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        if (k >= nr) break;
+      for (int k = 0; k < NF; ++k) {
         cplx<T> acc = v[k][r - s0];
 #pragma unroll
         for (int j = 0; j < PB; ++j)
@@ -163,49 +175,46 @@ __global__ void __launch_bounds__(256) bsweep_fwd_chain_kernel(const cplx<T>* __
     }
   }
   __syncthreads();
-  for (int e = tid; e < NR * SB; e += 256) {
+  cplx<T>* W = Gop + f.g_off + (long long)s * SB * SB;
+  for (int e = tid; e < NF * SB; e += 256) {
     const int k = e / SB, r = e % SB;
-    if (k < nr && r < len) vg[(long long)k * vstride + s0 + r] = v[k][r];
+    if (k < nr && r < len) W[(long long)(j0 + k) * SB + r] = v[k][r];
   }
 }
 
-// Backward chain over the panels of super-block [s0, s1), from the last:
-// x_b = U11_b^{-1} (t_b - U(b, k1:s1) x(k1:s1)); x goes to the front vector,
-// to the solution at the pivots' grid points and, when xw is given, widened
-// to complex128 there too.
-template <typename T, int NR>
-__global__ void __launch_bounds__(256) bsweep_bwd_chain_kernel(const cplx<T>* __restrict__ Fbuf,
-                                                               const cplx<T>* __restrict__ Dinv,
-                                                               const FrontDev* __restrict__ fr,
-                                                               const int* __restrict__ idx, cplx<T>* __restrict__ x,
-                                                               cplx<T>* __restrict__ vbuf, int first, int s0, int nrhs,
-                                                               long long N, long long vstride,
-                                                               double2* __restrict__ xw) {
+// Backward operator V_s: the backward panel chain of the super-block on the
+// unit vectors, columns j of V_s, stored after the front's forward ones.
+template <typename T>
+__global__ void __launch_bounds__(256) bsweep_form_bwd_kernel(const cplx<T>* __restrict__ Fbuf,
+                                                              const cplx<T>* __restrict__ Dinv,
+                                                              const FrontDev* __restrict__ fr, cplx<T>* __restrict__ Gop,
+                                                              int first, int nsbmax) {
   constexpr int G = 256 / PB;  // column groups
-  __shared__ cplx<T> v[NR][SB];
+  __shared__ cplx<T> v[NF][SB];
   __shared__ cplx<T> Ui[PB][PB + 1];
-  __shared__ cplx<T> part[G][NR][PB];
-  __shared__ cplx<T> rb[NR][PB];
-  const FrontDev f = fr[first + blockIdx.x];
+  __shared__ cplx<T> part[G][NF][PB];
+  __shared__ cplx<T> rb[NF][PB];
+  const FrontDev f = fr[first + blockIdx.x / nsbmax];
+  const int s = blockIdx.x % nsbmax, s0 = s * SB;
   if (f.p <= s0) return;
   const int s1 = min(s0 + SB, f.p), len = s1 - s0;
+  const int j0 = blockIdx.y * NF;
+  if (j0 >= len) return;
+  const int nr = min(NF, len - j0);
   const int m = f.p + f.q;
-  const int r0 = blockIdx.y * NR, nr = min(NR, nrhs - r0);
   const cplx<T>* F = Fbuf + f.f_off;
-  const int* id = idx + f.idx_off;
-  cplx<T>* vg = vbuf + (long long)r0 * vstride + f.idx_off;
   const int tid = threadIdx.x;
   const int j = tid % PB, grp = tid / PB;
-  for (int e = tid; e < NR * SB; e += 256) {
+  for (int e = tid; e < NF * SB; e += 256) {
     const int k = e / SB, r = e % SB;
-    if (k < nr && r < len) v[k][r] = vg[(long long)k * vstride + s0 + r];
+    v[k][r] = mk<T>(r == j0 + k ? 1 : 0, 0);
   }
   const int nb = (len + PB - 1) / PB;
   for (int b = nb - 1; b >= 0; --b) {
     const int k0 = s0 + b * PB, kb = min(PB, f.p - k0), k1 = k0 + kb;
     const cplx<T>* Ug = Dinv + f.dinv_off + (long long)(k0 / PB) * 2 * PB * PB + PB * PB;
     const cplx<T> u0 = Ug[tid], u1 = Ug[tid + 256], u2 = Ug[tid + 512], u3 = Ug[tid + 768];
-    // U(k0 + j, c) for this thread's columns c = k1 + grp + 8 t < s1 (at most 28)
+    // U(k0 + j, c) for this thread's columns c = k1 + grp + 8 t < s1
     constexpr int TU = SB / G;
     cplx<T> ucol[TU];
 #pragma unroll
@@ -218,86 +227,128 @@ __global__ void __launch_bounds__(256) bsweep_bwd_chain_kernel(const cplx<T>* __
     Ui[tid % PB][tid / PB + 8] = u1;
     Ui[tid % PB][tid / PB + 16] = u2;
     Ui[tid % PB][tid / PB + 24] = u3;
-    cplx<T> acc[NR];
+    cplx<T> acc[NF];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
+    for (int k = 0; k < NF; ++k) acc[k] = mk<T>(0, 0);
 #pragma unroll
     for (int t = 0; t < TU; ++t) {
       const int c = k1 + grp + G * t;
       if (c < s1)
 #pragma unroll
-        for (int k = 0; k < NR; ++k) acc[k] = cfma(acc[k], ucol[t], v[min(k, nr - 1)][c - s0]);
+        for (int k = 0; k < NF; ++k) acc[k] = cfma(acc[k], ucol[t], v[k][c - s0]);
     }
 #pragma unroll
-    for (int k = 0; k < NR; ++k) part[grp][k][j] = acc[k];
+    for (int k = 0; k < NF; ++k) part[grp][k][j] = acc[k];
     __syncthreads();
-    for (int e = tid; e < NR * PB; e += 256) {
-      const int jj = e % PB, k = e / PB;
-      cplx<T> s = part[0][k][jj];
+    {
+      const int jj = tid % PB, k = tid / PB;  // NF * PB == 256
+      cplx<T> sm = part[0][k][jj];
 #pragma unroll
-      for (int g = 1; g < G; ++g) s = cadd(s, part[g][k][jj]);
-      rb[k][jj] = (k < nr && jj < kb) ? csub(v[k][k0 - s0 + jj], s) : mk<T>(0, 0);
+      for (int g = 1; g < G; ++g) sm = cadd(sm, part[g][k][jj]);
+      rb[k][jj] = jj < kb ? csub(v[k][k0 - s0 + jj], sm) : mk<T>(0, 0);
     }
     __syncthreads();
     {
-      cplx<T> xs[NR];
-      tri_apply<T, NR>(Ui, rb, tid, xs);
+      cplx<T> xs[NF];
+      tri_apply<T, NF>(Ui, rb, tid, xs);
       const int i = tid / 8;
       if (tid % 8 == 0 && i < kb) {
-        const long long gi = id[k0 + i];
 #pragma unroll
-        for (int k = 0; k < NR; ++k) {
-          if (k < nr) {
-            v[k][k0 - s0 + i] = xs[k];
-            x[(long long)(r0 + k) * N + gi] = xs[k];
-            if (xw) xw[(long long)(r0 + k) * N + gi] = widen(xs[k]);
-          }
-        }
+        for (int k = 0; k < NF; ++k) v[k][k0 - s0 + i] = xs[k];
       }
     }
   }
   __syncthreads();
-  for (int e = tid; e < NR * SB; e += 256) {
+  const int nsb = (f.p + SB - 1) / SB;
+  cplx<T>* V = Gop + f.g_off + (long long)(nsb + s) * SB * SB;
+  for (int e = tid; e < NF * SB; e += 256) {
     const int k = e / SB, r = e % SB;
-    if (k < nr && r < len) vg[(long long)k * vstride + s0 + r] = v[k][r];
+    if (k < nr && r < len) V[(long long)(j0 + k) * SB + r] = v[k][r];
   }
 }
 
-// out(r) -= sum_c F(r, c) in(c) over a rectangle of each front's matrix
-// (column-major, leading dimension m), for the right-hand sides r0 .. r0+NR:
-//   MODE 0 (forward step):  rows [s1, m), columns [s0, s1), in = y in the
-//                           front vector;
-//   MODE 2 (backward B):    rows [0, p),  columns [p, m),  in = x_B read
-//                           from the solution at the front's grid points;
-//   MODE 3 (backward step): rows [0, s0), columns [s0, s1), in = x in the
-//                           front vector;
-// with s1 = min(s0 + SB, p).  Workgroup (64-row tile, front, group): lane l
-// of wave w owns row row0 + l and sums the columns w, w + 4, ... of each
-// staged chunk of GC columns; the four waves' sums are added in wave order.
+// ---- the sweeps' matrix-vector products
+//
+// acc(r) = sum_c A(r, c) in(c) over a rectangle of rows [rlo, rhi) and
+// columns [clo, chi) of each front (blockIdx.y), right-hand sides r0 ..
+// r0 + NR (blockIdx.z), 64-row tiles (blockIdx.x): lane l of wave w owns row
+// row0 + l and sums the columns w, w + 4, ... of each staged chunk of GC
+// columns; the four waves' sums are added in wave order.
+//   MODE_W   forward operator:  rows/columns [s0, s1), A = W_s, in = v (front
+//            vector), out: y_s -> ybuf
+//   MODE_V   backward operator: rows/columns [s0, s1), A = V_s, in = t, out:
+//            x_s -> ybuf, the solution at the pivots' grid points (and xw)
+//   MODE_FS  forward step:  rows [s1, m), columns [s0, s1), A = L, in = y_s
+//            from ybuf, out: v -= acc; tile 0 also copies y_s into v(s0:s1)
+//   MODE_BS  backward step: rows [0, s0), columns [s0, s1), A = U, in = x_s
+//            from ybuf, out: t -= acc
+//   MODE_BB  backward boundary: rows [0, p), columns [p + KC kc, ...) for
+//            the chunk kc = blockIdx.x % kch, A = U, in = x_B from the
+//            solution, out: the chunk's partial sums -> pbuf
+enum { MODE_W = 0, MODE_V = 1, MODE_FS = 2, MODE_BS = 3, MODE_BB = 4 };
+
+struct GemvArgs {
+  int first;         // first front of the level
+  int s;             // super-block (MODE_W/V/FS/BS)
+  int kch;           // column chunks of MODE_BB
+  int maxp;          // the level's largest p (pbuf row stride per front)
+  int nrhs;
+  long long N, vstride;
+  long long ystride;  // ybuf / pbuf elements per right-hand side
+};
+
 template <typename T, int NR, int MODE>
 __global__ void __launch_bounds__(256) bsweep_gemv_kernel(const cplx<T>* __restrict__ Fbuf,
+                                                          const cplx<T>* __restrict__ Gop,
                                                           const FrontDev* __restrict__ fr, const int* __restrict__ idx,
-                                                          const cplx<T>* __restrict__ x, cplx<T>* __restrict__ vbuf,
-                                                          int first, int s0, int nrhs, long long N,
-                                                          long long vstride) {
+                                                          cplx<T>* __restrict__ x, cplx<T>* __restrict__ vbuf,
+                                                          cplx<T>* __restrict__ ybuf, cplx<T>* __restrict__ pbuf,
+                                                          double2* __restrict__ xw, GemvArgs a) {
   constexpr int GC = NR >= 16 ? 128 : 256;  // columns staged per chunk
   __shared__ cplx<T> xin[NR][GC];
   __shared__ cplx<T> part[4][NR][GR];
-  const FrontDev f = fr[first + blockIdx.y];
+  const int fi = blockIdx.y;
+  const FrontDev f = fr[a.first + fi];
   const int p = f.p, m = p + f.q;
-  const int s1 = min(s0 + SB, p);
+  const int nsb = (p + SB - 1) / SB;
+  const int s0 = a.s * SB, s1 = min(s0 + SB, p);
+  int tile = blockIdx.x, kc = 0;
+  if constexpr (MODE == MODE_BB) { kc = tile % a.kch; tile /= a.kch; }
   int rlo, rhi, clo, chi;
-  if constexpr (MODE == 0) { rlo = s1; rhi = m; clo = s0; chi = s1; }
-  else if constexpr (MODE == 2) { rlo = 0; rhi = p; clo = p; chi = m; }
-  else { rlo = 0; rhi = min(s0, p); clo = s0; chi = s1; }
-  const int row0 = rlo + blockIdx.x * GR;
-  if (row0 >= rhi || clo >= chi) return;
-  const int r0 = blockIdx.z * NR, nr = min(NR, nrhs - r0);
+  if constexpr (MODE == MODE_W || MODE == MODE_V) { rlo = s0; rhi = s1; clo = s0; chi = s1; }
+  else if constexpr (MODE == MODE_FS) { rlo = s1; rhi = m; clo = s0; chi = s1; }
+  else if constexpr (MODE == MODE_BS) { rlo = 0; rhi = min(s0, p); clo = s0; chi = s1; }
+  else { rlo = 0; rhi = p; clo = p + kc * KC; chi = min(m, clo + KC); }
+  const int r0 = blockIdx.z * NR, nr = min(NR, a.nrhs - r0);
   const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+  cplx<T>* vg = vbuf + (long long)r0 * a.vstride + f.idx_off;
+  cplx<T>* yg = ybuf + (long long)r0 * a.ystride + (long long)fi * SB;  // y_s(c) at yg[c - s0]
+  if constexpr (MODE == MODE_FS) {
+    if (blockIdx.x == 0)  // y_s into the front vector at the pivot positions
+      for (int e = tid; e < NR * SB; e += 256) {
+        const int k = e / SB, c = s0 + e % SB;
+        if (k < nr && c < s1) vg[(long long)k * a.vstride + c] = yg[(long long)k * a.ystride + c - s0];
+      }
+  }
+  const int row0 = rlo + tile * GR;
+  if (row0 >= rhi || clo >= chi) return;
   const int r = min(row0 + lane, rhi - 1);
-  const cplx<T>* F = Fbuf + f.f_off;
+  // entry (r, c) of the rectangle's matrix at A[(c - cb) * ld + r - rb]
+  const cplx<T>* A;
+  long long ld;
+  int rb, cb;
+  if constexpr (MODE == MODE_W || MODE == MODE_V) {
+    A = Gop + f.g_off + (long long)(MODE == MODE_V ? nsb + a.s : a.s) * SB * SB;
+    ld = SB;
+    rb = s0;
+    cb = s0;
+  } else {
+    A = Fbuf + f.f_off;
+    ld = m;
+    rb = 0;
+    cb = 0;
+  }
   const int* id = idx + f.idx_off;
-  cplx<T>* vg = vbuf + (long long)r0 * vstride + f.idx_off;
   cplx<T> acc[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
@@ -307,25 +358,27 @@ __global__ void __launch_bounds__(256) bsweep_gemv_kernel(const cplx<T>* __restr
     for (int e = tid; e < NR * GC; e += 256) {
       const int k = e / GC, jj = e % GC;
       if (k < nr && jj < cn) {
-        if constexpr (MODE == 2) xin[k][jj] = x[(long long)(r0 + k) * N + id[c0 + jj]];
-        else xin[k][jj] = vg[(long long)k * vstride + c0 + jj];
+        const int c = c0 + jj;
+        if constexpr (MODE == MODE_BB) xin[k][jj] = x[(long long)(r0 + k) * a.N + id[c]];
+        else if constexpr (MODE == MODE_FS || MODE == MODE_BS) xin[k][jj] = yg[(long long)k * a.ystride + c - s0];
+        else xin[k][jj] = vg[(long long)k * a.vstride + c];
       }
     }
     __syncthreads();
     for (int t0 = 0; t0 < GC / 4; t0 += GU) {
       if (w + 4 * t0 >= cn) break;
-      cplx<T> a[GU];
+      cplx<T> av[GU];
 #pragma unroll
       for (int u = 0; u < GU; ++u) {
         const int jj = min(w + 4 * (t0 + u), cn - 1);
-        a[u] = F[(long long)(c0 + jj) * m + r];
+        av[u] = A[(long long)(c0 + jj - cb) * ld + (r - rb)];
       }
 #pragma unroll
       for (int u = 0; u < GU; ++u) {
         const int jj = w + 4 * (t0 + u);
         if (jj < cn)
 #pragma unroll
-          for (int k = 0; k < NR; ++k) acc[k] = cfma(acc[k], a[u], xin[min(k, nr - 1)][jj]);
+          for (int k = 0; k < NR; ++k) acc[k] = cfma(acc[k], av[u], xin[min(k, nr - 1)][jj]);
       }
     }
   }
@@ -335,89 +388,135 @@ __global__ void __launch_bounds__(256) bsweep_gemv_kernel(const cplx<T>* __restr
   for (int e = tid; e < NR * GR; e += 256) {
     const int k = e / GR, rl = e % GR, rr = row0 + rl;
     if (k < nr && rr < rhi) {
-      cplx<T> s = cadd(cadd(part[0][k][rl], part[1][k][rl]), cadd(part[2][k][rl], part[3][k][rl]));
-      cplx<T>* o = vg + (long long)k * vstride + rr;
-      *o = csub(*o, s);
+      const cplx<T> sm = cadd(cadd(part[0][k][rl], part[1][k][rl]), cadd(part[2][k][rl], part[3][k][rl]));
+      if constexpr (MODE == MODE_W) {
+        yg[(long long)k * a.ystride + rr - s0] = sm;
+      } else if constexpr (MODE == MODE_V) {
+        yg[(long long)k * a.ystride + rr - s0] = sm;
+        const long long gi = id[rr];
+        x[(long long)(r0 + k) * a.N + gi] = sm;
+        if (xw) xw[(long long)(r0 + k) * a.N + gi] = widen(sm);
+      } else if constexpr (MODE == MODE_BB) {
+        pbuf[((long long)kc * a.nrhs + r0 + k) * a.ystride + (long long)fi * a.maxp + rr] = sm;
+      } else {
+        cplx<T>* o = vg + (long long)k * a.vstride + rr;
+        *o = csub(*o, sm);
+      }
     }
   }
 }
 
+// t(r) = t(r) - sum over the boundary column chunks (in chunk order) of the
+// partial sums; one thread per (pivot row, front, right-hand side).
+template <typename T>
+__global__ void __launch_bounds__(256) bsweep_bb_reduce_kernel(const FrontDev* __restrict__ fr,
+                                                               cplx<T>* __restrict__ vbuf,
+                                                               const cplx<T>* __restrict__ pbuf, GemvArgs a) {
+  const int fi = blockIdx.y;
+  const FrontDev f = fr[a.first + fi];
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= f.p || f.q == 0) return;
+  const int k = blockIdx.z;
+  const int kch = (f.q + KC - 1) / KC;
+  cplx<T> sm = pbuf[((long long)0 * a.nrhs + k) * a.ystride + (long long)fi * a.maxp + r];
+  for (int c = 1; c < kch; ++c) sm = cadd(sm, pbuf[((long long)c * a.nrhs + k) * a.ystride + (long long)fi * a.maxp + r]);
+  cplx<T>* o = vbuf + (long long)k * a.vstride + f.idx_off + r;
+  *o = csub(*o, sm);
+}
+
 template <typename T, int NR, int MODE>
-void gemv_launch(const MfDev<T>& mf, const Plan& plan, int l, int s0, int nrows, int nrhs, const cplx<T>* x,
-                 cplx<T>* vbuf, hipStream_t st) {
+void gemv_launch(const MfDev<T>& mf, const Plan& plan, int l, int s, int nrows, int kch, int nrhs, cplx<T>* x,
+                 cplx<T>* vbuf, const SweepBufs<T>& sb, double2* xw, hipStream_t st) {
   if (nrows <= 0) return;
   const int first = plan.level_ptr[l];
   const int cnt = plan.level_ptr[l + 1] - first;
   const int groups = (nrhs + NR - 1) / NR;
+  GemvArgs a{first, s, kch, plan.level_maxp[l], nrhs, (long long)plan.N, (long long)plan.sum_pq, sb.ystride};
   LSP_LAUNCH("bsweep_gemv", (int)sizeof(cplx<T>), (bsweep_gemv_kernel<T, NR, MODE>),
-             dim3((nrows + GR - 1) / GR, cnt, groups), dim3(256), 0, st, mf.F, mf.fronts, mf.idx, x, vbuf, first, s0,
-             nrhs, (long long)plan.N, (long long)plan.sum_pq);
+             dim3((nrows + GR - 1) / GR * kch, cnt, groups), dim3(256), 0, st, mf.F, mf.G, mf.fronts, mf.idx, x, vbuf,
+             sb.ybuf, sb.pbuf, xw, a);
 }
 
 template <typename T, int NR>
 void blocked_level_fwd(const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* vbuf,
-                       hipStream_t st) {
-  constexpr int NG = NR > 8 ? 8 : NR;  // chain right-hand sides per workgroup
+                       const SweepBufs<T>& sb, hipStream_t st) {
   const int first = plan.level_ptr[l];
   const int cnt = plan.level_ptr[l + 1] - first;
   const int maxm = plan.level_maxpq[l], maxp = plan.level_maxp[l];
   LSP_LAUNCH("bsweep_gather", (int)sizeof(cplx<T>), bsweep_gather_kernel<T>, dim3((maxm + 255) / 256, cnt, nrhs),
              dim3(256), 0, st, mf.fronts, mf.idx, mf.cpos, z, vbuf, first, (long long)plan.N, (long long)plan.sum_pq);
-  const int cgroups = (nrhs + NG - 1) / NG;
-  for (int s0 = 0; s0 < maxp; s0 += SB) {
-    LSP_LAUNCH("bsweep_fwd_chain", (int)sizeof(cplx<T>), (bsweep_fwd_chain_kernel<T, NG>), dim3(cnt, cgroups),
-               dim3(256), 0, st, mf.F, mf.Dinv, mf.fronts, mf.perm, vbuf, first, s0, nrhs, (long long)plan.sum_pq);
-    // rows below the super-block, the most over the level's fronts
-    int rows = 0;
+  const int nsb = (maxp + SB - 1) / SB;
+  for (int s = 0; s < nsb; ++s) {
+    const int s0 = s * SB;
+    gemv_launch<T, NR, MODE_W>(mf, plan, l, s, std::min(SB, maxp - s0), 1, nrhs, nullptr, vbuf, sb, nullptr, st);
+    int rows = 0;  // rows below the super-block, the most over the level's fronts
     for (int i = first; i < first + cnt; ++i) {
       const FrontDev& f = plan.fronts[i];
       if (f.p > s0) rows = std::max(rows, f.p + f.q - std::min(s0 + SB, f.p));
     }
-    gemv_launch<T, NR, 0>(mf, plan, l, s0, rows, nrhs, nullptr, vbuf, st);
+    // at least one tile, so that tile 0 copies y_s into the front vector
+    gemv_launch<T, NR, MODE_FS>(mf, plan, l, s, std::max(rows, 1), 1, nrhs, nullptr, vbuf, sb, nullptr, st);
   }
 }
 
 template <typename T, int NR>
 void blocked_level_bwd(const MfDev<T>& mf, const Plan& plan, int l, int nrhs, cplx<T>* x, cplx<T>* vbuf,
-                       hipStream_t st, double2* xw) {
-  constexpr int NG = NR > 8 ? 8 : NR;
+                       const SweepBufs<T>& sb, hipStream_t st, double2* xw) {
   const int first = plan.level_ptr[l];
   const int cnt = plan.level_ptr[l + 1] - first;
   const int maxp = plan.level_maxp[l];
-  gemv_launch<T, NR, 2>(mf, plan, l, 0, maxp, nrhs, x, vbuf, st);
-  const int cgroups = (nrhs + NG - 1) / NG;
+  int maxq = 0;
+  for (int i = first; i < first + cnt; ++i) maxq = std::max(maxq, plan.fronts[i].q);
+  if (maxq > 0) {
+    const int kch = (maxq + KC - 1) / KC;
+    gemv_launch<T, NR, MODE_BB>(mf, plan, l, 0, maxp, kch, nrhs, x, vbuf, sb, nullptr, st);
+    GemvArgs a{first, 0, kch, maxp, nrhs, (long long)plan.N, (long long)plan.sum_pq, sb.ystride};
+    LSP_LAUNCH("bsweep_bb_reduce", (int)sizeof(cplx<T>), bsweep_bb_reduce_kernel<T>,
+               dim3((maxp + 255) / 256, cnt, nrhs), dim3(256), 0, st, mf.fronts, vbuf, sb.pbuf, a);
+  }
   const int nsb = (maxp + SB - 1) / SB;
   for (int s = nsb - 1; s >= 0; --s) {
     const int s0 = s * SB;
-    LSP_LAUNCH("bsweep_bwd_chain", (int)sizeof(cplx<T>), (bsweep_bwd_chain_kernel<T, NG>), dim3(cnt, cgroups),
-               dim3(256), 0, st, mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, s0, nrhs, (long long)plan.N,
-               (long long)plan.sum_pq, xw);
-    gemv_launch<T, NR, 3>(mf, plan, l, s0, s0, nrhs, nullptr, vbuf, st);
+    gemv_launch<T, NR, MODE_V>(mf, plan, l, s, std::min(SB, maxp - s0), 1, nrhs, x, vbuf, sb, xw, st);
+    gemv_launch<T, NR, MODE_BS>(mf, plan, l, s, s0, 1, nrhs, nullptr, vbuf, sb, nullptr, st);
   }
-}
-
-template <typename T, int NR>
-void blocked_dispatch(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
-                      cplx<T>* vbuf, hipStream_t st, double2* xw) {
-  if (fwd) blocked_level_fwd<T, NR>(mf, plan, l, nrhs, z, vbuf, st);
-  else blocked_level_bwd<T, NR>(mf, plan, l, nrhs, x, vbuf, st, xw);
 }
 
 }  // namespace
 
 template <typename T>
 void blocked_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
-                   cplx<T>* vbuf, hipStream_t st, double2* xw) {
-  if (nrhs >= 16) blocked_dispatch<T, 16>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
-  else if (nrhs >= 8) blocked_dispatch<T, 8>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
-  else if (nrhs >= 4) blocked_dispatch<T, 4>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
-  else if (nrhs >= 2) blocked_dispatch<T, 2>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
-  else blocked_dispatch<T, 1>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
+                   cplx<T>* vbuf, const SweepBufs<T>& sb, hipStream_t st, double2* xw) {
+#define LSP_BLOCKED(NR)                                               \
+  do {                                                                \
+    if (fwd) blocked_level_fwd<T, NR>(mf, plan, l, nrhs, z, vbuf, sb, st); \
+    else blocked_level_bwd<T, NR>(mf, plan, l, nrhs, x, vbuf, sb, st, xw); \
+  } while (0)
+  if (nrhs >= 16) LSP_BLOCKED(16);
+  else if (nrhs >= 8) LSP_BLOCKED(8);
+  else if (nrhs >= 4) LSP_BLOCKED(4);
+  else if (nrhs >= 2) LSP_BLOCKED(2);
+  else LSP_BLOCKED(1);
+#undef LSP_BLOCKED
+}
+
+template <typename T>
+void blocked_form(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st) {
+  const int first = plan.level_ptr[l];
+  const int cnt = plan.level_ptr[l + 1] - first;
+  const int nsbmax = (plan.level_maxp[l] + SB - 1) / SB;
+  const int ncol = (std::min(SB, plan.level_maxp[l]) + NF - 1) / NF;
+  LSP_LAUNCH("bsweep_form_fwd", (int)sizeof(cplx<T>), bsweep_form_fwd_kernel<T>, dim3(cnt * nsbmax, ncol), dim3(256),
+             0, st, mf.F, mf.Dinv, mf.fronts, mf.perm, mf.G, first, nsbmax);
+  LSP_LAUNCH("bsweep_form_bwd", (int)sizeof(cplx<T>), bsweep_form_bwd_kernel<T>, dim3(cnt * nsbmax, ncol), dim3(256),
+             0, st, mf.F, mf.Dinv, mf.fronts, mf.G, first, nsbmax);
 }
 
 template void blocked_sweep<double>(bool, const MfDev<double>&, const Plan&, int, int, const double2*, double2*,
-                                    double2*, hipStream_t, double2*);
+                                    double2*, const SweepBufs<double>&, hipStream_t, double2*);
 template void blocked_sweep<float>(bool, const MfDev<float>&, const Plan&, int, int, const float2*, float2*, float2*,
-                                   hipStream_t, double2*);
+                                   const SweepBufs<float>&, hipStream_t, double2*);
+template void blocked_form<double>(const MfDev<double>&, const Plan&, int, hipStream_t);
+template void blocked_form<float>(const MfDev<float>&, const Plan&, int, hipStream_t);
 
 }  // namespace lsp

@@ -44,7 +44,8 @@ class PlanStats(ctypes.Structure):
                 ("sweep_entries", ctypes.c_double), ("update_flops", ctypes.c_double),
                 ("panel_blocks", ctypes.c_double),
                 ("fused_blocks", ctypes.c_double), ("fused_update_flops", ctypes.c_double),
-                ("dense_entries", ctypes.c_double), ("dense_levels", ctypes.c_int)]
+                ("dense_entries", ctypes.c_double), ("dense_levels", ctypes.c_int),
+                ("blocked_levels", ctypes.c_int), ("blocked_entries", ctypes.c_double)]
 
 
 class LspError(RuntimeError):

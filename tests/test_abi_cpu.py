@@ -113,13 +113,34 @@ def test_dense_sweep_levels(lib):
     q1, q0 = L.Plan(8, 2).stats(), L.Plan(8, 2, dense_sweeps=0).stats()
     assert q1["dense_levels"] == 1 and q1["dense_entries"] == 64 * 64 and q1["sweep_entries"] == 0
     assert q0["dense_levels"] == 0 and q0["dense_entries"] == 0 and q0["sweep_entries"] == 3 * 32 * 32
-    p1, p0 = L.Plan(256, 2), L.Plan(256, 2, dense_sweeps=0)
+    p1, p0 = L.Plan(256, 2, blocked_sweeps=0), L.Plan(256, 2, dense_sweeps=0, blocked_sweeps=0)
     s1, s0 = p1.stats(), p0.stats()
     assert s1["dense_levels"] == 5 and s0["dense_levels"] == 0
     assert s1["sweep_entries"] < s0["sweep_entries"] and s1["dense_entries"] > 0
     for prec, esz in ((L.LSP_FP64, 16), (L.LSP_MIXED, 8)):
         grow = p1.bytes(1, prec)[0] - p0.bytes(1, prec)[0]
         assert 0 <= grow - 2 * s1["dense_entries"] * esz < 256
+
+
+def test_blocked_sweep_levels(lib):
+    """Blocked sweep levels: 3D n = 32 sweeps its three top non-dense levels
+    (8, 4, 2 fronts of more than 1024 rows) blocked; each front keeps a
+    forward and a backward 256 x 256 operator per 256-pivot super-block, so
+    the problem's device memory grows by exactly 2 blocked_entries entries
+    over the plan without blocked levels, and the solve workspace by the
+    blocked sweeps' work buffers only."""
+    b1, b0 = L.Plan(32, 3, max_nrhs=4), L.Plan(32, 3, max_nrhs=4, blocked_sweeps=0)
+    s1, s0 = b1.stats(), b0.stats()
+    assert s1["blocked_levels"] == 3 and s0["blocked_levels"] == 0
+    assert s1["dense_levels"] == s0["dense_levels"]
+    # fronts of those levels: 8 x 256, 4 x 256, 2 x 512 pivots -> 8 + 4 + 4 super-blocks
+    assert s1["blocked_entries"] == 16 * 256 * 256
+    for prec, esz in ((L.LSP_FP64, 16), (L.LSP_MIXED, 8)):
+        grow = b1.bytes(4, prec)[0] - b0.bytes(4, prec)[0]
+        assert 0 <= grow - 2 * s1["blocked_entries"] * esz < 256
+        assert b1.bytes(4, prec)[1] > b0.bytes(4, prec)[1]
+    # every non-dense, non-small level with blocked_sweeps = 2
+    assert L.Plan(32, 3, blocked_sweeps=2).stats()["blocked_levels"] > s1["blocked_levels"]
 
 
 def test_lookahead_schedule_stats(lib):
