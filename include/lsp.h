@@ -81,7 +81,12 @@ typedef struct {
                         1024 rows, lsp_factor also forms each front's
                         forward and backward sweep operators (2 m p entries
                         per front) and the sweeps apply them as dense
-                        products; 0: every level uses the panel chain */
+                        products; in plans for blocks of right-hand sides
+                        (max_nrhs >= 4) also on the levels of more than 16
+                        fronts of at most 64 pivots and 256 rows (one
+                        product per front); 2: those small-front levels
+                        whatever max_nrhs; 0: every level uses the panel
+                        chain (or the blocked sweeps) */
   int blocked_sweeps; /* 1 (default): on the levels (not swept with dense
                         operators) whose fronts have more than 1024 rows,
                         or with at most 32 fronts of more than two panels,
@@ -98,6 +103,15 @@ typedef struct {
   int converged;        /* 1 if the true relative residual met tol */
   double relres_true;   /* ||g - A u|| / ||g||, recomputed in complex128 */
   double relres_est;    /* GMRES estimate at the last step */
+  double t_setup;       /* milliseconds of the problem's lsp_setup work on the
+                           device (HIP events on its stream, kernel table to
+                           matrix M), the same for every right-hand side */
+  double t_factor;      /* milliseconds of its last lsp_factor on the stream
+                           (the factorisation and the pivot report; the
+                           operator formation on the side stream overlaps
+                           it and is not included) */
+  double t_solve;       /* milliseconds of this lsp_solve on the stream, from
+                           its first launch to its last report */
 } lsp_rhs_info;
 
 typedef struct {
@@ -133,6 +147,22 @@ typedef struct {
                                  reads on the blocked levels (their panels
                                  outside the super-blocks' diagonal blocks
                                  are in sweep_entries) */
+  double chain_entries;       /* of sweep_entries, the part on the levels swept
+                                 by panel chains (neither dense nor blocked) */
+  double blocked_panel_entries; /* factor entries one sweep's matrix-vector
+                                 products read on the blocked levels (each
+                                 super-block's columns below it, or its rows
+                                 right of it, outside its diagonal block) */
+  double trsm_flops;          /* real flops of the panel products U12 =
+                                 L11^{-1} P F12, L21 = F21 U11^{-1} run as
+                                 launches of their own (the rest run inside
+                                 the panel-strip launches) */
+  double assemble_entries;    /* front entries the assembly writes plus the
+                                 children's update-matrix entries it reads */
+  int sdense_levels;          /* small-front levels swept with formed
+                                 operators (dense_sweeps) */
+  double sdense_entries;      /* entries of their operators one sweep reads
+                                 (sum of m p over their fronts) */
 } lsp_plan_stats;
 
 typedef struct lsp_plan lsp_plan;        /* opaque; host-side, plus one device copy of

@@ -1040,9 +1040,10 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
                                                   const int* __restrict__ cpos, const int* __restrict__ perm,
                                                   const cplx<T>* __restrict__ z, cplx<T>* __restrict__ vbuf, int first,
                                                   int nrhs, long long N, long long vstride, cplx<T>* __restrict__ Gop) {
-  static_assert(NR * NB <= 256, "one gather thread per panel entry");
+  static_assert(NR * NB <= 2 * TPB, "at most two gathered panel entries per thread");
   static_assert(TPB == 256 || TPB == 512, "256 or 512 threads");
   static_assert(!FORM || VL, "operators are formed with the vectors in LDS");
+  constexpr bool G2 = NR * NB > TPB;  // a second gathered entry, right-hand side gk + TPB / NB
   static_assert(FORM || !TRANS, "the transposed chain only forms operators");
   constexpr int IPT = NB * NB / TPB;  // inverse-block entries per thread
   extern __shared__ unsigned char smem_raw[];
@@ -1160,6 +1161,12 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
     // gather P_b v_b (issued before the prefetches, so waiting for it does not wait for them)
     const cplx<T> gv = vp[min(gk, nr - 1) * vs + pnext];
     const cplx<T> g = tid < NR * NB && gk < nr && gj < kb ? gv : mk<T>(0, 0);
+    constexpr int GK2 = TPB / NB;
+    cplx<T> g2 = mk<T>(0, 0);
+    if constexpr (G2) {
+      const cplx<T> gv2 = vp[min(gk + GK2, nr - 1) * vs + pnext];
+      g2 = gk + GK2 < nr && gj < kb ? gv2 : mk<T>(0, 0);
+    }
     __builtin_amdgcn_sched_barrier(0);
     // next panel's L11^{-1} (the last panel reloads its own: unused, but it
     // keeps these loads unconditional so they stay in registers)
@@ -1171,6 +1178,7 @@ __global__ void __launch_bounds__(TPB) fwd_kernel(const cplx<T>* __restrict__ Fb
     if (b > 0) load_l(k0, lc);
     __builtin_amdgcn_sched_barrier(0);
     if (tid < NR * NB) tb[gk][gj] = g;
+    if constexpr (G2) tb[gk + GK2][gj] = g2;
     // Li[cur ^ 1] was last read before the previous panel's final barrier
     put_inv(Li[cur ^ 1], tid, lin0);
     put_inv(Li[cur ^ 1], tid + TPB, lin1);
@@ -1855,7 +1863,7 @@ void form_level(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st) {
 // Formation of dense level l once its factorisation is enqueued on st.
 template <typename T>
 void form_after(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st, const FormStream* fs) {
-  if (!plan.level_dense[l] && !plan.level_blocked[l]) return;
+  if (!plan.level_dense[l] && !plan.level_blocked[l] && !plan.level_sdense[l]) return;
   hipStream_t fst = st;
   if (fs) {
     LSP_HIP(hipEventRecord(fs->level, st));
@@ -1863,6 +1871,7 @@ void form_after(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st, con
     fst = fs->aux;
   }
   if (plan.level_blocked[l]) blocked_form<T>(mf, plan, l, fst);
+  else if (plan.level_sdense[l]) sdense_form<T>(mf, plan, l, fst);
   else if (wide_level(plan, l)) form_level<T, 512>(mf, plan, l, fst);
   else form_level<T, 256>(mf, plan, l, fst);
 }
@@ -1872,9 +1881,13 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
                   const SweepBufs<T>& sb, hipStream_t st, hipEvent_t form_done, double2* xw) {
   const int groups = (nrhs + NR - 1) / NR;
   for (int l = 0; l < plan.nlevels; ++l) {
-    if ((plan.level_dense[l] || plan.level_blocked[l]) && form_done) {
+    if ((plan.level_dense[l] || plan.level_blocked[l] || plan.level_sdense[l]) && form_done) {
       LSP_HIP(hipStreamWaitEvent(st, form_done, 0));
       form_done = nullptr;
+    }
+    if (plan.level_sdense[l]) {
+      sdense_sweep<T>(true, mf, plan, l, nrhs, z, x, vbuf, st, xw);
+      continue;
     }
     if constexpr (NR == 1) {
       if (plan.level_small_sweep[l]) {
@@ -1891,6 +1904,10 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
     else sweep_fwd<T, NR, 256>(mf, plan, l, groups, nrhs, z, vbuf, st);
   }
   for (int l = plan.nlevels - 1; l >= 0; --l) {
+    if (plan.level_sdense[l]) {
+      sdense_sweep<T>(false, mf, plan, l, nrhs, z, x, vbuf, st, xw);
+      continue;
+    }
     if constexpr (sizeof(T) == 4 && NR == 1) {
       if (plan.level_small_sweep[l]) {
         LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_small_kernel<T, NR>),
@@ -2050,6 +2067,14 @@ FactorSchedule factor_schedule(const Plan& plan, bool fp64) {
   FactorSchedule s;
   for (int l = 0; l < plan.nlevels; ++l) {
     const bool strips = strip_level(plan, l, fp64);
+    if (!strips)  // U12 = L11^{-1} P F12 and L21 = F21 U11^{-1}: 2 kb^2 (m - k1) complex multiply-adds per panel
+      for (int i = plan.level_ptr[l]; i < plan.level_ptr[l + 1]; ++i) {
+        const FrontDev& f = plan.fronts[i];
+        for (int k0 = 0; k0 < f.p; k0 += NB) {
+          const int kb = std::min(NB, f.p - k0);
+          s.trsm_flops += 8.0 * 2.0 * (double)kb * kb * (double)(f.p + f.q - k0 - kb);
+        }
+      }
     for (int k0 = 0; k0 < plan.level_maxp[l]; k0 += NB) {
       // update launches other than gemm_update: the panel steps of a strip
       // level (all but the last panel) and the lookahead launches
@@ -2072,6 +2097,9 @@ FactorSchedule factor_schedule(const Plan& plan, bool fp64) {
 template <typename T>
 void mf_solve(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, cplx<T>* x, cplx<T>* vbuf,
               const SweepBufs<T>& sb, hipStream_t st, hipEvent_t form_done, double2* xw) {
+  // groups of at most 8 right-hand sides on the panel-chain levels (16 per
+  // workgroup halves the workgroups and their occupancy: measured slower on
+  // 2D n = 1024); the blocked levels take up to 16 per product
   if (nrhs >= 8) solve_levels<T, 8>(mf, plan, nrhs, z, x, vbuf, sb, st, form_done, xw);
   else if (nrhs >= 4) solve_levels<T, 4>(mf, plan, nrhs, z, x, vbuf, sb, st, form_done, xw);
   else if (nrhs >= 2) solve_levels<T, 2>(mf, plan, nrhs, z, x, vbuf, sb, st, form_done, xw);

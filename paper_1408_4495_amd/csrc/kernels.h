@@ -106,6 +106,7 @@ void mf_factor(const MfDev<T>& mf, const Plan& plan, hipStream_t st, const FormS
 struct FactorSchedule {
   double fused_blocks = 0.0;
   double fused_update_flops = 0.0;
+  double trsm_flops = 0.0;  // real flops of the panel_trsm launches
 };
 FactorSchedule factor_schedule(const Plan& plan, bool fp64);
 // Forward and backward sweeps; form_done (may be null): an event the first
@@ -123,6 +124,16 @@ void mf_solve(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, 
 template <typename T>
 void blocked_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
                    cplx<T>* vbuf, const SweepBufs<T>& sb, hipStream_t st, double2* xw);
+// Sweep of a small-front level with formed operators (Plan::level_sdense):
+// per front one product with Gf (forward) or Gb (backward), formed by the
+// dense levels' formation at the front's g_off.
+template <typename T>
+void sdense_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
+                  cplx<T>* vbuf, hipStream_t st, double2* xw);
+// Forms the operators of small dense level l (one workgroup per front and
+// chunk of unit vectors, the chains in LDS).
+template <typename T>
+void sdense_form(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st);
 // Forms the super-block operators of blocked level l from its factor (the
 // panel chains on the unit vectors), into mf.G at each front's g_off.
 template <typename T>

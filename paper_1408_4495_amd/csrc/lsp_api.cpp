@@ -288,37 +288,52 @@ struct lsp_problem {
   // wait for fs.done
   FormStream fs{};
   bool form_pending = false;
+  // phase events (timing enabled) on the problem's stream: set-up, the last
+  // factorisation and the last solve, each a start / end pair
+  enum { EV_SETUP0, EV_SETUP1, EV_FACTOR0, EV_FACTOR1, EV_SOLVE0, EV_SOLVE1, EV_COUNT };
+  hipEvent_t ev[EV_COUNT] = {};
 
   ~lsp_problem() {
+    if (ev[0]) {
+      (void)hipEventSynchronize(ev[EV_SETUP1]);
+      std::lock_guard<std::mutex> g(event_pool_mu());
+      for (hipEvent_t e : ev) event_pool().emplace_back(device, e);
+    }
     if (ctl_host) ctl_pool().put({ctl_host, ctl_dev, host_cap});
     if (fs.aux) {
       // the caller may release the workspace next: the formation must be over
       (void)hipEventSynchronize(fs.done);
-      form_pool().put(device, fs);
+      form_pool().put(device, st, fs);
     }
   }
 
-  // One formation stream per device, shared by its problems (creating a
-  // stream costs milliseconds), and pooled event pairs; all live until the
-  // process ends.
+  // One formation stream per (device, problem stream), shared by the
+  // problems that run on that stream (creating a stream costs milliseconds),
+  // so that problems on different streams (serving slots) never wait for each
+  // other's formation; and pooled event pairs.  All live until the process
+  // ends.
+  struct FormKey {
+    int dev;
+    hipStream_t user;
+  };
   struct FormPool {
     std::mutex mu;
-    std::vector<std::pair<int, hipStream_t>> streams;
-    std::vector<std::pair<int, FormStream>> free;
-    FormStream get(int dev) {
+    std::vector<std::pair<FormKey, hipStream_t>> streams;
+    std::vector<std::pair<FormKey, FormStream>> free;
+    FormStream get(int dev, hipStream_t user) {
       std::lock_guard<std::mutex> g(mu);
       for (size_t i = 0; i < free.size(); ++i)
-        if (free[i].first == dev) {
+        if (free[i].first.dev == dev && free[i].first.user == user) {
           FormStream f = free[i].second;
           free.erase(free.begin() + i);
           return f;
         }
       FormStream f{};
       for (const auto& e : streams)
-        if (e.first == dev) f.aux = e.second;
+        if (e.first.dev == dev && e.first.user == user) f.aux = e.second;
       if (!f.aux) {
         LSP_HIP(hipStreamCreateWithFlags(&f.aux, hipStreamNonBlocking));
-        streams.emplace_back(dev, f.aux);
+        streams.push_back({FormKey{dev, user}, f.aux});
       }
       LSP_HIP(hipEventCreateWithFlags(&f.level, hipEventDisableTiming));
       if (hipEventCreateWithFlags(&f.done, hipEventDisableTiming) != hipSuccess) {
@@ -328,15 +343,50 @@ struct lsp_problem {
       LSP_HIP(hipEventRecord(f.done, f.aux));  // so that a first wait on it returns once the stream's work so far is done
       return f;
     }
-    void put(int dev, const FormStream& f) {
+    void put(int dev, hipStream_t user, const FormStream& f) {
       std::lock_guard<std::mutex> g(mu);
-      free.emplace_back(dev, f);
+      free.push_back({FormKey{dev, user}, f});
     }
   };
   static FormPool& form_pool() {
     static FormPool* pool = new FormPool();
     return *pool;
   }
+  // Timing events for the phases, pooled per device for the process's life.
+  static std::mutex& event_pool_mu() {
+    static std::mutex* m = new std::mutex();
+    return *m;
+  }
+  static std::vector<std::pair<int, hipEvent_t>>& event_pool() {
+    static auto* v = new std::vector<std::pair<int, hipEvent_t>>();
+    return *v;
+  }
+  void take_events() {
+    std::lock_guard<std::mutex> g(event_pool_mu());
+    auto& pool = event_pool();
+    for (int i = 0; i < EV_COUNT; ++i) {
+      ev[i] = nullptr;
+      for (size_t k = 0; k < pool.size(); ++k)
+        if (pool[k].first == device) {
+          ev[i] = pool[k].second;
+          pool.erase(pool.begin() + k);
+          break;
+        }
+      if (!ev[i]) LSP_HIP(hipEventCreate(&ev[i]));
+    }
+  }
+  // milliseconds between two recorded events of this problem (0 if either
+  // was never recorded)
+  double phase_ms(int a, int b, bool recorded) const {
+    float ms = 0.0f;
+    if (!recorded || hipEventElapsedTime(&ms, ev[a], ev[b]) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0.0;
+    }
+    return ms;
+  }
+  bool factor_timed = false;
+
   // the event the next sweeps wait for, once after each factorisation
   hipEvent_t take_form_wait() {
     if (!form_pending) return nullptr;
@@ -631,7 +681,7 @@ lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts, 
     LSP_REQUIRE(o.max_iters >= 1, "max_iters must be >= 1");
     LSP_REQUIRE(o.precision == LSP_FP64 || o.precision == LSP_MIXED, "unknown precision");
     LSP_REQUIRE(o.panel == 0 || o.panel == kNbMax, "panel must be 0 (auto) or 32");
-    LSP_REQUIRE(o.dense_sweeps == 0 || o.dense_sweeps == 1, "dense_sweeps must be 0 or 1");
+    LSP_REQUIRE(o.dense_sweeps >= 0 && o.dense_sweeps <= 2, "dense_sweeps must be 0, 1 or 2");
     LSP_REQUIRE(o.blocked_sweeps >= 0 && o.blocked_sweeps <= 2, "blocked_sweeps must be 0, 1 or 2");
     std::unique_ptr<lsp_plan> pl(new lsp_plan());
     build_plan(pl->p, n, d, max_nrhs, o);
@@ -665,6 +715,12 @@ lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* s) {
   s->dense_levels = P.dense_levels;
   s->blocked_levels = P.blocked_levels;
   s->blocked_entries = P.blocked_entries;
+  s->chain_entries = P.chain_entries;
+  s->blocked_panel_entries = P.blocked_panel_entries;
+  s->trsm_flops = fs.trsm_flops;
+  s->assemble_entries = P.assemble_entries;
+  s->sdense_levels = P.sdense_levels;
+  s->sdense_entries = P.sdense_entries;
   return LSP_OK;
 }
 
@@ -717,6 +773,8 @@ lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, vo
     LSP_REQUIRE(ws_bytes - ((size_t)base - (size_t)ws_dev) >= need - 256, "problem workspace too small");
     layout_problem(plan, prec, base, &pb->d);
     hipStream_t st = pb->st;
+    pb->take_events();
+    LSP_HIP(hipEventRecord(pb->ev[lsp_problem::EV_SETUP0], st));
 
     // the plan's constant arrays (uploaded once per device)
     const PlanDev& pd = plan_device(plan, pb->device);
@@ -741,6 +799,7 @@ lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, vo
     compute_stencils(pb->d.ktab, P.n, P.d, pb->d.geo, plan->nclass, plan->maxF, pb->d.partial, plan->gram_blocks,
                      pb->d.G, pb->d.U1, pb->d.alpha_pad, pb->d.C_pad, pb->d.sigma_pad, st);
     launch_assemble(pb->d.Mval, pb->d.alpha_pad, pb->d.C_pad, pb->d.w2m, P.n, P.d, P.N, st);
+    LSP_HIP(hipEventRecord(pb->ev[lsp_problem::EV_SETUP1], st));
     *out = pb.release();
     return LSP_OK;
   });
@@ -752,12 +811,12 @@ lsp_status lsp_factor(lsp_problem* pb) {
   return guarded([&]() -> lsp_status {
     LSP_REQUIRE(pb != nullptr, "null problem");
     const Plan& P = pb->plan->p;
-    if (P.dense_levels + P.blocked_levels > 0 && !pb->fs.aux) {
+    if (P.dense_levels + P.blocked_levels + P.sdense_levels > 0 && !pb->fs.aux) {
       int cur = 0;
       LSP_HIP(hipGetDevice(&cur));
       if (cur != pb->device) LSP_HIP(hipSetDevice(pb->device));
       try {
-        pb->fs = lsp_problem::form_pool().get(pb->device);
+        pb->fs = lsp_problem::form_pool().get(pb->device, pb->st);
       } catch (...) {
         if (cur != pb->device) (void)hipSetDevice(cur);
         throw;
@@ -766,6 +825,7 @@ lsp_status lsp_factor(lsp_problem* pb) {
     }
     const FormStream* fsp = pb->fs.aux ? &pb->fs : nullptr;
     pb->form_pending = fsp != nullptr;
+    LSP_HIP(hipEventRecord(pb->ev[lsp_problem::EV_FACTOR0], pb->st));
     if (pb->precision == LSP_FP64) {
       MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                        pb->d.pivstat, (double2*)pb->d.Gop};
@@ -780,6 +840,8 @@ lsp_status lsp_factor(lsp_problem* pb) {
     pb->ensure_host(1);
     k_min_report(pb->d.pivstat, (long long)P.panel_blocks, lsp_problem::ctl_view(pb->ctl_dev, pb->host_cap),
                  ++pb->ctl_tag, pb->st);
+    LSP_HIP(hipEventRecord(pb->ev[lsp_problem::EV_FACTOR1], pb->st));
+    pb->factor_timed = true;
     pb->wait_ctl(pb->ctl_tag);
     const double mn = lsp_problem::ctl_view(pb->ctl_host, pb->host_cap).hdr->value;
     pb->min_pivot_ratio = mn;
@@ -929,6 +991,7 @@ lsp_status lsp_solve(lsp_problem* pb, int nrhs, int rhs_kind, const void* rhs, v
     layout_solve(P, nrhs, R, true, (void*)align_up((size_t)ws, 256), &s);
     pb->ensure_host(nrhs);
     double2* x = (double2*)u;
+    LSP_HIP(hipEventRecord(pb->ev[lsp_problem::EV_SOLVE0], st));
 
     // g
     if (rhs_kind == LSP_RHS_INCIDENT) {
@@ -970,6 +1033,12 @@ lsp_status lsp_solve(lsp_problem* pb, int nrhs, int rhs_kind, const void* rhs, v
       k_gmres_control(true, nrhs, gs, gp, hv, ++pb->ctl_tag, st);
       nact = pb->wait_ctl(pb->ctl_tag);
     }
+    // every launch of the solve has completed (the last report is in)
+    LSP_HIP(hipEventRecord(pb->ev[lsp_problem::EV_SOLVE1], st));
+    LSP_HIP(hipEventSynchronize(pb->ev[lsp_problem::EV_SOLVE1]));
+    const double t_setup = pb->phase_ms(lsp_problem::EV_SETUP0, lsp_problem::EV_SETUP1, true);
+    const double t_factor = pb->phase_ms(lsp_problem::EV_FACTOR0, lsp_problem::EV_FACTOR1, pb->factor_timed);
+    const double t_solve = pb->phase_ms(lsp_problem::EV_SOLVE0, lsp_problem::EV_SOLVE1, true);
     const CtlView hh = lsp_problem::ctl_view(pb->ctl_host, pb->host_cap);
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
@@ -981,6 +1050,9 @@ lsp_status lsp_solve(lsp_problem* pb, int nrhs, int rhs_kind, const void* rhs, v
         info[r].converged = conv ? 1 : 0;
         info[r].relres_true = gnorm > 0 ? beta / gnorm : 0.0;
         info[r].relres_est = gnorm > 0 ? hh.est[r] / gnorm : 0.0;
+        info[r].t_setup = t_setup;
+        info[r].t_factor = t_factor;
+        info[r].t_solve = t_solve;
       }
     }
     if (!all) throw Error(LSP_ERR_NOCONV, "GMRES reached max_iters before the tolerance");

@@ -58,6 +58,14 @@ struct Plan {
   // Levels swept by the small-front kernels (not dense; at most two panels,
   // at most 160 rows, at most 128 rows below each front's first panel).
   std::vector<char> level_small_sweep;
+  // Small-front levels with formed operators (like level_dense, one product
+  // per front): more than 16 fronts of at most 64 pivots and 256 rows, in
+  // plans for blocks of right-hand sides (max_nrhs >= 4) unless
+  // dense_sweeps = 2; their operators follow the dense levels' in the same
+  // store (g_off).
+  std::vector<char> level_sdense;
+  int sdense_levels = 0;
+  double sdense_entries = 0.0;    // sum over their fronts of m p (one sweep's reads)
   // Levels swept by the blocked kernels (sweep.hip): not dense, not small,
   // and either fronts of more than 1024 rows or at most 32 fronts with more
   // than two panels.
@@ -68,6 +76,12 @@ struct Plan {
   long long bsweep_ystride = 0;   // per right-hand side: max over blocked
                                   // levels of fronts x max(SB, largest p)
   int bsweep_chunks = 0;          // max over blocked levels of boundary column chunks
+  double assemble_entries = 0.0;  // front entries the assembly writes plus the
+                                  // children's update-matrix entries it reads
+  double chain_entries = 0.0;     // factor entries one sweep reads on the panel-chain
+                                  // levels (neither dense nor blocked)
+  double blocked_panel_entries = 0.0;  // factor entries one sweep's products read on the
+                                       // blocked levels (outside the super-blocks' diagonal blocks)
   int nlevels = 0;
   long long front_elems = 0;      // sum (p+q)^2
   long long dinv_elems = 0;       // sum over panels of 2 nb^2

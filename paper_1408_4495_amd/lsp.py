@@ -33,7 +33,8 @@ class Options(ctypes.Structure):
 
 class RhsInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int),
-                ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double)]
+                ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double),
+                ("t_setup", ctypes.c_double), ("t_factor", ctypes.c_double), ("t_solve", ctypes.c_double)]
 
 
 class PlanStats(ctypes.Structure):
@@ -45,7 +46,10 @@ class PlanStats(ctypes.Structure):
                 ("panel_blocks", ctypes.c_double),
                 ("fused_blocks", ctypes.c_double), ("fused_update_flops", ctypes.c_double),
                 ("dense_entries", ctypes.c_double), ("dense_levels", ctypes.c_int),
-                ("blocked_levels", ctypes.c_int), ("blocked_entries", ctypes.c_double)]
+                ("blocked_levels", ctypes.c_int), ("blocked_entries", ctypes.c_double),
+                ("chain_entries", ctypes.c_double), ("blocked_panel_entries", ctypes.c_double),
+                ("trsm_flops", ctypes.c_double), ("assemble_entries", ctypes.c_double),
+                ("sdense_levels", ctypes.c_int), ("sdense_entries", ctypes.c_double)]
 
 
 class LspError(RuntimeError):
@@ -222,6 +226,7 @@ class Problem:
         self._h = h
         self.omega = float(omega)
         self.N = N
+        self._phases = {}
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -258,10 +263,19 @@ class Problem:
         k = LSP_RHS_INCIDENT if kind == "incident" else LSP_RHS_G
         st = _lib.lsp_solve(self._h, nrhs, k, _ptr(x), _ptr(u), _ptr(ws), ws.numel(), info)
         infos = [{"iters": i.iters, "converged": bool(i.converged), "relres_true": i.relres_true,
-                  "relres_est": i.relres_est} for i in info]
+                  "relres_est": i.relres_est, "t_setup": i.t_setup, "t_factor": i.t_factor,
+                  "t_solve": i.t_solve} for i in info]
+        if infos:
+            self._phases = {"setup": infos[0]["t_setup"], "factor": infos[0]["t_factor"],
+                            "solve": infos[0]["t_solve"]}
         if st != 0 and st != 6:
             _check(st)
         return u, infos, st
+
+    def phase_ms(self):
+        """Device milliseconds of set-up, the last factorisation and the last
+        solve (the library's HIP events on the problem's stream)."""
+        return dict(self._phases)
 
     def apply_op(self, x, precision=LSP_FP64):
         x = self._field(x)

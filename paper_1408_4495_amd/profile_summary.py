@@ -21,10 +21,11 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 SOURCE = {"fwd": "frontal.hip", "bwd": "frontal.hip", "diag_lu": "frontal.hip", "panel_trsm": "frontal.hip",
           "gemm_update": "frontal.hip", "update_lu": "frontal.hip", "assemble_front": "frontal.hip",
           "strip_first": "frontal.hip", "panel_step": "frontal.hip", "form_fwd": "frontal.hip",
-          "form_bwd": "frontal.hip",
+          "form_bwd": "frontal.hip", "bsweep": "sweep.hip",
           "fft_lines": "fft.hip",
           "gram": "stencil.hip", "gram_reduce": "stencil.hip", "eigen": "stencil.hip", "applyQ": "stencil.hip",
-          "dots_partial": "krylov.hip", "dots_final": "krylov.hip", "axpy": "krylov.hip"}
+          "dots_partial": "krylov.hip", "dots_final": "krylov.hip", "axpy": "krylov.hip", "cgs": "krylov.hip",
+          "scale_norm": "krylov.hip", "givens": "krylov.hip", "ktable": "greens.hip"}
 FFT_MODE = {"0": "fft_axis", "1": "fft_first", "2": "fft_conv", "3": "fft_last"}
 
 

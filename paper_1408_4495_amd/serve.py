@@ -91,9 +91,10 @@ class Server:
                 req.u = u.cpu().numpy()
             del pb, u, m, uI
 
-    def run(self, requests, realtime=True):
+    def run(self, requests, realtime=True, exclude_first=0):
         """Serve `requests` (arrival times in seconds from the start).  Returns
-        a report with per-request records and p50/p99 latency, solves/s."""
+        a report with p50/p99 latency and solves/s over the requests after the
+        first `exclude_first` by arrival (all of them are served)."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         for r in reqs:
             r.footprint = self.footprint(r)
@@ -151,11 +152,13 @@ class Server:
             th.join()
         if errors:
             raise RuntimeError(f"requests failed: {errors}")
-        makespan = max(r.finish for r in reqs) - t0
-        lat = np.array([r.finish - (t0 + r.arrival if realtime else r.admit) for r in reqs])
-        solves = sum(r.nrhs for r in reqs)
+        meas = reqs[exclude_first:] if exclude_first < len(reqs) else reqs
+        start = t0 + meas[0].arrival if realtime else min(r.admit for r in meas)
+        makespan = max(r.finish for r in meas) - start
+        lat = np.array([r.finish - (t0 + r.arrival if realtime else r.admit) for r in meas])
+        solves = sum(r.nrhs for r in meas)
         return {
-            "requests": len(reqs),
+            "requests": len(meas),
             "solves": solves,
             "makespan_s": makespan,
             "solves_per_s": solves / makespan,

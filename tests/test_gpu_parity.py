@@ -389,3 +389,23 @@ def test_blocked_batched_equals_solo_bitwise(prec):
     for r in (0, 9, 16):
         x1 = pb.solve_M(z[r:r + 1])
         assert torch.equal(x1[0], x_all[r])
+
+
+@pytest.mark.parametrize("n,d,prec,tol", [(128, 2, "fp64", 1e-12), (128, 2, "mixed", 2e-5),
+                                          (16, 3, "fp64", 1e-12), (16, 3, "mixed", 2e-5)])
+def test_small_dense_levels_match_panel_chains(n, d, prec, tol):
+    """Small-front levels swept with formed operators (plans for blocks of
+    right-hand sides: 2D n = 128 its six lowest levels, 3D n = 16 its two
+    lowest) give the panel chains' M^{-1} z up to rounding (FP64 1e-12,
+    complex64 2e-5); 5 right-hand sides (groups of 4 and 1)."""
+    omega = 2 * np.pi * n / 8
+    m = synth.medium_single_bump(n, d, 0.25, 0.12)
+    z = synth.random_complex((5, n ** d), seed=53)
+    out = []
+    for dense in (1, 0):
+        lsp, torch, plan, pb = _problem(n, d, omega, m, max_nrhs=5, precision=prec, dense_sweeps=dense)
+        assert (plan.stats()["sdense_levels"] > 0) == bool(dense)
+        pb.factor()
+        out.append(pb.solve_M(z).cpu().numpy())
+        del pb
+    assert _rel(out[0], out[1]) <= tol
