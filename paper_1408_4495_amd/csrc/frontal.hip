@@ -13,9 +13,9 @@
 //   2. U12 = L11^{-1} P F12 and L21 = F21 U11^{-1} as small dense products,
 //   3. trailing update F22 -= L21 U12 on MFMA (complex as four real products).
 // Pivoting is restricted to the panel's diagonal block (the paper leaves the
-// pivoting strategy open); each front records the smallest ratio
-// |u_jj| / max |column j of the block| it met, and the host rejects zero
-// pivots.  After the last panel F_BB holds the Schur complement S handed to
+// pivoting strategy open); each diagonal block records the smallest pivot
+// modulus |re| + |im| divided by the largest (NaN when a pivot is NaN), and
+// the host rejects the factorisation when the least ratio is tiny or NaN.  After the last panel F_BB holds the Schur complement S handed to
 // the parent.  Row swaps are not applied to columns left of a panel; the
 // forward solve applies each panel's permutation when it reaches the panel.
 // The kept inverses turn every panel step of the triangular solves into a
@@ -195,8 +195,11 @@ __device__ __forceinline__ void diag_elim(cplx<T> (&rowh)[NB / 2], int& rlog, cp
     const T rden = recip(d.x * d.x + d.y * d.y);
     const cplx<T> inv = mk<T>(d.x * rden, -d.y * rden);
     if (J < kb) {
+      // a NaN pivot makes dmin NaN for the rest of the block (fmin alone
+      // would skip it), so the block's ratio is NaN and the factorisation
+      // reports a singular pivot
       const T mag = cabs1(d);
-      dmin = fmin(dmin, mag);
+      dmin = (dmin != dmin || mag != mag) ? mag + dmin : fmin(dmin, mag);
       dmax = fmax(dmax, mag);
     }
     const bool upd = rlog < 0 && r != pl;

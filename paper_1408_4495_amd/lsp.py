@@ -212,15 +212,17 @@ class Problem:
         lib = load()
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         N = plan.n ** plan.d
-        m_t = torch.as_tensor(np.asarray(m, dtype=np.float64) if not isinstance(m, torch.Tensor) else m)
-        m_t = m_t.to(device=self.device, dtype=torch.float64).contiguous()
-        if m_t.numel() != N:
-            raise ValueError("medium has the wrong length")
-        pbytes, _ = plan.bytes(1)
-        self.ws = torch.empty(pbytes, dtype=torch.uint8, device=self.device)
-        self._solve_ws = None
-        h = ctypes.c_void_p()
-        with torch.cuda.device(self.device):
+        # every allocation below is made on the problem's stream, so torch's
+        # caching allocator reuses its memory only after that stream's work
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            m_t = torch.as_tensor(np.asarray(m, dtype=np.float64) if not isinstance(m, torch.Tensor) else m)
+            m_t = m_t.to(device=self.device, dtype=torch.float64).contiguous()
+            if m_t.numel() != N:
+                raise ValueError("medium has the wrong length")
+            pbytes, _ = plan.bytes(1)
+            self.ws = torch.empty(pbytes, dtype=torch.uint8, device=self.device)
+            self._solve_ws = None
+            h = ctypes.c_void_p()
             _check(lib.lsp_setup(plan._h, float(omega), _ptr(m_t), _ptr(self.ws), pbytes,
                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h
@@ -234,6 +236,25 @@ class Problem:
             self._h = None
 
     # -- helpers
+    def _ctx(self):
+        """Device and stream context of the problem: tensors created inside
+        belong to the problem's stream."""
+        import contextlib
+        stack = contextlib.ExitStack()
+        stack.enter_context(self.torch.cuda.device(self.device))
+        stack.enter_context(self.torch.cuda.stream(self.stream))
+        return stack
+
+    def _handoff(self, *ts):
+        """Make the caller's current stream wait for the problem's stream
+        before it uses the returned tensors."""
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            ev = self.torch.cuda.Event()
+            ev.record(self.stream)
+            cur.wait_event(ev)
+        return ts[0] if len(ts) == 1 else ts
+
     def _work(self, nrhs):
         _, sb = self.plan.bytes(nrhs)
         if self._solve_ws is None or self._solve_ws.numel() < sb:
@@ -255,13 +276,14 @@ class Problem:
         _check(_lib.lsp_factor(self._h))
 
     def solve(self, rhs, kind="incident"):
-        x = self._field(rhs)
-        nrhs = x.shape[0]
-        u = self.torch.empty_like(x)
-        ws = self._work(nrhs)
-        info = (RhsInfo * nrhs)()
-        k = LSP_RHS_INCIDENT if kind == "incident" else LSP_RHS_G
-        st = _lib.lsp_solve(self._h, nrhs, k, _ptr(x), _ptr(u), _ptr(ws), ws.numel(), info)
+        with self._ctx():
+            x = self._field(rhs)
+            nrhs = x.shape[0]
+            u = self.torch.empty_like(x)
+            ws = self._work(nrhs)
+            info = (RhsInfo * nrhs)()
+            k = LSP_RHS_INCIDENT if kind == "incident" else LSP_RHS_G
+            st = _lib.lsp_solve(self._h, nrhs, k, _ptr(x), _ptr(u), _ptr(ws), ws.numel(), info)
         infos = [{"iters": i.iters, "converged": bool(i.converged), "relres_true": i.relres_true,
                   "relres_est": i.relres_est, "t_setup": i.t_setup, "t_factor": i.t_factor,
                   "t_solve": i.t_solve} for i in info]
@@ -278,51 +300,58 @@ class Problem:
         return dict(self._phases)
 
     def apply_op(self, x, precision=LSP_FP64):
-        x = self._field(x)
-        y = self.torch.empty_like(x)
-        ws = self._work(x.shape[0])
-        _check(_lib.lsp_apply_op(self._h, x.shape[0], precision, _ptr(x), _ptr(y), _ptr(ws), ws.numel()))
-        return y
+        with self._ctx():
+            x = self._field(x)
+            y = self.torch.empty_like(x)
+            ws = self._work(x.shape[0])
+            _check(_lib.lsp_apply_op(self._h, x.shape[0], precision, _ptr(x), _ptr(y), _ptr(ws), ws.numel()))
+        return self._handoff(y)
 
     def apply_op_noalloc(self, x, precision=LSP_FP64):
         """y = x + K(w^2 m x) with the library's static scratch (no workspace)."""
-        x = self._field(x)
-        y = self.torch.empty_like(x)
-        _check(_lib.lsp_apply_op_noalloc(self._h, x.shape[0], precision, _ptr(x), _ptr(y)))
-        return y
+        with self._ctx():
+            x = self._field(x)
+            y = self.torch.empty_like(x)
+            _check(_lib.lsp_apply_op_noalloc(self._h, x.shape[0], precision, _ptr(x), _ptr(y)))
+        return self._handoff(y)
 
     def apply_K(self, x, precision=LSP_FP64):
-        x = self._field(x)
-        y = self.torch.empty_like(x)
-        ws = self._work(x.shape[0])
-        _check(_lib.lsp_apply_K(self._h, x.shape[0], precision, _ptr(x), _ptr(y), _ptr(ws), ws.numel()))
-        return y
+        with self._ctx():
+            x = self._field(x)
+            y = self.torch.empty_like(x)
+            ws = self._work(x.shape[0])
+            _check(_lib.lsp_apply_K(self._h, x.shape[0], precision, _ptr(x), _ptr(y), _ptr(ws), ws.numel()))
+        return self._handoff(y)
 
     def apply_Q(self, x):
-        x = self._field(x)
-        y = self.torch.empty_like(x)
-        _check(_lib.lsp_apply_Q(self._h, x.shape[0], _ptr(x), _ptr(y)))
-        return y
+        with self._ctx():
+            x = self._field(x)
+            y = self.torch.empty_like(x)
+            _check(_lib.lsp_apply_Q(self._h, x.shape[0], _ptr(x), _ptr(y)))
+        return self._handoff(y)
 
     def solve_M(self, z):
-        z = self._field(z)
-        x = self.torch.empty_like(z)
-        ws = self._work(z.shape[0])
-        _check(_lib.lsp_solve_M(self._h, z.shape[0], _ptr(z), _ptr(x), _ptr(ws), ws.numel()))
-        return x
+        with self._ctx():
+            z = self._field(z)
+            x = self.torch.empty_like(z)
+            ws = self._work(z.shape[0])
+            _check(_lib.lsp_solve_M(self._h, z.shape[0], _ptr(z), _ptr(x), _ptr(ws), ws.numel()))
+        return self._handoff(x)
 
     def apply_precond(self, v):
-        v = self._field(v)
-        x = self.torch.empty_like(v)
-        ws = self._work(v.shape[0])
-        _check(_lib.lsp_apply_precond(self._h, v.shape[0], _ptr(v), _ptr(x), _ptr(ws), ws.numel()))
-        return x
+        with self._ctx():
+            v = self._field(v)
+            x = self.torch.empty_like(v)
+            ws = self._work(v.shape[0])
+            _check(_lib.lsp_apply_precond(self._h, v.shape[0], _ptr(v), _ptr(x), _ptr(ws), ws.numel()))
+        return self._handoff(x)
 
     def kernel_table(self):
         t = self.torch
-        k = t.empty((self.plan.n + 1) ** self.plan.d, dtype=t.complex128, device=self.device)
-        _check(_lib.lsp_get_kernel_table(self._h, _ptr(k)))
-        return k
+        with self._ctx():
+            k = t.empty((self.plan.n + 1) ** self.plan.d, dtype=t.complex128, device=self.device)
+            _check(_lib.lsp_get_kernel_table(self._h, _ptr(k)))
+        return self._handoff(k)
 
     def stencils(self):
         nc = 3 ** self.plan.d
@@ -337,6 +366,7 @@ class Problem:
     def matrix(self):
         t = self.torch
         ns = 3 ** self.plan.d
-        M = t.empty((self.N, ns), dtype=t.complex128, device=self.device)
-        _check(_lib.lsp_get_matrix(self._h, _ptr(M)))
-        return M
+        with self._ctx():
+            M = t.empty((self.N, ns), dtype=t.complex128, device=self.device)
+            _check(_lib.lsp_get_matrix(self._h, _ptr(M)))
+        return self._handoff(M)
