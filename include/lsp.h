@@ -96,6 +96,20 @@ typedef struct {
                         level that is neither swept densely nor by the
                         small-front kernels; 0: the panel chain of one
                         workgroup per front */
+  int self_term;     /* k_0, the kernel table's self term (Section 2.1 uses a
+                        local quadrature correction it does not print):
+                        0 (default): the integral of G over the disk (2D) /
+                        ball (3D) of one cell's area / volume; 1: the
+                        integral of G over the grid cell itself (square /
+                        cube of side h), by Gauss-Legendre quadrature of
+                        its closed-form radial integral */
+  const char* tile_cache; /* NULL (default), or a text file of tuned
+                        trailing-update tile tables, one line per
+                        (n, d, precision): lsp_plan_create takes the tiles
+                        from the line of its (n, d, precision) when the file
+                        has one with the plan's level count (a missing file
+                        or malformed line is ignored); the string is read
+                        during lsp_plan_create only */
 } lsp_options;
 
 typedef struct {
@@ -197,6 +211,12 @@ lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* stats);
  * else LSP_ERR_ARG.  Not thread-safe against a concurrent lsp_factor. */
 lsp_status lsp_plan_get_tiles(const lsp_plan* plan, int* tiles, int cap);
 lsp_status lsp_plan_set_tiles(lsp_plan* plan, const int* tiles, int n);
+/* Writes the plan's tile table to the cache file `path` (the format
+ * lsp_options.tile_cache reads: "n d precision nlevels t_0 ... t_{L-1}"),
+ * replacing the line of the same (n, d, precision) and keeping the others;
+ * the file is rewritten through a temporary and renamed.  LSP_ERR_ARG on a
+ * null argument or when the file cannot be written. */
+lsp_status lsp_plan_save_tiles(const lsp_plan* plan, const char* path);
 
 /* Device bytes the caller must provide: *problem_bytes for lsp_setup (kernel
  * table, spectrum, stencils, matrix M, frontal factors),

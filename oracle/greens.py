@@ -11,6 +11,8 @@ Section 2.1 discretises the convolution with the trapezoid rule on the grid:
   and the antiderivative of r exp(i w r)):
     2D: k_0 = (i pi rho / (2 w)) H1^(1)(w rho) - 1/w^2
     3D: k_0 = (exp(i w rho)(1 - i w rho) - 1) / w^2
+  A second option (self_term 1) is the integral of G over the cell itself,
+  computed here by plain adaptive quadrature of that definition.
 """
 import numpy as np
 import scipy.special as sp
@@ -33,15 +35,40 @@ def self_radius(h, d):
     return h * (3.0 / (4.0 * np.pi)) ** (1.0 / 3.0)
 
 
-def self_term(h, omega, d):
-    """k_0: integral of G over the equal-measure disk/ball (reading above)."""
+def self_term(h, omega, d, mode=0):
+    """k_0 (Section 2.1's local correction; its value is not printed).
+    mode 0: integral of G over the equal-measure disk/ball (reading above);
+    mode 1: integral of G over the grid cell [-h/2, h/2]^d itself."""
+    if mode == 1:
+        return cell_self_term(h, omega, d)
     rho = self_radius(h, d)
     if d == 2:
         return 1j * np.pi * rho / (2.0 * omega) * sp.hankel1(1, omega * rho) - 1.0 / omega ** 2
     return (np.exp(1j * omega * rho) * (1.0 - 1j * omega * rho) - 1.0) / omega ** 2
 
 
-def kernel_table(n, d, omega):
+def cell_self_term(h, omega, d):
+    """Integral of G over the cell [-h/2, h/2]^d, by adaptive Cartesian
+    quadrature over the positive quadrant / octant (G is even in every axis),
+    real and imaginary parts separately; the singularity of G sits at the
+    integration region's corner."""
+    from scipy import integrate
+    a = 0.5 * h
+    if d == 2:
+        def part(fn):
+            val, _ = integrate.dblquad(lambda y, x: fn(green(np.hypot(x, y), omega, 2)), 0.0, a, 0.0, a,
+                                       epsabs=1e-16 * h * h, epsrel=1e-12)
+            return val
+        return 4.0 * (part(np.real) + 1j * part(np.imag))
+
+    def part3(fn):
+        val, _ = integrate.tplquad(lambda z, y, x: fn(green(np.sqrt(x * x + y * y + z * z), omega, 3)),
+                                   0.0, a, 0.0, a, 0.0, a, epsabs=1e-16 * h * h, epsrel=1e-11)
+        return val
+    return 8.0 * (part3(np.real) + 1j * part3(np.imag))
+
+
+def kernel_table(n, d, omega, self_term_mode=0):
     """k_t for t in [0, n]^d (absolute offsets per axis), shape (n+1,)*d.
 
     k depends on |t| only, so the table is symmetric under any permutation
@@ -53,5 +80,5 @@ def kernel_table(n, d, omega):
     k = np.empty(r.shape, dtype=np.complex128)
     nz = r > 0
     k[nz] = green(r[nz], omega, d) * h ** d
-    k[(0,) * d] = self_term(h, omega, d)
+    k[(0,) * d] = self_term(h, omega, d, self_term_mode)
     return k

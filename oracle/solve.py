@@ -9,10 +9,10 @@ from .gmres import gmres
 
 
 class OracleProblem:
-    def __init__(self, n, d, omega, m, b=2):
+    def __init__(self, n, d, omega, m, b=2, self_term=0):
         self.n, self.d, self.omega, self.b = n, d, float(omega), b
         self.m = np.asarray(m, dtype=np.float64)
-        self.ktab = kernel_table(n, d, omega)
+        self.ktab = kernel_table(n, d, omega, self_term)
         self.op = Operator(n, d, omega, self.m, self.ktab)
         self.stencils = all_stencils(self.ktab, d, n, b)
         self.Q, self.M = build_QM(n, d, omega, self.m, self.stencils)

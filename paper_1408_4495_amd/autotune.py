@@ -29,8 +29,10 @@ def _time_factor(torch, pb, reps):
     return statistics.median(ts)
 
 
-def tune_tiles(n, d, precision="mixed", omega=None, m=None, reps=3, device="cuda:0", log=None):
-    """Return {"tiles": [...], "factor_ms": best, "uniform_ms": {...}, "trials": k}."""
+def tune_tiles(n, d, precision="mixed", omega=None, m=None, reps=3, device="cuda:0", log=None, cache=None):
+    """Return {"tiles": [...], "factor_ms": best, "uniform_ms": {...}, "trials": k};
+    with `cache` (a file path) the table is also written there, where plans
+    created with tile_cache=path pick it up."""
     import torch
     omega = 2 * np.pi * n / 8 if omega is None else omega
     if m is None:
@@ -65,6 +67,8 @@ def tune_tiles(n, d, precision="mixed", omega=None, m=None, reps=3, device="cuda
         if log:
             log(f"[autotune] n={n} d={d} level {level}: tiles {best} {1e3 * best_time:.3f} ms")
     plan.set_tiles(best)
+    if cache is not None:
+        plan.save_tiles(cache)
     return {"tiles": best, "factor_ms": 1e3 * best_time,
             "uniform_ms": {str(k): 1e3 * v for k, v in uniform.items()}, "trials": trials}
 
@@ -77,8 +81,9 @@ def main():
     ap.add_argument("--d", type=int, default=2)
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--cache", default=None, help="tile cache file to write the table to")
     args = ap.parse_args()
-    print(json.dumps(tune_tiles(args.n, args.d, args.precision, reps=args.reps)))
+    print(json.dumps(tune_tiles(args.n, args.d, args.precision, reps=args.reps, cache=args.cache)))
 
 
 if __name__ == "__main__":

@@ -662,16 +662,21 @@ __device__ __forceinline__ void update_tile(GemmLds<T, TM>& G, cplx<T>* __restri
     for (int j = 0; j < BW; ++j)
       for (int v = 0; v < 4; ++v) { accr[i][j][v] = 0; acci[i][j][v] = 0; }
   const int li = lane % 16, lk = lane / 16;
+  // Each 16 x 16 block is computed transposed (the MFMA's first operand is
+  // B's column block, its second A's row block): the result lane l then
+  // holds C rows 16 i + l % 16, so consecutive lanes address consecutive
+  // rows of the column-major front and every load / store of C below covers
+  // whole cache lines.
   for (int k4 = 0; k4 < kpad; k4 += 4) {
     T ar[BW], ai[BW], br[BW], bi[BW];
     for (int i = 0; i < BW; ++i) { ar[i] = Ar[k4 + lk][wr + 16 * i + li]; ai[i] = Ai[k4 + lk][wr + 16 * i + li]; }
     for (int j = 0; j < BW; ++j) { br[j] = Br[k4 + lk][wc + 16 * j + li]; bi[j] = Bi[k4 + lk][wc + 16 * j + li]; }
     for (int i = 0; i < BW; ++i)
       for (int j = 0; j < BW; ++j) {
-        accr[i][j] = Mfma<T>::step(ar[i], br[j], accr[i][j]);
-        accr[i][j] = Mfma<T>::step(-ai[i], bi[j], accr[i][j]);
-        acci[i][j] = Mfma<T>::step(ar[i], bi[j], acci[i][j]);
-        acci[i][j] = Mfma<T>::step(ai[i], br[j], acci[i][j]);
+        accr[i][j] = Mfma<T>::step(br[j], ar[i], accr[i][j]);
+        accr[i][j] = Mfma<T>::step(bi[j], -ai[i], accr[i][j]);
+        acci[i][j] = Mfma<T>::step(bi[j], ar[i], acci[i][j]);
+        acci[i][j] = Mfma<T>::step(br[j], ai[i], acci[i][j]);
       }
   }
   // C -= A B: per 16-row block i, all BW x 4 loads of C first, then the stores
@@ -682,16 +687,16 @@ __device__ __forceinline__ void update_tile(GemmLds<T, TM>& G, cplx<T>* __restri
     for (int j = 0; j < BW; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int col = min(col0 + wc + 16 * j + li, rem - 1);
-        const int row = min(row0 + wr + 16 * i + Mfma<T>::row(lk, v), rem - 1);
+        const int col = min(col0 + wc + 16 * j + Mfma<T>::row(lk, v), rem - 1);
+        const int row = min(row0 + wr + 16 * i + li, rem - 1);
         cv[j][v] = F[(base + row) + (long long)(base + col) * m];
       }
 #pragma unroll
     for (int j = 0; j < BW; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int col = col0 + wc + 16 * j + li;
-        const int row = row0 + wr + 16 * i + Mfma<T>::row(lk, v);
+        const int col = col0 + wc + 16 * j + Mfma<T>::row(lk, v);
+        const int row = row0 + wr + 16 * i + li;
         if (col < rem && row < rem && !(row < skip && col < skip)) {
           cplx<T> c = cv[j][v];
           c.x -= accr[i][j][v];

@@ -7,7 +7,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <memory>
 #include <new>
 #include <string>
@@ -525,8 +528,68 @@ void build_class_geometry(lsp_plan* pl) {
   pl->gram_blocks = (int)std::max<long long>(1, std::min<long long>(nb, 512));
 }
 
-double2 self_term_host(double h, double omega, int d) {
+// Gauss-Legendre nodes and weights on [0, 1] (Newton iteration on the
+// Legendre recurrence from the Chebyshev-like initial guesses).
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
   const double pi = 3.14159265358979323846;
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp);  // 2 / ((1 - z^2) P'^2), halved for [0, 1]
+  }
+}
+
+// k_0 as the integral of G over the grid cell [-h/2, h/2]^d.  Over the part
+// of the cell seen through a face (an edge in 2D) at distance h/2, the radial
+// integral has a closed form at each distance rho = |(h/2, y[, z])| to the
+// face: 2D int_0^rho G r dr = i rho H1(w rho) / (4 w) - 1 / (2 pi w^2),
+// 3D (e^{i w rho}(1 - i w rho) - 1) / (4 pi w^2); the solid-angle element
+// is (h/2) / rho^d, and the 4 edges x 2 halves (2D) / 6 faces x 4 quarters
+// (3D) are equal by symmetry.  Gauss-Legendre on the smooth rest.
+double2 cell_self_term(double h, double omega, int d) {
+  const double pi = 3.14159265358979323846, a = 0.5 * h;
+  std::vector<double> x, w;
+  gauss_legendre01(32, x, w);
+  double re = 0.0, im = 0.0;
+  if (d == 2) {
+    for (size_t i = 0; i < x.size(); ++i) {
+      const double y = a * x[i], rho = std::sqrt(a * a + y * y), z = omega * rho;
+      const double j1 = std::cyl_bessel_j(1.0, z), y1 = std::cyl_neumann(1.0, z);
+      const double jac = a / (rho * rho) * a * w[i];
+      re += (-rho * y1 / (4.0 * omega) - 1.0 / (2.0 * pi * omega * omega)) * jac;
+      im += rho * j1 / (4.0 * omega) * jac;
+    }
+    return make_double2(8.0 * re, 8.0 * im);
+  }
+  for (size_t i = 0; i < x.size(); ++i)
+    for (size_t j = 0; j < x.size(); ++j) {
+      const double y = a * x[i], zz = a * x[j];
+      const double rho = std::sqrt(a * a + y * y + zz * zz), t = omega * rho;
+      const double c = std::cos(t), sn = std::sin(t);
+      const double jac = a / (rho * rho * rho) * a * a * w[i] * w[j] / (4.0 * pi * omega * omega);
+      re += (c + t * sn - 1.0) * jac;
+      im += (sn - t * c) * jac;
+    }
+  return make_double2(24.0 * re, 24.0 * im);
+}
+
+double2 self_term_host(double h, double omega, int d, int mode) {
+  const double pi = 3.14159265358979323846;
+  if (mode == 1) return cell_self_term(h, omega, d);
   if (d == 2) {
     double rho = h / std::sqrt(pi);
     double z = omega * rho;
@@ -541,6 +604,28 @@ double2 self_term_host(double h, double omega, int d) {
   // (e^{iz}(1 - iz) - 1) / w^2
   double re = c + z * sn - 1.0, im = sn - z * c;
   return make_double2(re / (omega * omega), im / (omega * omega));
+}
+
+// The tile table of (n, d, precision) from a cache file written by
+// lsp_plan_save_tiles; false when absent, malformed or of another level count.
+bool read_tile_line(const std::string& path, const Plan& P, std::vector<int>& tiles) {
+  std::ifstream in(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(in, line)) {
+    std::istringstream ss(line);
+    int n = 0, d = 0, prec = -1, nl = 0;
+    if (!(ss >> n >> d >> prec >> nl)) continue;
+    if (n != P.n || d != P.d || prec != P.opts.precision || nl != P.nlevels) continue;
+    std::vector<int> t(nl);
+    bool ok = true;
+    for (int l = 0; l < nl && ok; ++l) ok = (ss >> t[l]) && (t[l] == 32 || t[l] == 64 || t[l] == 128);
+    if (ok) {
+      tiles = t;
+      found = true;
+    }
+  }
+  return found;
 }
 
 template <typename T>
@@ -667,6 +752,8 @@ lsp_status lsp_options_default(lsp_options* o) {
   o->panel = 0;
   o->dense_sweeps = 1;
   o->blocked_sweeps = 1;
+  o->self_term = 0;
+  o->tile_cache = nullptr;
   return LSP_OK;
 }
 
@@ -683,10 +770,17 @@ lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts, 
     LSP_REQUIRE(o.panel == 0 || o.panel == kNbMax, "panel must be 0 (auto) or 32");
     LSP_REQUIRE(o.dense_sweeps >= 0 && o.dense_sweeps <= 2, "dense_sweeps must be 0, 1 or 2");
     LSP_REQUIRE(o.blocked_sweeps >= 0 && o.blocked_sweeps <= 2, "blocked_sweeps must be 0, 1 or 2");
+    LSP_REQUIRE(o.self_term == 0 || o.self_term == 1, "self_term must be 0 or 1");
+    const std::string cache = o.tile_cache ? o.tile_cache : "";
+    o.tile_cache = nullptr;  // the plan keeps no pointer into the caller's memory
     std::unique_ptr<lsp_plan> pl(new lsp_plan());
     build_plan(pl->p, n, d, max_nrhs, o);
     fix_radices(pl->p);
     build_class_geometry(pl.get());
+    if (!cache.empty()) {
+      std::vector<int> t;
+      if (read_tile_line(cache, pl->p, t)) pl->p.level_tile = t;
+    }
     *out = pl.release();
     return LSP_OK;
   });
@@ -741,6 +835,37 @@ lsp_status lsp_plan_set_tiles(lsp_plan* plan, const int* tiles, int n) {
   return LSP_OK;
 }
 
+lsp_status lsp_plan_save_tiles(const lsp_plan* plan, const char* path) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(plan != nullptr && path != nullptr, "null argument");
+    const Plan& P = plan->p;
+    std::vector<std::string> keep;
+    {
+      std::ifstream in(path);
+      std::string line;
+      while (std::getline(in, line)) {
+        std::istringstream ss(line);
+        int n = 0, d = 0, prec = -1;
+        if (ss >> n >> d >> prec && n == P.n && d == P.d && prec == P.opts.precision) continue;
+        if (!line.empty()) keep.push_back(line);
+      }
+    }
+    std::ostringstream mine;
+    mine << P.n << ' ' << P.d << ' ' << P.opts.precision << ' ' << P.nlevels;
+    for (int t : P.level_tile) mine << ' ' << t;
+    keep.push_back(mine.str());
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+      std::ofstream out(tmp, std::ios::trunc);
+      for (const auto& l : keep) out << l << '\n';
+      out.flush();
+      LSP_REQUIRE(out.good(), std::string("cannot write the tile cache ") + tmp);
+    }
+    LSP_REQUIRE(std::rename(tmp.c_str(), path) == 0, std::string("cannot replace the tile cache ") + path);
+    return LSP_OK;
+  });
+}
+
 lsp_status lsp_plan_bytes(const lsp_plan* plan, int precision, int nrhs, size_t* problem_bytes, size_t* solve_bytes) {
   return guarded([&]() -> lsp_status {
     LSP_REQUIRE(plan != nullptr, "null plan");
@@ -790,7 +915,7 @@ lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, vo
 
     // kernel table, medium, spectrum
     double h = 1.0 / P.n;
-    launch_ktable(pb->d.ktab, P.n, P.d, omega, self_term_host(h, omega, P.d), st);
+    launch_ktable(pb->d.ktab, P.n, P.d, omega, self_term_host(h, omega, P.d, P.opts.self_term), st);
     k_w2m(pb->d.w2m, m_dev, omega * omega, P.N, st);
     launch_embed(pb->d.E, pb->d.ktab, P.n, P.d, st);
     full_fft_forward<double>(pb->fp64, pb->d.E, st);

@@ -22,13 +22,14 @@ EXPORTED = ["lsp_options_default", "lsp_plan_create", "lsp_plan_destroy", "lsp_p
             "lsp_apply_op", "lsp_apply_K", "lsp_apply_Q", "lsp_solve_M", "lsp_apply_precond",
             "lsp_get_kernel_table", "lsp_get_stencils", "lsp_get_matrix", "lsp_status_string",
             "lsp_last_error", "lsp_timing_enable", "lsp_timing_reset", "lsp_timing_count",
-            "lsp_timing_get", "lsp_plan_get_tiles", "lsp_plan_set_tiles", "lsp_apply_op_noalloc"]
+            "lsp_timing_get", "lsp_plan_get_tiles", "lsp_plan_set_tiles", "lsp_apply_op_noalloc", "lsp_plan_save_tiles"]
 
 
 class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
                 ("precision", ctypes.c_int), ("buffer_b", ctypes.c_int), ("leaf", ctypes.c_int),
-                ("panel", ctypes.c_int), ("dense_sweeps", ctypes.c_int), ("blocked_sweeps", ctypes.c_int)]
+                ("panel", ctypes.c_int), ("dense_sweeps", ctypes.c_int), ("blocked_sweeps", ctypes.c_int),
+                ("self_term", ctypes.c_int), ("tile_cache", ctypes.c_char_p)]
 
 
 class RhsInfo(ctypes.Structure):
@@ -89,6 +90,7 @@ def load():
         "lsp_get_matrix": [vp, vp],
         "lsp_plan_get_tiles": [vp, ctypes.POINTER(ci), ci],
         "lsp_plan_set_tiles": [vp, ctypes.POINTER(ci), ci],
+        "lsp_plan_save_tiles": [vp, ctypes.c_char_p],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -154,7 +156,8 @@ class Plan:
     """Symbolic plan for an n^d grid (host-side nested dissection)."""
 
     def __init__(self, n, d, max_nrhs=1, tol=1e-8, restart=30, max_iters=1000, precision="fp64",
-                 buffer_b=2, leaf=0, panel=0, dense_sweeps=1, blocked_sweeps=1):
+                 buffer_b=2, leaf=0, panel=0, dense_sweeps=1, blocked_sweeps=1, self_term=0,
+                 tile_cache=None):
         lib = load()
         o = Options()
         _check(lib.lsp_options_default(ctypes.byref(o)))
@@ -162,6 +165,8 @@ class Plan:
         o.precision = LSP_MIXED if precision in ("mixed", LSP_MIXED) else LSP_FP64
         o.buffer_b, o.leaf, o.panel, o.dense_sweeps = buffer_b, leaf, panel, dense_sweeps
         o.blocked_sweeps = blocked_sweeps
+        o.self_term = self_term
+        o.tile_cache = None if tile_cache is None else os.fsencode(tile_cache)
         self.opts = o
         self.n, self.d, self.max_nrhs = n, d, max_nrhs
         self.precision = o.precision
@@ -184,6 +189,10 @@ class Plan:
     def set_tiles(self, tiles):
         arr = (ctypes.c_int * len(tiles))(*tiles)
         _check(_lib.lsp_plan_set_tiles(self._h, arr, len(tiles)))
+
+    def save_tiles(self, path):
+        """Write this plan's tile table to the cache file `path`."""
+        _check(_lib.lsp_plan_save_tiles(self._h, os.fsencode(path)))
 
     def stats(self):
         s = PlanStats()

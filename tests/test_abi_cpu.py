@@ -174,3 +174,48 @@ def test_lookahead_schedule_stats(lib):
     # factored by the strip launches
     q = L.Plan(8, 2, precision="mixed").stats()
     assert q["fused_blocks"] == 2 and q["fused_update_flops"] == q["update_flops"]
+
+
+def test_tile_cache_round_trip(lib, tmp_path):
+    """A tile table written with lsp_plan_save_tiles is picked up by plans of
+    the same (n, d, precision) created with tile_cache; other keys keep their
+    default, saving again replaces the line, and malformed lines and a
+    missing file are ignored."""
+    path = str(tmp_path / "tiles.txt")
+    p = L.Plan(64, 2, precision="mixed")
+    default = p.tiles()
+    tuned = [32 if i % 2 else 128 for i in range(len(default))]
+    p.set_tiles(tuned)
+    p.save_tiles(path)
+    assert L.Plan(64, 2, precision="mixed", tile_cache=path).tiles() == tuned
+    assert L.Plan(64, 2, precision="fp64", tile_cache=path).tiles() == L.Plan(64, 2, precision="fp64").tiles()
+    assert L.Plan(32, 2, precision="mixed", tile_cache=path).tiles() == L.Plan(32, 2, precision="mixed").tiles()
+    q = L.Plan(32, 2, precision="mixed")
+    q.set_tiles([64] * len(q.tiles()))
+    q.save_tiles(path)
+    p.set_tiles(default)
+    p.save_tiles(path)          # replaces the (64, 2, mixed) line
+    lines = open(path).read().splitlines()
+    assert len(lines) == 2
+    assert L.Plan(64, 2, precision="mixed", tile_cache=path).tiles() == default
+    assert L.Plan(32, 2, precision="mixed", tile_cache=path).tiles() == [64] * len(q.tiles())
+    with open(path, "a") as f:
+        f.write("64 2 1 not numbers\n")
+    assert L.Plan(64, 2, precision="mixed", tile_cache=path).tiles() == default
+    assert L.Plan(64, 2, precision="mixed", tile_cache=str(tmp_path / "absent.txt")).tiles() == default
+
+
+def test_default_tiles_by_precision(lib):
+    """Default trailing-update tiles: complex128 factors 32 on every level,
+    complex64 ones 32 up to 160 rows and 64 above."""
+    p64 = L.Plan(1024, 2, precision="fp64")
+    assert set(p64.tiles()) == {32}
+    pm = L.Plan(1024, 2, precision="mixed")
+    t = pm.tiles()
+    assert t[0] == 32 and t[-1] == 64 and set(t) == {32, 64}
+
+
+def test_self_term_option_validated(lib):
+    with pytest.raises(L.LspError):
+        L.Plan(32, 2, self_term=2)
+    L.Plan(32, 2, self_term=1)

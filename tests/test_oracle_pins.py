@@ -393,3 +393,61 @@ def test_golden_c1_regression():
     assert abs(kt[0, 0] - complex(*ref["k0"])) < 1e-15
     u = res.x
     assert abs(np.linalg.norm(u) - ref["u_norm"]) < 1e-8 * ref["u_norm"]
+
+
+# ---- the cell self-term (self_term option 1)
+
+def test_cell_self_term_laplace_limit_3d():
+    """3D: as w -> 0 the cell integral of G tends to the Laplace one,
+    h^2 (3 ln(2 + sqrt 3) - pi/2) / (4 pi) (the integral of 1/|x| over the
+    unit cube), plus i w h^3 / (4 pi) from G's expansion; the next term is
+    O(w^2 h^4)."""
+    from oracle.greens import cell_self_term
+    h, w = 1.0 / 32, 1e-3
+    k0 = cell_self_term(h, w, 3)
+    c3 = 3 * np.log(2 + np.sqrt(3)) - np.pi / 2
+    assert abs(k0.real - h * h * c3 / (4 * np.pi)) <= 1e-9 * h * h
+    assert abs(k0.imag - w * h ** 3 / (4 * np.pi)) <= 1e-9 * h ** 3 * w
+
+
+def test_cell_self_term_small_frequency_2d():
+    """2D: for small w h, G = -(ln(w r / 2) + gamma) / (2 pi) + i/4 + O((w r)^2 log),
+    so the cell integral is h^2 [i/4 - (ln(w h / 2) + gamma) / (2 pi)]
+    - h^2 J / (2 pi) with J = int over [-1/2, 1/2]^2 of ln|x| =
+    (ln 2 - 3 + pi/2) / 2 - ln 2 (from int_0^1 int_0^1 ln(x^2 + y^2) =
+    ln 2 - 3 + pi/2)."""
+    from oracle.greens import cell_self_term
+    h, w = 1.0 / 32, 1e-2
+    k0 = cell_self_term(h, w, 2)
+    J = (np.log(2) - 3 + np.pi / 2) / 2 - np.log(2)
+    ref = h * h * (0.25j - (np.log(w * h / 2) + np.euler_gamma) / (2 * np.pi)) - h * h * J / (2 * np.pi)
+    assert abs(k0 - ref) <= 1e-6 * abs(ref)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_cell_self_term_face_form(d):
+    """The oracle's Cartesian quadrature of G over the cell against the
+    same integral taken through the cell's faces: radial integral in closed
+    form at each face point, solid-angle element (h/2)/rho^d, 1D/2D adaptive
+    quadrature over the face (agreement 1e-9 relative)."""
+    from scipy import integrate, special
+    from oracle.greens import cell_self_term
+    n = 32
+    h, w = 1.0 / n, 2 * np.pi * n / 8
+    a = h / 2
+    if d == 2:
+        def f(y, part):
+            rho = np.hypot(a, y)
+            v = 1j * rho * special.hankel1(1, w * rho) / (4 * w) - 1 / (2 * np.pi * w * w)
+            return part(v * a / rho ** 2)
+        ref = 8 * (integrate.quad(f, 0, a, args=(np.real,), epsabs=1e-18)[0]
+                   + 1j * integrate.quad(f, 0, a, args=(np.imag,), epsabs=1e-18)[0])
+    else:
+        def f(z, y, part):
+            rho = np.sqrt(a * a + y * y + z * z)
+            v = (np.exp(1j * w * rho) * (1 - 1j * w * rho) - 1) / (4 * np.pi * w * w)
+            return part(v * a / rho ** 3)
+        ref = 24 * (integrate.dblquad(f, 0, a, 0, a, args=(np.real,), epsabs=1e-18)[0]
+                    + 1j * integrate.dblquad(f, 0, a, 0, a, args=(np.imag,), epsabs=1e-18)[0])
+    k0 = cell_self_term(h, w, d)
+    assert abs(k0 - ref) <= 1e-9 * abs(ref)
