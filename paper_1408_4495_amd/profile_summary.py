@@ -2,6 +2,8 @@
 
     python -m paper_1408_4495_amd.profile_summary stats <kernel_stats.csv> <title> <command>
         per-kernel time table (markdown) from a --kernel-trace --stats run;
+    python -m paper_1408_4495_amd.profile_summary counters <counter_collection.csv> <kernel_trace.csv> <title> <cmd>
+        per-kernel counter means (duration-weighted) and sums from one --pmc run;
     python -m paper_1408_4495_amd.profile_summary traffic <fetch.csv> <write.csv> <title> <cmd_fetch> <cmd_write>
         per-kernel HBM bytes from two --pmc runs (FETCH_SIZE, then WRITE_SIZE,
         counter_collection.csv each) of profile_probe, which ends with a
@@ -21,7 +23,9 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 SOURCE = {"fwd": "frontal.hip", "bwd": "frontal.hip", "diag_lu": "frontal.hip", "panel_trsm": "frontal.hip",
           "gemm_update": "frontal.hip", "update_lu": "frontal.hip", "assemble_front": "frontal.hip",
           "strip_first": "frontal.hip", "panel_step": "frontal.hip", "form_fwd": "frontal.hip",
-          "form_bwd": "frontal.hip", "bsweep": "sweep.hip",
+          "form_bwd": "frontal.hip", "bsweep": "sweep.hip", "sdense": "sweep.hip",
+          "fwd_sdense": "sweep.hip", "bwd_sdense": "sweep.hip", "sdense_form_fwd": "sweep.hip",
+          "sdense_form_bwd": "sweep.hip",
           "fft_lines": "fft.hip",
           "gram": "stencil.hip", "gram_reduce": "stencil.hip", "eigen": "stencil.hip", "applyQ": "stencil.hip",
           "dots_partial": "krylov.hip", "dots_final": "krylov.hip", "axpy": "krylov.hip", "cgs": "krylov.hip",
@@ -48,6 +52,10 @@ def registry_key(name):
         base = "update_lu"  # fused with the next diagonal-block factorisation
     if base in ("fwd_small", "bwd_small"):
         base = base[:3]  # the small-front levels' sweeps, timed under the same name
+    if base in ("sdense_fwd", "sdense_bwd"):
+        base = base[7:] + "_sdense"  # timed as fwd_sdense / bwd_sdense
+    if base == "sdense_form" and len(args) >= 2:
+        base = "sdense_form_bwd" if args[1] == "true" else "sdense_form_fwd"
     if base == "fwd" and len(args) >= 2 and args[-2] == "true":
         # the forward chain (or the transposed backward one) run on unit
         # vectors: formation of a dense level's operators
@@ -115,12 +123,51 @@ def traffic(fetch_csv, write_csv, title, cmd_f, cmd_w):
     return "\n".join(lines) + "\n"
 
 
+def counters(csv_path, trace_path, title, cmd):
+    """Per-kernel sums of the counters of one --pmc run (derived metrics as
+    rocprofv3 reports them per dispatch, averaged over a kernel's dispatches
+    weighted by duration), with the durations from the same run's trace."""
+    rows = list(csv.DictReader(open(csv_path)))
+    dur = {}
+    for r in csv.DictReader(open(trace_path)):
+        dur[r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    per = {}
+    for r in rows:
+        key, _ = registry_key(r["Kernel_Name"])
+        if key is None:
+            continue
+        a = per.setdefault(key, {"dispatches": set(), "time": 0.0, "vals": {}})
+        did = r["Dispatch_Id"]
+        t = dur.get(did, 0.0)
+        if did not in a["dispatches"]:
+            a["dispatches"].add(did)
+            a["time"] += t
+        v = a["vals"].setdefault(r["Counter_Name"], [0.0, 0.0])
+        v[0] += float(r["Counter_Value"]) * t   # duration-weighted (rates, percentages)
+        v[1] += float(r["Counter_Value"])       # plain sum (counts, flops)
+    names = sorted({n for a in per.values() for n in a["vals"]})
+    out = [f"# {title}", "", "Command (from the repository root, on the MI355X):", "", "```", cmd, "```", "",
+           "Per kernel: dispatches, summed duration, and for each counter the duration-weighted mean "
+           "(percentages) and the sum over dispatches (counts).", "",
+           "| kernel | dispatches | ms | " + " | ".join(f"{n} (mean) | {n} (sum)" for n in names) + " |",
+           "|---|---|---|" + "---|---|" * len(names)]
+    for key, a in sorted(per.items(), key=lambda kv: -kv[1]["time"])[:20]:
+        cells = []
+        for n in names:
+            v = a["vals"].get(n, [0.0, 0.0])
+            cells += [f"{v[0] / a['time']:.3g}" if a["time"] > 0 else "-", f"{v[1]:.4g}"]
+        out.append(f"| `{key}` | {len(a['dispatches'])} | {a['time'] * 1e3:.3f} | " + " | ".join(cells) + " |")
+    return "\n".join(out) + "\n"
+
+
 def main():
     mode = sys.argv[1]
     if mode == "stats":
         sys.stdout.write(stats(*sys.argv[2:5]))
     elif mode == "traffic":
         sys.stdout.write(traffic(*sys.argv[2:7]))
+    elif mode == "counters":
+        sys.stdout.write(counters(*sys.argv[2:6]))
     else:
         raise SystemExit(__doc__)
 
