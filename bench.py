@@ -145,10 +145,20 @@ def kernel_model(base, tag, st, w, nrhs, counts):
     if base == "applyQ":
         return "hbm", counts.get(f"applyQ [{tag}]", 0) * N * (16 + esz) * nrhs, "GB/s"
     if base in ("fft_first", "fft_last"):
-        return "hbm", counts.get(f"{base} [{tag}]", 0) * n ** (d - 1) * (n * 16 + L * esz) * nrhs, "GB/s"
+        # field rows (complex128) in or out, the work rows (L values each)
+        # out or in; fft_first also reads w^2 m once
+        per = n ** (d - 1) * (n * 16 + L * esz) * nrhs + (N * 8 if base == "fft_first" else 0)
+        return "hbm", counts.get(f"{base} [{tag}]", 0) * per, "GB/s"
+    if base in ("fft_axis_fwd", "fft_axis_inv"):
+        # 3D pass along i2 over the lines (k1, i3 < n): n values one way, L the other
+        return "hbm", counts.get(f"{base} [{tag}]", 0) * L * n * (n + L) * esz * nrhs, "GB/s"
     if base == "fft_conv":
-        per = L ** (d - 1) * 2 * n * esz * nrhs + (n + 1) ** d * esz
+        # n values in and out per line, the spectrum rows once
+        per = L ** (d - 1) * 2 * n * esz * nrhs + (n + 1) ** (d - 1) * L * esz
         return "hbm", counts.get(f"fft_conv [{tag}]", 0) * per, "GB/s"
+    if base in ("fwd_sdense", "bwd_sdense"):
+        # the formed small-front operators (Gf or Gb, m x p per front)
+        return "hbm", apps * st["sdense_entries"] * esz, "GB/s"
     return None
 
 

@@ -1,35 +1,47 @@
 // Zero-padded FFT convolution with the Green's spectrum (the K-matvec).
 //
-// The convolution y = K v over the n^d grid (eq:lso; Section 1 notes that its
-// convolution structure allows FFT application) is computed on the (2n)^d
-// circulant embedding: pad v, transform, multiply by the spectrum of the
-// embedded kernel, transform back, keep the n^d block.
+// y = K v over the n^d grid (eq:lso; Section 1 notes that its convolution
+// structure allows FFT application) is the n^d block of the circular
+// convolution on the (2n)^d embedding: pad v, transform, multiply by the
+// spectrum of the embedded kernel, transform back.
 //
-// Transforms are Stockham autosort FFTs (the formulation of Govindaraju et
-// al., "High performance discrete Fourier transforms on graphics processors",
-// SC 2008) of length L = 2^a 3^b held in LDS, one line per group of
-// L/EPT threads, each thread staging EPT values in registers per pass.
-// Passes over HBM, per right-hand side (2D):
-//   FIRST  rows i2 < n: load w^2 m v (n values), pad, forward FFT along i1
-//   CONV   all L columns: load n values, forward FFT along i2, multiply by the
-//          spectrum, inverse FFT, store n values
-//   LAST   rows i2 < n: inverse FFT along i1, keep n values, add v
-// In 3D an axis-2 forward pass runs after FIRST and an axis-2 inverse pass
-// before LAST; CONV then runs along i3.  Rows that are zero are never read or
-// transformed (pruning).  The 1/L^d normalisation is folded into the spectrum.
+// Half-length transforms.  With L = 2n and v zero beyond n along an axis, a
+// length-L transform of v splits into two length-n ones,
+//   X[2k] = DFT_n(v)[k],   X[2k+1] = DFT_n(v_j w^j)[k],   w = exp(-2 pi i / L),
+// and the first n outputs of a length-L inverse are
+//   y_j = IDFT_n(Y[2k])_j + w^-j IDFT_n(Y[2k+1])_j.
+// The work array keeps every transformed axis in this split order (the n
+// even frequencies, then the n odd ones), so each transform of the K-matvec
+// is an n-point one over data that is nonzero, and the spectrum is stored in
+// the same order (one row of L values per frequency of the other axes, see
+// the set-up in greens.hip).  Passes over HBM per right-hand side:
+//   2D  FIRST  rows i2 < n: w^2 m v (n values), two forward transforms along
+//              i1, L values out (split order)
+//       CONV   all L columns: n values, two forward transforms along i2, times
+//              the spectrum, two inverse transforms, n values back in place
+//       LAST   rows i2 < n: L values, two inverse transforms along i1, n
+//              values out (plus v for the operator)
+//   3D  FIRST, then the forward pass along i2 for i3 < n (n values in, L out),
+//       CONV along i3 over all L^2 lines, the inverse pass along i2, LAST.
+//
+// n-point transforms are Stockham autosort FFTs (the formulation of
+// Govindaraju et al., "High performance discrete Fourier transforms on
+// graphics processors", SC 2008), n = 2^a 3^b, P = n / EPT threads per line.
+// Thread t owns elements t + m P (m < EPT) before and after a transform: the
+// first radix pass takes them from registers and the last leaves them there,
+// so only the passes in between exchange through LDS (one pad element per 16
+// against bank conflicts).  Lines along a strided axis are handed to
+// consecutive lanes (lane = line + LPW t), so a load or store of element e
+// covers LPW adjacent lines' contiguous entries.
+//
+// The set-up's transform of the full embedded kernel (all L values nonzero)
+// uses the plain full-length line kernel at the end of this file.
 #include "lsp_common.h"
 #include "kernels.h"
 
 namespace lsp {
 
 namespace {
-
-template <typename T>
-__device__ inline cplx<T> twiddle(const cplx<T>* tw, int idx, bool inv) {
-  cplx<T> w = tw[idx];
-  if (inv) w.y = -w.y;
-  return w;
-}
 
 template <typename T, int R> struct Dft;
 
@@ -93,6 +105,437 @@ template <typename T> struct Dft<T, 3> {
   }
 };
 
+__device__ inline int fold(int k, int L) { return k <= L / 2 ? k : L - k; }
+
+// ---------------------------------------------------------------- half-length transforms
+
+constexpr int kHalfThreads = 256;          // largest workgroup of the half-length kernels
+constexpr size_t kHalfLds = 40 * 1024;     // LDS per workgroup
+
+__host__ __device__ __forceinline__ int padi(int e) { return e + (e >> 4); }
+
+// Twiddles of a pass (radix R, span Ns): for butterfly b (k = (t + b P) mod
+// Ns, idx = k L / (Ns R), tw[i] = w^i) the powers w^idx, w^(2 idx) and, for
+// R = 8, w^(4 idx) are loaded; the other powers are products of at most two
+// loaded ones (a bounded rounding depth).
+template <int R> struct TwLoads { static constexpr int value = R == 2 ? 1 : (R == 8 ? 3 : 2); };
+
+template <typename T, int R, int NB>
+__device__ __forceinline__ void load_tw(cplx<T> (&wt)[NB * TwLoads<R>::value], const int t, const int P,
+                                        const int Ns, const int L, const cplx<T>* __restrict__ tw) {
+  constexpr int NL = TwLoads<R>::value;
+  const int tstep = L / (Ns * R);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int idx = ((t + b * P) % Ns) * tstep;
+    wt[NL * b] = tw[idx];
+    if constexpr (NL >= 2) wt[NL * b + 1] = tw[2 * idx];
+    if constexpr (NL >= 3) wt[NL * b + 2] = tw[4 * idx];
+  }
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ cplx<T> twc(cplx<T> w) { return INV ? cconj(w) : w; }
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void apply_tw(cplx<T> (&v)[R], const cplx<T>* w) {
+  const cplx<T> w1 = twc<T, INV>(w[0]);
+  v[1] = cmul(v[1], w1);
+  if constexpr (R >= 3) {
+    const cplx<T> w2 = twc<T, INV>(w[1]);
+    v[2] = cmul(v[2], w2);
+    if constexpr (R >= 4) {
+      const cplx<T> w3 = cmul(w1, w2);
+      v[3] = cmul(v[3], w3);
+      if constexpr (R == 8) {
+        const cplx<T> w4 = twc<T, INV>(w[2]);
+        v[4] = cmul(v[4], w4);
+        v[5] = cmul(v[5], cmul(w1, w4));
+        v[6] = cmul(v[6], cmul(w2, w4));
+        v[7] = cmul(v[7], cmul(w3, w4));
+      }
+    }
+  }
+}
+
+// One radix-R pass of an n-point transform over the line s (LDS, padded
+// index).  a[m] holds element t + m P: read by the first pass, written by the
+// last; the other passes read and write s.  CARRY: the twiddles of this pass
+// are in wt8 (loaded by the previous pass) and those of the next pass, a
+// radix-8 one, are loaded here, a pass ahead of their use; otherwise the
+// pass loads its own.
+template <typename T, int R, int EPT, bool INV, bool CARRY>
+__device__ __forceinline__ void half_pass(cplx<T> (&a)[EPT], cplx<T> (&wt8)[3], cplx<T>* __restrict__ s,
+                                          const int t, const int P, const int n, const int L, const int Ns,
+                                          const bool first, const bool last, const cplx<T>* __restrict__ tw) {
+  constexpr int NB = EPT / R;
+  constexpr int NL = TwLoads<R>::value;
+  const int q = n / R;
+  cplx<T> v[NB][R];
+  if (first) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = a[b + r * NB];
+  } else {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = s[padi(t + b * P + r * q)];
+  }
+  if (!first) {
+    if constexpr (CARRY) {
+      // carried twiddles are radix-8 ones (the radix-2 and radix-4 passes
+      // of a carried schedule are first passes)
+      if constexpr (R == 8) apply_tw<T, 8, INV>(v[0], wt8);
+    } else {
+      cplx<T> wt[NB * NL];
+      load_tw<T, R, NB>(wt, t, P, Ns, L, tw);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) apply_tw<T, R, INV>(v[b], wt + NL * b);
+    }
+  }
+  if constexpr (CARRY) {
+    if (!last) load_tw<T, 8, 1>(wt8, t, P, Ns * R, L, tw);
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) Dft<T, R>::run(v[b], INV);
+  if (last) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[b + r * NB] = v[b][r];
+  } else {
+    __syncthreads();  // every earlier read of the line is complete
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = t + b * P, k = j % Ns, base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[padi(base + r * Ns)] = v[b][r];
+    }
+    __syncthreads();
+  }
+}
+
+// n = 2^a (EPT = 8): a radix 2, 4 or 8 pass, then radix-8 passes, the
+// twiddles of each radix-8 pass loaded a pass ahead.  n = 2^a 3^b: passes
+// of radix 4, 2, 3 in the plan's order, each loading its own twiddles.
+template <typename T, int EPT, bool INV>
+__device__ __forceinline__ void fft_half(cplx<T> (&a)[EPT], cplx<T>* __restrict__ s, const int t, const int P,
+                                         const int n, const int L, const FftRadices& hr,
+                                         const cplx<T>* __restrict__ tw) {
+  cplx<T> wt8[3];
+  if constexpr (EPT == 8) {
+    const int R0 = hr.r[0], np = hr.npass;
+    if (R0 == 8) half_pass<T, 8, 8, INV, true>(a, wt8, s, t, P, n, L, 1, true, np == 1, tw);
+    else if (R0 == 4) half_pass<T, 4, 8, INV, true>(a, wt8, s, t, P, n, L, 1, true, np == 1, tw);
+    else half_pass<T, 2, 8, INV, true>(a, wt8, s, t, P, n, L, 1, true, np == 1, tw);
+    int Ns = R0;
+    for (int ip = 1; ip < np; ++ip) {
+      half_pass<T, 8, 8, INV, true>(a, wt8, s, t, P, n, L, Ns, false, ip + 1 == np, tw);
+      Ns *= 8;
+    }
+  } else {
+    int Ns = 1;
+    for (int ip = 0; ip < hr.npass; ++ip) {
+      const int R = hr.r[ip];
+      const bool first = ip == 0, last = ip + 1 == hr.npass;
+      if constexpr (EPT % 4 == 0) { if (R == 4) half_pass<T, 4, EPT, INV, false>(a, wt8, s, t, P, n, L, Ns, first, last, tw); }
+      if constexpr (EPT % 2 == 0) { if (R == 2) half_pass<T, 2, EPT, INV, false>(a, wt8, s, t, P, n, L, Ns, first, last, tw); }
+      if constexpr (EPT % 3 == 0) { if (R == 3) half_pass<T, 3, EPT, INV, false>(a, wt8, s, t, P, n, L, Ns, first, last, tw); }
+      Ns *= R;
+    }
+  }
+}
+
+enum { HK_FWD_FIELD = 0, HK_FWD_WORK = 1, HK_CONV = 2, HK_INV_WORK = 3, HK_INV_FIELD = 4 };
+
+const char* half_name(int kind) {
+  static const char* names[5] = {"fft_first", "fft_axis_fwd", "fft_conv", "fft_axis_inv", "fft_last"};
+  return names[kind];
+}
+
+struct HalfArgs {
+  int n, L, d, P, LPW, Lp;
+  int ncols, nout, nrhs;
+  int ncb, GS;                 // line blocks of LPW lines; blocks per cache-line group
+  long long cs, os, es;        // work-array line (c, o): element e at c cs + o os + e es
+  long long wstride, fstride;  // per right-hand side: work array (L^d), fields (N)
+  FftRadices hr;               // radices of n
+};
+
+// Line (c, o) of right-hand side rhs, by kind:
+//   FWD_FIELD  field row c (n contiguous values, scaled by w2m when given) ->
+//              work row c: L values at (c mod n) L + (c div n) L^2
+//   FWD_WORK   n values of the work line -> L values of the same line
+//   CONV       n values -> n values in place, spectrum row of line c
+//   INV_WORK   L values of the work line -> its first n values
+//   INV_FIELD  work row c (L values) -> field row c (plus x when given)
+// Workgroups: LPW lines of one (o, rhs), line = tid / P, t = tid % P.  The
+// GS blocks whose lines share cache lines, then the right-hand sides of a
+// line block (sharing spectrum rows), are consecutive in dispatch order
+// within one XCD (workgroup b goes to XCD b mod 8).  TIO: a strided line's
+// loads and stores go through LDS, lane tid handling element tid / LPW +
+// m P of line tid % LPW, so that one load or store covers LPW adjacent
+// lines' entries (used when P lanes of one line would otherwise read single
+// entries of separate cache lines).
+template <typename T, int EPT, int KIND, bool TIO>
+__global__ void __launch_bounds__(kHalfThreads) half_lines_kernel(cplx<T>* __restrict__ W,
+                                                                  const double2* __restrict__ x,
+                                                                  double2* __restrict__ y,
+                                                                  const double* __restrict__ w2m,
+                                                                  const cplx<T>* __restrict__ spec,
+                                                                  const cplx<T>* __restrict__ tw, HalfArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  const int G = gridDim.x;
+  const int g = G % 8 == 0 ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  const int j = g % a.GS;
+  const int rest = g / a.GS;
+  const int rhs = rest % a.nrhs;
+  const int rest2 = rest / a.nrhs;
+  const int o = rest2 % a.nout;
+  const int cb = (rest2 / a.nout) * a.GS + j;
+  if (cb >= a.ncb) return;  // the last group's spare blocks (whole workgroups)
+  const int tid = threadIdx.x;
+  const int n = a.n, L = a.L, P = a.P;
+  const int line = tid / P, t = tid % P;
+  const int c = cb * a.LPW + line;
+  const bool live = c < a.ncols;
+  const int cc = live ? c : a.ncols - 1;  // lines past the end load in range and store nothing
+  cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* s = smem + line * a.Lp;
+  cplx<T>* Wr = W + rhs * a.wstride;
+  // IO lanes of TIO kinds
+  const int lio = tid % a.LPW, tio = tid / a.LPW;
+  const int cio = cb * a.LPW + lio;
+  const bool live_io = cio < a.ncols;
+  const int ccio = live_io ? cio : a.ncols - 1;
+  cplx<T>* sio = smem + lio * a.Lp;
+
+  // n values of this thread's work line from offset off (element e at
+  // base + off + e es) into d[m] = element t + m P
+  // (first: nothing has used the LDS lines yet, so the loads go straight
+  // to them)
+  auto load_work = [&](const long long off, cplx<T> (&d)[EPT], const bool first) {
+    if constexpr (TIO) {
+      const long long base = ccio * a.cs + o * a.os + off;
+      if (!first) __syncthreads();  // earlier reads of the lines are complete
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) sio[padi(tio + m * P)] = Wr[base + (long long)(tio + m * P) * a.es];
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) d[m] = s[padi(t + m * P)];
+    } else {
+      const long long base = cc * a.cs + o * a.os + off;
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) d[m] = Wr[base + (long long)(t + m * P) * a.es];
+    }
+  };
+  auto store_work = [&](const long long off, const cplx<T> (&d)[EPT]) {
+    if constexpr (TIO) {
+      __syncthreads();  // earlier reads of the lines are complete
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) s[padi(t + m * P)] = d[m];
+      __syncthreads();
+      if (live_io) {
+        const long long base = ccio * a.cs + o * a.os + off;
+#pragma unroll
+        for (int m = 0; m < EPT; ++m) Wr[base + (long long)(tio + m * P) * a.es] = sio[padi(tio + m * P)];
+      }
+    } else {
+      if (live) {
+        const long long base = cc * a.cs + o * a.os + off;
+#pragma unroll
+        for (int m = 0; m < EPT; ++m) Wr[base + (long long)(t + m * P) * a.es] = d[m];
+      }
+    }
+  };
+
+  cplx<T> v[EPT];
+  // the element twiddles w^e of this thread's elements (odd half)
+  cplx<T> we[EPT];
+#pragma unroll
+  for (int m = 0; m < EPT; ++m) we[m] = tw[t + m * P];
+
+  if constexpr (KIND == HK_FWD_FIELD) {
+    cplx<T> xin[EPT];
+    const long long fb = (long long)cc * n;
+    const double2* xr = x + rhs * a.fstride;
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const int e = t + m * P;
+      const double2 xv = xr[fb + e];
+      const double sc = w2m ? w2m[fb + e] : 1.0;
+      xin[m] = mk<T>((T)(xv.x * sc), (T)(xv.y * sc));
+    }
+    const long long wb = (long long)(cc % n) * L + (long long)(cc / n) * L * L;
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) v[m] = xin[m];
+    fft_half<T, EPT, false>(v, s, t, P, n, L, a.hr, tw);
+    if (live) {
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) Wr[wb + t + m * P] = v[m];
+    }
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) v[m] = cmul(xin[m], we[m]);
+    fft_half<T, EPT, false>(v, s, t, P, n, L, a.hr, tw);
+    if (live) {
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) Wr[wb + n + t + m * P] = v[m];
+    }
+  } else if constexpr (KIND == HK_FWD_WORK) {
+    cplx<T> xin[EPT];
+    load_work(0, xin, true);
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) v[m] = xin[m];
+    fft_half<T, EPT, false>(v, s, t, P, n, L, a.hr, tw);
+    store_work(0, v);
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) v[m] = cmul(xin[m], we[m]);
+    fft_half<T, EPT, false>(v, s, t, P, n, L, a.hr, tw);
+    store_work((long long)n * a.es, v);
+  } else if constexpr (KIND == HK_CONV) {
+    long long row;
+    {
+      const int H = n + 1;
+      const int c1 = a.d == 2 ? cc : cc % L;
+      const int k1 = c1 < n ? 2 * c1 : 2 * (c1 - n) + 1;
+      row = fold(k1, L);
+      if (a.d == 3) {
+        const int c2 = cc / L;
+        const int k2 = c2 < n ? 2 * c2 : 2 * (c2 - n) + 1;
+        row += (long long)H * fold(k2, L);
+      }
+    }
+    const cplx<T>* sp = spec + row * L;
+    cplx<T> xin[EPT], ya[EPT], sv[EPT];
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) sv[m] = sp[t + m * P];
+    load_work(0, xin, true);
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) v[m] = xin[m];
+    fft_half<T, EPT, false>(v, s, t, P, n, L, a.hr, tw);
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) { v[m] = cmul(v[m], sv[m]); sv[m] = sp[n + t + m * P]; }
+    fft_half<T, EPT, true>(v, s, t, P, n, L, a.hr, tw);
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) { ya[m] = v[m]; v[m] = cmul(xin[m], we[m]); }
+    fft_half<T, EPT, false>(v, s, t, P, n, L, a.hr, tw);
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) v[m] = cmul(v[m], sv[m]);
+    fft_half<T, EPT, true>(v, s, t, P, n, L, a.hr, tw);
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) v[m] = cadd(ya[m], cmulc(we[m], v[m]));
+    store_work(0, v);
+  } else if constexpr (KIND == HK_INV_WORK) {
+    cplx<T> yo[EPT];
+    load_work(0, v, true);
+    load_work((long long)n * a.es, yo, false);
+    fft_half<T, EPT, true>(v, s, t, P, n, L, a.hr, tw);
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) { const cplx<T> e = v[m]; v[m] = yo[m]; yo[m] = e; }
+    fft_half<T, EPT, true>(v, s, t, P, n, L, a.hr, tw);
+    // yo holds the even half's result
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) v[m] = cadd(yo[m], cmulc(we[m], v[m]));
+    store_work(0, v);
+  } else {  // HK_INV_FIELD
+    const long long wb = (long long)(cc % n) * L + (long long)(cc / n) * L * L;
+    cplx<T> yo[EPT];
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) v[m] = Wr[wb + t + m * P];
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) yo[m] = Wr[wb + n + t + m * P];
+    fft_half<T, EPT, true>(v, s, t, P, n, L, a.hr, tw);
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) { const cplx<T> e = v[m]; v[m] = yo[m]; yo[m] = e; }
+    fft_half<T, EPT, true>(v, s, t, P, n, L, a.hr, tw);
+    if (live) {
+      const long long fb = (long long)cc * n;
+      const double2* xr = x ? x + rhs * a.fstride : nullptr;
+      double2* yr = y + rhs * a.fstride;
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) {
+        const int e = t + m * P;
+        double2 r = widen(cadd(yo[m], cmulc(we[m], v[m])));
+        if (xr) { const double2 xv = xr[fb + e]; r.x += xv.x; r.y += xv.y; }
+        yr[fb + e] = r;
+      }
+    }
+  }
+}
+
+template <typename T, int EPT, int KIND, bool TIO>
+void launch_half_as(const HalfArgs& a, size_t lds, long long blocks, const FftPlanDev<T>& fp, cplx<T>* W,
+                    const double2* x, double2* y, const double* w2m, hipStream_t st) {
+  LSP_LAUNCH(half_name(KIND), (int)sizeof(cplx<T>), (half_lines_kernel<T, EPT, KIND, TIO>), dim3((unsigned)blocks),
+             dim3(a.LPW * a.P), lds, st, W, x, y, w2m, fp.spec, fp.tw, a);
+}
+
+template <typename T, int EPT, int KIND>
+void launch_half(const FftPlanDev<T>& fp, cplx<T>* W, const double2* x, double2* y, const double* w2m, int ncols,
+                 int nout, long long cs, long long os, long long es, int nrhs, hipStream_t st) {
+  constexpr int esz = (int)sizeof(cplx<T>);
+  constexpr bool field = KIND == HK_FWD_FIELD || KIND == HK_INV_FIELD;
+  HalfArgs a;
+  a.n = fp.n; a.L = fp.L; a.d = fp.d;
+  a.P = fp.n / EPT;
+  // transposed IO for a strided axis when a wave's lines would cover less
+  // than 64 contiguous bytes per element
+  const bool tio = !field && es != 1 && (64 / std::min(a.P, 64)) * esz < 64;
+  const int maxthr = kHalfThreads;
+  const int lp0 = padi(fp.n - 1) + 1;
+  int lpw = 1;
+  while (lpw < 64 && lpw * 2 * a.P <= maxthr && (size_t)lpw * 2 * (lp0 + 256 / esz) * esz <= kHalfLds) lpw *= 2;
+  // Line stride: the lines of a bank cycle (256 bytes, 256 / esz lanes)
+  // tile the banks: with TIO the IO lanes hold 256 / esz / LPW consecutive
+  // entries of each line, otherwise (P < 256 / esz) P entries of 256 / esz / P lines.
+  const int M = 256 / esz;
+  const int X = tio ? std::max(1, M / lpw) : (a.P < M ? a.P : 0);
+  int lp = lp0;
+  while (lp % M != X % M) ++lp;
+  a.Lp = lp;
+  a.LPW = lpw;
+  a.ncols = ncols; a.nout = nout; a.nrhs = nrhs;
+  a.cs = cs; a.os = os; a.es = es;
+  a.wstride = fp.wstride; a.fstride = fp.N;
+  a.hr = fp.hrad;
+  const long long ncb = (ncols + lpw - 1) / lpw;
+  // along a strided axis a block covers LPW adjacent lines' entries of a
+  // cache line (128 bytes): GS consecutive blocks complete it
+  int gs = 1;
+  if (!field && cs == 1)
+    while (gs * lpw * esz < 128 && gs < 16) gs *= 2;
+  a.ncb = (int)ncb; a.GS = gs;
+  const long long blocks = (ncb + gs - 1) / gs * gs * nout * nrhs;
+  LSP_REQUIRE(blocks < (1LL << 31), "FFT grid too large");
+  const size_t lds = (size_t)lpw * lp * esz;
+  if (tio) launch_half_as<T, EPT, KIND, !field>(a, lds, blocks, fp, W, x, y, w2m, st);
+  else launch_half_as<T, EPT, KIND, false>(a, lds, blocks, fp, W, x, y, w2m, st);
+}
+
+template <typename T, int EPT>
+void kmatvec_impl(const FftPlanDev<T>& fp, int nrhs, const double2* x, double2* y, const double* w2m,
+                  bool add_x, cplx<T>* W, hipStream_t st) {
+  const int n = fp.n, L = fp.L;
+  const long long LL = (long long)L * L;
+  if (fp.d == 2) {
+    launch_half<T, EPT, HK_FWD_FIELD>(fp, W, x, y, w2m, n, 1, 0, 0, 1, nrhs, st);
+    launch_half<T, EPT, HK_CONV>(fp, W, x, y, w2m, L, 1, 1, 0, L, nrhs, st);
+    launch_half<T, EPT, HK_INV_FIELD>(fp, W, add_x ? x : nullptr, y, w2m, n, 1, 0, 0, 1, nrhs, st);
+  } else {
+    launch_half<T, EPT, HK_FWD_FIELD>(fp, W, x, y, w2m, n * n, 1, 0, 0, 1, nrhs, st);
+    // along i2: lines (c1, i3 < n), elements at stride L
+    launch_half<T, EPT, HK_FWD_WORK>(fp, W, x, y, w2m, L, n, 1, LL, L, nrhs, st);
+    // along i3: lines c1 + L c2, elements at stride L^2
+    launch_half<T, EPT, HK_CONV>(fp, W, x, y, w2m, (int)LL, 1, 1, 0, LL, nrhs, st);
+    launch_half<T, EPT, HK_INV_WORK>(fp, W, x, y, w2m, L, n, 1, LL, L, nrhs, st);
+    launch_half<T, EPT, HK_INV_FIELD>(fp, W, add_x ? x : nullptr, y, w2m, n * n, 1, 0, 0, 1, nrhs, st);
+  }
+}
+
+// ---------------------------------------------------------------- full-length transforms (set-up)
+
 // One Stockham pass of radix R over a line in LDS.
 template <typename T, int R, int EPT>
 __device__ inline void fft_pass(cplx<T>* s, int L, int P, int t, int Ns, const cplx<T>* tw, bool inv) {
@@ -107,7 +550,11 @@ __device__ inline void fft_pass(cplx<T>* s, int L, int P, int t, int Ns, const c
 #pragma unroll
     for (int r = 0; r < R; ++r) v[b][r] = s[j + r * stride];
 #pragma unroll
-    for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], twiddle<T>(tw, r * k * tstep, inv));
+    for (int r = 1; r < R; ++r) {
+      cplx<T> w = tw[r * k * tstep];
+      if (inv) w.y = -w.y;
+      v[b][r] = cmul(v[b][r], w);
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -135,211 +582,51 @@ __device__ inline void fft_line(cplx<T>* s, int L, int P, int t, const cplx<T>* 
   }
 }
 
-__device__ inline int fold(int k, int L) { return k <= L / 2 ? k : L - k; }
-
-inline const char* fft_mode_name(int mode) {
-  static const char* names[4] = {"fft_axis", "fft_first", "fft_conv", "fft_last"};
-  return names[mode & 3];
-}
-
-// Generic line kernel.  Lines are indexed by (c, o): c in [0, ncols) runs over
-// LPW consecutive lines per workgroup, o over blockIdx.y; rhs over blockIdx.z.
-// Element e of line (c, o) of the work array sits at c*cs + o*os + e*es.
-//   MODE_PLAIN: read rl values of W (rest zero), FFT, write wl values of W.
-//   MODE_FIRST: line c is grid row c of the field x (n contiguous values):
-//               read w2m .* x (or x when w2m is null), forward FFT, write L values.
-//   MODE_CONV:  read rl, forward FFT, multiply by the spectrum, inverse FFT, write wl.
-//   MODE_LAST:  read L values of row c, inverse FFT, write n values to y
-//               (y = x + v when x is given, else y = v).
-enum { MODE_PLAIN = 0, MODE_FIRST = 1, MODE_CONV = 2, MODE_LAST = 3 };
-
 struct LineArgs {
-  int n, d, L, P, LPW, Lp;
+  int L, P, LPW, Lp;
   int ncols;
   long long cs, os, es;
-  int rl, wl;
-  int inv;
-  long long wstride;          // per-rhs stride of the work array
-  long long fstride;          // per-rhs stride of fields (N)
 };
 
-template <typename T, int EPT, int MODE>
-__global__ void __launch_bounds__(1024) fft_lines_kernel(cplx<T>* __restrict__ W, const double2* __restrict__ x,
-                                                         double2* __restrict__ y, const double* __restrict__ w2m,
-                                                         const cplx<T>* __restrict__ khat, const cplx<T>* __restrict__ tw,
-                                                         FftRadices rad, LineArgs a) {
+// Forward length-L transform of the lines (c, o) of W in place: c in
+// [0, ncols) in groups of LPW per workgroup, o over blockIdx.y; element e
+// of a line at c cs + o os + e es.
+template <typename T, int EPT>
+__global__ void __launch_bounds__(1024) full_lines_kernel(cplx<T>* __restrict__ W, const cplx<T>* __restrict__ tw,
+                                                          FftRadices rad, LineArgs a) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int tid = threadIdx.x;
-  const int nthr = blockDim.x;
-  // Workgroups go to the 8 XCDs round-robin (workgroup b to XCD b mod 8),
-  // each XCD with its own L2: give each XCD a contiguous range of line
-  // blocks, so that the lines sharing cache lines in a strided pass (16
-  // complex64 or 8 complex128 per 128 bytes) are read through one L2.
-  const int bx = gridDim.x % 8 == 0 ? (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8 : blockIdx.x;
-  const int c0 = bx * a.LPW;
-  const int o = blockIdx.y;
-  const int rhs = blockIdx.z;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int c0 = blockIdx.x * a.LPW;
   const int nl = min(a.LPW, a.ncols - c0);
-  cplx<T>* Wr = W + rhs * a.wstride;
   const int L = a.L, Lp = a.Lp;
-
-  // ---- load
-  if (MODE == MODE_FIRST) {
-    const double2* xr = x + rhs * a.fstride;
-    for (int idx = tid; idx < a.LPW * L; idx += nthr) {
-      int line = idx / L, e = idx % L;
-      cplx<T> v = mk<T>(0, 0);
-      if (line < nl && e < a.n) {
-        long long g = (long long)(c0 + line) * a.n + e;
-        double2 xv = xr[g];
-        double s = w2m ? w2m[g] : 1.0;
-        v = mk<T>((T)(xv.x * s), (T)(xv.y * s));
-      }
-      smem[line * Lp + e] = v;
-    }
-  } else if (MODE == MODE_LAST) {
-    for (int idx = tid; idx < a.LPW * L; idx += nthr) {
-      int line = idx / L, e = idx % L;
-      cplx<T> v = mk<T>(0, 0);
-      if (line < nl) {
-        int c = c0 + line;
-        long long base = (long long)(c % a.n) * L + (long long)(c / a.n) * L * L;
-        v = Wr[base + e];
-      }
-      smem[line * Lp + e] = v;
-    }
-  } else {
-    const long long obase = (long long)o * a.os;
-    if (a.es == 1) {
-      for (int idx = tid; idx < a.LPW * L; idx += nthr) {
-        int line = idx / L, e = idx % L;
-        cplx<T> v = mk<T>(0, 0);
-        if (line < nl && e < a.rl) v = Wr[(long long)(c0 + line) * a.cs + obase + e];
-        smem[line * Lp + e] = v;
-      }
-    } else {
-      for (int idx = tid; idx < a.LPW * L; idx += nthr) {
-        int line = idx % a.LPW, e = idx / a.LPW;
-        cplx<T> v = mk<T>(0, 0);
-        if (line < nl && e < a.rl) v = Wr[(long long)(c0 + line) * a.cs + obase + (long long)e * a.es];
-        smem[line * Lp + e] = v;
-      }
-    }
+  const long long obase = (long long)blockIdx.y * a.os;
+  for (int idx = tid; idx < a.LPW * L; idx += nthr) {
+    const int line = a.es == 1 ? idx / L : idx % a.LPW, e = a.es == 1 ? idx % L : idx / a.LPW;
+    smem[line * Lp + e] = line < nl ? W[(long long)(c0 + line) * a.cs + obase + (long long)e * a.es] : mk<T>(0, 0);
   }
   __syncthreads();
-
-  // ---- transform(s)
   const int line = tid / a.P, t = tid % a.P;
-  cplx<T>* s = smem + line * Lp;
-  bool inv = a.inv != 0;
-  if (MODE == MODE_FIRST) inv = false;
-  if (MODE == MODE_LAST) inv = true;
-  if (MODE == MODE_CONV) inv = false;
-  fft_line<T, EPT>(s, L, a.P, t, tw, rad, inv);
-  if (MODE == MODE_CONV) {
-    // multiply by the folded spectrum
-    const int H = a.n + 1;
-    if (line < nl) {
-      int c = c0 + line;
-      long long kb;
-      int k1 = c % L;
-      if (a.d == 2) kb = fold(k1, L);
-      else kb = fold(k1, L) + (long long)H * fold(c / L, L);
-      long long lstride = (a.d == 2) ? H : (long long)H * H;
-      for (int e = t; e < L; e += a.P) s[e] = cmul(s[e], khat[kb + fold(e, L) * lstride]);
-    }
-    __syncthreads();
-    fft_line<T, EPT>(s, L, a.P, t, tw, rad, true);
+  fft_line<T, EPT>(smem + line * Lp, L, a.P, t, tw, rad, false);
+  for (int idx = tid; idx < a.LPW * L; idx += nthr) {
+    const int ln = a.es == 1 ? idx / L : idx % a.LPW, e = a.es == 1 ? idx % L : idx / a.LPW;
+    if (ln < nl) W[(long long)(c0 + ln) * a.cs + obase + (long long)e * a.es] = smem[ln * Lp + e];
   }
-
-  // ---- store
-  if (MODE == MODE_FIRST) {
-    for (int idx = tid; idx < a.LPW * L; idx += nthr) {
-      int ln = idx / L, e = idx % L;
-      if (ln < nl) {
-        int c = c0 + ln;
-        long long base = (long long)(c % a.n) * L + (long long)(c / a.n) * L * L;
-        Wr[base + e] = smem[ln * Lp + e];
-      }
-    }
-  } else if (MODE == MODE_LAST) {
-    const double2* xr = x ? x + rhs * a.fstride : nullptr;
-    double2* yr = y + rhs * a.fstride;
-    for (int idx = tid; idx < a.LPW * a.n; idx += nthr) {
-      int ln = idx / a.n, e = idx % a.n;
-      if (ln < nl) {
-        long long g = (long long)(c0 + ln) * a.n + e;
-        double2 v = widen(smem[ln * Lp + e]);
-        if (xr) { double2 xv = xr[g]; v.x += xv.x; v.y += xv.y; }
-        yr[g] = v;
-      }
-    }
-  } else {
-    const long long obase = (long long)o * a.os;
-    if (a.es == 1) {
-      for (int idx = tid; idx < a.LPW * L; idx += nthr) {
-        int ln = idx / L, e = idx % L;
-        if (ln < nl && e < a.wl) Wr[(long long)(c0 + ln) * a.cs + obase + e] = smem[ln * Lp + e];
-      }
-    } else {
-      for (int idx = tid; idx < a.LPW * L; idx += nthr) {
-        int ln = idx % a.LPW, e = idx / a.LPW;
-        if (ln < nl && e < a.wl) Wr[(long long)(c0 + ln) * a.cs + obase + (long long)e * a.es] = smem[ln * Lp + e];
-      }
-    }
-  }
-}
-
-template <typename T>
-int lines_per_wg(int L, int P, long long total_lines) {
-  // up to 132 KB of the 160 KB LDS a gfx950 workgroup may use; a power of two
-  // so that strided passes read aligned runs of consecutive lines; and no more
-  // lines per workgroup than keeps about 512 workgroups in flight
-  size_t per_line = (size_t)(L + 1) * sizeof(cplx<T>);
-  int cap = (int)((132 * 1024) / per_line);
-  long long want = std::max<long long>(1, total_lines / 512);
-  int lpw = 1;
-  while (lpw * 2 <= std::min<long long>(std::min(cap, 16), want) && lpw * 2 * P <= 1024) lpw *= 2;
-  return lpw;
-}
-
-template <typename T, int EPT, int MODE>
-void launch_lines(const FftPlanDev<T>& fp, cplx<T>* W, const double2* x, double2* y, const double* w2m,
-                  int ncols, int nouter, long long cs, long long os, long long es, int rl, int wl, int inv,
-                  int nrhs, hipStream_t st) {
-  LineArgs a;
-  a.n = fp.n; a.d = fp.d; a.L = fp.L; a.P = fp.L / EPT;
-  a.LPW = lines_per_wg<T>(fp.L, a.P, (long long)ncols * nouter * nrhs);
-  a.Lp = fp.L + 1;
-  a.ncols = ncols; a.cs = cs; a.os = os; a.es = es; a.rl = rl; a.wl = wl; a.inv = inv;
-  a.wstride = fp.wstride; a.fstride = fp.N;
-  dim3 grid((ncols + a.LPW - 1) / a.LPW, nouter, nrhs);
-  dim3 block(a.LPW * a.P);
-  size_t lds = (size_t)a.LPW * a.Lp * sizeof(cplx<T>);
-  LSP_LAUNCH(fft_mode_name(MODE), (int)sizeof(cplx<T>), (fft_lines_kernel<T, EPT, MODE>), grid, block, lds, st, W, x, y, w2m, fp.khat, fp.tw,
-                     fp.rad, a);
 }
 
 template <typename T, int EPT>
-void kmatvec_impl(const FftPlanDev<T>& fp, int nrhs, const double2* x, double2* y, const double* w2m,
-                  bool add_x, cplx<T>* W, hipStream_t st) {
-  const int n = fp.n, L = fp.L;
-  const long long LL = (long long)L * L;
-  if (fp.d == 2) {
-    launch_lines<T, EPT, MODE_FIRST>(fp, W, x, y, w2m, n, 1, 0, 0, 1, n, L, 0, nrhs, st);
-    launch_lines<T, EPT, MODE_CONV>(fp, W, x, y, w2m, L, 1, 1, 0, L, n, n, 0, nrhs, st);
-    launch_lines<T, EPT, MODE_LAST>(fp, W, add_x ? x : nullptr, y, w2m, n, 1, 0, 0, 1, L, n, 1, nrhs, st);
-  } else {
-    launch_lines<T, EPT, MODE_FIRST>(fp, W, x, y, w2m, n * n, 1, 0, 0, 1, n, L, 0, nrhs, st);
-    // axis 2 forward: lines (k1, i3 < n), elements along i2 (stride L)
-    launch_lines<T, EPT, MODE_PLAIN>(fp, W, x, y, w2m, L, n, 1, LL, L, n, L, 0, nrhs, st);
-    // axis 3 convolution: lines (k1 + L k2), elements along i3 (stride L^2)
-    launch_lines<T, EPT, MODE_CONV>(fp, W, x, y, w2m, L * L, 1, 1, 0, LL, n, n, 0, nrhs, st);
-    // axis 2 inverse
-    launch_lines<T, EPT, MODE_PLAIN>(fp, W, x, y, w2m, L, n, 1, LL, L, L, n, 1, nrhs, st);
-    launch_lines<T, EPT, MODE_LAST>(fp, W, add_x ? x : nullptr, y, w2m, n * n, 1, 0, 0, 1, L, n, 1, nrhs, st);
-  }
+void launch_full(const FftPlanDev<T>& fp, cplx<T>* W, int ncols, int nouter, long long cs, long long os,
+                 long long es, hipStream_t st) {
+  LineArgs a;
+  a.L = fp.L; a.P = fp.L / EPT; a.Lp = fp.L + 1;
+  const size_t per_line = (size_t)a.Lp * sizeof(cplx<T>);
+  int lpw = 1;
+  while (lpw < 16 && (size_t)lpw * 2 * per_line <= 64 * 1024 && lpw * 2 * a.P <= 1024) lpw *= 2;
+  a.LPW = lpw;
+  a.ncols = ncols; a.cs = cs; a.os = os; a.es = es;
+  const dim3 grid((ncols + lpw - 1) / lpw, nouter);
+  LSP_LAUNCH("fft_full", (int)sizeof(cplx<T>), (full_lines_kernel<T, EPT>), grid, dim3(lpw * a.P),
+             (size_t)lpw * per_line, st, W, fp.tw, fp.rad, a);
 }
 
 template <typename T, int EPT>
@@ -347,12 +634,12 @@ void full_fft_impl(const FftPlanDev<T>& fp, cplx<T>* W, hipStream_t st) {
   const int L = fp.L;
   const long long LL = (long long)L * L;
   if (fp.d == 2) {
-    launch_lines<T, EPT, MODE_PLAIN>(fp, W, nullptr, nullptr, nullptr, L, 1, L, 0, 1, L, L, 0, 1, st);
-    launch_lines<T, EPT, MODE_PLAIN>(fp, W, nullptr, nullptr, nullptr, L, 1, 1, 0, L, L, L, 0, 1, st);
+    launch_full<T, EPT>(fp, W, L, 1, L, 0, 1, st);
+    launch_full<T, EPT>(fp, W, L, 1, 1, 0, L, st);
   } else {
-    launch_lines<T, EPT, MODE_PLAIN>(fp, W, nullptr, nullptr, nullptr, L * L, 1, L, 0, 1, L, L, 0, 1, st);
-    launch_lines<T, EPT, MODE_PLAIN>(fp, W, nullptr, nullptr, nullptr, L, L, 1, LL, L, L, L, 0, 1, st);
-    launch_lines<T, EPT, MODE_PLAIN>(fp, W, nullptr, nullptr, nullptr, (int)LL, 1, 1, 0, LL, L, L, 0, 1, st);
+    launch_full<T, EPT>(fp, W, L * L, 1, L, 0, 1, st);
+    launch_full<T, EPT>(fp, W, L, L, 1, LL, L, st);
+    launch_full<T, EPT>(fp, W, (int)LL, 1, 1, 0, LL, st);
   }
 }
 
@@ -361,10 +648,14 @@ void full_fft_impl(const FftPlanDev<T>& fp, cplx<T>* W, hipStream_t st) {
 template <typename T>
 void kmatvec(const FftPlanDev<T>& fp, int nrhs, const double2* x, double2* y, const double* w2m, bool add_x,
              cplx<T>* W, hipStream_t st) {
-  if (fp.ept == 8) kmatvec_impl<T, 8>(fp, nrhs, x, y, w2m, add_x, W, st);
-  else if (fp.ept == 12) kmatvec_impl<T, 12>(fp, nrhs, x, y, w2m, add_x, W, st);
-  else if (fp.ept == 6) kmatvec_impl<T, 6>(fp, nrhs, x, y, w2m, add_x, W, st);
-  else throw Error(LSP_ERR_ARG, "unsupported FFT length");
+  switch (fp.hept) {
+    case 12: kmatvec_impl<T, 12>(fp, nrhs, x, y, w2m, add_x, W, st); break;
+    case 8: kmatvec_impl<T, 8>(fp, nrhs, x, y, w2m, add_x, W, st); break;
+    case 6: kmatvec_impl<T, 6>(fp, nrhs, x, y, w2m, add_x, W, st); break;
+    case 4: kmatvec_impl<T, 4>(fp, nrhs, x, y, w2m, add_x, W, st); break;
+    case 3: kmatvec_impl<T, 3>(fp, nrhs, x, y, w2m, add_x, W, st); break;
+    default: throw Error(LSP_ERR_ARG, "unsupported FFT length");
+  }
 }
 
 template <typename T>

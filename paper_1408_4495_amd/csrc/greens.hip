@@ -113,20 +113,31 @@ __global__ void embed_kernel(double2* __restrict__ E, const double2* __restrict_
   E[id] = zero ? make_double2(0.0, 0.0) : k[src];
 }
 
-// Keeps the even-symmetric orthant [0, L/2]^d of the spectrum, scaled by
-// 1/L^d (the inverse transform's normalisation), in FP64 and FP32.
-__global__ void fold_khat_kernel(double2* __restrict__ kh64, float2* __restrict__ kh32,
-                                 const double2* __restrict__ E, int n, int d, double scale,
-                                 long long total) {
+// The spectrum in the K-matvec's order (fft.hip): for the split order
+// c -> frequency 2c (c < n) or 2(c - n) + 1 (c >= n) along every axis, row
+// fold(k1) [+ (n+1) fold(k2)] holds the L values along the last axis, where
+// fold(k) = min(k, L - k) (the embedded kernel is even along every axis);
+// scaled by 1/L^d (the inverse transform's normalisation), in FP64 and FP32.
+__global__ void split_spectrum_kernel(double2* __restrict__ s64, float2* __restrict__ s32,
+                                      const double2* __restrict__ E, int n, int d, double scale, long long total) {
   long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= total) return;
-  int L = 2 * n, H = n + 1;
-  int c1 = (int)(id % H), c2 = (int)((id / H) % H), c3 = d == 3 ? (int)(id / ((long long)H * H)) : 0;
-  long long src = c1 + (long long)L * c2 + (long long)L * L * c3;
+  const int L = 2 * n, H = n + 1;
+  const int c = (int)(id % L);
+  const long long row = id / L;
+  const int kl = c < n ? 2 * c : 2 * (c - n) + 1;
+  const int fl = kl <= n ? kl : L - kl;
+  long long src;
+  if (d == 2) {
+    src = row + (long long)L * fl;
+  } else {
+    const int f1 = (int)(row % H), f2 = (int)(row / H);
+    src = f1 + (long long)L * f2 + (long long)L * L * fl;
+  }
   double2 v = E[src];
   v.x *= scale; v.y *= scale;
-  kh64[id] = v;
-  kh32[id] = to_c64(v);
+  s64[id] = v;
+  s32[id] = to_c64(v);
 }
 
 }  // namespace
@@ -147,13 +158,14 @@ void launch_embed(double2* E, const double2* k, int n, int d, hipStream_t st) {
                      E, k, n, d, total);
 }
 
-void launch_fold_khat(double2* kh64, float2* kh32, const double2* E, int n, int d, hipStream_t st) {
-  long long total = 1;
+void launch_split_spectrum(double2* s64, float2* s32, const double2* E, int n, int d, hipStream_t st) {
+  long long total = 2LL * n;
   double scale = 1.0;
-  for (int a = 0; a < d; ++a) { total *= n + 1; scale /= 2.0 * n; }
+  for (int a = 0; a < d; ++a) scale /= 2.0 * n;
+  for (int a = 1; a < d; ++a) total *= n + 1;
   int bs = 256;
-  LSP_LAUNCH("fold_khat", 0, fold_khat_kernel, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st,
-                     kh64, kh32, E, n, d, scale, total);
+  LSP_LAUNCH("split_spectrum", 0, split_spectrum_kernel, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st,
+             s64, s32, E, n, d, scale, total);
 }
 
 }  // namespace lsp

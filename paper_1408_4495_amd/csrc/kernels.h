@@ -13,7 +13,7 @@ constexpr int kSweepChunk = kSweepCols;  // boundary columns per partial sum of 
 // ---- Green's table
 void launch_ktable(double2* k, int n, int d, double omega, double2 k0, hipStream_t st);
 void launch_embed(double2* E, const double2* k, int n, int d, hipStream_t st);
-void launch_fold_khat(double2* kh64, float2* kh32, const double2* E, int n, int d, hipStream_t st);
+void launch_split_spectrum(double2* s64, float2* s32, const double2* E, int n, int d, hipStream_t st);
 
 // ---- FFT
 struct FftRadices {
@@ -23,11 +23,14 @@ struct FftRadices {
 
 template <typename T>
 struct FftPlanDev {
-  int n, d, L, N, ept;
+  int n, d, L, N;
+  int ept;                   // elements per thread of the full-length (L-point) transforms
+  int hept;                  // elements per thread of the half-length (n-point) transforms
   long long wstride;         // work array elements per right-hand side (L^d)
-  FftRadices rad;
+  FftRadices rad;            // radices of L
+  FftRadices hrad;           // radices of n
   const cplx<T>* tw;         // exp(-2 pi i k / L), k < L
-  const cplx<T>* khat;       // folded spectrum (n+1)^d, scaled by 1/L^d
+  const cplx<T>* spec;       // spectrum rows in split order, (n+1)^(d-1) x L, scaled by 1/L^d
 };
 
 // y = [x +] K (w2m .* x), fields complex128 [nrhs][N]; w2m == nullptr means

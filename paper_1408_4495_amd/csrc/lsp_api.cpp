@@ -98,8 +98,8 @@ struct Carver {
 
 struct ProblemPtrs {
   double2* ktab;
-  double2* khat64;
-  float2* khat32;
+  double2* spec64;  // spectrum rows in the K-matvec's split order
+  float2* spec32;
   double2* tw64;
   float2* tw32;
   double* w2m;
@@ -127,12 +127,13 @@ size_t layout_problem(const lsp_plan* pl, int precision, void* base, ProblemPtrs
   const Plan& P = pl->p;
   Carver cv(base);
   ProblemPtrs q{};
-  long long n1d = 1, hd = 1, Ld = 1;
-  for (int a = 0; a < P.d; ++a) { n1d *= P.n + 1; hd *= P.n + 1; Ld *= P.L; }
+  long long n1d = 1, hd = P.L, Ld = 1;
+  for (int a = 0; a < P.d; ++a) { n1d *= P.n + 1; Ld *= P.L; }
+  for (int a = 1; a < P.d; ++a) hd *= P.n + 1;
   const int S = kMaxStencil;
   q.ktab = cv.take<double2>(n1d);
-  q.khat64 = cv.take<double2>(hd);
-  q.khat32 = cv.take<float2>(hd);
+  q.spec64 = cv.take<double2>(hd);
+  q.spec32 = cv.take<float2>(hd);
   q.w2m = cv.take<double>(P.N);
   q.Mval = cv.take<double2>((size_t)P.N * (P.d == 2 ? 9 : 27));
   q.alpha_pad = cv.take<double2>((size_t)pl->nclass * S);
@@ -629,7 +630,7 @@ bool read_tile_line(const std::string& path, const Plan& P, std::vector<int>& ti
 }
 
 template <typename T>
-FftPlanDev<T> make_fft_plan(const Plan& P, const cplx<T>* tw, const cplx<T>* khat) {
+FftPlanDev<T> make_fft_plan(const Plan& P, const cplx<T>* tw, const cplx<T>* spec) {
   FftPlanDev<T> f{};
   f.n = P.n; f.d = P.d; f.L = P.L; f.N = P.N;
   bool has3 = false;
@@ -645,7 +646,27 @@ FftPlanDev<T> make_fft_plan(const Plan& P, const cplx<T>* tw, const cplx<T>* kha
   f.wstride = Ld;
   f.rad.npass = (int)P.radices.size();
   for (int i = 0; i < f.rad.npass; ++i) f.rad.r[i] = P.radices[i];
-  f.tw = tw; f.khat = khat;
+  // the n-point transforms of the K-matvec: n = 2^a 3^b
+  {
+    int r = P.n, a = 0, b = 0;
+    while (r % 2 == 0) { r /= 2; ++a; }
+    while (r % 3 == 0) { r /= 3; ++b; }
+    std::vector<int> rad;
+    if (b == 0) {
+      f.hept = a >= 3 ? 8 : P.n;
+      if (a % 3) rad.push_back(1 << (a % 3));
+      for (int k = 0; k < a / 3; ++k) rad.push_back(8);
+    } else {
+      f.hept = 3 << std::min(a, 2);
+      for (int k = 0; k < a / 2; ++k) rad.push_back(4);
+      if (a % 2) rad.push_back(2);
+      for (int k = 0; k < b; ++k) rad.push_back(3);
+    }
+    LSP_REQUIRE(r == 1 && (int)rad.size() <= 16, "n must be 2^a 3^b");
+    f.hrad.npass = (int)rad.size();
+    for (int i = 0; i < f.hrad.npass; ++i) f.hrad.r[i] = rad[i];
+  }
+  f.tw = tw; f.spec = spec;
   return f;
 }
 
@@ -910,8 +931,8 @@ lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, vo
     pb->d.geo = pd.geo;
     pb->d.tw64 = pd.tw64;
     pb->d.tw32 = pd.tw32;
-    pb->fp64 = make_fft_plan<double>(P, pb->d.tw64, pb->d.khat64);
-    pb->fp32 = make_fft_plan<float>(P, pb->d.tw32, pb->d.khat32);
+    pb->fp64 = make_fft_plan<double>(P, pb->d.tw64, pb->d.spec64);
+    pb->fp32 = make_fft_plan<float>(P, pb->d.tw32, pb->d.spec32);
 
     // kernel table, medium, spectrum
     double h = 1.0 / P.n;
@@ -919,7 +940,7 @@ lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, vo
     k_w2m(pb->d.w2m, m_dev, omega * omega, P.N, st);
     launch_embed(pb->d.E, pb->d.ktab, P.n, P.d, st);
     full_fft_forward<double>(pb->fp64, pb->d.E, st);
-    launch_fold_khat(pb->d.khat64, pb->d.khat32, pb->d.E, P.n, P.d, st);
+    launch_split_spectrum(pb->d.spec64, pb->d.spec32, pb->d.E, P.n, P.d, st);
     // stencils and the sparse matrix
     compute_stencils(pb->d.ktab, P.n, P.d, pb->d.geo, plan->nclass, plan->maxF, pb->d.partial, plan->gram_blocks,
                      pb->d.G, pb->d.U1, pb->d.alpha_pad, pb->d.C_pad, pb->d.sigma_pad, st);

@@ -26,11 +26,11 @@ SOURCE = {"fwd": "frontal.hip", "bwd": "frontal.hip", "diag_lu": "frontal.hip", 
           "form_bwd": "frontal.hip", "bsweep": "sweep.hip", "sdense": "sweep.hip",
           "fwd_sdense": "sweep.hip", "bwd_sdense": "sweep.hip", "sdense_form_fwd": "sweep.hip",
           "sdense_form_bwd": "sweep.hip",
-          "fft_lines": "fft.hip",
+          "half_lines": "fft.hip", "full_lines": "fft.hip",
           "gram": "stencil.hip", "gram_reduce": "stencil.hip", "eigen": "stencil.hip", "applyQ": "stencil.hip",
           "dots_partial": "krylov.hip", "dots_final": "krylov.hip", "axpy": "krylov.hip", "cgs": "krylov.hip",
           "scale_norm": "krylov.hip", "givens": "krylov.hip", "ktable": "greens.hip"}
-FFT_MODE = {"0": "fft_axis", "1": "fft_first", "2": "fft_conv", "3": "fft_last"}
+FFT_KIND = {"0": "fft_first", "1": "fft_axis_fwd", "2": "fft_conv", "3": "fft_axis_inv", "4": "fft_last"}
 
 
 def short(name):
@@ -46,8 +46,10 @@ def registry_key(name):
         return None, None
     base, targs = m.group(1), (m.group(2) or "")
     args = [a.strip() for a in targs.split(",")] if targs else []
-    if base == "fft_lines" and len(args) == 3:
-        base = FFT_MODE.get(args[2], base)
+    if base == "half_lines" and len(args) == 4:
+        base = FFT_KIND.get(args[2], base)
+    if base == "full_lines":
+        base = "fft_full"
     if base == "gemm_update" and args and args[-1] == "true":
         base = "update_lu"  # fused with the next diagonal-block factorisation
     if base in ("fwd_small", "bwd_small"):
