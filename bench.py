@@ -156,9 +156,10 @@ def kernel_model(base, tag, st, w, nrhs, counts):
         # n values in and out per line, the spectrum rows once
         per = L ** (d - 1) * 2 * n * esz * nrhs + (n + 1) ** (d - 1) * L * esz
         return "hbm", counts.get(f"fft_conv [{tag}]", 0) * per, "GB/s"
-    if base in ("fwd_sdense", "bwd_sdense"):
-        # the formed small-front operators (Gf or Gb, m x p per front)
-        return "hbm", apps * st["sdense_entries"] * esz, "GB/s"
+    if base in ("fwd_mchain", "bwd_mchain"):
+        # the small-front levels' factor entries (their fronts' vectors are
+        # a small part of the fields)
+        return "hbm", apps * st["mchain_entries"] * esz, "GB/s"
     return None
 
 

@@ -82,11 +82,13 @@ typedef struct {
                         forward and backward sweep operators (2 m p entries
                         per front) and the sweeps apply them as dense
                         products; in plans for blocks of right-hand sides
-                        (max_nrhs >= 4) also on the levels of more than 16
-                        fronts of at most 64 pivots and 256 rows (one
-                        product per front); 2: those small-front levels
-                        whatever max_nrhs; 0: every level uses the panel
-                        chain (or the blocked sweeps) */
+                        (max_nrhs >= 4) the levels of more than 16 fronts
+                        of at most 64 pivots and 256 rows are swept by
+                        panel chains on the matrix cores (one wave per
+                        front and group of 16 right-hand sides); 2: those
+                        small-front levels whatever max_nrhs; 0: every
+                        level uses the panel chain (or the blocked
+                        sweeps) */
   int blocked_sweeps; /* 1 (default): on the levels (not swept with dense
                         operators) whose fronts have more than 1024 rows,
                         or with at most 32 fronts of more than two panels,
@@ -173,10 +175,11 @@ typedef struct {
                                  the panel-strip launches) */
   double assemble_entries;    /* front entries the assembly writes plus the
                                  children's update-matrix entries it reads */
-  int sdense_levels;          /* small-front levels swept with formed
-                                 operators (dense_sweeps) */
-  double sdense_entries;      /* entries of their operators one sweep reads
-                                 (sum of m p over their fronts) */
+  int mchain_levels;          /* small-front levels swept by panel chains
+                                 on the matrix cores (dense_sweeps) */
+  double mchain_entries;      /* factor entries one sweep of them reads
+                                 (inverse diagonal blocks and the panels'
+                                 entries below or right of them) */
 } lsp_plan_stats;
 
 typedef struct lsp_plan lsp_plan;        /* opaque; host-side, plus one device copy of

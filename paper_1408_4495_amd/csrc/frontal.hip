@@ -24,6 +24,7 @@
 
 #include "lsp_common.h"
 #include "kernels.h"
+#include "mfma.h"
 
 namespace lsp {
 
@@ -451,23 +452,6 @@ __device__ __forceinline__ void chunked(Load&& load, Use&& use) {
 
 
 // ---------------------------------------------------------------- panel products
-// ---------------------------------------------------------------- MFMA helpers
-// Operand layout of the 16x16x4 MFMAs: lane l supplies A(l%16, l/16) and
-// B(l/16, l%16).  Results: the FP32 form returns D(4*(l/16)+v, l%16), the
-// FP64 form D(l/16+4v, l%16), v = 0..3 (checked on gfx950).
-template <typename T> struct Mfma;
-template <> struct Mfma<double> {
-  using acc_t = __attribute__((__vector_size__(4 * sizeof(double)))) double;
-  __device__ static acc_t step(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  __device__ static int row(int lk, int v) { return lk + 4 * v; }
-};
-template <> struct Mfma<float> {
-  using acc_t = __attribute__((__vector_size__(4 * sizeof(float)))) float;
-  __device__ static acc_t step(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  __device__ static int row(int lk, int v) { return 4 * lk + v; }
-};
-
-
 // blockIdx.z == 0: U12(:, tile) = L11^{-1} P F12(:, tile), 64 columns per block.
 // blockIdx.z == 1: L21(tile, :) = F21(tile, :) U11^{-1}, 64 rows per block.
 // Every load is issued before the first LDS store (clamped in-range indices,
@@ -1871,7 +1855,7 @@ void form_level(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st) {
 // Formation of dense level l once its factorisation is enqueued on st.
 template <typename T>
 void form_after(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st, const FormStream* fs) {
-  if (!plan.level_dense[l] && !plan.level_blocked[l] && !plan.level_sdense[l]) return;
+  if (!plan.level_dense[l] && !plan.level_blocked[l]) return;
   hipStream_t fst = st;
   if (fs) {
     LSP_HIP(hipEventRecord(fs->level, st));
@@ -1879,7 +1863,6 @@ void form_after(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st, con
     fst = fs->aux;
   }
   if (plan.level_blocked[l]) blocked_form<T>(mf, plan, l, fst);
-  else if (plan.level_sdense[l]) sdense_form<T>(mf, plan, l, fst);
   else if (wide_level(plan, l)) form_level<T, 512>(mf, plan, l, fst);
   else form_level<T, 256>(mf, plan, l, fst);
 }
@@ -1889,12 +1872,12 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
                   const SweepBufs<T>& sb, hipStream_t st, hipEvent_t form_done, double2* xw) {
   const int groups = (nrhs + NR - 1) / NR;
   for (int l = 0; l < plan.nlevels; ++l) {
-    if ((plan.level_dense[l] || plan.level_blocked[l] || plan.level_sdense[l]) && form_done) {
+    if ((plan.level_dense[l] || plan.level_blocked[l]) && form_done) {
       LSP_HIP(hipStreamWaitEvent(st, form_done, 0));
       form_done = nullptr;
     }
-    if (plan.level_sdense[l]) {
-      sdense_sweep<T>(true, mf, plan, l, nrhs, z, x, vbuf, st, xw);
+    if (plan.level_mchain[l]) {
+      mchain_sweep<T>(true, mf, plan, l, nrhs, z, x, vbuf, st, xw);
       continue;
     }
     if constexpr (NR == 1) {
@@ -1912,8 +1895,8 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
     else sweep_fwd<T, NR, 256>(mf, plan, l, groups, nrhs, z, vbuf, st);
   }
   for (int l = plan.nlevels - 1; l >= 0; --l) {
-    if (plan.level_sdense[l]) {
-      sdense_sweep<T>(false, mf, plan, l, nrhs, z, x, vbuf, st, xw);
+    if (plan.level_mchain[l]) {
+      mchain_sweep<T>(false, mf, plan, l, nrhs, z, x, vbuf, st, xw);
       continue;
     }
     if constexpr (sizeof(T) == 4 && NR == 1) {

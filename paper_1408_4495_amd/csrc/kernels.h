@@ -127,16 +127,12 @@ void mf_solve(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>* z, 
 template <typename T>
 void blocked_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
                    cplx<T>* vbuf, const SweepBufs<T>& sb, hipStream_t st, double2* xw);
-// Sweep of a small-front level with formed operators (Plan::level_sdense):
-// per front one product with Gf (forward) or Gb (backward), formed by the
-// dense levels' formation at the front's g_off.
+// Sweep of a small-front level (Plan::level_mchain): per front and group of
+// 16 right-hand sides one wave runs the panel chain on the matrix cores.
+// Same inputs and outputs as the panel-chain sweeps of that level.
 template <typename T>
-void sdense_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
+void mchain_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
                   cplx<T>* vbuf, hipStream_t st, double2* xw);
-// Forms the operators of small dense level l (one workgroup per front and
-// chunk of unit vectors, the chains in LDS).
-template <typename T>
-void sdense_form(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st);
 // Forms the super-block operators of blocked level l from its factor (the
 // panel chains on the unit vectors), into mf.G at each front's g_off.
 template <typename T>

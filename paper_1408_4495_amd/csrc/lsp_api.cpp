@@ -834,8 +834,8 @@ lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* s) {
   s->blocked_panel_entries = P.blocked_panel_entries;
   s->trsm_flops = fs.trsm_flops;
   s->assemble_entries = P.assemble_entries;
-  s->sdense_levels = P.sdense_levels;
-  s->sdense_entries = P.sdense_entries;
+  s->mchain_levels = P.mchain_levels;
+  s->mchain_entries = P.mchain_entries;
   return LSP_OK;
 }
 
@@ -957,7 +957,7 @@ lsp_status lsp_factor(lsp_problem* pb) {
   return guarded([&]() -> lsp_status {
     LSP_REQUIRE(pb != nullptr, "null problem");
     const Plan& P = pb->plan->p;
-    if (P.dense_levels + P.blocked_levels + P.sdense_levels > 0 && !pb->fs.aux) {
+    if (P.dense_levels + P.blocked_levels > 0 && !pb->fs.aux) {
       int cur = 0;
       LSP_HIP(hipGetDevice(&cur));
       if (cur != pb->device) LSP_HIP(hipSetDevice(pb->device));

@@ -240,27 +240,23 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
       ok = P.fronts[i].q + P.fronts[i].p - std::min(P.fronts[i].p, P.nb) <= 128;
     P.level_small_sweep[l] = ok;
   }
-  P.level_sdense.assign(P.nlevels, 0);
-  P.sdense_levels = 0;
-  P.sdense_entries = 0.0;
+  // small-front levels (more than 16 fronts of at most two panels and 256
+  // rows) of plans for blocks of right-hand sides: panel chains with the
+  // right-hand sides on the matrix cores
+  P.level_mchain.assign(P.nlevels, 0);
+  P.mchain_levels = 0;
+  P.mchain_entries = 0.0;
   for (int l = 0; l < P.nlevels; ++l) {
     const int cnt = P.level_ptr[l + 1] - P.level_ptr[l];
     const bool want = opts.dense_sweeps == 2 || (opts.dense_sweeps == 1 && max_nrhs >= 4);
-    if (!want || P.level_dense[l] || cnt <= 16 || P.level_maxp[l] > 64 || P.level_maxpq[l] > 256) continue;
-    P.level_sdense[l] = 1;
-    ++P.sdense_levels;
-  }
-  for (FrontDev& f : P.fronts) {
-    if (!P.level_sdense[f.level]) continue;
-    const long long m = f.p + f.q;
-    f.g_off = P.dense_elems;
-    P.dense_elems += 2 * m * f.p;
-    P.sdense_entries += (double)m * f.p;
+    if (!want || P.level_dense[l] || cnt <= 16 || P.level_maxp[l] > 2 * P.nb || P.level_maxpq[l] > 256) continue;
+    P.level_mchain[l] = 1;
+    ++P.mchain_levels;
   }
   P.level_blocked.assign(P.nlevels, 0);
   for (int l = 0; l < P.nlevels; ++l) {
     const int cnt = P.level_ptr[l + 1] - P.level_ptr[l];
-    if (opts.blocked_sweeps == 0 || P.level_dense[l] || P.level_sdense[l] || P.level_small_sweep[l]) continue;
+    if (opts.blocked_sweeps == 0 || P.level_dense[l] || P.level_mchain[l] || P.level_small_sweep[l]) continue;
     P.level_blocked[l] = opts.blocked_sweeps == 2 || P.level_maxpq[l] > 1024 ||
                          (cnt <= 32 && P.level_maxp[l] > 2 * P.nb);
   }
@@ -296,8 +292,13 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
       P.assemble_entries += (double)m * m;
       if (f.child0 >= 0) P.assemble_entries += (double)P.fronts[f.child0].q * P.fronts[f.child0].q;
       if (f.child1 >= 0) P.assemble_entries += (double)P.fronts[f.child1].q * P.fronts[f.child1].q;
-      if (P.level_dense[f.level] || P.level_sdense[f.level]) continue;
-      if (P.level_blocked[f.level]) {
+      if (P.level_dense[f.level]) continue;
+      if (P.level_mchain[f.level]) {
+        for (int k0 = 0; k0 < f.p; k0 += P.nb) {
+          const int kb = std::min(P.nb, f.p - k0);
+          P.mchain_entries += (double)(m - k0 - kb) * kb + (double)P.nb * P.nb;
+        }
+      } else if (P.level_blocked[f.level]) {
         for (long long s0 = 0; s0 < f.p; s0 += SB) {
           const long long s1 = std::min<long long>(s0 + SB, f.p);
           P.blocked_panel_entries += (double)(m - s1) * (double)(s1 - s0);

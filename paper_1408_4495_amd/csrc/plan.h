@@ -63,9 +63,9 @@ struct Plan {
   // plans for blocks of right-hand sides (max_nrhs >= 4) unless
   // dense_sweeps = 2; their operators follow the dense levels' in the same
   // store (g_off).
-  std::vector<char> level_sdense;
-  int sdense_levels = 0;
-  double sdense_entries = 0.0;    // sum over their fronts of m p (one sweep's reads)
+  std::vector<char> level_mchain;  // small-front levels swept by matrix-core panel chains
+  int mchain_levels = 0;
+  double mchain_entries = 0.0;     // factor entries one sweep of them reads
   // Levels swept by the blocked kernels (sweep.hip): not dense, not small,
   // and either fronts of more than 1024 rows or at most 32 fronts with more
   // than two panels.

@@ -38,6 +38,7 @@
 
 #include "lsp_common.h"
 #include "kernels.h"
+#include "mfma.h"
 
 namespace lsp {
 
@@ -482,17 +483,25 @@ void blocked_level_bwd(const MfDev<T>& mf, const Plan& plan, int l, int nrhs, cp
   }
 }
 
-// ---- small-front levels with formed operators (Plan::level_sdense)
+// ---- small-front levels: panel chains on the matrix cores (Plan::level_mchain)
 //
-// Fronts of at most 64 pivots and 256 rows, many per level: the forward
-// sweep of a front is [0; v_B] + Gf v_I (Gf = m x p, the forward panel chain
-// run on the unit vectors, column-major at g_off) and the backward one
-// x_I = Gb [y_I; x_B] (Gb^T = m x p column-major after Gf), so a front's
-// sweep is one product with no sequential chain.  One workgroup per (front,
-// group of NR right-hand sides); a right-hand side's sums run over the
-// columns in order, whatever the group.
-constexpr int SDP = 64;   // largest p of a small dense level
-constexpr int SDM = 256;  // largest m
+// Fronts of at most two panels (p <= 64) and 256 rows, many per level.  One
+// wave per (front, group of 16 right-hand sides) runs the front's panel
+// chain with the right-hand sides as the 16 columns of 16x16x4 MFMA
+// products (complex as four real products):
+//   forward, per panel b:   y_b = L11_b^{-1} (P_b v_b)       (32 x 32 by 32 x 16)
+//                           v(k1:m) -= L21_b y_b              (16-row tiles)
+//   backward, per panel from the last:
+//                           t_b = y_b - U12_b x(k1:m)         (32 x (m - k1) by (m - k1) x 16)
+//                           x_b = U11_b^{-1} t_b
+// (the inverse blocks are exactly zero outside their kb x kb part, and the
+// operands past kb are zeroed).  The front's vectors stay in LDS, V[row][16].
+// Each output column of an MFMA is its own sum, so a right-hand side's
+// result does not depend on the others in its group: batched and solo solves
+// agree bit for bit.
+constexpr int MC = 16;    // right-hand sides per wave
+constexpr int MCP = 64;   // largest p of a matrix-core chain level
+constexpr int MCM = 256;  // largest m
 
 template <typename T>
 __device__ __forceinline__ cplx<T> front_input(const FrontDev& f, const int* __restrict__ id,
@@ -507,217 +516,220 @@ __device__ __forceinline__ cplx<T> front_input(const FrontDev& f, const int* __r
   return s;
 }
 
-template <typename T, int NR, int TPB>
-__global__ void __launch_bounds__(TPB) sdense_fwd_kernel(const cplx<T>* __restrict__ Gop,
-                                                         const FrontDev* __restrict__ fr, const int* __restrict__ idx,
-                                                         const int* __restrict__ cpos, const cplx<T>* __restrict__ z,
-                                                         cplx<T>* __restrict__ vbuf, int first, int nrhs, long long N,
-                                                         long long vstride) {
-  __shared__ cplx<T> vin[NR][SDP];
+template <typename T>
+struct CAcc {
+  typename Mfma<T>::acc_t re, im;
+  __device__ void zero() {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { re[v] = 0; im[v] = 0; }
+  }
+  __device__ cplx<T> at(int v) const { return mk<T>(re[v], im[v]); }
+};
+
+// c += a b with a from operand A, b from operand B (complex)
+template <typename T>
+__device__ __forceinline__ void cstep(CAcc<T>& c, const cplx<T> a, const cplx<T> b) {
+  c.re = Mfma<T>::step(a.x, b.x, c.re);
+  c.re = Mfma<T>::step(-a.y, b.y, c.re);
+  c.im = Mfma<T>::step(a.x, b.y, c.im);
+  c.im = Mfma<T>::step(a.y, b.x, c.im);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) mchain_fwd_kernel(const cplx<T>* __restrict__ Fbuf,
+                                                        const cplx<T>* __restrict__ Dinv,
+                                                        const FrontDev* __restrict__ fr, const int* __restrict__ idx,
+                                                        const int* __restrict__ cpos, const int* __restrict__ perm,
+                                                        const cplx<T>* __restrict__ z, cplx<T>* __restrict__ vbuf,
+                                                        int first, int nrhs, long long N, long long vstride) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* V = reinterpret_cast<cplx<T>*>(smem_raw);  // V[r * MC + k]
   const FrontDev f = fr[first + blockIdx.x];
   const int p = f.p, m = p + f.q;
-  const int r0 = blockIdx.y * NR, nr = min(NR, nrhs - r0);
+  const int r0 = blockIdx.y * MC, nr = min(MC, nrhs - r0);
+  const int lane = threadIdx.x, li = lane % 16, lk = lane / 16;
+  const cplx<T>* F = Fbuf + f.f_off;
   const int* id = idx + f.idx_off;
   const int* cp = cpos + 2 * f.idx_off;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NR * SDP; e += TPB) {
-    const int k = e / SDP, c = e % SDP;
-    if (k < nr && c < p) vin[k][c] = front_input<T>(f, id, cp, z, vbuf, c, r0 + k, N, vstride);
-  }
-  __syncthreads();
-  const cplx<T>* G = Gop + f.g_off;
-  for (int r = tid; r < m; r += TPB) {
-    cplx<T> acc[NR];
+  const int* pm = perm + f.piv_off;
+  // v = [z(I); 0] + children's updates: a row per lane, the row's index
+  // loads first, then its 16 right-hand sides' loads together
+  for (int r = lane; r < m; r += 64) {
+    const int gi = id[min(r, p - 1)];
+    const int q0 = f.cidx[0] >= 0 ? cp[2 * r] : -1, q1 = f.cidx[1] >= 0 ? cp[2 * r + 1] : -1;
+    cplx<T> val[MC];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
-    for (int c0 = 0; c0 < p; c0 += 16) {
-      cplx<T> g[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) g[u] = G[(long long)min(c0 + u, p - 1) * m + r];
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (c0 + u < p)
-#pragma unroll
-          for (int k = 0; k < NR; ++k) acc[k] = cfma(acc[k], g[u], vin[min(k, nr - 1)][c0 + u]);
+    for (int k = 0; k < MC; ++k) {
+      const cplx<T> zv = z[(long long)(r0 + min(k, nr - 1)) * N + gi];
+      val[k] = k < nr && r < p ? zv : mk<T>(0, 0);
     }
+    if (q0 >= 0) {
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      if (k >= nr) break;
-      const cplx<T> out = r >= p ? cadd(front_input<T>(f, id, cp, z, vbuf, r, r0 + k, N, vstride), acc[k]) : acc[k];
-      vbuf[(long long)(r0 + k) * vstride + f.idx_off + r] = out;
-    }
-  }
-}
-
-// Four lanes per pivot row i (lane j4 sums the columns j = j4 + 4u), the
-// partial sums combined by an xor butterfly (every lane ends with the same
-// value).
-template <typename T, int NR>
-__global__ void __launch_bounds__(256) sdense_bwd_kernel(const cplx<T>* __restrict__ Gop,
-                                                         const FrontDev* __restrict__ fr, const int* __restrict__ idx,
-                                                         cplx<T>* __restrict__ x, const cplx<T>* __restrict__ vbuf,
-                                                         int first, int nrhs, long long N, long long vstride,
-                                                         double2* __restrict__ xw) {
-  __shared__ cplx<T> vin[NR][SDM];
-  const FrontDev f = fr[first + blockIdx.x];
-  const int p = f.p, m = p + f.q;
-  const int r0 = blockIdx.y * NR, nr = min(NR, nrhs - r0);
-  const int* id = idx + f.idx_off;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NR * SDM; e += 256) {
-    const int k = e / SDM, j = e % SDM;
-    if (k < nr && j < m)
-      vin[k][j] = j < p ? vbuf[(long long)(r0 + k) * vstride + f.idx_off + j] : x[(long long)(r0 + k) * N + id[j]];
-  }
-  __syncthreads();
-  const int i = tid / 4, j4 = tid % 4;
-  const int ii = min(i, p - 1);
-  const cplx<T>* G = Gop + f.g_off + (long long)m * p + (long long)ii * m;  // row ii of Gb
-  cplx<T> acc[NR];
-#pragma unroll
-  for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
-  for (int j0 = 0; j0 < m; j0 += 4 * 16) {
-    cplx<T> g[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) g[u] = G[min(j0 + j4 + 4 * u, m - 1)];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int j = j0 + j4 + 4 * u;
-      if (j < m)
-#pragma unroll
-        for (int k = 0; k < NR; ++k) acc[k] = cfma(acc[k], g[u], vin[min(k, nr - 1)][j]);
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < NR; ++k) {
-#pragma unroll
-    for (int off = 1; off < 4; off <<= 1) {
-      acc[k].x += __shfl_xor(acc[k].x, off, 64);
-      acc[k].y += __shfl_xor(acc[k].y, off, 64);
-    }
-  }
-  if (j4 == 0 && i < p) {
-    const long long gi = id[i];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      if (k < nr) {
-        x[(long long)(r0 + k) * N + gi] = acc[k];
-        if (xw) xw[(long long)(r0 + k) * N + gi] = widen(acc[k]);
+      for (int k = 0; k < MC; ++k) {
+        const cplx<T> c = vbuf[(long long)(r0 + min(k, nr - 1)) * vstride + f.cidx[0] + q0];
+        if (k < nr) val[k] = cadd(val[k], c);
       }
     }
-  }
-}
-
-// Formation of a small front's operators: the forward panel chain (TRANS:
-// the transposed backward chain, U^T in place of P^T L, whose output for e_i
-// is row i of Gb) run on ncol unit vectors at once (columns c0 .. c0 + ncol
-// of the identity, blockIdx.y the chunk), the m x ncol block V in LDS (row
-// stride ncol + 1).  Per panel: the gathered rows times the inverted
-// diagonal block, then the rows below updated with the panel's L21 rows
-// (U12 columns), staged in LDS; thread t updates column t % ncol of the rows
-// t / ncol, t / ncol + 256 / ncol, ...  Written as columns of Gf (TRANS: of
-// Gb^T).
-constexpr int SFR = 128;  // rows of a staged panel chunk in the formation
-
-template <typename T, bool TRANS>
-__global__ void __launch_bounds__(256) sdense_form_kernel(const cplx<T>* __restrict__ Fbuf,
-                                                          const cplx<T>* __restrict__ Dinv,
-                                                          const FrontDev* __restrict__ fr, const int* __restrict__ perm,
-                                                          cplx<T>* __restrict__ Gop, int first, int ncol) {
-  extern __shared__ unsigned char smem_raw[];
-  const FrontDev f = fr[first + blockIdx.x];
-  const int p = f.p, m = p + f.q;
-  const int c0 = blockIdx.y * ncol;
-  if (c0 >= p) return;
-  const int nc = min(ncol, p - c0), ldv = ncol + 1;
-  cplx<T>* V = reinterpret_cast<cplx<T>*>(smem_raw);  // V[r * ldv + c]
-  cplx<T>* tb = V + (long long)m * ldv;               // tb[j * ncol + c]
-  cplx<T>(*Li)[PB + 1] = reinterpret_cast<cplx<T>(*)[PB + 1]>(tb + PB * ncol);
-  cplx<T>* Lp = reinterpret_cast<cplx<T>*>(Li + PB);  // Lp[r' * (PB + 1) + j], r' = r - k1
-  const cplx<T>* F = Fbuf + f.f_off;
-  const int* pm = perm + f.piv_off;
-  const int tid = threadIdx.x;
-  const int cc = tid % ncol, rg = tid / ncol, ng = 256 / ncol;
-  for (int e = tid; e < m * ncol; e += 256) {
-    const int r = e / ncol, c = e % ncol;
-    V[r * ldv + c] = mk<T>(r == c0 + c ? 1 : 0, 0);
+    if (q1 >= 0) {
+#pragma unroll
+      for (int k = 0; k < MC; ++k) {
+        const cplx<T> c = vbuf[(long long)(r0 + min(k, nr - 1)) * vstride + f.cidx[1] + q1];
+        if (k < nr) val[k] = cadd(val[k], c);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < MC; ++k) V[r * MC + k] = val[k];
   }
   for (int k0 = 0; k0 < p; k0 += PB) {
     const int kb = min(PB, p - k0), k1 = k0 + kb, nb = m - k1;
-    const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(k0 / PB) * 2 * PB * PB + (TRANS ? PB * PB : 0);
-    __syncthreads();  // the previous panel's updates of V and reads of Lp are complete
-    for (int e = tid; e < PB * PB; e += 256) {
-      const int i = e % PB, j = e / PB;  // entry (i, j) of the column-major block
-      if constexpr (TRANS) Li[j][i] = Lg[e];
-      else Li[i][j] = Lg[e];
+    const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(k0 / PB) * 2 * PB * PB;
+    __syncthreads();  // v is complete
+    // y_b = L11^{-1} P_b v_b: operand A the inverse block (column-major),
+    // operand B the gathered rows
+    CAcc<T> y[2];
+    y[0].zero();
+    y[1].zero();
+#pragma unroll
+    for (int s4 = 0; s4 < PB / 4; ++s4) {
+      const int j = 4 * s4 + lk;
+      const int src = pm[k0 + min(j, kb - 1)];
+      const cplx<T> tv = V[src * MC + li];
+      const cplx<T> b = j < kb ? tv : mk<T>(0, 0);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) cstep(y[h], Lg[(16 * h + li) + PB * j], b);
     }
-    for (int e = tid; e < PB * ncol; e += 256) {
-      const int j = e / ncol, c = e % ncol;
-      const int src = j < kb ? (TRANS ? k0 + j : pm[k0 + j]) : k0;
-      tb[e] = j < kb ? V[src * ldv + c] : mk<T>(0, 0);
-    }
+    __syncthreads();  // every gather of the panel's rows is done
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * h + Mfma<T>::row(lk, v);
+        if (i < kb) V[(k0 + i) * MC + li] = y[h].at(v);
+      }
     __syncthreads();
-    for (int e = tid; e < PB * ncol; e += 256) {
-      const int i = e / ncol, c = e % ncol;
-      if (i < kb) {
-        // the inverse block is zero outside its kb x kb part and tb's rows
-        // past kb are zero, so all 32 terms are summed (exact zeros beyond)
-        cplx<T> acc = mk<T>(0, 0);
+    // v(k1:m) -= L21 y_b, 16 rows at a time: operand A the rows of L21
+    for (int t0 = 0; t0 < nb; t0 += 16) {
+      CAcc<T> u;
+      u.zero();
+      const int rr = k1 + min(t0 + li, nb - 1);
 #pragma unroll
-        for (int j = 0; j < PB; ++j) acc = cfma(acc, Li[i][j], tb[j * ncol + c]);
-        V[(k0 + i) * ldv + c] = acc;
+      for (int s4 = 0; s4 < PB / 4; ++s4) {
+        const int j = 4 * s4 + lk;
+        const cplx<T> lv = F[(long long)(k0 + min(j, kb - 1)) * m + rr];
+        const cplx<T> yv = V[(k0 + min(j, kb - 1)) * MC + li];
+        cstep(u, j < kb ? lv : mk<T>(0, 0), j < kb ? yv : mk<T>(0, 0));
       }
-    }
-    // the rows below in chunks of SFR: the panel's entries there, L(r, k0 + j)
-    // (TRANS: U(k0 + j, r)), staged in LDS along the matrix's contiguous
-    // direction, then the update
-    for (int rc = 0; rc < nb; rc += SFR) {
-      const int nrw = min(SFR, nb - rc);
-      __syncthreads();  // the previous chunk's reads of Lp (and the Y rows above) are complete
-      for (int e = tid; e < nrw * kb; e += 256) {
-        int rr, j;
-        if constexpr (TRANS) { rr = e / kb; j = e % kb; }
-        else { rr = e % nrw; j = e / nrw; }
-        const int r = k1 + rc + rr;
-        Lp[rr * (PB + 1) + j] = TRANS ? F[(long long)(k0 + j) + (long long)r * m] : F[(long long)(k0 + j) * m + r];
-      }
-      __syncthreads();
-      for (int rr = rg; rr < nrw; rr += ng) {
-        const int r = k1 + rc + rr;
-        cplx<T> acc = V[r * ldv + cc];
 #pragma unroll
-        for (int j = 0; j < PB; ++j)
-          if (j < kb) acc = cfms(acc, Lp[rr * (PB + 1) + j], V[(k0 + j) * ldv + cc]);
-        V[r * ldv + cc] = acc;
+      for (int v = 0; v < 4; ++v) {
+        const int r = t0 + Mfma<T>::row(lk, v);
+        if (r < nb) {
+          const cplx<T> o = V[(k1 + r) * MC + li];
+          V[(k1 + r) * MC + li] = csub(o, u.at(v));
+        }
       }
     }
   }
   __syncthreads();
-  cplx<T>* G = Gop + f.g_off + (TRANS ? (long long)m * p : 0LL);
-  for (int e = tid; e < m * nc; e += 256) {
-    const int c = e / m, r = e % m;
-    G[(long long)(c0 + c) * m + r] = V[r * ldv + c];
+  for (int e = lane; e < m * nr; e += 64) {
+    const int r = e % m, k = e / m;
+    vbuf[(long long)(r0 + k) * vstride + f.idx_off + r] = V[r * MC + k];
   }
 }
 
-template <typename T, int NR>
-void sdense_dispatch(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
-                     cplx<T>* vbuf, hipStream_t st, double2* xw) {
-  const int first = plan.level_ptr[l];
-  const int cnt = plan.level_ptr[l + 1] - first;
-  const int groups = (nrhs + NR - 1) / NR;
-  if (fwd) {
-    if (plan.level_maxpq[l] <= 128)
-      LSP_LAUNCH("fwd_sdense", (int)sizeof(cplx<T>), (sdense_fwd_kernel<T, NR, 128>), dim3(cnt, groups), dim3(128),
-                 0, st, mf.G, mf.fronts, mf.idx, mf.cpos, z, vbuf, first, nrhs, (long long)plan.N,
-                 (long long)plan.sum_pq);
-    else
-      LSP_LAUNCH("fwd_sdense", (int)sizeof(cplx<T>), (sdense_fwd_kernel<T, NR, 256>), dim3(cnt, groups), dim3(256),
-                 0, st, mf.G, mf.fronts, mf.idx, mf.cpos, z, vbuf, first, nrhs, (long long)plan.N,
-                 (long long)plan.sum_pq);
-  } else {
-    LSP_LAUNCH("bwd_sdense", (int)sizeof(cplx<T>), (sdense_bwd_kernel<T, NR>), dim3(cnt, groups), dim3(256), 0, st,
-               mf.G, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq, xw);
+template <typename T>
+__global__ void __launch_bounds__(64) mchain_bwd_kernel(const cplx<T>* __restrict__ Fbuf,
+                                                        const cplx<T>* __restrict__ Dinv,
+                                                        const FrontDev* __restrict__ fr, const int* __restrict__ idx,
+                                                        cplx<T>* __restrict__ x, const cplx<T>* __restrict__ vbuf,
+                                                        int first, int nrhs, long long N, long long vstride,
+                                                        double2* __restrict__ xw) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* V = reinterpret_cast<cplx<T>*>(smem_raw);  // V[r * MC + k]
+  const FrontDev f = fr[first + blockIdx.x];
+  const int p = f.p, m = p + f.q;
+  const int r0 = blockIdx.y * MC, nr = min(MC, nrhs - r0);
+  const int lane = threadIdx.x, li = lane % 16, lk = lane / 16;
+  const cplx<T>* F = Fbuf + f.f_off;
+  const int* id = idx + f.idx_off;
+  // v = [y(I) from the forward sweep; x(B) from the ancestors]: a row per
+  // lane, its 16 right-hand sides' loads together
+  for (int r = lane; r < m; r += 64) {
+    cplx<T> val[MC];
+    if (r < p) {
+#pragma unroll
+      for (int k = 0; k < MC; ++k) val[k] = vbuf[(long long)(r0 + min(k, nr - 1)) * vstride + f.idx_off + r];
+    } else {
+      const long long gi = id[r];
+#pragma unroll
+      for (int k = 0; k < MC; ++k) val[k] = x[(long long)(r0 + min(k, nr - 1)) * N + gi];
+    }
+#pragma unroll
+    for (int k = 0; k < MC; ++k) V[r * MC + k] = k < nr ? val[k] : mk<T>(0, 0);
+  }
+  const int nblk = (p + PB - 1) / PB;
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int k0 = b * PB, kb = min(PB, p - k0), k1 = k0 + kb, nc = m - k1;
+    const cplx<T>* Ug = Dinv + f.dinv_off + (long long)b * 2 * PB * PB + PB * PB;
+    __syncthreads();  // x of the later panels is in place
+    // s = U12 x(k1:m): operand A the panel's rows of U12, four columns per step
+    CAcc<T> sa[2];
+    sa[0].zero();
+    sa[1].zero();
+    // 32 columns per pass: the pass's U12 loads first (clamped in range),
+    // then the products
+    for (int c0 = 0; c0 < nc; c0 += 32) {
+      cplx<T> ua[8][2];
+#pragma unroll
+      for (int s8 = 0; s8 < 8; ++s8) {
+        const long long col = (long long)(k1 + min(c0 + 4 * s8 + lk, nc - 1)) * m;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) ua[s8][h] = F[(k0 + min(16 * h + li, kb - 1)) + col];
+      }
+#pragma unroll
+      for (int s8 = 0; s8 < 8; ++s8) {
+        const int c = c0 + 4 * s8 + lk;
+        const cplx<T> xv = V[(k1 + min(c, nc - 1)) * MC + li];
+        const cplx<T> b4 = c < nc ? xv : mk<T>(0, 0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) cstep(sa[h], 16 * h + li < kb && c < nc ? ua[s8][h] : mk<T>(0, 0), b4);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * h + Mfma<T>::row(lk, v);
+        if (i < kb) V[(k0 + i) * MC + li] = csub(V[(k0 + i) * MC + li], sa[h].at(v));
+      }
+    __syncthreads();
+    // x_b = U11^{-1} t_b
+    CAcc<T> xa[2];
+    xa[0].zero();
+    xa[1].zero();
+#pragma unroll
+    for (int s4 = 0; s4 < PB / 4; ++s4) {
+      const int j = 4 * s4 + lk;
+      const cplx<T> tv = V[(k0 + min(j, kb - 1)) * MC + li];
+      const cplx<T> b4 = j < kb ? tv : mk<T>(0, 0);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) cstep(xa[h], Ug[(16 * h + li) + PB * j], b4);
+    }
+    __syncthreads();  // every read of t_b is done
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * h + Mfma<T>::row(lk, v);
+        if (i < kb) V[(k0 + i) * MC + li] = xa[h].at(v);
+      }
+  }
+  __syncthreads();
+  for (int e = lane; e < p * nr; e += 64) {
+    const int r = e % p, k = e / p;
+    const cplx<T> v = V[r * MC + k];
+    const long long gi = (long long)(r0 + k) * N + id[r];
+    x[gi] = v;
+    if (xw) xw[gi] = widen(v);
   }
 }
 
@@ -740,30 +752,19 @@ void blocked_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nr
 }
 
 template <typename T>
-void sdense_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
+void mchain_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
                   cplx<T>* vbuf, hipStream_t st, double2* xw) {
-  LSP_REQUIRE(plan.level_maxp[l] <= SDP && plan.level_maxpq[l] <= SDM, "small dense level exceeds its bounds");
-  if (nrhs >= 8) sdense_dispatch<T, 8>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
-  else if (nrhs >= 4) sdense_dispatch<T, 4>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
-  else if (nrhs >= 2) sdense_dispatch<T, 2>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
-  else sdense_dispatch<T, 1>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
-}
-
-template <typename T>
-void sdense_form(const MfDev<T>& mf, const Plan& plan, int l, hipStream_t st) {
+  LSP_REQUIRE(plan.level_maxp[l] <= MCP && plan.level_maxpq[l] <= MCM, "matrix-core chain level exceeds its bounds");
   const int first = plan.level_ptr[l];
   const int cnt = plan.level_ptr[l + 1] - first;
-  const int maxm = plan.level_maxpq[l], maxp = plan.level_maxp[l];
-  // unit vectors per workgroup: the most (64 .. 8) whose block fits 48 KB
-  int ncol = 64;
-  while (ncol > 8 && (size_t)maxm * (ncol + 1) * sizeof(cplx<T>) > 48 * 1024) ncol /= 2;
-  const size_t lds = ((size_t)maxm * (ncol + 1) + (size_t)PB * ncol + (size_t)PB * (PB + 1) +
-                      (size_t)SFR * (PB + 1)) * sizeof(cplx<T>);
-  const dim3 grid(cnt, (maxp + ncol - 1) / ncol);
-  LSP_LAUNCH("sdense_form_fwd", (int)sizeof(cplx<T>), (sdense_form_kernel<T, false>), grid, dim3(256), lds, st, mf.F,
-             mf.Dinv, mf.fronts, mf.perm, mf.G, first, ncol);
-  LSP_LAUNCH("sdense_form_bwd", (int)sizeof(cplx<T>), (sdense_form_kernel<T, true>), grid, dim3(256), lds, st, mf.F,
-             mf.Dinv, mf.fronts, mf.perm, mf.G, first, ncol);
+  const dim3 grid(cnt, (nrhs + MC - 1) / MC);
+  const size_t lds = (size_t)plan.level_maxpq[l] * MC * sizeof(cplx<T>);
+  if (fwd)
+    LSP_LAUNCH("fwd_mchain", (int)sizeof(cplx<T>), mchain_fwd_kernel<T>, grid, dim3(64), lds, st, mf.F, mf.Dinv,
+               mf.fronts, mf.idx, mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq);
+  else
+    LSP_LAUNCH("bwd_mchain", (int)sizeof(cplx<T>), mchain_bwd_kernel<T>, grid, dim3(64), lds, st, mf.F, mf.Dinv,
+               mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq, xw);
 }
 
 template <typename T>
@@ -782,12 +783,10 @@ template void blocked_sweep<double>(bool, const MfDev<double>&, const Plan&, int
                                     double2*, const SweepBufs<double>&, hipStream_t, double2*);
 template void blocked_sweep<float>(bool, const MfDev<float>&, const Plan&, int, int, const float2*, float2*, float2*,
                                    const SweepBufs<float>&, hipStream_t, double2*);
-template void sdense_sweep<double>(bool, const MfDev<double>&, const Plan&, int, int, const double2*, double2*,
+template void mchain_sweep<double>(bool, const MfDev<double>&, const Plan&, int, int, const double2*, double2*,
                                    double2*, hipStream_t, double2*);
-template void sdense_sweep<float>(bool, const MfDev<float>&, const Plan&, int, int, const float2*, float2*, float2*,
+template void mchain_sweep<float>(bool, const MfDev<float>&, const Plan&, int, int, const float2*, float2*, float2*,
                                   hipStream_t, double2*);
-template void sdense_form<double>(const MfDev<double>&, const Plan&, int, hipStream_t);
-template void sdense_form<float>(const MfDev<float>&, const Plan&, int, hipStream_t);
 template void blocked_form<double>(const MfDev<double>&, const Plan&, int, hipStream_t);
 template void blocked_form<float>(const MfDev<float>&, const Plan&, int, hipStream_t);
 

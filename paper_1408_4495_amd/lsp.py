@@ -50,7 +50,7 @@ class PlanStats(ctypes.Structure):
                 ("blocked_levels", ctypes.c_int), ("blocked_entries", ctypes.c_double),
                 ("chain_entries", ctypes.c_double), ("blocked_panel_entries", ctypes.c_double),
                 ("trsm_flops", ctypes.c_double), ("assemble_entries", ctypes.c_double),
-                ("sdense_levels", ctypes.c_int), ("sdense_entries", ctypes.c_double)]
+                ("mchain_levels", ctypes.c_int), ("mchain_entries", ctypes.c_double)]
 
 
 class LspError(RuntimeError):

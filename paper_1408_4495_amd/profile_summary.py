@@ -23,9 +23,8 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 SOURCE = {"fwd": "frontal.hip", "bwd": "frontal.hip", "diag_lu": "frontal.hip", "panel_trsm": "frontal.hip",
           "gemm_update": "frontal.hip", "update_lu": "frontal.hip", "assemble_front": "frontal.hip",
           "strip_first": "frontal.hip", "panel_step": "frontal.hip", "form_fwd": "frontal.hip",
-          "form_bwd": "frontal.hip", "bsweep": "sweep.hip", "sdense": "sweep.hip",
-          "fwd_sdense": "sweep.hip", "bwd_sdense": "sweep.hip", "sdense_form_fwd": "sweep.hip",
-          "sdense_form_bwd": "sweep.hip",
+          "form_bwd": "frontal.hip", "bsweep": "sweep.hip", "mchain": "sweep.hip",
+          "fwd_mchain": "sweep.hip", "bwd_mchain": "sweep.hip",
           "half_lines": "fft.hip", "full_lines": "fft.hip",
           "gram": "stencil.hip", "gram_reduce": "stencil.hip", "eigen": "stencil.hip", "applyQ": "stencil.hip",
           "dots_partial": "krylov.hip", "dots_final": "krylov.hip", "axpy": "krylov.hip", "cgs": "krylov.hip",
@@ -54,10 +53,8 @@ def registry_key(name):
         base = "update_lu"  # fused with the next diagonal-block factorisation
     if base in ("fwd_small", "bwd_small"):
         base = base[:3]  # the small-front levels' sweeps, timed under the same name
-    if base in ("sdense_fwd", "sdense_bwd"):
-        base = base[7:] + "_sdense"  # timed as fwd_sdense / bwd_sdense
-    if base == "sdense_form" and len(args) >= 2:
-        base = "sdense_form_bwd" if args[1] == "true" else "sdense_form_fwd"
+    if base in ("mchain_fwd", "mchain_bwd"):
+        base = base[7:] + "_mchain"  # timed as fwd_mchain / bwd_mchain
     if base == "fwd" and len(args) >= 2 and args[-2] == "true":
         # the forward chain (or the transposed backward one) run on unit
         # vectors: formation of a dense level's operators

@@ -246,12 +246,10 @@ def test_dense_formation_lifecycle():
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batched_equals_solo_bitwise(prec):
     """Lockstep batching: each right-hand side of a block of 5 (groups of 4 + 1
-    in the triangular sweeps) is bit-identical to its solo solve.  The solo
-    solves sweep the small-front levels with the one-right-hand-side kernels
-    (`fwd_small_kernel`, and `bwd_small_kernel` in complex64), the block
-    with the panel-chain kernels, so this also checks that the two compute
-    in the same order; the top levels use the formed dense operators in
-    both."""
+    in the panel-chain sweeps) is bit-identical to its solo solve.  The
+    small-front levels run the matrix-core chains in both (16-column
+    products, the unused columns zero), the middle levels the panel chains
+    with groups of 4 and 1, the top levels the formed dense operators."""
     n, d = 48, 2
     omega = 2 * np.pi * n / 8
     rng = np.random.default_rng([14084495, 77])
@@ -394,18 +392,18 @@ def test_blocked_batched_equals_solo_bitwise(prec):
 
 @pytest.mark.parametrize("n,d,prec,tol", [(128, 2, "fp64", 1e-12), (128, 2, "mixed", 2e-5),
                                           (16, 3, "fp64", 1e-12), (16, 3, "mixed", 2e-5)])
-def test_small_dense_levels_match_panel_chains(n, d, prec, tol):
-    """Small-front levels swept with formed operators (plans for blocks of
-    right-hand sides: 2D n = 128 its six lowest levels, 3D n = 16 its two
-    lowest) give the panel chains' M^{-1} z up to rounding (FP64 1e-12,
-    complex64 2e-5); 5 right-hand sides (groups of 4 and 1)."""
+def test_mchain_levels_match_panel_chains(n, d, prec, tol):
+    """Small-front levels swept by panel chains on the matrix cores (plans
+    for blocks of right-hand sides: 2D n = 128 its six lowest levels, 3D
+    n = 16 its two lowest) give the vector panel chains' M^{-1} z up to
+    rounding (FP64 1e-12, complex64 2e-5); 5 right-hand sides."""
     omega = 2 * np.pi * n / 8
     m = synth.medium_single_bump(n, d, 0.25, 0.12)
     z = synth.random_complex((5, n ** d), seed=53)
     out = []
     for dense in (1, 0):
         lsp, torch, plan, pb = _problem(n, d, omega, m, max_nrhs=5, precision=prec, dense_sweeps=dense)
-        assert (plan.stats()["sdense_levels"] > 0) == bool(dense)
+        assert (plan.stats()["mchain_levels"] > 0) == bool(dense)
         pb.factor()
         out.append(pb.solve_M(z).cpu().numpy())
         del pb
