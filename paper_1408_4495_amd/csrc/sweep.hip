@@ -535,26 +535,34 @@ __device__ __forceinline__ void cstep(CAcc<T>& c, const cplx<T> a, const cplx<T>
   c.im = Mfma<T>::step(a.y, b.x, c.im);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(64) mchain_fwd_kernel(const cplx<T>* __restrict__ Fbuf,
-                                                        const cplx<T>* __restrict__ Dinv,
-                                                        const FrontDev* __restrict__ fr, const int* __restrict__ idx,
-                                                        const int* __restrict__ cpos, const int* __restrict__ perm,
-                                                        const cplx<T>* __restrict__ z, cplx<T>* __restrict__ vbuf,
-                                                        int first, int nrhs, long long N, long long vstride) {
+// W waves per front (levels with fewer fronts take more): the gathers and
+// the stores are shared, the update's 16-row tiles go round-robin to the
+// waves, the inverse-block products' two tiles to waves 0 and 1 (wave 0
+// alone when W = 1), and the backward sweep's U12 columns in chunks of 32
+// to the waves, whose partial sums wave 0 and 1 add in wave order.  The
+// order of every sum depends on W only, which depends on the level's front
+// count, not on the right-hand sides.
+template <typename T, int W>
+__global__ void __launch_bounds__(64 * W) mchain_fwd_kernel(const cplx<T>* __restrict__ Fbuf,
+                                                            const cplx<T>* __restrict__ Dinv,
+                                                            const FrontDev* __restrict__ fr,
+                                                            const int* __restrict__ idx, const int* __restrict__ cpos,
+                                                            const int* __restrict__ perm,
+                                                            const cplx<T>* __restrict__ z, cplx<T>* __restrict__ vbuf,
+                                                            int first, int nrhs, long long N, long long vstride) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* V = reinterpret_cast<cplx<T>*>(smem_raw);  // V[r * MC + k]
   const FrontDev f = fr[first + blockIdx.x];
   const int p = f.p, m = p + f.q;
   const int r0 = blockIdx.y * MC, nr = min(MC, nrhs - r0);
-  const int lane = threadIdx.x, li = lane % 16, lk = lane / 16;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, li = lane % 16, lk = lane / 16;
   const cplx<T>* F = Fbuf + f.f_off;
   const int* id = idx + f.idx_off;
   const int* cp = cpos + 2 * f.idx_off;
   const int* pm = perm + f.piv_off;
-  // v = [z(I); 0] + children's updates: a row per lane, the row's index
+  // v = [z(I); 0] + children's updates: a row per thread, the row's index
   // loads first, then its 16 right-hand sides' loads together
-  for (int r = lane; r < m; r += 64) {
+  for (int r = tid; r < m; r += 64 * W) {
     const int gi = id[min(r, p - 1)];
     const int q0 = f.cidx[0] >= 0 ? cp[2 * r] : -1, q1 = f.cidx[1] >= 0 ? cp[2 * r + 1] : -1;
     cplx<T> val[MC];
@@ -582,78 +590,111 @@ __global__ void __launch_bounds__(64) mchain_fwd_kernel(const cplx<T>* __restric
   }
   for (int k0 = 0; k0 < p; k0 += PB) {
     const int kb = min(PB, p - k0), k1 = k0 + kb, nb = m - k1;
+    const int nh = (kb + 15) / 16, ns = (kb + 3) / 4;  // nonzero tiles and k-steps
     const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(k0 / PB) * 2 * PB * PB;
     __syncthreads();  // v is complete
     // y_b = L11^{-1} P_b v_b: operand A the inverse block (column-major),
-    // operand B the gathered rows
-    CAcc<T> y[2];
-    y[0].zero();
-    y[1].zero();
+    // operand B the gathered rows; tile h on wave h (wave 0 both if W = 1)
+    CAcc<T> y[W == 1 ? 2 : 1];
 #pragma unroll
-    for (int s4 = 0; s4 < PB / 4; ++s4) {
-      const int j = 4 * s4 + lk;
-      const int src = pm[k0 + min(j, kb - 1)];
-      const cplx<T> tv = V[src * MC + li];
-      const cplx<T> b = j < kb ? tv : mk<T>(0, 0);
+    for (int u = 0; u < (W == 1 ? 2 : 1); ++u) {
+      y[u].zero();
+      const int h = W == 1 ? u : wave;
+      if (h < nh) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) cstep(y[h], Lg[(16 * h + li) + PB * j], b);
+        for (int s4 = 0; s4 < PB / 4; ++s4) {
+          if (s4 < ns) {
+            const int j = 4 * s4 + lk;
+            const int src = pm[k0 + min(j, kb - 1)];
+            const cplx<T> tv = V[src * MC + li];
+            cstep(y[u], Lg[(16 * h + li) + PB * j], j < kb ? tv : mk<T>(0, 0));
+          }
+        }
+      }
     }
     __syncthreads();  // every gather of the panel's rows is done
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int u = 0; u < (W == 1 ? 2 : 1); ++u) {
+      const int h = W == 1 ? u : wave;
+      if (h < nh) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 16 * h + Mfma<T>::row(lk, v);
-        if (i < kb) V[(k0 + i) * MC + li] = y[h].at(v);
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * h + Mfma<T>::row(lk, v);
+          if (i < kb) V[(k0 + i) * MC + li] = y[u].at(v);
+        }
       }
+    }
     __syncthreads();
-    // v(k1:m) -= L21 y_b, 16 rows at a time: operand A the rows of L21
-    for (int t0 = 0; t0 < nb; t0 += 16) {
-      CAcc<T> u;
-      u.zero();
-      const int rr = k1 + min(t0 + li, nb - 1);
+    // v(k1:m) -= L21 y_b, 16 rows at a time (tiles round-robin over the
+    // waves): operand A the rows of L21, operand B y_b (held for all tiles);
+    // each tile's L21 entries are loaded a tile ahead
+    const int ntile = (nb + 15) / 16;
+    if (wave < ntile) {
+      cplx<T> yb[PB / 4];
 #pragma unroll
       for (int s4 = 0; s4 < PB / 4; ++s4) {
         const int j = 4 * s4 + lk;
-        const cplx<T> lv = F[(long long)(k0 + min(j, kb - 1)) * m + rr];
         const cplx<T> yv = V[(k0 + min(j, kb - 1)) * MC + li];
-        cstep(u, j < kb ? lv : mk<T>(0, 0), j < kb ? yv : mk<T>(0, 0));
+        yb[s4] = j < kb ? yv : mk<T>(0, 0);
       }
+      cplx<T> lc[PB / 4];
+      auto load_tile = [&](const int t, cplx<T>(&dst)[PB / 4]) {
+        const int rr = k1 + min(16 * t + li, nb - 1);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = t0 + Mfma<T>::row(lk, v);
-        if (r < nb) {
-          const cplx<T> o = V[(k1 + r) * MC + li];
-          V[(k1 + r) * MC + li] = csub(o, u.at(v));
+        for (int s4 = 0; s4 < PB / 4; ++s4)
+          if (s4 < ns) dst[s4] = F[(long long)(k0 + min(4 * s4 + lk, kb - 1)) * m + rr];
+      };
+      load_tile(wave, lc);
+      for (int t = wave; t < ntile; t += W) {
+        cplx<T> ln[PB / 4];
+        if (t + W < ntile) load_tile(t + W, ln);
+        CAcc<T> u;
+        u.zero();
+#pragma unroll
+        for (int s4 = 0; s4 < PB / 4; ++s4)
+          if (s4 < ns) cstep(u, 4 * s4 + lk < kb ? lc[s4] : mk<T>(0, 0), yb[s4]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * t + Mfma<T>::row(lk, v);
+          if (r < nb) {
+            const cplx<T> o = V[(k1 + r) * MC + li];
+            V[(k1 + r) * MC + li] = csub(o, u.at(v));
+          }
+        }
+        if (t + W < ntile) {
+#pragma unroll
+          for (int s4 = 0; s4 < PB / 4; ++s4) lc[s4] = ln[s4];
         }
       }
     }
   }
   __syncthreads();
-  for (int e = lane; e < m * nr; e += 64) {
+  for (int e = tid; e < m * nr; e += 64 * W) {
     const int r = e % m, k = e / m;
     vbuf[(long long)(r0 + k) * vstride + f.idx_off + r] = V[r * MC + k];
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(64) mchain_bwd_kernel(const cplx<T>* __restrict__ Fbuf,
-                                                        const cplx<T>* __restrict__ Dinv,
-                                                        const FrontDev* __restrict__ fr, const int* __restrict__ idx,
-                                                        cplx<T>* __restrict__ x, const cplx<T>* __restrict__ vbuf,
-                                                        int first, int nrhs, long long N, long long vstride,
-                                                        double2* __restrict__ xw) {
+template <typename T, int W>
+__global__ void __launch_bounds__(64 * W) mchain_bwd_kernel(const cplx<T>* __restrict__ Fbuf,
+                                                            const cplx<T>* __restrict__ Dinv,
+                                                            const FrontDev* __restrict__ fr,
+                                                            const int* __restrict__ idx, cplx<T>* __restrict__ x,
+                                                            const cplx<T>* __restrict__ vbuf, int first, int nrhs,
+                                                            long long N, long long vstride,
+                                                            double2* __restrict__ xw, int maxm) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* V = reinterpret_cast<cplx<T>*>(smem_raw);  // V[r * MC + k]
+  cplx<T>* part = V + (long long)maxm * MC;           // part[(w - 1) * 2 + h][64 lanes][4]: waves 1.. partial sums
   const FrontDev f = fr[first + blockIdx.x];
   const int p = f.p, m = p + f.q;
   const int r0 = blockIdx.y * MC, nr = min(MC, nrhs - r0);
-  const int lane = threadIdx.x, li = lane % 16, lk = lane / 16;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, li = lane % 16, lk = lane / 16;
   const cplx<T>* F = Fbuf + f.f_off;
   const int* id = idx + f.idx_off;
   // v = [y(I) from the forward sweep; x(B) from the ancestors]: a row per
-  // lane, its 16 right-hand sides' loads together
-  for (int r = lane; r < m; r += 64) {
+  // thread, its 16 right-hand sides' loads together
+  for (int r = tid; r < m; r += 64 * W) {
     cplx<T> val[MC];
     if (r < p) {
 #pragma unroll
@@ -669,21 +710,22 @@ __global__ void __launch_bounds__(64) mchain_bwd_kernel(const cplx<T>* __restric
   const int nblk = (p + PB - 1) / PB;
   for (int b = nblk - 1; b >= 0; --b) {
     const int k0 = b * PB, kb = min(PB, p - k0), k1 = k0 + kb, nc = m - k1;
+    const int nh = (kb + 15) / 16, ns = (kb + 3) / 4;
     const cplx<T>* Ug = Dinv + f.dinv_off + (long long)b * 2 * PB * PB + PB * PB;
     __syncthreads();  // x of the later panels is in place
-    // s = U12 x(k1:m): operand A the panel's rows of U12, four columns per step
+    // s = U12 x(k1:m): operand A the panel's rows of U12; wave w takes the
+    // column chunks 32 w, 32 (w + W), ..., each chunk's loads issued first
     CAcc<T> sa[2];
     sa[0].zero();
     sa[1].zero();
-    // 32 columns per pass: the pass's U12 loads first (clamped in range),
-    // then the products
-    for (int c0 = 0; c0 < nc; c0 += 32) {
+    for (int c0 = 32 * wave; c0 < nc; c0 += 32 * W) {
       cplx<T> ua[8][2];
 #pragma unroll
       for (int s8 = 0; s8 < 8; ++s8) {
         const long long col = (long long)(k1 + min(c0 + 4 * s8 + lk, nc - 1)) * m;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) ua[s8][h] = F[(k0 + min(16 * h + li, kb - 1)) + col];
+        for (int h = 0; h < 2; ++h)
+          if (h < nh) ua[s8][h] = F[(k0 + min(16 * h + li, kb - 1)) + col];
       }
 #pragma unroll
       for (int s8 = 0; s8 < 8; ++s8) {
@@ -691,40 +733,68 @@ __global__ void __launch_bounds__(64) mchain_bwd_kernel(const cplx<T>* __restric
         const cplx<T> xv = V[(k1 + min(c, nc - 1)) * MC + li];
         const cplx<T> b4 = c < nc ? xv : mk<T>(0, 0);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) cstep(sa[h], 16 * h + li < kb && c < nc ? ua[s8][h] : mk<T>(0, 0), b4);
+        for (int h = 0; h < 2; ++h)
+          if (h < nh) cstep(sa[h], 16 * h + li < kb && c < nc ? ua[s8][h] : mk<T>(0, 0), b4);
       }
     }
+    // t_b = y_b - s, s the partial sums added in wave order by wave 0
+    if constexpr (W > 1) {
+      if (wave > 0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 16 * h + Mfma<T>::row(lk, v);
-        if (i < kb) V[(k0 + i) * MC + li] = csub(V[(k0 + i) * MC + li], sa[h].at(v));
+          for (int v = 0; v < 4; ++v) part[(((wave - 1) * 2 + h) * 64 + lane) * 4 + v] = sa[h].at(v);
       }
+      __syncthreads();
+    }
+    if (wave == 0) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (h < nh) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            cplx<T> sv = sa[h].at(v);
+#pragma unroll
+            for (int w = 1; w < W; ++w) sv = cadd(sv, part[(((w - 1) * 2 + h) * 64 + lane) * 4 + v]);
+            const int i = 16 * h + Mfma<T>::row(lk, v);
+            if (i < kb) V[(k0 + i) * MC + li] = csub(V[(k0 + i) * MC + li], sv);
+          }
+        }
+      }
+    }
     __syncthreads();
     // x_b = U11^{-1} t_b
-    CAcc<T> xa[2];
-    xa[0].zero();
-    xa[1].zero();
+    CAcc<T> xa[W == 1 ? 2 : 1];
 #pragma unroll
-    for (int s4 = 0; s4 < PB / 4; ++s4) {
-      const int j = 4 * s4 + lk;
-      const cplx<T> tv = V[(k0 + min(j, kb - 1)) * MC + li];
-      const cplx<T> b4 = j < kb ? tv : mk<T>(0, 0);
+    for (int u = 0; u < (W == 1 ? 2 : 1); ++u) {
+      xa[u].zero();
+      const int h = W == 1 ? u : wave;
+      if (h < nh) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) cstep(xa[h], Ug[(16 * h + li) + PB * j], b4);
+        for (int s4 = 0; s4 < PB / 4; ++s4) {
+          if (s4 < ns) {
+            const int j = 4 * s4 + lk;
+            const cplx<T> tv = V[(k0 + min(j, kb - 1)) * MC + li];
+            cstep(xa[u], Ug[(16 * h + li) + PB * j], j < kb ? tv : mk<T>(0, 0));
+          }
+        }
+      }
     }
     __syncthreads();  // every read of t_b is done
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int u = 0; u < (W == 1 ? 2 : 1); ++u) {
+      const int h = W == 1 ? u : wave;
+      if (h < nh) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 16 * h + Mfma<T>::row(lk, v);
-        if (i < kb) V[(k0 + i) * MC + li] = xa[h].at(v);
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * h + Mfma<T>::row(lk, v);
+          if (i < kb) V[(k0 + i) * MC + li] = xa[u].at(v);
+        }
       }
+    }
   }
   __syncthreads();
-  for (int e = lane; e < p * nr; e += 64) {
+  for (int e = tid; e < p * nr; e += 64 * W) {
     const int r = e % p, k = e / p;
     const cplx<T> v = V[r * MC + k];
     const long long gi = (long long)(r0 + k) * N + id[r];
@@ -751,20 +821,37 @@ void blocked_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nr
 #undef LSP_BLOCKED
 }
 
+// waves per front: enough fronts' waves to fill the chip (about 16 per CU)
+inline int mchain_waves(int cnt) { return cnt >= 4096 ? 1 : (cnt >= 2048 ? 2 : 4); }
+
+template <typename T, int W>
+void mchain_launch(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
+                   cplx<T>* vbuf, hipStream_t st, double2* xw) {
+  const int first = plan.level_ptr[l];
+  const int cnt = plan.level_ptr[l + 1] - first;
+  const int maxm = plan.level_maxpq[l];
+  const dim3 grid(cnt, (nrhs + MC - 1) / MC);
+  const size_t vlds = (size_t)maxm * MC * sizeof(cplx<T>);
+  if (fwd) {
+    LSP_LAUNCH("fwd_mchain", (int)sizeof(cplx<T>), (mchain_fwd_kernel<T, W>), grid, dim3(64 * W), vlds, st, mf.F,
+               mf.Dinv, mf.fronts, mf.idx, mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N,
+               (long long)plan.sum_pq);
+  } else {
+    const size_t plds = (size_t)(W - 1) * 2 * 64 * 4 * sizeof(cplx<T>);
+    LSP_LAUNCH("bwd_mchain", (int)sizeof(cplx<T>), (mchain_bwd_kernel<T, W>), grid, dim3(64 * W), vlds + plds, st,
+               mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq, xw,
+               maxm);
+  }
+}
+
 template <typename T>
 void mchain_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
                   cplx<T>* vbuf, hipStream_t st, double2* xw) {
   LSP_REQUIRE(plan.level_maxp[l] <= MCP && plan.level_maxpq[l] <= MCM, "matrix-core chain level exceeds its bounds");
-  const int first = plan.level_ptr[l];
-  const int cnt = plan.level_ptr[l + 1] - first;
-  const dim3 grid(cnt, (nrhs + MC - 1) / MC);
-  const size_t lds = (size_t)plan.level_maxpq[l] * MC * sizeof(cplx<T>);
-  if (fwd)
-    LSP_LAUNCH("fwd_mchain", (int)sizeof(cplx<T>), mchain_fwd_kernel<T>, grid, dim3(64), lds, st, mf.F, mf.Dinv,
-               mf.fronts, mf.idx, mf.cpos, mf.perm, z, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq);
-  else
-    LSP_LAUNCH("bwd_mchain", (int)sizeof(cplx<T>), mchain_bwd_kernel<T>, grid, dim3(64), lds, st, mf.F, mf.Dinv,
-               mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq, xw);
+  const int W = mchain_waves(plan.level_ptr[l + 1] - plan.level_ptr[l]);
+  if (W == 1) mchain_launch<T, 1>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
+  else if (W == 2) mchain_launch<T, 2>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
+  else mchain_launch<T, 4>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
 }
 
 template <typename T>
