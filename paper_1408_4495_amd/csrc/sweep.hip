@@ -50,6 +50,27 @@ constexpr int KC = kSweepChunk;  // boundary columns per partial sum
 constexpr int GR = 64;           // gemv rows per workgroup (one per lane of a wave)
 constexpr int GU = 16;           // gemv column loads in flight per lane
 constexpr int NF = 8;            // unit vectors per formation workgroup
+constexpr int MC = 16;           // right-hand sides per matrix-core product group
+
+// complex accumulator of a 16x16x4 product block (real and imaginary parts)
+template <typename T>
+struct CAcc {
+  typename Mfma<T>::acc_t re, im;
+  __device__ void zero() {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { re[v] = 0; im[v] = 0; }
+  }
+  __device__ cplx<T> at(int v) const { return mk<T>(re[v], im[v]); }
+};
+
+// c += a b with a from operand A, b from operand B (complex)
+template <typename T>
+__device__ __forceinline__ void cstep(CAcc<T>& c, const cplx<T> a, const cplx<T> b) {
+  c.re = Mfma<T>::step(a.x, b.x, c.re);
+  c.re = Mfma<T>::step(-a.y, b.y, c.re);
+  c.im = Mfma<T>::step(a.x, b.y, c.im);
+  c.im = Mfma<T>::step(a.y, b.x, c.im);
+}
 
 // out[k] = sum_j D(i, j) in(k, j) for k < NR, i = tid / 8: eight threads per
 // row, each summing every eighth j in two interleaved partial sums, combined
@@ -271,10 +292,14 @@ __global__ void __launch_bounds__(256) bsweep_form_bwd_kernel(const cplx<T>* __r
 // ---- the sweeps' matrix-vector products
 //
 // acc(r) = sum_c A(r, c) in(c) over a rectangle of rows [rlo, rhi) and
-// columns [clo, chi) of each front (blockIdx.y), right-hand sides r0 ..
-// r0 + NR (blockIdx.z), 64-row tiles (blockIdx.x): lane l of wave w owns row
-// row0 + l and sums the columns w, w + 4, ... of each staged chunk of GC
-// columns; the four waves' sums are added in wave order.
+// columns [clo, chi) of each front (blockIdx.y), for a group of 16
+// right-hand sides (blockIdx.z), on the matrix cores: a workgroup takes 16
+// rows (blockIdx.x), its four waves a quarter of each staged chunk of GC
+// columns each, as 16x16x4 products of the staged inputs (operand A, the
+// right-hand sides as rows) and the matrix entries (operand B, 16
+// consecutive rows per load); the four waves' sums are added in wave
+// order.  Each output column of the products is its own sum, so a
+// right-hand side's result does not depend on the others in its group.
 //   MODE_W   forward operator:  rows/columns [s0, s1), A = W_s, in = v (front
 //            vector), out: y_s -> ybuf
 //   MODE_V   backward operator: rows/columns [s0, s1), A = V_s, in = t, out:
@@ -298,16 +323,18 @@ struct GemvArgs {
   long long ystride;  // ybuf / pbuf elements per right-hand side
 };
 
-template <typename T, int NR, int MODE>
+constexpr int GT = 16;   // rows per workgroup
+constexpr int GC = 128;  // columns staged per chunk (32 per wave)
+
+template <typename T, int MODE>
 __global__ void __launch_bounds__(256) bsweep_gemv_kernel(const cplx<T>* __restrict__ Fbuf,
                                                           const cplx<T>* __restrict__ Gop,
                                                           const FrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                           cplx<T>* __restrict__ x, cplx<T>* __restrict__ vbuf,
                                                           cplx<T>* __restrict__ ybuf, cplx<T>* __restrict__ pbuf,
                                                           double2* __restrict__ xw, GemvArgs a) {
-  constexpr int GC = NR >= 16 ? 128 : 256;  // columns staged per chunk
-  __shared__ cplx<T> xin[NR][GC];
-  __shared__ cplx<T> part[4][NR][GR];
+  __shared__ cplx<T> xin[MC][GC + 1];
+  __shared__ cplx<T> part[3][64][4];
   const int fi = blockIdx.y;
   const FrontDev f = fr[a.first + fi];
   const int p = f.p, m = p + f.q;
@@ -320,20 +347,20 @@ __global__ void __launch_bounds__(256) bsweep_gemv_kernel(const cplx<T>* __restr
   else if constexpr (MODE == MODE_FS) { rlo = s1; rhi = m; clo = s0; chi = s1; }
   else if constexpr (MODE == MODE_BS) { rlo = 0; rhi = min(s0, p); clo = s0; chi = s1; }
   else { rlo = 0; rhi = p; clo = p + kc * KC; chi = min(m, clo + KC); }
-  const int r0 = blockIdx.z * NR, nr = min(NR, a.nrhs - r0);
-  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+  const int r0 = blockIdx.z * MC, nr = min(MC, a.nrhs - r0);
+  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64, li = lane % 16, lk = lane / 16;
   cplx<T>* vg = vbuf + (long long)r0 * a.vstride + f.idx_off;
   cplx<T>* yg = ybuf + (long long)r0 * a.ystride + (long long)fi * SB;  // y_s(c) at yg[c - s0]
   if constexpr (MODE == MODE_FS) {
     if (blockIdx.x == 0)  // y_s into the front vector at the pivot positions
-      for (int e = tid; e < NR * SB; e += 256) {
+      for (int e = tid; e < MC * SB; e += 256) {
         const int k = e / SB, c = s0 + e % SB;
         if (k < nr && c < s1) vg[(long long)k * a.vstride + c] = yg[(long long)k * a.ystride + c - s0];
       }
   }
-  const int row0 = rlo + tile * GR;
+  const int row0 = rlo + tile * GT;
   if (row0 >= rhi || clo >= chi) return;
-  const int r = min(row0 + lane, rhi - 1);
+  const int rr = min(row0 + li, rhi - 1);  // this lane's matrix row (clamped in range)
   // entry (r, c) of the rectangle's matrix at A[(c - cb) * ld + r - rb]
   const cplx<T>* A;
   long long ld;
@@ -350,57 +377,64 @@ __global__ void __launch_bounds__(256) bsweep_gemv_kernel(const cplx<T>* __restr
     cb = 0;
   }
   const int* id = idx + f.idx_off;
-  cplx<T> acc[NR];
-#pragma unroll
-  for (int k = 0; k < NR; ++k) acc[k] = mk<T>(0, 0);
+  CAcc<T> acc;
+  acc.zero();
   for (int c0 = clo; c0 < chi; c0 += GC) {
     const int cn = min(GC, chi - c0);
     if (c0 > clo) __syncthreads();  // the previous chunk's reads of xin are done
-    for (int e = tid; e < NR * GC; e += 256) {
+    for (int e = tid; e < MC * GC; e += 256) {
       const int k = e / GC, jj = e % GC;
+      cplx<T> v = mk<T>(0, 0);
       if (k < nr && jj < cn) {
         const int c = c0 + jj;
-        if constexpr (MODE == MODE_BB) xin[k][jj] = x[(long long)(r0 + k) * a.N + id[c]];
-        else if constexpr (MODE == MODE_FS || MODE == MODE_BS) xin[k][jj] = yg[(long long)k * a.ystride + c - s0];
-        else xin[k][jj] = vg[(long long)k * a.vstride + c];
+        if constexpr (MODE == MODE_BB) v = x[(long long)(r0 + k) * a.N + id[c]];
+        else if constexpr (MODE == MODE_FS || MODE == MODE_BS) v = yg[(long long)k * a.ystride + c - s0];
+        else v = vg[(long long)k * a.vstride + c];
       }
+      xin[k][jj] = v;
     }
     __syncthreads();
-    for (int t0 = 0; t0 < GC / 4; t0 += GU) {
-      if (w + 4 * t0 >= cn) break;
-      cplx<T> av[GU];
+    // this wave's 32 columns: their matrix entries first, then the products
+    const int jw = w * (GC / 4);
+    if (jw < cn) {
+      cplx<T> av[GC / 16];
 #pragma unroll
-      for (int u = 0; u < GU; ++u) {
-        const int jj = min(w + 4 * (t0 + u), cn - 1);
-        av[u] = A[(long long)(c0 + jj - cb) * ld + (r - rb)];
+      for (int s4 = 0; s4 < GC / 16; ++s4) {
+        const int jj = min(jw + 4 * s4 + lk, cn - 1);
+        av[s4] = A[(long long)(c0 + jj - cb) * ld + (rr - rb)];
       }
 #pragma unroll
-      for (int u = 0; u < GU; ++u) {
-        const int jj = w + 4 * (t0 + u);
-        if (jj < cn)
-#pragma unroll
-          for (int k = 0; k < NR; ++k) acc[k] = cfma(acc[k], av[u], xin[min(k, nr - 1)][jj]);
+      for (int s4 = 0; s4 < GC / 16; ++s4) {
+        const int jj = jw + 4 * s4 + lk;
+        cstep(acc, xin[li][min(jj, GC - 1)], jj < cn ? av[s4] : mk<T>(0, 0));
       }
     }
   }
+  if (w > 0) {
 #pragma unroll
-  for (int k = 0; k < NR; ++k) part[w][k][lane] = acc[k];
+    for (int v = 0; v < 4; ++v) part[w - 1][lane][v] = acc.at(v);
+  }
   __syncthreads();
-  for (int e = tid; e < NR * GR; e += 256) {
-    const int k = e / GR, rl = e % GR, rr = row0 + rl;
-    if (k < nr && rr < rhi) {
-      const cplx<T> sm = cadd(cadd(part[0][k][rl], part[1][k][rl]), cadd(part[2][k][rl], part[3][k][rl]));
+  if (w > 0) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    cplx<T> sm = acc.at(v);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) sm = cadd(sm, part[q][lane][v]);
+    // the product's row v of this lane's block: right-hand side k, matrix row rw
+    const int k = Mfma<T>::row(lk, v), rw = row0 + li;
+    if (k < nr && rw < rhi) {
       if constexpr (MODE == MODE_W) {
-        yg[(long long)k * a.ystride + rr - s0] = sm;
+        yg[(long long)k * a.ystride + rw - s0] = sm;
       } else if constexpr (MODE == MODE_V) {
-        yg[(long long)k * a.ystride + rr - s0] = sm;
-        const long long gi = id[rr];
+        yg[(long long)k * a.ystride + rw - s0] = sm;
+        const long long gi = id[rw];
         x[(long long)(r0 + k) * a.N + gi] = sm;
         if (xw) xw[(long long)(r0 + k) * a.N + gi] = widen(sm);
       } else if constexpr (MODE == MODE_BB) {
-        pbuf[((long long)kc * a.nrhs + r0 + k) * a.ystride + (long long)fi * a.maxp + rr] = sm;
+        pbuf[((long long)kc * a.nrhs + r0 + k) * a.ystride + (long long)fi * a.maxp + rw] = sm;
       } else {
-        cplx<T>* o = vg + (long long)k * a.vstride + rr;
+        cplx<T>* o = vg + (long long)k * a.vstride + rw;
         *o = csub(*o, sm);
       }
     }
@@ -425,20 +459,20 @@ __global__ void __launch_bounds__(256) bsweep_bb_reduce_kernel(const FrontDev* _
   *o = csub(*o, sm);
 }
 
-template <typename T, int NR, int MODE>
+template <typename T, int MODE>
 void gemv_launch(const MfDev<T>& mf, const Plan& plan, int l, int s, int nrows, int kch, int nrhs, cplx<T>* x,
                  cplx<T>* vbuf, const SweepBufs<T>& sb, double2* xw, hipStream_t st) {
   if (nrows <= 0) return;
   const int first = plan.level_ptr[l];
   const int cnt = plan.level_ptr[l + 1] - first;
-  const int groups = (nrhs + NR - 1) / NR;
+  const int groups = (nrhs + MC - 1) / MC;
   GemvArgs a{first, s, kch, plan.level_maxp[l], nrhs, (long long)plan.N, (long long)plan.sum_pq, sb.ystride};
-  LSP_LAUNCH("bsweep_gemv", (int)sizeof(cplx<T>), (bsweep_gemv_kernel<T, NR, MODE>),
-             dim3((nrows + GR - 1) / GR * kch, cnt, groups), dim3(256), 0, st, mf.F, mf.G, mf.fronts, mf.idx, x, vbuf,
+  LSP_LAUNCH("bsweep_gemv", (int)sizeof(cplx<T>), (bsweep_gemv_kernel<T, MODE>),
+             dim3((nrows + GT - 1) / GT * kch, cnt, groups), dim3(256), 0, st, mf.F, mf.G, mf.fronts, mf.idx, x, vbuf,
              sb.ybuf, sb.pbuf, xw, a);
 }
 
-template <typename T, int NR>
+template <typename T>
 void blocked_level_fwd(const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* vbuf,
                        const SweepBufs<T>& sb, hipStream_t st) {
   const int first = plan.level_ptr[l];
@@ -449,18 +483,18 @@ void blocked_level_fwd(const MfDev<T>& mf, const Plan& plan, int l, int nrhs, co
   const int nsb = (maxp + SB - 1) / SB;
   for (int s = 0; s < nsb; ++s) {
     const int s0 = s * SB;
-    gemv_launch<T, NR, MODE_W>(mf, plan, l, s, std::min(SB, maxp - s0), 1, nrhs, nullptr, vbuf, sb, nullptr, st);
+    gemv_launch<T, MODE_W>(mf, plan, l, s, std::min(SB, maxp - s0), 1, nrhs, nullptr, vbuf, sb, nullptr, st);
     int rows = 0;  // rows below the super-block, the most over the level's fronts
     for (int i = first; i < first + cnt; ++i) {
       const FrontDev& f = plan.fronts[i];
       if (f.p > s0) rows = std::max(rows, f.p + f.q - std::min(s0 + SB, f.p));
     }
     // at least one tile, so that tile 0 copies y_s into the front vector
-    gemv_launch<T, NR, MODE_FS>(mf, plan, l, s, std::max(rows, 1), 1, nrhs, nullptr, vbuf, sb, nullptr, st);
+    gemv_launch<T, MODE_FS>(mf, plan, l, s, std::max(rows, 1), 1, nrhs, nullptr, vbuf, sb, nullptr, st);
   }
 }
 
-template <typename T, int NR>
+template <typename T>
 void blocked_level_bwd(const MfDev<T>& mf, const Plan& plan, int l, int nrhs, cplx<T>* x, cplx<T>* vbuf,
                        const SweepBufs<T>& sb, hipStream_t st, double2* xw) {
   const int first = plan.level_ptr[l];
@@ -470,7 +504,7 @@ void blocked_level_bwd(const MfDev<T>& mf, const Plan& plan, int l, int nrhs, cp
   for (int i = first; i < first + cnt; ++i) maxq = std::max(maxq, plan.fronts[i].q);
   if (maxq > 0) {
     const int kch = (maxq + KC - 1) / KC;
-    gemv_launch<T, NR, MODE_BB>(mf, plan, l, 0, maxp, kch, nrhs, x, vbuf, sb, nullptr, st);
+    gemv_launch<T, MODE_BB>(mf, plan, l, 0, maxp, kch, nrhs, x, vbuf, sb, nullptr, st);
     GemvArgs a{first, 0, kch, maxp, nrhs, (long long)plan.N, (long long)plan.sum_pq, sb.ystride};
     LSP_LAUNCH("bsweep_bb_reduce", (int)sizeof(cplx<T>), bsweep_bb_reduce_kernel<T>,
                dim3((maxp + 255) / 256, cnt, nrhs), dim3(256), 0, st, mf.fronts, vbuf, sb.pbuf, a);
@@ -478,8 +512,8 @@ void blocked_level_bwd(const MfDev<T>& mf, const Plan& plan, int l, int nrhs, cp
   const int nsb = (maxp + SB - 1) / SB;
   for (int s = nsb - 1; s >= 0; --s) {
     const int s0 = s * SB;
-    gemv_launch<T, NR, MODE_V>(mf, plan, l, s, std::min(SB, maxp - s0), 1, nrhs, x, vbuf, sb, xw, st);
-    gemv_launch<T, NR, MODE_BS>(mf, plan, l, s, s0, 1, nrhs, nullptr, vbuf, sb, nullptr, st);
+    gemv_launch<T, MODE_V>(mf, plan, l, s, std::min(SB, maxp - s0), 1, nrhs, x, vbuf, sb, xw, st);
+    gemv_launch<T, MODE_BS>(mf, plan, l, s, s0, 1, nrhs, nullptr, vbuf, sb, nullptr, st);
   }
 }
 
@@ -499,7 +533,6 @@ void blocked_level_bwd(const MfDev<T>& mf, const Plan& plan, int l, int nrhs, cp
 // Each output column of an MFMA is its own sum, so a right-hand side's
 // result does not depend on the others in its group: batched and solo solves
 // agree bit for bit.
-constexpr int MC = 16;    // right-hand sides per wave
 constexpr int MCP = 64;   // largest p of a matrix-core chain level
 constexpr int MCM = 256;  // largest m
 
@@ -514,25 +547,6 @@ __device__ __forceinline__ cplx<T> front_input(const FrontDev& f, const int* __r
   if (q0 >= 0) s = cadd(s, vbuf[rb + f.cidx[0] + q0]);
   if (q1 >= 0) s = cadd(s, vbuf[rb + f.cidx[1] + q1]);
   return s;
-}
-
-template <typename T>
-struct CAcc {
-  typename Mfma<T>::acc_t re, im;
-  __device__ void zero() {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) { re[v] = 0; im[v] = 0; }
-  }
-  __device__ cplx<T> at(int v) const { return mk<T>(re[v], im[v]); }
-};
-
-// c += a b with a from operand A, b from operand B (complex)
-template <typename T>
-__device__ __forceinline__ void cstep(CAcc<T>& c, const cplx<T> a, const cplx<T> b) {
-  c.re = Mfma<T>::step(a.x, b.x, c.re);
-  c.re = Mfma<T>::step(-a.y, b.y, c.re);
-  c.im = Mfma<T>::step(a.x, b.y, c.im);
-  c.im = Mfma<T>::step(a.y, b.x, c.im);
 }
 
 // W waves per front (levels with fewer fronts take more): the gathers and
@@ -808,17 +822,8 @@ __global__ void __launch_bounds__(64 * W) mchain_bwd_kernel(const cplx<T>* __res
 template <typename T>
 void blocked_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
                    cplx<T>* vbuf, const SweepBufs<T>& sb, hipStream_t st, double2* xw) {
-#define LSP_BLOCKED(NR)                                               \
-  do {                                                                \
-    if (fwd) blocked_level_fwd<T, NR>(mf, plan, l, nrhs, z, vbuf, sb, st); \
-    else blocked_level_bwd<T, NR>(mf, plan, l, nrhs, x, vbuf, sb, st, xw); \
-  } while (0)
-  if (nrhs >= 16) LSP_BLOCKED(16);
-  else if (nrhs >= 8) LSP_BLOCKED(8);
-  else if (nrhs >= 4) LSP_BLOCKED(4);
-  else if (nrhs >= 2) LSP_BLOCKED(2);
-  else LSP_BLOCKED(1);
-#undef LSP_BLOCKED
+  if (fwd) blocked_level_fwd<T>(mf, plan, l, nrhs, z, vbuf, sb, st);
+  else blocked_level_bwd<T>(mf, plan, l, nrhs, x, vbuf, sb, st, xw);
 }
 
 // waves per front: enough fronts' waves to fill the chip (about 16 per CU)
