@@ -64,8 +64,9 @@ void k_givens(double2* H, double2* cs, double2* sn, double2* gam, int k, int res
 // active set, Krylov sizes and targets; reports under `tag`.
 void k_gmres_control(bool cycle_end, int nrhs, const GmresState& gs, const GmresParams& gp, const CtlView& host,
                      unsigned tag, hipStream_t st);
+// (kmax: the most Arnoldi steps any right-hand side took in the cycle)
 void k_backsolve_update(const double2* H, const double2* gam, double2* y, const int* ksz, double2* x, const double2* Z,
-                        int restart, long long N, int nrhs, hipStream_t st);
+                        int restart, int kmax, long long N, int nrhs, hipStream_t st);
 void k_sub(double2* r, const double2* g, const double2* t, long long count, hipStream_t st);
 void k_cycle_init(double2* H, double2* gam, const double* scal, int restart, int nrhs, hipStream_t st);
 // host.hdr->value = min over v[0..n) (-1 if any entry is NaN), reported under tag.

@@ -31,15 +31,16 @@ __device__ inline double2 wave_sum(double2 v) {
 
 // partial[rhs][blk][i] = sum over this block's chunk of conj(V_i) w, i < nvec.
 // V_i of rhs r is at V + (i * nrhs + r) * N.
+template <int NV>
 __global__ void __launch_bounds__(KB) dots_partial_kernel(const double2* __restrict__ V, const double2* __restrict__ w,
                                                           double2* __restrict__ partial, int nvec, long long N,
                                                           int nrhs, const int* __restrict__ active) {
   const int r = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
   if (active && !active[r]) return;
   const long long e0 = N * blk / nblk, e1 = N * (blk + 1) / nblk;
-  double2 acc[kMaxVec];
+  double2 acc[NV];
 #pragma unroll
-  for (int i = 0; i < kMaxVec; ++i) acc[i] = make_double2(0, 0);
+  for (int i = 0; i < NV; ++i) acc[i] = make_double2(0, 0);
   const double2* wr = w + (long long)r * N;
   // four elements per thread per pass, their loads issued together
   for (long long eb = e0 + threadIdx.x; eb < e1; eb += 4 * KB) {
@@ -47,7 +48,7 @@ __global__ void __launch_bounds__(KB) dots_partial_kernel(const double2* __restr
 #pragma unroll
     for (int u = 0; u < 4; ++u) we[u] = eb + u * KB < e1 ? wr[eb + u * KB] : make_double2(0, 0);
 #pragma unroll
-    for (int i = 0; i < kMaxVec; ++i) {
+    for (int i = 0; i < NV; ++i) {
       if (i < nvec) {
         const double2* Vi = V + ((long long)i * nrhs + r) * N;
         double2 ve[4];
@@ -61,7 +62,7 @@ __global__ void __launch_bounds__(KB) dots_partial_kernel(const double2* __restr
   __shared__ double2 ws[KB / 64][kMaxVec];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
 #pragma unroll
-  for (int i = 0; i < kMaxVec; ++i) {
+  for (int i = 0; i < NV; ++i) {
     if (i < nvec) {
       double2 s = wave_sum(acc[i]);
       if (lane == 0) ws[wave][i] = s;
@@ -158,12 +159,13 @@ __device__ void final_sums(const double2* __restrict__ pin, int r, int nblk, int
 
 // This block's partial sums acc[i], i < nvec, combined over its waves in a
 // fixed order and written to pout[r][blk][i].
-__device__ void block_partials(const double2 (&acc)[kMaxVec], int nvec, double2* __restrict__ pout, int r, int blk,
+template <int NV>
+__device__ void block_partials(const double2 (&acc)[NV], int nvec, double2* __restrict__ pout, int r, int blk,
                                int nblk) {
   __shared__ double2 ws[KB / 64][kMaxVec];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
 #pragma unroll
-  for (int i = 0; i < kMaxVec; ++i) {
+  for (int i = 0; i < NV; ++i) {
     if (i < nvec) {
       double2 s = wave_sum(acc[i]);
       if (lane == 0) ws[wave][i] = s;
@@ -182,7 +184,7 @@ __device__ void block_partials(const double2 (&acc)[kMaxVec], int nvec, double2*
 // this block's elements, then this block's partial sums of the next
 // reduction to pout: V^H w (NEXT == 0) or ||w||^2 (NEXT == 1).  The element
 // partition and the per-thread order match dots_partial_kernel.
-template <int NEXT>
+template <int NEXT, int NV>
 __global__ void __launch_bounds__(KB) cgs_kernel(const double2* __restrict__ V, double2* __restrict__ w,
                                                  const double2* __restrict__ pin, double2* __restrict__ pout,
                                                  double2* __restrict__ h, double2* __restrict__ H, int nvec, long long N,
@@ -199,26 +201,64 @@ __global__ void __launch_bounds__(KB) cgs_kernel(const double2* __restrict__ V, 
     double2* Hc = H + (long long)r * (restart + 1) * restart + (restart + 1) * k;
     Hc[i] = mode == 0 ? hs[i] : cadd(Hc[i], hs[i]);
   }
+  double2 hv[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) hv[i] = i < nvec ? hs[i] : make_double2(0, 0);
   const long long e0 = N * blk / nblk, e1 = N * (blk + 1) / nblk;
-  double2 acc[kMaxVec];
+  constexpr int NA = NEXT == 0 ? NV : 1;
+  double2 acc[NA];
 #pragma unroll
-  for (int i = 0; i < kMaxVec; ++i) acc[i] = make_double2(0, 0);
+  for (int i = 0; i < NA; ++i) acc[i] = make_double2(0, 0);
   double2* wr = w + (long long)r * N;
-  for (long long e = e0 + threadIdx.x; e < e1; e += KB) {
-    double2 s = wr[e];
+  // EP elements per thread per pass (e, e + KB, ...), their loads issued
+  // together; the sums take them in element order.  Up to 8 vectors the
+  // loaded V entries are kept for the second product, beyond that they are
+  // loaded again (cached), so the registers stay within bounds.
+  constexpr int EP = NV <= 4 ? 2 : 1;
+  constexpr bool HOLD = NV <= 8;
+  for (long long e = e0 + threadIdx.x; e < e1; e += EP * KB) {
+    long long ee[EP];
+    bool ok[EP];
 #pragma unroll
-    for (int i = 0; i < kMaxVec; ++i)
-      if (i < nvec) s = cfms(s, hs[i], V[((long long)i * nrhs + r) * N + e]);
-    wr[e] = s;
-    if constexpr (NEXT == 0) {
+    for (int u = 0; u < EP; ++u) {
+      ok[u] = e + u * KB < e1;
+      ee[u] = ok[u] ? e + u * KB : e;
+    }
+    double2 sv[EP];
 #pragma unroll
-      for (int i = 0; i < kMaxVec; ++i)
-        if (i < nvec) acc[i] = cadd(acc[i], cmulc(V[((long long)i * nrhs + r) * N + e], s));
-    } else {
-      acc[0] = cadd(acc[0], cmulc(s, s));
+    for (int u = 0; u < EP; ++u) sv[u] = wr[ee[u]];
+    double2 vv[HOLD ? NV : 1][EP];
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      if (i < nvec) {
+#pragma unroll
+        for (int u = 0; u < EP; ++u) {
+          const double2 v = V[((long long)i * nrhs + r) * N + ee[u]];
+          if constexpr (HOLD) vv[i][u] = v;
+          sv[u] = cfms(sv[u], hv[i], v);
+        }
+      }
+#pragma unroll
+    for (int u = 0; u < EP; ++u)
+      if (ok[u]) wr[ee[u]] = sv[u];
+#pragma unroll
+    for (int u = 0; u < EP; ++u) {
+      if (!ok[u]) break;
+      if constexpr (NEXT == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+          if (i < nvec) {
+            double2 v;
+            if constexpr (HOLD) v = vv[i][u];
+            else v = V[((long long)i * nrhs + r) * N + ee[u]];
+            acc[i] = cadd(acc[i], cmulc(v, sv[u]));
+          }
+      } else {
+        acc[0] = cadd(acc[0], cmulc(sv[u], sv[u]));
+      }
     }
   }
-  block_partials(acc, NEXT == 0 ? nvec : 1, pout, r, blk, nblk);
+  block_partials<NA>(acc, NEXT == 0 ? nvec : 1, pout, r, blk, nblk);
 }
 
 // ||w|| from the partial sums pin; block 0 records H(k+1, k) and the
@@ -244,19 +284,20 @@ __global__ void __launch_bounds__(KB) scale_norm_kernel(double2* __restrict__ y,
 }
 
 // w -= sum_i h_i V_i
+template <int NV>
 __global__ void __launch_bounds__(KB) axpy_kernel(const double2* __restrict__ V, double2* __restrict__ w,
                                                   const double2* __restrict__ h, int nvec, long long N, int nrhs,
                                                   const int* __restrict__ active) {
   const int r = blockIdx.y;
   if (active && !active[r]) return;
-  double2 hv[kMaxVec];
+  double2 hv[NV];
 #pragma unroll
-  for (int i = 0; i < kMaxVec; ++i) hv[i] = i < nvec ? h[(long long)r * kMaxVec + i] : make_double2(0, 0);
+  for (int i = 0; i < NV; ++i) hv[i] = i < nvec ? h[(long long)r * kMaxVec + i] : make_double2(0, 0);
   double2* wr = w + (long long)r * N;
   for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < N; e += (long long)gridDim.x * KB) {
     double2 s = wr[e];
 #pragma unroll
-    for (int i = 0; i < kMaxVec; ++i)
+    for (int i = 0; i < NV; ++i)
       if (i < nvec) s = cfms(s, hv[i], V[((long long)i * nrhs + r) * N + e]);
     wr[e] = s;
   }
@@ -414,18 +455,19 @@ __global__ void backsolve_kernel(const double2* __restrict__ H, const double2* _
 }
 
 // x += sum_{j < ksz[r]} y_j Z_j
+template <int NV>
 __global__ void update_kernel(double2* __restrict__ x, const double2* __restrict__ Z, const double2* __restrict__ y,
                               const int* __restrict__ ksz, long long N, int nrhs) {
   const int r = blockIdx.y;
   const int k = ksz[r];
   if (k == 0) return;
-  double2 yv[kMaxVec];
+  double2 yv[NV];
 #pragma unroll
-  for (int i = 0; i < kMaxVec; ++i) yv[i] = i < k ? y[(long long)r * kMaxVec + i] : make_double2(0, 0);
+  for (int i = 0; i < NV; ++i) yv[i] = i < k ? y[(long long)r * kMaxVec + i] : make_double2(0, 0);
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += (long long)gridDim.x * blockDim.x) {
     double2 s = x[(long long)r * N + e];
 #pragma unroll
-    for (int i = 0; i < kMaxVec; ++i)
+    for (int i = 0; i < NV; ++i)
       if (i < k) s = cfma(s, yv[i], Z[((long long)i * nrhs + r) * N + e]);
     x[(long long)r * N + e] = s;
   }
@@ -462,6 +504,15 @@ inline unsigned grid1(long long count, int bs = 256, long long cap = 8192) {
   return (unsigned)std::max<long long>(1, std::min(g, cap));
 }
 
+// launches kernel<NV> with the smallest vector-count bucket NV >= nv
+#define LSP_NV_DISPATCH(nv, CALL)                 \
+  do {                                            \
+    if ((nv) <= 4) { constexpr int NV = 4; CALL; }        \
+    else if ((nv) <= 8) { constexpr int NV = 8; CALL; }   \
+    else if ((nv) <= 16) { constexpr int NV = 16; CALL; } \
+    else { constexpr int NV = kMaxVec; CALL; }            \
+  } while (0)
+
 }  // namespace
 
 int dot_blocks(long long N) {
@@ -472,7 +523,8 @@ int dot_blocks(long long N) {
 void k_dots(const double2* V, const double2* w, double2* partial, double2* h, double2* H, double* scal, int nvec,
             int k, int restart, int mode, long long N, int nrhs, const int* active, hipStream_t st) {
   int nblk = dot_blocks(N);
-  LSP_LAUNCH("dots_partial", 0, dots_partial_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, V, w, partial, nvec, N, nrhs, active);
+  LSP_NV_DISPATCH(nvec, LSP_LAUNCH("dots_partial", 0, dots_partial_kernel<NV>, dim3(nblk, nrhs), dim3(KB), 0, st, V, w,
+                                    partial, nvec, N, nrhs, active));
   LSP_LAUNCH("dots_final", 0, dots_final_kernel, dim3(nrhs), dim3(kFinSlices * kMaxVec), 0, st, partial, h, H, scal, nvec, nblk, k, restart, mode,
                      active);
 }
@@ -481,7 +533,7 @@ void k_norm(const double2* w, double2* partial, double2* h, double2* H, double* 
             int nrhs, const int* active, hipStream_t st) {
   // ||w||^2 = sum conj(w) w: the dot kernel with V = w and nrhs-strided layout
   int nblk = dot_blocks(N);
-  LSP_LAUNCH("dots_partial", 0, dots_partial_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, w, w, partial, 1, N, nrhs, active);
+  LSP_LAUNCH("dots_partial", 0, dots_partial_kernel<4>, dim3(nblk, nrhs), dim3(KB), 0, st, w, w, partial, 1, N, nrhs, active);
   LSP_LAUNCH("dots_final", 0, dots_final_kernel, dim3(nrhs), dim3(kFinSlices * kMaxVec), 0, st, partial, h, H, scal, 1, nblk, k, restart, 2,
                      active);
 }
@@ -489,18 +541,22 @@ void k_norm(const double2* w, double2* partial, double2* h, double2* H, double* 
 void k_arnoldi_orth(const double2* V, double2* w, double2* pA, double2* pB, double2* h, double2* H, double* scal,
                     double2* vnext, int k, int restart, long long N, int nrhs, const int* active, hipStream_t st) {
   const int nblk = dot_blocks(N), nvec = k + 1;
-  LSP_LAUNCH("dots_partial", 0, dots_partial_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, V, w, pA, nvec, N, nrhs, active);
-  LSP_LAUNCH("cgs", 0, cgs_kernel<0>, dim3(nblk, nrhs), dim3(KB), 0, st, V, w, pA, pB, h, H, nvec, N, nrhs, k, restart, 0,
-             active);
-  LSP_LAUNCH("cgs", 0, cgs_kernel<1>, dim3(nblk, nrhs), dim3(KB), 0, st, V, w, pB, pA, h, H, nvec, N, nrhs, k, restart, 1,
-             active);
+  LSP_NV_DISPATCH(nvec, {
+    LSP_LAUNCH("dots_partial", 0, dots_partial_kernel<NV>, dim3(nblk, nrhs), dim3(KB), 0, st, V, w, pA, nvec, N, nrhs,
+               active);
+    LSP_LAUNCH("cgs", 0, (cgs_kernel<0, NV>), dim3(nblk, nrhs), dim3(KB), 0, st, V, w, pA, pB, h, H, nvec, N, nrhs, k,
+               restart, 0, active);
+    LSP_LAUNCH("cgs", 0, (cgs_kernel<1, NV>), dim3(nblk, nrhs), dim3(KB), 0, st, V, w, pB, pA, h, H, nvec, N, nrhs, k,
+               restart, 1, active);
+  });
   LSP_LAUNCH("scale_norm", 0, scale_norm_kernel, dim3(nblk, nrhs), dim3(KB), 0, st, vnext, w, pA, H, scal, N, k, restart,
              active);
 }
 
 void k_axpy(const double2* V, double2* w, const double2* h, int nvec, long long N, int nrhs, const int* active,
             hipStream_t st) {
-  LSP_LAUNCH("axpy", 0, axpy_kernel, dim3(grid1(N, KB, 1024), nrhs), dim3(KB), 0, st, V, w, h, nvec, N, nrhs, active);
+  LSP_NV_DISPATCH(nvec, LSP_LAUNCH("axpy", 0, axpy_kernel<NV>, dim3(grid1(N, KB, 1024), nrhs), dim3(KB), 0, st, V, w, h,
+                                    nvec, N, nrhs, active));
 }
 
 void k_scale(double2* y, const double2* x, const double* scal, long long N, int nrhs, const int* active,
@@ -523,9 +579,10 @@ void k_gmres_control(bool cycle_end, int nrhs, const GmresState& gs, const Gmres
 }
 
 void k_backsolve_update(const double2* H, const double2* gam, double2* y, const int* ksz, double2* x, const double2* Z,
-                        int restart, long long N, int nrhs, hipStream_t st) {
+                        int restart, int kmax, long long N, int nrhs, hipStream_t st) {
   LSP_LAUNCH("backsolve", 0, backsolve_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, H, gam, y, ksz, restart, nrhs);
-  LSP_LAUNCH("update", 0, update_kernel, dim3(grid1(N, 256, 1024), nrhs), dim3(256), 0, st, x, Z, y, ksz, N, nrhs);
+  LSP_NV_DISPATCH(kmax, LSP_LAUNCH("update", 0, update_kernel<NV>, dim3(grid1(N, 256, 1024), nrhs), dim3(256), 0, st, x,
+                                   Z, y, ksz, N, nrhs));
 }
 
 void k_sub(double2* r, const double2* g, const double2* t, long long count, hipStream_t st) {

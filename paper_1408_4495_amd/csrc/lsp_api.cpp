@@ -1161,6 +1161,7 @@ lsp_status lsp_solve(lsp_problem* pb, int nrhs, int rhs_kind, const void* rhs, v
     while (nact > 0) {
       k_cycle_init(s.H, s.gam, s.scal, R, nrhs, st);
       k_scale(s.V, s.r, s.scal, N, nrhs, s.active, st);
+      int steps = 0;
       for (int k = 0; k < R; ++k) {
         double2* Vk = s.V + (size_t)k * NB;
         double2* Zk = s.Z + (size_t)k * NB;
@@ -1169,9 +1170,10 @@ lsp_status lsp_solve(lsp_problem* pb, int nrhs, int rhs_kind, const void* rhs, v
         k_arnoldi_orth(s.V, s.w, s.partial, s.partial2, s.h, s.H, s.scal, s.V + (size_t)(k + 1) * NB, k, R, N, nrhs,
                        s.active, st);
         k_givens(s.H, s.cs, s.sn, s.gam, k, R, nrhs, gs, gp, hv, ++pb->ctl_tag, st);
+        steps = k + 1;
         if (pb->wait_ctl(pb->ctl_tag) == 0) break;
       }
-      k_backsolve_update(s.H, s.gam, s.y, s.ksz, x, s.Z, R, N, nrhs, st);
+      k_backsolve_update(s.H, s.gam, s.y, s.ksz, x, s.Z, R, steps, N, nrhs, st);
       // true residual in complex128
       apply_conv(pb, s, nrhs, LSP_FP64, x, s.t, true, pb->d.w2m);
       k_sub(s.r, s.g, s.t, NB, st);
