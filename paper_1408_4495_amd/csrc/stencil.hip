@@ -453,31 +453,36 @@ __global__ void assemble_kernel(double2* __restrict__ Mval, const double2* __res
   Mval[id] = v;
 }
 
-// y_i = sum_s alpha_{c(i)}(s) x_{i+s}, complex128.
-template <typename Cx>
-__global__ void applyQ_kernel(Cx* __restrict__ y, const double2* __restrict__ x, const double2* __restrict__ alpha_pad,
-                              int n, int d, long long N, int nrhs) {
-  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= N * nrhs) return;
-  long long pt = id % N;
-  long long rbase = id - pt;
-  int i[3] = {(int)(pt % n), (int)((pt / n) % n), d == 3 ? (int)(pt / ((long long)n * n)) : 0};
-  int c = point_class(i, n, d);
-  const int ns = d == 2 ? 9 : 27;
+// y_i = sum_s alpha_{c(i)}(s) x_{i+s}, complex128.  Grid: blockIdx.x =
+// line (i2 + n i3) times the nb1 blocks of 256 along i1, plus the block;
+// blockIdx.y the right-hand side; the 3^D offsets unrolled, neighbours
+// outside the grid skipped.
+template <typename Cx, int D>
+__global__ void __launch_bounds__(256) applyQ_kernel(Cx* __restrict__ y, const double2* __restrict__ x,
+                                                     const double2* __restrict__ alpha_pad, int n, long long N,
+                                                     int nb1) {
+  const int line = blockIdx.x / nb1;
+  const int i1 = (blockIdx.x - line * nb1) * 256 + threadIdx.x;
+  if (i1 >= n) return;
+  const int i2 = D == 2 ? line : line % n, i3 = D == 2 ? 0 : line / n;
+  const int i[3] = {i1, i2, i3};
+  const int c = point_class(i, n, D);
+  const long long rb = (long long)blockIdx.y * N;
+  const long long pt = (long long)line * n + i1;
+  constexpr int NS = D == 2 ? 9 : 27;
+  const double2* al = alpha_pad + c * S;
   double2 acc = make_double2(0, 0);
-  for (int slot = 0; slot < ns; ++slot) {
-    int o[3] = {slot % 3 - 1, (slot / 3) % 3 - 1, slot / 9 - 1};
-    bool inside = true;
-    long long nb = 0, st = 1;
-    for (int a = 0; a < d; ++a) {
-      int j = i[a] + o[a];
-      inside = inside && j >= 0 && j < n;
-      nb += (long long)j * st;
-      st *= n;
+#pragma unroll
+  for (int slot = 0; slot < NS; ++slot) {
+    const int o1 = slot % 3 - 1, o2 = (slot / 3) % 3 - 1, o3 = slot / 9 - 1;
+    const bool inside = i1 + o1 >= 0 && i1 + o1 < n && i2 + o2 >= 0 && i2 + o2 < n &&
+                        (D == 2 || (i3 + o3 >= 0 && i3 + o3 < n));
+    if (inside) {
+      const long long nb = pt + o1 + (long long)o2 * n + (D == 3 ? (long long)o3 * n * n : 0);
+      acc = cadd(acc, cmul(al[slot], x[rb + nb]));
     }
-    if (inside) acc = cadd(acc, cmul(alpha_pad[c * S + slot], x[rbase + nb]));
   }
-  y[id] = from_c128<Cx>(acc);
+  y[rb + pt] = from_c128<Cx>(acc);
 }
 
 }  // namespace
@@ -509,10 +514,13 @@ void launch_assemble(double2* Mval, const double2* alpha_pad, const double2* C_p
 template <typename Cx>
 void launch_applyQ(Cx* y, const double2* x, const double2* alpha_pad, int n, int d, long long N, int nrhs,
                    hipStream_t st) {
-  long long total = N * nrhs;
-  int bs = 256;
-  LSP_LAUNCH("applyQ", (int)sizeof(Cx), applyQ_kernel<Cx>, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, y, x, alpha_pad,
-                     n, d, N, nrhs);
+  const int nb1 = (n + 255) / 256;
+  const long long lines = d == 2 ? n : (long long)n * n;
+  const dim3 grid((unsigned)(lines * nb1), nrhs);
+  if (d == 2)
+    LSP_LAUNCH("applyQ", (int)sizeof(Cx), (applyQ_kernel<Cx, 2>), grid, dim3(256), 0, st, y, x, alpha_pad, n, N, nb1);
+  else
+    LSP_LAUNCH("applyQ", (int)sizeof(Cx), (applyQ_kernel<Cx, 3>), grid, dim3(256), 0, st, y, x, alpha_pad, n, N, nb1);
 }
 
 template void launch_applyQ<double2>(double2*, const double2*, const double2*, int, int, long long, int, hipStream_t);
