@@ -13,15 +13,22 @@ Section 2.1 discretises the convolution with the trapezoid rule on the grid:
     3D: k_0 = (exp(i w rho)(1 - i w rho) - 1) / w^2
   A second option (self_term 1) is the integral of G over the cell itself,
   computed here by plain adaptive quadrature of that definition.
+
+Section 5 (eq:lap, eq:lslap): the 3D Laplace equation with a potential V is
+the limit w -> 0: G(x) = 1/(4 pi |x|), and the ball self-term tends to
+rho^2 / 2 (the series of exp(i w rho)(1 - i w rho) - 1 starts at (w rho)^2 / 2).
+omega = 0 selects it (3D only; the paper treats no 2D Laplace case).
 """
 import numpy as np
 import scipy.special as sp
 
 
 def green(r, omega, d):
-    """G at distance r > 0 (Section 1)."""
+    """G at distance r > 0 (Section 1; omega = 0: Section 5's 1/(4 pi r))."""
     r = np.asarray(r, dtype=np.float64)
     if d == 2:
+        if omega == 0:
+            raise ValueError("the Laplace case (omega = 0) is three-dimensional")
         return 0.25j * sp.hankel1(0, omega * r)
     if d == 3:
         return np.exp(1j * omega * r) / (4.0 * np.pi * r)
@@ -43,7 +50,11 @@ def self_term(h, omega, d, mode=0):
         return cell_self_term(h, omega, d)
     rho = self_radius(h, d)
     if d == 2:
+        if omega == 0:
+            raise ValueError("the Laplace case (omega = 0) is three-dimensional")
         return 1j * np.pi * rho / (2.0 * omega) * sp.hankel1(1, omega * rho) - 1.0 / omega ** 2
+    if omega == 0:
+        return complex(rho * rho / 2.0)  # integral of 1/(4 pi r) over the ball
     return (np.exp(1j * omega * rho) * (1.0 - 1j * omega * rho) - 1.0) / omega ** 2
 
 

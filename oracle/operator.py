@@ -83,11 +83,14 @@ def apply_K_fft(v, n, d, omega, khat=None):
 
 
 class Operator:
-    """A = I + K w^2 m and g = K(-w^2 m u_I), with K applied by FFT."""
+    """A = I + K p and g = K(-p u_I) with p = w^2 m, or for Section 5's
+    Laplace case (eq:lslap) p = V and g = K f; K applied by FFT."""
 
-    def __init__(self, n, d, omega, m, ktab=None):
+    def __init__(self, n, d, omega, m, ktab=None, potential=None):
         self.n, self.d, self.omega = n, d, float(omega)
-        self.m = np.asarray(m, dtype=np.float64)
+        self.m = np.asarray(m, dtype=np.float64) if m is not None else None
+        self.p = (np.asarray(potential, dtype=np.float64) if potential is not None
+                  else self.omega ** 2 * self.m)
         self.ktab = kernel_table(n, d, omega) if ktab is None else ktab
         self.khat = np.fft.fftn(embedded_kernel(n, d, omega, self.ktab))
 
@@ -95,7 +98,11 @@ class Operator:
         return apply_K_fft(v, self.n, self.d, self.omega, self.khat)
 
     def apply(self, u):
-        return u + self.K(self.omega ** 2 * self.m * u)
+        return u + self.K(self.p * u)
 
     def rhs(self, uI):
-        return self.K(-self.omega ** 2 * self.m * uI)
+        return self.K(-self.p * uI)
+
+    def rhs_source(self, f):
+        """g = K f: the source term of eq:lslap (G * f)."""
+        return self.K(np.asarray(f, dtype=np.complex128))

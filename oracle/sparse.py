@@ -2,7 +2,7 @@
 
 Section 2.2, eq:PCapp / eq:PC and Section 3.1 eq:ABop:
   Q = [A; B]      row i: Q(i, i+s) = alpha_{c(i)}(s) for s in mu_{c(i)}
-  M = [A + C w^2 m; B]
+  M = [A + C w^2 m; B]  (Section 5's Laplace case: V in place of w^2 m)
      interior row i: M(i, i+s) = alpha(s) + C(s) w^2 m_{i+s}
      boundary row i: M(i, :) = B(i, :) = Q(i, :)
   preconditioner: v -> M^{-1} (Q v).
@@ -33,13 +33,14 @@ def _neighbour(n, d, offsets):
     return out
 
 
-def build_QM(n, d, omega, m, stencils):
+def build_QM(n, d, omega, m, stencils, potential=None):
     N = n ** d
     cls = point_class(n, d)
     ic = interior_class(d)
     rows_q, cols_q, vals_q = [], [], []
     rows_m, cols_m, vals_m = [], [], []
-    w2m = omega ** 2 * np.asarray(m, dtype=np.float64)
+    w2m = (np.asarray(potential, dtype=np.float64) if potential is not None
+           else omega ** 2 * np.asarray(m, dtype=np.float64))
     for st in stencils:
         pts = np.nonzero(cls == st.c)[0]
         if pts.size == 0:

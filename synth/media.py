@@ -56,6 +56,36 @@ def medium_disks(n, rng, count=40, c_lo=0.1, c_hi=0.9, r_lo=0.01, r_hi=0.05,
     return m
 
 
+def potential_gaussian(n, peak_h2=1.1, width=0.12, centre=None):
+    """Section 5's first example: a negative Gaussian potential,
+    V(x) = -peak_h2 n^2 exp(-|x - c|^2 / (2 width^2)), c = (1/2, 1/2, 1/2)
+    (V proportional to 1/h^2 so that the problem loses ellipticity)."""
+    X = grid_coords(n, 3)
+    c = np.full(3, 0.5) if centre is None else np.asarray(centre, dtype=np.float64)
+    r2 = np.sum((X - c) ** 2, axis=1)
+    return -peak_h2 * n * n * np.exp(-r2 / (2.0 * width * width))
+
+
+def potential_ball(n, peak_h2=1.1, radius=0.25, centre=None):
+    """Section 5's second example: a negative smoothed characteristic
+    function of a ball, V(x) = -peak_h2 n^2 (1 - tanh((|x - c| - radius) / (2h))) / 2."""
+    X = grid_coords(n, 3)
+    c = np.full(3, 0.5) if centre is None else np.asarray(centre, dtype=np.float64)
+    dist = np.sqrt(np.sum((X - c) ** 2, axis=1))
+    return -peak_h2 * n * n * 0.5 * (1.0 - np.tanh((dist - radius) * n / 2.0))
+
+
+def delta_source(n, d, points):
+    """Discrete delta sources: row k is e_j / h^d at the grid point j nearest
+    to points[k] (so that the grid quadrature of f is 1)."""
+    points = np.atleast_2d(np.asarray(points, dtype=np.float64))
+    f = np.zeros((points.shape[0], n ** d), dtype=np.complex128)
+    for k, x in enumerate(points):
+        i = np.clip(np.floor(x * n).astype(np.int64), 0, n - 1)
+        f[k, int(np.sum(i * n ** np.arange(d)))] = float(n) ** d
+    return f
+
+
 def directions_2d(count, offset=0.0):
     """Unit vectors at angles offset + 2 pi j / count."""
     th = offset + 2.0 * np.pi * np.arange(count) / count
@@ -147,11 +177,28 @@ def _c4s():
     return dict(name="3d_n32_6bumps_8rhs", n=n, d=d, omega=omega, m=m, uI=uI)
 
 
-WORKLOADS = {"c1": _c1, "c2": _c2, "c3": _c3, "c4": _c4, "c4s": _c4s}
+# Section 5's Laplace tests: a delta source near the top left corner of the
+# middle cross-section (x1 = 1/8, x2 = 7/8, x3 = 1/2), potentials of about
+# -1.1 / h^2 at their peak (the paper's 5.8e2, 2.3e3, 9.2e3 at N = 1.2e4, 1.0e5,
+# 8.6e5); grids of 24, 48, 96 points per side.
+LAPLACE_SOURCE = (0.125, 0.875, 0.5)
+
+
+def _laplace(n, kind):
+    V = potential_gaussian(n) if kind == "gauss" else potential_ball(n)
+    f = delta_source(n, 3, [LAPLACE_SOURCE])
+    return dict(name=f"3d_n{n}_laplace_{kind}", n=n, d=3, omega=0.0, m=None, V=V, f=f, laplace=True)
+
+
+WORKLOADS = {"c1": _c1, "c2": _c2, "c3": _c3, "c4": _c4, "c4s": _c4s,
+             "l1": lambda: _laplace(24, "gauss"), "l2": lambda: _laplace(48, "gauss"),
+             "l3": lambda: _laplace(96, "gauss"), "l1b": lambda: _laplace(24, "ball"),
+             "l2b": lambda: _laplace(48, "ball")}
 
 
 def workload(key):
-    """Return the seeded workload dict (n, d, omega, m [N], uI [nrhs, N])."""
+    """Return the seeded workload dict: Helmholtz (n, d, omega, m [N],
+    uI [nrhs, N]) or Laplace (n, d = 3, omega = 0, V [N], f [nrhs, N])."""
     return WORKLOADS[key]()
 
 

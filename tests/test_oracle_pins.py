@@ -451,3 +451,77 @@ def test_cell_self_term_face_form(d):
                     + 1j * integrate.dblquad(f, 0, a, 0, a, args=(np.imag,), epsabs=1e-18)[0])
     k0 = cell_self_term(h, w, d)
     assert abs(k0 - ref) <= 1e-9 * abs(ref)
+
+
+# ---- Section 5: the 3D Laplace equation with a potential (omega = 0)
+
+def test_laplace_self_term_is_the_helmholtz_limit():
+    """Ball self-term: the Laplace value rho^2 / 2 against the Helmholtz
+    closed form at small w, whose series is rho^2/2 + i w rho^3/3 - w^2 rho^4/8
+    + ..., so |k0(w) - rho^2/2 - i w rho^3 / 3| <= w^2 rho^4 for w rho << 1."""
+    from oracle.greens import self_term, self_radius
+    h = 1.0 / 24
+    rho = self_radius(h, 3)
+    lap = self_term(h, 0.0, 3)
+    assert abs(lap - rho * rho / 2) <= 1e-15 * rho * rho
+    for w in (1e-1, 1e-2):
+        k0 = self_term(h, w, 3)
+        assert abs(k0 - lap - 1j * w * rho ** 3 / 3) <= w * w * rho ** 4
+
+
+def test_laplace_cell_self_term_closed_form():
+    """Cell self-term for G = 1/(4 pi r): the oracle's quadrature of G over
+    [-h/2, h/2]^3 against the closed-form potential of a uniform cube at its
+    centre, int over [-1, 1]^3 of 1/r = 24 ln(1 + sqrt 3) - 12 ln 2 - 2 pi,
+    scaled by (h/2)^2 / (4 pi) (agreement 1e-10 relative)."""
+    from oracle.greens import cell_self_term
+    h = 1.0 / 16
+    ref = (24 * np.log(1 + np.sqrt(3)) - 12 * np.log(2) - 2 * np.pi) * (h / 2) ** 2 / (4 * np.pi)
+    assert abs(cell_self_term(h, 0.0, 3) - ref) <= 1e-10 * ref
+
+
+def test_laplace_kernel_reproduces_gaussian_charge_potential():
+    """K f for a Gaussian charge density f (unit total charge, width 0.08)
+    against its exact Newtonian potential erf(r / (sqrt 2 s)) / (4 pi r):
+    second-order convergence of the trapezoid rule with the self-term
+    (max error 1.5e-2 at n = 16, 5e-3 at n = 32, ratio >= 2.5).  Dropping
+    k_0 (about 6% of the peak) or a wrong h^3 factor fails this."""
+    from scipy.special import erf
+    errs = []
+    for n in (16, 32):
+        X = synth.grid_coords(n, 3)
+        s = 0.08
+        r = np.linalg.norm(X - 0.5, axis=1)
+        f = np.exp(-r ** 2 / (2 * s * s)) / ((2 * np.pi) ** 1.5 * s ** 3)
+        op = Operator(n, 3, 0.0, None, potential=np.zeros(n ** 3))
+        g = op.rhs_source(f)
+        phi = erf(r / (np.sqrt(2) * s)) / (4 * np.pi * r)
+        errs.append(np.max(np.abs(g - phi)) / np.max(np.abs(phi)))
+    assert errs[0] <= 1.5e-2 and errs[1] <= 5e-3 and errs[0] / errs[1] >= 2.5
+
+
+def test_laplace_solve_matches_neumann_series():
+    """u + K(V u) = K f with a weak potential (||K V|| < 1): the oracle's
+    preconditioned GMRES solution against the Neumann series
+    sum_k (-K V)^k K f summed to 1e-14 with the oracle's FFT K (1e-10)."""
+    from oracle.solve import OracleProblem
+    n = 12
+    V = synth.potential_gaussian(n, peak_h2=0.05)
+    f = synth.delta_source(n, 3, [(0.25, 0.75, 0.5)])[0]
+    prob = OracleProblem(n, 3, 0.0, None, potential=V)
+    sol = prob.solve_source(f, tol=1e-12)
+    assert sol.converged
+    g = prob.op.rhs_source(f)
+    term, acc = g.copy(), g.copy()
+    for _ in range(200):
+        term = -prob.op.K(V * term)
+        acc += term
+        if np.linalg.norm(term) <= 1e-15 * np.linalg.norm(acc):
+            break
+    assert np.linalg.norm(sol.x - acc) <= 1e-10 * np.linalg.norm(acc)
+
+
+def test_laplace_rejects_2d():
+    from oracle.greens import green
+    with pytest.raises(ValueError):
+        green(np.array([0.1]), 0.0, 2)
