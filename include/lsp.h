@@ -64,8 +64,21 @@ typedef enum {
 
 typedef enum {
   LSP_RHS_INCIDENT = 0,  /* rhs holds u_I; the library forms g = K(-w^2 m u_I) */
-  LSP_RHS_G = 1          /* rhs holds g itself */
+  LSP_RHS_G = 1,         /* rhs holds g itself */
+  LSP_RHS_SOURCE = 2     /* rhs holds a source density f on the grid; the
+                            library forms g = K f (the right-hand side G * f
+                            of Section 5's eq:lslap; a discrete delta source
+                            at grid point j is f = e_j / h^d) */
 } lsp_rhs_kind;
+
+typedef enum {
+  LSP_HELMHOLTZ = 0,  /* eq:lsd: (I + K w^2 m) u = g, G the Helmholtz
+                         Green's function of Section 1, w > 0 */
+  LSP_LAPLACE = 1     /* Section 5 (eq:lap, eq:lslap), 3D only: (I + K V) u =
+                         K f with G(x) = 1/(4 pi |x|), the limit w -> 0 of
+                         the 3D Helmholtz G; lsp_setup takes w = 0 and the
+                         potential V in place of the medium m */
+} lsp_equation;
 
 typedef struct {
   double tol;        /* relative residual ||g - A u|| / ||g|| to reach (1e-8) */
@@ -105,6 +118,7 @@ typedef struct {
                         integral of G over the grid cell itself (square /
                         cube of side h), by Gauss-Legendre quadrature of
                         its closed-form radial integral */
+  int equation;      /* lsp_equation (LSP_HELMHOLTZ); LSP_LAPLACE needs d = 3 */
   const char* tile_cache; /* NULL (default), or a text file of tuned
                         trailing-update tile tables, one line per
                         (n, d, precision): lsp_plan_create takes the tiles
@@ -234,11 +248,15 @@ lsp_status lsp_plan_bytes(const lsp_plan* plan, int precision, int nrhs,
  *   the 3^d stencil null vectors alpha_c (eq:Fmin, eq:Emin, eq:Cmin) and
  *   C_c = alpha_c K(mu_c, mu_c) (Section 2.2),
  *   the stencil matrix M (eq:ABop) in N x 3^d form.
- * m_dev: [N] real double medium, read during this call only.
+ * m_dev: [N] real double medium m (Helmholtz) or potential V (Laplace:
+ * omega must be 0, V takes the place of w^2 m everywhere, and k_0 is the
+ * w -> 0 limit of the Helmholtz self term: rho^2 / 2 for the ball, the
+ * cube's potential at its centre for the cell), read during this call only.
  * ws_dev / ws_bytes: device workspace of at least problem_bytes; it must
  * outlive the problem.  stream: a hipStream_t (NULL = default stream).
  * precision comes from the plan's options.  Errors: LSP_ERR_ARG (w <= 0 or
- * not finite, null pointers, small workspace), LSP_ERR_OOM (the plan's
+ * not finite for Helmholtz, w != 0 for Laplace, null pointers, small
+ * workspace), LSP_ERR_OOM (the plan's
  * first upload to this device), LSP_ERR_HIP.  Only enqueues device work. */
 lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev,
                      void* ws_dev, size_t ws_bytes, void* stream,

@@ -580,10 +580,14 @@ double2 cell_self_term(double h, double omega, int d) {
     for (size_t j = 0; j < x.size(); ++j) {
       const double y = a * x[i], zz = a * x[j];
       const double rho = std::sqrt(a * a + y * y + zz * zz), t = omega * rho;
-      const double c = std::cos(t), sn = std::sin(t);
-      const double jac = a / (rho * rho * rho) * a * a * w[i] * w[j] / (4.0 * pi * omega * omega);
-      re += (c + t * sn - 1.0) * jac;
-      im += (sn - t * c) * jac;
+      const double jac = a / (rho * rho * rho) * a * a * w[i] * w[j] / (4.0 * pi);
+      if (omega == 0.0) {  // the radial integral of 1/(4 pi r) r^2: rho^2 / 2
+        re += 0.5 * rho * rho * jac;
+      } else {
+        const double c = std::cos(t), sn = std::sin(t);
+        re += (c + t * sn - 1.0) * jac / (omega * omega);
+        im += (sn - t * c) * jac / (omega * omega);
+      }
     }
   return make_double2(24.0 * re, 24.0 * im);
 }
@@ -600,6 +604,7 @@ double2 self_term_host(double h, double omega, int d, int mode) {
     return make_double2(-s * y1 - 1.0 / (omega * omega), s * j1);
   }
   double rho = h * std::cbrt(3.0 / (4.0 * pi));
+  if (omega == 0.0) return make_double2(0.5 * rho * rho, 0.0);  // the Laplace limit
   double z = omega * rho;
   double c = std::cos(z), sn = std::sin(z);
   // (e^{iz}(1 - iz) - 1) / w^2
@@ -774,6 +779,7 @@ lsp_status lsp_options_default(lsp_options* o) {
   o->dense_sweeps = 1;
   o->blocked_sweeps = 1;
   o->self_term = 0;
+  o->equation = LSP_HELMHOLTZ;
   o->tile_cache = nullptr;
   return LSP_OK;
 }
@@ -792,6 +798,8 @@ lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts, 
     LSP_REQUIRE(o.dense_sweeps >= 0 && o.dense_sweeps <= 2, "dense_sweeps must be 0, 1 or 2");
     LSP_REQUIRE(o.blocked_sweeps >= 0 && o.blocked_sweeps <= 2, "blocked_sweeps must be 0, 1 or 2");
     LSP_REQUIRE(o.self_term == 0 || o.self_term == 1, "self_term must be 0 or 1");
+    LSP_REQUIRE(o.equation == LSP_HELMHOLTZ || o.equation == LSP_LAPLACE, "unknown equation");
+    LSP_REQUIRE(o.equation == LSP_HELMHOLTZ || d == 3, "the Laplace equation is three-dimensional (d must be 3)");
     const std::string cache = o.tile_cache ? o.tile_cache : "";
     o.tile_cache = nullptr;  // the plan keeps no pointer into the caller's memory
     std::unique_ptr<lsp_plan> pl(new lsp_plan());
@@ -904,7 +912,10 @@ lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, vo
     LSP_REQUIRE(out != nullptr, "null problem pointer");
     *out = nullptr;
     LSP_REQUIRE(plan != nullptr && m_dev != nullptr && ws_dev != nullptr, "null argument");
-    LSP_REQUIRE(std::isfinite(omega) && omega > 0, "omega must be positive and finite");
+    if (plan->p.opts.equation == LSP_LAPLACE)
+      LSP_REQUIRE(omega == 0.0, "omega must be 0 for the Laplace equation");
+    else
+      LSP_REQUIRE(std::isfinite(omega) && omega > 0, "omega must be positive and finite");
     const Plan& P = plan->p;
     const int prec = P.opts.precision;
     size_t need = layout_problem(plan, prec, nullptr, nullptr);
@@ -937,7 +948,8 @@ lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, vo
     // kernel table, medium, spectrum
     double h = 1.0 / P.n;
     launch_ktable(pb->d.ktab, P.n, P.d, omega, self_term_host(h, omega, P.d, P.opts.self_term), st);
-    k_w2m(pb->d.w2m, m_dev, omega * omega, P.N, st);
+    // w^2 m, or the potential V itself for the Laplace equation
+    k_w2m(pb->d.w2m, m_dev, P.opts.equation == LSP_LAPLACE ? 1.0 : omega * omega, P.N, st);
     launch_embed(pb->d.E, pb->d.ktab, P.n, P.d, st);
     full_fft_forward<double>(pb->fp64, pb->d.E, st);
     launch_split_spectrum(pb->d.spec64, pb->d.spec32, pb->d.E, P.n, P.d, st);
@@ -1125,7 +1137,8 @@ lsp_status lsp_solve(lsp_problem* pb, int nrhs, int rhs_kind, const void* rhs, v
                      lsp_rhs_info* info) {
   return guarded([&]() -> lsp_status {
     LSP_REQUIRE(pb && rhs && u, "null argument");
-    LSP_REQUIRE(rhs_kind == LSP_RHS_INCIDENT || rhs_kind == LSP_RHS_G, "unknown rhs kind");
+    LSP_REQUIRE(rhs_kind == LSP_RHS_INCIDENT || rhs_kind == LSP_RHS_G || rhs_kind == LSP_RHS_SOURCE,
+                "unknown rhs kind");
     if (!pb->factored) throw Error(LSP_ERR_STATE, "lsp_factor has not succeeded on this problem");
     check_ws(pb, nrhs, true, ws, bytes);
     const Plan& P = pb->plan->p;
@@ -1143,6 +1156,8 @@ lsp_status lsp_solve(lsp_problem* pb, int nrhs, int rhs_kind, const void* rhs, v
     if (rhs_kind == LSP_RHS_INCIDENT) {
       apply_conv(pb, s, nrhs, LSP_FP64, (const double2*)rhs, s.t, false, pb->d.w2m);
       launch_scale_rhs(s.g, s.t, -1.0, NB, st);
+    } else if (rhs_kind == LSP_RHS_SOURCE) {
+      apply_conv(pb, s, nrhs, LSP_FP64, (const double2*)rhs, s.g, false, nullptr);  // g = K f
     } else {
       LSP_HIP(hipMemcpyAsync(s.g, rhs, NB * sizeof(double2), hipMemcpyDeviceToDevice, st));
     }

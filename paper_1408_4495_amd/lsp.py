@@ -14,7 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblsp.so")
 
 LSP_FP64, LSP_MIXED = 0, 1
-LSP_RHS_INCIDENT, LSP_RHS_G = 0, 1
+LSP_RHS_INCIDENT, LSP_RHS_G, LSP_RHS_SOURCE = 0, 1, 2
+LSP_HELMHOLTZ, LSP_LAPLACE = 0, 1
+RHS_KINDS = {"incident": LSP_RHS_INCIDENT, "g": LSP_RHS_G, "source": LSP_RHS_SOURCE}
 STATUS = {0: "LSP_OK", 1: "LSP_ERR_ARG", 2: "LSP_ERR_OOM", 3: "LSP_ERR_HIP",
           4: "LSP_ERR_STATE", 5: "LSP_ERR_SINGULAR", 6: "LSP_ERR_NOCONV"}
 EXPORTED = ["lsp_options_default", "lsp_plan_create", "lsp_plan_destroy", "lsp_plan_stats_get",
@@ -29,7 +31,7 @@ class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
                 ("precision", ctypes.c_int), ("buffer_b", ctypes.c_int), ("leaf", ctypes.c_int),
                 ("panel", ctypes.c_int), ("dense_sweeps", ctypes.c_int), ("blocked_sweeps", ctypes.c_int),
-                ("self_term", ctypes.c_int), ("tile_cache", ctypes.c_char_p)]
+                ("self_term", ctypes.c_int), ("equation", ctypes.c_int), ("tile_cache", ctypes.c_char_p)]
 
 
 class RhsInfo(ctypes.Structure):
@@ -157,7 +159,7 @@ class Plan:
 
     def __init__(self, n, d, max_nrhs=1, tol=1e-8, restart=30, max_iters=1000, precision="fp64",
                  buffer_b=2, leaf=0, panel=0, dense_sweeps=1, blocked_sweeps=1, self_term=0,
-                 tile_cache=None):
+                 tile_cache=None, equation="helmholtz"):
         lib = load()
         o = Options()
         _check(lib.lsp_options_default(ctypes.byref(o)))
@@ -166,6 +168,7 @@ class Plan:
         o.buffer_b, o.leaf, o.panel, o.dense_sweeps = buffer_b, leaf, panel, dense_sweeps
         o.blocked_sweeps = blocked_sweeps
         o.self_term = self_term
+        o.equation = LSP_LAPLACE if equation in ("laplace", LSP_LAPLACE) else LSP_HELMHOLTZ
         o.tile_cache = None if tile_cache is None else os.fsencode(tile_cache)
         self.opts = o
         self.n, self.d, self.max_nrhs = n, d, max_nrhs
@@ -208,8 +211,9 @@ class Plan:
 class Problem:
     """Set-up (kernel table, spectrum, stencils, M) on the GPU; factor; solve.
 
-    m: real medium of length n^d (numpy or torch); device memory comes from
-    torch; work is enqueued on `stream` (default: torch's current stream)."""
+    m: real medium of length n^d (numpy or torch), or for a Laplace plan the
+    potential V (with omega = 0); device memory comes from torch; work is
+    enqueued on `stream` (default: torch's current stream)."""
 
     def __init__(self, plan, omega, m, device="cuda:0", stream=None):
         import torch
@@ -291,7 +295,7 @@ class Problem:
             u = self.torch.empty_like(x)
             ws = self._work(nrhs)
             info = (RhsInfo * nrhs)()
-            k = LSP_RHS_INCIDENT if kind == "incident" else LSP_RHS_G
+            k = RHS_KINDS[kind]
             st = _lib.lsp_solve(self._h, nrhs, k, _ptr(x), _ptr(u), _ptr(ws), ws.numel(), info)
         infos = [{"iters": i.iters, "converged": bool(i.converged), "relres_true": i.relres_true,
                   "relres_est": i.relres_est, "t_setup": i.t_setup, "t_factor": i.t_factor,

@@ -219,3 +219,22 @@ def test_self_term_option_validated(lib):
     with pytest.raises(L.LspError):
         L.Plan(32, 2, self_term=2)
     L.Plan(32, 2, self_term=1)
+
+
+def test_laplace_options_validated(lib):
+    """The Laplace equation (Section 5) is three-dimensional, and its set-up
+    takes omega = 0 (the Helmholtz one omega > 0); both checked before any
+    HIP call."""
+    import ctypes
+    with pytest.raises(L.LspError) as e:
+        L.Plan(16, 2, equation="laplace")
+    assert "three-dimensional" in str(e.value)
+    p = L.Plan(8, 3, equation="laplace")
+    h = ctypes.c_void_p()
+    st = lib.lsp_setup(p._h, 1.0, ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 40, None, ctypes.byref(h))
+    assert st == 1
+    buf = ctypes.create_string_buffer(256)
+    lib.lsp_last_error(buf, 256)
+    assert b"omega must be 0" in buf.value
+    q = L.Plan(8, 3)
+    assert lib.lsp_setup(q._h, 0.0, ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 40, None, ctypes.byref(h)) == 1
