@@ -598,13 +598,16 @@ struct GemmLds {
 
 // One TM x TM tile of C -= A B over the block [base, m)^2 of a front's
 // trailing matrix: A = the L21 rows (columns k0 .. k0+kb), B = the U12
-// columns (rows k0 .. k0+kb) of the panel; (row0, col0) relative to base;
-// entries with row < skip and column < skip are left alone.  4 waves in a
-// 2x2 arrangement, each wave (TM/2)^2 as BW x BW MFMA 16x16 blocks.
+// columns (rows k0 .. k0+kb) of one panel, or of two adjacent panels
+// (kb up to 64, taken as two 32-wide chunks through LDS, the products
+// accumulated in registers, so C is read and written once); (row0, col0)
+// relative to base; entries with row < skip and column < skip, and rows >=
+// rlim or columns >= clim, are left alone.  4 waves in a 2x2 arrangement,
+// each wave (TM/2)^2 as BW x BW MFMA 16x16 blocks.
 template <typename T, int TM>
 __device__ __forceinline__ void update_tile(GemmLds<T, TM>& G, cplx<T>* __restrict__ F, const int k0, const int kb,
                                             const int base, const int m, const int row0, const int col0,
-                                            const int skip) {
+                                            const int skip, const int rlim = INT_MAX, const int clim = INT_MAX) {
   constexpr int BW = TM / 32;
   auto& Ar = G.Ar;
   auto& Ai = G.Ai;
@@ -612,32 +615,6 @@ __device__ __forceinline__ void update_tile(GemmLds<T, TM>& G, cplx<T>* __restri
   auto& Bi = G.Bi;
   const int rem = m - base;
   const int tid = threadIdx.x;
-  const int kpad = (kb + 3) & ~3;
-  // both operand tiles are loaded before the first LDS store (clamped
-  // in-range indices, zero outside the block), so the loads overlap
-  constexpr int LA = TM * NB / 256;
-  cplx<T> va[LA], vb[LA];
-#pragma unroll
-  for (int u = 0; u < LA; ++u) {
-    const int e = tid + 256 * u, r = e % TM, kk = e / TM;
-    const cplx<T> v = F[(base + min(row0 + r, rem - 1)) + (long long)(k0 + min(kk, kb - 1)) * m];
-    va[u] = row0 + r < rem && kk < kb ? v : mk<T>(0, 0);
-  }
-#pragma unroll
-  for (int u = 0; u < LA; ++u) {
-    const int e = tid + 256 * u, kk = e % NB, c = e / NB;
-    const cplx<T> v = F[(k0 + min(kk, kb - 1)) + (long long)(base + min(col0 + c, rem - 1)) * m];
-    vb[u] = col0 + c < rem && kk < kb ? v : mk<T>(0, 0);
-  }
-#pragma unroll
-  for (int u = 0; u < LA; ++u) {
-    const int e = tid + 256 * u;
-    Ar[e / TM][e % TM] = va[u].x;
-    Ai[e / TM][e % TM] = va[u].y;
-    Br[e % NB][e / NB] = vb[u].x;
-    Bi[e % NB][e / NB] = vb[u].y;
-  }
-  __syncthreads();
   using acc_t = typename Mfma<T>::acc_t;
   const int wave = tid / 64, lane = tid % 64;
   const int wr = (wave / 2) * (TM / 2), wc = (wave % 2) * (TM / 2);
@@ -646,24 +623,55 @@ __device__ __forceinline__ void update_tile(GemmLds<T, TM>& G, cplx<T>* __restri
     for (int j = 0; j < BW; ++j)
       for (int v = 0; v < 4; ++v) { accr[i][j][v] = 0; acci[i][j][v] = 0; }
   const int li = lane % 16, lk = lane / 16;
-  // Each 16 x 16 block is computed transposed (the MFMA's first operand is
-  // B's column block, its second A's row block): the result lane l then
-  // holds C rows 16 i + l % 16, so consecutive lanes address consecutive
-  // rows of the column-major front and every load / store of C below covers
-  // whole cache lines.
-  for (int k4 = 0; k4 < kpad; k4 += 4) {
-    T ar[BW], ai[BW], br[BW], bi[BW];
-    for (int i = 0; i < BW; ++i) { ar[i] = Ar[k4 + lk][wr + 16 * i + li]; ai[i] = Ai[k4 + lk][wr + 16 * i + li]; }
-    for (int j = 0; j < BW; ++j) { br[j] = Br[k4 + lk][wc + 16 * j + li]; bi[j] = Bi[k4 + lk][wc + 16 * j + li]; }
-    for (int i = 0; i < BW; ++i)
-      for (int j = 0; j < BW; ++j) {
-        accr[i][j] = Mfma<T>::step(br[j], ar[i], accr[i][j]);
-        accr[i][j] = Mfma<T>::step(bi[j], -ai[i], accr[i][j]);
-        acci[i][j] = Mfma<T>::step(bi[j], ar[i], acci[i][j]);
-        acci[i][j] = Mfma<T>::step(br[j], ai[i], acci[i][j]);
-      }
+  constexpr int LA = TM * NB / 256;
+  for (int kc = 0; kc < kb; kc += NB) {
+    const int kbc = min(NB, kb - kc), kcol = k0 + kc;
+    const int kpad = (kbc + 3) & ~3;
+    if (kc > 0) __syncthreads();  // the previous chunk's reads of the operand tiles are done
+    // both operand tiles are loaded before the first LDS store (clamped
+    // in-range indices, zero outside the block), so the loads overlap
+    cplx<T> va[LA], vb[LA];
+#pragma unroll
+    for (int u = 0; u < LA; ++u) {
+      const int e = tid + 256 * u, r = e % TM, kk = e / TM;
+      const cplx<T> v = F[(base + min(row0 + r, rem - 1)) + (long long)(kcol + min(kk, kbc - 1)) * m];
+      va[u] = row0 + r < rem && kk < kbc ? v : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < LA; ++u) {
+      const int e = tid + 256 * u, kk = e % NB, c = e / NB;
+      const cplx<T> v = F[(kcol + min(kk, kbc - 1)) + (long long)(base + min(col0 + c, rem - 1)) * m];
+      vb[u] = col0 + c < rem && kk < kbc ? v : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < LA; ++u) {
+      const int e = tid + 256 * u;
+      Ar[e / TM][e % TM] = va[u].x;
+      Ai[e / TM][e % TM] = va[u].y;
+      Br[e % NB][e / NB] = vb[u].x;
+      Bi[e % NB][e / NB] = vb[u].y;
+    }
+    __syncthreads();
+    // Each 16 x 16 block is computed transposed (the MFMA's first operand is
+    // B's column block, its second A's row block): the result lane l then
+    // holds C rows 16 i + l % 16, so consecutive lanes address consecutive
+    // rows of the column-major front and every load / store of C below covers
+    // whole cache lines.
+    for (int k4 = 0; k4 < kpad; k4 += 4) {
+      T ar[BW], ai[BW], br[BW], bi[BW];
+      for (int i = 0; i < BW; ++i) { ar[i] = Ar[k4 + lk][wr + 16 * i + li]; ai[i] = Ai[k4 + lk][wr + 16 * i + li]; }
+      for (int j = 0; j < BW; ++j) { br[j] = Br[k4 + lk][wc + 16 * j + li]; bi[j] = Bi[k4 + lk][wc + 16 * j + li]; }
+      for (int i = 0; i < BW; ++i)
+        for (int j = 0; j < BW; ++j) {
+          accr[i][j] = Mfma<T>::step(br[j], ar[i], accr[i][j]);
+          accr[i][j] = Mfma<T>::step(bi[j], -ai[i], accr[i][j]);
+          acci[i][j] = Mfma<T>::step(bi[j], ar[i], acci[i][j]);
+          acci[i][j] = Mfma<T>::step(br[j], ai[i], acci[i][j]);
+        }
+    }
   }
   // C -= A B: per 16-row block i, all BW x 4 loads of C first, then the stores
+  const int rmax = min(rem, rlim), cmax = min(rem, clim);
 #pragma unroll
   for (int i = 0; i < BW; ++i) {
     cplx<T> cv[BW][4];
@@ -681,7 +689,7 @@ __device__ __forceinline__ void update_tile(GemmLds<T, TM>& G, cplx<T>* __restri
       for (int v = 0; v < 4; ++v) {
         const int col = col0 + wc + 16 * j + Mfma<T>::row(lk, v);
         const int row = row0 + wr + 16 * i + li;
-        if (col < rem && row < rem && !(row < skip && col < skip)) {
+        if (col < cmax && row < rmax && !(row < skip && col < skip)) {
           cplx<T> c = cv[j][v];
           c.x -= accr[i][j][v];
           c.y -= acci[i][j][v];
@@ -773,6 +781,48 @@ __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ 
   const int row0 = brow * TM, col0 = blockIdx.x * TM;
   if (row0 >= rem || col0 >= rem) return;
   update_tile<T, TM>(G, F, k0, kb, k1, m, row0, col0, skip);
+}
+
+// Two-panel (rank-64) trailing updates for the large fronts of the levels
+// that run separate launches per panel: panel a = [k0, k0 + 32) is factored,
+// its update applied only to panel b's column and row strips (the "cross":
+// rows [k1, m) of columns [k1, k2), rows [k1, k2) of columns [k2, m)), panel b
+// is factored, and the rest [k2, m)^2 takes both panels' update at once, so
+// each tile of the trailing matrix is read and written once per two panels.
+// Fronts with no panel b take panel a's update over [k1, m)^2 in the second
+// launch.  The cross uses 32-wide tiles: grid x the tile along the strip,
+// y = 0 the column strip, y = 1 the row strip.
+template <typename T>
+__global__ void __launch_bounds__(256) cross_update_kernel(cplx<T>* __restrict__ Fbuf,
+                                                           const FrontDev* __restrict__ fr, int first, int k0) {
+  __shared__ __align__(16) GemmLds<T, 32> G;
+  const FrontDev f = fr[first + blockIdx.z];
+  if (f.p <= k0 + NB) return;  // no panel b: the pair update takes panel a's update
+  const int k1 = k0 + NB, kbb = min(NB, f.p - k1);
+  const int m = f.p + f.q;
+  cplx<T>* F = Fbuf + f.f_off;
+  const int t = blockIdx.x * 32;
+  if (blockIdx.y == 0) {
+    if (t >= m - k1) return;
+    update_tile<T, 32>(G, F, k0, NB, k1, m, t, 0, 0, INT_MAX, kbb);
+  } else {
+    if (kbb + t >= m - k1) return;
+    update_tile<T, 32>(G, F, k0, NB, k1, m, 0, kbb + t, 0, kbb, INT_MAX);
+  }
+}
+
+template <typename T, int TM>
+__global__ void __launch_bounds__(256) pair_update_kernel(cplx<T>* __restrict__ Fbuf,
+                                                          const FrontDev* __restrict__ fr, int first, int k0) {
+  __shared__ __align__(16) GemmLds<T, TM> G;
+  const FrontDev f = fr[first + blockIdx.z];
+  if (f.p <= k0) return;
+  const int m = f.p + f.q;
+  const int kb = min(2 * NB, f.p - k0);  // both panels' columns (panel a only when it is the last)
+  const int base = k0 + kb;
+  const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TM;
+  if (row0 >= m - base || col0 >= m - base) return;
+  update_tile<T, TM>(G, Fbuf + f.f_off, k0, kb, base, m, row0, col0, 0);
 }
 
 // ---------------------------------------------------------------- panel strips
@@ -1963,6 +2013,31 @@ static bool strip_level(const Plan& plan, int l, bool fp64) {
   return cnt * (gt * gt + 2 * nch) <= 256;
 }
 
+// Whether level l runs the two-panel schedule (cross_update_kernel,
+// pair_update_kernel): levels of separate launches per panel (not strip
+// levels) whose fronts reach 512 rows.
+static bool pair_level(const Plan& plan, int l, bool fp64) {
+  return !strip_level(plan, l, fp64) && plan.level_maxpq[l] >= 512;
+}
+
+template <typename T>
+void diag_launch(const MfDev<T>& mf, int cnt, int first, int k0, hipStream_t st) {
+  if (cnt > 512)  // more than two fronts per CU
+    LSP_LAUNCH("diag_lu", (int)sizeof(cplx<T>), (diag_lu_kernel<T, 64>), dim3(cnt), dim3(64), 0, st, mf.F, mf.Dinv,
+               mf.fronts, mf.perm, mf.pivstat, first, k0);
+  else
+    LSP_LAUNCH("diag_lu", (int)sizeof(cplx<T>), (diag_lu_kernel<T, 256>), dim3(cnt), dim3(256), 0, st, mf.F, mf.Dinv,
+               mf.fronts, mf.perm, mf.pivstat, first, k0);
+}
+
+// both panels' update of [k0 + kb, m)^2 (rem = the largest m - k0 - 1)
+template <typename T, int TM>
+void pair_launch(const MfDev<T>& mf, int rem, int cnt, int first, int k0, hipStream_t st) {
+  const int gt = (rem + TM - 1) / TM;
+  LSP_LAUNCH("gemm_update", (int)sizeof(cplx<T>), (pair_update_kernel<T, TM>), dim3(gt, gt, cnt), dim3(256), 0, st,
+             mf.F, mf.fronts, first, k0);
+}
+
 // Panel step k0 of a strip level (a later panel exists in some front):
 // grid row 0 the strip chunks of the next panel, rows 1.. the update tiles.
 template <typename T, int TM>
@@ -2027,6 +2102,33 @@ void mf_factor_levels(const MfDev<T>& mf, const Plan& plan, hipStream_t st, cons
       continue;
     }
     }
+    if (pair_level(plan, l, fp64)) {
+      const int tile = update_tile(plan, l, fp64);
+      for (int k0 = 0; k0 < maxp; k0 += 2 * NB) {
+        diag_launch(mf, cnt, first, k0, st);
+        const int rem = maxm - k0 - 1;
+        if (rem <= 0) continue;
+        LSP_LAUNCH("panel_trsm", (int)sizeof(cplx<T>), panel_trsm_kernel<T>, dim3((rem + 63) / 64, cnt, 2), dim3(256),
+                   0, st, mf.F, mf.Dinv, mf.fronts, mf.perm, first, k0);
+        if (k0 + NB < maxp) {  // some front has a panel b
+          LSP_LAUNCH("gemm_update", (int)sizeof(cplx<T>), cross_update_kernel<T>,
+                     dim3((maxm - k0 - NB + 31) / 32, 2, cnt), dim3(256), 0, st, mf.F, mf.fronts, first, k0);
+          diag_launch(mf, cnt, first, k0 + NB, st);
+          const int rem2 = maxm - k0 - NB - 1;
+          if (rem2 > 0)
+            LSP_LAUNCH("panel_trsm", (int)sizeof(cplx<T>), panel_trsm_kernel<T>, dim3((rem2 + 63) / 64, cnt, 2),
+                       dim3(256), 0, st, mf.F, mf.Dinv, mf.fronts, mf.perm, first, k0 + NB);
+        }
+        if (tile == 128) {
+          if constexpr (sizeof(T) == 4) pair_launch<T, 128>(mf, rem, cnt, first, k0, st);
+        } else if (tile == 64) {
+          pair_launch<T, 64>(mf, rem, cnt, first, k0, st);
+        } else {
+          pair_launch<T, 32>(mf, rem, cnt, first, k0, st);
+        }
+      }
+      continue;
+    }
     bool factored = false;  // panel k0's diagonal block done by the previous update
     for (int k0 = 0; k0 < maxp; k0 += NB) {
       if (!factored) {
@@ -2069,7 +2171,8 @@ FactorSchedule factor_schedule(const Plan& plan, bool fp64) {
     for (int k0 = 0; k0 < plan.level_maxp[l]; k0 += NB) {
       // update launches other than gemm_update: the panel steps of a strip
       // level (all but the last panel) and the lookahead launches
-      const bool step = strips ? k0 + NB < plan.level_maxp[l] : fuse_next(plan, l, k0, fp64);
+      const bool step = strips ? k0 + NB < plan.level_maxp[l]
+                               : (!pair_level(plan, l, fp64) && fuse_next(plan, l, k0, fp64));
       for (int i = plan.level_ptr[l]; i < plan.level_ptr[l + 1]; ++i) {
         const FrontDev& f = plan.fronts[i];
         if (f.p <= k0) continue;
