@@ -35,6 +35,10 @@ WORKLOAD_TEXT = {
     "c3": "2D n=1024 (N=1048576), omega=256pi (8 pts/wavelength), 40 seeded smoothed disks, "
           "16 plane waves as one block",
     "c4": "3D n=64 (N=262144), omega=16pi (8 pts/wavelength), 6 seeded Gaussian bumps, 8 plane waves as one block",
+    "l2": "3D Laplace with a potential (Section 5) n=48 (N=110592), negative Gaussian potential of peak "
+          "-1.1/h^2, one delta source",
+    "l3": "3D Laplace with a potential (Section 5) n=96 (N=884736), negative Gaussian potential of peak "
+          "-1.1/h^2, one delta source",
 }
 
 HBM_PEAK_GBS = 8000.0
@@ -54,14 +58,18 @@ def log(*a):
 
 
 def run_path(lsp, torch, w, m_dev, u_dev, prec, steps, warmup):
+    """m_dev: the medium m, or the potential V of a Laplace workload; u_dev:
+    the incident fields, or the source densities f of a Laplace workload."""
     n, d, omega = w["n"], w["d"], w["omega"]
     nrhs = u_dev.shape[0]
-    plan = lsp.Plan(n, d, max_nrhs=nrhs, precision=prec)
+    lap = bool(w.get("laplace"))
+    kind = "source" if lap else "incident"
+    plan = lsp.Plan(n, d, max_nrhs=nrhs, precision=prec, equation="laplace" if lap else "helmholtz")
 
     def step():
         pb = lsp.Problem(plan, omega, m_dev)
         pb.factor()
-        u, info, st = pb.solve(u_dev)
+        u, info, st = pb.solve(u_dev, kind=kind)
         return pb, u, info, st
 
     for _ in range(warmup):
@@ -85,14 +93,14 @@ def run_path(lsp, torch, w, m_dev, u_dev, prec, steps, warmup):
     # phase split (an untimed extra step): the library's own event times
     pb = lsp.Problem(plan, omega, m_dev)
     pb.factor()
-    u2, info2, _ = pb.solve(u_dev)
+    u2, info2, _ = pb.solve(u_dev, kind=kind)
     phases = pb.phase_ms()
     # solve-only rate with the factorisation cached
     reps = max(3, steps)
     torch.cuda.synchronize()
     s0 = time.perf_counter()
     for _ in range(reps):
-        pb.solve(u_dev)
+        pb.solve(u_dev, kind=kind)
     torch.cuda.synchronize()
     solve_only_s = (time.perf_counter() - s0) / reps
     out = {
@@ -130,7 +138,10 @@ def kernel_model(base, tag, st, w, nrhs, counts):
         # diagonal blocks and the formed super-block operators
         return "hbm", apps * 2.0 * (st["blocked_panel_entries"] + st["blocked_entries"]) * esz, "GB/s"
     if base == "gemm_update":
-        return "mfma", st["update_flops"] - st["fused_update_flops"], "TFLOP/s"
+        return "mfma", (st["update_flops"] - st["fused_update_flops"] - st["pair_update_flops"]
+                        - st["cross_update_flops"]), "TFLOP/s"
+    if base in ("pair_update", "cross_update"):
+        return "mfma", st[base + "_flops"], "TFLOP/s"
     if base in ("panel_step", "update_lu"):
         other = "update_lu" if base == "panel_step" else "panel_step"
         if any(k.startswith(other + " ") for k in counts):
@@ -195,7 +206,8 @@ def measure_roofline(lsp, torch, w, key, m_dev, u_dev, prec):
     per-kernel table and every modelled kernel's fraction."""
     n, d, omega = w["n"], w["d"], w["omega"]
     nrhs = u_dev.shape[0]
-    plan = lsp.Plan(n, d, max_nrhs=nrhs, precision=prec)
+    lap = bool(w.get("laplace"))
+    plan = lsp.Plan(n, d, max_nrhs=nrhs, precision=prec, equation="laplace" if lap else "helmholtz")
     st = plan.stats()
     torch.cuda.synchronize()
     lsp.timing_reset()
@@ -203,7 +215,7 @@ def measure_roofline(lsp, torch, w, key, m_dev, u_dev, prec):
     try:
         pb = lsp.Problem(plan, omega, m_dev)
         pb.factor()
-        pb.solve(u_dev)
+        pb.solve(u_dev, kind="source" if lap else "incident")
         torch.cuda.synchronize()
     finally:
         lsp.timing_enable(False)
@@ -304,8 +316,9 @@ def workload_record(lsp, torch, key, steps, warmup):
     import synth
     w = synth.workload(key)
     dev = torch.device("cuda:0")
-    m_dev = torch.tensor(w["m"], dtype=torch.float64, device=dev)
-    u_dev = torch.tensor(w["uI"], dtype=torch.complex128, device=dev)
+    lap = bool(w.get("laplace"))
+    m_dev = torch.tensor(w["V"] if lap else w["m"], dtype=torch.float64, device=dev)
+    u_dev = torch.tensor(w["f"] if lap else w["uI"], dtype=torch.complex128, device=dev)
     nrhs = u_dev.shape[0]
     log(f"[bench] workload {key}: {WORKLOAD_TEXT[key]}")
     res = {}
@@ -342,7 +355,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOAD_TEXT))
-    ap.add_argument("--extra", default="c4,c2", help="further workloads reported beside the headline")
+    ap.add_argument("--extra", default="c4,c2,l2", help="further workloads reported beside the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()

@@ -12,6 +12,9 @@ reads the GPU library.  Targets (one per run, any number on the command line):
             per-right-hand-side record when the sparse LU fits
   c4s       3D n=32, the same medium recipe and directions (the 3D end-to-end
             golden used when the n=64 sparse LU is out of reach)
+  l2, l2b   Section 5's Laplace equation at 3D n=48 (Gaussian / smoothed-ball
+            potential, delta source): iterations, residual, |u| and a strided
+            sample of u
 
 Usage: python tests/golden/make_golden.py c1 st256 c3 c4s
 """
@@ -31,7 +34,7 @@ from oracle.greens import kernel_table  # noqa: E402
 from oracle.stencil import all_stencils  # noqa: E402
 from oracle.solve import OracleProblem  # noqa: E402
 
-SAMPLE_STRIDE = {1024: 2055, 64: 517, 32: 67}
+SAMPLE_STRIDE = {1024: 2055, 64: 517, 32: 67, 48: 113}
 
 
 def log(*a):
@@ -130,8 +133,25 @@ def make_c4s():
     _full("c4s", None, "c4s_oracle.json", synth.workload("c4s"))
 
 
+def make_laplace(key):
+    w = synth.workload(key)
+    n = w["n"]
+    t0 = time.perf_counter()
+    prob = OracleProblem(n, 3, 0.0, None, b=2, potential=w["V"])
+    log(f"{key}: oracle set-up + SuperLU {time.perf_counter() - t0:.1f} s")
+    idx = np.arange(0, n ** 3, SAMPLE_STRIDE[n])
+    out = []
+    for r in range(w["f"].shape[0]):
+        res = prob.solve_source(w["f"][r])
+        log(f"  source {r}: iters {res.iters} relres {res.relres:.3e}")
+        out.append({"iters": int(res.iters), "relres": float(res.relres), "u_norm": float(np.linalg.norm(res.x)),
+                    "u_sample": [[float(v.real), float(v.imag)] for v in res.x[idx]]})
+    _dump(f"{key}_oracle.json", {"workload": key, "n": n, "d": 3, "omega": 0.0, "b": 2, "tol": 1e-8,
+                                 "restart": 30, "sample_start": 0, "sample_stride": SAMPLE_STRIDE[n], "rhs": out})
+
+
 TARGETS = {"c1": make_c1, "st256": make_st256, "c3": make_c3, "st3d64": make_c4_stencils,
-           "c4": make_c4, "c4s": make_c4s}
+           "c4": make_c4, "c4s": make_c4s, "l2": lambda: make_laplace("l2"), "l2b": lambda: make_laplace("l2b")}
 
 if __name__ == "__main__":
     for t in sys.argv[1:] or ["c1"]:

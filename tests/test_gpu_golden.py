@@ -11,7 +11,9 @@ GMRES) and the seeded input generators.  Compared here:
     in the benchmark's launch configuration (all right-hand sides in one
     batch): FP64 solution within 1e-8 of the oracle's (relative, on a fixed
     strided sample of entries, and the norms), iterations within 1; the
-    mixed path's true residual <= 1e-8 and its solution within 1e-6.
+    mixed path's true residual <= 1e-8 and its solution within 1e-6;
+  * the same for Section 5's Laplace equation with a potential at 3D n = 48
+    (negative Gaussian potential, one delta source, g = K f).
 """
 import json
 import os
@@ -105,3 +107,39 @@ def test_2d_n1024_16rhs_vs_oracle():
 
 def test_3d_n32_8rhs_vs_oracle():
     _end_to_end("c4s", "c4s_oracle.json")
+
+
+def _laplace_end_to_end(key, golden):
+    """Section 5's Laplace equation with a potential at 3D n=48: (I + K V) u =
+    K f solved on the GPU against the oracle's stored solution."""
+    g = _load(golden)
+    w = synth.workload(key)
+    n, V, f = w["n"], w["V"], w["f"]
+    assert (n, 3) == (g["n"], g["d"]) and g["omega"] == 0.0
+    lsp, torch = _lsp()
+    idx = np.arange(g["sample_start"], n ** 3, g["sample_stride"])
+    for prec in ("fp64", "mixed"):
+        plan = lsp.Plan(n, 3, max_nrhs=f.shape[0], equation="laplace", precision=prec, buffer_b=g["b"],
+                        restart=g["restart"], tol=g["tol"])
+        pb = lsp.Problem(plan, 0.0, V)
+        pb.factor()
+        u, info, st = pb.solve(f, kind="source")
+        assert st == 0, info
+        u = u.cpu().numpy()
+        print(f"{key} {prec}: iters {[i['iters'] for i in info]} oracle {[r['iters'] for r in g['rhs']]}", flush=True)
+        for r, ref in enumerate(g["rhs"]):
+            rs = _cplx(ref["u_sample"])
+            err = np.linalg.norm(u[r, idx] - rs) / np.linalg.norm(rs)
+            nerr = abs(np.linalg.norm(u[r]) - ref["u_norm"]) / ref["u_norm"]
+            assert info[r]["converged"] and info[r]["relres_true"] <= 1e-8, (prec, r, info[r])
+            if prec == "fp64":
+                assert err <= 1e-8 and nerr <= 1e-8, (r, err, nerr)
+                assert abs(info[r]["iters"] - ref["iters"]) <= 1, (r, info[r]["iters"], ref["iters"])
+            else:
+                assert err <= 1e-6 and nerr <= 1e-6, (r, err, nerr)
+        del pb
+        torch.cuda.empty_cache()
+
+
+def test_3d_n48_laplace_gauss_vs_oracle():
+    _laplace_end_to_end("l2", "l2_oracle.json")
