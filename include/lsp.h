@@ -194,6 +194,12 @@ typedef struct {
   double mchain_entries;      /* factor entries one sweep of them reads
                                  (inverse diagonal blocks and the panels'
                                  entries below or right of them) */
+  double pair_update_flops;   /* of update_flops, the two-panel products
+                                 over [k0 + kb, m)^2 (kb the two panels'
+                                 columns) on the levels of large fronts */
+  double cross_update_flops;  /* of update_flops, the first panel's update
+                                 of the second panel's column and row
+                                 strips on those levels */
 } lsp_plan_stats;
 
 typedef struct lsp_plan lsp_plan;        /* opaque; host-side, plus one device copy of

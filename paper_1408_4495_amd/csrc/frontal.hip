@@ -2034,7 +2034,7 @@ void diag_launch(const MfDev<T>& mf, int cnt, int first, int k0, hipStream_t st)
 template <typename T, int TM>
 void pair_launch(const MfDev<T>& mf, int rem, int cnt, int first, int k0, hipStream_t st) {
   const int gt = (rem + TM - 1) / TM;
-  LSP_LAUNCH("gemm_update", (int)sizeof(cplx<T>), (pair_update_kernel<T, TM>), dim3(gt, gt, cnt), dim3(256), 0, st,
+  LSP_LAUNCH("pair_update", (int)sizeof(cplx<T>), (pair_update_kernel<T, TM>), dim3(gt, gt, cnt), dim3(256), 0, st,
              mf.F, mf.fronts, first, k0);
 }
 
@@ -2111,7 +2111,7 @@ void mf_factor_levels(const MfDev<T>& mf, const Plan& plan, hipStream_t st, cons
         LSP_LAUNCH("panel_trsm", (int)sizeof(cplx<T>), panel_trsm_kernel<T>, dim3((rem + 63) / 64, cnt, 2), dim3(256),
                    0, st, mf.F, mf.Dinv, mf.fronts, mf.perm, first, k0);
         if (k0 + NB < maxp) {  // some front has a panel b
-          LSP_LAUNCH("gemm_update", (int)sizeof(cplx<T>), cross_update_kernel<T>,
+          LSP_LAUNCH("cross_update", (int)sizeof(cplx<T>), cross_update_kernel<T>,
                      dim3((maxm - k0 - NB + 31) / 32, 2, cnt), dim3(256), 0, st, mf.F, mf.fronts, first, k0);
           diag_launch(mf, cnt, first, k0 + NB, st);
           const int rem2 = maxm - k0 - NB - 1;
@@ -2168,6 +2168,23 @@ FactorSchedule factor_schedule(const Plan& plan, bool fp64) {
           s.trsm_flops += 8.0 * 2.0 * (double)kb * kb * (double)(f.p + f.q - k0 - kb);
         }
       }
+    if (pair_level(plan, l, fp64)) {
+      // rank-kb products over [k0 + kb, m)^2 (kb = both panels' columns),
+      // and panel a's rank-32 update of panel b's column and row strips
+      for (int i = plan.level_ptr[l]; i < plan.level_ptr[l + 1]; ++i) {
+        const FrontDev& f = plan.fronts[i];
+        const double m = (double)(f.p + f.q);
+        for (int k0 = 0; k0 < f.p; k0 += 2 * NB) {
+          const int kb = std::min(2 * NB, f.p - k0);
+          s.pair_update_flops += 8.0 * (m - k0 - kb) * (m - k0 - kb) * kb;
+          if (f.p > k0 + NB) {
+            const int kbb = std::min(NB, f.p - k0 - NB);
+            s.cross_update_flops += 8.0 * NB * kbb * (2.0 * (m - k0 - NB) - kbb);
+          }
+        }
+      }
+      continue;
+    }
     for (int k0 = 0; k0 < plan.level_maxp[l]; k0 += NB) {
       // update launches other than gemm_update: the panel steps of a strip
       // level (all but the last panel) and the lookahead launches

@@ -110,6 +110,8 @@ struct FactorSchedule {
   double fused_blocks = 0.0;
   double fused_update_flops = 0.0;
   double trsm_flops = 0.0;  // real flops of the panel_trsm launches
+  double pair_update_flops = 0.0;   // real flops of the two-panel updates (pair_update)
+  double cross_update_flops = 0.0;  // real flops of panel a's update of panel b's strips (cross_update)
 };
 FactorSchedule factor_schedule(const Plan& plan, bool fp64);
 // Forward and backward sweeps; form_done (may be null): an event the first

@@ -844,6 +844,8 @@ lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* s) {
   s->assemble_entries = P.assemble_entries;
   s->mchain_levels = P.mchain_levels;
   s->mchain_entries = P.mchain_entries;
+  s->pair_update_flops = fs.pair_update_flops;
+  s->cross_update_flops = fs.cross_update_flops;
   return LSP_OK;
 }
 

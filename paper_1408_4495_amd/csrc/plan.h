@@ -58,12 +58,12 @@ struct Plan {
   // Levels swept by the small-front kernels (not dense; at most two panels,
   // at most 160 rows, at most 128 rows below each front's first panel).
   std::vector<char> level_small_sweep;
-  // Small-front levels with formed operators (like level_dense, one product
-  // per front): more than 16 fronts of at most 64 pivots and 256 rows, in
-  // plans for blocks of right-hand sides (max_nrhs >= 4) unless
-  // dense_sweeps = 2; their operators follow the dense levels' in the same
-  // store (g_off).
-  std::vector<char> level_mchain;  // small-front levels swept by matrix-core panel chains
+  // Small-front levels swept by panel chains on the matrix cores (16
+  // right-hand sides per wave, straight from the factor; nothing formed):
+  // more than 16 fronts of at most 64 pivots and 256 rows, in plans for
+  // blocks of right-hand sides (max_nrhs >= 4), or always with
+  // dense_sweeps = 2.
+  std::vector<char> level_mchain;
   int mchain_levels = 0;
   double mchain_entries = 0.0;     // factor entries one sweep of them reads
   // Levels swept by the blocked kernels (sweep.hip): not dense, not small,

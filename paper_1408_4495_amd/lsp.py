@@ -52,7 +52,8 @@ class PlanStats(ctypes.Structure):
                 ("blocked_levels", ctypes.c_int), ("blocked_entries", ctypes.c_double),
                 ("chain_entries", ctypes.c_double), ("blocked_panel_entries", ctypes.c_double),
                 ("trsm_flops", ctypes.c_double), ("assemble_entries", ctypes.c_double),
-                ("mchain_levels", ctypes.c_int), ("mchain_entries", ctypes.c_double)]
+                ("mchain_levels", ctypes.c_int), ("mchain_entries", ctypes.c_double),
+                ("pair_update_flops", ctypes.c_double), ("cross_update_flops", ctypes.c_double)]
 
 
 class LspError(RuntimeError):

@@ -21,7 +21,8 @@ import sys
 
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 SOURCE = {"fwd": "frontal.hip", "bwd": "frontal.hip", "diag_lu": "frontal.hip", "panel_trsm": "frontal.hip",
-          "gemm_update": "frontal.hip", "update_lu": "frontal.hip", "assemble_front": "frontal.hip",
+          "gemm_update": "frontal.hip", "update_lu": "frontal.hip", "pair_update": "frontal.hip",
+          "cross_update": "frontal.hip", "assemble_front": "frontal.hip",
           "strip_first": "frontal.hip", "panel_step": "frontal.hip", "form_fwd": "frontal.hip",
           "form_bwd": "frontal.hip", "bsweep": "sweep.hip", "mchain": "sweep.hip",
           "fwd_mchain": "sweep.hip", "bwd_mchain": "sweep.hip",
@@ -79,6 +80,21 @@ def stats(path, title, cmd):
         t = float(r["TotalDurationNs"])
         out.append(f"| `{short(r['Name'])}` | {r['Calls']} | {t / 1e6:.3f} | {float(r['AverageNs']) / 1e3:.2f} | "
                    f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {100 * t / tot:.1f}% |")
+    # the same launches grouped under the library's timing names (template
+    # instances of one kernel together), whose averages bench.py's live
+    # timing reports
+    agg = {}
+    for r in rows:
+        key, _ = registry_key(r["Name"])
+        if key is None:
+            continue
+        a = agg.setdefault(key, [0, 0.0])
+        a[0] += int(r["Calls"])
+        a[1] += float(r["TotalDurationNs"])
+    out += ["", "Grouped by the library's timing names (all template instances of a kernel):", "",
+            "| timing name | calls | total ms | avg us |", "|---|---|---|---|"]
+    for key, (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:25]:
+        out.append(f"| `{key}` | {c} | {t / 1e6:.3f} | {t / c / 1e3:.2f} |")
     return "\n".join(out) + "\n"
 
 

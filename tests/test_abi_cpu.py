@@ -176,6 +176,22 @@ def test_lookahead_schedule_stats(lib):
     assert q["fused_blocks"] == 2 and q["fused_update_flops"] == q["update_flops"]
 
 
+def test_pair_update_stats(lib):
+    """Levels of fronts with at least 512 rows (not panel-strip levels) run
+    the two-panel schedule: its products (pair_update, cross_update) are a
+    part of update_flops disjoint from the lookahead launches'; the cross
+    products (rank 32 over two 32-wide strips) are far smaller than the
+    pair products on large fronts; plans without such fronts have none."""
+    for n, d, prec in ((1024, 2, "mixed"), (1024, 2, "fp64"), (32, 3, "fp64"), (64, 3, "mixed")):
+        s = L.Plan(n, d, precision=prec).stats()
+        assert s["pair_update_flops"] > 0 and s["cross_update_flops"] > 0, (n, d, prec)
+        assert s["cross_update_flops"] < 0.2 * s["pair_update_flops"], (n, d, prec)
+        assert (s["pair_update_flops"] + s["cross_update_flops"] + s["fused_update_flops"]
+                <= s["update_flops"] * (1 + 1e-12)), (n, d, prec)
+    s = L.Plan(64, 2).stats()  # largest front 96 rows
+    assert s["max_front"] < 512 and s["pair_update_flops"] == s["cross_update_flops"] == 0
+
+
 def test_tile_cache_round_trip(lib, tmp_path):
     """A tile table written with lsp_plan_save_tiles is picked up by plans of
     the same (n, d, precision) created with tile_cache; other keys keep their
