@@ -86,6 +86,36 @@ def delta_source(n, d, points):
     return f
 
 
+def cavity_rho(n, d, kind="l2", radius=0.45, centre=None):
+    """Scaled distance |x - c|_p / radius of every grid point (p = 2 for the
+    disk / ball, p = 1 for the diamond / octahedron)."""
+    X = grid_coords(n, d)
+    c = np.full(d, 0.5) if centre is None else np.asarray(centre, dtype=np.float64)
+    Y = X - c
+    dist = np.sqrt(np.sum(Y * Y, axis=1)) if kind == "l2" else np.sum(np.abs(Y), axis=1)
+    return dist / radius
+
+
+def domain_mask(n, d, kind="l2", radius=0.45, centre=None):
+    """The support Omega of a cavity medium: grid points with rho <= 1."""
+    return cavity_rho(n, d, kind, radius, centre) <= 1.0
+
+
+def medium_cavity(n, d, kind="l2", depth=-0.5, radius=0.45, core=0.6, centre=None):
+    """Smoothed cavity of an l2 or l1 ball: m = depth for rho <= core, a
+    raised-cosine ramp to 0 at rho = 1, and 0 outside (support = the mask)."""
+    rho = cavity_rho(n, d, kind, radius, centre)
+    ramp = 0.5 * (1.0 + np.cos(np.pi * np.clip((rho - core) / (1.0 - core), 0.0, 1.0)))
+    return depth * np.where(rho <= 1.0, ramp, 0.0)
+
+
+def sketch_matrix(n, d, r, seed):
+    """The r x n^d standard Gaussian matrix R of a general-domain set-up,
+    rows = sketch columns (Section 4 draws it at random; seeded here)."""
+    rng = np.random.default_rng([SEED_BASE, 2000 + int(seed)])
+    return rng.standard_normal((r, n ** d))
+
+
 def directions_2d(count, offset=0.0):
     """Unit vectors at angles offset + 2 pi j / count."""
     th = offset + 2.0 * np.pi * np.arange(count) / count
@@ -190,10 +220,25 @@ def _laplace(n, kind):
     return dict(name=f"3d_n{n}_laplace_{kind}", n=n, d=3, omega=0.0, m=None, V=V, f=f, laplace=True)
 
 
+# Section 4's tests: smoothed cavities of an l2 ball and of an l1 ball
+# (radius 0.45 around the centre, m = -0.5 in the core), a plane wave
+# pointing down, 8 points per wavelength; the sketch has r = 2 * 3^d columns.
+def _general(n, d, kind, seed):
+    omega = 2 * np.pi * n / 8.0
+    down = [0.0] * (d - 1) + [-1.0]
+    r = 2 * 3 ** d
+    return dict(name=f"{d}d_n{n}_{kind}_cavity", n=n, d=d, omega=omega, m=medium_cavity(n, d, kind),
+                mask=domain_mask(n, d, kind), R=sketch_matrix(n, d, r, seed),
+                uI=plane_waves(n, d, omega, [down]), general=True)
+
+
 WORKLOADS = {"c1": _c1, "c2": _c2, "c3": _c3, "c4": _c4, "c4s": _c4s,
              "l1": lambda: _laplace(24, "gauss"), "l2": lambda: _laplace(48, "gauss"),
              "l3": lambda: _laplace(96, "gauss"), "l1b": lambda: _laplace(24, "ball"),
-             "l2b": lambda: _laplace(48, "ball")}
+             "l2b": lambda: _laplace(48, "ball"),
+             "g1": lambda: _general(32, 2, "l2", 1), "g1d": lambda: _general(32, 2, "l1", 2),
+             "g2": lambda: _general(256, 2, "l2", 3), "g2d": lambda: _general(256, 2, "l1", 4),
+             "g3": lambda: _general(32, 3, "l2", 5)}
 
 
 def workload(key):
