@@ -200,6 +200,11 @@ typedef struct {
   double cross_update_flops;  /* of update_flops, the first panel's update
                                  of the second panel's column and row
                                  strips on those levels */
+  int domain_points;          /* grid points of the domain: N, or |Omega| of a
+                                 general-domain plan */
+  int boundary_points;        /* general domains: points of Omega with a
+                                 neighbour outside Omega (or the grid) */
+  int sketch_cols;            /* general domains: columns r of the sketch */
 } lsp_plan_stats;
 
 typedef struct lsp_plan lsp_plan;        /* opaque; host-side, plus one device copy of
@@ -223,6 +228,22 @@ lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts,
                            lsp_plan** plan);
 void lsp_plan_destroy(lsp_plan* plan);
 lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* stats);
+
+/* General domains (Section 4: the support Omega of m is not a rectangle).
+ * mask: host array of n^d bytes, nonzero at the grid points of Omega (the
+ * unknowns of the problem; m must vanish outside Omega), read during this
+ * call only.  sketch_cols: columns r of the Gaussian sketch R (0 = 2 * 3^d,
+ * a constant multiple of the stencil size as the section asks).  Points of
+ * Omega whose whole 3^d block lies in Omega take the rectangle's interior
+ * rows (Section 3.1); the others ("boundary points") take their own row
+ * B(i, mu(i)), mu(i) = the 3^d block intersected with Omega, from the
+ * sketch (lsp_setup_general).  The dissection is that of the n^d grid;
+ * points outside Omega stay in it as identity rows of M and Q, decoupled
+ * from Omega.  Helmholtz only (LSP_ERR_ARG for Laplace options, an empty
+ * mask, a null mask, r outside [1, 4096]). */
+lsp_status lsp_plan_create_general(int n, int d, int max_nrhs, const lsp_options* opts,
+                                   const unsigned char* mask, int sketch_cols,
+                                   lsp_plan** plan);
 
 /* Trailing-update tile shape (32, 64 or 128: square MFMA tile of the
  * F22 -= L21 U12 products) per elimination-tree level, leaves first.  The
@@ -267,6 +288,29 @@ lsp_status lsp_plan_bytes(const lsp_plan* plan, int precision, int nrhs,
 lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev,
                      void* ws_dev, size_t ws_bytes, void* stream,
                      lsp_problem** problem);
+/* lsp_setup for a plan of lsp_plan_create_general (Section 4).  R_dev: the
+ * sketch, [r][N] real double on the device (row c = column c of the
+ * section's N x r Gaussian matrix R; entries outside Omega are not used),
+ * read during this call only.  Besides lsp_setup's steps it forms
+ * T = (K w^2 m) R over Omega's columns (r K products on the GPU) and, per
+ * boundary point i, alpha = the conjugate of the least left singular vector
+ * of T(mu(i), :) (unit norm, centre entry real positive), which becomes
+ * row i of Q and of M.  On such a problem every operator application
+ * (lsp_apply_op, lsp_apply_K, lsp_solve) returns its output restricted to
+ * Omega (zero outside), the iterates live on Omega, and an LSP_RHS_G
+ * right-hand side must vanish outside Omega.  Errors as lsp_setup; also
+ * LSP_ERR_ARG when the plan and the call do not match. */
+lsp_status lsp_setup_general(const lsp_plan* plan, double omega, const double* m_dev,
+                             const double* R_dev, void* ws_dev, size_t ws_bytes,
+                             void* stream, lsp_problem** problem);
+/* A general-domain problem's boundary rows (synchronises the stream):
+ * points [nbnd] (int, linear grid indices, increasing), alpha [nbnd][27]
+ * complex128 (slot q = sum_a (s_a+1) 3^a, zero for slots outside Omega),
+ * sigma [nbnd][27] (singular values of T(mu(i), :), descending, zero-
+ * padded); nbnd = lsp_plan_stats.boundary_points; host pointers, any may
+ * be NULL.  LSP_ERR_ARG on a rectangle problem. */
+lsp_status lsp_get_boundary_stencils(lsp_problem* problem, int* points_host, double* alpha_host,
+                                     double* sigma_host);
 void lsp_problem_destroy(lsp_problem* problem);
 
 /* Numeric multifrontal LU of M (Section 2.2, nested dissection and the
@@ -351,6 +395,31 @@ lsp_status lsp_get_kernel_table(lsp_problem* problem, void* k_dev);
 lsp_status lsp_get_stencils(lsp_problem* problem, double* alpha_host, double* sigma_host,
                             double* C_host);
 lsp_status lsp_get_matrix(lsp_problem* problem, void* mval_dev);
+
+/* The scattered field away from the grid (Section 1: once u is known on
+ * Omega, u(x) = - int G(x - y) w^2 m(y) (u(y) + u_I(y)) dy everywhere, which
+ * meets the radiation condition), by the grid quadrature of Section 2.1:
+ *   lsp_exterior_field: u(x_p) = - sum_j h^d G(x_p - x_j) w^2 m_j
+ *       (u_j + u_I,j) at points_dev [npts][d] (the cell-centred grid
+ *       x_j = (j + 1/2) h; a point equal to a grid point takes k_0 there,
+ *       so at the grid points it returns the solution itself);
+ *   lsp_far_field: the far-field pattern A(xhat_p) = - c_d sum_j h^d
+ *       e^{-i w xhat_p . x_j} w^2 m_j (u_j + u_I,j) for unit directions
+ *       dirs_dev [ndirs][d], with u(x) = A(xhat) e^{i w |x|} |x|^{-(d-1)/2}
+ *       + O(|x|^{-(d+1)/2}), c_2 = e^{i pi/4} / sqrt(8 pi w), c_3 = 1/(4 pi).
+ * u_dev, uI_dev: [nrhs][N] complex128 (the solution of lsp_solve and the
+ * incident field); out_dev: [nrhs][npts] complex128; all device pointers.
+ * ws_dev: device workspace of lsp_field_bytes(plan, npts) bytes.  Helmholtz
+ * problems only; a general-domain problem's u vanishes outside Omega and is
+ * used as is.  Only enqueues device work.  Errors: LSP_ERR_ARG (null
+ * pointers, counts < 1, Laplace problems, small workspace), LSP_ERR_HIP. */
+lsp_status lsp_field_bytes(const lsp_plan* plan, int npts, size_t* bytes);
+lsp_status lsp_exterior_field(lsp_problem* problem, int nrhs, const void* u_dev, const void* uI_dev,
+                              int npts, const double* points_dev, void* out_dev, void* ws_dev,
+                              size_t ws_bytes);
+lsp_status lsp_far_field(lsp_problem* problem, int nrhs, const void* u_dev, const void* uI_dev,
+                         int ndirs, const double* dirs_dev, void* out_dev, void* ws_dev,
+                         size_t ws_bytes);
 
 /* ---- kernel timing (profiling aid) ----
  * When enabled, every kernel launch of the library is bracketed by two HIP

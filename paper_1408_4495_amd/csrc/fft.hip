@@ -270,7 +270,8 @@ struct HalfArgs {
 //   FWD_WORK   n values of the work line -> L values of the same line
 //   CONV       n values -> n values in place, spectrum row of line c
 //   INV_WORK   L values of the work line -> its first n values
-//   INV_FIELD  work row c (L values) -> field row c (plus x when given)
+//   INV_FIELD  work row c (L values) -> field row c (plus x when given;
+//              zero where the output mask, passed in place of w2m, is 0)
 // Workgroups: LPW lines of one (o, rhs), line = tid / P, t = tid % P.  The
 // GS blocks whose lines share cache lines, then the right-hand sides of a
 // line block (sharing spectrum rows), are consecutive in dispatch order
@@ -459,6 +460,7 @@ __global__ void __launch_bounds__(kHalfThreads) half_lines_kernel(cplx<T>* __res
         const int e = t + m * P;
         double2 r = widen(cadd(yo[m], cmulc(we[m], v[m])));
         if (xr) { const double2 xv = xr[fb + e]; r.x += xv.x; r.y += xv.y; }
+        if (w2m && w2m[fb + e] == 0.0) r = make_double2(0, 0);  // output mask
         yr[fb + e] = r;
       }
     }
@@ -516,13 +518,13 @@ void launch_half(const FftPlanDev<T>& fp, cplx<T>* W, const double2* x, double2*
 
 template <typename T, int EPT>
 void kmatvec_impl(const FftPlanDev<T>& fp, int nrhs, const double2* x, double2* y, const double* w2m,
-                  bool add_x, cplx<T>* W, hipStream_t st) {
+                  bool add_x, cplx<T>* W, const double* omask, hipStream_t st) {
   const int n = fp.n, L = fp.L;
   const long long LL = (long long)L * L;
   if (fp.d == 2) {
     launch_half<T, EPT, HK_FWD_FIELD>(fp, W, x, y, w2m, n, 1, 0, 0, 1, nrhs, st);
     launch_half<T, EPT, HK_CONV>(fp, W, x, y, w2m, L, 1, 1, 0, L, nrhs, st);
-    launch_half<T, EPT, HK_INV_FIELD>(fp, W, add_x ? x : nullptr, y, w2m, n, 1, 0, 0, 1, nrhs, st);
+    launch_half<T, EPT, HK_INV_FIELD>(fp, W, add_x ? x : nullptr, y, omask, n, 1, 0, 0, 1, nrhs, st);
   } else {
     launch_half<T, EPT, HK_FWD_FIELD>(fp, W, x, y, w2m, n * n, 1, 0, 0, 1, nrhs, st);
     // along i2: lines (c1, i3 < n), elements at stride L
@@ -530,7 +532,7 @@ void kmatvec_impl(const FftPlanDev<T>& fp, int nrhs, const double2* x, double2* 
     // along i3: lines c1 + L c2, elements at stride L^2
     launch_half<T, EPT, HK_CONV>(fp, W, x, y, w2m, (int)LL, 1, 1, 0, LL, nrhs, st);
     launch_half<T, EPT, HK_INV_WORK>(fp, W, x, y, w2m, L, n, 1, LL, L, nrhs, st);
-    launch_half<T, EPT, HK_INV_FIELD>(fp, W, add_x ? x : nullptr, y, w2m, n * n, 1, 0, 0, 1, nrhs, st);
+    launch_half<T, EPT, HK_INV_FIELD>(fp, W, add_x ? x : nullptr, y, omask, n * n, 1, 0, 0, 1, nrhs, st);
   }
 }
 
@@ -647,13 +649,13 @@ void full_fft_impl(const FftPlanDev<T>& fp, cplx<T>* W, hipStream_t st) {
 
 template <typename T>
 void kmatvec(const FftPlanDev<T>& fp, int nrhs, const double2* x, double2* y, const double* w2m, bool add_x,
-             cplx<T>* W, hipStream_t st) {
+             cplx<T>* W, hipStream_t st, const double* omask) {
   switch (fp.hept) {
-    case 12: kmatvec_impl<T, 12>(fp, nrhs, x, y, w2m, add_x, W, st); break;
-    case 8: kmatvec_impl<T, 8>(fp, nrhs, x, y, w2m, add_x, W, st); break;
-    case 6: kmatvec_impl<T, 6>(fp, nrhs, x, y, w2m, add_x, W, st); break;
-    case 4: kmatvec_impl<T, 4>(fp, nrhs, x, y, w2m, add_x, W, st); break;
-    case 3: kmatvec_impl<T, 3>(fp, nrhs, x, y, w2m, add_x, W, st); break;
+    case 12: kmatvec_impl<T, 12>(fp, nrhs, x, y, w2m, add_x, W, omask, st); break;
+    case 8: kmatvec_impl<T, 8>(fp, nrhs, x, y, w2m, add_x, W, omask, st); break;
+    case 6: kmatvec_impl<T, 6>(fp, nrhs, x, y, w2m, add_x, W, omask, st); break;
+    case 4: kmatvec_impl<T, 4>(fp, nrhs, x, y, w2m, add_x, W, omask, st); break;
+    case 3: kmatvec_impl<T, 3>(fp, nrhs, x, y, w2m, add_x, W, omask, st); break;
     default: throw Error(LSP_ERR_ARG, "unsupported FFT length");
   }
 }
@@ -667,9 +669,9 @@ void full_fft_forward(const FftPlanDev<T>& fp, cplx<T>* W, hipStream_t st) {
 }
 
 template void kmatvec<double>(const FftPlanDev<double>&, int, const double2*, double2*, const double*, bool,
-                              double2*, hipStream_t);
+                              double2*, hipStream_t, const double*);
 template void kmatvec<float>(const FftPlanDev<float>&, int, const double2*, double2*, const double*, bool,
-                             float2*, hipStream_t);
+                             float2*, hipStream_t, const double*);
 template void full_fft_forward<double>(const FftPlanDev<double>&, double2*, hipStream_t);
 
 }  // namespace lsp

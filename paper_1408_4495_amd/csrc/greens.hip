@@ -140,7 +140,150 @@ __global__ void split_spectrum_kernel(double2* __restrict__ s64, float2* __restr
   s32[id] = to_c64(v);
 }
 
+// ---- the scattered field away from the grid (Section 1)
+//
+// Section 1 represents the scattered field everywhere through its values on
+// Omega; with the grid quadrature of Section 2.1:
+//   MODE 0 (points x):      u(x) = - sum_j h^d G(x - x_j) w2m_j (u_j + uI_j)
+//                           (k_0 for a grid point j at x itself);
+//   MODE 1 (directions xh): A(xh) = - c_d sum_j h^d e^{-i w xh.x_j} w2m_j (u_j + uI_j),
+//                           the far-field pattern, u(x) = A e^{i w |x|} |x|^{-(d-1)/2} + ...,
+//                           c_2 = e^{i pi/4} / sqrt(8 pi w), c_3 = 1 / (4 pi).
+// Work split: a workgroup takes a tile of FT evaluation points (one per
+// lane) and a chunk of FC grid points, its four waves every fourth grid
+// point of the chunk (the same one across a wave, so grid points with
+// w2m = 0 are skipped without divergence); the source density of FS grid
+// points for up to FR right-hand sides is staged in LDS; the waves' sums are
+// added in wave order and stored per chunk; field_reduce adds the chunks in
+// order (the result does not depend on the right-hand sides' grouping).
+constexpr int FT = 64, FS = 64, FR = 16, FC = 2048;
+
+template <int MODE>
+__global__ void __launch_bounds__(256) field_partial_kernel(const double2* __restrict__ u,
+                                                            const double2* __restrict__ uI,
+                                                            const double* __restrict__ w2m,
+                                                            const double* __restrict__ pts, int npts, int nrhs,
+                                                            long long N, int n, int d, double omega, double2 k0,
+                                                            double2* __restrict__ partial) {
+  __shared__ double2 q[FS * FR];
+  __shared__ double wv[FS];
+  __shared__ double yc[FS][3];
+  __shared__ double2 red[FT * FR];
+  const int tile = blockIdx.x, chunk = blockIdx.y;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int p = tile * FT + lane;
+  const bool live = p < npts;
+  const double h = 1.0 / n, hd = d == 2 ? h * h : h * h * h;
+  double x[3] = {0.0, 0.0, 0.0};
+  if (live)
+    for (int a = 0; a < d; ++a) x[a] = pts[(long long)p * d + a];
+  double2 acc[FR];
+#pragma unroll
+  for (int k = 0; k < FR; ++k) acc[k] = make_double2(0, 0);
+  const long long j0 = (long long)chunk * FC, j1 = min(N, j0 + FC);
+  for (long long s0 = j0; s0 < j1; s0 += FS) {
+    const int cnt = (int)min((long long)FS, j1 - s0);
+    __syncthreads();  // the previous step's reads of q are done
+    for (int e = tid; e < cnt * nrhs; e += 256) {
+      const int c = e % cnt, k = e / cnt;
+      const long long j = s0 + c;
+      const double wj = w2m[j] * hd;
+      const double2 a = u[(long long)k * N + j], b = uI[(long long)k * N + j];
+      q[c * FR + k] = make_double2(wj * (a.x + b.x), wj * (a.y + b.y));
+    }
+    for (int c = tid; c < cnt; c += 256) {
+      // x_j = (i + 1/2) / n per axis (the same rounding as (i + 0.5) / n on the host)
+      const long long j = s0 + c;
+      wv[c] = w2m[j];
+      yc[c][0] = ((double)(j % n) + 0.5) / n;
+      yc[c][1] = ((double)((j / n) % n) + 0.5) / n;
+      yc[c][2] = d == 3 ? ((double)(j / ((long long)n * n)) + 0.5) / n : 0.0;
+    }
+    __syncthreads();
+    for (int c = wave; c < cnt; c += 4) {
+      if (wv[c] == 0.0) continue;
+      const double y0 = yc[c][0], y1 = yc[c][1], y2 = yc[c][2];
+      double2 g;
+      if (MODE == 0) {
+        const double e0 = x[0] - y0, e1 = x[1] - y1, e2 = x[2] - y2;
+        const double r = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+        if (r == 0.0) {
+          g = make_double2(k0.x / hd, k0.y / hd);
+        } else if (d == 2) {
+          const double2 H = hankel1_0(omega * r);
+          g = make_double2(-0.25 * H.y, 0.25 * H.x);  // (i/4) (J0 + i Y0)
+        } else {
+          double sn, cs;
+          sincos(omega * r, &sn, &cs);
+          const double s = 1.0 / (4.0 * kPi * r);
+          g = make_double2(cs * s, sn * s);
+        }
+      } else {
+        double sn, cs;
+        sincos(-omega * (x[0] * y0 + x[1] * y1 + x[2] * y2), &sn, &cs);
+        g = make_double2(cs, sn);
+      }
+#pragma unroll
+      for (int k = 0; k < FR; ++k)
+        if (k < nrhs) acc[k] = cadd(acc[k], cmul(g, q[c * FR + k]));
+    }
+  }
+  for (int w = 0; w < 4; ++w) {
+    __syncthreads();
+    if (wave == w) {
+#pragma unroll
+      for (int k = 0; k < FR; ++k) red[lane * FR + k] = w == 0 ? acc[k] : cadd(red[lane * FR + k], acc[k]);
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < FT * nrhs; e += 256) {
+    const int l = e % FT, k = e / FT, pp = tile * FT + l;
+    if (pp < npts) partial[((long long)chunk * nrhs + k) * npts + pp] = red[l * FR + k];
+  }
+}
+
+__global__ void field_reduce_kernel(const double2* __restrict__ partial, int nchunk, int nrhs, int npts, double2 scale,
+                                    double2* __restrict__ out) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long long)nrhs * npts) return;
+  const int k = (int)(id / npts), p = (int)(id % npts);
+  double2 s = make_double2(0, 0);
+  for (int c = 0; c < nchunk; ++c) s = cadd(s, partial[((long long)c * nrhs + k) * npts + p]);
+  out[id] = cmul(scale, s);
+}
+
 }  // namespace
+
+long long field_chunks(long long N) { return (N + FC - 1) / FC; }
+
+void field_eval(int mode, const double2* u, const double2* uI, const double* w2m, const double* pts, int npts,
+                int nrhs, int n, int d, double omega, double2 k0, double2* partial, double2* out, hipStream_t st) {
+  long long N = 1;
+  for (int a = 0; a < d; ++a) N *= n;
+  const int nchunk = (int)field_chunks(N);
+  double2 scale = make_double2(-1.0, 0.0);
+  if (mode == 1) {
+    if (d == 2) {
+      const double a = 1.0 / sqrt(8.0 * kPi * omega), c = 0.70710678118654752440;
+      scale = make_double2(-a * c, -a * c);  // -e^{i pi/4} / sqrt(8 pi w)
+    } else {
+      scale = make_double2(-1.0 / (4.0 * kPi), 0.0);
+    }
+  }
+  for (int r0 = 0; r0 < nrhs; r0 += FR) {
+    const int nr = nrhs - r0 < FR ? nrhs - r0 : FR;
+    const dim3 grid((unsigned)((npts + FT - 1) / FT), (unsigned)nchunk);
+    if (mode == 0)
+      LSP_LAUNCH("field_points", 0, field_partial_kernel<0>, grid, dim3(256), 0, st, u + (long long)r0 * N,
+                 uI + (long long)r0 * N, w2m, pts, npts, nr, N, n, d, omega, k0, partial);
+    else
+      LSP_LAUNCH("field_far", 0, field_partial_kernel<1>, grid, dim3(256), 0, st, u + (long long)r0 * N,
+                 uI + (long long)r0 * N, w2m, pts, npts, nr, N, n, d, omega, k0, partial);
+    const long long tot = (long long)nr * npts;
+    LSP_LAUNCH("field_reduce", 0, field_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, partial,
+               nchunk, nr, npts, scale, out + (long long)r0 * npts);
+  }
+}
 
 void launch_ktable(double2* k, int n, int d, double omega, double2 k0, hipStream_t st) {
   long long total = 1;

@@ -15,6 +15,14 @@ void launch_ktable(double2* k, int n, int d, double omega, double2 k0, hipStream
 void launch_embed(double2* E, const double2* k, int n, int d, hipStream_t st);
 void launch_split_spectrum(double2* s64, float2* s32, const double2* E, int n, int d, hipStream_t st);
 
+// Scattered field away from the grid (mode 0: at points [npts][d]) or its
+// far-field pattern (mode 1: unit directions [npts][d]) from u and u_I
+// ([nrhs][N] complex128) and w2m; partial: field_chunks(N) * min(nrhs, 16)
+// * npts complex128; out [nrhs][npts].
+long long field_chunks(long long N);
+void field_eval(int mode, const double2* u, const double2* uI, const double* w2m, const double* pts, int npts,
+                int nrhs, int n, int d, double omega, double2 k0, double2* partial, double2* out, hipStream_t st);
+
 // ---- FFT
 struct FftRadices {
   int r[16];
@@ -34,10 +42,11 @@ struct FftPlanDev {
 };
 
 // y = [x +] K (w2m .* x), fields complex128 [nrhs][N]; w2m == nullptr means
-// no scaling; W is the [nrhs][L^d] work array in precision T.
+// no scaling; W is the [nrhs][L^d] work array in precision T; omask (may be
+// null): y is set to zero where omask is 0 (a general domain's exterior).
 template <typename T>
 void kmatvec(const FftPlanDev<T>& fp, int nrhs, const double2* x, double2* y, const double* w2m, bool add_x,
-             cplx<T>* W, hipStream_t st);
+             cplx<T>* W, hipStream_t st, const double* omask = nullptr);
 // In-place forward transform of a full L^d array (one right-hand side).
 template <typename T>
 void full_fft_forward(const FftPlanDev<T>& fp, cplx<T>* W, hipStream_t st);
@@ -59,6 +68,17 @@ void launch_assemble(double2* Mval, const double2* alpha_pad, const double2* C_p
 template <typename Cx>
 void launch_applyQ(Cx* y, const double2* x, const double2* alpha_pad, int n, int d, long long N, int nrhs,
                    hipStream_t st);
+
+// general domains (Section 4); ptab / bpts / bslots as in Plan
+void launch_domain_mask(double* dmask, const int* ptab, long long N, hipStream_t st);
+void launch_sketch_widen(double2* T, const double* R, const int* ptab, long long N, hipStream_t st);
+void launch_bnd_stencils(const double2* T, int r, long long N, const int* bpts, const unsigned* bslots, int nbnd,
+                         int n, int d, double2* balpha, double* bsigma, hipStream_t st);
+void launch_assemble_general(double2* Mval, const double2* alpha_pad, const double2* C_pad, const double* w2m,
+                             const int* ptab, const double2* balpha, int n, int d, long long N, hipStream_t st);
+template <typename Cx>
+void launch_applyQ_general(Cx* y, const double2* x, const double2* alpha_pad, const int* ptab, const double2* balpha,
+                           int n, int d, long long N, int nrhs, hipStream_t st);
 
 // ---- multifrontal
 template <typename T>

@@ -39,6 +39,9 @@ struct PlanDev {
   ClassGeom* geo = nullptr;
   double2* tw64 = nullptr;
   float2* tw32 = nullptr;
+  int* ptab = nullptr;        // general domains: Plan::ptab, bpts, bslots
+  int* bpts = nullptr;
+  unsigned* bslots = nullptr;
 };
 
 struct lsp_plan {
@@ -121,6 +124,16 @@ struct ProblemPtrs {
   int* perm;
   double* pivstat;
   void* Gop;  // formed dense sweep operators
+  // general domains: the sketch T = (K w^2 m) R (r rows of N), the boundary
+  // points' stencils and singular values ([nbnd][27]), the output mask, and
+  // the plan's point tables
+  double2* T;
+  double2* balpha;
+  double* bsigma;
+  double* dmask;
+  int* ptab;
+  int* bpts;
+  unsigned* bslots;
 };
 
 size_t layout_problem(const lsp_plan* pl, int precision, void* base, ProblemPtrs* out) {
@@ -149,6 +162,12 @@ size_t layout_problem(const lsp_plan* pl, int precision, void* base, ProblemPtrs
   q.perm = cv.take<int>(P.sum_p);
   q.pivstat = cv.take<double>((size_t)P.panel_blocks);
   q.Gop = cv.take<char>((size_t)P.dense_elems * esz);
+  if (P.general) {
+    q.T = cv.take<double2>((size_t)P.sketch_r * P.N);
+    q.balpha = cv.take<double2>(std::max<size_t>(1, P.bpts.size()) * S);
+    q.bsigma = cv.take<double>(std::max<size_t>(1, P.bpts.size()) * S);
+    q.dmask = cv.take<double>(P.N);
+  }
   if (out) *out = q;
   return cv.off + 256;
 }
@@ -163,9 +182,10 @@ const PlanDev& plan_device(const lsp_plan* pl, int device) {
   const size_t bf = up(P.fronts.size() * sizeof(FrontDev)), bi = up(P.idx.size() * sizeof(int)),
                bp = up(P.gpos.size() * sizeof(unsigned)), bc = up(P.cpos.size() * sizeof(int)),
                bg = up(pl->geo.size() * sizeof(ClassGeom)), bt = up(P.L * sizeof(double2)),
-               bt32 = up(P.L * sizeof(float2));
+               bt32 = up(P.L * sizeof(float2)), bpt = up(P.ptab.size() * sizeof(int)),
+               bbp = up(P.bpts.size() * sizeof(int)), bbs = up(P.bslots.size() * sizeof(unsigned));
   PlanDev d;
-  if (hipMalloc(&d.block, bf + bi + bp + bc + bg + bt + bt32) != hipSuccess) {
+  if (hipMalloc(&d.block, bf + bi + bp + bc + bg + bt + bt32 + bpt + bbp + bbs) != hipSuccess) {
     (void)hipGetLastError();
     throw Error(LSP_ERR_OOM, "device allocation of the plan arrays failed");
   }
@@ -176,7 +196,12 @@ const PlanDev& plan_device(const lsp_plan* pl, int device) {
   d.cpos = (int*)b; b += bc;
   d.geo = (ClassGeom*)b; b += bg;
   d.tw64 = (double2*)b; b += bt;
-  d.tw32 = (float2*)b;
+  d.tw32 = (float2*)b; b += bt32;
+  if (P.general) {
+    d.ptab = (int*)b; b += bpt;
+    d.bpts = (int*)b; b += bbp;
+    d.bslots = (unsigned*)b;
+  }
   // twiddles exp(-2 pi i k / L) from long double
   std::vector<double2> tw64(P.L);
   std::vector<float2> tw32(P.L);
@@ -194,6 +219,13 @@ const PlanDev& plan_device(const lsp_plan* pl, int device) {
     LSP_HIP(hipMemcpy(d.geo, pl->geo.data(), pl->geo.size() * sizeof(ClassGeom), hipMemcpyHostToDevice));
     LSP_HIP(hipMemcpy(d.tw64, tw64.data(), P.L * sizeof(double2), hipMemcpyHostToDevice));
     LSP_HIP(hipMemcpy(d.tw32, tw32.data(), P.L * sizeof(float2), hipMemcpyHostToDevice));
+    if (P.general) {
+      LSP_HIP(hipMemcpy(d.ptab, P.ptab.data(), P.ptab.size() * sizeof(int), hipMemcpyHostToDevice));
+      if (!P.bpts.empty()) {
+        LSP_HIP(hipMemcpy(d.bpts, P.bpts.data(), P.bpts.size() * sizeof(int), hipMemcpyHostToDevice));
+        LSP_HIP(hipMemcpy(d.bslots, P.bslots.data(), P.bslots.size() * sizeof(unsigned), hipMemcpyHostToDevice));
+      }
+    }
   } catch (...) {
     (void)hipFree(d.block);
     throw;
@@ -691,17 +723,27 @@ void fix_radices(Plan& P) {
   P.radices = rad;
 }
 
+// z = Q v (the class stencils, or a general domain's per-point rows)
+template <typename Cx>
+void apply_Q(lsp_problem* pb, Cx* z, const double2* v, int nrhs) {
+  const Plan& P = pb->plan->p;
+  if (P.general)
+    launch_applyQ_general<Cx>(z, v, pb->d.alpha_pad, pb->d.ptab, pb->d.balpha, P.n, P.d, P.N, nrhs, pb->st);
+  else
+    launch_applyQ<Cx>(z, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, pb->st);
+}
+
 void apply_precond(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2* v, double2* out) {
   const Plan& P = pb->plan->p;
   hipStream_t st = pb->st;
   if (pb->precision == LSP_FP64) {
-    launch_applyQ<double2>((double2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
+    apply_Q<double2>(pb, (double2*)s.zq, v, nrhs);
     MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                      pb->d.pivstat, (double2*)pb->d.Gop};
     const SweepBufs<double> sb{(double2*)s.ybuf, (double2*)s.pbuf, P.bsweep_ystride};
     mf_solve<double>(mf, P, nrhs, (const double2*)s.zq, out, (double2*)s.vbuf, sb, st, pb->take_form_wait(), nullptr);
   } else {
-    launch_applyQ<float2>((float2*)s.zq, v, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, st);
+    apply_Q<float2>(pb, (float2*)s.zq, v, nrhs);
     MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                     pb->d.pivstat, (float2*)pb->d.Gop};
     // the backward sweeps also store the solution widened into out
@@ -727,13 +769,14 @@ void solve_M(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2* z, do
   }
 }
 
-// y = x + K(w2m .* x) (op) or K x, in the given precision
+// y = x + K(w2m .* x) (op) or K x, in the given precision; on a general
+// domain y is restricted to Omega (zero outside)
 void apply_conv(lsp_problem* pb, const SolvePtrs& s, int nrhs, int precision, const double2* x, double2* y, bool op,
                 const double* w2m) {
   if (precision == LSP_MIXED)
-    kmatvec<float>(pb->fp32, nrhs, x, y, w2m, op, (float2*)s.W, pb->st);
+    kmatvec<float>(pb->fp32, nrhs, x, y, w2m, op, (float2*)s.W, pb->st, pb->d.dmask);
   else
-    kmatvec<double>(pb->fp64, nrhs, x, y, w2m, op, (double2*)s.W, pb->st);
+    kmatvec<double>(pb->fp64, nrhs, x, y, w2m, op, (double2*)s.W, pb->st, pb->d.dmask);
 }
 
 void check_ws(const lsp_problem* pb, int nrhs, bool krylov, void* ws, size_t bytes) {
@@ -784,7 +827,8 @@ lsp_status lsp_options_default(lsp_options* o) {
   return LSP_OK;
 }
 
-lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts, lsp_plan** out) {
+static lsp_status plan_create_impl(int n, int d, int max_nrhs, const lsp_options* opts, const unsigned char* mask,
+                            int sketch_cols, lsp_plan** out) {
   return guarded([&]() -> lsp_status {
     LSP_REQUIRE(out != nullptr, "null plan pointer");
     *out = nullptr;
@@ -804,6 +848,10 @@ lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts, 
     o.tile_cache = nullptr;  // the plan keeps no pointer into the caller's memory
     std::unique_ptr<lsp_plan> pl(new lsp_plan());
     build_plan(pl->p, n, d, max_nrhs, o);
+    if (mask) {
+      LSP_REQUIRE(o.equation == LSP_HELMHOLTZ, "general domains are for the Helmholtz equation");
+      build_general(pl->p, mask, sketch_cols > 0 ? sketch_cols : 2 * ipow(3, d));
+    }
     fix_radices(pl->p);
     build_class_geometry(pl.get());
     if (!cache.empty()) {
@@ -813,6 +861,17 @@ lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts, 
     *out = pl.release();
     return LSP_OK;
   });
+}
+
+lsp_status lsp_plan_create(int n, int d, int max_nrhs, const lsp_options* opts, lsp_plan** out) {
+  return plan_create_impl(n, d, max_nrhs, opts, nullptr, 0, out);
+}
+
+lsp_status lsp_plan_create_general(int n, int d, int max_nrhs, const lsp_options* opts, const unsigned char* mask,
+                                   int sketch_cols, lsp_plan** out) {
+  if (!mask) return fail(LSP_ERR_ARG, "null domain mask");
+  if (sketch_cols < 0) return fail(LSP_ERR_ARG, "sketch_cols must be >= 0");
+  return plan_create_impl(n, d, max_nrhs, opts, mask, sketch_cols, out);
 }
 
 void lsp_plan_destroy(lsp_plan* plan) { delete plan; }
@@ -846,6 +905,9 @@ lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* s) {
   s->mchain_entries = P.mchain_entries;
   s->pair_update_flops = fs.pair_update_flops;
   s->cross_update_flops = fs.cross_update_flops;
+  s->domain_points = P.general ? P.domain_points : P.N;
+  s->boundary_points = (int)P.bpts.size();
+  s->sketch_cols = P.sketch_r;
   return LSP_OK;
 }
 
@@ -908,12 +970,15 @@ lsp_status lsp_plan_bytes(const lsp_plan* plan, int precision, int nrhs, size_t*
   });
 }
 
-lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, void* ws_dev, size_t ws_bytes,
-                     void* stream, lsp_problem** out) {
+static lsp_status setup_impl(const lsp_plan* plan, double omega, const double* m_dev, const double* R_dev, void* ws_dev,
+                      size_t ws_bytes, void* stream, lsp_problem** out) {
   return guarded([&]() -> lsp_status {
     LSP_REQUIRE(out != nullptr, "null problem pointer");
     *out = nullptr;
     LSP_REQUIRE(plan != nullptr && m_dev != nullptr && ws_dev != nullptr, "null argument");
+    LSP_REQUIRE(plan->p.general == (R_dev != nullptr),
+                plan->p.general ? "a general-domain plan is set up with lsp_setup_general (sketch R)"
+                                : "lsp_setup_general needs a plan from lsp_plan_create_general");
     if (plan->p.opts.equation == LSP_LAPLACE)
       LSP_REQUIRE(omega == 0.0, "omega must be 0 for the Laplace equation");
     else
@@ -944,6 +1009,9 @@ lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, vo
     pb->d.geo = pd.geo;
     pb->d.tw64 = pd.tw64;
     pb->d.tw32 = pd.tw32;
+    pb->d.ptab = pd.ptab;
+    pb->d.bpts = pd.bpts;
+    pb->d.bslots = pd.bslots;
     pb->fp64 = make_fft_plan<double>(P, pb->d.tw64, pb->d.spec64);
     pb->fp32 = make_fft_plan<float>(P, pb->d.tw32, pb->d.spec32);
 
@@ -958,9 +1026,86 @@ lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, vo
     // stencils and the sparse matrix
     compute_stencils(pb->d.ktab, P.n, P.d, pb->d.geo, plan->nclass, plan->maxF, pb->d.partial, plan->gram_blocks,
                      pb->d.G, pb->d.U1, pb->d.alpha_pad, pb->d.C_pad, pb->d.sigma_pad, st);
-    launch_assemble(pb->d.Mval, pb->d.alpha_pad, pb->d.C_pad, pb->d.w2m, P.n, P.d, P.N, st);
+    if (P.general) {
+      // Section 4: T = (K w^2 m) R over Omega's columns, one K product per
+      // sketch column (the embedding array, free after the spectrum, is the
+      // transform's work array), then the boundary points' stencils
+      launch_domain_mask(pb->d.dmask, pb->d.ptab, P.N, st);
+      for (int c = 0; c < P.sketch_r; ++c) {
+        double2* Tc = pb->d.T + (size_t)c * P.N;
+        launch_sketch_widen(Tc, R_dev + (size_t)c * P.N, pb->d.ptab, P.N, st);
+        kmatvec<double>(pb->fp64, 1, Tc, Tc, pb->d.w2m, false, pb->d.E, st);
+      }
+      launch_bnd_stencils(pb->d.T, P.sketch_r, P.N, pb->d.bpts, pb->d.bslots, (int)P.bpts.size(), P.n, P.d,
+                          pb->d.balpha, pb->d.bsigma, st);
+      launch_assemble_general(pb->d.Mval, pb->d.alpha_pad, pb->d.C_pad, pb->d.w2m, pb->d.ptab, pb->d.balpha, P.n,
+                              P.d, P.N, st);
+    } else {
+      launch_assemble(pb->d.Mval, pb->d.alpha_pad, pb->d.C_pad, pb->d.w2m, P.n, P.d, P.N, st);
+    }
     LSP_HIP(hipEventRecord(pb->ev[lsp_problem::EV_SETUP1], st));
     *out = pb.release();
+    return LSP_OK;
+  });
+}
+
+lsp_status lsp_setup(const lsp_plan* plan, double omega, const double* m_dev, void* ws_dev, size_t ws_bytes,
+                     void* stream, lsp_problem** out) {
+  return setup_impl(plan, omega, m_dev, nullptr, ws_dev, ws_bytes, stream, out);
+}
+
+lsp_status lsp_setup_general(const lsp_plan* plan, double omega, const double* m_dev, const double* R_dev,
+                             void* ws_dev, size_t ws_bytes, void* stream, lsp_problem** out) {
+  if (!R_dev) return fail(LSP_ERR_ARG, "null sketch matrix");
+  return setup_impl(plan, omega, m_dev, R_dev, ws_dev, ws_bytes, stream, out);
+}
+
+lsp_status lsp_field_bytes(const lsp_plan* plan, int npts, size_t* bytes) {
+  if (!plan || !bytes) return fail(LSP_ERR_ARG, "null argument");
+  if (npts < 1) return fail(LSP_ERR_ARG, "npts must be >= 1");
+  *bytes = (size_t)field_chunks(plan->p.N) * 16 * (size_t)npts * sizeof(double2) + 256;
+  return LSP_OK;
+}
+
+static lsp_status field_impl(int mode, lsp_problem* pb, int nrhs, const void* u, const void* uI, int npts,
+                             const double* pts, void* out, void* ws, size_t bytes) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(pb && u && uI && pts && out && ws, "null argument");
+    LSP_REQUIRE(nrhs >= 1 && npts >= 1, "nrhs and npts must be >= 1");
+    const Plan& P = pb->plan->p;
+    LSP_REQUIRE(P.opts.equation == LSP_HELMHOLTZ, "field evaluation is for the Helmholtz equation");
+    size_t need = 0;
+    lsp_field_bytes(pb->plan, npts, &need);
+    LSP_REQUIRE(bytes >= need, "field workspace too small");
+    const double2 k0 = self_term_host(1.0 / P.n, pb->omega, P.d, P.opts.self_term);
+    field_eval(mode, (const double2*)u, (const double2*)uI, pb->d.w2m, pts, npts, nrhs, P.n, P.d, pb->omega, k0,
+               (double2*)align_up((size_t)ws, 256), (double2*)out, pb->st);
+    return LSP_OK;
+  });
+}
+
+lsp_status lsp_exterior_field(lsp_problem* pb, int nrhs, const void* u, const void* uI, int npts,
+                              const double* points, void* out, void* ws, size_t bytes) {
+  return field_impl(0, pb, nrhs, u, uI, npts, points, out, ws, bytes);
+}
+
+lsp_status lsp_far_field(lsp_problem* pb, int nrhs, const void* u, const void* uI, int ndirs, const double* dirs,
+                         void* out, void* ws, size_t bytes) {
+  return field_impl(1, pb, nrhs, u, uI, ndirs, dirs, out, ws, bytes);
+}
+
+lsp_status lsp_get_boundary_stencils(lsp_problem* pb, int* points, double* alpha, double* sigma) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(pb != nullptr, "null problem");
+    const Plan& P = pb->plan->p;
+    LSP_REQUIRE(P.general, "not a general-domain problem");
+    const size_t nb = P.bpts.size(), S = kMaxStencil;
+    if (points && nb) std::memcpy(points, P.bpts.data(), nb * sizeof(int));
+    if (alpha && nb)
+      LSP_HIP(hipMemcpyAsync(alpha, pb->d.balpha, nb * S * sizeof(double2), hipMemcpyDeviceToHost, pb->st));
+    if (sigma && nb)
+      LSP_HIP(hipMemcpyAsync(sigma, pb->d.bsigma, nb * S * sizeof(double), hipMemcpyDeviceToHost, pb->st));
+    LSP_HIP(hipStreamSynchronize(pb->st));
     return LSP_OK;
   });
 }
@@ -1057,9 +1202,11 @@ lsp_status lsp_apply_op_noalloc(lsp_problem* pb, int nrhs, int precision, const 
     // the kernels overwrite every element of it they read, so nothing is cleared
     void* W = static_scratch(pb->device);
     if (precision == LSP_MIXED)
-      kmatvec<float>(pb->fp32, nrhs, (const double2*)x, (double2*)y, pb->d.w2m, true, (float2*)W, pb->st);
+      kmatvec<float>(pb->fp32, nrhs, (const double2*)x, (double2*)y, pb->d.w2m, true, (float2*)W, pb->st,
+                     pb->d.dmask);
     else
-      kmatvec<double>(pb->fp64, nrhs, (const double2*)x, (double2*)y, pb->d.w2m, true, (double2*)W, pb->st);
+      kmatvec<double>(pb->fp64, nrhs, (const double2*)x, (double2*)y, pb->d.w2m, true, (double2*)W, pb->st,
+                      pb->d.dmask);
     return LSP_OK;
   });
 }
@@ -1068,8 +1215,7 @@ lsp_status lsp_apply_Q(lsp_problem* pb, int nrhs, const void* x, void* y) {
   return guarded([&]() -> lsp_status {
     LSP_REQUIRE(pb && x && y, "null argument");
     LSP_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
-    const Plan& P = pb->plan->p;
-    launch_applyQ<double2>((double2*)y, (const double2*)x, pb->d.alpha_pad, P.n, P.d, P.N, nrhs, pb->st);
+    apply_Q<double2>(pb, (double2*)y, (const double2*)x, nrhs);
     return LSP_OK;
   });
 }

@@ -353,4 +353,42 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
   }
 }
 
+void build_general(Plan& P, const unsigned char* mask, int r) {
+  LSP_REQUIRE(mask != nullptr, "null domain mask");
+  LSP_REQUIRE(r >= 1 && r <= 4096, "sketch columns must be in [1, 4096]");
+  const int n = P.n, d = P.d, ns = d == 2 ? 9 : 27;
+  P.general = true;
+  P.sketch_r = r;
+  P.ptab.assign(P.N, -2);
+  P.bpts.clear();
+  P.bslots.clear();
+  P.domain_points = 0;
+  for (int pt = 0; pt < P.N; ++pt) {
+    if (!mask[pt]) continue;
+    ++P.domain_points;
+    const int i[3] = {pt % n, (pt / n) % n, d == 3 ? pt / (n * n) : 0};
+    unsigned bits = 0;
+    for (int q = 0; q < ns; ++q) {
+      const int o[3] = {q % 3 - 1, (q / 3) % 3 - 1, q / 9 - 1};
+      bool in = true;
+      long long nb = 0, st = 1;
+      for (int a = 0; a < d; ++a) {
+        const int j = i[a] + o[a];
+        in = in && j >= 0 && j < n;
+        nb += (long long)j * st;
+        st *= n;
+      }
+      if (in && mask[nb]) bits |= 1u << q;
+    }
+    if (bits == (ns == 32 ? ~0u : (1u << ns) - 1)) {
+      P.ptab[pt] = -1;
+    } else {
+      P.ptab[pt] = (int)P.bpts.size();
+      P.bpts.push_back(pt);
+      P.bslots.push_back(bits);
+    }
+  }
+  LSP_REQUIRE(P.domain_points > 0, "empty domain mask");
+}
+
 }  // namespace lsp

@@ -91,6 +91,18 @@ struct Plan {
   double flops = 0.0, factor_entries = 0.0, sweep_entries = 0.0, update_flops = 0.0;
   double panel_blocks = 0.0;  // sum over fronts of ceil(p / nb)
   std::vector<int> radices;       // FFT radices for L, in pass order
+  // General domain (Section 4): the support Omega of m as a mask over the
+  // grid.  ptab per grid point: -1 interior (the whole 3^d block in Omega),
+  // -2 outside Omega, else the point's row among the boundary points bpts
+  // (increasing linear index), whose neighbours in Omega are the set bits q
+  // = sum_a (s_a + 1) 3^a of bslots.  sketch_r: columns of the sketch R.
+  // Points outside Omega keep their place in the dissection as identity rows.
+  bool general = false;
+  std::vector<int> ptab;
+  std::vector<int> bpts;
+  std::vector<unsigned> bslots;
+  int sketch_r = 0;
+  long long domain_points = 0;
 };
 
 // Bits per axis of a packed grid position: 16 in 2D (n <= 4096), 10 in 3D
@@ -99,5 +111,8 @@ inline int gpos_shift(int d) { return d == 2 ? 16 : 10; }
 
 // Builds the plan; throws lsp::Error on invalid input.
 void build_plan(Plan& plan, int n, int d, int max_nrhs, const lsp_options& opts);
+// Classifies the points of a general domain (mask: n^d bytes, nonzero =
+// in Omega) into plan.ptab / bpts / bslots; r = sketch columns.
+void build_general(Plan& plan, const unsigned char* mask, int r);
 
 }  // namespace lsp

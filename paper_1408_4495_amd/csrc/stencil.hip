@@ -411,6 +411,169 @@ __global__ void __launch_bounds__(64) eigen_kernel(const double2* __restrict__ G
   }
 }
 
+// ---- general domains (Section 4)
+//
+// Boundary point b of a general domain (neighbours in Omega: the set bits of
+// bslots[b], listed in slot order) takes alpha = the conjugate of the least
+// left singular vector of X = T(mu, :), T = (K w^2 m) R the sketch (its r
+// columns stored as rows of length N), normalised like the class stencils.
+// X is reduced by the same two Gram passes: G = X X^H, Jacobi -> U1; then
+// G2 = (U1^H X)(U1^H X)^H, Jacobi -> U2, U = U1 U2 (pass 2 restores the
+// relative accuracy of the smallest singular value).  One wave per point;
+// the sketch columns are staged BC at a time.  Outputs: alpha slot-padded
+// (zero for slots outside Omega) and the singular values, descending.
+constexpr int BC = 16;
+
+__global__ void __launch_bounds__(64) bnd_stencil_kernel(const double2* __restrict__ T, int r, long long N,
+                                                         const int* __restrict__ bpts,
+                                                         const unsigned* __restrict__ bslots, int n, int d,
+                                                         double2* __restrict__ balpha, double* __restrict__ bsigma) {
+  __shared__ double2 X[S * BC];
+  __shared__ double2 Y[S * BC];
+  __shared__ double2 A[S * S];
+  __shared__ double2 U1[S * S];
+  __shared__ double2 U2[S * S];
+  __shared__ double2 u[S];
+  __shared__ double lam[S];
+  __shared__ int order[S];
+  __shared__ int sl[S];
+  __shared__ long long nbi[S];
+  __shared__ int ssz;
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const int ns = d == 2 ? 9 : 27, centre_slot = ns / 2;
+  const long long pt = bpts[b];
+  const unsigned bits = bslots[b];
+  if (lane == 0) {
+    int k = 0;
+    for (int q = 0; q < ns; ++q)
+      if ((bits >> q) & 1u) sl[k++] = q;
+    ssz = k;
+  }
+  __syncthreads();
+  const int s = ssz;
+  if (lane < s) {
+    const int q = sl[lane];
+    const long long o1 = q % 3 - 1, o2 = (q / 3) % 3 - 1, o3 = q / 9 - 1;
+    nbi[lane] = pt + o1 + o2 * n + (d == 3 ? o3 * (long long)n * n : 0);
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int e = lane; e < S * S; e += 64) A[e] = make_double2(0, 0);
+    __syncthreads();
+    for (int c0 = 0; c0 < r; c0 += BC) {
+      const int cols = min(BC, r - c0);
+      for (int e = lane; e < s * cols; e += 64) {
+        const int a = e % s, c = e / s;
+        X[a + S * c] = T[(long long)(c0 + c) * N + nbi[a]];
+      }
+      __syncthreads();
+      const double2* Z = X;
+      if (pass == 1) {  // Y = U1^H X
+        for (int e = lane; e < s * cols; e += 64) {
+          const int a = e % s, c = e / s;
+          double2 acc = make_double2(0, 0);
+          for (int k = 0; k < s; ++k) acc = cadd(acc, cmul(cconj(U1[k + S * a]), X[k + S * c]));
+          Y[a + S * c] = acc;
+        }
+        __syncthreads();
+        Z = Y;
+      }
+      // A += Z Z^H over this chunk's columns
+      for (int e = lane; e < s * s; e += 64) {
+        const int i = e % s, j = e / s;
+        double2 acc = A[i + S * j];
+        for (int c = 0; c < cols; ++c) acc = cadd(acc, cmul(Z[i + S * c], cconj(Z[j + S * c])));
+        A[i + S * j] = acc;
+      }
+      __syncthreads();
+    }
+    double2* Uc = pass == 0 ? U1 : U2;
+    for (int e = lane; e < S * S; e += 64) Uc[e] = make_double2((e % S) == (e / S) ? 1.0 : 0.0, 0.0);
+    __syncthreads();
+    jacobi_eigen(A, Uc, s, lane);
+    __syncthreads();
+  }
+  for (int k = lane; k < S; k += 64) lam[k] = k < s ? A[k + S * k].x : 0.0;
+  __syncthreads();
+  if (lane == 0) {
+    for (int k = 0; k < s; ++k) order[k] = k;
+    for (int i = 1; i < s; ++i) {  // insertion sort, descending
+      const int v = order[i];
+      int j = i - 1;
+      while (j >= 0 && lam[order[j]] < lam[v]) { order[j + 1] = order[j]; --j; }
+      order[j + 1] = v;
+    }
+  }
+  __syncthreads();
+  const int kmin = order[s - 1];
+  // u = U1 U2(:, kmin)
+  if (lane < s) {
+    double2 acc = make_double2(0, 0);
+    for (int k = 0; k < s; ++k) acc = cadd(acc, cmul(U1[lane + S * k], U2[k + S * kmin]));
+    u[lane] = acc;
+  }
+  __syncthreads();
+  int centre = 0;
+  for (int a = 0; a < s; ++a)
+    if (sl[a] == centre_slot) centre = a;
+  const double2 uc = cconj(u[centre]);
+  const double mag = sqrt(uc.x * uc.x + uc.y * uc.y);
+  const double2 ph = make_double2(uc.x / mag, -uc.y / mag);
+  double nrm2 = 0.0;
+  for (int a = 0; a < s; ++a) nrm2 += u[a].x * u[a].x + u[a].y * u[a].y;
+  const double inv = 1.0 / sqrt(nrm2);
+  if (lane < S) {
+    balpha[(long long)b * S + lane] = make_double2(0, 0);
+    bsigma[(long long)b * S + lane] = lane < s ? sqrt(fmax(lam[order[lane]], 0.0)) : 0.0;
+  }
+  __syncthreads();
+  if (lane < s) balpha[(long long)b * S + sl[lane]] = cscale(cmul(cconj(u[lane]), ph), inv);
+}
+
+// Rows of M for a general domain: outside Omega the identity row, interior
+// points the rectangle's interior row alpha + C w^2 m (class icls), boundary
+// points their own alpha (slot-padded, zero outside Omega).  [N][3^d].
+__global__ void assemble_general_kernel(double2* __restrict__ Mval, const double2* __restrict__ alpha_pad,
+                                        const double2* __restrict__ C_pad, const double* __restrict__ w2m,
+                                        const int* __restrict__ ptab, const double2* __restrict__ balpha, int n,
+                                        int d, long long N) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ns = d == 2 ? 9 : 27;
+  if (id >= N * ns) return;
+  const long long pt = id / ns;
+  const int slot = (int)(id % ns);
+  const int k = ptab[pt];
+  double2 v = make_double2(0, 0);
+  if (k == -2) {
+    v.x = slot == ns / 2 ? 1.0 : 0.0;
+  } else if (k == -1) {
+    const int icls = d == 2 ? 4 : 13;
+    const long long nb = pt + (slot % 3 - 1) + (long long)((slot / 3) % 3 - 1) * n +
+                         (d == 3 ? (long long)(slot / 9 - 1) * n * n : 0);
+    v = alpha_pad[icls * S + slot];
+    const double2 cc = C_pad[icls * S + slot];
+    const double w = w2m[nb];
+    v.x += cc.x * w;
+    v.y += cc.y * w;
+  } else {
+    v = balpha[(long long)k * S + slot];
+  }
+  Mval[id] = v;
+}
+
+// T row c = mask .* R row c, widened to complex128 (zero outside Omega);
+// dmask = 1 in Omega, 0 outside.
+__global__ void sketch_widen_kernel(double2* __restrict__ T, const double* __restrict__ R,
+                                    const int* __restrict__ ptab, long long N) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  T[i] = make_double2(ptab[i] != -2 ? R[i] : 0.0, 0.0);
+}
+
+__global__ void domain_mask_kernel(double* __restrict__ dmask, const int* __restrict__ ptab, long long N) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) dmask[i] = ptab[i] != -2 ? 1.0 : 0.0;
+}
+
 __device__ inline int point_class(const int* i, int n, int d) {
   int c = 0, m3 = 1;
   for (int a = 0; a < d; ++a) {
@@ -485,7 +648,86 @@ __global__ void __launch_bounds__(256) applyQ_kernel(Cx* __restrict__ y, const d
   y[rb + pt] = from_c128<Cx>(acc);
 }
 
+// Q apply of a general domain: outside Omega the identity row, interior
+// points the interior class stencil, boundary points their own (neighbours
+// outside the grid skipped; their alpha is zero).
+template <typename Cx, int D>
+__global__ void __launch_bounds__(256) applyQ_general_kernel(Cx* __restrict__ y, const double2* __restrict__ x,
+                                                             const double2* __restrict__ alpha_pad,
+                                                             const int* __restrict__ ptab,
+                                                             const double2* __restrict__ balpha, int n, long long N,
+                                                             int nb1) {
+  const int line = blockIdx.x / nb1;
+  const int i1 = (blockIdx.x - line * nb1) * 256 + threadIdx.x;
+  if (i1 >= n) return;
+  const int i2 = D == 2 ? line : line % n, i3 = D == 2 ? 0 : line / n;
+  const long long rb = (long long)blockIdx.y * N;
+  const long long pt = (long long)line * n + i1;
+  constexpr int NS = D == 2 ? 9 : 27;
+  const int k = ptab[pt];
+  if (k == -2) {
+    y[rb + pt] = from_c128<Cx>(x[rb + pt]);
+    return;
+  }
+  const double2* al = k == -1 ? alpha_pad + (D == 2 ? 4 : 13) * S : balpha + (long long)k * S;
+  double2 acc = make_double2(0, 0);
+#pragma unroll
+  for (int slot = 0; slot < NS; ++slot) {
+    const int o1 = slot % 3 - 1, o2 = (slot / 3) % 3 - 1, o3 = slot / 9 - 1;
+    const bool inside = i1 + o1 >= 0 && i1 + o1 < n && i2 + o2 >= 0 && i2 + o2 < n &&
+                        (D == 2 || (i3 + o3 >= 0 && i3 + o3 < n));
+    if (inside) {
+      const long long nb = pt + o1 + (long long)o2 * n + (D == 3 ? (long long)o3 * n * n : 0);
+      acc = cadd(acc, cmul(al[slot], x[rb + nb]));
+    }
+  }
+  y[rb + pt] = from_c128<Cx>(acc);
+}
+
 }  // namespace
+
+void launch_domain_mask(double* dmask, const int* ptab, long long N, hipStream_t st) {
+  LSP_LAUNCH("domain_mask", 0, domain_mask_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, dmask, ptab,
+             N);
+}
+
+void launch_sketch_widen(double2* T, const double* R, const int* ptab, long long N, hipStream_t st) {
+  LSP_LAUNCH("sketch_widen", 0, sketch_widen_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, T, R, ptab,
+             N);
+}
+
+void launch_bnd_stencils(const double2* T, int r, long long N, const int* bpts, const unsigned* bslots, int nbnd,
+                         int n, int d, double2* balpha, double* bsigma, hipStream_t st) {
+  if (nbnd == 0) return;
+  LSP_LAUNCH("bnd_stencil", 0, bnd_stencil_kernel, dim3(nbnd), dim3(64), 0, st, T, r, N, bpts, bslots, n, d, balpha,
+             bsigma);
+}
+
+void launch_assemble_general(double2* Mval, const double2* alpha_pad, const double2* C_pad, const double* w2m,
+                             const int* ptab, const double2* balpha, int n, int d, long long N, hipStream_t st) {
+  const long long total = N * (d == 2 ? 9 : 27);
+  LSP_LAUNCH("assemble", 0, assemble_general_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, Mval,
+             alpha_pad, C_pad, w2m, ptab, balpha, n, d, N);
+}
+
+template <typename Cx>
+void launch_applyQ_general(Cx* y, const double2* x, const double2* alpha_pad, const int* ptab, const double2* balpha,
+                           int n, int d, long long N, int nrhs, hipStream_t st) {
+  const int nb1 = (n + 255) / 256;
+  const long long lines = d == 2 ? n : (long long)n * n;
+  const dim3 grid((unsigned)(lines * nb1), nrhs);
+  if (d == 2)
+    LSP_LAUNCH("applyQ", (int)sizeof(Cx), (applyQ_general_kernel<Cx, 2>), grid, dim3(256), 0, st, y, x, alpha_pad,
+               ptab, balpha, n, N, nb1);
+  else
+    LSP_LAUNCH("applyQ", (int)sizeof(Cx), (applyQ_general_kernel<Cx, 3>), grid, dim3(256), 0, st, y, x, alpha_pad,
+               ptab, balpha, n, N, nb1);
+}
+
+template void launch_applyQ_general<double2>(double2*, const double2*, const double2*, const int*, const double2*,
+                                             int, int, long long, int, hipStream_t);
+template void launch_applyQ_general<float2>(float2*, const double2*, const double2*, const int*, const double2*, int,
+                                            int, long long, int, hipStream_t);
 
 void compute_stencils(const double2* ktab, int n, int d, const ClassGeom* geo_dev, int nclass, long long maxF,
                       double2* partial, int nblk, double2* G, double2* U1, double2* alpha_pad, double2* C_pad,

@@ -24,7 +24,9 @@ EXPORTED = ["lsp_options_default", "lsp_plan_create", "lsp_plan_destroy", "lsp_p
             "lsp_apply_op", "lsp_apply_K", "lsp_apply_Q", "lsp_solve_M", "lsp_apply_precond",
             "lsp_get_kernel_table", "lsp_get_stencils", "lsp_get_matrix", "lsp_status_string",
             "lsp_last_error", "lsp_timing_enable", "lsp_timing_reset", "lsp_timing_count",
-            "lsp_timing_get", "lsp_plan_get_tiles", "lsp_plan_set_tiles", "lsp_apply_op_noalloc", "lsp_plan_save_tiles"]
+            "lsp_timing_get", "lsp_plan_get_tiles", "lsp_plan_set_tiles", "lsp_apply_op_noalloc", "lsp_plan_save_tiles",
+            "lsp_plan_create_general", "lsp_setup_general", "lsp_get_boundary_stencils",
+            "lsp_field_bytes", "lsp_exterior_field", "lsp_far_field"]
 
 
 class Options(ctypes.Structure):
@@ -53,7 +55,8 @@ class PlanStats(ctypes.Structure):
                 ("chain_entries", ctypes.c_double), ("blocked_panel_entries", ctypes.c_double),
                 ("trsm_flops", ctypes.c_double), ("assemble_entries", ctypes.c_double),
                 ("mchain_levels", ctypes.c_int), ("mchain_entries", ctypes.c_double),
-                ("pair_update_flops", ctypes.c_double), ("cross_update_flops", ctypes.c_double)]
+                ("pair_update_flops", ctypes.c_double), ("cross_update_flops", ctypes.c_double),
+                ("domain_points", ctypes.c_int), ("boundary_points", ctypes.c_int), ("sketch_cols", ctypes.c_int)]
 
 
 class LspError(RuntimeError):
@@ -77,6 +80,12 @@ def load():
     sigs = {
         "lsp_options_default": [ctypes.POINTER(Options)],
         "lsp_plan_create": [ci, ci, ci, ctypes.POINTER(Options), ctypes.POINTER(vp)],
+        "lsp_plan_create_general": [ci, ci, ci, ctypes.POINTER(Options), vp, ci, ctypes.POINTER(vp)],
+        "lsp_setup_general": [vp, cd, vp, vp, vp, sz, vp, ctypes.POINTER(vp)],
+        "lsp_get_boundary_stencils": [vp, vp, vp, vp],
+        "lsp_field_bytes": [vp, ci, ctypes.POINTER(sz)],
+        "lsp_exterior_field": [vp, ci, vp, vp, ci, vp, vp, vp, sz],
+        "lsp_far_field": [vp, ci, vp, vp, ci, vp, vp, vp, sz],
         "lsp_plan_stats_get": [vp, ctypes.POINTER(PlanStats)],
         "lsp_plan_bytes": [vp, ci, ci, ctypes.POINTER(sz), ctypes.POINTER(sz)],
         "lsp_setup": [vp, cd, vp, vp, sz, vp, ctypes.POINTER(vp)],
@@ -156,11 +165,13 @@ def timing_read():
 
 
 class Plan:
-    """Symbolic plan for an n^d grid (host-side nested dissection)."""
+    """Symbolic plan for an n^d grid (host-side nested dissection).  With a
+    mask (n^d booleans), a general-domain plan (Section 4) whose unknowns
+    are the points of Omega; sketch_cols = r (0: 2 * 3^d)."""
 
     def __init__(self, n, d, max_nrhs=1, tol=1e-8, restart=30, max_iters=1000, precision="fp64",
                  buffer_b=2, leaf=0, panel=0, dense_sweeps=1, blocked_sweeps=1, self_term=0,
-                 tile_cache=None, equation="helmholtz"):
+                 tile_cache=None, equation="helmholtz", mask=None, sketch_cols=0):
         lib = load()
         o = Options()
         _check(lib.lsp_options_default(ctypes.byref(o)))
@@ -175,7 +186,15 @@ class Plan:
         self.n, self.d, self.max_nrhs = n, d, max_nrhs
         self.precision = o.precision
         h = ctypes.c_void_p()
-        _check(lib.lsp_plan_create(n, d, max_nrhs, ctypes.byref(o), ctypes.byref(h)))
+        self.general = mask is not None
+        if self.general:
+            mk = np.ascontiguousarray(np.asarray(mask).reshape(-1) != 0, dtype=np.uint8)
+            if mk.size != n ** d:
+                raise ValueError("mask has the wrong length")
+            _check(lib.lsp_plan_create_general(n, d, max_nrhs, ctypes.byref(o), mk.ctypes.data_as(ctypes.c_void_p),
+                                               int(sketch_cols), ctypes.byref(h)))
+        else:
+            _check(lib.lsp_plan_create(n, d, max_nrhs, ctypes.byref(o), ctypes.byref(h)))
         self._h = h
 
     def bytes(self, nrhs=1, precision=None):
@@ -213,10 +232,11 @@ class Problem:
     """Set-up (kernel table, spectrum, stencils, M) on the GPU; factor; solve.
 
     m: real medium of length n^d (numpy or torch), or for a Laplace plan the
-    potential V (with omega = 0); device memory comes from torch; work is
+    potential V (with omega = 0); R: the [r, n^d] real sketch of a
+    general-domain plan (Section 4); device memory comes from torch; work is
     enqueued on `stream` (default: torch's current stream)."""
 
-    def __init__(self, plan, omega, m, device="cuda:0", stream=None):
+    def __init__(self, plan, omega, m, device="cuda:0", stream=None, R=None):
         import torch
         self.torch = torch
         self.plan = plan
@@ -237,8 +257,19 @@ class Problem:
             self.ws = torch.empty(pbytes, dtype=torch.uint8, device=self.device)
             self._solve_ws = None
             h = ctypes.c_void_p()
-            _check(lib.lsp_setup(plan._h, float(omega), _ptr(m_t), _ptr(self.ws), pbytes,
-                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+            if getattr(plan, "general", False):
+                if R is None:
+                    raise ValueError("a general-domain plan needs the sketch R")
+                r = plan.stats()["sketch_cols"]
+                R_t = torch.as_tensor(np.asarray(R, dtype=np.float64) if not isinstance(R, torch.Tensor) else R)
+                R_t = R_t.to(device=self.device, dtype=torch.float64).contiguous()
+                if R_t.numel() != r * N:
+                    raise ValueError(f"sketch must be [{r}, {N}]")
+                _check(lib.lsp_setup_general(plan._h, float(omega), _ptr(m_t), _ptr(R_t), _ptr(self.ws), pbytes,
+                                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+            else:
+                _check(lib.lsp_setup(plan._h, float(omega), _ptr(m_t), _ptr(self.ws), pbytes,
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h
         self.omega = float(omega)
         self.N = N
@@ -376,6 +407,44 @@ class Problem:
                                      sigma.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      C.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return alpha.reshape(nc, 27), sigma.reshape(nc, 27), C.reshape(nc, 27)
+
+    def _eval_field(self, fn, u, uI, pts):
+        t = self.torch
+        with self._ctx():
+            u = self._field(u)
+            uI = self._field(uI)
+            if u.shape != uI.shape:
+                raise ValueError("u and u_I must have the same shape")
+            P = t.as_tensor(np.asarray(pts, dtype=np.float64) if not isinstance(pts, t.Tensor) else pts)
+            P = P.to(device=self.device, dtype=t.float64).reshape(-1, self.plan.d).contiguous()
+            npts = P.shape[0]
+            nb = ctypes.c_size_t()
+            _check(_lib.lsp_field_bytes(self.plan._h, npts, ctypes.byref(nb)))
+            ws = t.empty(nb.value, dtype=t.uint8, device=self.device)
+            out = t.empty((u.shape[0], npts), dtype=t.complex128, device=self.device)
+            _check(fn(self._h, u.shape[0], _ptr(u), _ptr(uI), npts, _ptr(P), _ptr(out), _ptr(ws), nb.value))
+        return self._handoff(out)
+
+    def exterior_field(self, u, uI, points):
+        """Scattered field at points [P, d] (Section 1's representation; see
+        lsp.h): [nrhs, P] complex128."""
+        return self._eval_field(_lib.lsp_exterior_field, u, uI, points)
+
+    def far_field(self, u, uI, dirs):
+        """Far-field pattern at unit directions [P, d]: [nrhs, P]."""
+        return self._eval_field(_lib.lsp_far_field, u, uI, dirs)
+
+    def boundary_stencils(self):
+        """General domains: (points [nbnd] int, alpha [nbnd, 27] complex,
+        sigma [nbnd, 27]) of the boundary points (see lsp.h)."""
+        nb = self.plan.stats()["boundary_points"]
+        pts = np.zeros(max(nb, 1), dtype=np.int32)
+        alpha = np.zeros(max(nb, 1) * 27, dtype=np.complex128)
+        sigma = np.zeros(max(nb, 1) * 27, dtype=np.float64)
+        _check(_lib.lsp_get_boundary_stencils(self._h, pts.ctypes.data_as(ctypes.c_void_p),
+                                              alpha.ctypes.data_as(ctypes.c_void_p),
+                                              sigma.ctypes.data_as(ctypes.c_void_p)))
+        return pts[:nb], alpha.reshape(-1, 27)[:nb], sigma.reshape(-1, 27)[:nb]
 
     def matrix(self):
         t = self.torch

@@ -5,6 +5,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 import paper_1408_4495_amd as pkg
@@ -254,3 +255,30 @@ def test_laplace_options_validated(lib):
     assert b"omega must be 0" in buf.value
     q = L.Plan(8, 3)
     assert lib.lsp_setup(q._h, 0.0, ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 40, None, ctypes.byref(h)) == 1
+
+
+def test_general_plan_classification(lib):
+    """A general-domain plan (Section 4) classifies the points of Omega like
+    the oracle: the same domain and boundary points; a rectangle plan
+    reports the whole grid; invalid masks and options are refused."""
+    import synth
+    from oracle.general import classify
+    for key in ("g1", "g1d", "g3"):
+        w = synth.workload(key)
+        n, d = w["n"], w["d"]
+        s = L.Plan(n, d, mask=w["mask"]).stats()
+        pts, _, interior = classify(w["mask"], n, d)
+        assert s["domain_points"] == pts.size
+        assert s["boundary_points"] == int(np.sum(~interior))
+        assert s["sketch_cols"] == 2 * 3 ** d == w["R"].shape[0]
+    s = L.Plan(16, 2).stats()
+    assert s["domain_points"] == 256 and s["boundary_points"] == 0 and s["sketch_cols"] == 0
+    assert L.Plan(16, 2, mask=np.ones(256, bool), sketch_cols=5).stats()["sketch_cols"] == 5
+    with pytest.raises(L.LspError):
+        L.Plan(16, 2, mask=np.zeros(256, bool))
+    with pytest.raises(L.LspError):
+        L.Plan(16, 3, mask=np.ones(16 ** 3, bool), equation="laplace")
+    with pytest.raises(L.LspError):
+        L.Plan(16, 2, mask=np.ones(256, bool), sketch_cols=5000)
+    with pytest.raises(ValueError):
+        L.Plan(16, 2, mask=np.ones(100, bool))

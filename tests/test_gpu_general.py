@@ -1,0 +1,154 @@
+"""General domains (Section 4) on the GPU against the oracle (oracle/general.py),
+same seeded inputs (cavity medium, mask, sketch R):
+
+  * boundary points, every singular value of T(mu(i), :) and the stencils
+    alpha (entrywise, where the least singular value is separated);
+  * the rows of M (interior rows of the rectangle, boundary rows alpha,
+    identity rows outside Omega);
+  * the end-to-end solve: FP64 solution within 1e-8 of the oracle's and
+    iterations within 1; the mixed path's true residual (oracle operator)
+    <= 1e-8 and its solution within 1e-6; zero outside Omega.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.general import GeneralProblem
+
+pytestmark = pytest.mark.gpu
+
+_CACHE = {}
+
+
+def _lsp():
+    import torch
+    from paper_1408_4495_amd import lsp
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lsp.load()
+    return lsp, torch
+
+
+def _oracle(key):
+    if key not in _CACHE:
+        w = synth.workload(key)
+        _CACHE[key] = (w, GeneralProblem(w["n"], w["d"], w["omega"], w["m"], w["mask"], w["R"]))
+    return _CACHE[key]
+
+
+def _gpu(key, precision="fp64", nrhs=1):
+    lsp, torch = _lsp()
+    w, _ = _oracle(key)
+    plan = lsp.Plan(w["n"], w["d"], max_nrhs=nrhs, precision=precision, mask=w["mask"])
+    pb = lsp.Problem(plan, w["omega"], w["m"], R=w["R"])
+    return lsp, torch, plan, pb
+
+
+@pytest.mark.parametrize("key", ["g1", "g1d", "g3"])
+def test_general_boundary_stencils_match_oracle(key):
+    w, g = _oracle(key)
+    lsp, torch, plan, pb = _gpu(key)
+    pts, alpha, sigma = pb.boundary_stencils()
+    assert np.array_equal(pts, g.gst.points)
+    worst_s = worst_a = 0.0
+    checked = 0
+    for k in range(pts.size):
+        sig = g.gst.sigma[k]
+        s = sig.size
+        err = np.abs(sigma[k, :s] - sig)
+        assert np.all(err <= 1e-9 * sig + 1e-13 * sig[0]), (k, sigma[k, :s], sig)
+        assert np.all(sigma[k, s:] == 0)
+        worst_s = max(worst_s, float(np.max(err / sig)))
+        sl = g.gst.slots[k]
+        off = np.setdiff1d(np.arange(alpha.shape[1]), sl)
+        assert np.all(alpha[k, off] == 0)
+        if s > 1 and (sig[-2] - sig[-1]) < 1e-6 * sig[0]:
+            continue  # nearly degenerate least singular value: alpha not unique
+        # (the computed alpha's error is about eps sigma_0 / gap)
+        ea = float(np.max(np.abs(alpha[k, sl] - g.gst.alpha[k, sl])))
+        worst_a = max(worst_a, ea)
+        assert ea <= 1e-8, (k, ea)
+        checked += 1
+    print(f"{key}: {pts.size} boundary points, alpha checked {checked}, worst sigma rel {worst_s:.2e}, "
+          f"worst alpha {worst_a:.2e}", flush=True)
+    assert checked >= pts.size // 2
+
+
+@pytest.mark.parametrize("key", ["g1", "g3"])
+def test_general_matrix_matches_oracle(key):
+    w, g = _oracle(key)
+    lsp, torch, plan, pb = _gpu(key)
+    n, d = w["n"], w["d"]
+    ns = 3 ** d
+    M = pb.matrix().cpu().numpy()
+    Mo = g.M.tocsr()
+    pos = -np.ones(n ** d, dtype=np.int64)
+    pos[g.pts] = np.arange(g.pts.size)
+    offs = np.stack([(np.arange(ns) // 3 ** a) % 3 - 1 for a in range(d)], axis=1)
+    lin = offs @ (n ** np.arange(d))
+    scale = np.abs(Mo.data).max()
+    for row, p in enumerate(g.pts):
+        ref = np.zeros(ns, dtype=np.complex128)
+        cols, vals = Mo.indices[Mo.indptr[row]:Mo.indptr[row + 1]], Mo.data[Mo.indptr[row]:Mo.indptr[row + 1]]
+        for c, v in zip(cols, vals):
+            q = int(np.nonzero(lin == g.pts[c] - p)[0][0])
+            ref[q] = v
+        assert np.max(np.abs(M[p] - ref)) <= 1e-12 * scale, (p, M[p], ref)
+    ext = np.nonzero(~w["mask"])[0]
+    ident = np.zeros(ns)
+    ident[ns // 2] = 1.0
+    assert np.all(M[ext] == ident)
+
+
+@pytest.mark.parametrize("key", ["g1", "g1d", "g3"])
+def test_general_solve_matches_oracle(key):
+    w, g = _oracle(key)
+    uI = w["uI"]
+    ref = g.solve(uI[0])
+    xo = g.to_box(ref.x)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        lsp, torch, plan, pb = _gpu(key, prec)
+        pb.factor()
+        u, info, st = pb.solve(uI)
+        assert st == 0, info
+        u = u.cpu().numpy()[0]
+        print(f"{key} {prec}: iters {info[0]['iters']} oracle {ref.iters}", flush=True)
+        assert np.all(u[~w["mask"]] == 0)
+        err = np.linalg.norm(u - xo) / np.linalg.norm(xo)
+        rr = np.linalg.norm(g.rhs(uI[0]) - g.apply(u[g.pts])) / np.linalg.norm(g.rhs(uI[0]))
+        assert info[0]["converged"] and rr <= 1e-8, (prec, rr)
+        if prec == "fp64":
+            assert err <= 1e-8, err
+            assert abs(info[0]["iters"] - ref.iters) <= 1, (info[0]["iters"], ref.iters)
+        else:
+            assert err <= 1e-6, err
+        out[prec] = u
+        del pb
+    assert np.linalg.norm(out["mixed"] - out["fp64"]) <= 1e-6 * np.linalg.norm(out["fp64"])
+
+
+def test_general_full_size_disk_matches_oracle():
+    """2D n = 256 (smoothed l2 cavity, 51k unknowns), FP64 and mixed, in the
+    benchmark's configuration, against the oracle solved here."""
+    key = "g2"
+    w, g = _oracle(key)
+    uI = w["uI"]
+    ref = g.solve(uI[0])
+    xo = g.to_box(ref.x)
+    for prec in ("fp64", "mixed"):
+        lsp, torch, plan, pb = _gpu(key, prec)
+        pts, alpha, sigma = pb.boundary_stencils()
+        assert np.array_equal(pts, g.gst.points)
+        assert np.allclose(sigma[:, 0], [s[0] for s in g.gst.sigma], rtol=1e-9)
+        pb.factor()
+        u, info, st = pb.solve(uI)
+        assert st == 0, info
+        u = u.cpu().numpy()[0]
+        err = np.linalg.norm(u - xo) / np.linalg.norm(xo)
+        print(f"{key} {prec}: iters {info[0]['iters']} oracle {ref.iters} err {err:.2e}", flush=True)
+        assert info[0]["converged"] and info[0]["relres_true"] <= 1e-8
+        if prec == "fp64":
+            assert err <= 1e-8 and abs(info[0]["iters"] - ref.iters) <= 1
+        else:
+            assert err <= 1e-6
+        del pb
