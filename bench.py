@@ -39,6 +39,10 @@ WORKLOAD_TEXT = {
           "-1.1/h^2, one delta source",
     "l3": "3D Laplace with a potential (Section 5) n=96 (N=884736), negative Gaussian potential of peak "
           "-1.1/h^2, one delta source",
+    "g2": "2D general domain (Section 4) n=256, omega=64pi, smoothed l2 cavity (disk of radius 0.45, 51k "
+          "unknowns), sketch of 18 Gaussian columns, 1 plane wave",
+    "g2d": "2D general domain (Section 4) n=256, omega=64pi, smoothed l1 cavity (diamond of radius 0.45), "
+           "sketch of 18 Gaussian columns, 1 plane wave",
 }
 
 HBM_PEAK_GBS = 8000.0
@@ -57,17 +61,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_path(lsp, torch, w, m_dev, u_dev, prec, steps, warmup):
+def make_plan(lsp, w, nrhs, prec):
+    """The workload's plan: Laplace (Section 5), a general domain (Section 4,
+    the mask), or the rectangle."""
+    lap = bool(w.get("laplace"))
+    return lsp.Plan(w["n"], w["d"], max_nrhs=nrhs, precision=prec, equation="laplace" if lap else "helmholtz",
+                    mask=w.get("mask"))
+
+
+def run_path(lsp, torch, w, m_dev, u_dev, prec, steps, warmup, R_dev=None):
     """m_dev: the medium m, or the potential V of a Laplace workload; u_dev:
-    the incident fields, or the source densities f of a Laplace workload."""
+    the incident fields, or the source densities f of a Laplace workload;
+    R_dev: a general-domain workload's sketch."""
     n, d, omega = w["n"], w["d"], w["omega"]
     nrhs = u_dev.shape[0]
     lap = bool(w.get("laplace"))
     kind = "source" if lap else "incident"
-    plan = lsp.Plan(n, d, max_nrhs=nrhs, precision=prec, equation="laplace" if lap else "helmholtz")
+    plan = make_plan(lsp, w, nrhs, prec)
 
     def step():
-        pb = lsp.Problem(plan, omega, m_dev)
+        pb = lsp.Problem(plan, omega, m_dev, R=R_dev)
         pb.factor()
         u, info, st = pb.solve(u_dev, kind=kind)
         return pb, u, info, st
@@ -91,7 +104,7 @@ def run_path(lsp, torch, w, m_dev, u_dev, prec, steps, warmup):
     if st != 0 or not all(i["converged"] for i in info):
         raise RuntimeError(f"{prec} path failed: status {st}, {info}")
     # phase split (an untimed extra step): the library's own event times
-    pb = lsp.Problem(plan, omega, m_dev)
+    pb = lsp.Problem(plan, omega, m_dev, R=R_dev)
     pb.factor()
     u2, info2, _ = pb.solve(u_dev, kind=kind)
     phases = pb.phase_ms()
@@ -199,7 +212,7 @@ def recorded_traffic(name, workload):
     return k["bytes_per_launch"], rec
 
 
-def measure_roofline(lsp, torch, w, key, m_dev, u_dev, prec):
+def measure_roofline(lsp, torch, w, key, m_dev, u_dev, prec, R_dev=None):
     """Live per-kernel timing (HIP events recorded by the library on the
     stream each kernel runs on) over one extra step; the roofline record of
     the kernel with the most time among those with a work model, the
@@ -207,13 +220,13 @@ def measure_roofline(lsp, torch, w, key, m_dev, u_dev, prec):
     n, d, omega = w["n"], w["d"], w["omega"]
     nrhs = u_dev.shape[0]
     lap = bool(w.get("laplace"))
-    plan = lsp.Plan(n, d, max_nrhs=nrhs, precision=prec, equation="laplace" if lap else "helmholtz")
+    plan = make_plan(lsp, w, nrhs, prec)
     st = plan.stats()
     torch.cuda.synchronize()
     lsp.timing_reset()
     lsp.timing_enable(True)
     try:
-        pb = lsp.Problem(plan, omega, m_dev)
+        pb = lsp.Problem(plan, omega, m_dev, R=R_dev)
         pb.factor()
         pb.solve(u_dev, kind="source" if lap else "incident")
         torch.cuda.synchronize()
@@ -319,18 +332,19 @@ def workload_record(lsp, torch, key, steps, warmup):
     lap = bool(w.get("laplace"))
     m_dev = torch.tensor(w["V"] if lap else w["m"], dtype=torch.float64, device=dev)
     u_dev = torch.tensor(w["f"] if lap else w["uI"], dtype=torch.complex128, device=dev)
+    R_dev = torch.tensor(w["R"], dtype=torch.float64, device=dev) if w.get("general") else None
     nrhs = u_dev.shape[0]
     log(f"[bench] workload {key}: {WORKLOAD_TEXT[key]}")
     res = {}
     for prec in ("fp64", "mixed"):
         log(f"[bench] {key} path {prec}: warmup {warmup}, steps {steps}")
-        res[prec] = run_path(lsp, torch, w, m_dev, u_dev, prec, steps, warmup)
+        res[prec] = run_path(lsp, torch, w, m_dev, u_dev, prec, steps, warmup, R_dev)
         r = res[prec]
         log(f"[bench] {key} {prec}: {r['ms_per_step']:.2f} ms/step, iters {r['iters']}, "
             f"phases {json.dumps({k: round(v, 2) for k, v in r['phase_ms'].items()})}")
     u64, umx = res["fp64"]["u"], res["mixed"]["u"]
     diff = float(torch.linalg.norm(umx - u64) / torch.linalg.norm(u64))
-    roof, ktable, fractions = measure_roofline(lsp, torch, w, key, m_dev, u_dev, "mixed")
+    roof, ktable, fractions = measure_roofline(lsp, torch, w, key, m_dev, u_dev, "mixed", R_dev)
     log(f"[bench] {key} kernels: {json.dumps(ktable)}")
     mx, fp = res["mixed"], res["fp64"]
     rec = {
@@ -355,7 +369,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOAD_TEXT))
-    ap.add_argument("--extra", default="c4,c2,l2", help="further workloads reported beside the headline")
+    ap.add_argument("--extra", default="c4,c2,l2,g2", help="further workloads reported beside the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
