@@ -13,7 +13,7 @@ GMRES) and the seeded input generators.  Compared here:
     strided sample of entries, and the norms), iterations within 1; the
     mixed path's true residual <= 1e-8 and its solution within 1e-6;
   * the same for Section 5's Laplace equation with a potential at 3D n = 48
-    (negative Gaussian potential, one delta source, g = K f).
+    (negative Gaussian and smoothed-ball potentials, one delta source, g = K f).
 """
 import json
 import os
@@ -143,3 +143,7 @@ def _laplace_end_to_end(key, golden):
 
 def test_3d_n48_laplace_gauss_vs_oracle():
     _laplace_end_to_end("l2", "l2_oracle.json")
+
+
+def test_3d_n48_laplace_ball_vs_oracle():
+    _laplace_end_to_end("l2b", "l2b_oracle.json")
