@@ -161,9 +161,11 @@ typedef struct {
   double fused_blocks;        /* of those, the ones not factored by a
                                  diagonal-block launch of their own: inside
                                  the previous panel's update launch
-                                 (lookahead) or by the panel-strip launches
-                                 of the upper levels (complex64); depends on
-                                 the tile table and the plan's precision */
+                                 (lookahead), by the panel-strip launches
+                                 of the upper levels (complex64), or, on the
+                                 two-panel levels, the second panel's block
+                                 by the cross-update launch; depends on the
+                                 tile table and the plan's precision */
   double fused_update_flops;  /* of update_flops, the part in update
                                  launches that also factor a block */
   double dense_entries;       /* entries of the formed dense sweep operators

@@ -791,20 +791,32 @@ __global__ void __launch_bounds__(256) gemm_update_kernel(cplx<T>* __restrict__ 
 // each tile of the trailing matrix is read and written once per two panels.
 // Fronts with no panel b take panel a's update over [k1, m)^2 in the second
 // launch.  The cross uses 32-wide tiles: grid x the tile along the strip,
-// y = 0 the column strip, y = 1 the row strip.
+// y = 0 the column strip (its diagonal block left out), y = 1 the row
+// strip, y = 2 (x = 0) the lookahead: panel a's update of panel b's
+// diagonal block and that block's factorisation, so panel b needs no
+// diagonal-block launch of its own.
 template <typename T>
 __global__ void __launch_bounds__(256) cross_update_kernel(cplx<T>* __restrict__ Fbuf,
-                                                           const FrontDev* __restrict__ fr, int first, int k0) {
-  __shared__ __align__(16) GemmLds<T, 32> G;
+                                                           const FrontDev* __restrict__ fr, int first, int k0,
+                                                           cplx<T>* __restrict__ Dinv, int* __restrict__ perm,
+                                                           double* __restrict__ pivstat) {
+  constexpr size_t kRaw =
+      sizeof(DiagLds<T>) > sizeof(GemmLds<T, 32>) ? sizeof(DiagLds<T>) : sizeof(GemmLds<T, 32>);
+  __shared__ __align__(16) unsigned char raw[kRaw];
+  GemmLds<T, 32>& G = *reinterpret_cast<GemmLds<T, 32>*>(raw);
   const FrontDev f = fr[first + blockIdx.z];
   if (f.p <= k0 + NB) return;  // no panel b: the pair update takes panel a's update
   const int k1 = k0 + NB, kbb = min(NB, f.p - k1);
   const int m = f.p + f.q;
   cplx<T>* F = Fbuf + f.f_off;
+  if (blockIdx.y == 2) {
+    if (blockIdx.x == 0) update_and_factor_next<T>(raw, f, F, k0, k1, m, Dinv, perm, pivstat);
+    return;
+  }
   const int t = blockIdx.x * 32;
   if (blockIdx.y == 0) {
     if (t >= m - k1) return;
-    update_tile<T, 32>(G, F, k0, NB, k1, m, t, 0, 0, INT_MAX, kbb);
+    update_tile<T, 32>(G, F, k0, NB, k1, m, t, 0, kbb, INT_MAX, kbb);
   } else {
     if (kbb + t >= m - k1) return;
     update_tile<T, 32>(G, F, k0, NB, k1, m, 0, kbb + t, 0, kbb, INT_MAX);
@@ -1927,7 +1939,7 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
       form_done = nullptr;
     }
     if (plan.level_mchain[l]) {
-      mchain_sweep<T>(true, mf, plan, l, nrhs, z, x, vbuf, st, xw);
+      mchain_sweep<T>(true, mf, plan, l, nrhs, z, x, vbuf, st, xw, sb.xpm);
       continue;
     }
     if constexpr (NR == 1) {
@@ -1944,9 +1956,12 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
     else if (wide_level(plan, l)) sweep_fwd<T, NR, 512>(mf, plan, l, groups, nrhs, z, vbuf, st);
     else sweep_fwd<T, NR, 256>(mf, plan, l, groups, nrhs, z, vbuf, st);
   }
+  bool point_major = false;  // xpm holds the solution of the levels above
   for (int l = plan.nlevels - 1; l >= 0; --l) {
     if (plan.level_mchain[l]) {
-      mchain_sweep<T>(false, mf, plan, l, nrhs, z, x, vbuf, st, xw);
+      if (!point_major) launch_point_major<T>(x, sb.xpm, nrhs, plan.N, st);
+      point_major = true;
+      mchain_sweep<T>(false, mf, plan, l, nrhs, z, x, vbuf, st, xw, sb.xpm);
       continue;
     }
     if constexpr (sizeof(T) == 4 && NR == 1) {
@@ -2112,8 +2127,8 @@ void mf_factor_levels(const MfDev<T>& mf, const Plan& plan, hipStream_t st, cons
                    0, st, mf.F, mf.Dinv, mf.fronts, mf.perm, first, k0);
         if (k0 + NB < maxp) {  // some front has a panel b
           LSP_LAUNCH("cross_update", (int)sizeof(cplx<T>), cross_update_kernel<T>,
-                     dim3((maxm - k0 - NB + 31) / 32, 2, cnt), dim3(256), 0, st, mf.F, mf.fronts, first, k0);
-          diag_launch(mf, cnt, first, k0 + NB, st);
+                     dim3((maxm - k0 - NB + 31) / 32, 3, cnt), dim3(256), 0, st, mf.F, mf.fronts, first, k0, mf.Dinv,
+                     mf.perm, mf.pivstat);
           const int rem2 = maxm - k0 - NB - 1;
           if (rem2 > 0)
             LSP_LAUNCH("panel_trsm", (int)sizeof(cplx<T>), panel_trsm_kernel<T>, dim3((rem2 + 63) / 64, cnt, 2),
@@ -2180,6 +2195,7 @@ FactorSchedule factor_schedule(const Plan& plan, bool fp64) {
           if (f.p > k0 + NB) {
             const int kbb = std::min(NB, f.p - k0 - NB);
             s.cross_update_flops += 8.0 * NB * kbb * (2.0 * (m - k0 - NB) - kbb);
+            s.fused_blocks += 1.0;  // panel b's block, factored by the cross launch
           }
         }
       }

@@ -104,6 +104,8 @@ struct SweepBufs {
   cplx<T>* ybuf;
   cplx<T>* pbuf;
   long long ystride;
+  cplx<T>* xpm;  // the solution point-major for the matrix-core levels'
+                 // gathers: [groups of 16 right-hand sides][N][16]
 };
 
 // Second stream for the dense levels' operator formation: each level's
@@ -154,7 +156,11 @@ void blocked_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nr
 // Same inputs and outputs as the panel-chain sweeps of that level.
 template <typename T>
 void mchain_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
-                  cplx<T>* vbuf, hipStream_t st, double2* xw);
+                  cplx<T>* vbuf, hipStream_t st, double2* xw, cplx<T>* xpm);
+// xpm[g][i][k] = x[16 g + k][i] (zero for k beyond nrhs): the backward
+// sweep's solution so far, point-major, before the matrix-core levels.
+template <typename T>
+void launch_point_major(const cplx<T>* x, cplx<T>* xpm, int nrhs, long long N, hipStream_t st);
 // Forms the super-block operators of blocked level l from its factor (the
 // panel chains on the unit vectors), into mf.G at each front's g_off.
 template <typename T>

@@ -240,6 +240,7 @@ struct SolvePtrs {
   void* xs;       // M^{-1} output [nrhs][N]
   void* ybuf;     // blocked sweeps: super-block outputs [nrhs][bsweep_ystride]
   void* pbuf;     // blocked sweeps: boundary partial sums [chunks][nrhs][bsweep_ystride]
+  void* xpm;      // matrix-core levels: the solution point-major, [ceil(nrhs/16)][N][16]
   double2* V;     // [restart+1][nrhs][N]
   double2* Z;     // [restart][nrhs][N]
   double2* w;     // [nrhs][N]
@@ -273,6 +274,7 @@ size_t layout_solve(const Plan& P, int nrhs, int restart, bool krylov, void* bas
   s.xs = cv.take<double2>((size_t)nrhs * N);
   s.ybuf = cv.take<double2>((size_t)nrhs * P.bsweep_ystride);
   s.pbuf = cv.take<double2>((size_t)P.bsweep_chunks * nrhs * P.bsweep_ystride);
+  s.xpm = cv.take<double2>(P.mchain_levels ? (size_t)((nrhs + 15) / 16) * 16 * N : 1);
   if (krylov) {
     s.V = cv.take<double2>((size_t)(restart + 1) * nrhs * N);
     s.Z = cv.take<double2>((size_t)restart * nrhs * N);
@@ -740,14 +742,14 @@ void apply_precond(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2*
     apply_Q<double2>(pb, (double2*)s.zq, v, nrhs);
     MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                      pb->d.pivstat, (double2*)pb->d.Gop};
-    const SweepBufs<double> sb{(double2*)s.ybuf, (double2*)s.pbuf, P.bsweep_ystride};
+    const SweepBufs<double> sb{(double2*)s.ybuf, (double2*)s.pbuf, P.bsweep_ystride, (double2*)s.xpm};
     mf_solve<double>(mf, P, nrhs, (const double2*)s.zq, out, (double2*)s.vbuf, sb, st, pb->take_form_wait(), nullptr);
   } else {
     apply_Q<float2>(pb, (float2*)s.zq, v, nrhs);
     MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                     pb->d.pivstat, (float2*)pb->d.Gop};
     // the backward sweeps also store the solution widened into out
-    const SweepBufs<float> sb{(float2*)s.ybuf, (float2*)s.pbuf, P.bsweep_ystride};
+    const SweepBufs<float> sb{(float2*)s.ybuf, (float2*)s.pbuf, P.bsweep_ystride, (float2*)s.xpm};
     mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, sb, st, pb->take_form_wait(), out);
   }
 }
@@ -758,13 +760,13 @@ void solve_M(lsp_problem* pb, const SolvePtrs& s, int nrhs, const double2* z, do
   if (pb->precision == LSP_FP64) {
     MfDev<double> mf{(double2*)pb->d.F, (double2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                      pb->d.pivstat, (double2*)pb->d.Gop};
-    const SweepBufs<double> sb{(double2*)s.ybuf, (double2*)s.pbuf, P.bsweep_ystride};
+    const SweepBufs<double> sb{(double2*)s.ybuf, (double2*)s.pbuf, P.bsweep_ystride, (double2*)s.xpm};
     mf_solve<double>(mf, P, nrhs, z, x, (double2*)s.vbuf, sb, st, pb->take_form_wait(), nullptr);
   } else {
     launch_narrow((float2*)s.zq, z, (long long)nrhs * P.N, st);
     MfDev<float> mf{(float2*)pb->d.F, (float2*)pb->d.Dinv, pb->d.fronts, pb->d.idx, pb->d.gpos, pb->d.cpos, pb->d.Mval, pb->d.perm,
                     pb->d.pivstat, (float2*)pb->d.Gop};
-    const SweepBufs<float> sb{(float2*)s.ybuf, (float2*)s.pbuf, P.bsweep_ystride};
+    const SweepBufs<float> sb{(float2*)s.ybuf, (float2*)s.pbuf, P.bsweep_ystride, (float2*)s.xpm};
     mf_solve<float>(mf, P, nrhs, (const float2*)s.zq, (float2*)s.xs, (float2*)s.vbuf, sb, st, pb->take_form_wait(), x);
   }
 }

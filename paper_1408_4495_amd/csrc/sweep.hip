@@ -689,6 +689,12 @@ __global__ void __launch_bounds__(64 * W) mchain_fwd_kernel(const cplx<T>* __res
   }
 }
 
+// The backward sweep gathers the boundary rows' solution from the point-
+// major copy xpm (a grid point's 16 right-hand sides in one 128-byte line,
+// where the [nrhs][N] layout spreads them over 16 lines) and stores its
+// pivots' solution there for the levels below, into xw when given (the
+// widened solution, mixed path) and into x unless store_x is 0 (x is not
+// needed when xw is the output and every level below is a matrix-core one).
 template <typename T, int W>
 __global__ void __launch_bounds__(64 * W) mchain_bwd_kernel(const cplx<T>* __restrict__ Fbuf,
                                                             const cplx<T>* __restrict__ Dinv,
@@ -696,7 +702,8 @@ __global__ void __launch_bounds__(64 * W) mchain_bwd_kernel(const cplx<T>* __res
                                                             const int* __restrict__ idx, cplx<T>* __restrict__ x,
                                                             const cplx<T>* __restrict__ vbuf, int first, int nrhs,
                                                             long long N, long long vstride,
-                                                            double2* __restrict__ xw, int maxm) {
+                                                            double2* __restrict__ xw, int maxm,
+                                                            cplx<T>* __restrict__ xpm, int store_x) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* V = reinterpret_cast<cplx<T>*>(smem_raw);  // V[r * MC + k]
   cplx<T>* part = V + (long long)maxm * MC;           // part[(w - 1) * 2 + h][64 lanes][4]: waves 1.. partial sums
@@ -714,9 +721,9 @@ __global__ void __launch_bounds__(64 * W) mchain_bwd_kernel(const cplx<T>* __res
 #pragma unroll
       for (int k = 0; k < MC; ++k) val[k] = vbuf[(long long)(r0 + min(k, nr - 1)) * vstride + f.idx_off + r];
     } else {
-      const long long gi = id[r];
+      const cplx<T>* src = xpm + ((long long)blockIdx.y * N + id[r]) * MC;
 #pragma unroll
-      for (int k = 0; k < MC; ++k) val[k] = x[(long long)(r0 + min(k, nr - 1)) * N + gi];
+      for (int k = 0; k < MC; ++k) val[k] = src[k];
     }
 #pragma unroll
     for (int k = 0; k < MC; ++k) V[r * MC + k] = k < nr ? val[k] : mk<T>(0, 0);
@@ -808,13 +815,34 @@ __global__ void __launch_bounds__(64 * W) mchain_bwd_kernel(const cplx<T>* __res
     }
   }
   __syncthreads();
+  for (int e = tid; e < p * MC; e += 64 * W) {
+    const int r = e / MC, k = e % MC;
+    xpm[((long long)blockIdx.y * N + id[r]) * MC + k] = V[r * MC + k];
+  }
   for (int e = tid; e < p * nr; e += 64 * W) {
     const int r = e % p, k = e / p;
     const cplx<T> v = V[r * MC + k];
     const long long gi = (long long)(r0 + k) * N + id[r];
-    x[gi] = v;
     if (xw) xw[gi] = widen(v);
+    if (store_x) x[gi] = v;
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) point_major_kernel(const cplx<T>* __restrict__ x, cplx<T>* __restrict__ xpm,
+                                                          int nrhs, long long N) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const int g = blockIdx.y, nr = min(MC, nrhs - g * MC);
+  cplx<T> v[MC];
+#pragma unroll
+  for (int k = 0; k < MC; ++k) {
+    const cplx<T> a = x[(long long)(g * MC + min(k, nr - 1)) * N + i];
+    v[k] = k < nr ? a : mk<T>(0, 0);
+  }
+  cplx<T>* dst = xpm + ((long long)g * N + i) * MC;
+#pragma unroll
+  for (int k = 0; k < MC; ++k) dst[k] = v[k];
 }
 
 }  // namespace
@@ -831,7 +859,10 @@ inline int mchain_waves(int cnt) { return cnt >= 4096 ? 1 : (cnt >= 2048 ? 2 : 4
 
 template <typename T, int W>
 void mchain_launch(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
-                   cplx<T>* vbuf, hipStream_t st, double2* xw) {
+                   cplx<T>* vbuf, hipStream_t st, double2* xw, cplx<T>* xpm) {
+  bool below = true;  // every level below l is a matrix-core one
+  for (int k = 0; k < l; ++k) below = below && plan.level_mchain[k];
+  const int store_x = xw == nullptr || !below;
   const int first = plan.level_ptr[l];
   const int cnt = plan.level_ptr[l + 1] - first;
   const int maxm = plan.level_maxpq[l];
@@ -845,18 +876,24 @@ void mchain_launch(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nr
     const size_t plds = (size_t)(W - 1) * 2 * 64 * 4 * sizeof(cplx<T>);
     LSP_LAUNCH("bwd_mchain", (int)sizeof(cplx<T>), (mchain_bwd_kernel<T, W>), grid, dim3(64 * W), vlds + plds, st,
                mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq, xw,
-               maxm);
+               maxm, xpm, store_x);
   }
 }
 
 template <typename T>
 void mchain_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
-                  cplx<T>* vbuf, hipStream_t st, double2* xw) {
+                  cplx<T>* vbuf, hipStream_t st, double2* xw, cplx<T>* xpm) {
   LSP_REQUIRE(plan.level_maxp[l] <= MCP && plan.level_maxpq[l] <= MCM, "matrix-core chain level exceeds its bounds");
   const int W = mchain_waves(plan.level_ptr[l + 1] - plan.level_ptr[l]);
-  if (W == 1) mchain_launch<T, 1>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
-  else if (W == 2) mchain_launch<T, 2>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
-  else mchain_launch<T, 4>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw);
+  if (W == 1) mchain_launch<T, 1>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw, xpm);
+  else if (W == 2) mchain_launch<T, 2>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw, xpm);
+  else mchain_launch<T, 4>(fwd, mf, plan, l, nrhs, z, x, vbuf, st, xw, xpm);
+}
+
+template <typename T>
+void launch_point_major(const cplx<T>* x, cplx<T>* xpm, int nrhs, long long N, hipStream_t st) {
+  LSP_LAUNCH("point_major", (int)sizeof(cplx<T>), point_major_kernel<T>,
+             dim3((unsigned)((N + 255) / 256), (unsigned)((nrhs + MC - 1) / MC)), dim3(256), 0, st, x, xpm, nrhs, N);
 }
 
 template <typename T>
@@ -876,9 +913,11 @@ template void blocked_sweep<double>(bool, const MfDev<double>&, const Plan&, int
 template void blocked_sweep<float>(bool, const MfDev<float>&, const Plan&, int, int, const float2*, float2*, float2*,
                                    const SweepBufs<float>&, hipStream_t, double2*);
 template void mchain_sweep<double>(bool, const MfDev<double>&, const Plan&, int, int, const double2*, double2*,
-                                   double2*, hipStream_t, double2*);
+                                   double2*, hipStream_t, double2*, double2*);
 template void mchain_sweep<float>(bool, const MfDev<float>&, const Plan&, int, int, const float2*, float2*, float2*,
-                                  hipStream_t, double2*);
+                                  hipStream_t, double2*, float2*);
+template void launch_point_major<double>(const double2*, double2*, int, long long, hipStream_t);
+template void launch_point_major<float>(const float2*, float2*, int, long long, hipStream_t);
 template void blocked_form<double>(const MfDev<double>&, const Plan&, int, hipStream_t);
 template void blocked_form<float>(const MfDev<float>&, const Plan&, int, hipStream_t);
 
