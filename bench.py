@@ -271,6 +271,57 @@ def measure_roofline(lsp, torch, w, key, m_dev, u_dev, prec, R_dev=None):
     return roof, table, fractions
 
 
+# ---- the field away from the grid (Section 1)
+def field_record(lsp, torch, key, reps=5, npts=360):
+    """Exterior field at npts receivers on a circle / sphere of radius 1.5
+    around the domain and the far-field pattern at npts directions, from
+    the mixed-precision solution of the workload's block (all right-hand
+    sides).  Work: one complex multiply-add (8 real flops) per receiver,
+    grid point with m != 0 and right-hand side (the grid points with m = 0
+    are skipped by the kernel); ALU-bound (FP64 vector, 78.6 TF/s), the
+    Green's function evaluation per receiver and grid point on top."""
+    import synth
+    w = synth.workload(key)
+    n, d, omega = w["n"], w["d"], w["omega"]
+    dev = torch.device("cuda:0")
+    m_dev = torch.tensor(w["m"], dtype=torch.float64, device=dev)
+    u_dev = torch.tensor(w["uI"], dtype=torch.complex128, device=dev)
+    nrhs = u_dev.shape[0]
+    plan = make_plan(lsp, w, nrhs, "mixed")
+    R_dev = torch.tensor(w["R"], dtype=torch.float64, device=dev) if w.get("general") else None
+    pb = lsp.Problem(plan, omega, m_dev, R=R_dev)
+    pb.factor()
+    u, _, _ = pb.solve(u_dev)
+    if d == 2:
+        th = 2 * np.pi * np.arange(npts) / npts
+        dirs = np.stack([np.cos(th), np.sin(th)], axis=1)
+    else:
+        dirs = synth.directions_fibonacci(npts)
+    pts = torch.tensor(0.5 + 1.5 * dirs, dtype=torch.float64, device=dev)
+    dirs_t = torch.tensor(dirs, dtype=torch.float64, device=dev)
+    nnz = int(np.count_nonzero(w["m"]))
+    out = {"workload": WORKLOAD_TEXT.get(key, key), "points": npts, "nrhs": nrhs, "grid_points_with_m": nnz}
+    for name, fn, arg in (("exterior", pb.exterior_field, pts), ("far_field", pb.far_field, dirs_t)):
+        fn(u, u_dev, arg)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn(u, u_dev, arg)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        flops = 8.0 * npts * nnz * nrhs
+        out[name] = {"ms": ms, "pairs_per_s": npts * nnz / (ms * 1e-3),
+                     "roofline": {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": 78.6,
+                                  "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / 78.6}}
+        log(f"[bench] {key} {name}: {ms:.3f} ms for {npts} x {nnz} x {nrhs}, "
+            f"{out[name]['roofline']['achieved']:.2f} TF/s of multiply-adds")
+    del pb
+    torch.cuda.empty_cache()
+    return out
+
+
 # ---- serving
 
 def serving(torch, count=200, warm=20, rhos=(0.5, 0.8), slots=4):
@@ -390,6 +441,9 @@ def main():
     extra = {}
     for key in [k for k in args.extra.split(",") if k and k != args.workload]:
         extra[key], _ = workload_record(lsp, torch, key, min(args.steps, 3), 1)
+    log("[bench] field away from the grid")
+    # (the headline workload's medium; the Laplace workloads have no incident field)
+    field = field_record(lsp, torch, "c3" if args.workload.startswith("l") else args.workload)
     serve_rec = None
     if not args.no_serving:
         log("[bench] serving loop")
@@ -423,6 +477,7 @@ def main():
         "kernel_fractions": head["kernel_fractions"],
         "serving": serve_rec,
         "workloads": extra,
+        "field": field,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
