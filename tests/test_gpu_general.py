@@ -152,3 +152,64 @@ def test_general_full_size_disk_matches_oracle():
         else:
             assert err <= 1e-6
         del pb
+
+
+def _star_mask(n, d, seed, holes=0.06):
+    """A star-shaped Omega with a ragged boundary (radius 0.32 plus five
+    seeded harmonics) and seeded one-point holes near its centre."""
+    X = synth.grid_coords(n, d) - 0.5
+    th, rr = np.arctan2(X[:, 1], X[:, 0]), np.hypot(X[:, 0], X[:, 1])
+    rng = np.random.default_rng([14084495, seed])
+    a, ph = rng.uniform(-0.08, 0.08, 5), rng.uniform(0, 2 * np.pi, 5)
+    rad = 0.32 + sum(a[k] * np.cos((k + 2) * th + ph[k]) for k in range(5))
+    return (rr <= rad) & ~((rng.random(n ** d) < holes) & (rr < 0.2))
+
+
+def test_general_ragged_mask():
+    """A non-convex Omega (ragged star-shaped boundary, one-point holes):
+    boundary stencils and the FP64 solve against the oracle (the section
+    notes the preconditioner weakens on non-convex domains: more
+    iterations, same solution)."""
+    lsp, torch = _lsp()
+    n, d = 24, 2
+    mask = _star_mask(n, d, 31)
+    omega = 2 * np.pi * 3
+    m = np.where(mask, -0.3 * synth.medium_single_bump(n, d, 1.0, 0.25), 0.0)
+    R = synth.sketch_matrix(n, d, 18, 32)
+    g = GeneralProblem(n, d, omega, m, mask, R)
+    plan = lsp.Plan(n, d, tol=1e-10, mask=mask)
+    pb = lsp.Problem(plan, omega, m, R=R)
+    pts, alpha, sigma = pb.boundary_stencils()
+    assert np.array_equal(pts, g.gst.points)
+    for k in range(pts.size):
+        sig = g.gst.sigma[k]
+        assert np.all(np.abs(sigma[k, :sig.size] - sig) <= 1e-9 * sig + 1e-13 * sig[0]), k
+        if (sig[-2] - sig[-1]) >= 1e-6 * sig[0]:
+            assert np.max(np.abs(alpha[k, :3 ** d] - g.gst.alpha[k])) <= 1e-8, k
+    uI = synth.plane_waves(n, d, omega, [[0.0, -1.0]])
+    ref = g.solve(uI[0], tol=1e-10)
+    pb.factor()
+    u, info, st = pb.solve(uI)
+    assert st == 0 and ref.converged
+    u = u.cpu().numpy()[0]
+    xo = g.to_box(ref.x)
+    assert np.all(u[~mask] == 0)
+    assert np.linalg.norm(u - xo) <= 1e-8 * np.linalg.norm(xo)
+    assert abs(info[0]["iters"] - ref.iters) <= 1, (info[0]["iters"], ref.iters)
+
+
+def test_general_isolated_cluster_is_singular():
+    """Points of a 2 x 2 cluster cut off from the rest of Omega all have the
+    same neighbourhood mu (the cluster), so Section 4's rows for them are
+    parallel and M is singular: the factorisation reports it."""
+    lsp, torch = _lsp()
+    n, d = 24, 2
+    mask = synth.domain_mask(n, d, "l2", radius=0.25).reshape(n, n).copy()
+    mask[1:3, 20:22] = True  # rows i2, columns i1: far from the disk
+    mask = mask.reshape(-1)
+    m = np.where(mask, -0.3 * synth.medium_single_bump(n, d, 1.0, 0.25), 0.0)
+    plan = lsp.Plan(n, d, mask=mask)
+    pb = lsp.Problem(plan, 2 * np.pi * 3, m, R=synth.sketch_matrix(n, d, 18, 33))
+    with pytest.raises(lsp.LspError) as e:
+        pb.factor()
+    assert e.value.status == 5  # LSP_ERR_SINGULAR
