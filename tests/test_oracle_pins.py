@@ -13,7 +13,7 @@ import scipy.sparse.linalg as spla
 
 import synth
 from oracle.greens import kernel_table, self_term, self_radius, green
-from oracle.operator import (dense_K, apply_K_direct, apply_K_fft, Operator, grid_index)
+from oracle.operator import (dense_K, apply_K_direct, apply_K_fft, Operator, grid_index, embedded_kernel)
 from oracle.stencil import (all_stencils, class_offsets, far_set, kernel_block,
                             class_tuple, interior_class, point_class, slot)
 from oracle.sparse import build_QM, Preconditioner
@@ -525,3 +525,56 @@ def test_laplace_rejects_2d():
     from oracle.greens import green
     with pytest.raises(ValueError):
         green(np.array([0.1]), 0.0, 2)
+
+
+# ---------------------------------------------------------------- fitted self term (self_term 2)
+@pytest.mark.parametrize("d,ns,order", [(2, (64, 128, 256), 3.6), (3, (64, 96), 3.4)])
+def test_fitted_self_term_is_fourth_order(d, ns, order):
+    """Section 2.1's one-point correction is of order h^4 log(1/h): with
+    the fitted k_0 the discrete K reproduces the continuous identity
+    G * ((-Lap - w^2) phi) = phi at (nearly) fourth order, where the
+    disk / ball term gives second."""
+    omega, s = 2 * np.pi * 4, 0.07
+    errs, errs0 = [], []
+    for n in ns:
+        X = synth.grid_coords(n, d)
+        r2 = np.sum((X - 0.5) ** 2, axis=1)
+        phi = np.exp(-r2 / (2 * s * s))
+        f = (-phi * (r2 / s ** 4 - d / s ** 2) - omega ** 2 * phi).astype(np.complex128)
+        for mode, out in ((2, errs), (0, errs0)):
+            kt = kernel_table(n, d, omega, mode)
+            y = apply_K_fft(f, n, d, omega, np.fft.fftn(embedded_kernel(n, d, omega, kt)))
+            out.append(np.max(np.abs(y - phi)) / np.max(np.abs(phi)))
+    for k in range(len(ns) - 1):
+        p = np.log(errs[k] / errs[k + 1]) / np.log(ns[k + 1] / ns[k])
+        p0 = np.log(errs0[k] / errs0[k + 1]) / np.log(ns[k + 1] / ns[k])
+        assert p > order and p0 < 3.0, (errs, errs0)
+    assert errs[-1] < errs0[-1] / 10
+
+
+@pytest.mark.parametrize("d,n,omega", [(2, 64, 8 * np.pi), (2, 512, 128 * np.pi), (3, 32, 8 * np.pi)])
+def test_fitted_self_term_imaginary_part_is_trapezoidal(d, n, omega):
+    """Im G is smooth (J0 / 4 in 2D, sin(w r) / (4 pi r) in 3D), so the
+    trapezoid rule alone is spectrally exact on Im(G g) and the fitted
+    correction's imaginary part is exactly the plain rule's value at the
+    origin: h^2 / 4 (2D), h^3 w / (4 pi) (3D)."""
+    h = 1.0 / n
+    k0 = self_term(h, omega, d, 2)
+    ref = h * h / 4 if d == 2 else h ** 3 * omega / (4 * np.pi)
+    assert abs(k0.imag - ref) <= 1e-12 * ref
+
+
+def test_fitted_self_term_does_not_depend_on_the_probe():
+    """The fitted k_0 is the local correction, not a property of the probe:
+    two probe widths agree up to a term that falls like h^4 (k_0 itself is
+    of order h^2 log(1/h); the difference is checked to fall at least
+    twelvefold per halving of h, and to stay below 1 % of k_0)."""
+    from oracle.greens import fitted_self_term
+    omega = 8 * np.pi
+    diffs = []
+    for n in (64, 128, 256):
+        a = fitted_self_term(1.0 / n, omega, 2, 0.05)
+        b = fitted_self_term(1.0 / n, omega, 2, 0.08)
+        diffs.append(abs(a - b))
+        assert abs(a - b) < 1e-2 * abs(b)
+    assert diffs[1] < diffs[0] / 12 and diffs[2] < diffs[1] / 12, diffs
