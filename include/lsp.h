@@ -117,7 +117,11 @@ typedef struct {
                         ball (3D) of one cell's area / volume; 1: the
                         integral of G over the grid cell itself (square /
                         cube of side h), by Gauss-Legendre quadrature of
-                        its closed-form radial integral */
+                        its closed-form radial integral; 2: the one-point
+                        correction of the trapezoid rule (fourth order)
+                        fitted so that the corrected rule integrates G
+                        times a unit Gaussian of width max(0.05, 3h)
+                        exactly (lsp_self_term) */
   int equation;      /* lsp_equation (LSP_HELMHOLTZ); LSP_LAPLACE needs d = 3 */
   const char* tile_cache; /* NULL (default), or a text file of tuned
                         trailing-update tile tables, one line per
@@ -416,6 +420,16 @@ lsp_status lsp_get_matrix(lsp_problem* problem, void* mval_dev);
  * used as is.  Only enqueues device work.  Errors: LSP_ERR_ARG (null
  * pointers, counts < 1, Laplace problems, small workspace), LSP_ERR_HIP. */
 lsp_status lsp_field_bytes(const lsp_plan* plan, int npts, size_t* bytes);
+
+/* The kernel table's self term k_0 (Section 2.1) for grid step h,
+ * frequency omega (0: the 3D Laplace kernel) and mode (lsp_options.
+ * self_term): mode 2 is k_0 = int G g dx - sum_{t != 0} h^d G(h t) g(h t)
+ * for g(x) = exp(-|x|^2 / (2 sigma^2)), sigma = max(0.05, 3h) (the integral
+ * in closed form, the lattice sum over 0 < |t| h <= 12 sigma; cached per
+ * (h, omega, d) since it takes up to a second at large n).  Host-only
+ * computation; k0[0], k0[1] receive the real and imaginary parts.  Errors:
+ * LSP_ERR_ARG. */
+lsp_status lsp_self_term(double h, double omega, int d, int mode, double* k0);
 lsp_status lsp_exterior_field(lsp_problem* problem, int nrhs, const void* u_dev, const void* uI_dev,
                               int npts, const double* points_dev, void* out_dev, void* ws_dev,
                               size_t ws_bytes);

@@ -105,9 +105,12 @@ def gaussian_integral(omega, d, sigma):
     F Dawson's integral; a = 1 / (2 sigma^2)."""
     a = 0.5 / (sigma * sigma)
     if d == 2:
+        import mpmath
         x = omega * omega / (4.0 * a)
+        with mpmath.workdps(40):  # e^{-x} Ei(x) without overflow for large x
+            ex = float(mpmath.exp(-mpmath.mpf(x)) * mpmath.ei(mpmath.mpf(x)))
         J = np.exp(-x) / (2.0 * a)
-        Y = np.exp(-x) * sp.expi(x) / (2.0 * np.pi * a)
+        Y = ex / (2.0 * np.pi * a)
         return complex(-0.5 * np.pi * Y, 0.5 * np.pi * J)  # 2 pi (i/4) (J + i Y)
     z = omega / (2.0 * np.sqrt(a))
     I0 = np.sqrt(np.pi) / (2.0 * np.sqrt(a)) * np.exp(-z * z) + 1j * sp.dawsn(z) / np.sqrt(a)

@@ -20,6 +20,7 @@
 #include "krylov.h"
 #include <map>
 #include <mutex>
+#include <tuple>
 
 #include "lsp_common.h"
 #include "plan.h"
@@ -626,9 +627,113 @@ double2 cell_self_term(double h, double omega, int d) {
   return make_double2(24.0 * re, 24.0 * im);
 }
 
+// e^{-x} Ei(x), x > 0: the series gamma + ln x + sum_{k>=1} x^k / (k k!)
+// (A&S 5.1.10; every term positive) up to x = 50, beyond it the asymptotic
+// series sum_k k! / x^{k+1} (A&S 5.1.51) to its smallest term.
+double expei(double x) {
+  if (x <= 50.0) {
+    double term = 1.0, sum = 0.0;
+    for (int k = 1; k < 500; ++k) {
+      term *= x / k;  // x^k / k!
+      const double add = term / k;
+      sum += add;
+      if (add < 1e-18 * sum) break;
+    }
+    return std::exp(-x) * (0.57721566490153286061 + std::log(x) + sum);
+  }
+  double term = 1.0 / x, sum = term;
+  for (int k = 1; k < 400; ++k) {
+    const double next = term * k / x;
+    if (next >= term || next < 1e-18 * sum) break;
+    term = next;
+    sum += term;
+  }
+  return sum;
+}
+
+// Dawson's integral F(z) = e^{-z^2} int_0^z e^{t^2} dt = int_0^z e^{-u (2z - u)} du
+// (t = z - u), by Gauss-Legendre on 8 panels of [0, min(z, 40 / z)]
+// (beyond, the integrand is below e^{-40}).
+double dawson(double z) {
+  if (z <= 0.0) return 0.0;
+  std::vector<double> x, w;
+  gauss_legendre01(32, x, w);
+  const double U = std::min(z, 40.0 / z), panel = U / 8.0;
+  double sum = 0.0;
+  for (int p = 0; p < 8; ++p)
+    for (size_t i = 0; i < x.size(); ++i) {
+      const double u = panel * (p + x[i]);
+      sum += w[i] * std::exp(-u * (2.0 * z - u));
+    }
+  return sum * panel;
+}
+
+// k_0 as a one-point correction of the trapezoid rule fitted to a unit
+// Gaussian probe g of width sigma = max(0.05, 3h): k_0 = int G g - sum_{t != 0}
+// h^d G(h t) g(h t), so the corrected rule integrates G g exactly; the
+// integral in closed form (2D: Re = -sigma^2 e^{-x} Ei(x) / 2, Im = (pi/2)
+// sigma^2 e^{-x}, x = w^2 sigma^2 / 2; 3D: Re = sigma^2 - sqrt(2) w sigma^3
+// F(z), Im = sqrt(pi/2) w sigma^3 e^{-z^2}, z = w sigma / sqrt(2)), the
+// lattice sum over 0 < |t| h <= 12 sigma, one representative per class of
+// signed permutations, times the class size.  Cached per (h, w, d).
+double2 fitted_self_term(double h, double omega, int d) {
+  static std::mutex mu;
+  static std::map<std::tuple<double, double, int>, double2> cache;
+  const auto key = std::make_tuple(h, omega, d);
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  const double pi = 3.14159265358979323846;
+  const double sigma = std::max(0.05, 3.0 * h), a = 0.5 / (sigma * sigma), R = 12.0 * sigma;
+  const double s2 = sigma * sigma;
+  double ire, iim;
+  if (d == 2) {
+    const double x = 0.5 * omega * omega * s2;
+    ire = -0.5 * s2 * expei(x);
+    iim = 0.5 * pi * s2 * std::exp(-x);
+  } else {
+    const double z = omega * sigma / std::sqrt(2.0);
+    ire = s2 - std::sqrt(2.0) * omega * s2 * sigma * dawson(z);
+    iim = std::sqrt(0.5 * pi) * omega * s2 * sigma * std::exp(-z * z);
+  }
+  const int m = (int)std::floor(R / h);
+  double sre = 0.0, sim = 0.0;
+  for (int t1 = 1; t1 <= m; ++t1)
+    for (int t2 = 0; t2 <= t1; ++t2)
+      for (int t3 = 0; t3 <= (d == 3 ? t2 : 0); ++t3) {
+        const double r = h * std::sqrt((double)t1 * t1 + (double)t2 * t2 + (double)t3 * t3);
+        if (r > R) continue;
+        double mult;
+        if (d == 2) {
+          mult = (t2 == 0 || t2 == t1) ? 4.0 : 8.0;
+        } else {
+          const int perms = (t1 == t2 && t2 == t3) ? 1 : ((t1 == t2 || t2 == t3) ? 3 : 6);
+          mult = perms * (double)(1 << (1 + (t2 > 0) + (t3 > 0)));
+        }
+        const double gw = mult * std::exp(-a * r * r);
+        if (d == 2) {  // G = (i/4)(J0 + i Y0)
+          const double z = omega * r;
+          sre += gw * (-0.25 * std::cyl_neumann(0.0, z));
+          sim += gw * (0.25 * std::cyl_bessel_j(0.0, z));
+        } else {
+          const double c = std::cos(omega * r), sn = std::sin(omega * r), inv = 1.0 / (4.0 * pi * r);
+          sre += gw * c * inv;
+          sim += gw * sn * inv;
+        }
+      }
+  const double hd = d == 2 ? h * h : h * h * h;
+  const double2 k0 = make_double2(ire - hd * sre, iim - hd * sim);
+  std::lock_guard<std::mutex> lock(mu);
+  cache[key] = k0;
+  return k0;
+}
+
 double2 self_term_host(double h, double omega, int d, int mode) {
   const double pi = 3.14159265358979323846;
   if (mode == 1) return cell_self_term(h, omega, d);
+  if (mode == 2) return fitted_self_term(h, omega, d);
   if (d == 2) {
     double rho = h / std::sqrt(pi);
     double z = omega * rho;
@@ -843,7 +948,7 @@ static lsp_status plan_create_impl(int n, int d, int max_nrhs, const lsp_options
     LSP_REQUIRE(o.panel == 0 || o.panel == kNbMax, "panel must be 0 (auto) or 32");
     LSP_REQUIRE(o.dense_sweeps >= 0 && o.dense_sweeps <= 2, "dense_sweeps must be 0, 1 or 2");
     LSP_REQUIRE(o.blocked_sweeps >= 0 && o.blocked_sweeps <= 2, "blocked_sweeps must be 0, 1 or 2");
-    LSP_REQUIRE(o.self_term == 0 || o.self_term == 1, "self_term must be 0 or 1");
+    LSP_REQUIRE(o.self_term >= 0 && o.self_term <= 2, "self_term must be 0, 1 or 2");
     LSP_REQUIRE(o.equation == LSP_HELMHOLTZ || o.equation == LSP_LAPLACE, "unknown equation");
     LSP_REQUIRE(o.equation == LSP_HELMHOLTZ || d == 3, "the Laplace equation is three-dimensional (d must be 3)");
     const std::string cache = o.tile_cache ? o.tile_cache : "";
@@ -1060,6 +1165,20 @@ lsp_status lsp_setup_general(const lsp_plan* plan, double omega, const double* m
                              void* ws_dev, size_t ws_bytes, void* stream, lsp_problem** out) {
   if (!R_dev) return fail(LSP_ERR_ARG, "null sketch matrix");
   return setup_impl(plan, omega, m_dev, R_dev, ws_dev, ws_bytes, stream, out);
+}
+
+lsp_status lsp_self_term(double h, double omega, int d, int mode, double* k0) {
+  return guarded([&]() -> lsp_status {
+    LSP_REQUIRE(k0 != nullptr, "null output");
+    LSP_REQUIRE(d == 2 || d == 3, "d must be 2 or 3");
+    LSP_REQUIRE(mode >= 0 && mode <= 2, "self_term must be 0, 1 or 2");
+    LSP_REQUIRE(h > 0 && std::isfinite(h) && omega >= 0 && std::isfinite(omega), "invalid h or omega");
+    LSP_REQUIRE(d == 3 || omega > 0, "omega = 0 (the Laplace kernel) is three-dimensional");
+    const double2 v = self_term_host(h, omega, d, mode);
+    k0[0] = v.x;
+    k0[1] = v.y;
+    return LSP_OK;
+  });
 }
 
 lsp_status lsp_field_bytes(const lsp_plan* plan, int npts, size_t* bytes) {

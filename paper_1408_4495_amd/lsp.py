@@ -26,7 +26,7 @@ EXPORTED = ["lsp_options_default", "lsp_plan_create", "lsp_plan_destroy", "lsp_p
             "lsp_last_error", "lsp_timing_enable", "lsp_timing_reset", "lsp_timing_count",
             "lsp_timing_get", "lsp_plan_get_tiles", "lsp_plan_set_tiles", "lsp_apply_op_noalloc", "lsp_plan_save_tiles",
             "lsp_plan_create_general", "lsp_setup_general", "lsp_get_boundary_stencils",
-            "lsp_field_bytes", "lsp_exterior_field", "lsp_far_field"]
+            "lsp_field_bytes", "lsp_exterior_field", "lsp_far_field", "lsp_self_term"]
 
 
 class Options(ctypes.Structure):
@@ -84,6 +84,7 @@ def load():
         "lsp_setup_general": [vp, cd, vp, vp, vp, sz, vp, ctypes.POINTER(vp)],
         "lsp_get_boundary_stencils": [vp, vp, vp, vp],
         "lsp_field_bytes": [vp, ci, ctypes.POINTER(sz)],
+        "lsp_self_term": [cd, cd, ci, ci, ctypes.POINTER(cd)],
         "lsp_exterior_field": [vp, ci, vp, vp, ci, vp, vp, vp, sz],
         "lsp_far_field": [vp, ci, vp, vp, ci, vp, vp, vp, sz],
         "lsp_plan_stats_get": [vp, ctypes.POINTER(PlanStats)],
@@ -138,6 +139,13 @@ def _check(status):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def self_term(h, omega, d, mode=0):
+    """k_0 of the kernel table (see lsp.h, lsp_self_term), host computation."""
+    out = (ctypes.c_double * 2)()
+    _check(load().lsp_self_term(float(h), float(omega), int(d), int(mode), out))
+    return complex(out[0], out[1])
 
 
 def timing_enable(on=True):

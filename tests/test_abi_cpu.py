@@ -238,8 +238,27 @@ def test_default_tiles_by_precision(lib):
 
 def test_self_term_option_validated(lib):
     with pytest.raises(L.LspError):
-        L.Plan(32, 2, self_term=2)
+        L.Plan(32, 2, self_term=3)
     L.Plan(32, 2, self_term=1)
+    L.Plan(32, 2, self_term=2)
+    with pytest.raises(L.LspError):
+        L.self_term(1 / 32, 0.0, 2, 2)  # no 2D Laplace kernel
+
+
+@pytest.mark.parametrize("n,d,omega", [(32, 2, 8 * np.pi), (256, 2, 64 * np.pi), (16, 3, 4 * np.pi),
+                                       (96, 3, 24 * np.pi), (48, 3, 0.0)])
+def test_host_self_terms_match_oracle(lib, n, d, omega):
+    """The library's host self terms (Section 2.1's k_0) against the
+    oracle's: the disk / ball closed forms and the cell integral to 1e-13,
+    the fitted one-point correction (own e^{-x} Ei(x), Dawson, symmetric
+    lattice sum, against mpmath / scipy and the full lattice) to 2e-12."""
+    from oracle.greens import self_term
+    h = 1.0 / n
+    for mode, tol in ((0, 1e-13), (1, 1e-13), (2, 2e-12)):
+        if mode == 1 and omega == 0:
+            continue
+        a, b = L.self_term(h, omega, d, mode), self_term(h, omega, d, mode)
+        assert abs(a - b) <= tol * abs(b), (mode, a, b)
 
 
 def test_laplace_options_validated(lib):

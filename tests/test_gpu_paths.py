@@ -177,6 +177,33 @@ def test_nan_medium_is_singular(prec):
     assert e2.value.status == 4
 
 
+@pytest.mark.parametrize("n,d", [(32, 2), (64, 3)])
+def test_fitted_self_term(n, d):
+    """self_term = 2 (the fourth-order one-point correction fitted to a
+    Gaussian probe): the GPU's table (k_0 from the host) against the
+    oracle's, k_0 to 2e-12 (lattice-sum rounding), the rest to 1e-13; and
+    the 2D n = 32 workload solved with it against the oracle with the same
+    self term (FP64, 1e-8, iterations within 1)."""
+    lsp, torch = _lsp()
+    omega = 2 * np.pi * n / 8
+    plan = lsp.Plan(n, d, self_term=2)
+    pb = lsp.Problem(plan, omega, np.zeros(n ** d))
+    k = pb.kernel_table().cpu().numpy()
+    ref = kernel_table(n, d, omega, self_term_mode=2).transpose(tuple(range(d))[::-1]).reshape(-1)
+    assert abs(k[0] - ref[0]) <= 2e-12 * abs(ref[0])
+    assert np.max(np.abs(k[1:] - ref[1:])) <= 1e-13 * np.abs(ref).max()
+    if d == 2:
+        w = synth.workload("c1")
+        plan = lsp.Plan(w["n"], 2, self_term=2)
+        pb = lsp.Problem(plan, w["omega"], w["m"])
+        pb.factor()
+        u, info, st = pb.solve(w["uI"])
+        assert st == 0
+        sol = OracleProblem(w["n"], 2, w["omega"], w["m"], self_term=2).solve(w["uI"][0])
+        assert _rel(u.cpu().numpy()[0], sol.x) <= 1e-8
+        assert abs(info[0]["iters"] - sol.iters) <= 1
+
+
 @pytest.mark.parametrize("n,d", [(32, 2), (16, 3)])
 def test_cell_self_term(n, d):
     """self_term = 1 (k_0 = the integral of G over the cell, Section 2.1's
