@@ -180,10 +180,18 @@ def kernel_model(base, tag, st, w, nrhs, counts):
         # n values in and out per line, the spectrum rows once
         per = L ** (d - 1) * 2 * n * esz * nrhs + (n + 1) ** (d - 1) * L * esz
         return "hbm", counts.get(f"fft_conv [{tag}]", 0) * per, "GB/s"
-    if base in ("fwd_mchain", "bwd_mchain"):
-        # the small-front levels' factor entries (their fronts' vectors are
-        # a small part of the fields)
-        return "hbm", apps * st["mchain_entries"] * esz, "GB/s"
+    if base == "fwd_mchain":
+        # the small-front levels' factor entries, the pivots' z gathered,
+        # the children's update rows read and the front vectors written,
+        # for every right-hand side
+        vec = st["mchain_pivots"] + st["mchain_child_rows"] + st["mchain_rows"]
+        return "hbm", apps * (st["mchain_entries"] + nrhs * vec) * esz, "GB/s"
+    if base == "bwd_mchain":
+        # factor entries, the pivots' forward results and the boundary rows'
+        # solution read, the pivots' solution written point-major and
+        # widened to complex128 (mixed) or as the complex128 solution
+        vec = (2 * st["mchain_pivots"] + (st["mchain_rows"] - st["mchain_pivots"])) * esz
+        return "hbm", apps * (st["mchain_entries"] * esz + nrhs * (vec + 16 * st["mchain_pivots"])), "GB/s"
     return None
 
 

@@ -206,6 +206,12 @@ typedef struct {
   double cross_update_flops;  /* of update_flops, the first panel's update
                                  of the second panel's column and row
                                  strips on those levels */
+  double mchain_pivots;       /* of the matrix-core levels' fronts: the sum of
+                                 p (rows gathered from / scattered to the
+                                 grid), */
+  double mchain_rows;         /* the sum of p + q (front vector rows), and */
+  double mchain_child_rows;   /* the sum of their children's q (update rows
+                                 the forward sweep adds in) */
   int domain_points;          /* grid points of the domain: N, or |Omega| of a
                                  general-domain plan */
   int boundary_points;        /* general domains: points of Omega with a

@@ -1012,6 +1012,9 @@ lsp_status lsp_plan_stats_get(const lsp_plan* plan, lsp_plan_stats* s) {
   s->mchain_entries = P.mchain_entries;
   s->pair_update_flops = fs.pair_update_flops;
   s->cross_update_flops = fs.cross_update_flops;
+  s->mchain_pivots = P.mchain_pivots;
+  s->mchain_rows = P.mchain_rows;
+  s->mchain_child_rows = P.mchain_child_rows;
   s->domain_points = P.general ? P.domain_points : P.N;
   s->boundary_points = (int)P.bpts.size();
   s->sketch_cols = P.sketch_r;

@@ -253,6 +253,7 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
   P.level_mchain.assign(P.nlevels, 0);
   P.mchain_levels = 0;
   P.mchain_entries = 0.0;
+  P.mchain_pivots = P.mchain_rows = P.mchain_child_rows = 0.0;
   for (int l = 0; l < P.nlevels; ++l) {
     const int cnt = P.level_ptr[l + 1] - P.level_ptr[l];
     const bool want = opts.dense_sweeps == 2 || (opts.dense_sweeps == 1 && max_nrhs >= 4);
@@ -301,6 +302,10 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
       if (f.child1 >= 0) P.assemble_entries += (double)P.fronts[f.child1].q * P.fronts[f.child1].q;
       if (P.level_dense[f.level]) continue;
       if (P.level_mchain[f.level]) {
+        P.mchain_pivots += f.p;
+        P.mchain_rows += (double)m;
+        if (f.child0 >= 0) P.mchain_child_rows += P.fronts[f.child0].q;
+        if (f.child1 >= 0) P.mchain_child_rows += P.fronts[f.child1].q;
         for (int k0 = 0; k0 < f.p; k0 += P.nb) {
           const int kb = std::min(P.nb, f.p - k0);
           P.mchain_entries += (double)(m - k0 - kb) * kb + (double)P.nb * P.nb;

@@ -66,6 +66,9 @@ struct Plan {
   std::vector<char> level_mchain;
   int mchain_levels = 0;
   double mchain_entries = 0.0;     // factor entries one sweep of them reads
+  // their fronts' vector rows: pivots (sum p), front rows (sum p + q), and
+  // the children's update rows their forward sweeps add in (sum of q)
+  double mchain_pivots = 0.0, mchain_rows = 0.0, mchain_child_rows = 0.0;
   // Levels swept by the blocked kernels (sweep.hip): not dense, not small,
   // and either fronts of more than 1024 rows or at most 32 fronts with more
   // than two panels.

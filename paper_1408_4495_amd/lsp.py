@@ -56,6 +56,8 @@ class PlanStats(ctypes.Structure):
                 ("trsm_flops", ctypes.c_double), ("assemble_entries", ctypes.c_double),
                 ("mchain_levels", ctypes.c_int), ("mchain_entries", ctypes.c_double),
                 ("pair_update_flops", ctypes.c_double), ("cross_update_flops", ctypes.c_double),
+                ("mchain_pivots", ctypes.c_double), ("mchain_rows", ctypes.c_double),
+                ("mchain_child_rows", ctypes.c_double),
                 ("domain_points", ctypes.c_int), ("boundary_points", ctypes.c_int), ("sketch_cols", ctypes.c_int)]
 
 
