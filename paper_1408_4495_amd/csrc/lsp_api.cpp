@@ -129,6 +129,7 @@ struct ProblemPtrs {
   // points' stencils and singular values ([nbnd][27]), the output mask, and
   // the plan's point tables
   double2* T;
+  double2* Tw;      // the sketch products' FFT work array, kSketchBatch columns
   double2* balpha;
   double* bsigma;
   double* dmask;
@@ -136,6 +137,8 @@ struct ProblemPtrs {
   int* bpts;
   unsigned* bslots;
 };
+
+constexpr int kSketchBatch = 8;  // sketch columns per batched K product
 
 size_t layout_problem(const lsp_plan* pl, int precision, void* base, ProblemPtrs* out) {
   const Plan& P = pl->p;
@@ -165,6 +168,7 @@ size_t layout_problem(const lsp_plan* pl, int precision, void* base, ProblemPtrs
   q.Gop = cv.take<char>((size_t)P.dense_elems * esz);
   if (P.general) {
     q.T = cv.take<double2>((size_t)P.sketch_r * P.N);
+    q.Tw = cv.take<double2>((size_t)std::min(P.sketch_r, kSketchBatch) * Ld);
     q.balpha = cv.take<double2>(std::max<size_t>(1, P.bpts.size()) * S);
     q.bsigma = cv.take<double>(std::max<size_t>(1, P.bpts.size()) * S);
     q.dmask = cv.take<double>(P.N);
@@ -1137,14 +1141,16 @@ static lsp_status setup_impl(const lsp_plan* plan, double omega, const double* m
     compute_stencils(pb->d.ktab, P.n, P.d, pb->d.geo, plan->nclass, plan->maxF, pb->d.partial, plan->gram_blocks,
                      pb->d.G, pb->d.U1, pb->d.alpha_pad, pb->d.C_pad, pb->d.sigma_pad, st);
     if (P.general) {
-      // Section 4: T = (K w^2 m) R over Omega's columns, one K product per
-      // sketch column (the embedding array, free after the spectrum, is the
-      // transform's work array), then the boundary points' stencils
+      // Section 4: T = (K w^2 m) R over Omega's columns, the K products in
+      // batches of kSketchBatch sketch columns (in place), then the
+      // boundary points' stencils
       launch_domain_mask(pb->d.dmask, pb->d.ptab, P.N, st);
-      for (int c = 0; c < P.sketch_r; ++c) {
-        double2* Tc = pb->d.T + (size_t)c * P.N;
-        launch_sketch_widen(Tc, R_dev + (size_t)c * P.N, pb->d.ptab, P.N, st);
-        kmatvec<double>(pb->fp64, 1, Tc, Tc, pb->d.w2m, false, pb->d.E, st);
+      for (int c = 0; c < P.sketch_r; ++c)
+        launch_sketch_widen(pb->d.T + (size_t)c * P.N, R_dev + (size_t)c * P.N, pb->d.ptab, P.N, st);
+      for (int c0 = 0; c0 < P.sketch_r; c0 += kSketchBatch) {
+        const int g = std::min(kSketchBatch, P.sketch_r - c0);
+        double2* Tc = pb->d.T + (size_t)c0 * P.N;
+        kmatvec<double>(pb->fp64, g, Tc, Tc, pb->d.w2m, false, pb->d.Tw, st);
       }
       launch_bnd_stencils(pb->d.T, P.sketch_r, P.N, pb->d.bpts, pb->d.bslots, (int)P.bpts.size(), P.n, P.d,
                           pb->d.balpha, pb->d.bsigma, st);

@@ -684,6 +684,54 @@ __global__ void __launch_bounds__(256) applyQ_general_kernel(Cx* __restrict__ y,
   y[rb + pt] = from_c128<Cx>(acc);
 }
 
+// The 2D stencil product over row blocks: a workgroup takes 256 columns of
+// RB consecutive rows of one right-hand side and keeps a window of three
+// rows of x (with one halo column on each side) in LDS, so every row of x
+// is read once per block (plus two halo rows) instead of once per row
+// above, at and below; each point's sum runs over the slots in the same
+// order as applyQ_kernel's (the same values bit for bit).
+constexpr int QRB = 16;
+
+template <typename Cx>
+__global__ void __launch_bounds__(256) applyQ_rows_kernel(Cx* __restrict__ y, const double2* __restrict__ x,
+                                                          const double2* __restrict__ alpha_pad, int n, long long N,
+                                                          int nb1) {
+  __shared__ double2 win[3][258];
+  __shared__ double2 alp[9 * 9];  // the 9 classes' stencils (9 slots each)
+  const int cb = blockIdx.x % nb1, r0 = (blockIdx.x / nb1) * QRB, tid = threadIdx.x;
+  if (tid < 81) alp[tid] = alpha_pad[(tid / 9) * S + tid % 9];
+  const int c0 = cb * 256, i1 = c0 + tid;
+  const long long rb = (long long)blockIdx.y * N;
+  const int r1 = min(n, r0 + QRB);
+  auto load_row = [&](int j) {  // row j (in the grid) into slot j mod 3
+    double2* w = win[(j + 3) % 3];
+    for (int e = tid; e < 258; e += 256) {
+      const int c = c0 - 1 + e;
+      w[e] = (j >= 0 && j < n && c >= 0 && c < n) ? x[rb + (long long)j * n + c] : make_double2(0, 0);
+    }
+  };
+  load_row(r0 - 1);
+  load_row(r0);
+  for (int j = r0; j < r1; ++j) {
+    load_row(j + 1);
+    __syncthreads();
+    if (i1 < n) {
+      const int ii[3] = {i1, j, 0};
+      const int c = point_class(ii, n, 2);
+      const double2* al = alp + c * 9;
+      double2 acc = make_double2(0, 0);
+#pragma unroll
+      for (int slot = 0; slot < 9; ++slot) {
+        const int o1 = slot % 3 - 1, o2 = slot / 3 - 1;
+        const bool inside = i1 + o1 >= 0 && i1 + o1 < n && j + o2 >= 0 && j + o2 < n;
+        if (inside) acc = cadd(acc, cmul(al[slot], win[(j + o2 + 3) % 3][tid + 1 + o1]));
+      }
+      y[rb + (long long)j * n + i1] = from_c128<Cx>(acc);
+    }
+    __syncthreads();  // the slot of row j - 1 is reloaded next
+  }
+}
+
 }  // namespace
 
 void launch_domain_mask(double* dmask, const int* ptab, long long N, hipStream_t st) {
@@ -760,7 +808,8 @@ void launch_applyQ(Cx* y, const double2* x, const double2* alpha_pad, int n, int
   const long long lines = d == 2 ? n : (long long)n * n;
   const dim3 grid((unsigned)(lines * nb1), nrhs);
   if (d == 2)
-    LSP_LAUNCH("applyQ", (int)sizeof(Cx), (applyQ_kernel<Cx, 2>), grid, dim3(256), 0, st, y, x, alpha_pad, n, N, nb1);
+    LSP_LAUNCH("applyQ", (int)sizeof(Cx), (applyQ_rows_kernel<Cx>), dim3((unsigned)(((n + QRB - 1) / QRB) * nb1), nrhs),
+               dim3(256), 0, st, y, x, alpha_pad, n, N, nb1);
   else
     LSP_LAUNCH("applyQ", (int)sizeof(Cx), (applyQ_kernel<Cx, 3>), grid, dim3(256), 0, st, y, x, alpha_pad, n, N, nb1);
 }
