@@ -261,12 +261,16 @@ struct HalfArgs {
   int ncb, GS;                 // line blocks of LPW lines; blocks per cache-line group
   long long cs, os, es;        // work-array line (c, o): element e at c cs + o os + e es
   long long wstride, fstride;  // per right-hand side: work array (L^d), fields (N)
+  long long lr;                // row stride of the work array (L, padded in 2D)
   FftRadices hr;               // radices of n
 };
 
 // Line (c, o) of right-hand side rhs, by kind:
 //   FWD_FIELD  field row c (n contiguous values, scaled by w2m when given) ->
-//              work row c: L values at (c mod n) L + (c div n) L^2
+//              work row c: L values at (c mod n) lr + (c div n) lr L (lr:
+//              the work rows' stride, L + 16 in 2D so that a column's
+//              entries are not a power of two apart and spread over the
+//              L2's sets)
 //   FWD_WORK   n values of the work line -> L values of the same line
 //   CONV       n values -> n values in place, spectrum row of line c
 //   INV_WORK   L values of the work line -> its first n values
@@ -369,7 +373,7 @@ __global__ void __launch_bounds__(kHalfThreads) half_lines_kernel(cplx<T>* __res
       const double sc = w2m ? w2m[fb + e] : 1.0;
       xin[m] = mk<T>((T)(xv.x * sc), (T)(xv.y * sc));
     }
-    const long long wb = (long long)(cc % n) * L + (long long)(cc / n) * L * L;
+    const long long wb = (long long)(cc % n) * a.lr + (long long)(cc / n) * a.lr * L;
 #pragma unroll
     for (int m = 0; m < EPT; ++m) v[m] = xin[m];
     fft_half<T, EPT, false>(v, s, t, P, n, L, a.hr, tw);
@@ -441,7 +445,7 @@ __global__ void __launch_bounds__(kHalfThreads) half_lines_kernel(cplx<T>* __res
     for (int m = 0; m < EPT; ++m) v[m] = cadd(yo[m], cmulc(we[m], v[m]));
     store_work(0, v);
   } else {  // HK_INV_FIELD
-    const long long wb = (long long)(cc % n) * L + (long long)(cc / n) * L * L;
+    const long long wb = (long long)(cc % n) * a.lr + (long long)(cc / n) * a.lr * L;
     cplx<T> yo[EPT];
 #pragma unroll
     for (int m = 0; m < EPT; ++m) v[m] = Wr[wb + t + m * P];
@@ -501,6 +505,7 @@ void launch_half(const FftPlanDev<T>& fp, cplx<T>* W, const double2* x, double2*
   a.ncols = ncols; a.nout = nout; a.nrhs = nrhs;
   a.cs = cs; a.os = os; a.es = es;
   a.wstride = fp.wstride; a.fstride = fp.N;
+  a.lr = fp.lr;
   a.hr = fp.hrad;
   const long long ncb = (ncols + lpw - 1) / lpw;
   // along a strided axis a block covers LPW adjacent lines' entries of a
@@ -523,7 +528,7 @@ void kmatvec_impl(const FftPlanDev<T>& fp, int nrhs, const double2* x, double2* 
   const long long LL = (long long)L * L;
   if (fp.d == 2) {
     launch_half<T, EPT, HK_FWD_FIELD>(fp, W, x, y, w2m, n, 1, 0, 0, 1, nrhs, st);
-    launch_half<T, EPT, HK_CONV>(fp, W, x, y, w2m, L, 1, 1, 0, L, nrhs, st);
+    launch_half<T, EPT, HK_CONV>(fp, W, x, y, w2m, L, 1, 1, 0, fp.lr, nrhs, st);
     launch_half<T, EPT, HK_INV_FIELD>(fp, W, add_x ? x : nullptr, y, omask, n, 1, 0, 0, 1, nrhs, st);
   } else {
     launch_half<T, EPT, HK_FWD_FIELD>(fp, W, x, y, w2m, n * n, 1, 0, 0, 1, nrhs, st);

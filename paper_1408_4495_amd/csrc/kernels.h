@@ -35,6 +35,7 @@ struct FftPlanDev {
   int ept;                   // elements per thread of the full-length (L-point) transforms
   int hept;                  // elements per thread of the half-length (n-point) transforms
   long long wstride;         // work array elements per right-hand side (L^d)
+  long long lr;              // row stride of the K-matvec's work rows (L; L + 16 in 2D, n >= 16)
   FftRadices rad;            // radices of L
   FftRadices hrad;           // radices of n
   const cplx<T>* tw;         // exp(-2 pi i k / L), k < L

@@ -792,6 +792,8 @@ FftPlanDev<T> make_fft_plan(const Plan& P, const cplx<T>* tw, const cplx<T>* spe
   long long Ld = 1;
   for (int a = 0; a < P.d; ++a) Ld *= P.L;
   f.wstride = Ld;
+  // 2D work rows padded by 16 elements (n rows of L + 16 fit in L^2 for n >= 16)
+  f.lr = P.d == 2 && P.n >= 16 ? P.L + 16 : P.L;
   f.rad.npass = (int)P.radices.size();
   for (int i = 0; i < f.rad.npass; ++i) f.rad.r[i] = P.radices[i];
   // the n-point transforms of the K-matvec: n = 2^a 3^b
