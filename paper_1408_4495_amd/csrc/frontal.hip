@@ -61,34 +61,51 @@ __global__ void __launch_bounds__(256) assemble_front_kernel(cplx<T>* __restrict
   const bool h0 = f.cfoff[0] >= 0, h1 = f.cfoff[1] >= 0;
   const int mc0 = f.cm[0], mc1 = f.cm[1];
   const float rm = 1.0f / (float)m;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < mm; e += gridDim.x * blockDim.x) {
-    // (c, r) = divmod(e, m) from a float estimate of e / m instead of an
-    // integer division: its relative error is below 2e-7 and e / m < m <
-    // 46341 (the plan bounds m^2 by 2^31), so it is off by at most one
-    int c = (int)((float)e * rm), r = e - c * m;
-    if (r < 0) { --c; r += m; } else if (r >= m) { ++c; r -= m; }
-    double2 v = make_double2(0, 0);
-    if (r < f.p || c < f.p) {
-      const unsigned pi = gp[r], pj = gp[c];
-      int slot = 0, m3 = 1;
-      bool near = true;
-      for (int a = 0; a < d; ++a) {
-        const int di = (int)((pj >> (sh * a)) & mask) - (int)((pi >> (sh * a)) & mask);
-        near = near && di >= -1 && di <= 1;
-        slot += (di + 1) * m3;
-        m3 *= 3;
+  // four entries per thread and step, all their loads issued before any
+  // entry is combined and stored
+  constexpr int U = 4;
+  const int stride = gridDim.x * blockDim.x;
+  for (int e0 = blockIdx.x * blockDim.x + threadIdx.x; e0 < mm; e0 += U * stride) {
+    int rr[U], cc[U];
+    bool live[U];
+    double2 mv[U], c0v[U], c1v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * stride;
+      live[u] = e < mm;
+      const int ee = live[u] ? e : 0;
+      // (c, r) = divmod(e, m) from a float estimate of e / m instead of an
+      // integer division: its relative error is below 2e-7 and e / m < m <
+      // 46341 (the plan bounds m^2 by 2^31), so it is off by at most one
+      int c = (int)((float)ee * rm), r = ee - c * m;
+      if (r < 0) { --c; r += m; } else if (r >= m) { ++c; r -= m; }
+      rr[u] = r;
+      cc[u] = c;
+      mv[u] = c0v[u] = c1v[u] = make_double2(0, 0);
+      if (r < f.p || c < f.p) {
+        const unsigned pi = gp[r], pj = gp[c];
+        int slot = 0, m3 = 1;
+        bool near = true;
+        for (int a = 0; a < d; ++a) {
+          const int di = (int)((pj >> (sh * a)) & mask) - (int)((pi >> (sh * a)) & mask);
+          near = near && di >= -1 && di <= 1;
+          slot += (di + 1) * m3;
+          m3 *= 3;
+        }
+        if (near) mv[u] = Mval[(long long)id[r] * ns + slot];
       }
-      if (near) v = Mval[(long long)id[r] * ns + slot];
+      if (h0) {
+        const int pr = cp[2 * r], pc = cp[2 * c];
+        if (pr >= 0 && pc >= 0) c0v[u] = widen(Fc0[pr + pc * mc0]);
+      }
+      if (h1) {
+        const int pr = cp[2 * r + 1], pc = cp[2 * c + 1];
+        if (pr >= 0 && pc >= 0) c1v[u] = widen(Fc1[pr + pc * mc1]);
+      }
     }
-    if (h0) {
-      const int pr = cp[2 * r], pc = cp[2 * c];
-      if (pr >= 0 && pc >= 0) v = cadd(v, widen(Fc0[pr + pc * mc0]));
-    }
-    if (h1) {
-      const int pr = cp[2 * r + 1], pc = cp[2 * c + 1];
-      if (pr >= 0 && pc >= 0) v = cadd(v, widen(Fc1[pr + pc * mc1]));
-    }
-    F[e] = from_c128<cplx<T>>(v);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (live[u]) F[e0 + u * stride] = from_c128<cplx<T>>(cadd(cadd(mv[u], c0v[u]), c1v[u]));
   }
 }
 
@@ -2094,7 +2111,8 @@ void mf_factor_levels(const MfDev<T>& mf, const Plan& plan, hipStream_t st, cons
     const int maxm = plan.level_maxpq[l];
     const int maxp = plan.level_maxp[l];
     long long mm = (long long)maxm * maxm;
-    int gx = (int)std::min<long long>((mm + 255) / 256, 4096);  // one element per thread up to 1M-entry fronts
+    // four entries per thread and step; about 8192 workgroups over the level
+    int gx = (int)std::min<long long>((mm + 1023) / 1024, std::max(1, 8192 / cnt));
     LSP_LAUNCH("assemble_front", (int)sizeof(cplx<T>), assemble_front_kernel<T>, dim3(gx, cnt), dim3(256), 0, st, mf.F,
                mf.fronts, mf.idx, mf.gpos, mf.cpos, mf.Mval, first, plan.d);
     const bool fp64 = sizeof(T) == 8;
