@@ -30,7 +30,10 @@
 // Thread t owns elements t + m P (m < EPT) before and after a transform: the
 // first radix pass takes them from registers and the last leaves them there,
 // so only the passes in between exchange through LDS (one pad element per 16
-// against bank conflicts).  Lines along a strided axis are handed to
+// against bank conflicts).  The two n-point transforms of a line (even and
+// odd half) are independent and run in lockstep: each pass loads its
+// twiddles once for both and the pair shares the pass's barriers, each
+// half in its own bank of LDS lines.  Lines along a strided axis are handed to
 // consecutive lanes (lane = line + LPW t), so a load or store of element e
 // covers LPW adjacent lines' contiguous entries.
 //
@@ -110,7 +113,7 @@ __device__ inline int fold(int k, int L) { return k <= L / 2 ? k : L - k; }
 // ---------------------------------------------------------------- half-length transforms
 
 constexpr int kHalfThreads = 256;          // largest workgroup of the half-length kernels
-constexpr size_t kHalfLds = 40 * 1024;     // LDS per workgroup
+constexpr size_t kHalfLds = 72 * 1024;     // LDS per workgroup (two banks of lines)
 
 __host__ __device__ __forceinline__ int padi(int e) { return e + (e >> 4); }
 
@@ -158,61 +161,79 @@ __device__ __forceinline__ void apply_tw(cplx<T> (&v)[R], const cplx<T>* w) {
   }
 }
 
-// One radix-R pass of an n-point transform over the line s (LDS, padded
-// index).  a[m] holds element t + m P: read by the first pass, written by the
-// last; the other passes read and write s.  CARRY: the twiddles of this pass
-// are in wt8 (loaded by the previous pass) and those of the next pass, a
-// radix-8 one, are loaded here, a pass ahead of their use; otherwise the
-// pass loads its own.
-template <typename T, int R, int EPT, bool INV, bool CARRY>
-__device__ __forceinline__ void half_pass(cplx<T> (&a)[EPT], cplx<T> (&wt8)[3], cplx<T>* __restrict__ s,
-                                          const int t, const int P, const int n, const int L, const int Ns,
-                                          const bool first, const bool last, const cplx<T>* __restrict__ tw) {
+// One radix-R pass of K n-point transforms in lockstep (the even and odd
+// halves of a line: same length, same twiddles), line k in LDS at
+// s + k sstep (padded index).  a[k][m] holds element t + m P of transform k:
+// read by the first pass, written by the last; the other passes read and
+// write LDS.  The K transforms share the twiddle loads and the barriers.
+// CARRY: the twiddles of this pass are in wt8 (loaded by the previous pass)
+// and those of the next pass, a radix-8 one, are loaded here, a pass ahead
+// of their use; otherwise the pass loads its own.
+template <typename T, int R, int EPT, int K, bool INV, bool CARRY>
+__device__ __forceinline__ void half_pass(cplx<T> (&a)[K][EPT], cplx<T> (&wt8)[3], cplx<T>* __restrict__ s,
+                                          const int sstep, const int t, const int P, const int n, const int L,
+                                          const int Ns, const bool first, const bool last,
+                                          const cplx<T>* __restrict__ tw) {
   constexpr int NB = EPT / R;
   constexpr int NL = TwLoads<R>::value;
   const int q = n / R;
-  cplx<T> v[NB][R];
+  cplx<T> v[K][NB][R];
   if (first) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
+    for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = a[b + r * NB];
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[k][b][r] = a[k][b + r * NB];
   } else {
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
+    for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = s[padi(t + b * P + r * q)];
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[k][b][r] = s[k * sstep + padi(t + b * P + r * q)];
   }
   if (!first) {
     if constexpr (CARRY) {
       // carried twiddles are radix-8 ones (the radix-2 and radix-4 passes
       // of a carried schedule are first passes)
-      if constexpr (R == 8) apply_tw<T, 8, INV>(v[0], wt8);
+      if constexpr (R == 8) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) apply_tw<T, 8, INV>(v[k][0], wt8);
+      }
     } else {
       cplx<T> wt[NB * NL];
       load_tw<T, R, NB>(wt, t, P, Ns, L, tw);
 #pragma unroll
-      for (int b = 0; b < NB; ++b) apply_tw<T, R, INV>(v[b], wt + NL * b);
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) apply_tw<T, R, INV>(v[k][b], wt + NL * b);
     }
   }
   if constexpr (CARRY) {
     if (!last) load_tw<T, 8, 1>(wt8, t, P, Ns * R, L, tw);
   }
 #pragma unroll
-  for (int b = 0; b < NB; ++b) Dft<T, R>::run(v[b], INV);
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) Dft<T, R>::run(v[k][b], INV);
   if (last) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
+    for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int r = 0; r < R; ++r) a[b + r * NB] = v[b][r];
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[k][b + r * NB] = v[k][b][r];
   } else {
-    __syncthreads();  // every earlier read of the line is complete
+    __syncthreads();  // every earlier read of the lines is complete
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int j = t + b * P, k = j % Ns, base = (j - k) * R + k;
+    for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int r = 0; r < R; ++r) s[padi(base + r * Ns)] = v[b][r];
-    }
+      for (int b = 0; b < NB; ++b) {
+        const int j = t + b * P, kk = j % Ns, base = (j - kk) * R + kk;
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[k * sstep + padi(base + r * Ns)] = v[k][b][r];
+      }
     __syncthreads();
   }
 }
@@ -220,19 +241,19 @@ __device__ __forceinline__ void half_pass(cplx<T> (&a)[EPT], cplx<T> (&wt8)[3], 
 // n = 2^a (EPT = 8): a radix 2, 4 or 8 pass, then radix-8 passes, the
 // twiddles of each radix-8 pass loaded a pass ahead.  n = 2^a 3^b: passes
 // of radix 4, 2, 3 in the plan's order, each loading its own twiddles.
-template <typename T, int EPT, bool INV>
-__device__ __forceinline__ void fft_half(cplx<T> (&a)[EPT], cplx<T>* __restrict__ s, const int t, const int P,
-                                         const int n, const int L, const FftRadices& hr,
+template <typename T, int EPT, int K, bool INV>
+__device__ __forceinline__ void fft_half(cplx<T> (&a)[K][EPT], cplx<T>* __restrict__ s, const int sstep,
+                                         const int t, const int P, const int n, const int L, const FftRadices& hr,
                                          const cplx<T>* __restrict__ tw) {
   cplx<T> wt8[3];
   if constexpr (EPT == 8) {
     const int R0 = hr.r[0], np = hr.npass;
-    if (R0 == 8) half_pass<T, 8, 8, INV, true>(a, wt8, s, t, P, n, L, 1, true, np == 1, tw);
-    else if (R0 == 4) half_pass<T, 4, 8, INV, true>(a, wt8, s, t, P, n, L, 1, true, np == 1, tw);
-    else half_pass<T, 2, 8, INV, true>(a, wt8, s, t, P, n, L, 1, true, np == 1, tw);
+    if (R0 == 8) half_pass<T, 8, 8, K, INV, true>(a, wt8, s, sstep, t, P, n, L, 1, true, np == 1, tw);
+    else if (R0 == 4) half_pass<T, 4, 8, K, INV, true>(a, wt8, s, sstep, t, P, n, L, 1, true, np == 1, tw);
+    else half_pass<T, 2, 8, K, INV, true>(a, wt8, s, sstep, t, P, n, L, 1, true, np == 1, tw);
     int Ns = R0;
     for (int ip = 1; ip < np; ++ip) {
-      half_pass<T, 8, 8, INV, true>(a, wt8, s, t, P, n, L, Ns, false, ip + 1 == np, tw);
+      half_pass<T, 8, 8, K, INV, true>(a, wt8, s, sstep, t, P, n, L, Ns, false, ip + 1 == np, tw);
       Ns *= 8;
     }
   } else {
@@ -240,9 +261,9 @@ __device__ __forceinline__ void fft_half(cplx<T> (&a)[EPT], cplx<T>* __restrict_
     for (int ip = 0; ip < hr.npass; ++ip) {
       const int R = hr.r[ip];
       const bool first = ip == 0, last = ip + 1 == hr.npass;
-      if constexpr (EPT % 4 == 0) { if (R == 4) half_pass<T, 4, EPT, INV, false>(a, wt8, s, t, P, n, L, Ns, first, last, tw); }
-      if constexpr (EPT % 2 == 0) { if (R == 2) half_pass<T, 2, EPT, INV, false>(a, wt8, s, t, P, n, L, Ns, first, last, tw); }
-      if constexpr (EPT % 3 == 0) { if (R == 3) half_pass<T, 3, EPT, INV, false>(a, wt8, s, t, P, n, L, Ns, first, last, tw); }
+      if constexpr (EPT % 4 == 0) { if (R == 4) half_pass<T, 4, EPT, K, INV, false>(a, wt8, s, sstep, t, P, n, L, Ns, first, last, tw); }
+      if constexpr (EPT % 2 == 0) { if (R == 2) half_pass<T, 2, EPT, K, INV, false>(a, wt8, s, sstep, t, P, n, L, Ns, first, last, tw); }
+      if constexpr (EPT % 3 == 0) { if (R == 3) half_pass<T, 3, EPT, K, INV, false>(a, wt8, s, sstep, t, P, n, L, Ns, first, last, tw); }
       Ns *= R;
     }
   }
@@ -356,14 +377,11 @@ __global__ void __launch_bounds__(kHalfThreads) half_lines_kernel(cplx<T>* __res
     }
   };
 
-  cplx<T> v[EPT];
-  // the element twiddles w^e of this thread's elements (odd half)
-  cplx<T> we[EPT];
-#pragma unroll
-  for (int m = 0; m < EPT; ++m) we[m] = tw[t + m * P];
-
+  // the even and odd halves of a line run as two transforms in lockstep,
+  // line k of the pair in LDS at s + k sstep
+  const int sstep = a.LPW * a.Lp;
+  cplx<T> v[2][EPT];
   if constexpr (KIND == HK_FWD_FIELD) {
-    cplx<T> xin[EPT];
     const long long fb = (long long)cc * n;
     const double2* xr = x + rhs * a.fstride;
 #pragma unroll
@@ -371,34 +389,24 @@ __global__ void __launch_bounds__(kHalfThreads) half_lines_kernel(cplx<T>* __res
       const int e = t + m * P;
       const double2 xv = xr[fb + e];
       const double sc = w2m ? w2m[fb + e] : 1.0;
-      xin[m] = mk<T>((T)(xv.x * sc), (T)(xv.y * sc));
+      v[0][m] = mk<T>((T)(xv.x * sc), (T)(xv.y * sc));
+      v[1][m] = cmul(v[0][m], tw[e]);
     }
     const long long wb = (long long)(cc % n) * a.lr + (long long)(cc / n) * a.lr * L;
-#pragma unroll
-    for (int m = 0; m < EPT; ++m) v[m] = xin[m];
-    fft_half<T, EPT, false>(v, s, t, P, n, L, a.hr, tw);
+    fft_half<T, EPT, 2, false>(v, s, sstep, t, P, n, L, a.hr, tw);
     if (live) {
 #pragma unroll
-      for (int m = 0; m < EPT; ++m) Wr[wb + t + m * P] = v[m];
-    }
+      for (int m = 0; m < EPT; ++m) Wr[wb + t + m * P] = v[0][m];
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) v[m] = cmul(xin[m], we[m]);
-    fft_half<T, EPT, false>(v, s, t, P, n, L, a.hr, tw);
-    if (live) {
-#pragma unroll
-      for (int m = 0; m < EPT; ++m) Wr[wb + n + t + m * P] = v[m];
+      for (int m = 0; m < EPT; ++m) Wr[wb + n + t + m * P] = v[1][m];
     }
   } else if constexpr (KIND == HK_FWD_WORK) {
-    cplx<T> xin[EPT];
-    load_work(0, xin, true);
+    load_work(0, v[0], true);
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) v[m] = xin[m];
-    fft_half<T, EPT, false>(v, s, t, P, n, L, a.hr, tw);
-    store_work(0, v);
-#pragma unroll
-    for (int m = 0; m < EPT; ++m) v[m] = cmul(xin[m], we[m]);
-    fft_half<T, EPT, false>(v, s, t, P, n, L, a.hr, tw);
-    store_work((long long)n * a.es, v);
+    for (int m = 0; m < EPT; ++m) v[1][m] = cmul(v[0][m], tw[t + m * P]);
+    fft_half<T, EPT, 2, false>(v, s, sstep, t, P, n, L, a.hr, tw);
+    store_work(0, v[0]);
+    store_work((long long)n * a.es, v[1]);
   } else if constexpr (KIND == HK_CONV) {
     long long row;
     {
@@ -413,48 +421,30 @@ __global__ void __launch_bounds__(kHalfThreads) half_lines_kernel(cplx<T>* __res
       }
     }
     const cplx<T>* sp = spec + row * L;
-    cplx<T> xin[EPT], ya[EPT], sv[EPT];
+    load_work(0, v[0], true);
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) sv[m] = sp[t + m * P];
-    load_work(0, xin, true);
+    for (int m = 0; m < EPT; ++m) v[1][m] = cmul(v[0][m], tw[t + m * P]);
+    fft_half<T, EPT, 2, false>(v, s, sstep, t, P, n, L, a.hr, tw);
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) v[m] = xin[m];
-    fft_half<T, EPT, false>(v, s, t, P, n, L, a.hr, tw);
+    for (int m = 0; m < EPT; ++m) { v[0][m] = cmul(v[0][m], sp[t + m * P]); v[1][m] = cmul(v[1][m], sp[n + t + m * P]); }
+    fft_half<T, EPT, 2, true>(v, s, sstep, t, P, n, L, a.hr, tw);
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) { v[m] = cmul(v[m], sv[m]); sv[m] = sp[n + t + m * P]; }
-    fft_half<T, EPT, true>(v, s, t, P, n, L, a.hr, tw);
-#pragma unroll
-    for (int m = 0; m < EPT; ++m) { ya[m] = v[m]; v[m] = cmul(xin[m], we[m]); }
-    fft_half<T, EPT, false>(v, s, t, P, n, L, a.hr, tw);
-#pragma unroll
-    for (int m = 0; m < EPT; ++m) v[m] = cmul(v[m], sv[m]);
-    fft_half<T, EPT, true>(v, s, t, P, n, L, a.hr, tw);
-#pragma unroll
-    for (int m = 0; m < EPT; ++m) v[m] = cadd(ya[m], cmulc(we[m], v[m]));
-    store_work(0, v);
+    for (int m = 0; m < EPT; ++m) v[0][m] = cadd(v[0][m], cmulc(tw[t + m * P], v[1][m]));
+    store_work(0, v[0]);
   } else if constexpr (KIND == HK_INV_WORK) {
-    cplx<T> yo[EPT];
-    load_work(0, v, true);
-    load_work((long long)n * a.es, yo, false);
-    fft_half<T, EPT, true>(v, s, t, P, n, L, a.hr, tw);
+    load_work(0, v[0], true);
+    load_work((long long)n * a.es, v[1], false);
+    fft_half<T, EPT, 2, true>(v, s, sstep, t, P, n, L, a.hr, tw);
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) { const cplx<T> e = v[m]; v[m] = yo[m]; yo[m] = e; }
-    fft_half<T, EPT, true>(v, s, t, P, n, L, a.hr, tw);
-    // yo holds the even half's result
-#pragma unroll
-    for (int m = 0; m < EPT; ++m) v[m] = cadd(yo[m], cmulc(we[m], v[m]));
-    store_work(0, v);
+    for (int m = 0; m < EPT; ++m) v[0][m] = cadd(v[0][m], cmulc(tw[t + m * P], v[1][m]));
+    store_work(0, v[0]);
   } else {  // HK_INV_FIELD
     const long long wb = (long long)(cc % n) * a.lr + (long long)(cc / n) * a.lr * L;
-    cplx<T> yo[EPT];
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) v[m] = Wr[wb + t + m * P];
+    for (int m = 0; m < EPT; ++m) v[0][m] = Wr[wb + t + m * P];
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) yo[m] = Wr[wb + n + t + m * P];
-    fft_half<T, EPT, true>(v, s, t, P, n, L, a.hr, tw);
-#pragma unroll
-    for (int m = 0; m < EPT; ++m) { const cplx<T> e = v[m]; v[m] = yo[m]; yo[m] = e; }
-    fft_half<T, EPT, true>(v, s, t, P, n, L, a.hr, tw);
+    for (int m = 0; m < EPT; ++m) v[1][m] = Wr[wb + n + t + m * P];
+    fft_half<T, EPT, 2, true>(v, s, sstep, t, P, n, L, a.hr, tw);
     if (live) {
       const long long fb = (long long)cc * n;
       const double2* xr = x ? x + rhs * a.fstride : nullptr;
@@ -462,7 +452,7 @@ __global__ void __launch_bounds__(kHalfThreads) half_lines_kernel(cplx<T>* __res
 #pragma unroll
       for (int m = 0; m < EPT; ++m) {
         const int e = t + m * P;
-        double2 r = widen(cadd(yo[m], cmulc(we[m], v[m])));
+        double2 r = widen(cadd(v[0][m], cmulc(tw[e], v[1][m])));
         if (xr) { const double2 xv = xr[fb + e]; r.x += xv.x; r.y += xv.y; }
         if (w2m && w2m[fb + e] == 0.0) r = make_double2(0, 0);  // output mask
         yr[fb + e] = r;
@@ -492,7 +482,7 @@ void launch_half(const FftPlanDev<T>& fp, cplx<T>* W, const double2* x, double2*
   const int maxthr = kHalfThreads;
   const int lp0 = padi(fp.n - 1) + 1;
   int lpw = 1;
-  while (lpw < 64 && lpw * 2 * a.P <= maxthr && (size_t)lpw * 2 * (lp0 + 256 / esz) * esz <= kHalfLds) lpw *= 2;
+  while (lpw < 64 && lpw * 2 * a.P <= maxthr && (size_t)2 * lpw * 2 * (lp0 + 256 / esz) * esz <= kHalfLds) lpw *= 2;
   // Line stride: the lines of a bank cycle (256 bytes, 256 / esz lanes)
   // tile the banks: with TIO the IO lanes hold 256 / esz / LPW consecutive
   // entries of each line, otherwise (P < 256 / esz) P entries of 256 / esz / P lines.
@@ -516,7 +506,7 @@ void launch_half(const FftPlanDev<T>& fp, cplx<T>* W, const double2* x, double2*
   a.ncb = (int)ncb; a.GS = gs;
   const long long blocks = (ncb + gs - 1) / gs * gs * nout * nrhs;
   LSP_REQUIRE(blocks < (1LL << 31), "FFT grid too large");
-  const size_t lds = (size_t)lpw * lp * esz;
+  const size_t lds = (size_t)2 * lpw * lp * esz;  // two banks of LPW lines
   if (tio) launch_half_as<T, EPT, KIND, !field>(a, lds, blocks, fp, W, x, y, w2m, st);
   else launch_half_as<T, EPT, KIND, false>(a, lds, blocks, fp, W, x, y, w2m, st);
 }
