@@ -685,24 +685,26 @@ __global__ void __launch_bounds__(256) applyQ_general_kernel(Cx* __restrict__ y,
 }
 
 // The 2D stencil product over row blocks: a workgroup takes 256 columns of
-// RB consecutive rows of one right-hand side and keeps a window of three
+// qrb consecutive rows of one right-hand side and keeps a window of three
 // rows of x (with one halo column on each side) in LDS, so every row of x
 // is read once per block (plus two halo rows) instead of once per row
 // above, at and below; each point's sum runs over the slots in the same
-// order as applyQ_kernel's (the same values bit for bit).
+// order as applyQ_kernel's (the same values bit for bit).  qrb is 16 unless
+// that leaves fewer than 2048 workgroups (small grids, few right-hand
+// sides), then halved until it does not, down to one row per workgroup.
 constexpr int QRB = 16;
 
 template <typename Cx>
 __global__ void __launch_bounds__(256) applyQ_rows_kernel(Cx* __restrict__ y, const double2* __restrict__ x,
                                                           const double2* __restrict__ alpha_pad, int n, long long N,
-                                                          int nb1) {
+                                                          int nb1, int qrb) {
   __shared__ double2 win[3][258];
   __shared__ double2 alp[9 * 9];  // the 9 classes' stencils (9 slots each)
-  const int cb = blockIdx.x % nb1, r0 = (blockIdx.x / nb1) * QRB, tid = threadIdx.x;
+  const int cb = blockIdx.x % nb1, r0 = (blockIdx.x / nb1) * qrb, tid = threadIdx.x;
   if (tid < 81) alp[tid] = alpha_pad[(tid / 9) * S + tid % 9];
   const int c0 = cb * 256, i1 = c0 + tid;
   const long long rb = (long long)blockIdx.y * N;
-  const int r1 = min(n, r0 + QRB);
+  const int r1 = min(n, r0 + qrb);
   auto load_row = [&](int j) {  // row j (in the grid) into slot j mod 3
     double2* w = win[(j + 3) % 3];
     for (int e = tid; e < 258; e += 256) {
@@ -807,10 +809,12 @@ void launch_applyQ(Cx* y, const double2* x, const double2* alpha_pad, int n, int
   const int nb1 = (n + 255) / 256;
   const long long lines = d == 2 ? n : (long long)n * n;
   const dim3 grid((unsigned)(lines * nb1), nrhs);
-  if (d == 2)
-    LSP_LAUNCH("applyQ", (int)sizeof(Cx), (applyQ_rows_kernel<Cx>), dim3((unsigned)(((n + QRB - 1) / QRB) * nb1), nrhs),
-               dim3(256), 0, st, y, x, alpha_pad, n, N, nb1);
-  else
+  if (d == 2) {
+    int qrb = QRB;
+    while (qrb > 1 && (long long)((n + qrb - 1) / qrb) * nb1 * nrhs < 2048) qrb /= 2;
+    LSP_LAUNCH("applyQ", (int)sizeof(Cx), (applyQ_rows_kernel<Cx>), dim3((unsigned)(((n + qrb - 1) / qrb) * nb1), nrhs),
+               dim3(256), 0, st, y, x, alpha_pad, n, N, nb1, qrb);
+  } else
     LSP_LAUNCH("applyQ", (int)sizeof(Cx), (applyQ_kernel<Cx, 3>), grid, dim3(256), 0, st, y, x, alpha_pad, n, N, nb1);
 }
 
