@@ -646,13 +646,10 @@ __device__ __forceinline__ void update_tile(GemmLds<T, TM>& G, cplx<T>* __restri
       for (int v = 0; v < 4; ++v) { accr[i][j][v] = 0; acci[i][j][v] = 0; }
   const int li = lane % 16, lk = lane / 16;
   constexpr int LA = TM * NB / 256;
-  for (int kc = 0; kc < kb; kc += NB) {
+  // a chunk's operand tiles into registers (clamped in-range indices, zero
+  // outside the block), then into LDS
+  auto load_ops = [&](const int kc, cplx<T>(&va)[LA], cplx<T>(&vb)[LA]) {
     const int kbc = min(NB, kb - kc), kcol = k0 + kc;
-    const int kpad = (kbc + 3) & ~3;
-    if (kc > 0) __syncthreads();  // the previous chunk's reads of the operand tiles are done
-    // both operand tiles are loaded before the first LDS store (clamped
-    // in-range indices, zero outside the block), so the loads overlap
-    cplx<T> va[LA], vb[LA];
 #pragma unroll
     for (int u = 0; u < LA; ++u) {
       const int e = tid + 256 * u, r = e % TM, kk = e / TM;
@@ -665,6 +662,8 @@ __device__ __forceinline__ void update_tile(GemmLds<T, TM>& G, cplx<T>* __restri
       const cplx<T> v = F[(kcol + min(kk, kbc - 1)) + (long long)(base + min(col0 + c, rem - 1)) * m];
       vb[u] = col0 + c < rem && kk < kbc ? v : mk<T>(0, 0);
     }
+  };
+  auto store_ops = [&](const cplx<T>(&va)[LA], const cplx<T>(&vb)[LA]) {
 #pragma unroll
     for (int u = 0; u < LA; ++u) {
       const int e = tid + 256 * u;
@@ -673,7 +672,35 @@ __device__ __forceinline__ void update_tile(GemmLds<T, TM>& G, cplx<T>* __restri
       Br[e % NB][e / NB] = vb[u].x;
       Bi[e % NB][e / NB] = vb[u].y;
     }
-    __syncthreads();
+  };
+  // C's entries of this lane (BW x BW blocks of 4), for tiles of up to 64
+  // rows loaded right after the first chunk's operands are in LDS, so that
+  // their latency and that of the next chunk's operands pass during the
+  // products; wider tiles load them at the end (registers)
+  constexpr bool kEarlyC = BW <= 2;
+  auto c_index = [&](const int i, const int j, const int v) {
+    const int col = min(col0 + wc + 16 * j + Mfma<T>::row(lk, v), rem - 1);
+    const int row = min(row0 + wr + 16 * i + li, rem - 1);
+    return (long long)(base + row) + (long long)(base + col) * m;
+  };
+  cplx<T> ce[kEarlyC ? BW : 1][kEarlyC ? BW : 1][4];
+  cplx<T> va[LA], vb[LA];
+  load_ops(0, va, vb);
+  store_ops(va, vb);
+  if constexpr (kEarlyC) {
+#pragma unroll
+    for (int i = 0; i < BW; ++i)
+#pragma unroll
+      for (int j = 0; j < BW; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ce[i][j][v] = F[c_index(i, j, v)];
+  }
+  for (int kc = 0; kc < kb; kc += NB) {
+    const int kbc = min(NB, kb - kc);
+    const int kpad = (kbc + 3) & ~3;
+    const bool more = kc + NB < kb;
+    if (more) load_ops(kc + NB, va, vb);  // in flight during this chunk's products
+    __syncthreads();  // this chunk's operand tiles are in LDS
     // Each 16 x 16 block is computed transposed (the MFMA's first operand is
     // B's column block, its second A's row block): the result lane l then
     // holds C rows 16 i + l % 16, so consecutive lanes address consecutive
@@ -691,8 +718,13 @@ __device__ __forceinline__ void update_tile(GemmLds<T, TM>& G, cplx<T>* __restri
           acci[i][j] = Mfma<T>::step(br[j], ai[i], acci[i][j]);
         }
     }
+    if (more) {
+      __syncthreads();  // this chunk's reads of the operand tiles are done
+      store_ops(va, vb);
+    }
   }
-  // C -= A B: per 16-row block i, all BW x 4 loads of C first, then the stores
+  // C -= A B: per 16-row block i (wide tiles: all BW x 4 loads of C first),
+  // then the stores
   const int rmax = min(rem, rlim), cmax = min(rem, clim);
 #pragma unroll
   for (int i = 0; i < BW; ++i) {
@@ -701,9 +733,8 @@ __device__ __forceinline__ void update_tile(GemmLds<T, TM>& G, cplx<T>* __restri
     for (int j = 0; j < BW; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int col = min(col0 + wc + 16 * j + Mfma<T>::row(lk, v), rem - 1);
-        const int row = min(row0 + wr + 16 * i + li, rem - 1);
-        cv[j][v] = F[(base + row) + (long long)(base + col) * m];
+        if constexpr (kEarlyC) cv[j][v] = ce[i][j][v];
+        else cv[j][v] = F[c_index(i, j, v)];
       }
 #pragma unroll
     for (int j = 0; j < BW; ++j)
