@@ -144,11 +144,22 @@ __global__ void __launch_bounds__(256) gram_kernel(const double2* __restrict__ k
     if (base + CHs < j1) fetch(base + CHs, vnext);
     __syncthreads();
     if (PASS2) {
-      for (int e = tid; e < s * CHs; e += blockDim.x) {
-        int k = e / CHs, jj = e % CHs;
-        double2 z = make_double2(0, 0);
-        for (int a = 0; a < s; ++a) z = cadd(z, cmulc(Us[a + S * k], Xf[a * ld + jj]));
-        Zf[k * ld + jj] = z;
+      // Z = U1^H X, three rows of Z per thread so that each staged entry of
+      // X is read once for three products (rows past s are computed from
+      // U1's padding and not stored); each entry's sum runs over a in order
+      const int nk3 = (s + 2) / 3;
+      for (int e = tid; e < nk3 * CHs; e += blockDim.x) {
+        const int k = 3 * (e / CHs), jj = e % CHs;
+        double2 z0 = make_double2(0, 0), z1 = z0, z2 = z0;
+        for (int a = 0; a < s; ++a) {
+          const double2 xa = Xf[a * ld + jj];
+          z0 = cadd(z0, cmulc(Us[a + S * k], xa));
+          z1 = cadd(z1, cmulc(Us[a + S * min(k + 1, S - 1)], xa));
+          z2 = cadd(z2, cmulc(Us[a + S * min(k + 2, S - 1)], xa));
+        }
+        Zf[k * ld + jj] = z0;
+        if (k + 1 < s) Zf[(k + 1) * ld + jj] = z1;
+        if (k + 2 < s) Zf[(k + 2) * ld + jj] = z2;
       }
       __syncthreads();
     }
