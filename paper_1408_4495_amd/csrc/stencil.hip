@@ -236,8 +236,12 @@ __global__ void __launch_bounds__(768) gram_reduce_kernel(const double2* __restr
     if (z % S >= s || z / S >= s) G[(long long)c * S * S + z] = make_double2(0, 0);
 }
 
-// Parallel cyclic Jacobi on the s x s Hermitian matrix of class blockIdx.x,
-// one wave.  A and U are column-major with leading dimension S.  A sweep is
+// Parallel cyclic Jacobi on an s x s Hermitian matrix by one workgroup (the
+// class stencils: 256 threads per class, the boundary points of a general
+// domain: one wave per point); the first s'/2 threads compute a round's
+// rotations, all threads share its column and row updates (each entry's
+// arithmetic is the same whichever thread does it).  A and U are
+// column-major with leading dimension S.  A sweep is
 // s' - 1 rounds (s' = s rounded up to even) of s'/2 disjoint pairs in the
 // round-robin order (position 0 fixed, the others shifted by the round; the
 // index s, when s is odd, is a dummy that pairs with nobody), all rotated
@@ -337,7 +341,7 @@ __device__ void jacobi_eigen(double2* A, double2* U, int s, int lane) {
   }
 }
 
-__global__ void __launch_bounds__(64) eigen_kernel(const double2* __restrict__ G, const ClassGeom* __restrict__ geo,
+__global__ void __launch_bounds__(256) eigen_kernel(const double2* __restrict__ G, const ClassGeom* __restrict__ geo,
                                                    double2* __restrict__ Uout, const double2* __restrict__ U1,
                                                    const double2* __restrict__ ktab, int n, int d, int final_pass,
                                                    double2* __restrict__ alpha_pad, double2* __restrict__ C_pad,
@@ -798,11 +802,11 @@ void compute_stencils(const double2* ktab, int n, int d, const ClassGeom* geo_de
   LSP_LAUNCH("gram", 0, gram_kernel<false>, grid, dim3(256), 0, st, ktab, n, d, geo_dev, (const double2*)nullptr,
                      partial, nblk);
   LSP_LAUNCH("gram_reduce", 0, gram_reduce_kernel, dim3(nclass), dim3(768), 0, st, partial, G, nblk, nclass, geo_dev);
-  LSP_LAUNCH("eigen", 0, eigen_kernel, dim3(nclass), dim3(64), 0, st, G, geo_dev, U1, (const double2*)nullptr, ktab, n,
+  LSP_LAUNCH("eigen", 0, eigen_kernel, dim3(nclass), dim3(256), 0, st, G, geo_dev, U1, (const double2*)nullptr, ktab, n,
                      d, 0, alpha_pad, C_pad, sigma_pad);
   LSP_LAUNCH("gram", 0, gram_kernel<true>, grid, dim3(256), 0, st, ktab, n, d, geo_dev, U1, partial, nblk);
   LSP_LAUNCH("gram_reduce", 0, gram_reduce_kernel, dim3(nclass), dim3(768), 0, st, partial, G, nblk, nclass, geo_dev);
-  LSP_LAUNCH("eigen", 0, eigen_kernel, dim3(nclass), dim3(64), 0, st, G, geo_dev, (double2*)nullptr, U1, ktab, n, d, 1,
+  LSP_LAUNCH("eigen", 0, eigen_kernel, dim3(nclass), dim3(256), 0, st, G, geo_dev, (double2*)nullptr, U1, ktab, n, d, 1,
                      alpha_pad, C_pad, sigma_pad);
 }
 
