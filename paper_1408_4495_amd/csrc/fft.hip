@@ -297,7 +297,8 @@ struct HalfArgs {
 //   INV_WORK   L values of the work line -> its first n values
 //   INV_FIELD  work row c (L values) -> field row c (plus x when given;
 //              zero where the output mask, passed in place of w2m, is 0)
-// Workgroups: LPW lines of one (o, rhs), line = tid / P, t = tid % P.  The
+// Workgroups: LPW lines of one (o, rhs), line = tid / P, t = tid % P, with
+// two banks of LPW lines in LDS (the even and odd halves' transforms).  The
 // GS blocks whose lines share cache lines, then the right-hand sides of a
 // line block (sharing spectrum rows), are consecutive in dispatch order
 // within one XCD (workgroup b goes to XCD b mod 8).  TIO: a strided line's
