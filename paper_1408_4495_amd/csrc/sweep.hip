@@ -692,7 +692,7 @@ __global__ void __launch_bounds__(64 * W) mchain_fwd_kernel(const cplx<T>* __res
 // The backward sweep gathers the boundary rows' solution from the point-
 // major copy xpm (a grid point's 16 right-hand sides in one 128-byte line,
 // where the [nrhs][N] layout spreads them over 16 lines) and stores its
-// pivots' solution there for the levels below, into xw when given (the
+// pivots' solution there for the levels below (if any), into xw when given (the
 // widened solution, mixed path) and into x unless store_x is 0 (x is not
 // needed when xw is the output and every level below is a matrix-core one).
 template <typename T, int W>
@@ -703,7 +703,7 @@ __global__ void __launch_bounds__(64 * W) mchain_bwd_kernel(const cplx<T>* __res
                                                             const cplx<T>* __restrict__ vbuf, int first, int nrhs,
                                                             long long N, long long vstride,
                                                             double2* __restrict__ xw, int maxm,
-                                                            cplx<T>* __restrict__ xpm, int store_x) {
+                                                            cplx<T>* __restrict__ xpm, int store_x, int store_pm) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* V = reinterpret_cast<cplx<T>*>(smem_raw);  // V[r * MC + k]
   cplx<T>* part = V + (long long)maxm * MC;           // part[(w - 1) * 2 + h][64 lanes][4]: waves 1.. partial sums
@@ -740,9 +740,13 @@ __global__ void __launch_bounds__(64 * W) mchain_bwd_kernel(const cplx<T>* __res
     sa[0].zero();
     sa[1].zero();
     for (int c0 = 32 * wave; c0 < nc; c0 += 32 * W) {
+      // k-steps of the chunk inside the front (a chunk past the last column
+      // contributes exact zeros, so its empty steps are skipped)
+      const int n8 = min(8, (nc - c0 + 3) / 4);
       cplx<T> ua[8][2];
 #pragma unroll
       for (int s8 = 0; s8 < 8; ++s8) {
+        if (s8 >= n8) break;
         const long long col = (long long)(k1 + min(c0 + 4 * s8 + lk, nc - 1)) * m;
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -750,6 +754,7 @@ __global__ void __launch_bounds__(64 * W) mchain_bwd_kernel(const cplx<T>* __res
       }
 #pragma unroll
       for (int s8 = 0; s8 < 8; ++s8) {
+        if (s8 >= n8) break;
         const int c = c0 + 4 * s8 + lk;
         const cplx<T> xv = V[(k1 + min(c, nc - 1)) * MC + li];
         const cplx<T> b4 = c < nc ? xv : mk<T>(0, 0);
@@ -815,9 +820,11 @@ __global__ void __launch_bounds__(64 * W) mchain_bwd_kernel(const cplx<T>* __res
     }
   }
   __syncthreads();
-  for (int e = tid; e < p * MC; e += 64 * W) {
-    const int r = e / MC, k = e % MC;
-    xpm[((long long)blockIdx.y * N + id[r]) * MC + k] = V[r * MC + k];
+  if (store_pm) {  // read by the levels below for their boundary rows
+    for (int e = tid; e < p * MC; e += 64 * W) {
+      const int r = e / MC, k = e % MC;
+      xpm[((long long)blockIdx.y * N + id[r]) * MC + k] = V[r * MC + k];
+    }
   }
   for (int e = tid; e < p * nr; e += 64 * W) {
     const int r = e % p, k = e / p;
@@ -876,7 +883,7 @@ void mchain_launch(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nr
     const size_t plds = (size_t)(W - 1) * 2 * 64 * 4 * sizeof(cplx<T>);
     LSP_LAUNCH("bwd_mchain", (int)sizeof(cplx<T>), (mchain_bwd_kernel<T, W>), grid, dim3(64 * W), vlds + plds, st,
                mf.F, mf.Dinv, mf.fronts, mf.idx, x, vbuf, first, nrhs, (long long)plan.N, (long long)plan.sum_pq, xw,
-               maxm, xpm, store_x);
+               maxm, xpm, store_x, (int)(l > 0));
   }
 }
 
