@@ -608,7 +608,9 @@ __global__ void __launch_bounds__(64 * W) mchain_fwd_kernel(const cplx<T>* __res
     const cplx<T>* Lg = Dinv + f.dinv_off + (long long)(k0 / PB) * 2 * PB * PB;
     __syncthreads();  // v is complete
     // y_b = L11^{-1} P_b v_b: operand A the inverse block (column-major),
-    // operand B the gathered rows; tile h on wave h (wave 0 both if W = 1)
+    // operand B the gathered rows; tile h on wave h (wave 0 both if W = 1);
+    // L11^{-1} is lower triangular, so tile 0's k-steps past column 16 are
+    // exact zeros and skipped
     CAcc<T> y[W == 1 ? 2 : 1];
 #pragma unroll
     for (int u = 0; u < (W == 1 ? 2 : 1); ++u) {
@@ -617,7 +619,7 @@ __global__ void __launch_bounds__(64 * W) mchain_fwd_kernel(const cplx<T>* __res
       if (h < nh) {
 #pragma unroll
         for (int s4 = 0; s4 < PB / 4; ++s4) {
-          if (s4 < ns) {
+          if (s4 < ns && !(h == 0 && 4 * s4 >= 16)) {
             const int j = 4 * s4 + lk;
             const int src = pm[k0 + min(j, kb - 1)];
             const cplx<T> tv = V[src * MC + li];
@@ -789,7 +791,8 @@ __global__ void __launch_bounds__(64 * W) mchain_bwd_kernel(const cplx<T>* __res
       }
     }
     __syncthreads();
-    // x_b = U11^{-1} t_b
+    // x_b = U11^{-1} t_b (upper triangular: tile 1's k-steps before column
+    // 16 are exact zeros and skipped)
     CAcc<T> xa[W == 1 ? 2 : 1];
 #pragma unroll
     for (int u = 0; u < (W == 1 ? 2 : 1); ++u) {
@@ -798,7 +801,7 @@ __global__ void __launch_bounds__(64 * W) mchain_bwd_kernel(const cplx<T>* __res
       if (h < nh) {
 #pragma unroll
         for (int s4 = 0; s4 < PB / 4; ++s4) {
-          if (s4 < ns) {
+          if (s4 < ns && !(h == 1 && 4 * s4 < 16)) {
             const int j = 4 * s4 + lk;
             const cplx<T> tv = V[(k0 + min(j, kb - 1)) * MC + li];
             cstep(xa[u], Ug[(16 * h + li) + PB * j], j < kb ? tv : mk<T>(0, 0));
