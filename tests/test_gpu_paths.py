@@ -1,7 +1,8 @@
 """Options and failure paths of the C ABI on the GPU, each against the oracle:
 the buffer constant b of Section 3.1 other than the default, GMRES with a
 short restart and with an iteration cap (LSP_ERR_NOCONV, Section 3.3
-experiments' solver), the stencil application Q v (eq:PC) in isolation, the
+experiments' solver), the stencil application Q v (eq:PC) in isolation (and its
+row blocks, batched against solo bit for bit), the
 complex64 factor in 3D, and a medium carrying a NaN (LSP_ERR_SINGULAR)."""
 import numpy as np
 import pytest
@@ -136,6 +137,31 @@ def test_Q_apply_exact(n, d):
     y = pb.apply_Q(x).cpu().numpy()
     y_ref = (Q @ x.T).T
     assert _rel(y, y_ref) <= 1e-14
+
+
+def test_Q_apply_row_blocks_bitwise():
+    """2D n = 256: the stencil product's row blocks shrink with the number of
+    right-hand sides (16 right-hand sides: 2 rows per workgroup, one: 1), yet
+    each point's sum is the same, so a batched product equals the solo ones
+    bit for bit; and it matches the oracle's Q built from the GPU's stencils
+    (relative 1e-14)."""
+    lsp, torch = _lsp()
+    n, d = 256, 2
+    omega = 2 * np.pi * n / 8
+    plan = lsp.Plan(n, d, max_nrhs=16)
+    pb = lsp.Problem(plan, omega, np.zeros(n ** d))
+    x = synth.random_complex((16, n ** d), seed=62)
+    y = pb.apply_Q(x).cpu().numpy()
+    for r in (0, 7, 15):
+        assert np.array_equal(pb.apply_Q(x[r:r + 1]).cpu().numpy()[0], y[r])
+    alpha, sigma, C = pb.stencils()
+    sts = []
+    for c in range(3 ** d):
+        off = class_offsets(c, d)
+        sl = np.sum((off + 1) * (3 ** np.arange(d)), axis=1)
+        sts.append(StencilClass(c, off, alpha[c, sl], sigma[c, :off.shape[0]], C[c, sl]))
+    Q, _ = build_QM(n, d, omega, np.zeros(n ** d), sts)
+    assert _rel(y[:2], (Q @ x[:2].T).T) <= 1e-14
 
 
 @pytest.mark.parametrize("n", [12, 16])
