@@ -2009,14 +2009,18 @@ void solve_levels(const MfDev<T>& mf, const Plan& plan, int nrhs, const cplx<T>*
     else if (wide_level(plan, l)) sweep_fwd<T, NR, 512>(mf, plan, l, groups, nrhs, z, vbuf, st);
     else sweep_fwd<T, NR, 256>(mf, plan, l, groups, nrhs, z, vbuf, st);
   }
-  bool point_major = false;  // xpm holds the solution of the levels above
+  // the matrix-core levels gather their boundary rows from xpm: the levels
+  // swept by other kernels since the last matrix-core one (from unconv_top
+  // down) have their pivots copied there first
+  int unconv_top = -1;
   for (int l = plan.nlevels - 1; l >= 0; --l) {
     if (plan.level_mchain[l]) {
-      if (!point_major) launch_point_major<T>(x, sb.xpm, nrhs, plan.N, st);
-      point_major = true;
+      if (unconv_top >= 0) launch_point_major<T>(mf, plan, l + 1, unconv_top + 1, x, sb.xpm, nrhs, st);
+      unconv_top = -1;
       mchain_sweep<T>(false, mf, plan, l, nrhs, z, x, vbuf, st, xw, sb.xpm);
       continue;
     }
+    if (unconv_top < 0) unconv_top = l;
     if constexpr (sizeof(T) == 4 && NR == 1) {
       if (plan.level_small_sweep[l]) {
         LSP_LAUNCH("bwd", (int)sizeof(cplx<T>), (bwd_small_kernel<T, NR>),

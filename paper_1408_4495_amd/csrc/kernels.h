@@ -158,10 +158,13 @@ void blocked_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nr
 template <typename T>
 void mchain_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrhs, const cplx<T>* z, cplx<T>* x,
                   cplx<T>* vbuf, hipStream_t st, double2* xw, cplx<T>* xpm);
-// xpm[g][i][k] = x[16 g + k][i] (zero for k beyond nrhs): the backward
-// sweep's solution so far, point-major, before the matrix-core levels.
+// xpm[g][i][k] = x[16 g + k][i] (zero for k beyond nrhs) for the pivots i of
+// levels lo .. hi - 1: the backward sweep's solution of levels swept by other
+// kernels, point-major, for the matrix-core levels below them (which store
+// their own pivots there themselves).
 template <typename T>
-void launch_point_major(const cplx<T>* x, cplx<T>* xpm, int nrhs, long long N, hipStream_t st);
+void launch_point_major(const MfDev<T>& mf, const Plan& plan, int lo, int hi, const cplx<T>* x, cplx<T>* xpm,
+                        int nrhs, hipStream_t st);
 // Forms the super-block operators of blocked level l from its factor (the
 // panel chains on the unit vectors), into mf.G at each front's g_off.
 template <typename T>

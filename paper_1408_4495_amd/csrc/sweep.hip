@@ -838,21 +838,29 @@ __global__ void __launch_bounds__(64 * W) mchain_bwd_kernel(const cplx<T>* __res
   }
 }
 
+// The pivots of the fronts first .. first + gridDim.x - 1 (levels whose
+// solution the backward sweep has just computed with other kernels than the
+// matrix-core chains), point-major: one workgroup per front, a pivot per
+// thread.
 template <typename T>
 __global__ void __launch_bounds__(256) point_major_kernel(const cplx<T>* __restrict__ x, cplx<T>* __restrict__ xpm,
-                                                          int nrhs, long long N) {
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= N) return;
+                                                          const FrontDev* __restrict__ fr,
+                                                          const int* __restrict__ idx, int first, int nrhs,
+                                                          long long N) {
+  const FrontDev f = fr[first + blockIdx.x];
   const int g = blockIdx.y, nr = min(MC, nrhs - g * MC);
-  cplx<T> v[MC];
+  for (int r = threadIdx.x; r < f.p; r += 256) {
+    const long long i = idx[f.idx_off + r];
+    cplx<T> v[MC];
 #pragma unroll
-  for (int k = 0; k < MC; ++k) {
-    const cplx<T> a = x[(long long)(g * MC + min(k, nr - 1)) * N + i];
-    v[k] = k < nr ? a : mk<T>(0, 0);
+    for (int k = 0; k < MC; ++k) {
+      const cplx<T> a = x[(long long)(g * MC + min(k, nr - 1)) * N + i];
+      v[k] = k < nr ? a : mk<T>(0, 0);
+    }
+    cplx<T>* dst = xpm + ((long long)g * N + i) * MC;
+#pragma unroll
+    for (int k = 0; k < MC; ++k) dst[k] = v[k];
   }
-  cplx<T>* dst = xpm + ((long long)g * N + i) * MC;
-#pragma unroll
-  for (int k = 0; k < MC; ++k) dst[k] = v[k];
 }
 
 }  // namespace
@@ -901,9 +909,14 @@ void mchain_sweep(bool fwd, const MfDev<T>& mf, const Plan& plan, int l, int nrh
 }
 
 template <typename T>
-void launch_point_major(const cplx<T>* x, cplx<T>* xpm, int nrhs, long long N, hipStream_t st) {
+void launch_point_major(const MfDev<T>& mf, const Plan& plan, int lo, int hi, const cplx<T>* x, cplx<T>* xpm,
+                        int nrhs, hipStream_t st) {
+  const int first = plan.level_ptr[lo];
+  const int cnt = plan.level_ptr[hi] - first;
+  if (cnt == 0) return;
   LSP_LAUNCH("point_major", (int)sizeof(cplx<T>), point_major_kernel<T>,
-             dim3((unsigned)((N + 255) / 256), (unsigned)((nrhs + MC - 1) / MC)), dim3(256), 0, st, x, xpm, nrhs, N);
+             dim3((unsigned)cnt, (unsigned)((nrhs + MC - 1) / MC)), dim3(256), 0, st, x, xpm, mf.fronts, mf.idx, first,
+             nrhs, (long long)plan.N);
 }
 
 template <typename T>
@@ -926,8 +939,10 @@ template void mchain_sweep<double>(bool, const MfDev<double>&, const Plan&, int,
                                    double2*, hipStream_t, double2*, double2*);
 template void mchain_sweep<float>(bool, const MfDev<float>&, const Plan&, int, int, const float2*, float2*, float2*,
                                   hipStream_t, double2*, float2*);
-template void launch_point_major<double>(const double2*, double2*, int, long long, hipStream_t);
-template void launch_point_major<float>(const float2*, float2*, int, long long, hipStream_t);
+template void launch_point_major<double>(const MfDev<double>&, const Plan&, int, int, const double2*, double2*,
+                                         int, hipStream_t);
+template void launch_point_major<float>(const MfDev<float>&, const Plan&, int, int, const float2*, float2*, int,
+                                        hipStream_t);
 template void blocked_form<double>(const MfDev<double>&, const Plan&, int, hipStream_t);
 template void blocked_form<float>(const MfDev<float>&, const Plan&, int, hipStream_t);
 
