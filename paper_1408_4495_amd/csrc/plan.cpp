@@ -203,13 +203,13 @@ void build_plan(Plan& P, int n, int d, int max_nrhs, const lsp_options& opts) {
   // default trailing-update tiles by front order; an autotuner may replace them
   // (measured with the autotuner on 2D n = 256 and 1024 and 3D n = 64:
   // complex128 factors run fastest with 32-wide tiles everywhere; complex64
-  // ones with 64-wide tiles above 160 rows, except in 2D above 512 rows
+  // ones with 64-wide tiles, except in 2D up to 160 rows and above 512 rows
   // (the two-panel levels), where 32-wide ones win, and a single 2D root
   // front of 1024 rows or more, which takes 128-wide ones)
   P.level_tile.assign(P.nlevels, 64);
   for (int l = 0; l < P.nlevels; ++l) {
     const int cnt = P.level_ptr[l + 1] - P.level_ptr[l], mq = P.level_maxpq[l];
-    if (opts.precision == LSP_FP64 || mq <= 160) P.level_tile[l] = 32;
+    if (opts.precision == LSP_FP64 || (d == 2 && mq <= 160)) P.level_tile[l] = 32;
     else if (d == 2 && mq >= 1024 && cnt == 1) P.level_tile[l] = 128;
     else if (d == 2 && mq > 512) P.level_tile[l] = 32;
     else P.level_tile[l] = 64;
