@@ -123,14 +123,15 @@ __host__ __device__ __forceinline__ int padi(int e) { return e + (e >> 4); }
 // loaded ones (a bounded rounding depth).
 template <int R> struct TwLoads { static constexpr int value = R == 2 ? 1 : (R == 8 ? 3 : 2); };
 
-template <typename T, int R, int NB>
+// P2: Ns and L are powers of two (modulo and division by masks and shifts).
+template <typename T, int R, int NB, bool P2>
 __device__ __forceinline__ void load_tw(cplx<T> (&wt)[NB * TwLoads<R>::value], const int t, const int P,
                                         const int Ns, const int L, const cplx<T>* __restrict__ tw) {
   constexpr int NL = TwLoads<R>::value;
-  const int tstep = L / (Ns * R);
+  const int tstep = P2 ? L >> (31 - __builtin_clz(Ns * R)) : L / (Ns * R);
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int idx = ((t + b * P) % Ns) * tstep;
+    const int idx = (P2 ? (t + b * P) & (Ns - 1) : (t + b * P) % Ns) * tstep;
     wt[NL * b] = tw[idx];
     if constexpr (NL >= 2) wt[NL * b + 1] = tw[2 * idx];
     if constexpr (NL >= 3) wt[NL * b + 2] = tw[4 * idx];
@@ -203,7 +204,7 @@ __device__ __forceinline__ void half_pass(cplx<T> (&a)[K][EPT], cplx<T> (&wt8)[3
       }
     } else {
       cplx<T> wt[NB * NL];
-      load_tw<T, R, NB>(wt, t, P, Ns, L, tw);
+      load_tw<T, R, NB, false>(wt, t, P, Ns, L, tw);
 #pragma unroll
       for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -211,7 +212,7 @@ __device__ __forceinline__ void half_pass(cplx<T> (&a)[K][EPT], cplx<T> (&wt8)[3
     }
   }
   if constexpr (CARRY) {
-    if (!last) load_tw<T, 8, 1>(wt8, t, P, Ns * R, L, tw);
+    if (!last) load_tw<T, 8, 1, true>(wt8, t, P, Ns * R, L, tw);
   }
 #pragma unroll
   for (int k = 0; k < K; ++k)
@@ -230,7 +231,8 @@ __device__ __forceinline__ void half_pass(cplx<T> (&a)[K][EPT], cplx<T> (&wt8)[3
     for (int k = 0; k < K; ++k)
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const int j = t + b * P, kk = j % Ns, base = (j - kk) * R + kk;
+        // (a carried schedule is the n = 2^a one: Ns is a power of two)
+        const int j = t + b * P, kk = CARRY ? j & (Ns - 1) : j % Ns, base = (j - kk) * R + kk;
 #pragma unroll
         for (int r = 0; r < R; ++r) s[k * sstep + padi(base + r * Ns)] = v[k][b][r];
       }
