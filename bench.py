@@ -422,6 +422,64 @@ def workload_record(lsp, torch, key, steps, warmup):
     return rec, w
 
 
+# The first 2D example of the paper's numerical results (its Gaussian-bump
+# table): c(x) from 1 down to 2/3 (m down to -1.25), a plane wave pointing
+# down, 6 points per wavelength, GMRES to 1e-6.  The paper's grids are
+# n = 6 w / (2 pi) = 95.5, 191, 382; the library takes n = 2^a 3^b, so the
+# next such sizes (96, 192, 384, about 6.03 points per wavelength).  Its
+# iteration counts there are 5, 5 and 6.
+PAPER_R21 = ((100.0, 96, 5), (200.0, 192, 5), (400.0, 384, 6))
+
+
+def paper_context(lsp, torch, reps=5):
+    """n_p (iterations to 1e-6), the set-up + factorisation time T_s, one
+    preconditioner application T_a and the solve time T_p for the paper's
+    first 2D example, both precision paths, beside the paper's n_p.  Context
+    only: the paper's times are MATLAB on a 2.0 GHz desktop CPU."""
+    import synth
+    dev = torch.device("cuda:0")
+    rows = []
+    for omega, n, np_paper in PAPER_R21:
+        m = synth.medium_single_bump(n, 2, -1.25, 0.12)
+        uI = synth.plane_waves(n, 2, omega, [[0.0, -1.0]])
+        m_dev = torch.tensor(m, dtype=torch.float64, device=dev)
+        u_dev = torch.tensor(uI, dtype=torch.complex128, device=dev)
+        row = {"omega": omega, "n": n, "N": n * n, "n_p_paper": np_paper}
+        for prec in ("fp64", "mixed"):
+            plan = lsp.Plan(n, 2, max_nrhs=1, precision=prec, tol=1e-6)
+            pb = lsp.Problem(plan, omega, m_dev)
+            pb.factor()
+            u, info, st = pb.solve(u_dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pb = lsp.Problem(plan, omega, m_dev)
+            pb.factor()
+            torch.cuda.synchronize()
+            t_s = (time.perf_counter() - t0) * 1e3
+            v = torch.tensor(synth.random_complex((1, n * n), seed=3), dtype=torch.complex128, device=dev)
+            pb.apply_precond(v)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                pb.apply_precond(v)
+            e1.record()
+            torch.cuda.synchronize()
+            t_a = e0.elapsed_time(e1) / reps
+            t0 = time.perf_counter()
+            u, info, st = pb.solve(u_dev)
+            torch.cuda.synchronize()
+            t_p = (time.perf_counter() - t0) * 1e3
+            row[prec] = {"n_p": info[0]["iters"], "relres_true": info[0]["relres_true"], "T_s_ms": t_s,
+                         "T_a_ms": t_a, "T_p_ms": t_p}
+            del pb, plan
+        log(f"[bench] paper example 1, w={omega:.0f} n={n}: n_p {row['fp64']['n_p']} (complex128), "
+            f"{row['mixed']['n_p']} (mixed); the paper's {np_paper}")
+        rows.append(row)
+    torch.cuda.empty_cache()
+    return {"example": "Gaussian bump, c in [2/3, 1], downward plane wave, 6 points per wavelength, tol 1e-6",
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -431,6 +489,7 @@ def main():
     ap.add_argument("--extra", default="c4,c2,l2,g2", help="further workloads reported beside the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-paper-context", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only: the solver has no multi-GPU path "
@@ -452,6 +511,10 @@ def main():
     log("[bench] field away from the grid")
     # (the headline workload's medium; the Laplace workloads have no incident field)
     field = field_record(lsp, torch, "c3" if args.workload.startswith("l") else args.workload)
+    paper = None
+    if not args.no_paper_context:
+        log("[bench] the paper's first 2D example (context)")
+        paper = paper_context(lsp, torch)
     serve_rec = None
     if not args.no_serving:
         log("[bench] serving loop")
@@ -486,6 +549,7 @@ def main():
         "serving": serve_rec,
         "workloads": extra,
         "field": field,
+        "paper_example": paper,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
