@@ -422,31 +422,34 @@ def workload_record(lsp, torch, key, steps, warmup):
     return rec, w
 
 
-# The first 2D example of the paper's numerical results (its Gaussian-bump
-# table): c(x) from 1 down to 2/3 (m down to -1.25), a plane wave pointing
-# down, 6 points per wavelength, GMRES to 1e-6.  The paper's grids are
-# n = 6 w / (2 pi) = 95.5, 191, 382; the library takes n = 2^a 3^b, so the
-# next such sizes (96, 192, 384, about 6.03 points per wavelength).  Its
-# iteration counts there are 5, 5 and 6.
-PAPER_R21 = ((100.0, 96, 5), (200.0, 192, 5), (400.0, 384, 6))
+# The first 2D and the first 3D example of the paper's numerical results
+# (its Gaussian-bump tables): c(x) from 1 down to 2/3 (m down to -1.25), a
+# plane wave pointing down, 6 points per wavelength, GMRES to 1e-6.  The
+# paper's grids are n = 6 w / (2 pi) (95.5, 191, 382 in 2D; 23.9, 47.7,
+# 95.5 in 3D); the library takes n = 2^a 3^b, so the next such sizes (about
+# 6.03 points per wavelength).  Its iteration counts: 5, 5, 6 in 2D and 4,
+# 4, 4 in 3D.  Entries: (d, w, n, the paper's n_p).
+PAPER_EXAMPLES = ((2, 100.0, 96, 5), (2, 200.0, 192, 5), (2, 400.0, 384, 6),
+                  (3, 25.0, 24, 4), (3, 50.0, 48, 4), (3, 100.0, 96, 4))
 
 
 def paper_context(lsp, torch, reps=5):
     """n_p (iterations to 1e-6), the set-up + factorisation time T_s, one
     preconditioner application T_a and the solve time T_p for the paper's
-    first 2D example, both precision paths, beside the paper's n_p.  Context
-    only: the paper's times are MATLAB on a 2.0 GHz desktop CPU."""
+    first 2D and 3D examples, both precision paths, beside the paper's n_p.
+    Context only: the paper's times are MATLAB on a 2.0 GHz desktop CPU."""
     import synth
     dev = torch.device("cuda:0")
     rows = []
-    for omega, n, np_paper in PAPER_R21:
-        m = synth.medium_single_bump(n, 2, -1.25, 0.12)
-        uI = synth.plane_waves(n, 2, omega, [[0.0, -1.0]])
+    for d, omega, n, np_paper in PAPER_EXAMPLES:
+        m = synth.medium_single_bump(n, d, -1.25, 0.12)
+        down = [0.0, -1.0] if d == 2 else [0.0, 0.0, -1.0]
+        uI = synth.plane_waves(n, d, omega, [down])
         m_dev = torch.tensor(m, dtype=torch.float64, device=dev)
         u_dev = torch.tensor(uI, dtype=torch.complex128, device=dev)
-        row = {"omega": omega, "n": n, "N": n * n, "n_p_paper": np_paper}
+        row = {"d": d, "omega": omega, "n": n, "N": n ** d, "n_p_paper": np_paper}
         for prec in ("fp64", "mixed"):
-            plan = lsp.Plan(n, 2, max_nrhs=1, precision=prec, tol=1e-6)
+            plan = lsp.Plan(n, d, max_nrhs=1, precision=prec, tol=1e-6)
             pb = lsp.Problem(plan, omega, m_dev)
             pb.factor()
             u, info, st = pb.solve(u_dev)
@@ -456,7 +459,7 @@ def paper_context(lsp, torch, reps=5):
             pb.factor()
             torch.cuda.synchronize()
             t_s = (time.perf_counter() - t0) * 1e3
-            v = torch.tensor(synth.random_complex((1, n * n), seed=3), dtype=torch.complex128, device=dev)
+            v = torch.tensor(synth.random_complex((1, n ** d), seed=3), dtype=torch.complex128, device=dev)
             pb.apply_precond(v)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
@@ -472,12 +475,12 @@ def paper_context(lsp, torch, reps=5):
             row[prec] = {"n_p": info[0]["iters"], "relres_true": info[0]["relres_true"], "T_s_ms": t_s,
                          "T_a_ms": t_a, "T_p_ms": t_p}
             del pb, plan
-        log(f"[bench] paper example 1, w={omega:.0f} n={n}: n_p {row['fp64']['n_p']} (complex128), "
+        log(f"[bench] paper example 1 ({d}D), w={omega:.0f} n={n}: n_p {row['fp64']['n_p']} (complex128), "
             f"{row['mixed']['n_p']} (mixed); the paper's {np_paper}")
         rows.append(row)
     torch.cuda.empty_cache()
-    return {"example": "Gaussian bump, c in [2/3, 1], downward plane wave, 6 points per wavelength, tol 1e-6",
-            "rows": rows}
+    return {"example": "Gaussian bump (2D and 3D), c in [2/3, 1], downward plane wave, 6 points per wavelength, "
+                       "tol 1e-6", "rows": rows}
 
 
 def main():
@@ -513,7 +516,7 @@ def main():
     field = field_record(lsp, torch, "c3" if args.workload.startswith("l") else args.workload)
     paper = None
     if not args.no_paper_context:
-        log("[bench] the paper's first 2D example (context)")
+        log("[bench] the paper's first 2D and 3D examples (context)")
         paper = paper_context(lsp, torch)
     serve_rec = None
     if not args.no_serving:
