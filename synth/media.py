@@ -88,11 +88,17 @@ def delta_source(n, d, points):
 
 def cavity_rho(n, d, kind="l2", radius=0.45, centre=None):
     """Scaled distance |x - c|_p / radius of every grid point (p = 2 for the
-    disk / ball, p = 1 for the diamond / octahedron)."""
+    disk / ball, p = 1 for the diamond / octahedron, p = inf for the square /
+    cube)."""
     X = grid_coords(n, d)
     c = np.full(d, 0.5) if centre is None else np.asarray(centre, dtype=np.float64)
     Y = X - c
-    dist = np.sqrt(np.sum(Y * Y, axis=1)) if kind == "l2" else np.sum(np.abs(Y), axis=1)
+    if kind == "l2":
+        dist = np.sqrt(np.sum(Y * Y, axis=1))
+    elif kind == "linf":
+        dist = np.max(np.abs(Y), axis=1)
+    else:
+        dist = np.sum(np.abs(Y), axis=1)
     return dist / radius
 
 
@@ -102,7 +108,7 @@ def domain_mask(n, d, kind="l2", radius=0.45, centre=None):
 
 
 def medium_cavity(n, d, kind="l2", depth=-0.5, radius=0.45, core=0.6, centre=None):
-    """Smoothed cavity of an l2 or l1 ball: m = depth for rho <= core, a
+    """Smoothed cavity of an l2, l1 or l-infinity ball: m = depth for rho <= core, a
     raised-cosine ramp to 0 at rho = 1, and 0 outside (support = the mask)."""
     rho = cavity_rho(n, d, kind, radius, centre)
     ramp = 0.5 * (1.0 + np.cos(np.pi * np.clip((rho - core) / (1.0 - core), 0.0, 1.0)))
