@@ -347,10 +347,23 @@ def serving(torch, count=200, warm=20, rhos=(0.5, 0.8), slots=4):
            "excluded_warmup": warm, "slots": slots}
     for rho in rhos:
         specs = synth.serving_requests(count, rho * rps, seed=5)
-        rep = srv.run(requests_from_synth(specs), exclude_first=warm)
+        rep = srv.run(requests_from_synth(specs), exclude_first=warm, strict=False)
         out[f"rho={rho}"] = {k: rep[k] for k in ("latency_ms", "solves_per_s", "solves", "makespan_s",
                                                   "peak_concurrency", "peak_admitted_bytes", "all_converged",
-                                                  "max_iters")}
+                                                  "max_iters", "failed")}
+        # a failed request is run again alone on one slot, to tell a property
+        # of the request from an interaction with the requests beside it
+        reruns = []
+        for rid, err in rep["failed"]:
+            log(f"[bench] serving rho={rho}: request {rid} FAILED: {err}")
+            again = requests_from_synth([sp for sp in specs if sp["id"] == rid])[0]
+            try:
+                srv._run_one(again, srv.streams[0])
+                reruns.append({"id": rid, "alone": "ok", "status": again.status})
+            except Exception as e:  # reported
+                reruns.append({"id": rid, "alone": repr(e)})
+            log(f"[bench] serving rho={rho}: request {rid} alone: {reruns[-1]}")
+        out[f"rho={rho}"]["failed_rerun_alone"] = reruns
         log(f"[bench] serving rho={rho}: p50 {rep['latency_ms']['p50']:.1f} ms, p99 {rep['latency_ms']['p99']:.1f} ms, "
             f"{rep['solves_per_s']:.1f} solves/s, peak concurrency {rep['peak_concurrency']}")
     return out

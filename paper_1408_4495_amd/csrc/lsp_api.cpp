@@ -231,6 +231,9 @@ const PlanDev& plan_device(const lsp_plan* pl, int device) {
         LSP_HIP(hipMemcpy(d.bslots, P.bslots.data(), P.bslots.size() * sizeof(unsigned), hipMemcpyHostToDevice));
       }
     }
+    // a copy from pageable memory may return before its DMA has landed, and
+    // the problems' streams do not wait for the null stream
+    LSP_HIP(hipDeviceSynchronize());
   } catch (...) {
     (void)hipFree(d.block);
     throw;

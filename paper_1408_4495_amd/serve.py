@@ -91,10 +91,12 @@ class Server:
                 req.u = u.cpu().numpy()
             del pb, u, m, uI
 
-    def run(self, requests, realtime=True, exclude_first=0):
+    def run(self, requests, realtime=True, exclude_first=0, strict=True):
         """Serve `requests` (arrival times in seconds from the start).  Returns
         a report with p50/p99 latency and solves/s over the requests after the
-        first `exclude_first` by arrival (all of them are served)."""
+        first `exclude_first` by arrival (all of them are served).  A request
+        that fails raises at the end with strict, else it is listed under
+        "failed" and left out of the statistics."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         for r in reqs:
             r.footprint = self.footprint(r)
@@ -150,9 +152,14 @@ class Server:
                 self.cv.wait(timeout=wait if wait is not None else 0.5)
         for th in threads:
             th.join()
-        if errors:
+        if errors and strict:
             raise RuntimeError(f"requests failed: {errors}")
+        failed = {rid for rid, _ in errors}
         meas = reqs[exclude_first:] if exclude_first < len(reqs) else reqs
+        meas = [r for r in meas if r.id not in failed]
+        ok = [r for r in reqs if r.id not in failed]
+        if not meas:
+            raise RuntimeError(f"every measured request failed: {errors}")
         start = t0 + meas[0].arrival if realtime else min(r.admit for r in meas)
         makespan = max(r.finish for r in meas) - start
         lat = np.array([r.finish - (t0 + r.arrival if realtime else r.admit) for r in meas])
@@ -167,8 +174,9 @@ class Server:
             "peak_concurrency": peak[0],
             "peak_admitted_bytes": peak_used[0],
             "hbm_budget_bytes": self.budget,
-            "all_converged": all(r.status == 0 and all(x["converged"] for x in r.info) for r in reqs),
-            "max_iters": max(max(x["iters"] for x in r.info) for r in reqs),
+            "all_converged": not failed and all(r.status == 0 and all(x["converged"] for x in r.info) for r in reqs),
+            "max_iters": max(max(x["iters"] for x in r.info) for r in ok),
+            "failed": sorted(errors),
         }
 
 
