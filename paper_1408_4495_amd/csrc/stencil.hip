@@ -337,7 +337,11 @@ __device__ void jacobi_eigen(double2* A, double2* U, int s, int lane) {
       }
       __syncthreads();
     }
-    if (!rotated) break;
+    // every wave reads the flag before the next sweep's reset (several
+    // waves: a reset seen early would end some waves' sweeps and not others')
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
   }
 }
 
